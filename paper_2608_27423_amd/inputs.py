@@ -1,0 +1,136 @@
+"""Named workloads and seeded synthetic inputs.
+
+This module is shared by the HIP path's tests/benchmark and by the oracle's
+tests.  It holds no arithmetic of the method: only mesh descriptions, seeded
+random numbers (numpy PCG64) and smooth synthetic fields defined on the DoF
+index grid.  The paper's own meshes, CAD geometries and measured data are not
+available; these annular rotor/stator meshes stand in for them.
+"""
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+# Annular rotor/stator workloads.  Cell counts are per domain
+# (n_theta azimuthal x n_r radial [x n_z axial]).
+WORKLOADS = {
+    "annulus2d_q2_32x4": dict(
+        dim=2, degree=2, r_in=0.25, r_if=0.5, r_out=1.0, height=1.0, n_theta=32, n_r_rotor=4,
+        n_r_stator=4, n_z=1, nu=0.01, omega=1.0, steady=1, dt=1.0),
+    "annulus3d_q2_64x8x32": dict(
+        dim=3, degree=2, r_in=0.2, r_if=0.5, r_out=1.0, height=1.0, n_theta=64, n_r_rotor=8,
+        n_r_stator=8, n_z=32, nu=0.01, omega=1.0, steady=1, dt=1.0),
+    "annulus3d_q3_64x16x32": dict(
+        dim=3, degree=3, r_in=0.2, r_if=0.5, r_out=1.0, height=1.0, n_theta=64, n_r_rotor=16,
+        n_r_stator=16, n_z=32, nu=0.005, omega=1.0, steady=1, dt=1.0),
+    "annulus3d_q2_256x32x128": dict(
+        dim=3, degree=2, r_in=0.2, r_if=0.5, r_out=1.0, height=1.0, n_theta=256, n_r_rotor=32,
+        n_r_stator=32, n_z=128, nu=5e-4, omega=1.0, steady=0, dt=0.01),
+}
+
+# rotor angle of each workload: fixed 0.1 rad for the 2D case, seeded otherwise
+ANGLE_SEED = {"annulus3d_q2_64x8x32": 2, "annulus3d_q3_64x16x32": 6, "annulus3d_q2_256x32x128": 11}
+STATE_SEED = {"annulus2d_q2_32x4": 0, "annulus3d_q2_64x8x32": 3, "annulus3d_q3_64x16x32": 7,
+              "annulus3d_q2_256x32x128": 12}
+VECTOR_SEED = {"annulus2d_q2_32x4": 1, "annulus3d_q2_64x8x32": 4, "annulus3d_q3_64x16x32": 8,
+               "annulus3d_q2_256x32x128": 13}
+SOLUTION_SEED = {"annulus2d_q2_32x4": 14, "annulus3d_q2_64x8x32": 5, "annulus3d_q3_64x16x32": 9,
+                 "annulus3d_q2_256x32x128": 15}
+
+
+def mesh(name, **overrides):
+    m = dict(WORKLOADS[name])
+    m.update(overrides)
+    return m
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform(n, seed, lo=-1.0, hi=1.0):
+    """n values uniform in [lo, hi) from PCG64(seed)."""
+    return rng(seed).uniform(lo, hi, n)
+
+
+def rotor_angle(name):
+    if name == "annulus2d_q2_32x4":
+        return 0.1
+    return float(rng(ANGLE_SEED[name]).uniform(0.0, TWO_PI))
+
+
+def node_grid(m):
+    """Per-direction node counts: (k*n_theta, k*n_r_rotor+1, k*n_r_stator+1, k*n_z+1 or 1)."""
+    k = m["degree"]
+    nzn = k * m["n_z"] + 1 if m["dim"] == 3 else 1
+    return k * m["n_theta"], k * m["n_r_rotor"] + 1, k * m["n_r_stator"] + 1, nzn
+
+
+def n_dofs(m):
+    ntn, nrr, nrs, nzn = node_grid(m)
+    return ntn * (nrr + nrs) * nzn * (m["dim"] + 1)
+
+
+def _index_coords(m):
+    """Approximate node positions from the node indices alone (theta, r, z equally
+    spaced per domain, rotor at zero angle); smooth-field inputs only."""
+    ntn, nrr, nrs, nzn = node_grid(m)
+    out = []
+    for nr_nodes, r0, r1 in ((nrr, m["r_in"], m["r_if"]), (nrs, m["r_if"], m["r_out"])):
+        th = TWO_PI * np.arange(ntn) / ntn
+        r = np.linspace(r0, r1, nr_nodes)
+        z = np.linspace(0.0, m["height"], nzn) if m["dim"] == 3 else np.zeros(1)
+        Z, R, T = np.meshgrid(z, r, th, indexing="ij")
+        out.append((R * np.cos(T)).ravel())
+        out.append((R * np.sin(T)).ravel())
+        out.append(Z.ravel())
+    x = np.concatenate([out[0], out[3]])
+    y = np.concatenate([out[1], out[4]])
+    z = np.concatenate([out[2], out[5]])
+    return x, y, z
+
+
+def smooth_field(m, seed, max_wavenumber=3):
+    """Every component = sum over m, n <= max_wavenumber of
+    A cos(m pi x) cos(n pi y) + B sin sin + C cos sin + D sin cos, coefficients
+    uniform in [-1, 1] (PCG64(seed)); in 3D multiplied by a z series
+    sum_l E_l cos(l pi z) + F_l sin(l pi z).  Returned in DoF layout."""
+    x, y, z = _index_coords(m)
+    nc = m["dim"] + 1
+    g = rng(seed)
+    K = max_wavenumber + 1
+    out = np.empty((x.size, nc))
+    pix, piy, piz = math.pi * x, math.pi * y, math.pi * z
+    cx = [np.cos(i * pix) for i in range(K)]
+    sx = [np.sin(i * pix) for i in range(K)]
+    cy = [np.cos(i * piy) for i in range(K)]
+    sy = [np.sin(i * piy) for i in range(K)]
+    for comp in range(nc):
+        coef = g.uniform(-1.0, 1.0, (K, K, 4))
+        f = np.zeros_like(x)
+        for i in range(K):
+            for j in range(K):
+                A, B, C, D = coef[i, j]
+                f += A * cx[i] * cy[j] + B * sx[i] * sy[j] + C * cx[i] * sy[j] + D * sx[i] * cy[j]
+        if m["dim"] == 3:
+            zc = g.uniform(-1.0, 1.0, (K, 2))
+            fz = np.zeros_like(z)
+            for l in range(K):
+                fz += zc[l, 0] * np.cos(l * piz) + zc[l, 1] * np.sin(l * piz)
+            f *= fz
+        out[:, comp] = f
+    return out.ravel()
+
+
+def state_for(name):
+    """Linearization state of a workload: smooth manufactured field for the 2D
+    case, nodal uniform [-1, 1] otherwise."""
+    m = WORKLOADS[name]
+    if name == "annulus2d_q2_32x4":
+        return smooth_field(m, STATE_SEED[name])
+    return uniform(n_dofs(m), STATE_SEED[name])
+
+
+def vector_for(name):
+    return uniform(n_dofs(WORKLOADS[name]), VECTOR_SEED[name])
