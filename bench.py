@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free stabilized Navier-Stokes Jacobian with mortar
+faces on one MI355X.
+
+Timed region: K applications of the FP64 Jacobian (the metric's unit of work)
+on the 3D Q2 annular rotor/stator workload (64 x 8 x 32 cells per domain,
+1,131,520 DoFs), inputs resident in HBM, bracketed by device synchronization.
+The other rows of the hot path are timed in the same run and reported beside
+the metric: rotor rotation + mortar setup, linearization, the FP32 Jacobian,
+the diagonal, and the FGMRES solve (plain FP64 vs FP32-preconditioned).
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoFs/s of stabilized NS Jacobian vmult (FP64 vs FP32) + GMRES solve time to 1e-8"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="annulus3d_q2_64x8x32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--solve-maxit", type=int, default=4000)
+    ap.add_argument("--solve-restart", type=int, default=300)
+    ap.add_argument("--cheb-degree", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes_volume(mesh, n_dofs, real_bytes):
+    """Minimum HBM bytes of one volume-kernel launch: read src once, write dst
+    once, read the per-point linearization data once (16 values per point in
+    3D, 9 in 2D)."""
+    dim, k = mesh["dim"], mesh["degree"]
+    n = k + 1
+    nz = mesh["n_z"] if dim == 3 else 1
+    cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * nz
+    lin = (16 if dim == 3 else 9) * n ** dim * cells
+    return (2 * n_dofs + lin) * real_bytes, cells
+
+
+def timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    out = fn()
+    sync()
+    return out, time.perf_counter() - t0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
+                                   "(axial slabs, see the design notes)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2608_27423_amd import binding, inputs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    sync = torch.cuda.synchronize
+    name = args.workload
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    omega = mesh["omega"]
+    state_np = inputs.state_for(name)
+    x_np = inputs.vector_for(name)
+    n = x_np.size
+    state = torch.from_numpy(state_np).to(dev)
+    x64 = torch.from_numpy(x_np).to(dev)
+    x32 = x64.float()
+    y64 = torch.empty_like(x64)
+    y32 = torch.empty_like(x32)
+    rec = {}
+    op = binding.Operator(mesh)
+    _, t_rot = timed(lambda: op.rotate_rotor(theta, omega), sync)
+    _, t_lin = timed(lambda: op.set_linearization(state), sync)
+    rec["rotate_rotor_ms"] = 1e3 * t_rot
+    rec["set_linearization_ms"] = 1e3 * t_lin
+
+    def run(src, dst, steps, warmup):
+        for _ in range(warmup):
+            op.apply_jacobian(src, dst)
+        sync()
+        op.enable_timing(steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sync()
+        e0.record()
+        for _ in range(steps):
+            op.apply_jacobian(src, dst)
+        e1.record()
+        sync()
+        ms = e0.elapsed_time(e1) / steps
+        t = op.read_timing()
+        op.enable_timing(0)
+        return ms, t
+
+    ms64, t64 = run(x64, y64, args.steps, args.warmup)
+    ms32, t32 = run(x32, y32, args.steps, args.warmup)
+    sync()
+    err32 = float((y32.double() - y64).abs().max() / y64.abs().max())
+    _, t_diag = timed(lambda: op.compute_diagonal(torch.float64), sync)
+    rec["diagonal_ms"] = 1e3 * t_diag
+
+    vol_ms64 = t64["ms_volume"] / max(1, t64["n_volume"])
+    vol_ms32 = t32["ms_volume"] / max(1, t32["n_volume"])
+    bytes64, cells = algorithmic_bytes_volume(mesh, n, 8)
+    bytes32, _ = algorithmic_bytes_volume(mesh, n, 4)
+    achieved = bytes64 / (vol_ms64 * 1e-3) / 1e9
+    rec["fp64"] = {"ms_per_vmult": ms64, "dofs_per_s": n / (ms64 * 1e-3), "volume_kernel_ms": vol_ms64,
+                   "mortar_kernel_ms": t64["ms_mortar"] / max(1, t64["n_mortar"]),
+                   "other_kernels_ms": t64["ms_other"] / max(1, t64["n_volume"])}
+    rec["fp32"] = {"ms_per_vmult": ms32, "dofs_per_s": n / (ms32 * 1e-3), "volume_kernel_ms": vol_ms32,
+                   "mortar_kernel_ms": t32["ms_mortar"] / max(1, t32["n_mortar"]),
+                   "algorithmic_GBs": bytes32 / (vol_ms32 * 1e-3) / 1e9,
+                   "rel_maxnorm_err_vs_fp64": err32}
+
+    # FGMRES(FP64) solve to 1e-8: plain (FP64 Chebyshev) vs mixed (FP32 Chebyshev)
+    if not args.no_solve:
+        sstate = inputs.smooth_field(mesh, inputs.STATE_SEED[name])
+        sstate /= np.abs(sstate).max()
+        op.set_linearization(torch.from_numpy(sstate).to(dev))
+        xstar = torch.from_numpy(inputs.uniform(n, inputs.SOLUTION_SEED[name])).to(dev)
+        rhs = op.apply_jacobian(xstar)
+        solves = {}
+        for label, prec in (("plain_fp64", "f64"), ("mixed_fp32", "f32")):
+            xs = torch.zeros_like(rhs)
+            sync()
+            _, info = op.solve(rhs, xs, check=False, rtol=1e-8, restart=args.solve_restart,
+                               maxit=args.solve_maxit, precond=prec, cheb_degree=args.cheb_degree)
+            chk = op.apply_jacobian(xs)
+            sync()
+            true_rel = float((rhs - chk).norm() / rhs.norm())
+            solves[label] = {"seconds": info["seconds"], "iterations": info["iterations"],
+                             "converged": info["rc"] == 0, "true_rel_residual": true_rel,
+                             "vmults_f64": info["vmults_f64"], "vmults_f32": info["vmults_f32"],
+                             "lambda_max": info["lambda_max"]}
+        p, m = solves["plain_fp64"], solves["mixed_fp32"]
+        solves["speedup_mixed_over_plain"] = (p["seconds"] / m["seconds"]) if m["seconds"] > 0 else None
+        solves["state"] = "smooth manufactured field scaled to max |u| = 1"
+        solves["preconditioner"] = f"Jacobi-Chebyshev degree {args.cheb_degree}, FGMRES({args.solve_restart})"
+        rec["solve"] = solves
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ocfg = oracle.params(**{k: mesh[k] for k in ("dim", "degree", "r_in", "r_if", "r_out", "height",
+                                                    "n_theta", "n_r_rotor", "n_r_stator", "n_z", "nu",
+                                                    "steady", "dt")}, theta_rot=theta, omega=omega)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        reps, t_cpu, yo = 0, 0.0, None
+        while t_cpu < args.cpu_seconds and reps < 50:
+            t0 = time.perf_counter()
+            yo = oracle.apply_jacobian(ocfg, state_np, x_np)
+            t_cpu += time.perf_counter() - t0
+            reps += 1
+        cpu = {"value": n * reps / t_cpu, "unit": "DoFs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{reps} full FP64 Jacobian applications of {name} ({n} DoFs) by the C oracle "
+                         f"(element by element, full basis tables, OpenMP over 8 cell colours)"}
+        rec["fp64"]["rel_maxnorm_err_vs_oracle"] = float(np.abs(y64.cpu().numpy() - yo).max() / np.abs(yo).max())
+
+    line = {
+        "metric": METRIC,
+        "value": n / (ms64 * 1e-3),
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "dofs": n, "cells": cells, "degree": mesh["degree"], "dim": mesh["dim"],
+                   "rotor_angle": theta, "nu": mesh["nu"], "step": "one FP64 Jacobian application"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_jacobian_volume<double,3,3>",
+                     "algorithmic_bytes_per_launch": bytes64},
+        "cpu_baseline": cpu,
+        "hot_path": rec,
+    }
+    op.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * mortarns.h -- C-ABI of libmortarns.so: matrix-free Jacobian of the
+ * linearized SUPG/PSPG-stabilized ALE incompressible Navier-Stokes operator on
+ * a rotor/stator pair of annular Q_k-Q_k meshes coupled by mortar face
+ * integrals, on one AMD Instinct MI355X (gfx950).
+ *
+ * Operator (arXiv 2608.27423):
+ *   - weak form with mortar interface terms: Sec. 2.1, Eqs. EqMortarPre,
+ *     EqMortarDiff (SIPG), EqPenalty (Hillewaert penalty), EqMortarMass
+ *     (strong-DG mass term), Eq-NSweakWmortar;
+ *   - SUPG/PSPG stabilization with the Tezduyar parameter: Sec. 2.2, Eqs.
+ *     Eq-NSweakComplete, Eq-strong-residual, Eq-stab-param;
+ *   - Newton system and the stabilized Jacobian blocks: Sec. 2.3, Eqs.
+ *     Eq-Newton-method, Eq-Newton-matrix, Eq-discrete-1..4;
+ *   - rigid rotor rotation and mortar segments with a mapped reference
+ *     quadrature: Sec. 3.1, Sec. 3.2, Eq. Eq-Jacobian;
+ *   - diagonal by unit-vector columns of the mortar terms: Alg. Alg-diagonal.
+ *
+ * Conventions fixed by this library where the paper leaves them open: jump and
+ * normal are taken per side (jump = own - other, n = own outward normal, rotor
+ * +e_r, stator -e_r); tau_u is frozen in the Jacobian; h = 2 sqrt(A/pi) (2D),
+ * (6V/pi)^(1/3) (3D); Gauss-Lobatto nodes with k+1 Gauss points per direction;
+ * exact polar geometry; no-slip on every external wall and one pinned pressure
+ * DoF (stator node at theta index 0, outermost radius, z index 0).
+ *
+ * Vector layout (every vector argument): DoF index = node*(d+1) + comp, comps
+ * (u_x, u_y[, u_z], p) in the lab frame's Cartesian axes.  Per domain, nodes are
+ * lexicographic with theta fastest (periodic, k*n_theta positions), then r
+ * (k*n_r+1 positions), then z (k*n_z+1, 3D only).  The rotor block comes first.
+ * Rotor nodes are numbered in the rotor's material frame, so rotation never
+ * permutes a vector.
+ *
+ * Memory and streams: every vector pointer is DEVICE memory on the current HIP
+ * device, contiguous, 8-byte aligned (double) or 4-byte aligned (float).  The
+ * caller owns all vectors; the library owns the handle and its workspace,
+ * which is allocated in mns_setup_mesh, mns_rotate_rotor, mns_set_linearization
+ * and on the first mns_solve, never in mns_apply_*.  Work is enqueued on the
+ * stream argument (a hipStream_t, NULL = default stream) in stream order;
+ * nothing synchronizes the host except mns_solve and mns_n_dofs-like queries.
+ *
+ * Errors: every int-returning call returns MNS_OK (0) or a negative MNS_ERR_*
+ * code; the handle keeps a message readable with mns_last_error.  No C++
+ * exception crosses this interface.  A handle must not be used from two host
+ * threads at once.
+ */
+#ifndef MORTARNS_H
+#define MORTARNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MNS_OK = 0,
+  MNS_ERR_INVALID_ARG = -1,   /* bad size, ordering, null or misaligned pointer */
+  MNS_ERR_HIP = -2,           /* a HIP runtime call failed */
+  MNS_ERR_NOT_LINEARIZED = -3,/* mns_set_linearization has not been called */
+  MNS_ERR_NOT_CONVERGED = -4, /* mns_solve stopped at maxit; x holds the last iterate */
+  MNS_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement */
+  MNS_ERR_NO_ROTATION = -6    /* mns_rotate_rotor has not been called */
+};
+
+enum { MNS_F64 = 0, MNS_F32 = 1 };
+
+typedef struct mns_handle mns_handle;
+
+/* Mesh and physics description (Sec. 2, Sec. 3.1).  Rotor annulus
+ * r_in < r < r_interface, stator annulus r_interface < r < r_out, each with
+ * n_theta azimuthal cells (equal on both sides, Sec. 2.1 / Sec. 3.1), n_r_rotor
+ * resp. n_r_stator radial cells, and in 3D n_z axial layers on [0, height]. */
+typedef struct {
+  int dim;               /* 2 or 3 */
+  int degree;            /* k >= 2: 2..5 in 2D, 2..4 in 3D */
+  double r_in, r_interface, r_out;
+  double height;         /* 3D only */
+  int n_theta, n_r_rotor, n_r_stator, n_z; /* n_z ignored in 2D */
+  double nu;             /* kinematic viscosity > 0 */
+  double penalty_F;      /* F of Eq. EqPenalty, > 0 (1 .. 10 typical) */
+  int penalty_side_rule; /* 0: each side its own cell tau_k; 1: max of both sides */
+  int steady;            /* 1: no time derivative; 0: BDF2 with constant dt */
+  double dt;             /* time step (transient only) */
+} mns_mesh_desc;
+
+/* Create a handle: validates the description, builds the 1D tables, the
+ * constraint list and the per-layer element sizes, and allocates device
+ * tables.  The rotor angle is unset until mns_rotate_rotor.
+ * Errors: INVALID_ARG (k < 2, n_theta < 3, radii not increasing, nu <= 0,
+ * ...), UNSUPPORTED (degree outside the compiled set), HIP. */
+int mns_setup_mesh(const mns_mesh_desc* desc, void* stream, mns_handle** out);
+
+/* Total DoFs and rotor DoFs (the rotor block is [0, n_rotor)). */
+int mns_n_dofs(const mns_handle* h, int64_t* n_total, int64_t* n_rotor);
+
+/* Rigid rotation x = R(theta) x0 of the rotor (Sec. 3.1) and mesh velocity
+ * u_ALE = omega e_z x x in rotor cells.  Rebuilds the mortar segments of every
+ * stator face (one when aligned to 1e-12 of a cell angle, else two), the
+ * mapped quadrature tables of Sec. 3.2 and the rotated geometry tables, all in
+ * FP64 (cast copies for FP32).  Invalidates the linearization.
+ * Errors: INVALID_ARG (non-finite theta or omega), HIP. */
+int mns_rotate_rotor(mns_handle* h, double theta, double omega);
+
+/* Fix the state (u, p) at which the Jacobian is taken (Eq. Eq-Newton-method)
+ * and precompute per quadrature point the convective velocity a = u - u_ALE,
+ * grad u, tau_u (Eq. Eq-stab-param) and tau_u R (Eq. Eq-strong-residual), in
+ * FP64 and FP32.  u_hist: BDF2 history term (-4 u^n + u^(n-1)) / (2 dt) in the
+ * vector layout (pressure slots ignored), or NULL; ignored when steady.
+ * force: body force f in the vector layout, or NULL.  The arrays are read on
+ * `stream` before return of the enqueued work; the library keeps copies.
+ * Errors: NO_ROTATION, INVALID_ARG (null or misaligned state), HIP. */
+int mns_set_linearization(mns_handle* h, const double* state, const double* u_hist, const double* force,
+                          void* stream);
+
+/* dst = J src: the stabilized Jacobian of Sec. 2.3 with the mortar face terms
+ * of Sec. 2.1 at the current angle and linearization.  Constrained columns
+ * read as zero; constrained rows give dst = src.  precision MNS_F64: src and
+ * dst are double*; MNS_F32: float* and the whole product runs in FP32.  src
+ * and dst must not overlap.  Allocates nothing.
+ * Errors: NOT_LINEARIZED, INVALID_ARG, HIP. */
+int mns_apply_jacobian(mns_handle* h, int precision, const void* src, void* dst, void* stream);
+
+/* res = R(state): the discrete nonlinear residual of Eq. Eq-NSweakWmortar plus
+ * the SUPG/PSPG terms of Eq. Eq-NSweakComplete (tau_u from `state`), with the
+ * history and force given at the last mns_set_linearization; constrained rows
+ * are zero.  Allocates nothing.  Errors: NO_ROTATION, INVALID_ARG, HIP. */
+int mns_apply_residual(mns_handle* h, const double* state, double* res, void* stream);
+
+/* diag = diagonal of J (volume columns plus Alg. Alg-diagonal for the mortar
+ * terms); constrained rows are 1.  Errors: NOT_LINEARIZED, INVALID_ARG, HIP. */
+int mns_compute_diagonal(mns_handle* h, int precision, void* diag, void* stream);
+
+typedef struct {
+  double rtol;        /* stop at ||rhs - J x||_2 <= rtol ||rhs||_2 (default 1e-8) */
+  int restart;        /* FGMRES restart length m (default 50) */
+  int maxit;          /* max outer iterations in total (default 2000) */
+  int precond;        /* -1: none, MNS_F64 or MNS_F32: precision of the Chebyshev vmults */
+  int cheb_degree;    /* Chebyshev polynomial degree (default 4) */
+  double cheb_range;  /* ratio lambda_max / lambda_min of the Chebyshev interval (default 30) */
+  int eig_iters;      /* power iterations for lambda_max of D^-1 J (default 20) */
+} mns_solve_opts;
+
+typedef struct {
+  int iterations;         /* outer FGMRES iterations taken */
+  int restarts;
+  int status;             /* MNS_OK or MNS_ERR_NOT_CONVERGED */
+  double rel_residual;    /* true ||rhs - J x||_2 / ||rhs||_2, recomputed in FP64 */
+  double lambda_max;      /* estimate used by the Chebyshev preconditioner */
+  double seconds;         /* wall time of the call */
+  int vmults_f64, vmults_f32;
+} mns_solve_report;
+
+/* Fill opts with the defaults above. */
+void mns_default_solve_opts(mns_solve_opts* opts);
+
+/* Solve J x = rhs with flexible GMRES in FP64 (classical Gram-Schmidt with one
+ * reorthogonalization), right-preconditioned by a Jacobi-Chebyshev polynomial
+ * of D^-1 J whose vmults run in the precision opts->precond.  x holds the
+ * initial guess on entry and the iterate on return; rhs is any device vector
+ * and, since constrained rows of J are identity rows, the constrained entries
+ * of the solution equal those of rhs.  Synchronizes the stream.  The first
+ * call (and any call with a larger restart) allocates the Krylov workspace
+ * (2 * restart + 6 FP64 vectors plus 4 FP32 vectors).
+ * Errors: NOT_LINEARIZED, INVALID_ARG, NOT_CONVERGED (report filled), HIP. */
+int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
+              void* stream);
+
+/* Kernel timing for measurement.  mns_enable_timing(h, capacity) makes every
+ * later mns_apply_jacobian record a pair of HIP events around each of its
+ * kernels on the launch stream (capacity = max recorded launches per kernel
+ * class; the events are created here, not in the apply call); capacity 0
+ * turns timing off.  mns_read_timing synchronizes on those events, returns
+ * the summed milliseconds and launch counts of the volume, mortar and other
+ * (fill, constraint) kernels since the last read, and resets them.
+ * Errors: INVALID_ARG, HIP. */
+typedef struct {
+  double ms_volume, ms_mortar, ms_other;
+  int n_volume, n_mortar, n_other;
+} mns_timing;
+int mns_enable_timing(mns_handle* h, int capacity);
+int mns_read_timing(mns_handle* h, mns_timing* out);
+
+/* Last error message of the handle ("" if none).  Never NULL. */
+const char* mns_last_error(const mns_handle* h);
+
+/* Release the handle and all its device memory (synchronizes its stream). */
+void mns_destroy(mns_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

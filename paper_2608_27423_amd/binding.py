@@ -1,0 +1,248 @@
+"""ctypes binding of libmortarns.so (C-ABI in include/mortarns.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+vectors are torch tensors (contiguous, float64 or float32, on the current HIP
+device); their data pointers and torch's current stream are handed to the
+library.  If the library is missing, `lib()` raises: there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmortarns.so")
+
+MNS_OK = 0
+MNS_ERR_INVALID_ARG = -1
+MNS_ERR_HIP = -2
+MNS_ERR_NOT_LINEARIZED = -3
+MNS_ERR_NOT_CONVERGED = -4
+MNS_ERR_UNSUPPORTED = -5
+MNS_ERR_NO_ROTATION = -6
+MNS_F64 = 0
+MNS_F32 = 1
+
+EXPORTED = [
+    "mns_setup_mesh", "mns_n_dofs", "mns_rotate_rotor", "mns_set_linearization", "mns_apply_jacobian",
+    "mns_apply_residual", "mns_compute_diagonal", "mns_default_solve_opts", "mns_solve", "mns_enable_timing",
+    "mns_read_timing", "mns_last_error", "mns_destroy",
+]
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("degree", ctypes.c_int),
+        ("r_in", ctypes.c_double), ("r_interface", ctypes.c_double), ("r_out", ctypes.c_double),
+        ("height", ctypes.c_double),
+        ("n_theta", ctypes.c_int), ("n_r_rotor", ctypes.c_int), ("n_r_stator", ctypes.c_int), ("n_z", ctypes.c_int),
+        ("nu", ctypes.c_double), ("penalty_F", ctypes.c_double), ("penalty_side_rule", ctypes.c_int),
+        ("steady", ctypes.c_int), ("dt", ctypes.c_double),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
+        ("cheb_degree", ctypes.c_int), ("cheb_range", ctypes.c_double), ("eig_iters", ctypes.c_int),
+    ]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
+        ("rel_residual", ctypes.c_double), ("lambda_max", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("vmults_f64", ctypes.c_int), ("vmults_f32", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [
+        ("ms_volume", ctypes.c_double), ("ms_mortar", ctypes.c_double), ("ms_other", ctypes.c_double),
+        ("n_volume", ctypes.c_int), ("n_mortar", ctypes.c_int), ("n_other", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libmortarns.so; raises FileNotFoundError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is missing: build it with paper_2608_27423_amd/build_lib.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+        L.mns_setup_mesh.argtypes = [ctypes.POINTER(MeshDesc), vp, ctypes.POINTER(vp)]
+        L.mns_n_dofs.argtypes = [vp, i64p, i64p]
+        L.mns_rotate_rotor.argtypes = [vp, ctypes.c_double, ctypes.c_double]
+        L.mns_set_linearization.argtypes = [vp, vp, vp, vp, vp]
+        L.mns_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mns_apply_residual.argtypes = [vp, vp, vp, vp]
+        L.mns_compute_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
+        L.mns_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
+        L.mns_default_solve_opts.restype = None
+        L.mns_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), vp]
+        L.mns_enable_timing.argtypes = [vp, ctypes.c_int]
+        L.mns_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.mns_last_error.argtypes = [vp]
+        L.mns_last_error.restype = ctypes.c_char_p
+        L.mns_destroy.argtypes = [vp]
+        L.mns_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+class MnsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmortarns error {code}: {msg}")
+        self.code = code
+
+
+def mesh_desc(mesh):
+    """MeshDesc from a workload dictionary (see inputs.WORKLOADS)."""
+    return MeshDesc(
+        dim=int(mesh["dim"]), degree=int(mesh["degree"]), r_in=float(mesh["r_in"]),
+        r_interface=float(mesh["r_if"]), r_out=float(mesh["r_out"]), height=float(mesh.get("height", 1.0)),
+        n_theta=int(mesh["n_theta"]), n_r_rotor=int(mesh["n_r_rotor"]), n_r_stator=int(mesh["n_r_stator"]),
+        n_z=int(mesh.get("n_z", 1)), nu=float(mesh["nu"]), penalty_F=float(mesh.get("penalty_F", 1.0)),
+        penalty_side_rule=int(mesh.get("penalty_rule", 0)), steady=int(mesh.get("steady", 1)),
+        dt=float(mesh.get("dt", 1.0)),
+    )
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """Handle around one rotor/stator problem (one mns_handle)."""
+
+    def __init__(self, mesh):
+        self._L = lib()
+        self._h = ctypes.c_void_p()
+        self.mesh = dict(mesh)
+        desc = mesh_desc(mesh)
+        rc = self._L.mns_setup_mesh(ctypes.byref(desc), _stream(), ctypes.byref(self._h))
+        if rc != MNS_OK:
+            msg = self.last_error()
+            self.close()
+            raise MnsError(rc, msg)
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._L.mns_n_dofs(self._h, ctypes.byref(a), ctypes.byref(b)))
+        self.n_dofs, self.n_rotor = a.value, b.value
+
+    def last_error(self):
+        if not self._h:
+            return ""
+        return self._L.mns_last_error(self._h).decode()
+
+    def _check(self, rc):
+        if rc != MNS_OK:
+            raise MnsError(rc, self.last_error())
+        return rc
+
+    def rotate_rotor(self, theta, omega):
+        return self._check(self._L.mns_rotate_rotor(self._h, float(theta), float(omega)))
+
+    def set_linearization(self, state, hist=None, force=None):
+        self._keep = (state, hist, force)
+        return self._check(self._L.mns_set_linearization(self._h, _ptr(state), _ptr(hist), _ptr(force), _stream()))
+
+    def apply_jacobian(self, src, dst=None):
+        import torch
+
+        if dst is None:
+            dst = torch.empty_like(src)
+        prec = MNS_F64 if src.dtype == torch.float64 else MNS_F32
+        if src.dtype not in (torch.float64, torch.float32) or dst.dtype != src.dtype:
+            raise ValueError("src/dst must both be float64 or both float32")
+        if src.numel() != self.n_dofs or dst.numel() != self.n_dofs:
+            raise ValueError("vector length != n_dofs")
+        self._check(self._L.mns_apply_jacobian(self._h, prec, _ptr(src), _ptr(dst), _stream()))
+        return dst
+
+    def apply_residual(self, state, res=None):
+        import torch
+
+        if res is None:
+            res = torch.empty_like(state)
+        if state.dtype != torch.float64 or state.numel() != self.n_dofs:
+            raise ValueError("state must be float64 of length n_dofs")
+        self._check(self._L.mns_apply_residual(self._h, _ptr(state), _ptr(res), _stream()))
+        return res
+
+    def compute_diagonal(self, dtype=None, out=None):
+        import torch
+
+        dtype = dtype or torch.float64
+        if out is None:
+            out = torch.empty(self.n_dofs, dtype=dtype, device="cuda")
+        prec = MNS_F64 if out.dtype == torch.float64 else MNS_F32
+        self._check(self._L.mns_compute_diagonal(self._h, prec, _ptr(out), _stream()))
+        return out
+
+    @staticmethod
+    def default_solve_opts():
+        o = SolveOpts()
+        lib().mns_default_solve_opts(ctypes.byref(o))
+        return o
+
+    def solve(self, rhs, x=None, check=True, **opts):
+        """FGMRES(FP64) with a Jacobi-Chebyshev preconditioner; returns (x, report dict)."""
+        import torch
+
+        o = self.default_solve_opts()
+        for k, v in opts.items():
+            if k == "precond" and isinstance(v, str):
+                v = {"none": -1, "f64": MNS_F64, "f32": MNS_F32}[v]
+            setattr(o, k, v)
+        if x is None:
+            x = torch.zeros_like(rhs)
+        rep = SolveReport()
+        rc = self._L.mns_solve(self._h, _ptr(rhs), _ptr(x), ctypes.byref(o), ctypes.byref(rep), _stream())
+        if check and rc not in (MNS_OK,):
+            raise MnsError(rc, self.last_error())
+        d = rep.as_dict()
+        d["rc"] = rc
+        return x, d
+
+    def enable_timing(self, capacity):
+        return self._check(self._L.mns_enable_timing(self._h, int(capacity)))
+
+    def read_timing(self):
+        t = Timing()
+        self._check(self._L.mns_read_timing(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mns_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

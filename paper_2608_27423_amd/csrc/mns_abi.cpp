@@ -1,0 +1,286 @@
+// extern "C" entry points of libmortarns (declared in include/mortarns.h).
+// Every entry point validates its arguments, maps failures to MNS_ERR_* codes
+// and never lets a C++ exception cross the interface.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <new>
+#include <string>
+
+#include "mns_internal.hpp"
+
+using namespace mns;
+
+int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h);
+int mns_rotate_tables(mns_handle* h, double theta, double omega);
+int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* rep,
+                   hipStream_t s);
+
+static void free_events(mns_handle* h) {
+  for (int c = 0; c < 3; ++c) {
+    for (hipEvent_t e : h->ev[c]) (void)hipEventDestroy(e);
+    h->ev[c].clear();
+    h->ev_used[c] = 0;
+  }
+  h->timing_cap = 0;
+}
+
+static void free_all(mns_handle* h) {
+  free_events(h);
+  void* ptrs[] = {h->d_hcell64, h->d_hcell32, h->d_trig64, h->d_trig32, h->d_mtab64, h->d_mtab32, h->d_mtrig64,
+                  h->d_mtrig32, h->d_cons, h->d_lin64, h->d_lin32, h->d_hist, h->d_force, h->ws64, h->ws32,
+                  h->d_diag64, h->d_diag32, h->d_red};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->h_red) (void)hipHostFree(h->h_red);
+}
+
+static bool aligned(const void* p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
+
+static hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+extern "C" {
+
+int mns_setup_mesh(const mns_mesh_desc* desc, void* stream, mns_handle** out) {
+  if (!desc || !out) return MNS_ERR_INVALID_ARG;
+  *out = nullptr;
+  mns_handle* h = new (std::nothrow) mns_handle();
+  if (!h) return MNS_ERR_HIP;
+  int rc;
+  try {
+    rc = mns_build_handle(desc, as_stream(stream), h);
+  } catch (...) {
+    rc = MNS_ERR_HIP;
+  }
+  if (rc != MNS_OK) {
+    // keep the handle so the caller can read the message; it holds no rotation
+    free_all(h);
+    h->d_hcell64 = nullptr;
+    h->d_hcell32 = nullptr;
+    h->d_cons = nullptr;
+    h->d_trig64 = nullptr;
+    h->d_trig32 = nullptr;
+    h->d_mtab64 = h->d_mtab32 = nullptr;
+    h->d_mtrig64 = nullptr;
+    h->d_mtrig32 = nullptr;
+    h->d_lin64 = nullptr;
+    h->d_lin32 = nullptr;
+    h->d_hist = h->d_force = nullptr;
+    h->ws64 = nullptr;
+    h->ws32 = nullptr;
+    h->d_diag64 = nullptr;
+    h->d_diag32 = nullptr;
+    h->d_red = nullptr;
+    h->h_red = nullptr;
+    *out = h;
+    return rc;
+  }
+  *out = h;
+  return MNS_OK;
+}
+
+int mns_n_dofs(const mns_handle* h, int64_t* n_total, int64_t* n_rotor) {
+  if (!h || !n_total || !n_rotor) return MNS_ERR_INVALID_ARG;
+  *n_total = h->ndofs;
+  *n_rotor = h->node_off1 * h->nc;
+  return MNS_OK;
+}
+
+int mns_rotate_rotor(mns_handle* h, double theta, double omega) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (h->ndofs == 0) return set_error(h, MNS_ERR_INVALID_ARG, "handle was not set up");
+  if (!std::isfinite(theta) || !std::isfinite(omega))
+    return set_error(h, MNS_ERR_INVALID_ARG, "theta and omega must be finite");
+  // the tables are rewritten in place: drain every stream that may read them
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return set_error(h, MNS_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+  int rc;
+  try {
+    rc = mns_rotate_tables(h, theta, omega);
+  } catch (...) {
+    rc = set_error(h, MNS_ERR_HIP, "exception in rotate");
+  }
+  h->rotated = rc == MNS_OK;
+  h->linearized = false;
+  h->diag_valid = false;
+  return rc;
+}
+
+int mns_set_linearization(mns_handle* h, const double* state, const double* u_hist, const double* force,
+                          void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->rotated) return set_error(h, MNS_ERR_NO_ROTATION, "call mns_rotate_rotor first");
+  if (!aligned(state, 8)) return set_error(h, MNS_ERR_INVALID_ARG, "state must be a non-null 8-byte aligned pointer");
+  if ((u_hist && !aligned(u_hist, 8)) || (force && !aligned(force, 8)))
+    return set_error(h, MNS_ERR_INVALID_ARG, "history/force must be 8-byte aligned");
+  hipStream_t s = as_stream(stream);
+  const int LS = h->dim == 3 ? LinLayout<3>::SIZE : LinLayout<2>::SIZE;
+  const size_t nlin = (size_t)h->ncells * (size_t)(h->dim == 3 ? h->n * h->n * h->n : h->n * h->n) * LS;
+  hipError_t e;
+  if (!h->d_lin64) {
+    if ((e = hipMalloc((void**)&h->d_lin64, nlin * sizeof(double))) != hipSuccess)
+      return set_error(h, MNS_ERR_HIP, std::string("hipMalloc lin: ") + hipGetErrorString(e));
+    if ((e = hipMalloc((void**)&h->d_lin32, nlin * sizeof(float))) != hipSuccess)
+      return set_error(h, MNS_ERR_HIP, std::string("hipMalloc lin32: ") + hipGetErrorString(e));
+  }
+  // keep copies of the history and force for mns_apply_residual
+  const double* srcs[2] = {u_hist, force};
+  double** dsts[2] = {&h->d_hist, &h->d_force};
+  for (int i = 0; i < 2; ++i) {
+    if (srcs[i]) {
+      if (!*dsts[i] && (e = hipMalloc((void**)dsts[i], h->ndofs * sizeof(double))) != hipSuccess)
+        return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+      if ((e = hipMemcpyAsync(*dsts[i], srcs[i], h->ndofs * sizeof(double), hipMemcpyDeviceToDevice, s)) !=
+          hipSuccess)
+        return set_error(h, MNS_ERR_HIP, std::string("copy: ") + hipGetErrorString(e));
+    } else if (*dsts[i]) {
+      (void)hipFree(*dsts[i]);
+      *dsts[i] = nullptr;
+    }
+  }
+  int rc = launch_linearize<double>(h, state, h->desc.steady ? nullptr : h->d_hist, h->d_force, h->d_lin64, s);
+  if (rc) return rc;
+  rc = mns::launch_cast_f64_f32(h->d_lin64, h->d_lin32, (int64_t)nlin, s);
+  if (rc) return set_error(h, rc, "cast");
+  h->linearized = true;
+  h->diag_valid = false;
+  return MNS_OK;
+}
+
+int mns_apply_jacobian(mns_handle* h, int precision, const void* src, void* dst, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (src == dst) return set_error(h, MNS_ERR_INVALID_ARG, "src and dst must not overlap");
+  try {
+    if (precision == MNS_F64) {
+      if (!aligned(src, 8) || !aligned(dst, 8)) return set_error(h, MNS_ERR_INVALID_ARG, "misaligned or null vector");
+      return launch_jacobian<double>(h, (const double*)src, (double*)dst, as_stream(stream));
+    }
+    if (precision == MNS_F32) {
+      if (!aligned(src, 4) || !aligned(dst, 4)) return set_error(h, MNS_ERR_INVALID_ARG, "misaligned or null vector");
+      return launch_jacobian<float>(h, (const float*)src, (float*)dst, as_stream(stream));
+    }
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in apply_jacobian");
+  }
+  return set_error(h, MNS_ERR_INVALID_ARG, "precision must be MNS_F64 or MNS_F32");
+}
+
+int mns_apply_residual(mns_handle* h, const double* state, double* res, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->rotated) return set_error(h, MNS_ERR_NO_ROTATION, "call mns_rotate_rotor first");
+  if (!aligned(state, 8) || !aligned(res, 8) || state == res)
+    return set_error(h, MNS_ERR_INVALID_ARG, "state/res must be distinct 8-byte aligned pointers");
+  try {
+    return launch_residual(h, state, res, as_stream(stream));
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in apply_residual");
+  }
+}
+
+int mns_compute_diagonal(mns_handle* h, int precision, void* diag, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  try {
+    if (precision == MNS_F64) {
+      if (!aligned(diag, 8)) return set_error(h, MNS_ERR_INVALID_ARG, "misaligned or null vector");
+      return launch_diagonal<double>(h, (double*)diag, as_stream(stream));
+    }
+    if (precision == MNS_F32) {
+      if (!aligned(diag, 4)) return set_error(h, MNS_ERR_INVALID_ARG, "misaligned or null vector");
+      return launch_diagonal<float>(h, (float*)diag, as_stream(stream));
+    }
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in compute_diagonal");
+  }
+  return set_error(h, MNS_ERR_INVALID_ARG, "precision must be MNS_F64 or MNS_F32");
+}
+
+void mns_default_solve_opts(mns_solve_opts* o) {
+  if (!o) return;
+  o->rtol = 1e-8;
+  o->restart = 50;
+  o->maxit = 2000;
+  o->precond = MNS_F32;
+  o->cheb_degree = 4;
+  o->cheb_range = 30.0;
+  o->eig_iters = 20;
+}
+
+int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
+              void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (!aligned(rhs, 8) || !aligned(x, 8) || rhs == x)
+    return set_error(h, MNS_ERR_INVALID_ARG, "rhs/x must be distinct 8-byte aligned pointers");
+  mns_solve_opts o;
+  mns_default_solve_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.rtol > 0) || o.restart < 1 || o.restart > 1000 || o.maxit < 1 || o.cheb_degree < 1 ||
+      o.cheb_degree > 100 || !(o.cheb_range > 1) || o.eig_iters < 1 ||
+      (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32))
+    return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
+  mns_solve_report rep{};
+  int rc;
+  try {
+    rc = mns_solve_impl(h, rhs, x, &o, &rep, as_stream(stream));
+  } catch (...) {
+    rc = set_error(h, MNS_ERR_HIP, "exception in solve");
+  }
+  if (report) *report = rep;
+  return rc;
+}
+
+int mns_enable_timing(mns_handle* h, int capacity) {
+  if (!h || capacity < 0) return MNS_ERR_INVALID_ARG;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return set_error(h, MNS_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+  free_events(h);
+  for (int c = 0; c < 3; ++c) {
+    h->ev[c].resize(2 * (size_t)capacity);
+    for (int i = 0; i < 2 * capacity; ++i)
+      if ((e = hipEventCreate(&h->ev[c][i])) != hipSuccess) {
+        h->ev[c].resize(i);
+        free_events(h);
+        return set_error(h, MNS_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+      }
+  }
+  h->timing_cap = capacity;
+  return MNS_OK;
+}
+
+int mns_read_timing(mns_handle* h, mns_timing* out) {
+  if (!h || !out) return MNS_ERR_INVALID_ARG;
+  double ms[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < h->ev_used[c]; ++i) {
+      hipError_t e = hipEventSynchronize(h->ev[c][2 * i + 1]);
+      float t = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, h->ev[c][2 * i], h->ev[c][2 * i + 1]);
+      if (e != hipSuccess) return set_error(h, MNS_ERR_HIP, std::string("event: ") + hipGetErrorString(e));
+      ms[c] += t;
+    }
+  out->ms_volume = ms[0];
+  out->ms_mortar = ms[1];
+  out->ms_other = ms[2];
+  out->n_volume = h->ev_used[0];
+  out->n_mortar = h->ev_used[1];
+  out->n_other = h->ev_used[2];
+  for (int c = 0; c < 3; ++c) h->ev_used[c] = 0;
+  return MNS_OK;
+}
+
+const char* mns_last_error(const mns_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+void mns_destroy(mns_handle* h) {
+  if (!h) return;
+  if (h->d_cons) {  // the handle reached the device: drain its work first
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+  }
+  free_all(h);
+  delete h;
+}
+
+}  // extern "C"

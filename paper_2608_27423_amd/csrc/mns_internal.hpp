@@ -1,0 +1,172 @@
+// Internal declarations of libmortarns: handle, device-side parameter blocks
+// and kernel launchers.  Not part of the public C-ABI (include/mortarns.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mortarns.h"
+
+namespace mns {
+
+constexpr int kMaxN = 6;  // points per direction: degree 2..5
+
+// Per-quadrature-point linearization data (Sec. 2.3: the state enters the
+// Jacobian only through these): a = u - u_ALE (d), grad u (d*d, row m = u_m),
+// tau_u (1), tau_u * R (d).  16 values in 3D, 9 in 2D.
+template <int DIM>
+struct LinLayout {
+  static constexpr int A = 0;
+  static constexpr int GU = DIM;
+  static constexpr int TAU = DIM + DIM * DIM;
+  static constexpr int TR = TAU + 1;
+  static constexpr int SIZE = TR + DIM;
+};
+
+// 1D tables: Lagrange basis on N Gauss-Lobatto nodes of [0,1] evaluated at the
+// N Gauss points (the volume quadrature of every cell).
+template <typename Real, int N>
+struct Tab1D {
+  Real V[N][N];   // V[q][a]  = L_a(x_q)
+  Real D[N][N];   // D[q][a]  = L_a'(x_q)
+  Real DD[N][N];  // DD[q][a] = L_a''(x_q)
+  Real x[N];      // Gauss points on [0,1]
+  Real w[N];      // Gauss weights on [0,1]
+};
+
+// Structured annular geometry: cell and node numbering, radial spacing and
+// physics constants of one launch.
+template <typename Real>
+struct Geom {
+  long long ncells;     // both domains
+  long long cell_off1;  // first stator cell
+  long long node_off1;  // first stator node
+  long long ndofs;
+  int n_theta, nz;      // cells per ring, axial layers (1 in 2D)
+  int ntn, nzn;         // nodes per ring, axial node planes (1 in 2D)
+  int nr[2], nrn[2];    // radial cells / node rows per domain
+  Real r0[2], dr[2];    // inner radius and radial cell size per domain
+  Real dth, dz;         // cell angle, layer height (1 in 2D)
+  Real nu, omega;
+  Real ct;              // BDF2 coefficient 3/(2 dt), 0 when steady
+  Real ctau2;           // (1/dt)^2 in tau_u, 0 when steady
+  Real h[2];            // element size per domain for each radial layer: see hcell
+  const Real* hcell;    // [2][hstride] element size by (domain, radial layer)
+  int hstride;
+  const Real* trig;     // [2][n_theta][N][2]: cos, sin of theta at (domain, cell, Gauss point)
+};
+
+// Mortar quadrature tables for the current rotor angle (Sec. 3.2).  Segment 0
+// of stator face j spans [j dth, j dth + phi], segment 1 [j dth + phi, (j+1) dth];
+// the rotor face on segment 0 is j - m - 1, on segment 1 it is j - m (mod n_theta).
+template <typename Real, int N>
+struct MortarTab {
+  Real MV[2][2][N][N];  // [side][seg][q][a]: L_a at the side's theta-coordinate of mortar point q
+  Real MD[2][2][N][N];  // d/dxi_theta of the same
+  Real FV[2][N];        // [side][b]: L_b at the interface (xi_r = 1 rotor, 0 stator)
+  Real FD[2][N];        // L_b' at the interface
+  Real jxw[2][N][N];    // [seg][q_theta][q_z]: w R dtheta_seg (* w dz in 3D)
+  Real tau_pen[2];      // penalty of the side's interface cells (Eq. EqPenalty)
+  Real R;
+  int seg_active[2];
+  int m;                // pairing offset, in [0, n_theta)
+};
+
+struct Buffers {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace mns
+
+struct mns_handle {
+  mns_mesh_desc desc{};
+  int dim = 0, k = 0, n = 0, nc = 0;
+  int ntn = 0, nzn = 0, nz = 0;
+  int nrn[2] = {0, 0};
+  int64_t ncells = 0, cell_off1 = 0, node_off1 = 0, nnodes = 0, ndofs = 0;
+  double dth = 0, dz = 0;
+  std::vector<double> gll, gx, gw;  // 1D rules
+  std::vector<double> hcell;        // [2][hstride]
+  int hstride = 0;
+  double tau_pen[2] = {0, 0};
+  bool rotated = false, linearized = false;
+  double theta = 0, omega = 0;
+  int m = 0;
+  double phi = 0;
+  // device buffers
+  double* d_hcell64 = nullptr;
+  float* d_hcell32 = nullptr;
+  double* d_trig64 = nullptr;
+  float* d_trig32 = nullptr;
+  void* d_mtab64 = nullptr;  // MortarTab<double, N>
+  void* d_mtab32 = nullptr;  // MortarTab<float, N>
+  double* d_mtrig64 = nullptr;  // [n_theta][2][N][2] cos/sin at the mortar points of stator faces
+  float* d_mtrig32 = nullptr;
+  int64_t* d_cons = nullptr;    // constrained DoF indices (sorted)
+  int64_t n_cons = 0;
+  double* d_lin64 = nullptr;    // per-qp linearization data
+  float* d_lin32 = nullptr;
+  double* d_hist = nullptr;     // copies of the BDF2 history / force (or null)
+  double* d_force = nullptr;
+  // solver workspace
+  int ws_restart = 0;
+  double* ws64 = nullptr;
+  float* ws32 = nullptr;
+  double* d_diag64 = nullptr;
+  float* d_diag32 = nullptr;
+  double* d_red = nullptr;      // reduction scratch
+  double* h_red = nullptr;      // pinned host mirror
+  int red_cap = 0;
+  bool diag_valid = false;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // optional kernel timing (mns_enable_timing): event pairs per kernel class
+  int timing_cap = 0;
+  std::vector<hipEvent_t> ev[3];  // 2 * cap events per class: volume, mortar, other
+  int ev_used[3] = {0, 0, 0};
+};
+
+namespace mns {
+
+// kernel launchers (mns_kernels.hip)
+template <typename Real>
+int launch_linearize(mns_handle* h, const double* state, const double* hist, const double* force,
+                     Real* lin, hipStream_t s);
+template <typename Real>
+int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s);
+int launch_residual(mns_handle* h, const double* state, double* res, hipStream_t s);
+template <typename Real>
+int launch_diagonal(mns_handle* h, Real* diag, hipStream_t s);
+template <typename Real>
+int launch_fill(Real* x, Real v, int64_t n, hipStream_t s);
+template <typename Real>
+int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real diag_value, int mode,
+                       hipStream_t s);
+
+// vector casts (mns_solver.hip)
+int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s);
+int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
+
+// host setup (mns_setup.cpp)
+void rules_1d(int n, std::vector<double>& gll, std::vector<double>& gx, std::vector<double>& gw);
+void lagrange_1d(const std::vector<double>& nodes, double t, double* L, double* dL, double* d2L);
+
+int set_error(mns_handle* h, int code, const std::string& msg);
+
+// timing hooks around a kernel launch (no-ops unless timing is enabled)
+enum { TIMER_VOLUME = 0, TIMER_MORTAR = 1, TIMER_OTHER = 2 };
+inline void timer_begin(mns_handle* h, int cls, hipStream_t s) {
+  if (h->timing_cap && h->ev_used[cls] < h->timing_cap) (void)hipEventRecord(h->ev[cls][2 * h->ev_used[cls]], s);
+}
+inline void timer_end(mns_handle* h, int cls, hipStream_t s) {
+  if (h->timing_cap && h->ev_used[cls] < h->timing_cap) {
+    (void)hipEventRecord(h->ev[cls][2 * h->ev_used[cls] + 1], s);
+    ++h->ev_used[cls];
+  }
+}
+
+}  // namespace mns

@@ -1,0 +1,1191 @@
+// Volume, mortar, diagonal and constraint kernels of the stabilized ALE
+// Navier-Stokes Jacobian (gfx950).
+//
+// Work decomposition of the volume kernels: one 64-lane wavefront per block;
+// each cell is handled by N*N lanes (lane t owns the node/point line at
+// (i_theta, i_r) = (t % N, t / N) along z).  The z contraction of the
+// sum-factorized evaluation runs in registers, the r and theta contractions
+// go through LDS.  2D is the same code with a line of length one.
+//
+// Scatter: FP64/FP32 atomic adds into a zeroed destination; constrained rows
+// are overwritten afterwards by the constraint kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mns_internal.hpp"
+
+namespace mns {
+
+template <typename Real, int DIM, int N>
+struct Shape {
+  static constexpr int NZ = (DIM == 3) ? N : 1;  // line length along z
+  static constexpr int PLANE = N * N;
+  static constexpr int TPC = N * N;              // lanes per cell
+  static constexpr int CPW = 64 / TPC;           // cells per wavefront
+  static constexpr int NPT = PLANE * NZ;         // nodes (= quadrature points) per cell
+  static constexpr int NC = DIM + 1;             // components
+  static constexpr int NYV = (DIM == 3) ? 5 : 3; // r-stage outputs per velocity component
+  static constexpr int NYP = (DIM == 3) ? 3 : 2; // r-stage outputs of the pressure
+  static constexpr int NT = DIM + 1;             // test coefficients per component
+  static constexpr int EVAL_SLOTS = DIM * NYV + NYP;
+  static constexpr int TEST_SLOTS = NC * NT;
+  static constexpr int SLOTS = (EVAL_SLOTS > TEST_SLOTS) ? EVAL_SLOTS : TEST_SLOTS;
+};
+
+struct CellId {
+  int dom, ct, cr, cz;
+};
+
+template <typename Real>
+__device__ inline CellId decode_cell(const Geom<Real>& G, int cell) {
+  CellId c;
+  c.dom = cell >= (int)G.cell_off1;
+  int l = cell - (c.dom ? (int)G.cell_off1 : 0);
+  c.ct = l % G.n_theta;
+  l /= G.n_theta;
+  c.cr = l % G.nr[c.dom];
+  c.cz = l / G.nr[c.dom];
+  return c;
+}
+
+// global node of local node (a, b, c) of cell C; also returns the node's
+// structured indices for the constraint predicates
+template <typename Real, int DIM>
+__device__ inline long long node_of(const Geom<Real>& G, int k, const CellId& C, int a, int b, int c, int& it,
+                                    int& ir, int& iz) {
+  it = k * C.ct + a;
+  if (it >= G.ntn) it -= G.ntn;
+  ir = k * C.cr + b;
+  iz = (DIM == 3) ? k * C.cz + c : 0;
+  long long base = C.dom ? G.node_off1 : 0;
+  return base + it + (long long)G.ntn * (ir + (long long)G.nrn[C.dom] * iz);
+}
+
+template <typename Real, int DIM>
+__device__ inline bool vel_fixed(const Geom<Real>& G, int dom, int ir, int iz) {
+  if (dom == 0 && ir == 0) return true;
+  if (dom == 1 && ir == G.nrn[1] - 1) return true;
+  if (DIM == 3 && (iz == 0 || iz == G.nzn - 1)) return true;
+  return false;
+}
+
+template <typename Real>
+__device__ inline bool p_fixed(const Geom<Real>& G, int dom, int it, int ir, int iz) {
+  return dom == 1 && it == 0 && ir == G.nrn[1] - 1 && iz == 0;
+}
+
+template <typename T>
+__device__ inline void atomic_add(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation: nodal line values -> reference values and derivatives at the
+// lane's points (i_theta = tqi, i_r = tqj, all z points).
+// ---------------------------------------------------------------------------
+
+// reference derivatives of one component at one point
+template <typename Real, int DIM>
+struct RefVal {
+  Real v;
+  Real d[DIM];   // d/dxi_theta, d/dxi_r [, d/dxi_z]
+  Real dd[DIM];  // second derivatives along the same directions
+};
+
+// Stage 1 of the evaluation (z in registers) and write to LDS; u[comp][c] is
+// the lane's nodal line.  Velocity components use slots comp*NYV + {0: V,
+// 1: D, 2: DD}; the pressure slots DIM*NYV + {0: V, 1: D}.  In 2D the line has
+// one node and only the value slot is written.
+template <typename Real, int DIM, int N, int NCOMP_V, bool PRES>
+__device__ inline void eval_stage_z(const Tab1D<Real, N>& T, const Real (*u)[Shape<Real, DIM, N>::NZ], Real* L,
+                                    int ta, int tb, bool active) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NZ = S::NZ;
+  if (!active) return;
+#pragma unroll
+  for (int m = 0; m < NCOMP_V + (PRES ? 1 : 0); ++m) {
+    const bool vel = m < NCOMP_V;
+    const int base = vel ? m * S::NYV : NCOMP_V * S::NYV;
+    if constexpr (DIM == 3) {
+#pragma unroll
+      for (int q = 0; q < NZ; ++q) {
+        Real sv = 0, sd = 0, sdd = 0;
+#pragma unroll
+        for (int c = 0; c < NZ; ++c) {
+          sv += T.V[q][c] * u[m][c];
+          sd += T.D[q][c] * u[m][c];
+          if (vel) sdd += T.DD[q][c] * u[m][c];
+        }
+        const int idx = q * S::PLANE + tb * N + ta;
+        L[(base + 0) * S::NPT + idx] = sv;
+        L[(base + 1) * S::NPT + idx] = sd;
+        if (vel) L[(base + 2) * S::NPT + idx] = sdd;
+      }
+    } else {
+      L[base * S::NPT + tb * N + ta] = u[m][0];
+    }
+  }
+}
+
+// Stage 2 (r through LDS).  Lane (ta, tqj) reads the column (b = 0..N-1) of
+// its theta node and writes back, after a barrier, the r-contracted arrays:
+// velocity {VV, DV, DDV, VD, VDD} (3D) or {V, D, DD} (2D); pressure {VV, DV, VD}
+// (3D) or {V, D} (2D).  First letter: r operator, second: z operator.
+template <typename Real, int DIM, int N, int NCOMP_V, bool PRES>
+__device__ inline void eval_stage_r(const Tab1D<Real, N>& T, Real* L, int ta, int tqj, bool active) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NZ = S::NZ;
+  constexpr int NF = NCOMP_V + (PRES ? 1 : 0);
+  Real out[NF][S::NYV][NZ];
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const bool vel = m < NCOMP_V;
+      const int base = vel ? m * S::NYV : NCOMP_V * S::NYV;
+#pragma unroll
+      for (int q = 0; q < NZ; ++q) {
+        Real vv = 0, dv = 0, ddv = 0, vd = 0, vdd = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const int idx = q * S::PLANE + b * N + ta;
+          const Real zv = L[(base + 0) * S::NPT + idx];
+          vv += T.V[tqj][b] * zv;
+          dv += T.D[tqj][b] * zv;
+          if (vel) ddv += T.DD[tqj][b] * zv;
+          if constexpr (DIM == 3) {
+            const Real zd = L[(base + 1) * S::NPT + idx];
+            vd += T.V[tqj][b] * zd;
+            if (vel) vdd += T.V[tqj][b] * L[(base + 2) * S::NPT + idx];
+          }
+        }
+        out[m][0][q] = vv;
+        out[m][1][q] = dv;
+        if constexpr (DIM == 3) {
+          if (vel) {
+            out[m][2][q] = ddv;
+            out[m][3][q] = vd;
+            out[m][4][q] = vdd;
+          } else {
+            out[m][2][q] = vd;
+          }
+        } else {
+          if (vel) out[m][2][q] = ddv;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const bool vel = m < NCOMP_V;
+      const int base = vel ? m * S::NYV : NCOMP_V * S::NYV;
+      const int nout = vel ? S::NYV : S::NYP;
+#pragma unroll
+      for (int j = 0; j < S::NYV; ++j) {
+        if (j >= nout) break;
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) L[(base + j) * S::NPT + q * S::PLANE + tqj * N + ta] = out[m][j][q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Stage 3 (theta through LDS) for one z point q: lane (tqi, tqj).
+template <typename Real, int DIM, int N>
+__device__ inline void eval_stage_t_vel(const Tab1D<Real, N>& T, const Real* L, int base, int tqi, int tqj, int q,
+                                        RefVal<Real, DIM>& r) {
+  using S = Shape<Real, DIM, N>;
+  Real v = 0, dt = 0, ddt = 0, dr = 0, ddr = 0, dz = 0, ddz = 0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const int idx = q * S::PLANE + tqj * N + a;
+    const Real yvv = L[(base + 0) * S::NPT + idx];
+    v += T.V[tqi][a] * yvv;
+    dt += T.D[tqi][a] * yvv;
+    ddt += T.DD[tqi][a] * yvv;
+    dr += T.V[tqi][a] * L[(base + 1) * S::NPT + idx];
+    ddr += T.V[tqi][a] * L[(base + 2) * S::NPT + idx];
+    if constexpr (DIM == 3) {
+      dz += T.V[tqi][a] * L[(base + 3) * S::NPT + idx];
+      ddz += T.V[tqi][a] * L[(base + 4) * S::NPT + idx];
+    }
+  }
+  r.v = v;
+  r.d[0] = dt;
+  r.d[1] = dr;
+  r.dd[0] = ddt;
+  r.dd[1] = ddr;
+  if constexpr (DIM == 3) {
+    r.d[2] = dz;
+    r.dd[2] = ddz;
+  }
+}
+
+template <typename Real, int DIM, int N>
+__device__ inline void eval_stage_t_pres(const Tab1D<Real, N>& T, const Real* L, int base, int tqi, int tqj, int q,
+                                         RefVal<Real, DIM>& r) {
+  using S = Shape<Real, DIM, N>;
+  Real v = 0, dt = 0, dr = 0, dz = 0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const int idx = q * S::PLANE + tqj * N + a;
+    const Real yvv = L[(base + 0) * S::NPT + idx];
+    v += T.V[tqi][a] * yvv;
+    dt += T.D[tqi][a] * yvv;
+    dr += T.V[tqi][a] * L[(base + 1) * S::NPT + idx];
+    if constexpr (DIM == 3) dz += T.V[tqi][a] * L[(base + 2) * S::NPT + idx];
+  }
+  r.v = v;
+  r.d[0] = dt;
+  r.d[1] = dr;
+  if constexpr (DIM == 3) r.d[2] = dz;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) r.dd[e] = 0;
+}
+
+// value-only field (history, force): single slot per component, stage z and r
+// fold into values; theta stage here
+template <typename Real, int DIM, int N>
+__device__ inline Real eval_stage_t_value(const Tab1D<Real, N>& T, const Real* L, int slot, int tqi, int tqj,
+                                          int q) {
+  using S = Shape<Real, DIM, N>;
+  Real v = 0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) v += T.V[tqi][a] * L[slot * S::NPT + q * S::PLANE + tqj * N + a];
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Polar geometry at a volume quadrature point
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct PtGeom {
+  Real c, s;       // cos, sin of theta
+  Real r, inv_r;
+  Real inv_dr;     // 1 / dr
+  Real inv_rdth;   // 1 / (r dtheta)
+  Real inv_dz;
+  Real jxw;
+};
+
+template <typename Real, int DIM, int N>
+__device__ inline PtGeom<Real> point_geom(const Geom<Real>& G, const Tab1D<Real, N>& T, const CellId& C, int tqi,
+                                          int tqj, int q) {
+  PtGeom<Real> g;
+  const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + tqi) * 2;
+  g.c = tr[0];
+  g.s = tr[1];
+  const Real dr = G.dr[C.dom];
+  g.r = G.r0[C.dom] + dr * (Real(C.cr) + T.x[tqj]);
+  g.inv_r = Real(1) / g.r;
+  g.inv_dr = Real(1) / dr;
+  g.inv_rdth = g.inv_r / G.dth;
+  g.inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
+  Real w = T.w[tqi] * T.w[tqj] * g.r * G.dth * dr;
+  if constexpr (DIM == 3) w *= T.w[q] * G.dz;
+  g.jxw = w;
+  return g;
+}
+
+// reference derivatives -> Cartesian gradient and Laplacian (exact polar map)
+template <typename Real, int DIM>
+__device__ inline void to_physical(const PtGeom<Real>& g, const Real* dz_scale, const RefVal<Real, DIM>& rv,
+                                   Real (&grad)[DIM], Real& lap, bool want_lap) {
+  const Real dr = rv.d[1] * g.inv_dr;    // d/dr
+  const Real dt = rv.d[0] * g.inv_rdth;  // (1/r) d/dtheta
+  grad[0] = g.c * dr - g.s * dt;
+  grad[1] = g.s * dr + g.c * dt;
+  if constexpr (DIM == 3) grad[2] = rv.d[2] * g.inv_dz;
+  if (want_lap) {
+    lap = rv.dd[1] * g.inv_dr * g.inv_dr + dr * g.inv_r + rv.dd[0] * g.inv_rdth * g.inv_rdth;
+    if constexpr (DIM == 3) lap += rv.dd[2] * g.inv_dz * g.inv_dz;
+  }
+  (void)dz_scale;
+}
+
+// physical test coefficients (value g0, gradient G) -> reference ones times JxW
+template <typename Real, int DIM>
+__device__ inline void to_reference(const PtGeom<Real>& g, Real jxw, Real g0, const Real (&Gp)[DIM], Real* f) {
+  f[0] = jxw * g0;
+  f[1] = jxw * (-g.s * Gp[0] + g.c * Gp[1]) * g.inv_rdth;  // theta
+  f[2] = jxw * (g.c * Gp[0] + g.s * Gp[1]) * g.inv_dr;     // r
+  if constexpr (DIM == 3) f[3] = jxw * Gp[2] * g.inv_dz;   // z
+}
+
+// ---------------------------------------------------------------------------
+// Integration: test coefficients in LDS slots comp*NT + {0: value, 1: theta,
+// 2: r, 3: z} at point [q][qj][qi] -> nodal line of the lane, scattered.
+// ---------------------------------------------------------------------------
+template <typename Real, int DIM, int N>
+__device__ inline void integrate_scatter(const Tab1D<Real, N>& T, Real* L, int ta, int tb, bool active,
+                                         const Geom<Real>& G, int k, const CellId& C, Real* __restrict__ dst) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NZ = S::NZ, NC = S::NC, NT = S::NT;
+  constexpr int NX = (DIM == 3) ? 3 : 2;
+  // theta stage: lane (ta, tqj=tb) contracts over qi
+  Real X[NC][NX][NZ];
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < NC; ++m)
+#pragma unroll
+      for (int q = 0; q < NZ; ++q) {
+        Real x0 = 0, xr = 0, xz = 0;
+#pragma unroll
+        for (int qi = 0; qi < N; ++qi) {
+          const int idx = q * S::PLANE + tb * N + qi;
+          x0 += T.V[qi][ta] * L[(m * NT + 0) * S::NPT + idx] + T.D[qi][ta] * L[(m * NT + 1) * S::NPT + idx];
+          xr += T.V[qi][ta] * L[(m * NT + 2) * S::NPT + idx];
+          if constexpr (DIM == 3) xz += T.V[qi][ta] * L[(m * NT + 3) * S::NPT + idx];
+        }
+        X[m][0][q] = x0;
+        X[m][1][q] = xr;
+        if constexpr (DIM == 3) X[m][2][q] = xz;
+      }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < NC; ++m)
+#pragma unroll
+      for (int j = 0; j < NX; ++j)
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) L[(m * NX + j) * S::NPT + q * S::PLANE + tb * N + ta] = X[m][j][q];
+  }
+  __syncthreads();
+  if (!active) return;
+  // r stage: lane (ta, tb) contracts over qj; z stage in registers
+#pragma unroll
+  for (int m = 0; m < NC; ++m) {
+    Real Y0[NZ], Yz[NZ];
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      Real y0 = 0, yz = 0;
+#pragma unroll
+      for (int qj = 0; qj < N; ++qj) {
+        const int idx = q * S::PLANE + qj * N + ta;
+        y0 += T.V[qj][tb] * L[(m * NX + 0) * S::NPT + idx] + T.D[qj][tb] * L[(m * NX + 1) * S::NPT + idx];
+        if constexpr (DIM == 3) yz += T.V[qj][tb] * L[(m * NX + 2) * S::NPT + idx];
+      }
+      Y0[q] = y0;
+      Yz[q] = yz;
+    }
+#pragma unroll
+    for (int c = 0; c < NZ; ++c) {
+      Real o;
+      if constexpr (DIM == 3) {
+        o = 0;
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) o += T.V[q][c] * Y0[q] + T.D[q][c] * Yz[q];
+      } else {
+        o = Y0[0];
+      }
+      int it, ir, iz;
+      const long long node = node_of<Real, DIM>(G, k, C, ta, tb, c, it, ir, iz);
+      atomic_add(dst + node * NC + m, o);
+    }
+  }
+}
+
+// lane's nodal line of a vector (all components), constrained entries as zero
+// when mask is set
+template <typename Real, int DIM, int N, typename In>
+__device__ inline void gather_line(const Geom<Real>& G, int k, const CellId& C, int ta, int tb,
+                                   const In* __restrict__ v, bool mask, Real (*u)[Shape<Real, DIM, N>::NZ]) {
+  using S = Shape<Real, DIM, N>;
+#pragma unroll
+  for (int c = 0; c < S::NZ; ++c) {
+    int it, ir, iz;
+    const long long node = node_of<Real, DIM>(G, k, C, ta, tb, c, it, ir, iz);
+    const bool vf = mask && vel_fixed<Real, DIM>(G, C.dom, ir, iz);
+    const bool pf = mask && p_fixed(G, C.dom, it, ir, iz);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) u[m][c] = vf ? Real(0) : Real(v[node * S::NC + m]);
+    u[DIM][c] = pf ? Real(0) : Real(v[node * S::NC + DIM]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian vmult with stored linearization (Sec. 2.3 blocks, volume part)
+// ---------------------------------------------------------------------------
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                                        const Real* __restrict__ lin,
+                                                        const Real* __restrict__ src, Real* __restrict__ dst) {
+  using S = Shape<Real, DIM, N>;
+  using LL = LinLayout<DIM>;
+  constexpr int NZ = S::NZ, NC = S::NC;
+  __shared__ Real lds[S::CPW][S::SLOTS * S::NPT];
+  const int lane = threadIdx.x;
+  const int cl = lane / S::TPC;
+  const int t = lane % S::TPC;
+  const int ta = t % N, tb = t / N;
+  const int cell = blockIdx.x * S::CPW + cl;
+  const bool active = cl < S::CPW && cell < G.ncells;
+  Real* L = lds[active ? cl : 0];
+  CellId C = decode_cell(G, active ? cell : 0);
+
+  Real u[NC][NZ];
+  if (active) gather_line<Real, DIM, N>(G, k, C, ta, tb, src, true, u);
+  eval_stage_z<Real, DIM, N, DIM, true>(T, u, L, ta, tb, active);
+  __syncthreads();
+  eval_stage_r<Real, DIM, N, DIM, true>(T, L, ta, tb, active);
+
+  // theta stage and pointwise operator, one z point at a time
+  Real tc[NZ][NC][S::NT];
+  if (active) {
+    const Real nu = G.nu, ct = G.ct;
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      RefVal<Real, DIM> rv[DIM], rp;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(T, L, m * S::NYV, ta, tb, q, rv[m]);
+      eval_stage_t_pres<Real, DIM, N>(T, L, DIM * S::NYV, ta, tb, q, rp);
+      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, ta, tb, q);
+      Real du[DIM], gdu[DIM][DIM], ldu[DIM], gdp[DIM], dummy;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        du[m] = rv[m].v;
+        to_physical<Real, DIM>(g, nullptr, rv[m], gdu[m], ldu[m], true);
+      }
+      to_physical<Real, DIM>(g, nullptr, rp, gdp, dummy, false);
+      const Real dp = rp.v;
+      const Real* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + tb * N + ta) * LL::SIZE;
+      Real a[DIM], gu[DIM][DIM], tR[DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        a[m] = lp[LL::A + m];
+        tR[m] = lp[LL::TR + m];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) gu[m][e] = lp[LL::GU + m * DIM + e];
+      }
+      const Real tau = lp[LL::TAU];
+      // g_v = c_t du + (grad u) du + (grad du) a ;  R' du = g_v - nu lap du + grad dp
+      Real gv[DIM], Rp[DIM], divdu = 0;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        Real s = ct * du[m];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) s += gu[m][e] * du[e] + gdu[m][e] * a[e];
+        gv[m] = s;
+        Rp[m] = s - nu * ldu[m] + gdp[m];
+        divdu += gdu[m][m];
+      }
+      // G_v = nu grad du - dp I + tau R' du (x) a + tau R (x) du ;  G_q = tau R' du
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        Real Gm[DIM];
+        const Real tRp = tau * Rp[m];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) Gm[e] = nu * gdu[m][e] + tRp * a[e] + tR[m] * du[e];
+        Gm[m] -= dp;
+        to_reference<Real, DIM>(g, g.jxw, gv[m], Gm, tc[q][m]);
+      }
+      Real Gq[DIM];
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) Gq[e] = tau * Rp[e];
+      to_reference<Real, DIM>(g, g.jxw, divdu, Gq, tc[q][DIM]);
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < NZ; ++q)
+#pragma unroll
+      for (int m = 0; m < NC; ++m)
+#pragma unroll
+        for (int j = 0; j < S::NT; ++j) L[(m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta] = tc[q][m][j];
+  }
+  __syncthreads();
+  integrate_scatter<Real, DIM, N>(T, L, ta, tb, active, G, k, C, dst);
+}
+
+// ---------------------------------------------------------------------------
+// State kernel: per-point linearization data (LIN) or nonlinear residual (RES)
+// ---------------------------------------------------------------------------
+template <int DIM, int N, bool RES>
+__global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T, int k,
+                                              const double* __restrict__ state, const double* __restrict__ hist,
+                                              const double* __restrict__ force, double* __restrict__ lin,
+                                              double* __restrict__ res) {
+  using Real = double;
+  using S = Shape<Real, DIM, N>;
+  using LL = LinLayout<DIM>;
+  constexpr int NZ = S::NZ, NC = S::NC;
+  constexpr int XSLOT = S::EVAL_SLOTS;  // first slot of the value-only fields
+  constexpr int SL = (S::SLOTS > XSLOT + 2 * DIM) ? S::SLOTS : XSLOT + 2 * DIM;
+  __shared__ Real lds[S::CPW][SL * S::NPT];
+  const int lane = threadIdx.x;
+  const int cl = lane / S::TPC;
+  const int t = lane % S::TPC;
+  const int ta = t % N, tb = t / N;
+  const int cell = blockIdx.x * S::CPW + cl;
+  const bool active = cl < S::CPW && cell < G.ncells;
+  Real* L = lds[active ? cl : 0];
+  CellId C = decode_cell(G, active ? cell : 0);
+  const bool has_hist = hist != nullptr, has_force = force != nullptr;
+
+  Real u[NC][NZ];
+  if (active) gather_line<Real, DIM, N>(G, k, C, ta, tb, state, false, u);
+  eval_stage_z<Real, DIM, N, DIM, true>(T, u, L, ta, tb, active);
+  // value-only fields: history and force, reduced along z and r right here
+  if (active && (has_hist || has_force)) {
+    for (int f = 0; f < 2; ++f) {
+      const double* v = f == 0 ? hist : force;
+      if (!v) continue;
+      Real w[NC][NZ];
+      gather_line<Real, DIM, N>(G, k, C, ta, tb, v, false, w);
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) {
+          Real s = 0;
+          if constexpr (DIM == 3) {
+#pragma unroll
+            for (int c = 0; c < NZ; ++c) s += T.V[q][c] * w[m][c];
+          } else {
+            s = w[m][0];
+          }
+          L[(XSLOT + f * DIM + m) * S::NPT + q * S::PLANE + tb * N + ta] = s;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (has_hist || has_force) {
+    Real o[2 * DIM][NZ];
+    if (active) {
+      for (int f = 0; f < 2 * DIM; ++f)
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) {
+          Real s = 0;
+#pragma unroll
+          for (int b = 0; b < N; ++b) s += T.V[tb][b] * L[(XSLOT + f) * S::NPT + q * S::PLANE + b * N + ta];
+          o[f][q] = s;
+        }
+    }
+    __syncthreads();
+    if (active)
+      for (int f = 0; f < 2 * DIM; ++f)
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) L[(XSLOT + f) * S::NPT + q * S::PLANE + tb * N + ta] = o[f][q];
+  }
+  eval_stage_r<Real, DIM, N, DIM, true>(T, L, ta, tb, active);
+
+  Real tc[NZ][NC][S::NT];
+  if (active) {
+    const Real nu = G.nu, ct = G.ct;
+    const Real hc = G.hcell[C.dom * G.hstride + C.cr];
+    const Real ih2 = 1.0 / (hc * hc);
+    const Real visc = 9.0 * (4.0 * nu * ih2) * (4.0 * nu * ih2);
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      RefVal<Real, DIM> rv[DIM], rp;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(T, L, m * S::NYV, ta, tb, q, rv[m]);
+      eval_stage_t_pres<Real, DIM, N>(T, L, DIM * S::NYV, ta, tb, q, rp);
+      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, ta, tb, q);
+      Real uu[DIM], gu[DIM][DIM], lu[DIM], gp[DIM], dummy, hv[DIM], fv[DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        uu[m] = rv[m].v;
+        to_physical<Real, DIM>(g, nullptr, rv[m], gu[m], lu[m], true);
+        hv[m] = (has_hist && ct != 0) ? eval_stage_t_value<Real, DIM, N>(T, L, XSLOT + m, ta, tb, q) : 0.0;
+        fv[m] = has_force ? eval_stage_t_value<Real, DIM, N>(T, L, XSLOT + DIM + m, ta, tb, q) : 0.0;
+      }
+      to_physical<Real, DIM>(g, nullptr, rp, gp, dummy, false);
+      // mesh velocity omega e_z x x in rotor cells
+      Real w[DIM] = {};
+      if (C.dom == 0) {
+        w[0] = -G.omega * g.r * g.s;
+        w[1] = G.omega * g.r * g.c;
+      }
+      Real a[DIM], an2 = 0;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        a[m] = uu[m] - w[m];
+        an2 += a[m] * a[m];
+      }
+      const Real tau = 1.0 / sqrt(G.ctau2 + 4.0 * an2 * ih2 + visc);
+      Real R[DIM], conv[DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        Real s = 0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) s += gu[m][e] * a[e];
+        conv[m] = s;
+        R[m] = ct * uu[m] + hv[m] + s + gp[m] - nu * lu[m] - fv[m];
+      }
+      if constexpr (!RES) {
+        double* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + tb * N + ta) * LL::SIZE;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          lp[LL::A + m] = a[m];
+          lp[LL::TR + m] = tau * R[m];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e) lp[LL::GU + m * DIM + e] = gu[m][e];
+        }
+        lp[LL::TAU] = tau;
+      } else {
+        Real divu = 0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          divu += gu[m][m];
+          Real Gm[DIM];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e) Gm[e] = nu * gu[m][e] + tau * R[m] * a[e];
+          Gm[m] -= rp.v;
+          to_reference<Real, DIM>(g, g.jxw, ct * uu[m] + hv[m] + conv[m] - fv[m], Gm, tc[q][m]);
+        }
+        Real Gq[DIM];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) Gq[e] = tau * R[e];
+        to_reference<Real, DIM>(g, g.jxw, divu, Gq, tc[q][DIM]);
+      }
+    }
+  }
+  if constexpr (RES) {
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < NZ; ++q)
+#pragma unroll
+        for (int m = 0; m < NC; ++m)
+#pragma unroll
+          for (int j = 0; j < S::NT; ++j) L[(m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta] = tc[q][m][j];
+    }
+    __syncthreads();
+    integrate_scatter<Real, DIM, N>(T, L, ta, tb, active, G, k, C, res);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Volume diagonal (column i of the element matrix, entry i) from stored
+// linearization data: one lane per (cell, local DoF), loop over points.
+// ---------------------------------------------------------------------------
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                                     const Real* __restrict__ lin, Real* __restrict__ diag) {
+  using S = Shape<Real, DIM, N>;
+  using LL = LinLayout<DIM>;
+  constexpr int NZ = S::NZ, NC = S::NC;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)G.ncells * S::NPT * NC;
+  if (gid >= total) return;
+  const int comp = gid % NC;
+  const int node = (gid / NC) % S::NPT;
+  const int cell = gid / (NC * S::NPT);
+  const int a0 = node % N, a1 = (node / N) % N, a2 = node / S::PLANE;
+  const CellId C = decode_cell(G, cell);
+  const Real nu = G.nu, ct = G.ct;
+  Real acc = 0;
+  for (int q = 0; q < NZ; ++q)
+    for (int qj = 0; qj < N; ++qj)
+      for (int qi = 0; qi < N; ++qi) {
+        const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, qi, qj, q);
+        const Real vz = (DIM == 3) ? T.V[q][a2] : Real(1);
+        const Real dz_ = (DIM == 3) ? T.D[q][a2] : Real(0);
+        const Real ddz = (DIM == 3) ? T.DD[q][a2] : Real(0);
+        RefVal<Real, DIM> rv;
+        rv.v = T.V[qi][a0] * T.V[qj][a1] * vz;
+        rv.d[0] = T.D[qi][a0] * T.V[qj][a1] * vz;
+        rv.d[1] = T.V[qi][a0] * T.D[qj][a1] * vz;
+        rv.dd[0] = T.DD[qi][a0] * T.V[qj][a1] * vz;
+        rv.dd[1] = T.V[qi][a0] * T.DD[qj][a1] * vz;
+        if constexpr (DIM == 3) {
+          rv.d[2] = T.V[qi][a0] * T.V[qj][a1] * dz_;
+          rv.dd[2] = T.V[qi][a0] * T.V[qj][a1] * ddz;
+        }
+        Real gphi[DIM], lphi;
+        to_physical<Real, DIM>(g, nullptr, rv, gphi, lphi, true);
+        const Real phi = rv.v;
+        const Real* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + qj * N + qi) * LL::SIZE;
+        const Real tau = lp[LL::TAU];
+        Real adg = 0, g2 = 0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+          adg += lp[LL::A + e] * gphi[e];
+          g2 += gphi[e] * gphi[e];
+        }
+        Real val;
+        if (comp < DIM) {
+          // trial phi e_c tested with phi e_c (Sec. 2.3, A-hat diagonal)
+          const Real guc = lp[LL::GU + comp * DIM + comp];
+          const Real Rpc = (ct + guc) * phi + adg - nu * lphi;
+          val = phi * phi * (ct + guc) + phi * adg + nu * g2 + tau * Rpc * adg + lp[LL::TR + comp] * phi * gphi[comp];
+        } else {
+          // D-hat diagonal: tau |grad psi|^2
+          val = tau * g2;
+        }
+        acc += g.jxw * val;
+      }
+  int it, ir, iz;
+  const long long nd = node_of<Real, DIM>(G, k, C, a0, a1, a2, it, ir, iz);
+  atomic_add(diag + nd * NC + comp, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Mortar face terms (Sec. 2.1, Eqs. EqMortarPre / EqMortarDiff / EqMortarMass
+// with the mapped segment quadrature of Sec. 3.2).  One wavefront per
+// interface cell side: it evaluates its own cell and the two cells of the
+// other side that overlap it, forms the side's face coefficients at every
+// mortar point and integrates them against its own test functions.
+// ---------------------------------------------------------------------------
+template <typename Real, int DIM, int N>
+struct Piece {
+  int seg;         // segment index (0 or 1) of the stator face
+  int jface;       // stator face index (for the mortar point angles)
+  CellId other;
+};
+
+template <typename Real, int DIM, int N>
+__device__ inline void mortar_pieces(const Geom<Real>& G, const MortarTab<Real, N>& M, int side, int ct, int cz,
+                                     Piece<Real, DIM, N> (&p)[2]) {
+  const int nt = G.n_theta;
+  if (side == 1) {
+    const int j = ct;
+    p[0].seg = 0;
+    p[0].jface = j;
+    p[1].seg = 1;
+    p[1].jface = j;
+    p[0].other = CellId{0, ((j - M.m - 1) % nt + nt) % nt, G.nr[0] - 1, cz};
+    p[1].other = CellId{0, ((j - M.m) % nt + nt) % nt, G.nr[0] - 1, cz};
+  } else {
+    const int i = ct;
+    const int j0 = (M.m + i) % nt, j1 = (M.m + i + 1) % nt;
+    p[0].seg = 1;
+    p[0].jface = j0;
+    p[1].seg = 0;
+    p[1].jface = j1;
+    p[0].other = CellId{1, j0, 0, cz};
+    p[1].other = CellId{1, j1, 0, cz};
+  }
+}
+
+template <typename Real, int DIM, int N>
+__device__ inline void face_eval(const MortarTab<Real, N>& M, const Tab1D<Real, N>& T, int side, int seg, int qt,
+                                 int qz, const Real* nod /*[NPT][NC]*/, Real (*val)[DIM + 1] /*[NC][1+DIM]*/) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC;
+#pragma unroll
+  for (int m = 0; m < NC; ++m)
+#pragma unroll
+    for (int e = 0; e <= DIM; ++e) val[m][e] = 0;
+  for (int c = 0; c < S::NZ; ++c) {
+    const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+    const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
+    for (int b = 0; b < N; ++b) {
+      const Real fv = M.FV[side][b], fd = M.FD[side][b];
+      if (fv == Real(0) && fd == Real(0)) continue;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const Real mv = M.MV[side][seg][qt][a], md = M.MD[side][seg][qt][a];
+        const Real wv = mv * fv * vz, wt = md * fv * vz, wr = mv * fd * vz, wz = mv * fv * dzv;
+        const Real* x = nod + ((c * N + b) * N + a) * NC;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          val[m][0] += wv * x[m];
+          val[m][1] += wt * x[m];
+          val[m][2] += wr * x[m];
+          if constexpr (DIM == 3) val[m][3] += wz * x[m];
+        }
+      }
+    }
+  }
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                               const MortarTab<Real, N>* __restrict__ Mp,
+                                               const Real* __restrict__ mtrig, const Real* __restrict__ src,
+                                               Real* __restrict__ dst, int mask) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ;
+  constexpr int NQ = N * NZ;  // mortar points per segment
+  __shared__ Real nod[3][NPT * NC];
+  __shared__ Real coef[2][NQ][NC][DIM + 1];
+  const MortarTab<Real, N>& M = *Mp;
+  const int nfaces = G.n_theta * G.nz;
+  const int side = blockIdx.x / nfaces;
+  const int f = blockIdx.x % nfaces;
+  const int ct = f % G.n_theta, cz = f / G.n_theta;
+  const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
+  Piece<Real, DIM, N> P[2];
+  mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
+  // load own cell and the two other-side cells (constrained entries as zero
+  // when `mask` is set: Jacobian columns; the residual reads the state as is)
+  for (int e = threadIdx.x; e < 3 * NPT; e += blockDim.x) {
+    const int which = e / NPT, node = e % NPT;
+    const CellId C = which == 0 ? own : P[which - 1].other;
+    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+    int it, ir, iz;
+    const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
+    const bool vf = mask && vel_fixed<Real, DIM>(G, C.dom, ir, iz);
+    const bool pf = mask && p_fixed(G, C.dom, it, ir, iz);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) nod[which][node * NC + m] = vf ? Real(0) : src[nd * NC + m];
+    nod[which][node * NC + DIM] = pf ? Real(0) : src[nd * NC + DIM];
+  }
+  __syncthreads();
+  const Real nu = G.nu;
+  for (int e = threadIdx.x; e < 2 * NQ; e += blockDim.x) {
+    const int pc = e / NQ, qq = e % NQ;
+    const int qt = qq % N, qz = qq / N;
+    const int seg = P[pc].seg;
+    if (!M.seg_active[seg]) {
+      for (int m = 0; m < NC; ++m)
+        for (int j = 0; j <= DIM; ++j) coef[pc][qq][m][j] = 0;
+      continue;
+    }
+    Real vo[NC][DIM + 1], vx[NC][DIM + 1];
+    face_eval<Real, DIM, N>(M, T, side, seg, qt, qz, nod[0], vo);
+    face_eval<Real, DIM, N>(M, T, 1 - side, seg, qt, qz, nod[1 + pc], vx);
+    const Real* tr = mtrig + (((size_t)P[pc].jface * 2 + seg) * N + qt) * 2;
+    const Real cth = tr[0], sth = tr[1];
+    const Real inv_rdth = Real(1) / (M.R * G.dth);
+    const Real inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
+    // Cartesian gradients of both sides at the point
+    Real go[DIM][DIM], gx[DIM][DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+      const Real dro = vo[m][2] / G.dr[side], dto = vo[m][1] * inv_rdth;
+      const Real drx = vx[m][2] / G.dr[1 - side], dtx = vx[m][1] * inv_rdth;
+      go[m][0] = cth * dro - sth * dto;
+      go[m][1] = sth * dro + cth * dto;
+      gx[m][0] = cth * drx - sth * dtx;
+      gx[m][1] = sth * drx + cth * dtx;
+      if constexpr (DIM == 3) {
+        go[m][2] = vo[m][3] * inv_dz;
+        gx[m][2] = vx[m][3] * inv_dz;
+      }
+    }
+    Real n[DIM] = {};
+    n[0] = side == 0 ? cth : -cth;
+    n[1] = side == 0 ? sth : -sth;
+    const Real pbar = Real(0.5) * (vo[DIM][0] + vx[DIM][0]);
+    const Real tau = M.tau_pen[side];
+    const Real jxw = M.jxw[seg][qt][(DIM == 3) ? qz : 0];
+    Real jn = 0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+      const Real j = vo[m][0] - vx[m][0];
+      jn += j * n[m];
+      Real gn = 0;
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) gn += Real(0.5) * (go[m][e] + gx[m][e]) * n[e];
+      const Real cv = pbar * n[m] - nu * gn + nu * tau * j;
+      // grad v coefficient -(nu/2) j n, as reference coefficients
+      Real Gm[DIM];
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) Gm[e] = Real(-0.5) * nu * j * n[e];
+      coef[pc][qq][m][0] = jxw * cv;
+      coef[pc][qq][m][1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
+      coef[pc][qq][m][2] = jxw * (cth * Gm[0] + sth * Gm[1]) / G.dr[side];
+      if constexpr (DIM == 3) coef[pc][qq][m][3] = jxw * Gm[2] * inv_dz;
+    }
+    coef[pc][qq][DIM][0] = jxw * Real(-0.5) * jn;
+    for (int j = 1; j <= DIM; ++j) coef[pc][qq][DIM][j] = 0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NPT * NC; e += blockDim.x) {
+    const int m = e % NC, node = e / NC;
+    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+    const Real fv = M.FV[side][b], fd = M.FD[side][b];
+    if (fv == Real(0) && fd == Real(0)) continue;
+    Real acc = 0;
+    for (int pc = 0; pc < 2; ++pc) {
+      const int seg = P[pc].seg;
+      for (int qq = 0; qq < NQ; ++qq) {
+        const int qt = qq % N, qz = qq / N;
+        const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+        const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
+        const Real mv = M.MV[side][seg][qt][a], md = M.MD[side][seg][qt][a];
+        const Real* cf = coef[pc][qq][m];
+        Real s = cf[0] * mv * fv * vz + cf[1] * md * fv * vz + cf[2] * mv * fd * vz;
+        if constexpr (DIM == 3) s += cf[3] * mv * fv * dzv;
+        acc += s;
+      }
+    }
+    int it, ir, iz;
+    const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
+    atomic_add(dst + nd * NC + m, acc);
+  }
+}
+
+// Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
+// i (other side zero) gives, tested with the same basis function,
+// nu tau phi^2 - nu phi (grad phi . n) for velocity rows and 0 for pressure rows.
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_mortar_diag(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                                    const MortarTab<Real, N>* __restrict__ Mp,
+                                                    const Real* __restrict__ mtrig, Real* __restrict__ diag) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ;
+  const MortarTab<Real, N>& M = *Mp;
+  const int nfaces = G.n_theta * G.nz;
+  const int side = blockIdx.x / nfaces;
+  const int f = blockIdx.x % nfaces;
+  const int ct = f % G.n_theta, cz = f / G.n_theta;
+  const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
+  Piece<Real, DIM, N> P[2];
+  mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
+  const Real nu = G.nu, tau = M.tau_pen[side];
+  for (int node = threadIdx.x; node < NPT; node += blockDim.x) {
+    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+    const Real fv = M.FV[side][b], fd = M.FD[side][b];
+    if (fv == Real(0) && fd == Real(0)) continue;
+    Real acc[DIM] = {};
+    for (int pc = 0; pc < 2; ++pc) {
+      const int seg = P[pc].seg;
+      if (!M.seg_active[seg]) continue;
+      for (int qz = 0; qz < NZ; ++qz)
+        for (int qt = 0; qt < N; ++qt) {
+          const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+          const Real mv = M.MV[side][seg][qt][a];
+          const Real phi = mv * fv * vz;
+          const Real dr = mv * fd * vz / G.dr[side];
+          // grad phi . n with n = +-e_r is +-(d phi / dr)
+          const Real gn = side == 0 ? dr : -dr;
+          const Real jxw = M.jxw[seg][qt][(DIM == 3) ? qz : 0];
+          const Real v = jxw * (nu * tau * phi * phi - nu * phi * gn);
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) acc[m] += v;
+        }
+    }
+    int it, ir, iz;
+    const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) atomic_add(diag + nd * NC + m, acc[m]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small vector kernels
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_fill(Real* x, Real v, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long j = i; j < n; j += stride) x[j] = v;
+}
+
+// mode 0: dst[c] = src[c]; mode 1: dst[c] = 0; mode 2: dst[c] = value
+template <typename Real>
+__global__ void k_constraints(const int64_t* __restrict__ cons, long long n, const Real* __restrict__ src,
+                              Real* __restrict__ dst, Real value, int mode) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = cons[i];
+  dst[c] = mode == 0 ? src[c] : (mode == 1 ? Real(0) : value);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <typename Real, int N>
+static Tab1D<Real, N> make_tab(const mns_handle* h) {
+  Tab1D<Real, N> T;
+  std::vector<double> L(N), dL(N), d2L(N);
+  for (int q = 0; q < N; ++q) {
+    lagrange_1d(h->gll, h->gx[q], L.data(), dL.data(), d2L.data());
+    for (int a = 0; a < N; ++a) {
+      T.V[q][a] = (Real)L[a];
+      T.D[q][a] = (Real)dL[a];
+      T.DD[q][a] = (Real)d2L[a];
+    }
+    T.x[q] = (Real)h->gx[q];
+    T.w[q] = (Real)h->gw[q];
+  }
+  return T;
+}
+
+template <typename Real>
+static Geom<Real> make_geom(const mns_handle* h) {
+  Geom<Real> G;
+  const mns_mesh_desc& d = h->desc;
+  G.ncells = h->ncells;
+  G.cell_off1 = h->cell_off1;
+  G.node_off1 = h->node_off1;
+  G.ndofs = h->ndofs;
+  G.n_theta = d.n_theta;
+  G.nz = h->nz;
+  G.ntn = h->ntn;
+  G.nzn = h->nzn;
+  G.nr[0] = d.n_r_rotor;
+  G.nr[1] = d.n_r_stator;
+  G.nrn[0] = h->nrn[0];
+  G.nrn[1] = h->nrn[1];
+  G.r0[0] = (Real)d.r_in;
+  G.r0[1] = (Real)d.r_interface;
+  G.dr[0] = (Real)((d.r_interface - d.r_in) / d.n_r_rotor);
+  G.dr[1] = (Real)((d.r_out - d.r_interface) / d.n_r_stator);
+  G.dth = (Real)h->dth;
+  G.dz = (Real)h->dz;
+  G.nu = (Real)d.nu;
+  G.omega = (Real)h->omega;
+  G.ct = d.steady ? Real(0) : (Real)(1.5 / d.dt);
+  G.ctau2 = d.steady ? Real(0) : (Real)(1.0 / (d.dt * d.dt));
+  G.h[0] = G.h[1] = 0;
+  G.hstride = h->hstride;
+  if constexpr (sizeof(Real) == 8) {
+    G.hcell = (const Real*)h->d_hcell64;
+    G.trig = (const Real*)h->d_trig64;
+  } else {
+    G.hcell = (const Real*)h->d_hcell32;
+    G.trig = (const Real*)h->d_trig32;
+  }
+  return G;
+}
+
+static int hip_check(mns_handle* h, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(h, MNS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return MNS_OK;
+}
+
+template <typename Real>
+int launch_fill(Real* x, Real v, int64_t n, hipStream_t s) {
+  if (n <= 0) return MNS_OK;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill<Real>, dim3((unsigned)blocks), dim3(256), 0, s, x, v, (long long)n);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+template <typename Real>
+int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real value, int mode, hipStream_t s) {
+  if (h->n_cons == 0) return MNS_OK;
+  const long long blocks = (h->n_cons + 255) / 256;
+  hipLaunchKernelGGL(k_constraints<Real>, dim3((unsigned)blocks), dim3(256), 0, s, h->d_cons, (long long)h->n_cons,
+                     src, dst, value, mode);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+#define MNS_DISPATCH(DIMV, KV, ...)                                 \
+  switch (DIMV * 10 + KV) {                                          \
+    case 22: { constexpr int DIM = 2, N = 3; __VA_ARGS__; } break;          \
+    case 23: { constexpr int DIM = 2, N = 4; __VA_ARGS__; } break;          \
+    case 24: { constexpr int DIM = 2, N = 5; __VA_ARGS__; } break;          \
+    case 25: { constexpr int DIM = 2, N = 6; __VA_ARGS__; } break;          \
+    case 32: { constexpr int DIM = 3, N = 3; __VA_ARGS__; } break;          \
+    case 33: { constexpr int DIM = 3, N = 4; __VA_ARGS__; } break;          \
+    case 34: { constexpr int DIM = 3, N = 5; __VA_ARGS__; } break;          \
+    default: return set_error(h, MNS_ERR_UNSUPPORTED, "degree not compiled"); \
+  }
+
+template <typename Real, int DIM, int N>
+static int do_mortar(mns_handle* h, const Real* src, Real* dst, int mask, hipStream_t s) {
+  const Geom<Real> G = make_geom<Real>(h);
+  const Tab1D<Real, N> T = make_tab<Real, N>(h);
+  const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
+  const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
+  const unsigned blocks = 2u * (unsigned)(G.n_theta * G.nz);
+  timer_begin(h, TIMER_MORTAR, s);
+  hipLaunchKernelGGL((k_mortar<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, M, mtrig, src, dst, mask);
+  timer_end(h, TIMER_MORTAR, s);
+  return hip_check(h, "mortar kernel");
+}
+
+template <typename Real, int DIM, int N>
+static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
+  using S = Shape<Real, DIM, N>;
+  const Geom<Real> G = make_geom<Real>(h);
+  const Tab1D<Real, N> T = make_tab<Real, N>(h);
+  const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
+  timer_begin(h, TIMER_OTHER, s);
+  int rc = launch_fill<Real>(dst, Real(0), h->ndofs, s);
+  timer_end(h, TIMER_OTHER, s);
+  if (rc) return set_error(h, rc, "fill");
+  const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
+  timer_begin(h, TIMER_VOLUME, s);
+  hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, dst);
+  timer_end(h, TIMER_VOLUME, s);
+  rc = hip_check(h, "volume kernel");
+  if (rc) return rc;
+  rc = do_mortar<Real, DIM, N>(h, src, dst, 1, s);
+  if (rc) return rc;
+  timer_begin(h, TIMER_OTHER, s);
+  rc = launch_constraints<Real>(h, src, dst, Real(0), 0, s);
+  timer_end(h, TIMER_OTHER, s);
+  return rc ? set_error(h, rc, "constraints") : MNS_OK;
+}
+
+template <typename Real>
+int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
+  MNS_DISPATCH(h->dim, h->k, return (do_jacobian<Real, DIM, N>(h, src, dst, s)));
+  return MNS_OK;
+}
+
+template <int DIM, int N, bool RES>
+static int do_state(mns_handle* h, const double* state, const double* hist, const double* force, double* lin,
+                    double* res, hipStream_t s) {
+  using S = Shape<double, DIM, N>;
+  const Geom<double> G = make_geom<double>(h);
+  const Tab1D<double, N> T = make_tab<double, N>(h);
+  const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
+  hipLaunchKernelGGL((k_state<DIM, N, RES>), dim3(blocks), dim3(64), 0, s, G, T, h->k, state, hist, force, lin,
+                     res);
+  return hip_check(h, RES ? "residual kernel" : "linearization kernel");
+}
+
+template <>
+int launch_linearize<double>(mns_handle* h, const double* state, const double* hist, const double* force,
+                             double* lin, hipStream_t s) {
+  MNS_DISPATCH(h->dim, h->k, return (do_state<DIM, N, false>(h, state, hist, force, lin, nullptr, s)));
+  return MNS_OK;
+}
+
+int launch_residual(mns_handle* h, const double* state, double* res, hipStream_t s) {
+  int rc = launch_fill<double>(res, 0.0, h->ndofs, s);
+  if (rc) return set_error(h, rc, "fill");
+  MNS_DISPATCH(h->dim, h->k, {
+    rc = do_state<DIM, N, true>(h, state, h->d_hist, h->d_force, nullptr, res, s);
+    if (rc) return rc;
+    rc = do_mortar<double, DIM, N>(h, state, res, 0, s);
+    if (rc) return rc;
+  });
+  rc = launch_constraints<double>(h, state, res, 0.0, 1, s);
+  return rc ? set_error(h, rc, "constraints") : MNS_OK;
+}
+
+template <typename Real, int DIM, int N>
+static int do_diag(mns_handle* h, Real* diag, hipStream_t s) {
+  using S = Shape<Real, DIM, N>;
+  const Geom<Real> G = make_geom<Real>(h);
+  const Tab1D<Real, N> T = make_tab<Real, N>(h);
+  const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
+  int rc = launch_fill<Real>(diag, Real(0), h->ndofs, s);
+  if (rc) return set_error(h, rc, "fill");
+  const long long total = (long long)G.ncells * S::NPT * S::NC;
+  hipLaunchKernelGGL((k_diag_volume<Real, DIM, N>), dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, G, T,
+                     h->k, lin, diag);
+  rc = hip_check(h, "diagonal kernel");
+  if (rc) return rc;
+  const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
+  const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
+  hipLaunchKernelGGL((k_mortar_diag<Real, DIM, N>), dim3(2u * (unsigned)(G.n_theta * G.nz)), dim3(64), 0, s, G, T,
+                     h->k, M, mtrig, diag);
+  rc = hip_check(h, "mortar diagonal kernel");
+  if (rc) return rc;
+  rc = launch_constraints<Real>(h, diag, diag, Real(1), 2, s);
+  return rc ? set_error(h, rc, "constraints") : MNS_OK;
+}
+
+template <typename Real>
+int launch_diagonal(mns_handle* h, Real* diag, hipStream_t s) {
+  MNS_DISPATCH(h->dim, h->k, return (do_diag<Real, DIM, N>(h, diag, s)));
+  return MNS_OK;
+}
+
+template int launch_jacobian<double>(mns_handle*, const double*, double*, hipStream_t);
+template int launch_jacobian<float>(mns_handle*, const float*, float*, hipStream_t);
+template int launch_diagonal<double>(mns_handle*, double*, hipStream_t);
+template int launch_diagonal<float>(mns_handle*, float*, hipStream_t);
+template int launch_fill<double>(double*, double, int64_t, hipStream_t);
+template int launch_fill<float>(float*, float, int64_t, hipStream_t);
+template int launch_constraints<double>(const mns_handle*, const double*, double*, double, int, hipStream_t);
+template int launch_constraints<float>(const mns_handle*, const float*, float*, float, int, hipStream_t);
+
+}  // namespace mns

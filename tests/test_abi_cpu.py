@@ -1,0 +1,55 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every entry point declared in include/mortarns.h, and rejects invalid meshes
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2608_27423_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mortarns.h")).read()
+    return sorted(set(re.findall(r"\b(mns_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_names():
+    assert _declared() == sorted(binding.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=4), dict(degree=1), dict(degree=9), dict(r_in=0.6), dict(r_out=0.4), dict(n_theta=2),
+    dict(n_r_rotor=0), dict(nu=0.0), dict(penalty_F=-1.0), dict(penalty_rule=3), dict(steady=0, dt=0.0),
+    dict(dim=3, n_z=0), dict(dim=3, height=-1.0),
+])
+def test_invalid_mesh_rejected(bad):
+    mesh = dict(dim=2, degree=2, r_in=0.25, r_if=0.5, r_out=1.0, height=1.0, n_theta=8, n_r_rotor=2, n_r_stator=2,
+                n_z=2, nu=0.01, penalty_F=1.0, penalty_rule=0, steady=1, dt=1.0)
+    mesh.update(bad)
+    desc = binding.mesh_desc(mesh)
+    L = binding.lib()
+    h = ctypes.c_void_p()
+    rc = L.mns_setup_mesh(ctypes.byref(desc), None, ctypes.byref(h))
+    try:
+        assert rc in (binding.MNS_ERR_INVALID_ARG, binding.MNS_ERR_UNSUPPORTED)
+        assert L.mns_last_error(h).decode() != ""
+    finally:
+        L.mns_destroy(h)
+
+
+def test_null_arguments():
+    L = binding.lib()
+    assert L.mns_setup_mesh(None, None, None) == binding.MNS_ERR_INVALID_ARG
+    assert L.mns_rotate_rotor(None, 0.0, 0.0) == binding.MNS_ERR_INVALID_ARG
+    assert L.mns_apply_jacobian(None, 0, None, None, None) == binding.MNS_ERR_INVALID_ARG
+    assert L.mns_last_error(None) == b"null handle"

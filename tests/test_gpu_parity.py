@@ -1,0 +1,192 @@
+"""GPU (HIP, gfx950) vs the FP64 oracle, element by element, through the C-ABI.
+
+Bar: FP64 results match the oracle to a relative max-norm of 1e-12; the FP32
+instance is reported and held to a loose sanity bound (it is a preconditioner
+precision, not a parity claim).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import oracle_cfg, relmax, small_mesh
+from paper_2608_27423_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 5e-5
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None):
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, omega)
+        op.set_linearization(_dev(state), None if hist is None else _dev(hist),
+                             None if force is None else _dev(force))
+        y64 = op.apply_jacobian(_dev(x)).cpu().numpy()
+        y32 = op.apply_jacobian(_dev(x, torch.float32)).double().cpu().numpy()
+        torch.cuda.synchronize()
+    return y64, y32
+
+
+CASES = [(2, 2), (2, 3), (2, 4), (2, 5), (3, 2), (3, 3), (3, 4)]
+
+
+@pytest.mark.parametrize("dim,k", CASES)
+@pytest.mark.parametrize("angle", ["random", "aligned", "near_aligned", "negative_wrapped"])
+def test_jacobian_small(dim, k, angle):
+    mesh = small_mesh(dim, k)
+    dth = 2 * math.pi / mesh["n_theta"]
+    theta = {"random": 2.345, "aligned": 2 * dth, "near_aligned": 3 * dth - 1e-14,
+             "negative_wrapped": -7.9}[angle]
+    g = np.random.default_rng(100 * dim + k)
+    n = inputs.n_dofs(mesh)
+    state, x = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
+    y64, y32 = _gpu_apply(mesh, theta, 0.8, state, x)
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, 0.8), state, x)
+    e64, e32 = relmax(y64, yo), relmax(y32, yo)
+    print(f"dim={dim} k={k} {angle}: fp64 {e64:.2e} fp32 {e32:.2e}")
+    assert e64 <= TOL64
+    assert e32 <= TOL32
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_jacobian_transient_with_history_and_force(dim):
+    mesh = small_mesh(dim, 2, steady=0, dt=0.05, penalty_rule=1, penalty_F=3.0, n_theta=7)
+    g = np.random.default_rng(7 + dim)
+    n = inputs.n_dofs(mesh)
+    state, x, hist, force = (g.uniform(-1, 1, n) for _ in range(4))
+    y64, _ = _gpu_apply(mesh, 1.1, -0.4, state, x, hist, force)
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, 1.1, -0.4), state, x, hist=hist, force=force)
+    assert relmax(y64, yo) <= TOL64
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_residual(dim, k):
+    mesh = small_mesh(dim, k, steady=0, dt=0.1)
+    g = np.random.default_rng(3 + k)
+    n = inputs.n_dofs(mesh)
+    state, hist, force = (g.uniform(-1, 1, n) for _ in range(3))
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(0.77, 1.3)
+        op.set_linearization(_dev(state), _dev(hist), _dev(force))
+        r = op.apply_residual(_dev(state)).cpu().numpy()
+    ro = oracle.residual(oracle_cfg(mesh, 0.77, 1.3), state, hist, force)
+    assert relmax(r, ro) <= TOL64
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 2), (3, 3)])
+def test_diagonal(dim, k):
+    mesh = small_mesh(dim, k)
+    g = np.random.default_rng(11)
+    n = inputs.n_dofs(mesh)
+    state = g.uniform(-1, 1, n)
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(0.4, 0.9)
+        op.set_linearization(_dev(state))
+        d64 = op.compute_diagonal(torch.float64).cpu().numpy()
+        d32 = op.compute_diagonal(torch.float32).double().cpu().numpy()
+    do = oracle.diagonal(oracle_cfg(mesh, 0.4, 0.9), state)
+    assert relmax(d64, do) <= TOL64
+    assert relmax(d32, do) <= TOL32
+
+
+def test_degenerate_inputs():
+    """Zero input gives zero output except constrained rows (= input); the
+    minimum mesh (3 cells per ring, one radial cell) and a zero state."""
+    mesh = small_mesh(3, 2, n_theta=3, n_r_rotor=1, n_r_stator=1, n_z=1)
+    n = inputs.n_dofs(mesh)
+    zero = np.zeros(n)
+    y64, _ = _gpu_apply(mesh, 0.3, 0.0, zero, zero)
+    assert np.all(y64 == 0)
+    g = np.random.default_rng(2)
+    x = g.uniform(-1, 1, n)
+    y64, _ = _gpu_apply(mesh, 0.3, 0.0, zero, x)
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, 0.3, 0.0), zero, x)
+    assert relmax(y64, yo) <= TOL64
+
+
+def test_workload_2d_q2_full():
+    name = "annulus2d_q2_32x4"
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    state, x = inputs.state_for(name), inputs.vector_for(name)
+    y64, y32 = _gpu_apply(mesh, theta, mesh["omega"], state, x)
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, mesh["omega"]), state, x)
+    print(f"{name}: fp64 {relmax(y64, yo):.2e} fp32 {relmax(y32, yo):.2e}")
+    assert relmax(y64, yo) <= TOL64
+    assert relmax(y32, yo) <= TOL32
+
+
+def test_workload_3d_q2_full():
+    name = "annulus3d_q2_64x8x32"
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    state, x = inputs.state_for(name), inputs.vector_for(name)
+    y64, y32 = _gpu_apply(mesh, theta, mesh["omega"], state, x)
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, mesh["omega"]), state, x)
+    print(f"{name}: fp64 {relmax(y64, yo):.2e} fp32 {relmax(y32, yo):.2e}")
+    assert relmax(y64, yo) <= TOL64
+    assert relmax(y32, yo) <= TOL32
+
+
+def _sampled_rows(mesh, n, seed):
+    """Random rows plus every row of a few interface and wall nodes."""
+    g = np.random.default_rng(seed)
+    rows = set(g.choice(n, 3000, replace=False).tolist())
+    nc = mesh["dim"] + 1
+    ntn, nrr, nrs, nzn = inputs.node_grid(mesh)
+    rot_if = [(it + ntn * (nrr - 1 + nrr * iz)) for it in range(0, ntn, 7) for iz in (0, nzn // 2)]
+    off = ntn * nrr * nzn
+    sta_if = [off + it + ntn * (0 + nrs * iz) for it in range(0, ntn, 5) for iz in (1, nzn - 1)]
+    for node in rot_if + sta_if:
+        rows.update(node * nc + c for c in range(nc))
+    return np.array(sorted(rows), dtype=np.int64)
+
+
+@pytest.mark.parametrize("name", ["annulus3d_q3_64x16x32", "annulus3d_q2_256x32x128"])
+def test_workload_large_sampled(name):
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    state, x = inputs.state_for(name), inputs.vector_for(name)
+    n = x.size
+    y64, y32 = _gpu_apply(mesh, theta, mesh["omega"], state, x)
+    rows = _sampled_rows(mesh, n, 5)
+    yo = oracle.apply_jacobian_rows(oracle_cfg(mesh, theta, mesh["omega"]), state, x, rows)
+    e64 = float(np.abs(y64[rows] - yo).max() / np.abs(yo).max())
+    e32 = float(np.abs(y32[rows] - yo).max() / np.abs(yo).max())
+    print(f"{name}: {rows.size} rows, fp64 {e64:.2e} fp32 {e32:.2e}")
+    assert e64 <= TOL64
+    assert e32 <= TOL32
+
+
+@pytest.mark.parametrize("precond", ["f64", "f32"])
+def test_solve_2d_workload(precond):
+    """FGMRES(FP64) with the Jacobi-Chebyshev preconditioner in FP64 or FP32
+    reaches 1e-8; the true residual is recomputed with the oracle's operator."""
+    name = "annulus2d_q2_32x4"
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    st = inputs.state_for(name)
+    st = st / np.abs(st).max()
+    n = st.size
+    xstar = inputs.uniform(n, inputs.SOLUTION_SEED[name])
+    cfg = oracle_cfg(mesh, theta, mesh["omega"])
+    b = oracle.apply_jacobian(cfg, st, xstar)
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, mesh["omega"])
+        op.set_linearization(_dev(st))
+        x, info = op.solve(_dev(b), restart=250, maxit=2000, precond=precond, cheb_degree=4)
+        x = x.cpu().numpy()
+    r = b - oracle.apply_jacobian(cfg, st, x)
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    print(f"solve {precond}: {info['iterations']} its, {info['seconds']:.3f}s, reported {info['rel_residual']:.2e},"
+          f" oracle {rel:.2e}")
+    assert info["rc"] == 0
+    assert rel <= 1.01e-8
