@@ -30,6 +30,7 @@ static void free_all(mns_handle* h) {
   free_events(h);
   void* ptrs[] = {h->d_hcell64, h->d_hcell32, h->d_trig64, h->d_trig32, h->d_mtab64, h->d_mtab32, h->d_mtrig64,
                   h->d_mtrig32, h->d_cons, h->d_lin64, h->d_lin32, h->d_hist, h->d_force, h->ws64, h->ws32,
+                  h->d_E64, h->d_E32, h->d_Em64, h->d_Em32,
                   h->d_diag64, h->d_diag32, h->d_red};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -67,6 +68,8 @@ int mns_setup_mesh(const mns_mesh_desc* desc, void* stream, mns_handle** out) {
     h->d_lin64 = nullptr;
     h->d_lin32 = nullptr;
     h->d_hist = h->d_force = nullptr;
+    h->d_E64 = h->d_Em64 = nullptr;
+    h->d_E32 = h->d_Em32 = nullptr;
     h->ws64 = nullptr;
     h->ws32 = nullptr;
     h->d_diag64 = nullptr;

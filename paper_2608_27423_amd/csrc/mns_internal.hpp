@@ -110,6 +110,10 @@ struct mns_handle {
   int64_t n_cons = 0;
   double* d_lin64 = nullptr;    // per-qp linearization data
   float* d_lin32 = nullptr;
+  double* d_E64 = nullptr;      // local results [comp][local node][cell]
+  float* d_E32 = nullptr;
+  double* d_Em64 = nullptr;     // mortar cell-side local results [comp][local node][side*faces + face]
+  float* d_Em32 = nullptr;
   double* d_hist = nullptr;     // copies of the BDF2 history / force (or null)
   double* d_force = nullptr;
   // solver workspace

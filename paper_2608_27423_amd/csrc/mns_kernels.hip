@@ -7,8 +7,9 @@
 // sum-factorized evaluation runs in registers, the r and theta contractions
 // go through LDS.  2D is the same code with a line of length one.
 //
-// Scatter: FP64/FP32 atomic adds into a zeroed destination; constrained rows
-// are overwritten afterwards by the constraint kernel.
+// Scatter without atomics: every cell (and mortar cell side) stores its local
+// result; k_gather sums the contributions of each node in a fixed order and
+// applies the constraint rows, so the product is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,6 +17,16 @@
 #include "mns_internal.hpp"
 
 namespace mns {
+
+#ifndef MNS_LDS_INTERLEAVE
+#define MNS_LDS_INTERLEAVE 0
+#endif
+#ifndef MNS_LDS_CPAD
+#define MNS_LDS_CPAD 0
+#endif
+#ifndef MNS_LDS_PAD
+#define MNS_LDS_PAD 4
+#endif
 
 template <typename Real, int DIM, int N>
 struct Shape {
@@ -31,11 +42,32 @@ struct Shape {
   static constexpr int EVAL_SLOTS = DIM * NYV + NYP;
   static constexpr int TEST_SLOTS = NC * NT;
   static constexpr int SLOTS = (EVAL_SLOTS > TEST_SLOTS) ? EVAL_SLOTS : TEST_SLOTS;
+  // LDS layout of the per-cell work arrays.  Interleaved (default): element e
+  // of cell c at e * ES + c, so the cells of a wavefront touching the same
+  // element hit adjacent banks.  Blocked: cell c owns [c * REGION, ...).
+#if MNS_LDS_INTERLEAVE
+  static constexpr int ES = CPW + MNS_LDS_CPAD;
+  static constexpr int REGION = 1;
+#else
+  static constexpr int ES = 1;
+  static constexpr int REGION = SLOTS * NPT + MNS_LDS_PAD;
+#endif
+  template <int NSLOTS>
+  static constexpr int lds_size() {
+    return MNS_LDS_INTERLEAVE ? NSLOTS * NPT * ES : (CPW - 1) * (NSLOTS * NPT + MNS_LDS_PAD) + NSLOTS * NPT;
+  }
 };
 
 struct CellId {
   int dom, ct, cr, cz;
 };
+
+// per-domain parameter selected without indexing the kernel-argument block
+// by a lane-dependent value (which would turn into a vector memory load)
+template <typename T>
+__device__ inline T pick(int d, const T (&a)[2]) {
+  return d ? a[1] : a[0];
+}
 
 template <typename Real>
 __device__ inline CellId decode_cell(const Geom<Real>& G, int cell) {
@@ -44,8 +76,9 @@ __device__ inline CellId decode_cell(const Geom<Real>& G, int cell) {
   int l = cell - (c.dom ? (int)G.cell_off1 : 0);
   c.ct = l % G.n_theta;
   l /= G.n_theta;
-  c.cr = l % G.nr[c.dom];
-  c.cz = l / G.nr[c.dom];
+  const int nr = pick(c.dom, G.nr);
+  c.cr = l % nr;
+  c.cz = l / nr;
   return c;
 }
 
@@ -59,7 +92,7 @@ __device__ inline long long node_of(const Geom<Real>& G, int k, const CellId& C,
   ir = k * C.cr + b;
   iz = (DIM == 3) ? k * C.cz + c : 0;
   long long base = C.dom ? G.node_off1 : 0;
-  return base + it + (long long)G.ntn * (ir + (long long)G.nrn[C.dom] * iz);
+  return base + it + (long long)G.ntn * (ir + (long long)pick(C.dom, G.nrn) * iz);
 }
 
 template <typename Real, int DIM>
@@ -118,12 +151,12 @@ __device__ inline void eval_stage_z(const Tab1D<Real, N>& T, const Real (*u)[Sha
           if (vel) sdd += T.DD[q][c] * u[m][c];
         }
         const int idx = q * S::PLANE + tb * N + ta;
-        L[(base + 0) * S::NPT + idx] = sv;
-        L[(base + 1) * S::NPT + idx] = sd;
-        if (vel) L[(base + 2) * S::NPT + idx] = sdd;
+        L[((base + 0) * S::NPT + idx) * S::ES] = sv;
+        L[((base + 1) * S::NPT + idx) * S::ES] = sd;
+        if (vel) L[((base + 2) * S::NPT + idx) * S::ES] = sdd;
       }
     } else {
-      L[base * S::NPT + tb * N + ta] = u[m][0];
+      L[(base * S::NPT + tb * N + ta) * S::ES] = u[m][0];
     }
   }
 }
@@ -149,14 +182,14 @@ __device__ inline void eval_stage_r(const Tab1D<Real, N>& T, Real* L, int ta, in
 #pragma unroll
         for (int b = 0; b < N; ++b) {
           const int idx = q * S::PLANE + b * N + ta;
-          const Real zv = L[(base + 0) * S::NPT + idx];
+          const Real zv = L[((base + 0) * S::NPT + idx) * S::ES];
           vv += T.V[tqj][b] * zv;
           dv += T.D[tqj][b] * zv;
           if (vel) ddv += T.DD[tqj][b] * zv;
           if constexpr (DIM == 3) {
-            const Real zd = L[(base + 1) * S::NPT + idx];
+            const Real zd = L[((base + 1) * S::NPT + idx) * S::ES];
             vd += T.V[tqj][b] * zd;
-            if (vel) vdd += T.V[tqj][b] * L[(base + 2) * S::NPT + idx];
+            if (vel) vdd += T.V[tqj][b] * L[((base + 2) * S::NPT + idx) * S::ES];
           }
         }
         out[m][0][q] = vv;
@@ -186,7 +219,7 @@ __device__ inline void eval_stage_r(const Tab1D<Real, N>& T, Real* L, int ta, in
       for (int j = 0; j < S::NYV; ++j) {
         if (j >= nout) break;
 #pragma unroll
-        for (int q = 0; q < NZ; ++q) L[(base + j) * S::NPT + q * S::PLANE + tqj * N + ta] = out[m][j][q];
+        for (int q = 0; q < NZ; ++q) L[((base + j) * S::NPT + q * S::PLANE + tqj * N + ta) * S::ES] = out[m][j][q];
       }
     }
   }
@@ -202,15 +235,15 @@ __device__ inline void eval_stage_t_vel(const Tab1D<Real, N>& T, const Real* L, 
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     const int idx = q * S::PLANE + tqj * N + a;
-    const Real yvv = L[(base + 0) * S::NPT + idx];
+    const Real yvv = L[((base + 0) * S::NPT + idx) * S::ES];
     v += T.V[tqi][a] * yvv;
     dt += T.D[tqi][a] * yvv;
     ddt += T.DD[tqi][a] * yvv;
-    dr += T.V[tqi][a] * L[(base + 1) * S::NPT + idx];
-    ddr += T.V[tqi][a] * L[(base + 2) * S::NPT + idx];
+    dr += T.V[tqi][a] * L[((base + 1) * S::NPT + idx) * S::ES];
+    ddr += T.V[tqi][a] * L[((base + 2) * S::NPT + idx) * S::ES];
     if constexpr (DIM == 3) {
-      dz += T.V[tqi][a] * L[(base + 3) * S::NPT + idx];
-      ddz += T.V[tqi][a] * L[(base + 4) * S::NPT + idx];
+      dz += T.V[tqi][a] * L[((base + 3) * S::NPT + idx) * S::ES];
+      ddz += T.V[tqi][a] * L[((base + 4) * S::NPT + idx) * S::ES];
     }
   }
   r.v = v;
@@ -232,11 +265,11 @@ __device__ inline void eval_stage_t_pres(const Tab1D<Real, N>& T, const Real* L,
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     const int idx = q * S::PLANE + tqj * N + a;
-    const Real yvv = L[(base + 0) * S::NPT + idx];
+    const Real yvv = L[((base + 0) * S::NPT + idx) * S::ES];
     v += T.V[tqi][a] * yvv;
     dt += T.D[tqi][a] * yvv;
-    dr += T.V[tqi][a] * L[(base + 1) * S::NPT + idx];
-    if constexpr (DIM == 3) dz += T.V[tqi][a] * L[(base + 2) * S::NPT + idx];
+    dr += T.V[tqi][a] * L[((base + 1) * S::NPT + idx) * S::ES];
+    if constexpr (DIM == 3) dz += T.V[tqi][a] * L[((base + 2) * S::NPT + idx) * S::ES];
   }
   r.v = v;
   r.d[0] = dt;
@@ -254,7 +287,7 @@ __device__ inline Real eval_stage_t_value(const Tab1D<Real, N>& T, const Real* L
   using S = Shape<Real, DIM, N>;
   Real v = 0;
 #pragma unroll
-  for (int a = 0; a < N; ++a) v += T.V[tqi][a] * L[slot * S::NPT + q * S::PLANE + tqj * N + a];
+  for (int a = 0; a < N; ++a) v += T.V[tqi][a] * L[(slot * S::NPT + q * S::PLANE + tqj * N + a) * S::ES];
   return v;
 }
 
@@ -278,8 +311,8 @@ __device__ inline PtGeom<Real> point_geom(const Geom<Real>& G, const Tab1D<Real,
   const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + tqi) * 2;
   g.c = tr[0];
   g.s = tr[1];
-  const Real dr = G.dr[C.dom];
-  g.r = G.r0[C.dom] + dr * (Real(C.cr) + T.x[tqj]);
+  const Real dr = pick(C.dom, G.dr);
+  g.r = pick(C.dom, G.r0) + dr * (Real(C.cr) + T.x[tqj]);
   g.inv_r = Real(1) / g.r;
   g.inv_dr = Real(1) / dr;
   g.inv_rdth = g.inv_r / G.dth;
@@ -317,11 +350,13 @@ __device__ inline void to_reference(const PtGeom<Real>& g, Real jxw, Real g0, co
 
 // ---------------------------------------------------------------------------
 // Integration: test coefficients in LDS slots comp*NT + {0: value, 1: theta,
-// 2: r, 3: z} at point [q][qj][qi] -> nodal line of the lane, scattered.
+// 2: r, 3: z} at point [q][qj][qi] -> nodal line of the lane, stored into the
+// local-result buffer E[comp][local node][cell] (cell fastest; no atomics:
+// the per-node sum over cells is done by k_gather in a fixed order).
 // ---------------------------------------------------------------------------
 template <typename Real, int DIM, int N>
-__device__ inline void integrate_scatter(const Tab1D<Real, N>& T, Real* L, int ta, int tb, bool active,
-                                         const Geom<Real>& G, int k, const CellId& C, Real* __restrict__ dst) {
+__device__ inline void integrate_store(const Tab1D<Real, N>& T, const Tab1D<Real, N>& Tz, Real* L, int ta, int tb,
+                                       bool active, int cell, long long ncells, Real* __restrict__ E) {
   using S = Shape<Real, DIM, N>;
   constexpr int NZ = S::NZ, NC = S::NC, NT = S::NT;
   constexpr int NX = (DIM == 3) ? 3 : 2;
@@ -336,9 +371,9 @@ __device__ inline void integrate_scatter(const Tab1D<Real, N>& T, Real* L, int t
 #pragma unroll
         for (int qi = 0; qi < N; ++qi) {
           const int idx = q * S::PLANE + tb * N + qi;
-          x0 += T.V[qi][ta] * L[(m * NT + 0) * S::NPT + idx] + T.D[qi][ta] * L[(m * NT + 1) * S::NPT + idx];
-          xr += T.V[qi][ta] * L[(m * NT + 2) * S::NPT + idx];
-          if constexpr (DIM == 3) xz += T.V[qi][ta] * L[(m * NT + 3) * S::NPT + idx];
+          x0 += T.V[qi][ta] * L[((m * NT + 0) * S::NPT + idx) * S::ES] + T.D[qi][ta] * L[((m * NT + 1) * S::NPT + idx) * S::ES];
+          xr += T.V[qi][ta] * L[((m * NT + 2) * S::NPT + idx) * S::ES];
+          if constexpr (DIM == 3) xz += T.V[qi][ta] * L[((m * NT + 3) * S::NPT + idx) * S::ES];
         }
         X[m][0][q] = x0;
         X[m][1][q] = xr;
@@ -352,11 +387,12 @@ __device__ inline void integrate_scatter(const Tab1D<Real, N>& T, Real* L, int t
 #pragma unroll
       for (int j = 0; j < NX; ++j)
 #pragma unroll
-        for (int q = 0; q < NZ; ++q) L[(m * NX + j) * S::NPT + q * S::PLANE + tb * N + ta] = X[m][j][q];
+        for (int q = 0; q < NZ; ++q) L[((m * NX + j) * S::NPT + q * S::PLANE + tb * N + ta) * S::ES] = X[m][j][q];
   }
   __syncthreads();
   if (!active) return;
   // r stage: lane (ta, tb) contracts over qj; z stage in registers
+  Real* Ec = E + cell;
 #pragma unroll
   for (int m = 0; m < NC; ++m) {
     Real Y0[NZ], Yz[NZ];
@@ -366,8 +402,8 @@ __device__ inline void integrate_scatter(const Tab1D<Real, N>& T, Real* L, int t
 #pragma unroll
       for (int qj = 0; qj < N; ++qj) {
         const int idx = q * S::PLANE + qj * N + ta;
-        y0 += T.V[qj][tb] * L[(m * NX + 0) * S::NPT + idx] + T.D[qj][tb] * L[(m * NX + 1) * S::NPT + idx];
-        if constexpr (DIM == 3) yz += T.V[qj][tb] * L[(m * NX + 2) * S::NPT + idx];
+        y0 += T.V[qj][tb] * L[((m * NX + 0) * S::NPT + idx) * S::ES] + T.D[qj][tb] * L[((m * NX + 1) * S::NPT + idx) * S::ES];
+        if constexpr (DIM == 3) yz += T.V[qj][tb] * L[((m * NX + 2) * S::NPT + idx) * S::ES];
       }
       Y0[q] = y0;
       Yz[q] = yz;
@@ -378,14 +414,95 @@ __device__ inline void integrate_scatter(const Tab1D<Real, N>& T, Real* L, int t
       if constexpr (DIM == 3) {
         o = 0;
 #pragma unroll
-        for (int q = 0; q < NZ; ++q) o += T.V[q][c] * Y0[q] + T.D[q][c] * Yz[q];
+        for (int q = 0; q < NZ; ++q) o += Tz.V[q][c] * Y0[q] + Tz.D[q][c] * Yz[q];
       } else {
         o = Y0[0];
       }
-      int it, ir, iz;
-      const long long node = node_of<Real, DIM>(G, k, C, ta, tb, c, it, ir, iz);
-      atomic_add(dst + node * NC + m, o);
+      Ec[(size_t)(m * S::NPT + c * S::PLANE + tb * N + ta) * ncells] = o;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather: dst[node] = sum of the local results of every cell (and, on the
+// interface, every mortar cell side) that contains the node, in a fixed order;
+// constrained rows: mode 0 dst = src, mode 1 dst = 0.  One lane per node.
+// ---------------------------------------------------------------------------
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real* __restrict__ E,
+                                                const Real* __restrict__ Em, const Real* __restrict__ src,
+                                                Real* __restrict__ dst, int mode) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nnodes = G.ndofs / NC;
+  if (g >= nnodes) return;
+  const int dom = g >= G.node_off1;
+  const long long l = g - (dom ? G.node_off1 : 0);
+  const int it = (int)(l % G.ntn);
+  const long long l2 = l / G.ntn;
+  const int nrn = pick(dom, G.nrn), nrd = pick(dom, G.nr);
+  const int ir = (int)(l2 % nrn);
+  const int iz = (int)(l2 / nrn);
+  // candidate cells per direction (cell index, local node index)
+  int tc[2], ta[2], nt = 1;
+  tc[0] = it / k;
+  ta[0] = it % k;
+  if (ta[0] == 0) {
+    tc[1] = (tc[0] == 0 ? G.n_theta : tc[0]) - 1;
+    ta[1] = k;
+    nt = 2;
+  }
+  int rc[2], rb[2], nrc = 0;
+  if (ir / k < nrd) { rc[nrc] = ir / k; rb[nrc] = ir % k; ++nrc; }
+  if (ir % k == 0 && ir > 0) { rc[nrc] = ir / k - 1; rb[nrc] = k; ++nrc; }
+  int zc[2], zb[2], nzc = 0;
+  if constexpr (DIM == 3) {
+    if (iz / k < G.nz) { zc[nzc] = iz / k; zb[nzc] = iz % k; ++nzc; }
+    if (iz % k == 0 && iz > 0) { zc[nzc] = iz / k - 1; zb[nzc] = k; ++nzc; }
+  } else {
+    zc[0] = 0;
+    zb[0] = 0;
+    nzc = 1;
+  }
+  Real acc[NC];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) acc[m] = 0;
+  const int cbase = dom ? (int)G.cell_off1 : 0;
+  for (int z = 0; z < nzc; ++z)
+    for (int r = 0; r < nrc; ++r)
+      for (int t = 0; t < nt; ++t) {
+        const int cell = cbase + tc[t] + G.n_theta * (rc[r] + nrd * zc[z]);
+        const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + rb[r] * N + ta[t];
+        const Real* e = E + (size_t)loc * G.ncells + cell;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) acc[m] += e[(size_t)m * S::NPT * G.ncells];
+      }
+  // mortar cell sides: every node of a rotor outer-ring cell or a stator
+  // inner-ring cell (the grad v face term reaches all of them)
+  int bm = -1;
+  if (dom == 0 && ir >= k * (G.nr[0] - 1)) bm = ir - k * (G.nr[0] - 1);
+  if (dom == 1 && ir <= k) bm = ir;
+  if (bm >= 0 && Em) {
+    const int nfaces = G.n_theta * G.nz;
+    const int nsides = 2 * nfaces;
+    for (int z = 0; z < nzc; ++z)
+      for (int t = 0; t < nt; ++t) {
+        const int cs = dom * nfaces + tc[t] + G.n_theta * zc[z];
+        const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + bm * N + ta[t];
+        const Real* e = Em + (size_t)loc * nsides + cs;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) acc[m] += e[(size_t)m * S::NPT * nsides];
+      }
+  }
+  const bool vf = vel_fixed<Real, DIM>(G, dom, ir, iz);
+  const bool pf = p_fixed(G, dom, it, ir, iz);
+  Real* d = dst + g * NC;
+  const Real* sv = src + g * NC;
+#pragma unroll
+  for (int m = 0; m < NC; ++m) {
+    const bool fixed = m < DIM ? vf : pf;
+    d[m] = fixed ? (mode == 0 ? sv[m] : Real(0)) : acc[m];
   }
 }
 
@@ -401,9 +518,13 @@ __device__ inline void gather_line(const Geom<Real>& G, int k, const CellId& C, 
     const long long node = node_of<Real, DIM>(G, k, C, ta, tb, c, it, ir, iz);
     const bool vf = mask && vel_fixed<Real, DIM>(G, C.dom, ir, iz);
     const bool pf = mask && p_fixed(G, C.dom, it, ir, iz);
+    // load unconditionally so the loads of all nodes are in flight together
+    Real w[S::NC];
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) u[m][c] = vf ? Real(0) : Real(v[node * S::NC + m]);
-    u[DIM][c] = pf ? Real(0) : Real(v[node * S::NC + DIM]);
+    for (int m = 0; m < S::NC; ++m) w[m] = Real(v[node * S::NC + m]);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) u[m][c] = vf ? Real(0) : w[m];
+    u[DIM][c] = pf ? Real(0) : w[DIM];
   }
 }
 
@@ -413,25 +534,44 @@ __device__ inline void gather_line(const Geom<Real>& G, int k, const CellId& C, 
 template <typename Real, int DIM, int N>
 __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                         const Real* __restrict__ lin,
-                                                        const Real* __restrict__ src, Real* __restrict__ dst) {
+                                                        const Real* __restrict__ src, Real* __restrict__ E) {
   using S = Shape<Real, DIM, N>;
   using LL = LinLayout<DIM>;
   constexpr int NZ = S::NZ, NC = S::NC;
-  __shared__ Real lds[S::CPW][S::SLOTS * S::NPT];
+  __shared__ Real lds[S::template lds_size<S::SLOTS>()];
+  // 1D tables in LDS for the lane-indexed rows and columns (the kernel
+  // argument copy T serves the uniform z contractions)
+  __shared__ Tab1D<Real, N> sT;
   const int lane = threadIdx.x;
+  {
+    constexpr int NW = (int)(sizeof(Tab1D<Real, N>) / sizeof(Real));
+    const Real* tw = (const Real*)&T;
+    for (int i = lane; i < NW; i += 64) ((Real*)&sT)[i] = tw[i];
+  }
   const int cl = lane / S::TPC;
   const int t = lane % S::TPC;
   const int ta = t % N, tb = t / N;
   const int cell = blockIdx.x * S::CPW + cl;
   const bool active = cl < S::CPW && cell < G.ncells;
-  Real* L = lds[active ? cl : 0];
+  Real* L = lds + (active ? cl : 0) * (S::ES == 1 ? S::SLOTS * S::NPT + MNS_LDS_PAD : 1);
   CellId C = decode_cell(G, active ? cell : 0);
 
   Real u[NC][NZ];
   if (active) gather_line<Real, DIM, N>(G, k, C, ta, tb, src, true, u);
+  // linearization data of every point of the lane, requested before the
+  // evaluation so its latency overlaps the contractions
+  Real lv[NZ][LL::SIZE];
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      const Real* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + tb * N + ta) * LL::SIZE;
+#pragma unroll
+      for (int j = 0; j < LL::SIZE; ++j) lv[q][j] = lp[j];
+    }
+  }
   eval_stage_z<Real, DIM, N, DIM, true>(T, u, L, ta, tb, active);
   __syncthreads();
-  eval_stage_r<Real, DIM, N, DIM, true>(T, L, ta, tb, active);
+  eval_stage_r<Real, DIM, N, DIM, true>(sT, L, ta, tb, active);
 
   // theta stage and pointwise operator, one z point at a time
   Real tc[NZ][NC][S::NT];
@@ -441,9 +581,9 @@ __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real
     for (int q = 0; q < NZ; ++q) {
       RefVal<Real, DIM> rv[DIM], rp;
 #pragma unroll
-      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(T, L, m * S::NYV, ta, tb, q, rv[m]);
-      eval_stage_t_pres<Real, DIM, N>(T, L, DIM * S::NYV, ta, tb, q, rp);
-      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, ta, tb, q);
+      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(sT, L, m * S::NYV, ta, tb, q, rv[m]);
+      eval_stage_t_pres<Real, DIM, N>(sT, L, DIM * S::NYV, ta, tb, q, rp);
+      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
       Real du[DIM], gdu[DIM][DIM], ldu[DIM], gdp[DIM], dummy;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
@@ -452,7 +592,7 @@ __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real
       }
       to_physical<Real, DIM>(g, nullptr, rp, gdp, dummy, false);
       const Real dp = rp.v;
-      const Real* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + tb * N + ta) * LL::SIZE;
+      const Real* lp = lv[q];
       Real a[DIM], gu[DIM][DIM], tR[DIM];
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
@@ -496,10 +636,10 @@ __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real
 #pragma unroll
       for (int m = 0; m < NC; ++m)
 #pragma unroll
-        for (int j = 0; j < S::NT; ++j) L[(m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta] = tc[q][m][j];
+        for (int j = 0; j < S::NT; ++j) L[((m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta) * S::ES] = tc[q][m][j];
   }
   __syncthreads();
-  integrate_scatter<Real, DIM, N>(T, L, ta, tb, active, G, k, C, dst);
+  integrate_store<Real, DIM, N>(sT, T, L, ta, tb, active, cell, G.ncells, E);
 }
 
 // ---------------------------------------------------------------------------
@@ -516,14 +656,20 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
   constexpr int NZ = S::NZ, NC = S::NC;
   constexpr int XSLOT = S::EVAL_SLOTS;  // first slot of the value-only fields
   constexpr int SL = (S::SLOTS > XSLOT + 2 * DIM) ? S::SLOTS : XSLOT + 2 * DIM;
-  __shared__ Real lds[S::CPW][SL * S::NPT];
+  __shared__ Real lds[S::template lds_size<SL>()];
+  __shared__ Tab1D<Real, N> sT;
   const int lane = threadIdx.x;
+  {
+    constexpr int NW = (int)(sizeof(Tab1D<Real, N>) / sizeof(Real));
+    const Real* tw = (const Real*)&T;
+    for (int i = lane; i < NW; i += 64) ((Real*)&sT)[i] = tw[i];
+  }
   const int cl = lane / S::TPC;
   const int t = lane % S::TPC;
   const int ta = t % N, tb = t / N;
   const int cell = blockIdx.x * S::CPW + cl;
   const bool active = cl < S::CPW && cell < G.ncells;
-  Real* L = lds[active ? cl : 0];
+  Real* L = lds + (active ? cl : 0) * (S::ES == 1 ? SL * S::NPT + MNS_LDS_PAD : 1);
   CellId C = decode_cell(G, active ? cell : 0);
   const bool has_hist = hist != nullptr, has_force = force != nullptr;
 
@@ -548,7 +694,7 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
           } else {
             s = w[m][0];
           }
-          L[(XSLOT + f * DIM + m) * S::NPT + q * S::PLANE + tb * N + ta] = s;
+          L[((XSLOT + f * DIM + m) * S::NPT + q * S::PLANE + tb * N + ta) * S::ES] = s;
         }
       }
     }
@@ -562,7 +708,7 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
         for (int q = 0; q < NZ; ++q) {
           Real s = 0;
 #pragma unroll
-          for (int b = 0; b < N; ++b) s += T.V[tb][b] * L[(XSLOT + f) * S::NPT + q * S::PLANE + b * N + ta];
+          for (int b = 0; b < N; ++b) s += sT.V[tb][b] * L[((XSLOT + f) * S::NPT + q * S::PLANE + b * N + ta) * S::ES];
           o[f][q] = s;
         }
     }
@@ -570,9 +716,9 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
     if (active)
       for (int f = 0; f < 2 * DIM; ++f)
 #pragma unroll
-        for (int q = 0; q < NZ; ++q) L[(XSLOT + f) * S::NPT + q * S::PLANE + tb * N + ta] = o[f][q];
+        for (int q = 0; q < NZ; ++q) L[((XSLOT + f) * S::NPT + q * S::PLANE + tb * N + ta) * S::ES] = o[f][q];
   }
-  eval_stage_r<Real, DIM, N, DIM, true>(T, L, ta, tb, active);
+  eval_stage_r<Real, DIM, N, DIM, true>(sT, L, ta, tb, active);
 
   Real tc[NZ][NC][S::NT];
   if (active) {
@@ -584,16 +730,16 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
     for (int q = 0; q < NZ; ++q) {
       RefVal<Real, DIM> rv[DIM], rp;
 #pragma unroll
-      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(T, L, m * S::NYV, ta, tb, q, rv[m]);
-      eval_stage_t_pres<Real, DIM, N>(T, L, DIM * S::NYV, ta, tb, q, rp);
-      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, ta, tb, q);
+      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(sT, L, m * S::NYV, ta, tb, q, rv[m]);
+      eval_stage_t_pres<Real, DIM, N>(sT, L, DIM * S::NYV, ta, tb, q, rp);
+      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
       Real uu[DIM], gu[DIM][DIM], lu[DIM], gp[DIM], dummy, hv[DIM], fv[DIM];
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
         uu[m] = rv[m].v;
         to_physical<Real, DIM>(g, nullptr, rv[m], gu[m], lu[m], true);
-        hv[m] = (has_hist && ct != 0) ? eval_stage_t_value<Real, DIM, N>(T, L, XSLOT + m, ta, tb, q) : 0.0;
-        fv[m] = has_force ? eval_stage_t_value<Real, DIM, N>(T, L, XSLOT + DIM + m, ta, tb, q) : 0.0;
+        hv[m] = (has_hist && ct != 0) ? eval_stage_t_value<Real, DIM, N>(sT, L, XSLOT + m, ta, tb, q) : 0.0;
+        fv[m] = has_force ? eval_stage_t_value<Real, DIM, N>(sT, L, XSLOT + DIM + m, ta, tb, q) : 0.0;
       }
       to_physical<Real, DIM>(g, nullptr, rp, gp, dummy, false);
       // mesh velocity omega e_z x x in rotor cells
@@ -654,10 +800,10 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
 #pragma unroll
         for (int m = 0; m < NC; ++m)
 #pragma unroll
-          for (int j = 0; j < S::NT; ++j) L[(m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta] = tc[q][m][j];
+          for (int j = 0; j < S::NT; ++j) L[((m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta) * S::ES] = tc[q][m][j];
     }
     __syncthreads();
-    integrate_scatter<Real, DIM, N>(T, L, ta, tb, active, G, k, C, res);
+    integrate_store<Real, DIM, N>(sT, T, L, ta, tb, active, cell, G.ncells, res);
   }
 }
 
@@ -764,58 +910,47 @@ __device__ inline void mortar_pieces(const Geom<Real>& G, const MortarTab<Real, 
   }
 }
 
-template <typename Real, int DIM, int N>
-__device__ inline void face_eval(const MortarTab<Real, N>& M, const Tab1D<Real, N>& T, int side, int seg, int qt,
-                                 int qz, const Real* nod /*[NPT][NC]*/, Real (*val)[DIM + 1] /*[NC][1+DIM]*/) {
-  using S = Shape<Real, DIM, N>;
-  constexpr int NC = S::NC;
-#pragma unroll
-  for (int m = 0; m < NC; ++m)
-#pragma unroll
-    for (int e = 0; e <= DIM; ++e) val[m][e] = 0;
-  for (int c = 0; c < S::NZ; ++c) {
-    const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
-    const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
-    for (int b = 0; b < N; ++b) {
-      const Real fv = M.FV[side][b], fd = M.FD[side][b];
-      if (fv == Real(0) && fd == Real(0)) continue;
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        const Real mv = M.MV[side][seg][qt][a], md = M.MD[side][seg][qt][a];
-        const Real wv = mv * fv * vz, wt = md * fv * vz, wr = mv * fd * vz, wz = mv * fv * dzv;
-        const Real* x = nod + ((c * N + b) * N + a) * NC;
-#pragma unroll
-        for (int m = 0; m < NC; ++m) {
-          val[m][0] += wv * x[m];
-          val[m][1] += wt * x[m];
-          val[m][2] += wr * x[m];
-          if constexpr (DIM == 3) val[m][3] += wz * x[m];
-        }
-      }
-    }
-  }
-}
-
+// Mortar kernel: one 64-lane block per interface cell side (own cell) with
+// its two overlapping other-side cells.  Phase 1 stages the three cells'
+// nodal data, the mortar tables and the point angles in LDS; phase 2
+// evaluates value and reference derivatives of every component at every
+// mortar point on both sides (lanes over piece x side x point x component);
+// phase 3 forms the own side's face coefficients per point; phase 4
+// integrates them against the own cell's test functions and stores the
+// cell side's local result Em[comp][local node][cell side].
 template <typename Real, int DIM, int N>
 __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                const MortarTab<Real, N>* __restrict__ Mp,
                                                const Real* __restrict__ mtrig, const Real* __restrict__ src,
-                                               Real* __restrict__ dst, int mask) {
+                                               Real* __restrict__ Em, int mask) {
   using S = Shape<Real, DIM, N>;
   constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ;
   constexpr int NQ = N * NZ;  // mortar points per segment
-  __shared__ Real nod[3][NPT * NC];
-  __shared__ Real coef[2][NQ][NC][DIM + 1];
-  const MortarTab<Real, N>& M = *Mp;
+  constexpr int NE = DIM + 1; // value + reference derivatives
+  __shared__ Real nod[3][NC][NPT];
+  __shared__ MortarTab<Real, N> M;
+  __shared__ Real trg[2][N][2];
+  __shared__ Real ev[2][2][NQ][NC][NE];  // [piece][own=0 / other=1][point][comp][value, d_theta, d_r, d_z]
+  __shared__ Real coef[2][NQ][NC][NE];
   const int nfaces = G.n_theta * G.nz;
   const int side = blockIdx.x / nfaces;
   const int f = blockIdx.x % nfaces;
   const int ct = f % G.n_theta, cz = f / G.n_theta;
   const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
+  // phase 1: tables and nodal data
+  {
+    const int* srcw = (const int*)Mp;
+    int* dstw = (int*)&M;
+    constexpr int NW = (int)(sizeof(MortarTab<Real, N>) / sizeof(int));
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) dstw[i] = srcw[i];
+  }
+  __syncthreads();
   Piece<Real, DIM, N> P[2];
   mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
-  // load own cell and the two other-side cells (constrained entries as zero
-  // when `mask` is set: Jacobian columns; the residual reads the state as is)
+  for (int i = threadIdx.x; i < 2 * N * 2; i += blockDim.x) {
+    const int pc = i / (2 * N), q = (i / 2) % N, c = i % 2;
+    trg[pc][q][c] = mtrig[(((size_t)P[pc].jface * 2 + P[pc].seg) * N + q) * 2 + c];
+  }
   for (int e = threadIdx.x; e < 3 * NPT; e += blockDim.x) {
     const int which = e / NPT, node = e % NPT;
     const CellId C = which == 0 ? own : P[which - 1].other;
@@ -825,92 +960,117 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
     const bool vf = mask && vel_fixed<Real, DIM>(G, C.dom, ir, iz);
     const bool pf = mask && p_fixed(G, C.dom, it, ir, iz);
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) nod[which][node * NC + m] = vf ? Real(0) : src[nd * NC + m];
-    nod[which][node * NC + DIM] = pf ? Real(0) : src[nd * NC + DIM];
+    for (int m = 0; m < DIM; ++m) nod[which][m][node] = vf ? Real(0) : src[nd * NC + m];
+    nod[which][DIM][node] = pf ? Real(0) : src[nd * NC + DIM];
   }
   __syncthreads();
-  const Real nu = G.nu;
-  for (int e = threadIdx.x; e < 2 * NQ; e += blockDim.x) {
-    const int pc = e / NQ, qq = e % NQ;
-    const int qt = qq % N, qz = qq / N;
+  // phase 2: evaluation at the mortar points
+  for (int e = threadIdx.x; e < 2 * 2 * NQ * NC; e += blockDim.x) {
+    const int m = e % NC;
+    const int q = (e / NC) % NQ;
+    const int sd = (e / (NC * NQ)) % 2;
+    const int pc = e / (NC * NQ * 2);
     const int seg = P[pc].seg;
-    if (!M.seg_active[seg]) {
-      for (int m = 0; m < NC; ++m)
-        for (int j = 0; j <= DIM; ++j) coef[pc][qq][m][j] = 0;
-      continue;
-    }
-    Real vo[NC][DIM + 1], vx[NC][DIM + 1];
-    face_eval<Real, DIM, N>(M, T, side, seg, qt, qz, nod[0], vo);
-    face_eval<Real, DIM, N>(M, T, 1 - side, seg, qt, qz, nod[1 + pc], vx);
-    const Real* tr = mtrig + (((size_t)P[pc].jface * 2 + seg) * N + qt) * 2;
-    const Real cth = tr[0], sth = tr[1];
-    const Real inv_rdth = Real(1) / (M.R * G.dth);
-    const Real inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
-    // Cartesian gradients of both sides at the point
-    Real go[DIM][DIM], gx[DIM][DIM];
+    const int cside = sd == 0 ? side : 1 - side;
+    const int qt = q % N, qz = q / N;
+    const Real* x = nod[sd == 0 ? 0 : 1 + pc][m];
+    Real v = 0, dt = 0, dr = 0, dz = 0;
+    for (int c = 0; c < NZ; ++c) {
+      const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+      const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) {
-      const Real dro = vo[m][2] / G.dr[side], dto = vo[m][1] * inv_rdth;
-      const Real drx = vx[m][2] / G.dr[1 - side], dtx = vx[m][1] * inv_rdth;
-      go[m][0] = cth * dro - sth * dto;
-      go[m][1] = sth * dro + cth * dto;
-      gx[m][0] = cth * drx - sth * dtx;
-      gx[m][1] = sth * drx + cth * dtx;
-      if constexpr (DIM == 3) {
-        go[m][2] = vo[m][3] * inv_dz;
-        gx[m][2] = vx[m][3] * inv_dz;
+      for (int b = 0; b < N; ++b) {
+        const Real fv = M.FV[cside][b], fd = M.FD[cside][b];
+        Real sv = 0, st = 0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          const Real xv = x[(c * N + b) * N + a];
+          sv += M.MV[cside][seg][qt][a] * xv;
+          st += M.MD[cside][seg][qt][a] * xv;
+        }
+        v += fv * vz * sv;
+        dt += fv * vz * st;
+        dr += fd * vz * sv;
+        dz += fv * dzv * sv;
       }
     }
+    ev[pc][sd][q][m][0] = v;
+    ev[pc][sd][q][m][1] = dt;
+    ev[pc][sd][q][m][2] = dr;
+    if constexpr (DIM == 3) ev[pc][sd][q][m][3] = dz;
+  }
+  __syncthreads();
+  // phase 3: the own side's face coefficients (Eqs. EqMortarPre, EqMortarDiff,
+  // EqMortarMass with jump = own - other and n = own outward normal)
+  const Real nu = G.nu;
+  const Real inv_rdth = Real(1) / (M.R * G.dth);
+  const Real inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
+  for (int e = threadIdx.x; e < 2 * NQ; e += blockDim.x) {
+    const int pc = e / NQ, q = e % NQ;
+    const int qt = q % N, qz = q / N;
+    const int seg = P[pc].seg;
+    const Real jxw = M.seg_active[seg] ? M.jxw[seg][qt][(DIM == 3) ? qz : 0] : Real(0);
+    const Real cth = trg[pc][qt][0], sth = trg[pc][qt][1];
     Real n[DIM] = {};
     n[0] = side == 0 ? cth : -cth;
     n[1] = side == 0 ? sth : -sth;
-    const Real pbar = Real(0.5) * (vo[DIM][0] + vx[DIM][0]);
+    const Real idr_o = Real(1) / G.dr[side], idr_x = Real(1) / G.dr[1 - side];
+    const Real pbar = Real(0.5) * (ev[pc][0][q][DIM][0] + ev[pc][1][q][DIM][0]);
     const Real tau = M.tau_pen[side];
-    const Real jxw = M.jxw[seg][qt][(DIM == 3) ? qz : 0];
     Real jn = 0;
 #pragma unroll
     for (int m = 0; m < DIM; ++m) {
-      const Real j = vo[m][0] - vx[m][0];
-      jn += j * n[m];
+      const Real* eo = ev[pc][0][q][m];
+      const Real* ex = ev[pc][1][q][m];
+      // Cartesian gradients of both sides, averaged, dotted with n
+      const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
+      const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
+      Real gavg[DIM];
+      gavg[0] = Real(0.5) * ((cth * dro - sth * dto) + (cth * drx - sth * dtx));
+      gavg[1] = Real(0.5) * ((sth * dro + cth * dto) + (sth * drx + cth * dtx));
+      if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * inv_dz;
       Real gn = 0;
 #pragma unroll
-      for (int e = 0; e < DIM; ++e) gn += Real(0.5) * (go[m][e] + gx[m][e]) * n[e];
+      for (int d2 = 0; d2 < DIM; ++d2) gn += gavg[d2] * n[d2];
+      const Real j = eo[0] - ex[0];
+      jn += j * n[m];
       const Real cv = pbar * n[m] - nu * gn + nu * tau * j;
-      // grad v coefficient -(nu/2) j n, as reference coefficients
       Real Gm[DIM];
 #pragma unroll
-      for (int e = 0; e < DIM; ++e) Gm[e] = Real(-0.5) * nu * j * n[e];
-      coef[pc][qq][m][0] = jxw * cv;
-      coef[pc][qq][m][1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
-      coef[pc][qq][m][2] = jxw * (cth * Gm[0] + sth * Gm[1]) / G.dr[side];
-      if constexpr (DIM == 3) coef[pc][qq][m][3] = jxw * Gm[2] * inv_dz;
+      for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
+      coef[pc][q][m][0] = jxw * cv;
+      coef[pc][q][m][1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
+      coef[pc][q][m][2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
+      if constexpr (DIM == 3) coef[pc][q][m][3] = jxw * Gm[2] * inv_dz;
     }
-    coef[pc][qq][DIM][0] = jxw * Real(-0.5) * jn;
-    for (int j = 1; j <= DIM; ++j) coef[pc][qq][DIM][j] = 0;
+    coef[pc][q][DIM][0] = jxw * Real(-0.5) * jn;
+#pragma unroll
+    for (int j = 1; j < NE; ++j) coef[pc][q][DIM][j] = 0;
   }
   __syncthreads();
+  // phase 4: integrate against the own cell's test functions
+  const size_t nsides = gridDim.x;
+  Real* Eo = Em + blockIdx.x;
   for (int e = threadIdx.x; e < NPT * NC; e += blockDim.x) {
-    const int m = e % NC, node = e / NC;
+    const int node = e % NPT, m = e / NPT;
     const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
     const Real fv = M.FV[side][b], fd = M.FD[side][b];
-    if (fv == Real(0) && fd == Real(0)) continue;
     Real acc = 0;
     for (int pc = 0; pc < 2; ++pc) {
       const int seg = P[pc].seg;
-      for (int qq = 0; qq < NQ; ++qq) {
-        const int qt = qq % N, qz = qq / N;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int qt = q % N, qz = q / N;
         const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
         const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
         const Real mv = M.MV[side][seg][qt][a], md = M.MD[side][seg][qt][a];
-        const Real* cf = coef[pc][qq][m];
-        Real s = cf[0] * mv * fv * vz + cf[1] * md * fv * vz + cf[2] * mv * fd * vz;
-        if constexpr (DIM == 3) s += cf[3] * mv * fv * dzv;
-        acc += s;
+        const Real* cf = coef[pc][q][m];
+        Real sq = (cf[0] * mv * fv + cf[1] * md * fv + cf[2] * mv * fd) * vz;
+        if constexpr (DIM == 3) sq += cf[3] * mv * fv * dzv;
+        acc += sq;
       }
     }
-    int it, ir, iz;
-    const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
-    atomic_add(dst + nd * NC + m, acc);
+    Eo[(size_t)(m * NPT + node) * nsides] = acc;
   }
 }
 
@@ -1076,16 +1236,28 @@ int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real val
   }
 
 template <typename Real, int DIM, int N>
-static int do_mortar(mns_handle* h, const Real* src, Real* dst, int mask, hipStream_t s) {
+static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStream_t s) {
   const Geom<Real> G = make_geom<Real>(h);
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
   const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
   const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
   const unsigned blocks = 2u * (unsigned)(G.n_theta * G.nz);
   timer_begin(h, TIMER_MORTAR, s);
-  hipLaunchKernelGGL((k_mortar<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, M, mtrig, src, dst, mask);
+  hipLaunchKernelGGL((k_mortar<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, M, mtrig, src, Em, mask);
   timer_end(h, TIMER_MORTAR, s);
   return hip_check(h, "mortar kernel");
+}
+
+template <typename Real, int DIM, int N>
+static int do_gather(mns_handle* h, const Real* E, const Real* Em, const Real* src, Real* dst, int mode,
+                     hipStream_t s) {
+  const Geom<Real> G = make_geom<Real>(h);
+  const long long nnodes = h->nnodes;
+  timer_begin(h, TIMER_OTHER, s);
+  hipLaunchKernelGGL((k_gather<Real, DIM, N>), dim3((unsigned)((nnodes + 255) / 256)), dim3(256), 0, s, G, h->k, E,
+                     Em, src, dst, mode);
+  timer_end(h, TIMER_OTHER, s);
+  return hip_check(h, "gather kernel");
 }
 
 template <typename Real, int DIM, int N>
@@ -1094,22 +1266,17 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   const Geom<Real> G = make_geom<Real>(h);
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
   const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
-  timer_begin(h, TIMER_OTHER, s);
-  int rc = launch_fill<Real>(dst, Real(0), h->ndofs, s);
-  timer_end(h, TIMER_OTHER, s);
-  if (rc) return set_error(h, rc, "fill");
+  Real* E = sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32;
+  Real* Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
   const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
   timer_begin(h, TIMER_VOLUME, s);
-  hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, dst);
+  hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
   timer_end(h, TIMER_VOLUME, s);
-  rc = hip_check(h, "volume kernel");
+  int rc = hip_check(h, "volume kernel");
   if (rc) return rc;
-  rc = do_mortar<Real, DIM, N>(h, src, dst, 1, s);
+  rc = do_mortar<Real, DIM, N>(h, src, Em, 1, s);
   if (rc) return rc;
-  timer_begin(h, TIMER_OTHER, s);
-  rc = launch_constraints<Real>(h, src, dst, Real(0), 0, s);
-  timer_end(h, TIMER_OTHER, s);
-  return rc ? set_error(h, rc, "constraints") : MNS_OK;
+  return do_gather<Real, DIM, N>(h, E, Em, src, dst, 0, s);
 }
 
 template <typename Real>
@@ -1138,16 +1305,16 @@ int launch_linearize<double>(mns_handle* h, const double* state, const double* h
 }
 
 int launch_residual(mns_handle* h, const double* state, double* res, hipStream_t s) {
-  int rc = launch_fill<double>(res, 0.0, h->ndofs, s);
-  if (rc) return set_error(h, rc, "fill");
+  int rc = MNS_OK;
   MNS_DISPATCH(h->dim, h->k, {
-    rc = do_state<DIM, N, true>(h, state, h->d_hist, h->d_force, nullptr, res, s);
+    rc = do_state<DIM, N, true>(h, state, h->desc.steady ? nullptr : h->d_hist, h->d_force, nullptr, h->d_E64, s);
     if (rc) return rc;
-    rc = do_mortar<double, DIM, N>(h, state, res, 0, s);
+    rc = do_mortar<double, DIM, N>(h, state, h->d_Em64, 0, s);
+    if (rc) return rc;
+    rc = do_gather<double, DIM, N>(h, h->d_E64, h->d_Em64, state, res, 1, s);
     if (rc) return rc;
   });
-  rc = launch_constraints<double>(h, state, res, 0.0, 1, s);
-  return rc ? set_error(h, rc, "constraints") : MNS_OK;
+  return MNS_OK;
 }
 
 template <typename Real, int DIM, int N>

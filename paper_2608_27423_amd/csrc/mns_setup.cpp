@@ -241,7 +241,17 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
   rc = upload(h, &h->d_hcell64, h->hcell);
   if (rc) return rc;
   rc = upload(h, &h->d_hcell32, to_f32(h->hcell));
-  return rc;
+  if (rc) return rc;
+  // local-result buffers of the volume and mortar kernels (summed by the gather kernel)
+  const size_t npt = (size_t)(d->dim == 3 ? h->n * h->n * h->n : h->n * h->n);
+  const size_t nE = (size_t)h->ncells * h->nc * npt;
+  const size_t nEm = (size_t)2 * d->n_theta * h->nz * h->nc * npt;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&h->d_E64, nE * sizeof(double))) != hipSuccess) return hipfail(h, e, "hipMalloc E");
+  if ((e = hipMalloc((void**)&h->d_E32, nE * sizeof(float))) != hipSuccess) return hipfail(h, e, "hipMalloc E");
+  if ((e = hipMalloc((void**)&h->d_Em64, nEm * sizeof(double))) != hipSuccess) return hipfail(h, e, "hipMalloc Em");
+  if ((e = hipMalloc((void**)&h->d_Em32, nEm * sizeof(float))) != hipSuccess) return hipfail(h, e, "hipMalloc Em");
+  return MNS_OK;
 }
 
 template <typename Real, int N>
