@@ -25,7 +25,20 @@ namespace mns {
 #define MNS_LDS_CPAD 0
 #endif
 #ifndef MNS_LDS_PAD
-#define MNS_LDS_PAD 4
+#define MNS_LDS_PAD 0
+#endif
+#ifndef MNS_PL_TRANSPOSE
+#define MNS_PL_TRANSPOSE 1
+#endif
+// occupancy hint for the volume kernel: the LDS footprint already limits it
+// to about two wavefronts per SIMD, so the scheduler may spend registers on ILP
+#ifndef MNS_VOL_WAVES
+#define MNS_VOL_WAVES 0
+#endif
+#if MNS_VOL_WAVES > 0
+#define MNS_VOL_ATTR __attribute__((amdgpu_waves_per_eu(MNS_VOL_WAVES, MNS_VOL_WAVES)))
+#else
+#define MNS_VOL_ATTR
 #endif
 
 template <typename Real, int DIM, int N>
@@ -532,15 +545,31 @@ __device__ inline void gather_line(const Geom<Real>& G, int k, const CellId& C, 
 // Jacobian vmult with stored linearization (Sec. 2.3 blocks, volume part)
 // ---------------------------------------------------------------------------
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
+struct PlaneShape {
+  static constexpr int ZS = (DIM == 3) ? 3 * DIM + 2 : DIM + 1;  // z-stage arrays (velocity V,D,DD; pressure V,D)
+  static constexpr int YS = (DIM == 3) ? 5 * DIM + 3 : 3 * DIM + 2; // r-stage arrays
+  static constexpr int TS = (DIM + 1) * (DIM + 1);                  // test coefficients
+  static constexpr int XS = (DIM + 1) * ((DIM == 3) ? 3 : 2);       // theta-transposed test arrays
+  static constexpr int A = (ZS > TS ? ZS : TS) * N * N;             // doubles per cell in buffer A
+  static constexpr int B = (YS > XS ? YS : XS) * N * N;             // doubles per cell in buffer B
+  static constexpr int REGION = A + B + MNS_LDS_PAD;
+};
+
+// Jacobian vmult with stored linearization, volume part (Sec. 2.3 blocks).
+// Plane pipeline: for every z plane q of Gauss points the lanes run the z
+// contraction of their nodal line for that plane, the r and theta
+// contractions through LDS, the pointwise operator, and the transposed theta
+// and r contractions; the z part of the integration accumulates in registers.
+// LDS holds one plane per cell in two ping-pong buffers.
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                         const Real* __restrict__ lin,
                                                         const Real* __restrict__ src, Real* __restrict__ E) {
   using S = Shape<Real, DIM, N>;
+  using P = PlaneShape<Real, DIM, N>;
   using LL = LinLayout<DIM>;
-  constexpr int NZ = S::NZ, NC = S::NC;
-  __shared__ Real lds[S::template lds_size<S::SLOTS>()];
-  // 1D tables in LDS for the lane-indexed rows and columns (the kernel
-  // argument copy T serves the uniform z contractions)
+  constexpr int NZ = S::NZ, NC = S::NC, PL = N * N;
+  __shared__ Real lds[S::CPW * P::REGION];
   __shared__ Tab1D<Real, N> sT;
   const int lane = threadIdx.x;
   {
@@ -553,36 +582,151 @@ __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real
   const int ta = t % N, tb = t / N;
   const int cell = blockIdx.x * S::CPW + cl;
   const bool active = cl < S::CPW && cell < G.ncells;
-  Real* L = lds + (active ? cl : 0) * (S::ES == 1 ? S::SLOTS * S::NPT + MNS_LDS_PAD : 1);
-  CellId C = decode_cell(G, active ? cell : 0);
+  Real* A = lds + (active ? cl : 0) * P::REGION;
+  Real* B = A + P::A;
+  const CellId C = decode_cell(G, active ? cell : 0);
+  const int me = tb * N + ta;  // this lane's position in a plane
+  // z-stage outputs and theta-transposed test arrays are written transposed
+  // (theta index major) so that every later LDS read is contiguous
+  const int meT = MNS_PL_TRANSPOSE ? ta * N + tb : me;
 
   Real u[NC][NZ];
   if (active) gather_line<Real, DIM, N>(G, k, C, ta, tb, src, true, u);
-  // linearization data of every point of the lane, requested before the
-  // evaluation so its latency overlaps the contractions
-  Real lv[NZ][LL::SIZE];
-  if (active) {
+  Real o[NC][NZ];
 #pragma unroll
-    for (int q = 0; q < NZ; ++q) {
-      const Real* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + tb * N + ta) * LL::SIZE;
+  for (int m = 0; m < NC; ++m)
 #pragma unroll
-      for (int j = 0; j < LL::SIZE; ++j) lv[q][j] = lp[j];
-    }
-  }
-  eval_stage_z<Real, DIM, N, DIM, true>(T, u, L, ta, tb, active);
-  __syncthreads();
-  eval_stage_r<Real, DIM, N, DIM, true>(sT, L, ta, tb, active);
+    for (int c = 0; c < NZ; ++c) o[m][c] = 0;
+  Real lv[LL::SIZE];
+  const Real* lbase = lin + ((size_t)(active ? cell : 0) * S::NPT + me) * LL::SIZE;
+  if (active)
+#pragma unroll
+    for (int j = 0; j < LL::SIZE; ++j) lv[j] = lbase[j];
+  const Real nu = G.nu, ct = G.ct;
 
-  // theta stage and pointwise operator, one z point at a time
-  Real tc[NZ][NC][S::NT];
-  if (active) {
-    const Real nu = G.nu, ct = G.ct;
 #pragma unroll
-    for (int q = 0; q < NZ; ++q) {
+  for (int q = 0; q < NZ; ++q) {
+    // ---- z stage for plane q (registers) -> A
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const bool vel = m < DIM;
+        const int base = vel ? m * (DIM == 3 ? 3 : 1) : DIM * (DIM == 3 ? 3 : 1);
+        if constexpr (DIM == 3) {
+          Real sv = 0, sd = 0, sdd = 0;
+#pragma unroll
+          for (int c = 0; c < NZ; ++c) {
+            sv += T.V[q][c] * u[m][c];
+            sd += T.D[q][c] * u[m][c];
+            if (vel) sdd += T.DD[q][c] * u[m][c];
+          }
+          A[(base + 0) * PL + meT] = sv;
+          A[(base + 1) * PL + meT] = sd;
+          if (vel) A[(base + 2) * PL + meT] = sdd;
+        } else {
+          A[base * PL + meT] = u[m][0];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- r stage: lane (ta, tqj = tb) reads column ta of A -> B.  All reads
+    // are issued before any store so they overlap (A and B may alias as far
+    // as the compiler can tell).
+    if (active) {
+      constexpr int ZV = (DIM == 3) ? 3 : 1, ZP = (DIM == 3) ? 2 : 1;
+      Real zin[P::ZS][N];
+#pragma unroll
+      for (int arr = 0; arr < P::ZS; ++arr)
+#pragma unroll
+        for (int b = 0; b < N; ++b) zin[arr][b] = A[arr * PL + (MNS_PL_TRANSPOSE ? ta * N + b : b * N + ta)];
+      Real yout[P::YS];
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const bool vel = m < DIM;
+        const int zb = vel ? m * ZV : DIM * ZV;
+        const int yb = vel ? m * S::NYV : DIM * S::NYV;
+        Real vv = 0, dv = 0, ddv = 0, vd = 0, vdd = 0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const Real zv = zin[zb][b];
+          vv += sT.V[tb][b] * zv;
+          dv += sT.D[tb][b] * zv;
+          if (vel) ddv += sT.DD[tb][b] * zv;
+          if constexpr (DIM == 3) {
+            vd += sT.V[tb][b] * zin[zb + 1][b];
+            if (vel) vdd += sT.V[tb][b] * zin[zb + 2][b];
+          }
+        }
+        yout[yb + 0] = vv;
+        yout[yb + 1] = dv;
+        if constexpr (DIM == 3) {
+          if (vel) {
+            yout[yb + 2] = ddv;
+            yout[yb + 3] = vd;
+            yout[yb + 4] = vdd;
+          } else {
+            yout[yb + 2] = vd;
+          }
+        } else {
+          if (vel) yout[yb + 2] = ddv;
+        }
+      }
+      (void)ZP;
+#pragma unroll
+      for (int arr = 0; arr < P::YS; ++arr) B[arr * PL + me] = yout[arr];
+    }
+    __syncthreads();
+    // ---- theta stage + pointwise operator: lane (tqi = ta, tqj = tb) -> test coefficients in A
+    Real lnext[LL::SIZE];
+    if (active && q + 1 < NZ)
+#pragma unroll
+      for (int j = 0; j < LL::SIZE; ++j) lnext[j] = lbase[(q + 1) * PL * LL::SIZE + j];
+    if (active) {
       RefVal<Real, DIM> rv[DIM], rp;
 #pragma unroll
-      for (int m = 0; m < DIM; ++m) eval_stage_t_vel<Real, DIM, N>(sT, L, m * S::NYV, ta, tb, q, rv[m]);
-      eval_stage_t_pres<Real, DIM, N>(sT, L, DIM * S::NYV, ta, tb, q, rp);
+      for (int m = 0; m < DIM; ++m) {
+        const Real* y = B + m * S::NYV * PL + tb * N;
+        Real v = 0, dt = 0, ddt = 0, dr = 0, ddr = 0, dz = 0, ddz = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2) {
+          const Real yvv = y[a2];
+          v += sT.V[ta][a2] * yvv;
+          dt += sT.D[ta][a2] * yvv;
+          ddt += sT.DD[ta][a2] * yvv;
+          dr += sT.V[ta][a2] * y[1 * PL + a2];
+          ddr += sT.V[ta][a2] * y[2 * PL + a2];
+          if constexpr (DIM == 3) {
+            dz += sT.V[ta][a2] * y[3 * PL + a2];
+            ddz += sT.V[ta][a2] * y[4 * PL + a2];
+          }
+        }
+        rv[m].v = v;
+        rv[m].d[0] = dt;
+        rv[m].d[1] = dr;
+        rv[m].dd[0] = ddt;
+        rv[m].dd[1] = ddr;
+        if constexpr (DIM == 3) {
+          rv[m].d[2] = dz;
+          rv[m].dd[2] = ddz;
+        }
+      }
+      {
+        const Real* y = B + DIM * S::NYV * PL + tb * N;
+        Real v = 0, dt = 0, dr = 0, dz = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2) {
+          v += sT.V[ta][a2] * y[a2];
+          dt += sT.D[ta][a2] * y[a2];
+          dr += sT.V[ta][a2] * y[1 * PL + a2];
+          if constexpr (DIM == 3) dz += sT.V[ta][a2] * y[2 * PL + a2];
+        }
+        rp.v = v;
+        rp.d[0] = dt;
+        rp.d[1] = dr;
+        if constexpr (DIM == 3) rp.d[2] = dz;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) rp.dd[e] = 0;
+      }
       const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
       Real du[DIM], gdu[DIM][DIM], ldu[DIM], gdp[DIM], dummy;
 #pragma unroll
@@ -592,28 +736,28 @@ __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real
       }
       to_physical<Real, DIM>(g, nullptr, rp, gdp, dummy, false);
       const Real dp = rp.v;
-      const Real* lp = lv[q];
       Real a[DIM], gu[DIM][DIM], tR[DIM];
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
-        a[m] = lp[LL::A + m];
-        tR[m] = lp[LL::TR + m];
+        a[m] = lv[LL::A + m];
+        tR[m] = lv[LL::TR + m];
 #pragma unroll
-        for (int e = 0; e < DIM; ++e) gu[m][e] = lp[LL::GU + m * DIM + e];
+        for (int e = 0; e < DIM; ++e) gu[m][e] = lv[LL::GU + m * DIM + e];
       }
-      const Real tau = lp[LL::TAU];
+      const Real tau = lv[LL::TAU];
       // g_v = c_t du + (grad u) du + (grad du) a ;  R' du = g_v - nu lap du + grad dp
       Real gv[DIM], Rp[DIM], divdu = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
-        Real s = ct * du[m];
+        Real s2 = ct * du[m];
 #pragma unroll
-        for (int e = 0; e < DIM; ++e) s += gu[m][e] * du[e] + gdu[m][e] * a[e];
-        gv[m] = s;
-        Rp[m] = s - nu * ldu[m] + gdp[m];
+        for (int e = 0; e < DIM; ++e) s2 += gu[m][e] * du[e] + gdu[m][e] * a[e];
+        gv[m] = s2;
+        Rp[m] = s2 - nu * ldu[m] + gdp[m];
         divdu += gdu[m][m];
       }
       // G_v = nu grad du - dp I + tau R' du (x) a + tau R (x) du ;  G_q = tau R' du
+      Real tc[NC][S::NT];
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
         Real Gm[DIM];
@@ -621,25 +765,75 @@ __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real
 #pragma unroll
         for (int e = 0; e < DIM; ++e) Gm[e] = nu * gdu[m][e] + tRp * a[e] + tR[m] * du[e];
         Gm[m] -= dp;
-        to_reference<Real, DIM>(g, g.jxw, gv[m], Gm, tc[q][m]);
+        to_reference<Real, DIM>(g, g.jxw, gv[m], Gm, tc[m]);
       }
       Real Gq[DIM];
 #pragma unroll
       for (int e = 0; e < DIM; ++e) Gq[e] = tau * Rp[e];
-      to_reference<Real, DIM>(g, g.jxw, divdu, Gq, tc[q][DIM]);
-    }
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int q = 0; q < NZ; ++q)
+      to_reference<Real, DIM>(g, g.jxw, divdu, Gq, tc[DIM]);
 #pragma unroll
       for (int m = 0; m < NC; ++m)
 #pragma unroll
-        for (int j = 0; j < S::NT; ++j) L[((m * S::NT + j) * S::NPT + q * S::PLANE + tb * N + ta) * S::ES] = tc[q][m][j];
+        for (int j = 0; j < S::NT; ++j) A[(m * S::NT + j) * PL + me] = tc[m][j];
+    }
+    if (active && q + 1 < NZ)
+#pragma unroll
+      for (int j = 0; j < LL::SIZE; ++j) lv[j] = lnext[j];
+    __syncthreads();
+    // ---- theta transpose: lane (ta, tqj = tb) contracts over qi -> B (all
+    // reads first, then the stores)
+    constexpr int NX = (DIM == 3) ? 3 : 2;
+    if (active) {
+      Real tin[P::TS][N];
+#pragma unroll
+      for (int arr = 0; arr < P::TS; ++arr)
+#pragma unroll
+        for (int qi = 0; qi < N; ++qi) tin[arr][qi] = A[arr * PL + tb * N + qi];
+      Real xout[P::XS];
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const Real(*tp)[N] = tin + m * S::NT;
+        Real x0 = 0, xr = 0, xz = 0;
+#pragma unroll
+        for (int qi = 0; qi < N; ++qi) {
+          x0 += sT.V[qi][ta] * tp[0][qi] + sT.D[qi][ta] * tp[1][qi];
+          xr += sT.V[qi][ta] * tp[2][qi];
+          if constexpr (DIM == 3) xz += sT.V[qi][ta] * tp[3][qi];
+        }
+        xout[m * NX + 0] = x0;
+        xout[m * NX + 1] = xr;
+        if constexpr (DIM == 3) xout[m * NX + 2] = xz;
+      }
+#pragma unroll
+      for (int arr = 0; arr < P::XS; ++arr) B[arr * PL + meT] = xout[arr];
+    }
+    __syncthreads();
+    // ---- r transpose: lane (ta, tb) contracts over qj; z part accumulates
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        Real y0 = 0, yz = 0;
+#pragma unroll
+        for (int qj = 0; qj < N; ++qj) {
+          const int xi = MNS_PL_TRANSPOSE ? ta * N + qj : qj * N + ta;
+          y0 += sT.V[qj][tb] * B[(m * NX + 0) * PL + xi] + sT.D[qj][tb] * B[(m * NX + 1) * PL + xi];
+          if constexpr (DIM == 3) yz += sT.V[qj][tb] * B[(m * NX + 2) * PL + xi];
+        }
+        if constexpr (DIM == 3) {
+#pragma unroll
+          for (int c = 0; c < NZ; ++c) o[m][c] += T.V[q][c] * y0 + T.D[q][c] * yz;
+        } else {
+          o[m][0] = y0;
+        }
+      }
+    }
   }
-  __syncthreads();
-  integrate_store<Real, DIM, N>(sT, T, L, ta, tb, active, cell, G.ncells, E);
+  if (!active) return;
+  Real* Ec = E + cell;
+#pragma unroll
+  for (int m = 0; m < NC; ++m)
+#pragma unroll
+    for (int c = 0; c < NZ; ++c) Ec[(size_t)(m * S::NPT + c * PL + me) * G.ncells] = o[m][c];
 }
 
 // ---------------------------------------------------------------------------
