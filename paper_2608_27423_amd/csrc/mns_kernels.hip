@@ -1104,34 +1104,46 @@ __device__ inline void mortar_pieces(const Geom<Real>& G, const MortarTab<Real, 
   }
 }
 
-// Mortar kernel: one 64-lane block per interface cell side (own cell) with
-// its two overlapping other-side cells.  Phase 1 stages the three cells'
-// nodal data, the mortar tables and the point angles in LDS; phase 2
-// evaluates value and reference derivatives of every component at every
-// mortar point on both sides (lanes over piece x side x point x component);
-// phase 3 forms the own side's face coefficients per point; phase 4
-// integrates them against the own cell's test functions and stores the
-// cell side's local result Em[comp][local node][cell side].
+// Mortar kernel (Sec. 2.1 face terms with the mapped segment quadrature of
+// Sec. 3.2).  A 64-lane block handles FPB interface cell sides ("faces"); each
+// face couples its own cell with the two overlapping cells of the other side.
+//   Phase A, lane = (face, piece, side, component): the lane loads the 27 (or
+//     n^d) nodal values of that component of that cell and evaluates value and
+//     reference derivatives at the piece's mortar points by sum factorization
+//     in registers: r first (interface value and normal derivative), then
+//     theta at the segment's points, then z at the Gauss points.
+//   Phase B, lane = (face, piece, point): the own side's face coefficients
+//     (jump = own - other, n = own outward normal).
+//   Phase C, lane = (face, component, radial node row): the transposed sum
+//     factorization integrates the coefficients against the own cell's test
+//     functions; the result is stored as Em[comp][local node][face].
+template <typename Real, int DIM, int N>
+struct MortarShape {
+  static constexpr int NZ = (DIM == 3) ? N : 1;
+  static constexpr int NC = DIM + 1;
+  static constexpr int NQ = N * NZ;   // mortar points per piece
+  static constexpr int NE = DIM + 1;  // value + reference derivatives
+  static constexpr int LPF = 4 * NC;  // lanes per face in phase A
+  static constexpr int PER_FACE = (2 * 2 * NQ * NC * NE + 2 * NQ * NC * NE) * (int)sizeof(Real);
+  static constexpr int FPB0 = 64 / LPF;
+  static constexpr int FPB_LDS = 36000 / PER_FACE > 0 ? 36000 / PER_FACE : 1;
+  static constexpr int FPB = FPB0 < FPB_LDS ? FPB0 : FPB_LDS;
+};
+
 template <typename Real, int DIM, int N>
 __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                const MortarTab<Real, N>* __restrict__ Mp,
                                                const Real* __restrict__ mtrig, const Real* __restrict__ src,
                                                Real* __restrict__ Em, int mask) {
   using S = Shape<Real, DIM, N>;
-  constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ;
-  constexpr int NQ = N * NZ;  // mortar points per segment
-  constexpr int NE = DIM + 1; // value + reference derivatives
-  __shared__ Real nod[3][NC][NPT];
+  using MS = MortarShape<Real, DIM, N>;
+  constexpr int NC = MS::NC, NZ = MS::NZ, NQ = MS::NQ, NE = MS::NE, FPB = MS::FPB;
   __shared__ MortarTab<Real, N> M;
-  __shared__ Real trg[2][N][2];
-  __shared__ Real ev[2][2][NQ][NC][NE];  // [piece][own=0 / other=1][point][comp][value, d_theta, d_r, d_z]
-  __shared__ Real coef[2][NQ][NC][NE];
+  __shared__ Real trg[FPB][2][N][2];
+  __shared__ Real ev[FPB][2][2][NQ][NC][NE];  // [face][piece][own=0 / other=1][point][comp][quantity]
+  __shared__ Real coef[FPB][2][NQ][NC][NE];
   const int nfaces = G.n_theta * G.nz;
-  const int side = blockIdx.x / nfaces;
-  const int f = blockIdx.x % nfaces;
-  const int ct = f % G.n_theta, cz = f / G.n_theta;
-  const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
-  // phase 1: tables and nodal data
+  const int nsides = 2 * nfaces;
   {
     const int* srcw = (const int*)Mp;
     int* dstw = (int*)&M;
@@ -1139,84 +1151,118 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
     for (int i = threadIdx.x; i < NW; i += blockDim.x) dstw[i] = srcw[i];
   }
   __syncthreads();
-  Piece<Real, DIM, N> P[2];
-  mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
-  for (int i = threadIdx.x; i < 2 * N * 2; i += blockDim.x) {
-    const int pc = i / (2 * N), q = (i / 2) % N, c = i % 2;
-    trg[pc][q][c] = mtrig[(((size_t)P[pc].jface * 2 + P[pc].seg) * N + q) * 2 + c];
-  }
-  for (int e = threadIdx.x; e < 3 * NPT; e += blockDim.x) {
-    const int which = e / NPT, node = e % NPT;
-    const CellId C = which == 0 ? own : P[which - 1].other;
-    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
-    int it, ir, iz;
-    const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
-    const bool vf = mask && vel_fixed<Real, DIM>(G, C.dom, ir, iz);
-    const bool pf = mask && p_fixed(G, C.dom, it, ir, iz);
+  // ---- phase A: evaluation
+  {
+    const int fl = threadIdx.x / MS::LPF;
+    const int r = threadIdx.x % MS::LPF;
+    const int m = r % NC, sd = (r / NC) % 2, pc = r / (2 * NC);
+    const int fs = blockIdx.x * FPB + fl;  // face-side index: side * nfaces + face
+    if (fl < FPB && fs < nsides) {
+      const int side = fs / nfaces, f = fs % nfaces;
+      const int ct = f % G.n_theta, cz = f / G.n_theta;
+      Piece<Real, DIM, N> P[2];
+      mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
+      const int seg = P[pc].seg;
+      const CellId C = sd == 0 ? CellId{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz} : P[pc].other;
+      const int cside = sd == 0 ? side : 1 - side;
+      if (sd == 0 && m == 0) {
+        // point angles of this piece (one lane per face and piece)
+        for (int q = 0; q < N; ++q)
+          for (int c2 = 0; c2 < 2; ++c2)
+            trg[fl][pc][q][c2] = mtrig[(((size_t)P[pc].jface * 2 + seg) * N + q) * 2 + c2];
+      }
+      // r reduction at the interface: F0 = face value, F1 = normal derivative
+      Real F0[NZ][N], F1[NZ][N];
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) nod[which][m][node] = vf ? Real(0) : src[nd * NC + m];
-    nod[which][DIM][node] = pf ? Real(0) : src[nd * NC + DIM];
-  }
-  __syncthreads();
-  // phase 2: evaluation at the mortar points
-  for (int e = threadIdx.x; e < 2 * 2 * NQ * NC; e += blockDim.x) {
-    const int m = e % NC;
-    const int q = (e / NC) % NQ;
-    const int sd = (e / (NC * NQ)) % 2;
-    const int pc = e / (NC * NQ * 2);
-    const int seg = P[pc].seg;
-    const int cside = sd == 0 ? side : 1 - side;
-    const int qt = q % N, qz = q / N;
-    const Real* x = nod[sd == 0 ? 0 : 1 + pc][m];
-    Real v = 0, dt = 0, dr = 0, dz = 0;
-    for (int c = 0; c < NZ; ++c) {
-      const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
-      const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
+      for (int c = 0; c < NZ; ++c)
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        const Real fv = M.FV[cside][b], fd = M.FD[cside][b];
-        Real sv = 0, st = 0;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-          const Real xv = x[(c * N + b) * N + a];
-          sv += M.MV[cside][seg][qt][a] * xv;
-          st += M.MD[cside][seg][qt][a] * xv;
+        for (int a2 = 0; a2 < N; ++a2) {
+          F0[c][a2] = 0;
+          F1[c][a2] = 0;
         }
-        v += fv * vz * sv;
-        dt += fv * vz * st;
-        dr += fd * vz * sv;
-        dz += fv * dzv * sv;
+#pragma unroll
+      for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int b2 = 0; b2 < N; ++b2) {
+          const Real fv = M.FV[cside][b2], fd = M.FD[cside][b2];
+#pragma unroll
+          for (int a2 = 0; a2 < N; ++a2) {
+            int it, ir, iz;
+            const long long nd = node_of<Real, DIM>(G, k, C, a2, b2, c, it, ir, iz);
+            const bool fixed = mask && (m < DIM ? vel_fixed<Real, DIM>(G, C.dom, ir, iz) : p_fixed(G, C.dom, it, ir, iz));
+            const Real xv = src[nd * NC + m];
+            const Real x = fixed ? Real(0) : xv;
+            F0[c][a2] += fv * x;
+            F1[c][a2] += fd * x;
+          }
+        }
+      // theta at the piece's points, then z at the Gauss points
+#pragma unroll
+      for (int qt = 0; qt < N; ++qt) {
+        Real G0[NZ], Gt[NZ], Gr[NZ];
+#pragma unroll
+        for (int c = 0; c < NZ; ++c) {
+          Real s0 = 0, st = 0, sr = 0;
+#pragma unroll
+          for (int a2 = 0; a2 < N; ++a2) {
+            const Real mv = M.MV[cside][seg][qt][a2], md = M.MD[cside][seg][qt][a2];
+            s0 += mv * F0[c][a2];
+            st += md * F0[c][a2];
+            sr += mv * F1[c][a2];
+          }
+          G0[c] = s0;
+          Gt[c] = st;
+          Gr[c] = sr;
+        }
+#pragma unroll
+        for (int qz = 0; qz < NZ; ++qz) {
+          Real v = 0, dt = 0, dr = 0, dz = 0;
+#pragma unroll
+          for (int c = 0; c < NZ; ++c) {
+            const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+            const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
+            v += vz * G0[c];
+            dt += vz * Gt[c];
+            dr += vz * Gr[c];
+            dz += dzv * G0[c];
+          }
+          Real* e = ev[fl][pc][sd][qz * N + qt][m];
+          e[0] = v;
+          e[1] = dt;
+          e[2] = dr;
+          if constexpr (DIM == 3) e[3] = dz;
+        }
       }
     }
-    ev[pc][sd][q][m][0] = v;
-    ev[pc][sd][q][m][1] = dt;
-    ev[pc][sd][q][m][2] = dr;
-    if constexpr (DIM == 3) ev[pc][sd][q][m][3] = dz;
   }
   __syncthreads();
-  // phase 3: the own side's face coefficients (Eqs. EqMortarPre, EqMortarDiff,
-  // EqMortarMass with jump = own - other and n = own outward normal)
+  // ---- phase B: face coefficients of the own side
   const Real nu = G.nu;
   const Real inv_rdth = Real(1) / (M.R * G.dth);
   const Real inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
-  for (int e = threadIdx.x; e < 2 * NQ; e += blockDim.x) {
-    const int pc = e / NQ, q = e % NQ;
+  for (int e = threadIdx.x; e < FPB * 2 * NQ; e += blockDim.x) {
+    const int fl = e / (2 * NQ), pc = (e / NQ) % 2, q = e % NQ;
+    const int fs = blockIdx.x * FPB + fl;
+    if (fs >= nsides) continue;
+    const int side = fs / nfaces, f = fs % nfaces;
+    Piece<Real, DIM, N> P[2];
+    mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
     const int qt = q % N, qz = q / N;
     const int seg = P[pc].seg;
     const Real jxw = M.seg_active[seg] ? M.jxw[seg][qt][(DIM == 3) ? qz : 0] : Real(0);
-    const Real cth = trg[pc][qt][0], sth = trg[pc][qt][1];
+    const Real cth = trg[fl][pc][qt][0], sth = trg[fl][pc][qt][1];
     Real n[DIM] = {};
     n[0] = side == 0 ? cth : -cth;
     n[1] = side == 0 ? sth : -sth;
-    const Real idr_o = Real(1) / G.dr[side], idr_x = Real(1) / G.dr[1 - side];
-    const Real pbar = Real(0.5) * (ev[pc][0][q][DIM][0] + ev[pc][1][q][DIM][0]);
-    const Real tau = M.tau_pen[side];
+    const Real idr_o = Real(1) / (side == 0 ? G.dr[0] : G.dr[1]);
+    const Real idr_x = Real(1) / (side == 0 ? G.dr[1] : G.dr[0]);
+    const Real pbar = Real(0.5) * (ev[fl][pc][0][q][DIM][0] + ev[fl][pc][1][q][DIM][0]);
+    const Real tau = side == 0 ? M.tau_pen[0] : M.tau_pen[1];
     Real jn = 0;
 #pragma unroll
     for (int m = 0; m < DIM; ++m) {
-      const Real* eo = ev[pc][0][q][m];
-      const Real* ex = ev[pc][1][q][m];
-      // Cartesian gradients of both sides, averaged, dotted with n
+      const Real* eo = ev[fl][pc][0][q][m];
+      const Real* ex = ev[fl][pc][1][q][m];
       const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
       const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
       Real gavg[DIM];
@@ -1232,39 +1278,83 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
       Real Gm[DIM];
 #pragma unroll
       for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
-      coef[pc][q][m][0] = jxw * cv;
-      coef[pc][q][m][1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
-      coef[pc][q][m][2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
-      if constexpr (DIM == 3) coef[pc][q][m][3] = jxw * Gm[2] * inv_dz;
+      Real* cf = coef[fl][pc][q][m];
+      cf[0] = jxw * cv;
+      cf[1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
+      cf[2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
+      if constexpr (DIM == 3) cf[3] = jxw * Gm[2] * inv_dz;
     }
-    coef[pc][q][DIM][0] = jxw * Real(-0.5) * jn;
+    Real* cf = coef[fl][pc][q][DIM];
+    cf[0] = jxw * Real(-0.5) * jn;
 #pragma unroll
-    for (int j = 1; j < NE; ++j) coef[pc][q][DIM][j] = 0;
+    for (int j = 1; j < NE; ++j) cf[j] = 0;
   }
   __syncthreads();
-  // phase 4: integrate against the own cell's test functions
-  const size_t nsides = gridDim.x;
-  Real* Eo = Em + blockIdx.x;
-  for (int e = threadIdx.x; e < NPT * NC; e += blockDim.x) {
-    const int node = e % NPT, m = e / NPT;
-    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
-    const Real fv = M.FV[side][b], fd = M.FD[side][b];
-    Real acc = 0;
+  // ---- phase C: integration against the own cell's test functions
+  for (int e = threadIdx.x; e < FPB * NC * N; e += blockDim.x) {
+    const int fl = e / (NC * N), m = (e / N) % NC, b2 = e % N;
+    const int fs = blockIdx.x * FPB + fl;
+    if (fs >= nsides) continue;
+    const int side = fs / nfaces, f = fs % nfaces;
+    Piece<Real, DIM, N> P[2];
+    mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
+    const Real fv = M.FV[side][b2], fd = M.FD[side][b2];
+    Real out[NZ][N];
+#pragma unroll
+    for (int c = 0; c < NZ; ++c)
+#pragma unroll
+      for (int a2 = 0; a2 < N; ++a2) out[c][a2] = 0;
     for (int pc = 0; pc < 2; ++pc) {
       const int seg = P[pc].seg;
+      // z reverse: H0 (value + z-derivative terms), Ht, Hr at (c, qt)
+      Real H0[NZ][N], Ht[NZ][N], Hr[NZ][N];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int qt = q % N, qz = q / N;
-        const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
-        const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
-        const Real mv = M.MV[side][seg][qt][a], md = M.MD[side][seg][qt][a];
-        const Real* cf = coef[pc][q][m];
-        Real sq = (cf[0] * mv * fv + cf[1] * md * fv + cf[2] * mv * fd) * vz;
-        if constexpr (DIM == 3) sq += cf[3] * mv * fv * dzv;
-        acc += sq;
+      for (int qt = 0; qt < N; ++qt) {
+        Real f0[NZ], ft[NZ], fr[NZ], fz[NZ];
+#pragma unroll
+        for (int qz = 0; qz < NZ; ++qz) {
+          const Real* cf = coef[fl][pc][qz * N + qt][m];
+          f0[qz] = cf[0];
+          ft[qz] = cf[1];
+          fr[qz] = cf[2];
+          fz[qz] = (DIM == 3) ? cf[3] : Real(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NZ; ++c) {
+          Real h0 = 0, ht = 0, hr = 0;
+#pragma unroll
+          for (int qz = 0; qz < NZ; ++qz) {
+            const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+            const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
+            h0 += vz * f0[qz] + dzv * fz[qz];
+            ht += vz * ft[qz];
+            hr += vz * fr[qz];
+          }
+          H0[c][qt] = h0;
+          Ht[c][qt] = ht;
+          Hr[c][qt] = hr;
+        }
       }
+      // theta reverse and the r expansion for this lane's row b2
+#pragma unroll
+      for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2) {
+          Real k0 = 0, k1 = 0;
+#pragma unroll
+          for (int qt = 0; qt < N; ++qt) {
+            const Real mv = M.MV[side][seg][qt][a2], md = M.MD[side][seg][qt][a2];
+            k0 += mv * H0[c][qt] + md * Ht[c][qt];
+            k1 += mv * Hr[c][qt];
+          }
+          out[c][a2] += fv * k0 + fd * k1;
+        }
     }
-    Eo[(size_t)(m * NPT + node) * nsides] = acc;
+#pragma unroll
+    for (int c = 0; c < NZ; ++c)
+#pragma unroll
+      for (int a2 = 0; a2 < N; ++a2)
+        Em[(size_t)(m * S::NPT + c * S::PLANE + b2 * N + a2) * nsides + fs] = out[c][a2];
   }
 }
 
@@ -1435,7 +1525,8 @@ static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStre
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
   const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
   const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
-  const unsigned blocks = 2u * (unsigned)(G.n_theta * G.nz);
+  const unsigned blocks = (2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
+                         MortarShape<Real, DIM, N>::FPB;
   timer_begin(h, TIMER_MORTAR, s);
   hipLaunchKernelGGL((k_mortar<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, M, mtrig, src, Em, mask);
   timer_end(h, TIMER_MORTAR, s);
