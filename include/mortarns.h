@@ -165,6 +165,17 @@ void mns_default_solve_opts(mns_solve_opts* opts);
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
               void* stream);
 
+/* Kernel configuration of the Jacobian application (tuning knobs; every
+ * setting computes the same product).  fused_launch = 1 (default): volume
+ * cells and mortar faces are integrated in one launch whose first blocks take
+ * the mortar faces; 0: two launches.  Takes effect on the next apply call.
+ * Errors: INVALID_ARG. */
+typedef struct {
+  int fused_launch;
+} mns_kernel_config;
+int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg);
+int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg);
+
 /* Kernel timing for measurement.  mns_enable_timing(h, capacity) makes every
  * later mns_apply_jacobian record a pair of HIP events around each of its
  * kernels on the launch stream (capacity = max recorded launches per kernel

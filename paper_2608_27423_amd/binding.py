@@ -24,7 +24,7 @@ MNS_F32 = 1
 EXPORTED = [
     "mns_setup_mesh", "mns_n_dofs", "mns_rotate_rotor", "mns_set_linearization", "mns_apply_jacobian",
     "mns_apply_residual", "mns_compute_diagonal", "mns_default_solve_opts", "mns_solve", "mns_enable_timing",
-    "mns_read_timing", "mns_last_error", "mns_destroy",
+    "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
 ]
 
 
@@ -55,6 +55,10 @@ class SolveReport(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelConfig(ctypes.Structure):
+    _fields_ = [("fused_launch", ctypes.c_int)]
 
 
 class Timing(ctypes.Structure):
@@ -90,6 +94,8 @@ def lib():
         L.mns_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), vp]
         L.mns_enable_timing.argtypes = [vp, ctypes.c_int]
         L.mns_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.mns_set_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
+        L.mns_get_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
         L.mns_last_error.argtypes = [vp]
         L.mns_last_error.restype = ctypes.c_char_p
         L.mns_destroy.argtypes = [vp]
@@ -221,6 +227,18 @@ class Operator:
         d = rep.as_dict()
         d["rc"] = rc
         return x, d
+
+    def set_kernel_config(self, **kw):
+        c = KernelConfig()
+        self._check(self._L.mns_get_kernel_config(self._h, ctypes.byref(c)))
+        for k2, v in kw.items():
+            setattr(c, k2, int(v))
+        return self._check(self._L.mns_set_kernel_config(self._h, ctypes.byref(c)))
+
+    def get_kernel_config(self):
+        c = KernelConfig()
+        self._check(self._L.mns_get_kernel_config(self._h, ctypes.byref(c)))
+        return {k2: getattr(c, k2) for k2, _ in c._fields_}
 
     def enable_timing(self, capacity):
         return self._check(self._L.mns_enable_timing(self._h, int(capacity)))

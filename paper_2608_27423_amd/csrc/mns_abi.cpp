@@ -235,6 +235,20 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
   return rc;
 }
 
+int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg) {
+  if (!h || !cfg) return MNS_ERR_INVALID_ARG;
+  if (cfg->fused_launch != 0 && cfg->fused_launch != 1)
+    return set_error(h, MNS_ERR_INVALID_ARG, "fused_launch must be 0 or 1");
+  h->fused = cfg->fused_launch;
+  return MNS_OK;
+}
+
+int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg) {
+  if (!h || !cfg) return MNS_ERR_INVALID_ARG;
+  cfg->fused_launch = h->fused;
+  return MNS_OK;
+}
+
 int mns_enable_timing(mns_handle* h, int capacity) {
   if (!h || capacity < 0) return MNS_ERR_INVALID_ARG;
   hipError_t e = hipDeviceSynchronize();

@@ -126,6 +126,8 @@ struct mns_handle {
   double* h_red = nullptr;      // pinned host mirror
   int red_cap = 0;
   bool diag_valid = false;
+  // kernel configuration (mns_set_kernel_config): fused volume + mortar launch
+  int fused = 1;
   hipStream_t stream = nullptr;
   std::string err;
   // optional kernel timing (mns_enable_timing): event pairs per kernel class

@@ -457,39 +457,57 @@ __global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real*
   const int nrn = pick(dom, G.nrn), nrd = pick(dom, G.nr);
   const int ir = (int)(l2 % nrn);
   const int iz = (int)(l2 / nrn);
-  // candidate cells per direction (cell index, local node index)
-  int tc[2], ta[2], nt = 1;
+  // candidate cells per direction: (cell index, local node index, valid);
+  // the loops below have fixed trip counts so that all loads are issued
+  // together (invalid candidates are predicated off)
+  int tc[2], ta[2];
+  bool tv[2];
   tc[0] = it / k;
   ta[0] = it % k;
-  if (ta[0] == 0) {
-    tc[1] = (tc[0] == 0 ? G.n_theta : tc[0]) - 1;
-    ta[1] = k;
-    nt = 2;
-  }
-  int rc[2], rb[2], nrc = 0;
-  if (ir / k < nrd) { rc[nrc] = ir / k; rb[nrc] = ir % k; ++nrc; }
-  if (ir % k == 0 && ir > 0) { rc[nrc] = ir / k - 1; rb[nrc] = k; ++nrc; }
-  int zc[2], zb[2], nzc = 0;
+  tv[0] = true;
+  tc[1] = (tc[0] == 0 ? G.n_theta : tc[0]) - 1;
+  ta[1] = k;
+  tv[1] = ta[0] == 0;
+  int rc[2], rb[2];
+  bool rv[2];
+  rc[0] = ir / k;
+  rb[0] = ir % k;
+  rv[0] = rc[0] < nrd;
+  rc[1] = ir / k - 1;
+  rb[1] = k;
+  rv[1] = (ir % k == 0) && ir > 0;
+  int zc[2], zb[2];
+  bool zv[2];
   if constexpr (DIM == 3) {
-    if (iz / k < G.nz) { zc[nzc] = iz / k; zb[nzc] = iz % k; ++nzc; }
-    if (iz % k == 0 && iz > 0) { zc[nzc] = iz / k - 1; zb[nzc] = k; ++nzc; }
+    zc[0] = iz / k;
+    zb[0] = iz % k;
+    zv[0] = zc[0] < G.nz;
+    zc[1] = iz / k - 1;
+    zb[1] = k;
+    zv[1] = (iz % k == 0) && iz > 0;
   } else {
-    zc[0] = 0;
-    zb[0] = 0;
-    nzc = 1;
+    zc[0] = zc[1] = 0;
+    zb[0] = zb[1] = 0;
+    zv[0] = true;
+    zv[1] = false;
   }
   Real acc[NC];
 #pragma unroll
   for (int m = 0; m < NC; ++m) acc[m] = 0;
   const int cbase = dom ? (int)G.cell_off1 : 0;
-  for (int z = 0; z < nzc; ++z)
-    for (int r = 0; r < nrc; ++r)
-      for (int t = 0; t < nt; ++t) {
+  const size_t cstride = (size_t)S::NPT * G.ncells;
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (!(zv[z] && rv[r] && tv[t])) continue;
         const int cell = cbase + tc[t] + G.n_theta * (rc[r] + nrd * zc[z]);
         const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + rb[r] * N + ta[t];
         const Real* e = E + (size_t)loc * G.ncells + cell;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) acc[m] += e[(size_t)m * S::NPT * G.ncells];
+        for (int m = 0; m < NC; ++m) acc[m] += e[m * cstride];
       }
   // mortar cell sides: every node of a rotor outer-ring cell or a stator
   // inner-ring cell (the grad v face term reaches all of them)
@@ -499,13 +517,17 @@ __global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real*
   if (bm >= 0 && Em) {
     const int nfaces = G.n_theta * G.nz;
     const int nsides = 2 * nfaces;
-    for (int z = 0; z < nzc; ++z)
-      for (int t = 0; t < nt; ++t) {
+    const size_t mstride = (size_t)S::NPT * nsides;
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (!(zv[z] && tv[t])) continue;
         const int cs = dom * nfaces + tc[t] + G.n_theta * zc[z];
         const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + bm * N + ta[t];
         const Real* e = Em + (size_t)loc * nsides + cs;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) acc[m] += e[(size_t)m * S::NPT * nsides];
+        for (int m = 0; m < NC; ++m) acc[m] += e[m * mstride];
       }
   }
   const bool vf = vel_fixed<Real, DIM>(G, dom, ir, iz);
@@ -562,15 +584,21 @@ struct PlaneShape {
 // and r contractions; the z part of the integration accumulates in registers.
 // LDS holds one plane per cell in two ping-pong buffers.
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
-                                                        const Real* __restrict__ lin,
-                                                        const Real* __restrict__ src, Real* __restrict__ E) {
+struct VolumeSmem {
+  Tab1D<Real, N> sT;
+  Real lds[Shape<Real, DIM, N>::CPW * PlaneShape<Real, DIM, N>::REGION];
+};
+
+template <typename Real, int DIM, int N>
+__device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
+                                    const Real* __restrict__ lin, const Real* __restrict__ src,
+                                    Real* __restrict__ E, VolumeSmem<Real, DIM, N>& sm) {
   using S = Shape<Real, DIM, N>;
   using P = PlaneShape<Real, DIM, N>;
   using LL = LinLayout<DIM>;
   constexpr int NZ = S::NZ, NC = S::NC, PL = N * N;
-  __shared__ Real lds[S::CPW * P::REGION];
-  __shared__ Tab1D<Real, N> sT;
+  Real* lds = sm.lds;
+  Tab1D<Real, N>& sT = sm.sT;
   const int lane = threadIdx.x;
   {
     constexpr int NW = (int)(sizeof(Tab1D<Real, N>) / sizeof(Real));
@@ -580,7 +608,7 @@ __global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> 
   const int cl = lane / S::TPC;
   const int t = lane % S::TPC;
   const int ta = t % N, tb = t / N;
-  const int cell = blockIdx.x * S::CPW + cl;
+  const int cell = vblock * S::CPW + cl;
   const bool active = cl < S::CPW && cell < G.ncells;
   Real* A = lds + (active ? cl : 0) * P::REGION;
   Real* B = A + P::A;
@@ -834,6 +862,15 @@ __global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> 
   for (int m = 0; m < NC; ++m)
 #pragma unroll
     for (int c = 0; c < NZ; ++c) Ec[(size_t)(m * S::NPT + c * PL + me) * G.ncells] = o[m][c];
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                                                     const Real* __restrict__ lin,
+                                                                     const Real* __restrict__ src,
+                                                                     Real* __restrict__ E) {
+  __shared__ VolumeSmem<Real, DIM, N> sm;
+  volume_block<Real, DIM, N>(G, T, k, blockIdx.x, lin, src, E, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1131,17 +1168,26 @@ struct MortarShape {
 };
 
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, int k,
-                                               const MortarTab<Real, N>* __restrict__ Mp,
-                                               const Real* __restrict__ mtrig, const Real* __restrict__ src,
-                                               Real* __restrict__ Em, int mask) {
+struct MortarSmem {
+  using MS = MortarShape<Real, DIM, N>;
+  MortarTab<Real, N> M;
+  Real trg[MS::FPB][2][N][2];
+  Real ev[MS::FPB][2][2][MS::NQ][MS::NC][MS::NE];  // [face][piece][own=0 / other=1][point][comp][quantity]
+  Real coef[MS::FPB][2][MS::NQ][MS::NC][MS::NE];
+};
+
+template <typename Real, int DIM, int N>
+__device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int mblock,
+                                    const MortarTab<Real, N>* __restrict__ Mp, const Real* __restrict__ mtrig,
+                                    const Real* __restrict__ src, Real* __restrict__ Em, int mask,
+                                    MortarSmem<Real, DIM, N>& sm) {
   using S = Shape<Real, DIM, N>;
   using MS = MortarShape<Real, DIM, N>;
   constexpr int NC = MS::NC, NZ = MS::NZ, NQ = MS::NQ, NE = MS::NE, FPB = MS::FPB;
-  __shared__ MortarTab<Real, N> M;
-  __shared__ Real trg[FPB][2][N][2];
-  __shared__ Real ev[FPB][2][2][NQ][NC][NE];  // [face][piece][own=0 / other=1][point][comp][quantity]
-  __shared__ Real coef[FPB][2][NQ][NC][NE];
+  MortarTab<Real, N>& M = sm.M;
+  auto& trg = sm.trg;
+  auto& ev = sm.ev;
+  auto& coef = sm.coef;
   const int nfaces = G.n_theta * G.nz;
   const int nsides = 2 * nfaces;
   {
@@ -1156,7 +1202,7 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
     const int fl = threadIdx.x / MS::LPF;
     const int r = threadIdx.x % MS::LPF;
     const int m = r % NC, sd = (r / NC) % 2, pc = r / (2 * NC);
-    const int fs = blockIdx.x * FPB + fl;  // face-side index: side * nfaces + face
+    const int fs = mblock * FPB + fl;  // face-side index: side * nfaces + face
     if (fl < FPB && fs < nsides) {
       const int side = fs / nfaces, f = fs % nfaces;
       const int ct = f % G.n_theta, cz = f / G.n_theta;
@@ -1242,7 +1288,7 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
   const Real inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
   for (int e = threadIdx.x; e < FPB * 2 * NQ; e += blockDim.x) {
     const int fl = e / (2 * NQ), pc = (e / NQ) % 2, q = e % NQ;
-    const int fs = blockIdx.x * FPB + fl;
+    const int fs = mblock * FPB + fl;
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
@@ -1293,7 +1339,7 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
   // ---- phase C: integration against the own cell's test functions
   for (int e = threadIdx.x; e < FPB * NC * N; e += blockDim.x) {
     const int fl = e / (NC * N), m = (e / N) % NC, b2 = e % N;
-    const int fs = blockIdx.x * FPB + fl;
+    const int fs = mblock * FPB + fl;
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
@@ -1356,6 +1402,35 @@ __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, i
       for (int a2 = 0; a2 < N; ++a2)
         Em[(size_t)(m * S::NPT + c * S::PLANE + b2 * N + a2) * nsides + fs] = out[c][a2];
   }
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                               const MortarTab<Real, N>* __restrict__ Mp,
+                                               const Real* __restrict__ mtrig, const Real* __restrict__ src,
+                                               Real* __restrict__ Em, int mask) {
+  __shared__ MortarSmem<Real, DIM, N> sm;
+  mortar_block<Real, DIM, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, mask, sm);
+}
+
+// Fused launch: blocks [0, nmb) integrate mortar faces, the rest integrate
+// volume cells; the two block kinds share one LDS allocation.
+template <typename Real, int DIM, int N>
+union FusedSmem {
+  VolumeSmem<Real, DIM, N> v;
+  MortarSmem<Real, DIM, N> m;
+};
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_fused(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
+                                                                    const Real* __restrict__ lin,
+                                                                    const MortarTab<Real, N>* __restrict__ Mp,
+                                                                    const Real* __restrict__ mtrig,
+                                                                    const Real* __restrict__ src,
+                                                                    Real* __restrict__ E, Real* __restrict__ Em) {
+  __shared__ FusedSmem<Real, DIM, N> sm;
+  if ((int)blockIdx.x < nmb) mortar_block<Real, DIM, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1, sm.m);
+  else volume_block<Real, DIM, N>(G, T, k, blockIdx.x - nmb, lin, src, E, sm.v);
 }
 
 // Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
@@ -1554,13 +1629,28 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   Real* E = sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32;
   Real* Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
   const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
-  timer_begin(h, TIMER_VOLUME, s);
-  hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
-  timer_end(h, TIMER_VOLUME, s);
-  int rc = hip_check(h, "volume kernel");
-  if (rc) return rc;
-  rc = do_mortar<Real, DIM, N>(h, src, Em, 1, s);
-  if (rc) return rc;
+  int rc;
+  if (h->fused) {
+    // one launch: mortar face blocks first, then volume cell blocks
+    const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
+    const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
+    const int nmb = (int)((2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
+                          MortarShape<Real, DIM, N>::FPB);
+    timer_begin(h, TIMER_VOLUME, s);
+    hipLaunchKernelGGL((k_jacobian_fused<Real, DIM, N>), dim3(blocks + nmb), dim3(64), 0, s, G, T, h->k, nmb, lin, M,
+                       mtrig, src, E, Em);
+    timer_end(h, TIMER_VOLUME, s);
+    rc = hip_check(h, "fused volume/mortar kernel");
+    if (rc) return rc;
+  } else {
+    timer_begin(h, TIMER_VOLUME, s);
+    hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
+    timer_end(h, TIMER_VOLUME, s);
+    rc = hip_check(h, "volume kernel");
+    if (rc) return rc;
+    rc = do_mortar<Real, DIM, N>(h, src, Em, 1, s);
+    if (rc) return rc;
+  }
   return do_gather<Real, DIM, N>(h, E, Em, src, dst, 0, s);
 }
 

@@ -24,8 +24,9 @@ def _dev(a, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None):
+def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=1):
     with binding.Operator(mesh) as op:
+        op.set_kernel_config(fused_launch=fused)
         op.rotate_rotor(theta, omega)
         op.set_linearization(_dev(state), None if hist is None else _dev(hist),
                              None if force is None else _dev(force))
@@ -40,7 +41,8 @@ CASES = [(2, 2), (2, 3), (2, 4), (2, 5), (3, 2), (3, 3), (3, 4)]
 
 @pytest.mark.parametrize("dim,k", CASES)
 @pytest.mark.parametrize("angle", ["random", "aligned", "near_aligned", "negative_wrapped"])
-def test_jacobian_small(dim, k, angle):
+@pytest.mark.parametrize("fused", [1, 0])
+def test_jacobian_small(dim, k, angle, fused):
     mesh = small_mesh(dim, k)
     dth = 2 * math.pi / mesh["n_theta"]
     theta = {"random": 2.345, "aligned": 2 * dth, "near_aligned": 3 * dth - 1e-14,
@@ -48,10 +50,10 @@ def test_jacobian_small(dim, k, angle):
     g = np.random.default_rng(100 * dim + k)
     n = inputs.n_dofs(mesh)
     state, x = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
-    y64, y32 = _gpu_apply(mesh, theta, 0.8, state, x)
+    y64, y32 = _gpu_apply(mesh, theta, 0.8, state, x, fused=fused)
     yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, 0.8), state, x)
     e64, e32 = relmax(y64, yo), relmax(y32, yo)
-    print(f"dim={dim} k={k} {angle}: fp64 {e64:.2e} fp32 {e32:.2e}")
+    print(f"dim={dim} k={k} {angle} fused={fused}: fp64 {e64:.2e} fp32 {e32:.2e}")
     assert e64 <= TOL64
     assert e32 <= TOL32
 
