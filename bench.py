@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--solve-restart", type=int, default=300)
     ap.add_argument("--cheb-degree", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fused", type=int, default=1, help="1: volume and mortar in one launch")
+    ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k <= 3); 0: LDS planes")
     return ap.parse_args()
 
 
@@ -89,6 +91,7 @@ def main():
     y32 = torch.empty_like(x32)
     rec = {}
     op = binding.Operator(mesh)
+    op.set_kernel_config(fused_launch=args.fused, volume_layout=args.volume_layout)
     _, t_rot = timed(lambda: op.rotate_rotor(theta, omega), sync)
     _, t_lin = timed(lambda: op.set_linearization(state), sync)
     rec["rotate_rotor_ms"] = 1e3 * t_rot

@@ -168,10 +168,16 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
 /* Kernel configuration of the Jacobian application (tuning knobs; every
  * setting computes the same product).  fused_launch = 1 (default): volume
  * cells and mortar faces are integrated in one launch whose first blocks take
- * the mortar faces; 0: two launches.  Takes effect on the next apply call.
+ * the mortar faces; 0: two launches.  volume_layout = 1 (default): in 3D
+ * with degree <= 3 a quad of four lanes owns a cell and the theta
+ * contractions exchange values between lanes without LDS; 0: nine (degree
+ * 2) or sixteen (degree 3) lanes per cell with the r and theta contractions
+ * staged through LDS (the only layout in 2D and for degree >= 4).  Takes
+ * effect on the next apply call.
  * Errors: INVALID_ARG. */
 typedef struct {
   int fused_launch;
+  int volume_layout;
 } mns_kernel_config;
 int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg);
 int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg);

@@ -58,7 +58,7 @@ class SolveReport(ctypes.Structure):
 
 
 class KernelConfig(ctypes.Structure):
-    _fields_ = [("fused_launch", ctypes.c_int)]
+    _fields_ = [("fused_launch", ctypes.c_int), ("volume_layout", ctypes.c_int)]
 
 
 class Timing(ctypes.Structure):

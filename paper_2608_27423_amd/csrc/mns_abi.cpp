@@ -239,13 +239,17 @@ int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg) {
   if (!h || !cfg) return MNS_ERR_INVALID_ARG;
   if (cfg->fused_launch != 0 && cfg->fused_launch != 1)
     return set_error(h, MNS_ERR_INVALID_ARG, "fused_launch must be 0 or 1");
+  if (cfg->volume_layout != 0 && cfg->volume_layout != 1)
+    return set_error(h, MNS_ERR_INVALID_ARG, "volume_layout must be 0 or 1");
   h->fused = cfg->fused_launch;
+  h->quad = cfg->volume_layout;
   return MNS_OK;
 }
 
 int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg) {
   if (!h || !cfg) return MNS_ERR_INVALID_ARG;
   cfg->fused_launch = h->fused;
+  cfg->volume_layout = h->quad;
   return MNS_OK;
 }
 

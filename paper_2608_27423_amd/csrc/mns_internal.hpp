@@ -33,6 +33,8 @@ struct Tab1D {
   Real V[N][N];   // V[q][a]  = L_a(x_q)
   Real D[N][N];   // D[q][a]  = L_a'(x_q)
   Real DD[N][N];  // DD[q][a] = L_a''(x_q)
+  Real CD[N][N];  // CD[q][j]  = l_j'(x_q), l_j the Lagrange basis on the Gauss points
+  Real CDD[N][N]; // CDD[q][j] = l_j''(x_q)
   Real x[N];      // Gauss points on [0,1]
   Real w[N];      // Gauss weights on [0,1]
 };
@@ -128,6 +130,8 @@ struct mns_handle {
   bool diag_valid = false;
   // kernel configuration (mns_set_kernel_config): fused volume + mortar launch
   int fused = 1;
+  // volume layout: 1 = lane quad per cell (3D, degree <= 3), 0 = LDS planes
+  int quad = 1;
   hipStream_t stream = nullptr;
   std::string err;
   // optional kernel timing (mns_enable_timing): event pairs per kernel class

@@ -35,6 +35,17 @@ namespace mns {
 #ifndef MNS_VOL_WAVES
 #define MNS_VOL_WAVES 0
 #endif
+// quad volume kernel: prefetch the next point's linearization data, fence
+// the scheduler between points, waves per SIMD requested from the compiler
+#ifndef MNS_QUAD_PREFETCH
+#define MNS_QUAD_PREFETCH 1
+#endif
+#ifndef MNS_QUAD_SCHED_BARRIER
+#define MNS_QUAD_SCHED_BARRIER 1
+#endif
+#ifndef MNS_QUAD_WAVES
+#define MNS_QUAD_WAVES 0
+#endif
 #if MNS_VOL_WAVES > 0
 #define MNS_VOL_ATTR __attribute__((amdgpu_waves_per_eu(MNS_VOL_WAVES, MNS_VOL_WAVES)))
 #else
@@ -359,6 +370,59 @@ __device__ inline void to_reference(const PtGeom<Real>& g, Real jxw, Real g0, co
   f[1] = jxw * (-g.s * Gp[0] + g.c * Gp[1]) * g.inv_rdth;  // theta
   f[2] = jxw * (g.c * Gp[0] + g.s * Gp[1]) * g.inv_dr;     // r
   if constexpr (DIM == 3) f[3] = jxw * Gp[2] * g.inv_dz;   // z
+}
+
+// Pointwise linearized operator at one volume point (Sec. 2.3 blocks):
+// reference values/derivatives of the increment (rv velocity, rp pressure)
+// and the stored linearization lv -> reference test coefficients times JxW,
+// tc[comp][{value, theta, r, z}].
+//   g_v = c_t du + (grad u) du + (grad du) a,   R' du = g_v - nu lap du + grad dp
+//   G_v = nu grad du - dp I + tau R' du (x) a + tau R (x) du,  g_q = div du,  G_q = tau R' du
+template <typename Real, int DIM>
+__device__ inline void pointwise_jacobian(const PtGeom<Real>& g, const RefVal<Real, DIM> (&rv)[DIM],
+                                          const RefVal<Real, DIM>& rp, const Real* lv, Real nu, Real ct,
+                                          Real (&tc)[DIM + 1][DIM + 1]) {
+  using LL = LinLayout<DIM>;
+  Real du[DIM], gdu[DIM][DIM], ldu[DIM], gdp[DIM], dummy;
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    du[m] = rv[m].v;
+    to_physical<Real, DIM>(g, nullptr, rv[m], gdu[m], ldu[m], true);
+  }
+  to_physical<Real, DIM>(g, nullptr, rp, gdp, dummy, false);
+  const Real dp = rp.v;
+  Real a[DIM], gu[DIM][DIM], tR[DIM];
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    a[m] = lv[LL::A + m];
+    tR[m] = lv[LL::TR + m];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) gu[m][e] = lv[LL::GU + m * DIM + e];
+  }
+  const Real tau = lv[LL::TAU];
+  Real gv[DIM], Rp[DIM], divdu = 0;
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    Real s2 = ct * du[m];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) s2 += gu[m][e] * du[e] + gdu[m][e] * a[e];
+    gv[m] = s2;
+    Rp[m] = s2 - nu * ldu[m] + gdp[m];
+    divdu += gdu[m][m];
+  }
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    Real Gm[DIM];
+    const Real tRp = tau * Rp[m];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) Gm[e] = nu * gdu[m][e] + tRp * a[e] + tR[m] * du[e];
+    Gm[m] -= dp;
+    to_reference<Real, DIM>(g, g.jxw, gv[m], Gm, tc[m]);
+  }
+  Real Gq[DIM];
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) Gq[e] = tau * Rp[e];
+  to_reference<Real, DIM>(g, g.jxw, divdu, Gq, tc[DIM]);
 }
 
 // ---------------------------------------------------------------------------
@@ -756,49 +820,8 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         for (int e = 0; e < DIM; ++e) rp.dd[e] = 0;
       }
       const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
-      Real du[DIM], gdu[DIM][DIM], ldu[DIM], gdp[DIM], dummy;
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) {
-        du[m] = rv[m].v;
-        to_physical<Real, DIM>(g, nullptr, rv[m], gdu[m], ldu[m], true);
-      }
-      to_physical<Real, DIM>(g, nullptr, rp, gdp, dummy, false);
-      const Real dp = rp.v;
-      Real a[DIM], gu[DIM][DIM], tR[DIM];
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) {
-        a[m] = lv[LL::A + m];
-        tR[m] = lv[LL::TR + m];
-#pragma unroll
-        for (int e = 0; e < DIM; ++e) gu[m][e] = lv[LL::GU + m * DIM + e];
-      }
-      const Real tau = lv[LL::TAU];
-      // g_v = c_t du + (grad u) du + (grad du) a ;  R' du = g_v - nu lap du + grad dp
-      Real gv[DIM], Rp[DIM], divdu = 0;
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) {
-        Real s2 = ct * du[m];
-#pragma unroll
-        for (int e = 0; e < DIM; ++e) s2 += gu[m][e] * du[e] + gdu[m][e] * a[e];
-        gv[m] = s2;
-        Rp[m] = s2 - nu * ldu[m] + gdp[m];
-        divdu += gdu[m][m];
-      }
-      // G_v = nu grad du - dp I + tau R' du (x) a + tau R (x) du ;  G_q = tau R' du
       Real tc[NC][S::NT];
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) {
-        Real Gm[DIM];
-        const Real tRp = tau * Rp[m];
-#pragma unroll
-        for (int e = 0; e < DIM; ++e) Gm[e] = nu * gdu[m][e] + tRp * a[e] + tR[m] * du[e];
-        Gm[m] -= dp;
-        to_reference<Real, DIM>(g, g.jxw, gv[m], Gm, tc[m]);
-      }
-      Real Gq[DIM];
-#pragma unroll
-      for (int e = 0; e < DIM; ++e) Gq[e] = tau * Rp[e];
-      to_reference<Real, DIM>(g, g.jxw, divdu, Gq, tc[DIM]);
+      pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
 #pragma unroll
       for (int m = 0; m < NC; ++m)
 #pragma unroll
@@ -871,6 +894,398 @@ __global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> 
                                                                      Real* __restrict__ E) {
   __shared__ VolumeSmem<Real, DIM, N> sm;
   volume_block<Real, DIM, N>(G, T, k, blockIdx.x, lin, src, E, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian vmult, volume part, quad layout (3D, N <= 4).  A quad of four
+// lanes owns one cell: lane t holds the theta-slice t of the cell's nodes
+// (all r and z positions).  The z and r contractions run in registers; the
+// theta contractions exchange values inside the quad with DPP quad
+// permutations, so the sum factorization needs no LDS.  With N = 3 the
+// fourth lane of a quad duplicates the last slice and stores nothing; every
+// lane runs every instruction so the cross-lane reads always see live data.
+// ---------------------------------------------------------------------------
+template <typename Real, int N>
+struct QuadShape {
+  static constexpr int CPW = 16;  // cells per wavefront
+  static constexpr int PL = N * N;
+  static constexpr int NPT = N * N * N;
+};
+
+// DPP quad permutation: lane t of a quad reads lane (t + S) mod N; lanes
+// t >= N read themselves
+template <int S, int N>
+__device__ constexpr int quad_ctrl() {
+  int c = 0;
+  for (int t = 0; t < 4; ++t) c |= ((t < N) ? (t + S) % N : t) << (2 * t);
+  return c;
+}
+
+template <int S, int N, typename Real>
+__device__ inline Real qshift(Real x) {
+  constexpr int ctrl = quad_ctrl<S, N>();
+  if constexpr (S == 0) {
+    return x;
+  } else if constexpr (sizeof(Real) == 8) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, true));
+  }
+}
+
+// the N values of x held by the quad, rotated so that xs[s] is lane t+s's
+template <int N, typename Real>
+__device__ inline void quad_rotate(Real x, Real (&xs)[N]) {
+  xs[0] = x;
+  if constexpr (N > 1) xs[1] = qshift<1, N>(x);
+  if constexpr (N > 2) xs[2] = qshift<2, N>(x);
+  if constexpr (N > 3) xs[3] = qshift<3, N>(x);
+}
+
+template <int N, typename Real>
+__device__ inline Real quad_dot(const Real (&c)[N], const Real (&xs)[N]) {
+  Real v = c[0] * xs[0];
+#pragma unroll
+  for (int s = 1; s < N; ++s) v += c[s] * xs[s];
+  return v;
+}
+
+// sum over the quad of per-destination partials: lane t receives
+// sum_s p[s] evaluated at lane t+s
+template <int N, typename Real>
+__device__ inline Real quad_reduce(const Real (&p)[N]) {
+  Real v = p[0];
+  if constexpr (N > 1) v += qshift<1, N>(p[1]);
+  if constexpr (N > 2) v += qshift<2, N>(p[2]);
+  if constexpr (N > 3) v += qshift<3, N>(p[3]);
+  return v;
+}
+
+// value v[t] of a lane-indexed table whose entries are wave-uniform
+template <int N, typename Real>
+__device__ inline Real lane_select(int t, const Real (&v)[N]) {
+  Real r = v[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) r = (t == i) ? v[i] : r;
+  return r;
+}
+
+template <typename Real>
+__device__ inline void load_node4(const Real* p, Real (&w)[4]) {
+  if constexpr (sizeof(Real) == 8) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 a = q[0], b = q[1];
+    w[0] = a.x;
+    w[1] = a.y;
+    w[2] = b.x;
+    w[3] = b.y;
+  } else {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    w[0] = a.x;
+    w[1] = a.y;
+    w[2] = a.z;
+    w[3] = a.w;
+  }
+}
+
+template <typename Real, int NV>
+__device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
+  if constexpr (sizeof(Real) == 8) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < NV / 2; ++i) {
+      const double2 a = q[i];
+      w[2 * i] = a.x;
+      w[2 * i + 1] = a.y;
+    }
+  } else {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < NV / 4; ++i) {
+      const float4 a = q[i];
+      w[4 * i] = a.x;
+      w[4 * i + 1] = a.y;
+      w[4 * i + 2] = a.z;
+      w[4 * i + 3] = a.w;
+    }
+  }
+}
+
+// The quad kernel works in the collocation basis of the Gauss points: the
+// nodal values are first interpolated to the cell's Gauss points (z, r in
+// registers, theta across the quad); first and second reference derivatives
+// at every point then follow from the Gauss-point derivative matrices CD and
+// CDD along each direction.  The transposed steps run in reverse: the test
+// coefficients of every point are accumulated in the collocation basis (the
+// transposed CD applied along r, z and, across the quad, theta) and finally
+// interpolated back to the nodes.
+template <typename Real, int N>
+__device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
+                                   const Real* __restrict__ lin, const Real* __restrict__ src,
+                                   Real* __restrict__ E) {
+  constexpr int DIM = 3, NC = 4, NT = 4;
+  using Q = QuadShape<Real, N>;
+  using LL = LinLayout<DIM>;
+  static_assert(N <= 4, "quad layout holds at most four theta slices");
+  const int lane = threadIdx.x & 63;
+  const int t = lane & 3;
+  const long long craw = (long long)vblock * Q::CPW + (lane >> 2);
+  const bool active = t < N && craw < G.ncells;
+  const int cell = (int)(craw < G.ncells ? craw : G.ncells - 1);
+  const int ts = t < N ? t : N - 1;  // theta slice held by this lane
+  const CellId C = decode_cell(G, cell);
+
+  // nodal values of the slice, constrained entries read as zero
+  Real U[NC][N][N];  // [comp][r][z]
+  {
+    int it = k * C.ct + ts;
+    it = it >= G.ntn ? it - G.ntn : it;
+    const int nrn = pick(C.dom, G.nrn);
+    const long long nbase = (C.dom ? G.node_off1 : 0) + it + (long long)G.ntn * (k * C.cr + (long long)nrn * k * C.cz);
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const int ir = k * C.cr + b, iz = k * C.cz + c;
+        const long long node = nbase + (long long)G.ntn * (b + (long long)nrn * c);
+        Real w[4];
+        load_node4<Real>(src + node * NC, w);
+        const bool outer = (C.dom == 0) ? (ir == 0) : (ir == G.nrn[1] - 1);
+        const bool vf = outer | (iz == 0) | (iz == G.nzn - 1);
+        const bool pf = (C.dom == 1) & (it == 0) & (ir == G.nrn[1] - 1) & (iz == 0);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) U[m][b][c] = vf ? Real(0) : w[m];
+        U[DIM][b][c] = pf ? Real(0) : w[DIM];
+      }
+  }
+
+  // interpolation to the Gauss points: z, r in registers, theta across the quad
+  {
+    Real cV[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+      Real a[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = T.V[i][(i + s) % N];
+      cV[s] = lane_select<N>(ts, a);
+    }
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      Real A[N][N];
+#pragma unroll
+      for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          Real v = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) v += T.V[q][c] * U[m][b][c];
+          A[b][q] = v;
+        }
+#pragma unroll
+      for (int qj = 0; qj < N; ++qj)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          Real v = 0;
+#pragma unroll
+          for (int b = 0; b < N; ++b) v += T.V[qj][b] * A[b][q];
+          Real xs[N];
+          quad_rotate<N>(v, xs);
+          U[m][qj][q] = quad_dot<N>(cV, xs);
+        }
+#if MNS_QUAD_SCHED_BARRIER
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+    }
+  }
+
+  // per-lane theta coefficients of the collocation derivatives: rows
+  // cX[s] = X[ts][ts+s], columns sX[s] = X[ts][ts-s] (indices mod N)
+  Real cD[N], cDD[N], sD[N];
+#pragma unroll
+  for (int s = 0; s < N; ++s) {
+    Real a[N], b[N], c[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      a[i] = T.CD[i][(i + s) % N];
+      b[i] = T.CDD[i][(i + s) % N];
+      c[i] = T.CD[i][(i - s + N) % N];
+    }
+    cD[s] = lane_select<N>(ts, a);
+    cDD[s] = lane_select<N>(ts, b);
+    sD[s] = lane_select<N>(ts, c);
+  }
+
+  // geometry of the lane's theta point
+  PtGeom<Real> g;
+  {
+    const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + ts) * 2;
+    g.c = tr[0];
+    g.s = tr[1];
+  }
+  const Real dr = pick(C.dom, G.dr), r0 = pick(C.dom, G.r0);
+  g.inv_dr = Real(1) / dr;
+  g.inv_dz = Real(1) / G.dz;
+  const Real wt = lane_select<N>(ts, T.w) * G.dth * dr * G.dz;
+  const Real nu = G.nu, ct = G.ct;
+  const Real inv_dth = Real(1) / G.dth;
+  Real rq[N], inv_rq[N];
+#pragma unroll
+  for (int qj = 0; qj < N; ++qj) {
+    rq[qj] = r0 + dr * (Real(C.cr) + T.x[qj]);
+    inv_rq[qj] = Real(1) / rq[qj];
+  }
+
+  Real F[NC][N][N];  // test coefficients in the collocation basis
+#pragma unroll
+  for (int m = 0; m < NC; ++m)
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+      for (int c = 0; c < N; ++c) F[m][b][c] = 0;
+
+  const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
+  Real lv[LL::SIZE];
+#if MNS_QUAD_PREFETCH
+  load_lin<Real, LL::SIZE>(lbase, lv);
+#endif
+
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+#pragma unroll
+    for (int qj = 0; qj < N; ++qj) {
+#if MNS_QUAD_PREFETCH
+      Real ln[LL::SIZE];
+      const bool more = qj + 1 < N || q + 1 < N;
+      if (more)
+        load_lin<Real, LL::SIZE>(lbase + (qj + 1 < N ? q * Q::PL + (qj + 1) * N : (q + 1) * Q::PL) * LL::SIZE, ln);
+#else
+      load_lin<Real, LL::SIZE>(lbase + (q * Q::PL + qj * N) * LL::SIZE, lv);
+#endif
+      RefVal<Real, DIM> rv[DIM], rp;
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const bool vel = m < DIM;
+        RefVal<Real, DIM>& R = vel ? rv[m] : rp;
+        const Real v = U[m][qj][q];
+        Real d1 = T.CD[qj][0] * U[m][0][q], e1 = T.CD[q][0] * U[m][qj][0];
+        Real d2 = vel ? T.CDD[qj][0] * U[m][0][q] : Real(0), e2 = vel ? T.CDD[q][0] * U[m][qj][0] : Real(0);
+#pragma unroll
+        for (int j = 1; j < N; ++j) {
+          d1 += T.CD[qj][j] * U[m][j][q];
+          e1 += T.CD[q][j] * U[m][qj][j];
+          if (vel) {
+            d2 += T.CDD[qj][j] * U[m][j][q];
+            e2 += T.CDD[q][j] * U[m][qj][j];
+          }
+        }
+        Real xs[N];
+        quad_rotate<N>(v, xs);
+        R.v = v;
+        R.d[0] = quad_dot<N>(cD, xs);
+        R.d[1] = d1;
+        R.d[2] = e1;
+        R.dd[0] = vel ? quad_dot<N>(cDD, xs) : Real(0);
+        R.dd[1] = d2;
+        R.dd[2] = e2;
+      }
+      g.r = rq[qj];
+      g.inv_r = inv_rq[qj];
+      g.inv_rdth = g.inv_r * inv_dth;
+      g.jxw = wt * T.w[qj] * T.w[q] * g.r;
+      Real tc[NC][NT];
+      pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        Real p[N];
+#pragma unroll
+        for (int s = 0; s < N; ++s) p[s] = sD[s] * tc[m][1];
+        F[m][qj][q] += tc[m][0] + quad_reduce<N>(p);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          F[m][j][q] += T.CD[qj][j] * tc[m][2];
+          F[m][qj][j] += T.CD[q][j] * tc[m][3];
+        }
+      }
+#if MNS_QUAD_PREFETCH
+      if (more)
+#pragma unroll
+        for (int j = 0; j < LL::SIZE; ++j) lv[j] = ln[j];
+#endif
+#if MNS_QUAD_SCHED_BARRIER
+      // pin the accumulators at the end of every point (otherwise the
+      // additions are deferred and every product stays live), and keep the
+      // scheduler from interleaving points
+#pragma unroll
+      for (int m = 0; m < NC; ++m)
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+          for (int c = 0; c < N; ++c) asm volatile("" : "+v"(F[m][b][c]));
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+    }
+
+  // back to the nodes: transposed interpolation across the quad (theta),
+  // then along r and z in registers
+  Real sV[N];
+#pragma unroll
+  for (int s = 0; s < N; ++s) {
+    Real a[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] = T.V[i][(i - s + N) % N];
+    sV[s] = lane_select<N>(ts, a);
+  }
+  Real* Ec = E + cell;
+#pragma unroll
+  for (int m = 0; m < NC; ++m) {
+    Real X[N][N];
+#pragma unroll
+    for (int qj = 0; qj < N; ++qj)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        Real p[N];
+#pragma unroll
+        for (int s = 0; s < N; ++s) p[s] = sV[s] * F[m][qj][q];
+        X[qj][q] = quad_reduce<N>(p);
+      }
+    Real Y[N][N];
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        Real v = 0;
+#pragma unroll
+        for (int qj = 0; qj < N; ++qj) v += T.V[qj][b] * X[qj][q];
+        Y[b][q] = v;
+      }
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        Real v = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) v += T.V[q][c] * Y[b][q];
+        if (active) Ec[(size_t)(m * Q::NPT + c * Q::PL + b * N + ts) * G.ncells] = v;
+      }
+#if MNS_QUAD_SCHED_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+  }
+}
+
+#if MNS_QUAD_WAVES
+#define MNS_QUAD_ATTR __attribute__((amdgpu_waves_per_eu(MNS_QUAD_WAVES, MNS_QUAD_WAVES)))
+#else
+#define MNS_QUAD_ATTR
+#endif
+
+template <typename Real, int N>
+__global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_volume_quad(Geom<Real> G, Tab1D<Real, N> T, int k,
+                                                             const Real* __restrict__ lin,
+                                                             const Real* __restrict__ src, Real* __restrict__ E) {
+  volume_quad<Real, N>(G, T, k, blockIdx.x, lin, src, E);
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,6 +1848,19 @@ __global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_fused(Geom<Real> G
   else volume_block<Real, DIM, N>(G, T, k, blockIdx.x - nmb, lin, src, E, sm.v);
 }
 
+// fused launch with the quad volume layout (3D)
+template <typename Real, int N>
+__global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_fused_quad(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
+                                                            const Real* __restrict__ lin,
+                                                            const MortarTab<Real, N>* __restrict__ Mp,
+                                                            const Real* __restrict__ mtrig,
+                                                            const Real* __restrict__ src, Real* __restrict__ E,
+                                                            Real* __restrict__ Em) {
+  __shared__ MortarSmem<Real, 3, N> sm;
+  if ((int)blockIdx.x < nmb) mortar_block<Real, 3, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1, sm);
+  else volume_quad<Real, N>(G, T, k, blockIdx.x - nmb, lin, src, E);
+}
+
 // Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
 // i (other side zero) gives, tested with the same basis function,
 // nu tau phi^2 - nu phi (grad phi . n) for velocity rows and 0 for pressure rows.
@@ -1513,6 +1941,11 @@ static Tab1D<Real, N> make_tab(const mns_handle* h) {
       T.V[q][a] = (Real)L[a];
       T.D[q][a] = (Real)dL[a];
       T.DD[q][a] = (Real)d2L[a];
+    }
+    lagrange_1d(h->gx, h->gx[q], L.data(), dL.data(), d2L.data());
+    for (int j = 0; j < N; ++j) {
+      T.CD[q][j] = (Real)dL[j];
+      T.CDD[q][j] = (Real)d2L[j];
     }
     T.x[q] = (Real)h->gx[q];
     T.w[q] = (Real)h->gw[q];
@@ -1628,7 +2061,10 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
   Real* E = sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32;
   Real* Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
-  const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
+  constexpr bool kQuad = DIM == 3 && N == 3;
+  const bool quad = kQuad && h->quad;
+  const int cpw = quad ? QuadShape<Real, N>::CPW : S::CPW;
+  const unsigned blocks = (unsigned)((G.ncells + cpw - 1) / cpw);
   int rc;
   if (h->fused) {
     // one launch: mortar face blocks first, then volume cell blocks
@@ -1637,14 +2073,25 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
     const int nmb = (int)((2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                           MortarShape<Real, DIM, N>::FPB);
     timer_begin(h, TIMER_VOLUME, s);
-    hipLaunchKernelGGL((k_jacobian_fused<Real, DIM, N>), dim3(blocks + nmb), dim3(64), 0, s, G, T, h->k, nmb, lin, M,
-                       mtrig, src, E, Em);
+    if constexpr (kQuad) {
+      if (quad)
+        hipLaunchKernelGGL((k_jacobian_fused_quad<Real, N>), dim3(blocks + nmb), dim3(64), 0, s, G, T, h->k, nmb, lin,
+                           M, mtrig, src, E, Em);
+    }
+    if (!quad)
+      hipLaunchKernelGGL((k_jacobian_fused<Real, DIM, N>), dim3(blocks + nmb), dim3(64), 0, s, G, T, h->k, nmb, lin,
+                         M, mtrig, src, E, Em);
     timer_end(h, TIMER_VOLUME, s);
     rc = hip_check(h, "fused volume/mortar kernel");
     if (rc) return rc;
   } else {
     timer_begin(h, TIMER_VOLUME, s);
-    hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
+    if constexpr (kQuad) {
+      if (quad)
+        hipLaunchKernelGGL((k_jacobian_volume_quad<Real, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
+    }
+    if (!quad)
+      hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
     timer_end(h, TIMER_VOLUME, s);
     rc = hip_check(h, "volume kernel");
     if (rc) return rc;

@@ -24,9 +24,9 @@ def _dev(a, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=1):
+def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=1, layout=1):
     with binding.Operator(mesh) as op:
-        op.set_kernel_config(fused_launch=fused)
+        op.set_kernel_config(fused_launch=fused, volume_layout=layout)
         op.rotate_rotor(theta, omega)
         op.set_linearization(_dev(state), None if hist is None else _dev(hist),
                              None if force is None else _dev(force))
@@ -37,12 +37,14 @@ def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=1):
 
 
 CASES = [(2, 2), (2, 3), (2, 4), (2, 5), (3, 2), (3, 3), (3, 4)]
+# kernel configurations: (fused launch, volume layout)
+KCONF = [(1, 1), (0, 1), (1, 0), (0, 0)]
 
 
 @pytest.mark.parametrize("dim,k", CASES)
 @pytest.mark.parametrize("angle", ["random", "aligned", "near_aligned", "negative_wrapped"])
-@pytest.mark.parametrize("fused", [1, 0])
-def test_jacobian_small(dim, k, angle, fused):
+@pytest.mark.parametrize("fused,layout", KCONF)
+def test_jacobian_small(dim, k, angle, fused, layout):
     mesh = small_mesh(dim, k)
     dth = 2 * math.pi / mesh["n_theta"]
     theta = {"random": 2.345, "aligned": 2 * dth, "near_aligned": 3 * dth - 1e-14,
@@ -50,10 +52,10 @@ def test_jacobian_small(dim, k, angle, fused):
     g = np.random.default_rng(100 * dim + k)
     n = inputs.n_dofs(mesh)
     state, x = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
-    y64, y32 = _gpu_apply(mesh, theta, 0.8, state, x, fused=fused)
+    y64, y32 = _gpu_apply(mesh, theta, 0.8, state, x, fused=fused, layout=layout)
     yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, 0.8), state, x)
     e64, e32 = relmax(y64, yo), relmax(y32, yo)
-    print(f"dim={dim} k={k} {angle} fused={fused}: fp64 {e64:.2e} fp32 {e32:.2e}")
+    print(f"dim={dim} k={k} {angle} fused={fused} layout={layout}: fp64 {e64:.2e} fp32 {e32:.2e}")
     assert e64 <= TOL64
     assert e32 <= TOL32
 
@@ -126,14 +128,15 @@ def test_workload_2d_q2_full():
     assert relmax(y32, yo) <= TOL32
 
 
-def test_workload_3d_q2_full():
+@pytest.mark.parametrize("layout", [1, 0])
+def test_workload_3d_q2_full(layout):
     name = "annulus3d_q2_64x8x32"
     mesh = inputs.mesh(name)
     theta = inputs.rotor_angle(name)
     state, x = inputs.state_for(name), inputs.vector_for(name)
-    y64, y32 = _gpu_apply(mesh, theta, mesh["omega"], state, x)
+    y64, y32 = _gpu_apply(mesh, theta, mesh["omega"], state, x, layout=layout)
     yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, mesh["omega"]), state, x)
-    print(f"{name}: fp64 {relmax(y64, yo):.2e} fp32 {relmax(y32, yo):.2e}")
+    print(f"{name} layout={layout}: fp64 {relmax(y64, yo):.2e} fp32 {relmax(y32, yo):.2e}")
     assert relmax(y64, yo) <= TOL64
     assert relmax(y32, yo) <= TOL32
 
