@@ -55,6 +55,42 @@ def algorithmic_bytes_volume(mesh, n_dofs, real_bytes):
     return (2 * n_dofs + lin) * real_bytes, cells
 
 
+def dominant_kernel(mesh, fused, layout, real="double"):
+    """Name of the launch that the volume timer brackets."""
+    dim, k = mesh["dim"], mesh["degree"]
+    quad = layout == 1 and dim == 3 and k == 2
+    if quad:
+        return f"mns::k_jacobian_{'fused' if fused else 'volume'}_quad<{real}, {k + 1}>"
+    return f"mns::k_jacobian_{'fused' if fused else 'volume'}<{real}, {dim}, {k + 1}>"
+
+
+def kernel_source_digest():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2608_27423_amd", "csrc", "mns_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy),
+    or None when there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#", "|")):
+            key, val = line.split(":", 1)
+            rec[key.strip()] = val.strip()
+    if rec.get("kernel_source_sha256") != kernel_source_digest() or rec.get("kernel") != kernel:
+        return None
+    try:
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def timed(fn, sync):
     sync()
     t0 = time.perf_counter()
@@ -98,24 +134,43 @@ def main():
     rec["set_linearization_ms"] = 1e3 * t_lin
 
     def run(src, dst, steps, warmup):
+        """Timed region: `steps` back-to-back applications bracketed by device
+        synchronization (no events between the kernels).  A second pass of the
+        same length records HIP events around every kernel class on the launch
+        stream, for the per-kernel durations."""
         for _ in range(warmup):
             op.apply_jacobian(src, dst)
         sync()
-        op.enable_timing(steps)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        sync()
-        e0.record()
+        t0 = time.perf_counter()
         for _ in range(steps):
             op.apply_jacobian(src, dst)
-        e1.record()
         sync()
-        ms = e0.elapsed_time(e1) / steps
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        op.enable_timing(steps)
+        for _ in range(steps):
+            op.apply_jacobian(src, dst)
+        sync()
         t = op.read_timing()
         op.enable_timing(0)
         return ms, t
 
     ms64, t64 = run(x64, y64, args.steps, args.warmup)
     ms32, t32 = run(x32, y32, args.steps, args.warmup)
+
+    def distribution(src, dst, calls):
+        """Per-call FP64 vmult times (events around each call): median, p10, p90."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        sync()
+        for a, b in ev:
+            a.record()
+            op.apply_jacobian(src, dst)
+            b.record()
+        sync()
+        t = sorted(a.elapsed_time(b) for a, b in ev)
+        return {"median_ms": t[len(t) // 2], "p10_ms": t[len(t) // 10], "p90_ms": t[(9 * len(t)) // 10],
+                "calls": calls}
+
+    rec["fp64_per_call"] = distribution(x64, y64, max(args.steps, 20))
     sync()
     err32 = float((y32.double() - y64).abs().max() / y64.abs().max())
     _, t_diag = timed(lambda: op.compute_diagonal(torch.float64), sync)
@@ -126,6 +181,9 @@ def main():
     bytes64, cells = algorithmic_bytes_volume(mesh, n, 8)
     bytes32, _ = algorithmic_bytes_volume(mesh, n, 4)
     achieved = bytes64 / (vol_ms64 * 1e-3) / 1e9
+    kname = dominant_kernel(mesh, args.fused, args.volume_layout)
+    tb = measured_traffic(name, kname)
+    traffic = None if tb is None else tb / (vol_ms64 * 1e-3) / 1e9
     rec["fp64"] = {"ms_per_vmult": ms64, "dofs_per_s": n / (ms64 * 1e-3), "volume_kernel_ms": vol_ms64,
                    "mortar_kernel_ms": t64["ms_mortar"] / max(1, t64["n_mortar"]),
                    "other_kernels_ms": t64["ms_other"] / max(1, t64["n_volume"])}
@@ -195,8 +253,8 @@ def main():
         "config": {"workload": name, "dofs": n, "cells": cells, "degree": mesh["degree"], "dim": mesh["dim"],
                    "rotor_angle": theta, "nu": mesh["nu"], "step": "one FP64 Jacobian application"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_jacobian_volume<double,3,3>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "kernel_ms": vol_ms64,
                      "algorithmic_bytes_per_launch": bytes64},
         "cpu_baseline": cpu,
         "hot_path": rec,

@@ -966,9 +966,11 @@ __device__ inline Real quad_reduce(const Real (&p)[N]) {
 // value v[t] of a lane-indexed table whose entries are wave-uniform
 template <int N, typename Real>
 __device__ inline Real lane_select(int t, const Real (&v)[N]) {
-  Real r = v[0];
+  // written as a masked sum: a chain of selects is turned into a table in
+  // private (scratch) memory indexed by the lane
+  Real r = Real(0);
 #pragma unroll
-  for (int i = 1; i < N; ++i) r = (t == i) ? v[i] : r;
+  for (int i = 0; i < N; ++i) r = __builtin_fma(t == i ? Real(1) : Real(0), v[i], r);
   return r;
 }
 
@@ -1623,14 +1625,18 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
       const int ct = f % G.n_theta, cz = f / G.n_theta;
       Piece<Real, DIM, N> P[2];
       mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
-      const int seg = P[pc].seg;
-      const CellId C = sd == 0 ? CellId{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz} : P[pc].other;
+      // lane-dependent piece picked by selects (an indexed access would put
+      // the two pieces in private memory)
+      const int seg = pc ? P[1].seg : P[0].seg;
+      const int jface = pc ? P[1].jface : P[0].jface;
+      const CellId other = pc ? P[1].other : P[0].other;
+      const CellId C = sd == 0 ? CellId{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz} : other;
       const int cside = sd == 0 ? side : 1 - side;
       if (sd == 0 && m == 0) {
         // point angles of this piece (one lane per face and piece)
         for (int q = 0; q < N; ++q)
           for (int c2 = 0; c2 < 2; ++c2)
-            trg[fl][pc][q][c2] = mtrig[(((size_t)P[pc].jface * 2 + seg) * N + q) * 2 + c2];
+            trg[fl][pc][q][c2] = mtrig[(((size_t)jface * 2 + seg) * N + q) * 2 + c2];
       }
       // r reduction at the interface: F0 = face value, F1 = normal derivative
       Real F0[NZ][N], F1[NZ][N];
@@ -1709,7 +1715,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     Piece<Real, DIM, N> P[2];
     mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
     const int qt = q % N, qz = q / N;
-    const int seg = P[pc].seg;
+    const int seg = pc ? P[1].seg : P[0].seg;
     const Real jxw = M.seg_active[seg] ? M.jxw[seg][qt][(DIM == 3) ? qz : 0] : Real(0);
     const Real cth = trg[fl][pc][qt][0], sth = trg[fl][pc][qt][1];
     Real n[DIM] = {};
@@ -1766,7 +1772,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
 #pragma unroll
       for (int a2 = 0; a2 < N; ++a2) out[c][a2] = 0;
     for (int pc = 0; pc < 2; ++pc) {
-      const int seg = P[pc].seg;
+      const int seg = pc ? P[1].seg : P[0].seg;
       // z reverse: H0 (value + z-derivative terms), Ht, Hr at (c, qt)
       Real H0[NZ][N], Ht[NZ][N], Hr[NZ][N];
 #pragma unroll
@@ -1885,7 +1891,7 @@ __global__ __launch_bounds__(64) void k_mortar_diag(Geom<Real> G, Tab1D<Real, N>
     if (fv == Real(0) && fd == Real(0)) continue;
     Real acc[DIM] = {};
     for (int pc = 0; pc < 2; ++pc) {
-      const int seg = P[pc].seg;
+      const int seg = pc ? P[1].seg : P[0].seg;
       if (!M.seg_active[seg]) continue;
       for (int qz = 0; qz < NZ; ++qz)
         for (int qt = 0; qt < N; ++qt) {
