@@ -326,6 +326,26 @@ struct PtGeom {
   Real inv_rdth;   // 1 / (r dtheta)
   Real inv_dz;
   Real jxw;
+  // products of the above used by the transformations below
+  Real a1, a2, b1, b2;          // c / dr, s / dr, c / (r dtheta), s / (r dtheta)
+  Real l_rr, l_r, l_tt, l_zz;   // Laplacian weights of the reference derivatives
+  Real jr1, jr2, jt1, jt2, jz;  // JxW times a1, a2, b1, b2, 1 / dz
+
+  __device__ inline void complete() {
+    a1 = c * inv_dr;
+    a2 = s * inv_dr;
+    b1 = c * inv_rdth;
+    b2 = s * inv_rdth;
+    l_rr = inv_dr * inv_dr;
+    l_r = inv_dr * inv_r;
+    l_tt = inv_rdth * inv_rdth;
+    l_zz = inv_dz * inv_dz;
+    jr1 = jxw * a1;
+    jr2 = jxw * a2;
+    jt1 = jxw * b1;
+    jt2 = jxw * b2;
+    jz = jxw * inv_dz;
+  }
 };
 
 template <typename Real, int DIM, int N>
@@ -344,6 +364,7 @@ __device__ inline PtGeom<Real> point_geom(const Geom<Real>& G, const Tab1D<Real,
   Real w = T.w[tqi] * T.w[tqj] * g.r * G.dth * dr;
   if constexpr (DIM == 3) w *= T.w[q] * G.dz;
   g.jxw = w;
+  g.complete();
   return g;
 }
 
@@ -351,25 +372,25 @@ __device__ inline PtGeom<Real> point_geom(const Geom<Real>& G, const Tab1D<Real,
 template <typename Real, int DIM>
 __device__ inline void to_physical(const PtGeom<Real>& g, const Real* dz_scale, const RefVal<Real, DIM>& rv,
                                    Real (&grad)[DIM], Real& lap, bool want_lap) {
-  const Real dr = rv.d[1] * g.inv_dr;    // d/dr
-  const Real dt = rv.d[0] * g.inv_rdth;  // (1/r) d/dtheta
-  grad[0] = g.c * dr - g.s * dt;
-  grad[1] = g.s * dr + g.c * dt;
+  // d/dr = d1 / dr, (1/r) d/dtheta = d0 / (r dtheta); x = r cos, y = r sin
+  grad[0] = g.a1 * rv.d[1] - g.b2 * rv.d[0];
+  grad[1] = g.a2 * rv.d[1] + g.b1 * rv.d[0];
   if constexpr (DIM == 3) grad[2] = rv.d[2] * g.inv_dz;
   if (want_lap) {
-    lap = rv.dd[1] * g.inv_dr * g.inv_dr + dr * g.inv_r + rv.dd[0] * g.inv_rdth * g.inv_rdth;
-    if constexpr (DIM == 3) lap += rv.dd[2] * g.inv_dz * g.inv_dz;
+    // u_rr + u_r / r + u_tt / r^2 (+ u_zz)
+    lap = rv.dd[1] * g.l_rr + rv.d[1] * g.l_r + rv.dd[0] * g.l_tt;
+    if constexpr (DIM == 3) lap += rv.dd[2] * g.l_zz;
   }
   (void)dz_scale;
 }
 
 // physical test coefficients (value g0, gradient G) -> reference ones times JxW
 template <typename Real, int DIM>
-__device__ inline void to_reference(const PtGeom<Real>& g, Real jxw, Real g0, const Real (&Gp)[DIM], Real* f) {
-  f[0] = jxw * g0;
-  f[1] = jxw * (-g.s * Gp[0] + g.c * Gp[1]) * g.inv_rdth;  // theta
-  f[2] = jxw * (g.c * Gp[0] + g.s * Gp[1]) * g.inv_dr;     // r
-  if constexpr (DIM == 3) f[3] = jxw * Gp[2] * g.inv_dz;   // z
+__device__ inline void to_reference(const PtGeom<Real>& g, Real g0, const Real (&Gp)[DIM], Real* f) {
+  f[0] = g.jxw * g0;
+  f[1] = g.jt1 * Gp[1] - g.jt2 * Gp[0];                  // theta
+  f[2] = g.jr1 * Gp[0] + g.jr2 * Gp[1];                  // r
+  if constexpr (DIM == 3) f[3] = g.jz * Gp[2];           // z
 }
 
 // Pointwise linearized operator at one volume point (Sec. 2.3 blocks):
@@ -417,12 +438,12 @@ __device__ inline void pointwise_jacobian(const PtGeom<Real>& g, const RefVal<Re
 #pragma unroll
     for (int e = 0; e < DIM; ++e) Gm[e] = nu * gdu[m][e] + tRp * a[e] + tR[m] * du[e];
     Gm[m] -= dp;
-    to_reference<Real, DIM>(g, g.jxw, gv[m], Gm, tc[m]);
+    to_reference<Real, DIM>(g, gv[m], Gm, tc[m]);
   }
   Real Gq[DIM];
 #pragma unroll
   for (int e = 0; e < DIM; ++e) Gq[e] = tau * Rp[e];
-  to_reference<Real, DIM>(g, g.jxw, divdu, Gq, tc[DIM]);
+  to_reference<Real, DIM>(g, divdu, Gq, tc[DIM]);
 }
 
 // ---------------------------------------------------------------------------
@@ -952,17 +973,6 @@ __device__ inline Real quad_dot(const Real (&c)[N], const Real (&xs)[N]) {
   return v;
 }
 
-// sum over the quad of per-destination partials: lane t receives
-// sum_s p[s] evaluated at lane t+s
-template <int N, typename Real>
-__device__ inline Real quad_reduce(const Real (&p)[N]) {
-  Real v = p[0];
-  if constexpr (N > 1) v += qshift<1, N>(p[1]);
-  if constexpr (N > 2) v += qshift<2, N>(p[2]);
-  if constexpr (N > 3) v += qshift<3, N>(p[3]);
-  return v;
-}
-
 // value v[t] of a lane-indexed table whose entries are wave-uniform
 template <int N, typename Real>
 __device__ inline Real lane_select(int t, const Real (&v)[N]) {
@@ -1102,9 +1112,11 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
     }
   }
 
-  // per-lane theta coefficients of the collocation derivatives: rows
-  // cX[s] = X[ts][ts+s], columns sX[s] = X[ts][ts-s] (indices mod N)
-  Real cD[N], cDD[N], sD[N];
+  // per-lane theta coefficients of the collocation derivatives, applied to
+  // the quad-rotated values (xs[s] from lane ts+s): rows cX[s] = X[ts][ts+s]
+  // and, for the transposed contraction, columns tX[s] = X[ts+s][ts]
+  // (indices mod N)
+  Real cD[N], cDD[N], tD[N];
 #pragma unroll
   for (int s = 0; s < N; ++s) {
     Real a[N], b[N], c[N];
@@ -1112,11 +1124,11 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
     for (int i = 0; i < N; ++i) {
       a[i] = T.CD[i][(i + s) % N];
       b[i] = T.CDD[i][(i + s) % N];
-      c[i] = T.CD[i][(i - s + N) % N];
+      c[i] = T.CD[(i + s) % N][i];
     }
     cD[s] = lane_select<N>(ts, a);
     cDD[s] = lane_select<N>(ts, b);
-    sD[s] = lane_select<N>(ts, c);
+    tD[s] = lane_select<N>(ts, c);
   }
 
   // geometry of the lane's theta point
@@ -1147,24 +1159,29 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
 #pragma unroll
       for (int c = 0; c < N; ++c) F[m][b][c] = 0;
 
+  // linearization data of the lane's points, loaded MNS_QUAD_PREFETCH points
+  // ahead through a register ring (points in (q, qj) order)
+  constexpr int PF = MNS_QUAD_PREFETCH > 0 ? MNS_QUAD_PREFETCH : 1;
   const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
+  Real ring[PF][LL::SIZE];
+#pragma unroll
+  for (int i = 0; i < PF; ++i)
+    if (i < Q::PL) load_lin<Real, LL::SIZE>(lbase + ((i / N) * Q::PL + (i % N) * N) * LL::SIZE, ring[i]);
   Real lv[LL::SIZE];
-#if MNS_QUAD_PREFETCH
-  load_lin<Real, LL::SIZE>(lbase, lv);
-#endif
 
 #pragma unroll
   for (int q = 0; q < N; ++q)
 #pragma unroll
     for (int qj = 0; qj < N; ++qj) {
-#if MNS_QUAD_PREFETCH
-      Real ln[LL::SIZE];
-      const bool more = qj + 1 < N || q + 1 < N;
-      if (more)
-        load_lin<Real, LL::SIZE>(lbase + (qj + 1 < N ? q * Q::PL + (qj + 1) * N : (q + 1) * Q::PL) * LL::SIZE, ln);
-#else
-      load_lin<Real, LL::SIZE>(lbase + (q * Q::PL + qj * N) * LL::SIZE, lv);
-#endif
+      const int pt = q * N + qj;
+#pragma unroll
+      for (int j = 0; j < LL::SIZE; ++j) lv[j] = ring[0][j];
+#pragma unroll
+      for (int i = 0; i + 1 < PF; ++i)
+#pragma unroll
+        for (int j = 0; j < LL::SIZE; ++j) ring[i][j] = ring[i + 1][j];
+      if (pt + PF < Q::PL)
+        load_lin<Real, LL::SIZE>(lbase + (((pt + PF) / N) * Q::PL + ((pt + PF) % N) * N) * LL::SIZE, ring[PF - 1]);
       RefVal<Real, DIM> rv[DIM], rp;
 #pragma unroll
       for (int m = 0; m < NC; ++m) {
@@ -1196,25 +1213,23 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
       g.inv_r = inv_rq[qj];
       g.inv_rdth = g.inv_r * inv_dth;
       g.jxw = wt * T.w[qj] * T.w[q] * g.r;
+      g.complete();
       Real tc[NC][NT];
       pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
 #pragma unroll
       for (int m = 0; m < NC; ++m) {
-        Real p[N];
+        Real xs[N];
+        quad_rotate<N>(tc[m][1], xs);
+        Real f = F[m][qj][q] + tc[m][0];
 #pragma unroll
-        for (int s = 0; s < N; ++s) p[s] = sD[s] * tc[m][1];
-        F[m][qj][q] += tc[m][0] + quad_reduce<N>(p);
+        for (int s = 0; s < N; ++s) f += tD[s] * xs[s];
+        F[m][qj][q] = f;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           F[m][j][q] += T.CD[qj][j] * tc[m][2];
           F[m][qj][j] += T.CD[q][j] * tc[m][3];
         }
       }
-#if MNS_QUAD_PREFETCH
-      if (more)
-#pragma unroll
-        for (int j = 0; j < LL::SIZE; ++j) lv[j] = ln[j];
-#endif
 #if MNS_QUAD_SCHED_BARRIER
       // pin the accumulators at the end of every point (otherwise the
       // additions are deferred and every product stays live), and keep the
@@ -1231,13 +1246,13 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
 
   // back to the nodes: transposed interpolation across the quad (theta),
   // then along r and z in registers
-  Real sV[N];
+  Real tV[N];
 #pragma unroll
   for (int s = 0; s < N; ++s) {
     Real a[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) a[i] = T.V[i][(i - s + N) % N];
-    sV[s] = lane_select<N>(ts, a);
+    for (int i = 0; i < N; ++i) a[i] = T.V[(i + s) % N][i];
+    tV[s] = lane_select<N>(ts, a);
   }
   Real* Ec = E + cell;
 #pragma unroll
@@ -1247,10 +1262,9 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
     for (int qj = 0; qj < N; ++qj)
 #pragma unroll
       for (int q = 0; q < N; ++q) {
-        Real p[N];
-#pragma unroll
-        for (int s = 0; s < N; ++s) p[s] = sV[s] * F[m][qj][q];
-        X[qj][q] = quad_reduce<N>(p);
+        Real xs[N];
+        quad_rotate<N>(F[m][qj][q], xs);
+        X[qj][q] = quad_dot<N>(tV, xs);
       }
     Real Y[N][N];
 #pragma unroll
@@ -1431,12 +1445,12 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
 #pragma unroll
           for (int e = 0; e < DIM; ++e) Gm[e] = nu * gu[m][e] + tau * R[m] * a[e];
           Gm[m] -= rp.v;
-          to_reference<Real, DIM>(g, g.jxw, ct * uu[m] + hv[m] + conv[m] - fv[m], Gm, tc[q][m]);
+          to_reference<Real, DIM>(g, ct * uu[m] + hv[m] + conv[m] - fv[m], Gm, tc[q][m]);
         }
         Real Gq[DIM];
 #pragma unroll
         for (int e = 0; e < DIM; ++e) Gq[e] = tau * R[e];
-        to_reference<Real, DIM>(g, g.jxw, divu, Gq, tc[q][DIM]);
+        to_reference<Real, DIM>(g, divu, Gq, tc[q][DIM]);
       }
     }
   }
