@@ -254,6 +254,7 @@ def main():
                    "rotor_angle": theta, "nu": mesh["nu"], "step": "one FP64 Jacobian application"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": tb, "traffic_source": f"profiles/traffic_{name}.txt" if tb else None,
                      "kernel": kname, "kernel_ms": vol_ms64,
                      "algorithmic_bytes_per_launch": bytes64},
         "cpu_baseline": cpu,

@@ -169,14 +169,4 @@ int set_error(mns_handle* h, int code, const std::string& msg);
 
 // timing hooks around a kernel launch (no-ops unless timing is enabled)
 enum { TIMER_VOLUME = 0, TIMER_MORTAR = 1, TIMER_OTHER = 2 };
-inline void timer_begin(mns_handle* h, int cls, hipStream_t s) {
-  if (h->timing_cap && h->ev_used[cls] < h->timing_cap) (void)hipEventRecord(h->ev[cls][2 * h->ev_used[cls]], s);
-}
-inline void timer_end(mns_handle* h, int cls, hipStream_t s) {
-  if (h->timing_cap && h->ev_used[cls] < h->timing_cap) {
-    (void)hipEventRecord(h->ev[cls][2 * h->ev_used[cls] + 1], s);
-    ++h->ev_used[cls];
-  }
-}
-
 }  // namespace mns

@@ -14,6 +14,8 @@
 
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "mns_internal.hpp"
 
 namespace mns {
@@ -2017,6 +2019,19 @@ static int hip_check(mns_handle* h, const char* what) {
   return MNS_OK;
 }
 
+// Launch of a kernel of timer class cls: while timing is enabled the launch
+// carries the start and stop events of its own dispatch (so they bracket the
+// kernel alone, not the queue around it).
+template <typename K, typename... Args>
+static void launch_k(mns_handle* h, int cls, K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (h->timing_cap && h->ev_used[cls] < h->timing_cap) {
+    const int u = h->ev_used[cls]++;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, h->ev[cls][2 * u], h->ev[cls][2 * u + 1], 0, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
+}
+
 template <typename Real>
 int launch_fill(Real* x, Real v, int64_t n, hipStream_t s) {
   if (n <= 0) return MNS_OK;
@@ -2055,9 +2070,7 @@ static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStre
   const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
   const unsigned blocks = (2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                          MortarShape<Real, DIM, N>::FPB;
-  timer_begin(h, TIMER_MORTAR, s);
-  hipLaunchKernelGGL((k_mortar<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, M, mtrig, src, Em, mask);
-  timer_end(h, TIMER_MORTAR, s);
+  launch_k(h, TIMER_MORTAR, k_mortar<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, M, mtrig, src, Em, mask);
   return hip_check(h, "mortar kernel");
 }
 
@@ -2066,10 +2079,8 @@ static int do_gather(mns_handle* h, const Real* E, const Real* Em, const Real* s
                      hipStream_t s) {
   const Geom<Real> G = make_geom<Real>(h);
   const long long nnodes = h->nnodes;
-  timer_begin(h, TIMER_OTHER, s);
-  hipLaunchKernelGGL((k_gather<Real, DIM, N>), dim3((unsigned)((nnodes + 255) / 256)), dim3(256), 0, s, G, h->k, E,
-                     Em, src, dst, mode);
-  timer_end(h, TIMER_OTHER, s);
+  launch_k(h, TIMER_OTHER, k_gather<Real, DIM, N>, dim3((unsigned)((nnodes + 255) / 256)), dim3(256), s, G, h->k, E,
+           Em, src, dst, mode);
   return hip_check(h, "gather kernel");
 }
 
@@ -2092,27 +2103,23 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
     const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
     const int nmb = (int)((2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                           MortarShape<Real, DIM, N>::FPB);
-    timer_begin(h, TIMER_VOLUME, s);
     if constexpr (kQuad) {
       if (quad)
-        hipLaunchKernelGGL((k_jacobian_fused_quad<Real, N>), dim3(blocks + nmb), dim3(64), 0, s, G, T, h->k, nmb, lin,
-                           M, mtrig, src, E, Em);
+        launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb,
+                 lin, M, mtrig, src, E, Em);
     }
     if (!quad)
-      hipLaunchKernelGGL((k_jacobian_fused<Real, DIM, N>), dim3(blocks + nmb), dim3(64), 0, s, G, T, h->k, nmb, lin,
-                         M, mtrig, src, E, Em);
-    timer_end(h, TIMER_VOLUME, s);
+      launch_k(h, TIMER_VOLUME, k_jacobian_fused<Real, DIM, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb, lin,
+               M, mtrig, src, E, Em);
     rc = hip_check(h, "fused volume/mortar kernel");
     if (rc) return rc;
   } else {
-    timer_begin(h, TIMER_VOLUME, s);
     if constexpr (kQuad) {
       if (quad)
-        hipLaunchKernelGGL((k_jacobian_volume_quad<Real, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
+        launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E);
     }
     if (!quad)
-      hipLaunchKernelGGL((k_jacobian_volume<Real, DIM, N>), dim3(blocks), dim3(64), 0, s, G, T, h->k, lin, src, E);
-    timer_end(h, TIMER_VOLUME, s);
+      launch_k(h, TIMER_VOLUME, k_jacobian_volume<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E);
     rc = hip_check(h, "volume kernel");
     if (rc) return rc;
     rc = do_mortar<Real, DIM, N>(h, src, Em, 1, s);
