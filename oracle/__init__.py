@@ -58,32 +58,55 @@ _DEFAULTS = dict(
 )
 
 
+def _configure(lib):
+    P = ctypes.POINTER(_Params)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.orc_ndofs.argtypes = [P, i64p, i64p, i64p, i64p]
+    lib.orc_constrained.argtypes = [P, ctypes.c_void_p]
+    lib.orc_node_coords.argtypes = [P, dp]
+    lib.orc_cell_info.argtypes = [P, dp, dp, dp, dp]
+    lib.orc_segments.argtypes = [P, ctypes.c_void_p, dp, dp]
+    lib.orc_rules.argtypes = [ctypes.c_int, dp, dp, dp]
+    lib.orc_lagrange.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp, dp]
+    lib.orc_phys_basis.argtypes = [P, ctypes.c_int64, dp, dp, dp, dp, dp]
+    lib.orc_apply_jacobian.argtypes = [P, dp, dp, dp, dp, dp]
+    lib.orc_apply_jacobian_rows.argtypes = [P, dp, dp, dp, dp, ctypes.c_int64, i64p, dp]
+    lib.orc_residual.argtypes = [P, dp, dp, dp, dp, dp]
+    lib.orc_diagonal.argtypes = [P, dp, dp, dp, dp]
+    lib.orc_assemble.argtypes = [P, dp, dp, dp, ctypes.c_int64, i64p, i64p, dp, i64p]
+    lib.orc_mms_interpolate.argtypes = [P, dp]
+    lib.orc_mms_errors.argtypes = [P, dp, dp]
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.POINTER(_Params)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        lib.orc_ndofs.argtypes = [P, i64p, i64p, i64p, i64p]
-        lib.orc_constrained.argtypes = [P, ctypes.c_void_p]
-        lib.orc_node_coords.argtypes = [P, dp]
-        lib.orc_cell_info.argtypes = [P, dp, dp, dp, dp]
-        lib.orc_segments.argtypes = [P, ctypes.c_void_p, dp, dp]
-        lib.orc_rules.argtypes = [ctypes.c_int, dp, dp, dp]
-        lib.orc_lagrange.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp, dp]
-        lib.orc_phys_basis.argtypes = [P, ctypes.c_int64, dp, dp, dp, dp, dp]
-        lib.orc_apply_jacobian.argtypes = [P, dp, dp, dp, dp, dp]
-        lib.orc_apply_jacobian_rows.argtypes = [P, dp, dp, dp, dp, ctypes.c_int64, i64p, dp]
-        lib.orc_residual.argtypes = [P, dp, dp, dp, dp, dp]
-        lib.orc_diagonal.argtypes = [P, dp, dp, dp, dp]
-        lib.orc_assemble.argtypes = [P, dp, dp, dp, ctypes.c_int64, i64p, i64p, dp, i64p]
-        lib.orc_mms_interpolate.argtypes = [P, dp]
-        lib.orc_mms_errors.argtypes = [P, dp, dp]
-        _lib = lib
+        _lib = _configure(ctypes.CDLL(_LIB))
     return _lib
+
+
+def build_variant(source_text, path):
+    """Compile another version of the oracle source (the planted-mistake tests
+    use this to check that the pins reject a wrong oracle)."""
+    src = path + ".c"
+    with open(src, "w") as f:
+        f.write(source_text)
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared", src, "-o", path,
+                           "-lm"])
+    return path
+
+
+def swap_library(path):
+    """Route every oracle call to the library at `path` (None: the real
+    oracle).  Returns the previously active library handle."""
+    global _lib
+    old = _lib
+    _lib = None if path is None else _configure(ctypes.CDLL(path))
+    return old
 
 
 def params(**kw):

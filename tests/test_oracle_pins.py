@@ -193,6 +193,125 @@ def test_mortar_segments(dim):
             assert rot_lo < 1e-9 or rot_lo > 2 * math.pi - dth - 1e-9
 
 
+# ----------------------------------- closed forms on one interior cell (2D) --
+# Rows of J at the interior node of one cell couple only that cell's nodes, so
+# special increments and states reduce them to integrals of the basis over the
+# cell, evaluated here with the cell's Gauss rule (pinned above) and the
+# closed-form polar Jacobian r dr dtheta.
+
+def _interior_cell_setup(**kw):
+    cfg = _cfg(dim=2, degree=2, n_theta=6, n_r_rotor=3, n_r_stator=2, omega=0.0, theta_rot=0.37, **kw)
+    k, nt = 2, cfg["n_theta"]
+    ct, cr = 2, 1                                     # rotor cell away from every wall and the interface
+    cell = ct + nt * cr
+    node = (k * ct + 1) + (k * nt) * (k * cr + 1)     # its interior node (theta fastest, rotor first)
+    n = k + 1
+    _, gx, gw = oracle.rules(n)
+    dr = (cfg["r_if"] - cfg["r_in"]) / cfg["n_r_rotor"]
+    dth = 2 * math.pi / nt
+    pts = []
+    for j in range(n):
+        for i in range(n):
+            phi, grad, _, x = oracle.phys_basis(cfg, cell, (gx[i], gx[j]))
+            r = math.hypot(x[0], x[1])
+            pts.append((phi, grad, x, r, gw[i] * gw[j] * r * dr * dth))
+    phi_c, _, _, xc = oracle.phys_basis(cfg, cell, (0.5, 0.5))
+    assert np.abs(oracle.node_coords(cfg)[node] - xc).max() < 1e-14   # the node is the cell centre
+    a = 4                                                              # its local index (1, 1)
+    assert abs(phi_c[a] - 1.0) < 1e-14
+    r0 = cfg["r_in"] + cr * dr
+    A = 0.5 * ((r0 + dr) ** 2 - r0 ** 2) * dth
+    return cfg, cell, node, a, pts, A
+
+
+@pytest.mark.parametrize("U,steady", [(0.0, 1), (0.7, 1), (0.7, 0)])
+def test_tau_closed_form(U, steady):
+    """Eq. Eq-stab-param through the PSPG block: for a uniform state u = (U, 0),
+    p = 0, omega = 0 the pressure-pressure entry at a cell-interior node is
+    tau (grad psi, grad psi) with tau = (c^2 + (2U/h)^2 + 9 (4 nu / h^2)^2)^(-1/2),
+    c = 1/dt (0 when steady), h = 2 sqrt(A / pi)."""
+    cfg, cell, node, a, pts, A = _interior_cell_setup(steady=steady, dt=0.05, nu=0.03)
+    n = oracle.n_dofs(cfg)
+    state = np.zeros(n)
+    state[0::3] = U
+    i = 3 * node + 2
+    x = np.zeros(n)
+    x[i] = 1.0
+    Jii = oracle.apply_jacobian(cfg, state, x)[i]
+    K = sum(w * grad[a] @ grad[a] for _, grad, _, _, w in pts)
+    h = 2 * math.sqrt(A / math.pi)
+    c = 0.0 if steady else 1.0 / 0.05
+    tau = (c * c + (2 * U / h) ** 2 + 9 * (4 * 0.03 / h ** 2) ** 2) ** -0.5
+    assert abs(Jii - tau * K) < 1e-13 * tau * K
+
+
+@pytest.mark.parametrize("steady", [1, 0])
+def test_mass_and_viscous_coefficients(steady):
+    """Eq. Eq-discrete-1 at u = 0, omega = 0 (a = 0, R = 0, so no SUPG term):
+    the velocity diagonal entry at a cell-interior node is
+    c_t (psi, psi) + nu (grad psi, grad psi), c_t = 3 / (2 dt) for BDF2."""
+    cfg, cell, node, a, pts, _ = _interior_cell_setup(steady=steady, dt=0.05, nu=0.03)
+    n = oracle.n_dofs(cfg)
+    i = 3 * node
+    x = np.zeros(n)
+    x[i] = 1.0
+    y = oracle.apply_jacobian(cfg, np.zeros(n), x)
+    Mii = sum(w * phi[a] ** 2 for phi, _, _, _, w in pts)
+    Kii = sum(w * grad[a] @ grad[a] for _, grad, _, _, w in pts)
+    ct = 0.0 if steady else 1.5 / 0.05
+    assert abs(y[i] - (ct * Mii + 0.03 * Kii)) < 1e-13 * abs(y[i])
+    assert abs(y[i + 1]) < 1e-15 * abs(y[i])
+
+
+def test_ale_convection_of_rigid_rotation():
+    """Sec. 3.1 mesh velocity u_ALE = omega e_z x x in the convective term: with
+    u = 0 the advecting velocity is a = -u_ALE, and the increment
+    du_x = theta - theta_c (exact on the cell) has grad du_x = e_theta / r, so
+    the row of the cell-interior node is -omega (psi, 1) + nu (grad psi, e_theta / r)."""
+    omega, nu = 0.8, 0.03
+    cfg, cell, node, a, pts, _ = _interior_cell_setup(nu=nu, stabilization=0)
+    cfg = dict(cfg, omega=omega)
+    n = oracle.n_dofs(cfg)
+    xyz = oracle.node_coords(cfg)
+    xc = xyz[node]
+    k, nt = 2, cfg["n_theta"]
+    x = np.zeros(n)
+    ct, cr = 2, 1
+    for b in range(k + 1):
+        for a0 in range(k + 1):
+            nd = (k * ct + a0) + (k * nt) * (k * cr + b)
+            p = xyz[nd]
+            x[3 * nd] = math.atan2(xc[0] * p[1] - xc[1] * p[0], xc[0] * p[0] + xc[1] * p[1])
+    y = oracle.apply_jacobian(cfg, np.zeros(n), x)
+    exp = 0.0
+    for phi, grad, xq, r, w in pts:
+        et = np.array([-xq[1], xq[0], 0.0]) / r
+        exp += w * (-omega * phi[a] + nu * grad[a] @ et / r)
+    assert abs(exp) > 1e-3
+    assert abs(y[3 * node] - exp) < 1e-12 * abs(exp)
+
+
+def test_interface_penalty_closed_form():
+    """Eq. EqPenalty in the face term: only the penalty depends on F, so for the
+    velocity DoF of a rotor interface node inside one face, J_ii(F=3) - J_ii(F=1)
+    = nu (tau_rot(3) - tau_rot(1)) R dtheta * integral of L_1^2 over the face
+    (Gauss rule exact for this degree; tau_rot from its own closed-form pin)."""
+    nt, k, nu = 6, 2, 0.07
+    dth = 2 * math.pi / nt
+    cfg = _cfg(dim=2, degree=k, n_theta=nt, n_r_rotor=2, n_r_stator=2, nu=nu, theta_rot=2 * dth, omega=0.0)
+    n = oracle.n_dofs(cfg)
+    node = (k * 1 + 1) + (k * nt) * (k * cfg["n_r_rotor"])   # rotor cell 1, face-interior node on r = R
+    i = 3 * node
+    x = np.zeros(n)
+    x[i] = 1.0
+    J = {F: oracle.apply_jacobian(dict(cfg, penalty_F=F), np.zeros(n), x)[i] for F in (1.0, 3.0)}
+    tau = {F: oracle.cell_info(dict(cfg, penalty_F=F))["tau_side"][0] for F in (1.0, 3.0)}
+    gll, gx, gw = oracle.rules(k + 1)
+    face = cfg["r_if"] * dth * sum(w * oracle.lagrange(gll, t)[0][1] ** 2 for t, w in zip(gx, gw))
+    exp = nu * (tau[3.0] - tau[1.0]) * face
+    assert abs((J[3.0] - J[1.0]) - exp) < 1e-12 * exp
+
+
 # --------------------------------------------- operator: brute force checks --
 
 @pytest.mark.parametrize("dim", [2, 3])
