@@ -1051,6 +1051,24 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
   const int ts = t < N ? t : N - 1;  // theta slice held by this lane
   const CellId C = decode_cell(G, cell);
 
+  // every load that does not depend on arithmetic is issued here, before the
+  // nodal values are used, so that their latencies overlap: the cos/sin of the
+  // lane's theta point, the linearization data of the first MNS_QUAD_PREFETCH
+  // points (then kept that many points ahead through a register ring, points
+  // in (q, qj) order) and the nodal values
+  Real trc, trs;
+  {
+    const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + ts) * 2;
+    trc = tr[0];
+    trs = tr[1];
+  }
+  constexpr int PF = MNS_QUAD_PREFETCH > 0 ? MNS_QUAD_PREFETCH : 1;
+  const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
+  Real ring[PF][LL::SIZE];
+#pragma unroll
+  for (int i = 0; i < PF; ++i)
+    if (i < Q::PL) load_lin<Real, LL::SIZE>(lbase + ((i / N) * Q::PL + (i % N) * N) * LL::SIZE, ring[i]);
+
   // nodal values of the slice, constrained entries read as zero
   Real U[NC][N][N];  // [comp][r][z]
   {
@@ -1135,11 +1153,8 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
 
   // geometry of the lane's theta point
   PtGeom<Real> g;
-  {
-    const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + ts) * 2;
-    g.c = tr[0];
-    g.s = tr[1];
-  }
+  g.c = trc;
+  g.s = trs;
   const Real dr = pick(C.dom, G.dr), r0 = pick(C.dom, G.r0);
   g.inv_dr = Real(1) / dr;
   g.inv_dz = Real(1) / G.dz;
@@ -1161,14 +1176,6 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
 #pragma unroll
       for (int c = 0; c < N; ++c) F[m][b][c] = 0;
 
-  // linearization data of the lane's points, loaded MNS_QUAD_PREFETCH points
-  // ahead through a register ring (points in (q, qj) order)
-  constexpr int PF = MNS_QUAD_PREFETCH > 0 ? MNS_QUAD_PREFETCH : 1;
-  const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
-  Real ring[PF][LL::SIZE];
-#pragma unroll
-  for (int i = 0; i < PF; ++i)
-    if (i < Q::PL) load_lin<Real, LL::SIZE>(lbase + ((i / N) * Q::PL + (i % N) * N) * LL::SIZE, ring[i]);
   Real lv[LL::SIZE];
 
 #pragma unroll
