@@ -531,7 +531,7 @@ __device__ inline void integrate_store(const Tab1D<Real, N>& T, const Tab1D<Real
 template <typename Real, int DIM, int N>
 __global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real* __restrict__ E,
                                                 const Real* __restrict__ Em, const Real* __restrict__ src,
-                                                Real* __restrict__ dst, int mode) {
+                                                Real* __restrict__ dst, int mode, int strip) {
   using S = Shape<Real, DIM, N>;
   constexpr int NC = S::NC;
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -583,19 +583,51 @@ __global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real*
   for (int m = 0; m < NC; ++m) acc[m] = 0;
   const int cbase = dom ? (int)G.cell_off1 : 0;
   const size_t cstride = (size_t)S::NPT * G.ncells;
+  if (strip) {
+    // strip layout of the quad volume kernel: batches of 16 theta-consecutive
+    // cells, 16 k + 1 node columns per (comp, z, r) node position; a node on a
+    // batch boundary appears in two batches (last column of the earlier one)
+    const int S16 = 16 * k, nbt = G.n_theta / 16;
+    const size_t nblk = (size_t)(G.ncells / 16), pstride = nblk * S16;
+    const Real* Eb = E + (size_t)N * N * NC * pstride;  // last columns of the batches
+    int sb[2], sj[2];
+    bool sv[2];
+    sb[0] = it / S16;
+    sj[0] = it % S16;
+    sv[0] = true;
+    sb[1] = (sb[0] == 0 ? nbt : sb[0]) - 1;
+    sj[1] = S16;
+    sv[1] = sj[0] == 0;
 #pragma unroll
-  for (int z = 0; z < 2; ++z)
+    for (int z = 0; z < 2; ++z)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        if (!(zv[z] && rv[r] && tv[t])) continue;
-        const int cell = cbase + tc[t] + G.n_theta * (rc[r] + nrd * zc[z]);
-        const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + rb[r] * N + ta[t];
-        const Real* e = E + (size_t)loc * G.ncells + cell;
+        for (int t = 0; t < 2; ++t) {
+          if (!(zv[z] && rv[r] && sv[t])) continue;
+          const int ring = (cbase + G.n_theta * (rc[r] + nrd * zc[z])) / 16;
+          const size_t pos = (size_t)(zb[z] * N + rb[r]);
+          const size_t st = t == 0 ? pstride : nblk;
+          const Real* e = t == 0 ? E + pos * pstride + (size_t)(ring + sb[0]) * S16 + sj[0]
+                                 : Eb + pos * nblk + (ring + sb[1]);
 #pragma unroll
-        for (int m = 0; m < NC; ++m) acc[m] += e[m * cstride];
-      }
+          for (int m = 0; m < NC; ++m) acc[m] += e[(size_t)m * N * N * st];
+        }
+  } else {
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (!(zv[z] && rv[r] && tv[t])) continue;
+          const int cell = cbase + tc[t] + G.n_theta * (rc[r] + nrd * zc[z]);
+          const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + rb[r] * N + ta[t];
+          const Real* e = E + (size_t)loc * G.ncells + cell;
+#pragma unroll
+          for (int m = 0; m < NC; ++m) acc[m] += e[m * cstride];
+        }
+  }
   // mortar cell sides: every node of a rotor outer-ring cell or a stator
   // inner-ring cell (the grad v face term reaches all of them)
   int bm = -1;
@@ -936,11 +968,11 @@ struct QuadShape {
 };
 
 // DPP quad permutation: lane t of a quad reads lane (t + S) mod N; lanes
-// t >= N read themselves
+// t >= N read what lane N-1 reads, so that they repeat lane N-1 exactly
 template <int S, int N>
 __device__ constexpr int quad_ctrl() {
   int c = 0;
-  for (int t = 0; t < 4; ++t) c |= ((t < N) ? (t + S) % N : t) << (2 * t);
+  for (int t = 0; t < 4; ++t) c |= (((t < N ? t : N - 1) + S) % N) << (2 * t);
   return c;
 }
 
@@ -973,6 +1005,20 @@ __device__ inline Real quad_dot(const Real (&c)[N], const Real (&xs)[N]) {
 #pragma unroll
   for (int s = 1; s < N; ++s) v += c[s] * xs[s];
   return v;
+}
+
+// value of x held by the previous lane of the wavefront (DPP wave shift right
+// by one; lane 0 reads 0)
+template <typename Real>
+__device__ inline Real from_prev_lane(Real x) {
+  constexpr int kWaveShr1 = 0x138;
+  if constexpr (sizeof(Real) == 8) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), kWaveShr1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), kWaveShr1, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kWaveShr1, 0xF, 0xF, true));
+  }
 }
 
 // value v[t] of a lane-indexed table whose entries are wave-uniform
@@ -1038,7 +1084,7 @@ __device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
 template <typename Real, int N>
 __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                    const Real* __restrict__ lin, const Real* __restrict__ src,
-                                   Real* __restrict__ E) {
+                                   Real* __restrict__ E, bool strip) {
   constexpr int DIM = 3, NC = 4, NT = 4;
   using Q = QuadShape<Real, N>;
   using LL = LinLayout<DIM>;
@@ -1264,6 +1310,21 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
     tV[s] = lane_select<N>(ts, a);
   }
   Real* Ec = E + cell;
+  // strip layout: the 16 cells of the wavefront are theta-consecutive, so the
+  // theta-face shared by cells i-1 and i is summed here and the batch stores
+  // 16 k + 1 node columns per (r, z) node position instead of 16 (k + 1).
+  // Lane (i, 0) adds the value of the lane just before it, lane (i-1, 3),
+  // which holds slice k of cell i-1 (for k = 2 it duplicates lane (i-1, 2)).
+  // Columns 0 .. 16k-1 of a batch are contiguous (aligned 16 k values per
+  // batch and node position); column 16k, the face shared with the next
+  // batch, goes to a separate array after them.
+  constexpr int KD = N - 1, SL = 16 * KD;
+  const int ci = lane >> 2;
+  const bool store_s = active && (ts < KD || ci == Q::CPW - 1);
+  const size_t nblk = (size_t)(G.ncells / Q::CPW);
+  const size_t pstride = nblk * SL;  // per (comp, z, r) node position
+  Real* Es = (ts < KD) ? E + (size_t)vblock * SL + KD * ci + ts : E + (size_t)N * N * NC * pstride + vblock;
+  const size_t estride = (ts < KD) ? pstride : nblk;
 #pragma unroll
   for (int m = 0; m < NC; ++m) {
     Real X[N][N];
@@ -1292,7 +1353,13 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
         Real v = 0;
 #pragma unroll
         for (int q = 0; q < N; ++q) v += T.V[q][c] * Y[b][q];
-        if (active) Ec[(size_t)(m * Q::NPT + c * Q::PL + b * N + ts) * G.ncells] = v;
+        if (strip) {
+          const Real nb = from_prev_lane(v);
+          if (t == 0 && ci > 0) v += nb;
+          if (store_s) Es[(size_t)((m * N + c) * N + b) * estride] = v;
+        } else if (active) {
+          Ec[(size_t)(m * Q::NPT + c * Q::PL + b * N + ts) * G.ncells] = v;
+        }
       }
 #if MNS_QUAD_SCHED_BARRIER
     __builtin_amdgcn_sched_barrier(0);
@@ -1309,8 +1376,9 @@ __device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T,
 template <typename Real, int N>
 __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_volume_quad(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                              const Real* __restrict__ lin,
-                                                             const Real* __restrict__ src, Real* __restrict__ E) {
-  volume_quad<Real, N>(G, T, k, blockIdx.x, lin, src, E);
+                                                             const Real* __restrict__ src, Real* __restrict__ E,
+                                                             int strip) {
+  volume_quad<Real, N>(G, T, k, blockIdx.x, lin, src, E, strip != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1884,10 +1952,10 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_fused_quad(Geom<R
                                                             const MortarTab<Real, N>* __restrict__ Mp,
                                                             const Real* __restrict__ mtrig,
                                                             const Real* __restrict__ src, Real* __restrict__ E,
-                                                            Real* __restrict__ Em) {
+                                                            Real* __restrict__ Em, int strip) {
   __shared__ MortarSmem<Real, 3, N> sm;
   if ((int)blockIdx.x < nmb) mortar_block<Real, 3, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1, sm);
-  else volume_quad<Real, N>(G, T, k, blockIdx.x - nmb, lin, src, E);
+  else volume_quad<Real, N>(G, T, k, blockIdx.x - nmb, lin, src, E, strip != 0);
 }
 
 // Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
@@ -2083,11 +2151,11 @@ static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStre
 
 template <typename Real, int DIM, int N>
 static int do_gather(mns_handle* h, const Real* E, const Real* Em, const Real* src, Real* dst, int mode,
-                     hipStream_t s) {
+                     hipStream_t s, int strip = 0) {
   const Geom<Real> G = make_geom<Real>(h);
   const long long nnodes = h->nnodes;
   launch_k(h, TIMER_OTHER, k_gather<Real, DIM, N>, dim3((unsigned)((nnodes + 255) / 256)), dim3(256), s, G, h->k, E,
-           Em, src, dst, mode);
+           Em, src, dst, mode, strip);
   return hip_check(h, "gather kernel");
 }
 
@@ -2101,6 +2169,9 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   Real* Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
   constexpr bool kQuad = DIM == 3 && N == 3;
   const bool quad = kQuad && h->quad;
+  // strip layout of the local results: batches of 16 cells stay inside one
+  // ring when the ring length is a multiple of 16
+  const int strip = (quad && h->desc.n_theta % 16 == 0) ? 1 : 0;
   const int cpw = quad ? QuadShape<Real, N>::CPW : S::CPW;
   const unsigned blocks = (unsigned)((G.ncells + cpw - 1) / cpw);
   int rc;
@@ -2113,7 +2184,7 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
     if constexpr (kQuad) {
       if (quad)
         launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb,
-                 lin, M, mtrig, src, E, Em);
+                 lin, M, mtrig, src, E, Em, strip);
     }
     if (!quad)
       launch_k(h, TIMER_VOLUME, k_jacobian_fused<Real, DIM, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb, lin,
@@ -2123,7 +2194,8 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   } else {
     if constexpr (kQuad) {
       if (quad)
-        launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E);
+        launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E,
+                 strip);
     }
     if (!quad)
       launch_k(h, TIMER_VOLUME, k_jacobian_volume<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E);
@@ -2132,7 +2204,7 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
     rc = do_mortar<Real, DIM, N>(h, src, Em, 1, s);
     if (rc) return rc;
   }
-  return do_gather<Real, DIM, N>(h, E, Em, src, dst, 0, s);
+  return do_gather<Real, DIM, N>(h, E, Em, src, dst, 0, s, strip);
 }
 
 template <typename Real>

@@ -60,6 +60,28 @@ def test_jacobian_small(dim, k, angle, fused, layout):
     assert e32 <= TOL32
 
 
+@pytest.mark.parametrize("n_theta", [16, 32])
+@pytest.mark.parametrize("angle", ["random", "aligned"])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_jacobian_strip_layout(n_theta, angle, fused):
+    """3D Q2 with a ring length that is a multiple of 16: the quad kernel sums
+    the shared theta faces of its 16 cells before storing (strip layout) and
+    the gather reads that layout, including the batch-boundary columns and the
+    periodic wrap."""
+    mesh = small_mesh(3, 2, n_theta=n_theta)
+    dth = 2 * math.pi / n_theta
+    theta = {"random": 2.345, "aligned": 5 * dth}[angle]
+    g = np.random.default_rng(300 + n_theta)
+    n = inputs.n_dofs(mesh)
+    state, x = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
+    y64, y32 = _gpu_apply(mesh, theta, 0.8, state, x, fused=fused, layout=1)
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, theta, 0.8), state, x)
+    e64, e32 = relmax(y64, yo), relmax(y32, yo)
+    print(f"strip n_theta={n_theta} {angle} fused={fused}: fp64 {e64:.2e} fp32 {e32:.2e}")
+    assert e64 <= TOL64
+    assert e32 <= TOL32
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_jacobian_transient_with_history_and_force(dim):
     mesh = small_mesh(dim, 2, steady=0, dt=0.05, penalty_rule=1, penalty_F=3.0, n_theta=7)
