@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused", type=int, default=1, help="1: volume and mortar in one launch")
     ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k <= 3); 0: LDS planes")
+    ap.add_argument("--transient", action="store_true",
+                    help="also time one BDF2 + Newton step (transient workloads; rotor advances omega * dt)")
     return ap.parse_args()
 
 
@@ -217,6 +219,24 @@ def main():
         solves["state"] = "smooth manufactured field scaled to max |u| = 1"
         solves["preconditioner"] = f"Jacobi-Chebyshev degree {args.cheb_degree}, FGMRES({args.solve_restart})"
         rec["solve"] = solves
+
+    if args.transient and not mesh.get("steady", 1):
+        # one implicit time step: the rotor advances by omega dt, the start
+        # level is the smooth field with the wall values (fluid at rest before)
+        dt = mesh["dt"]
+        un = torch.from_numpy(inputs.transient_start(mesh, inputs.STATE_SEED[name])).to(dev)
+        u = un.clone()
+        sync()
+        info = op.bdf2_step(theta + omega * dt, omega, un, u, u_nm1=un, check=False, newton_rtol=1e-8,
+                            max_newton=10, linear=dict(rtol=1e-6, restart=30, maxit=600, precond="mg"))
+        rec["transient_step"] = {
+            "seconds": info["seconds"], "newton_iterations": info["newton_iterations"],
+            "linear_iterations": info["linear_iterations"], "converged": info["rc"] == 0,
+            "residual0": info["residual0"], "residual": info["residual"], "dt": dt, "rotation_rad": omega * dt,
+            "newton_rtol": 1e-8,
+            "linear": "FGMRES(30) FP64 to 1e-6, geometric multigrid V-cycle (FP32 Jacobi-Chebyshev smoothing)",
+        }
+        del un, u
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -63,6 +63,8 @@ enum {
 };
 
 enum { MNS_F64 = 0, MNS_F32 = 1 };
+/* preconditioner choice of mns_solve_opts.precond besides -1 / MNS_F64 / MNS_F32 */
+enum { MNS_PRECOND_MG = 2 };
 
 typedef struct mns_handle mns_handle;
 
@@ -134,10 +136,15 @@ typedef struct {
   double rtol;        /* stop at ||rhs - J x||_2 <= rtol ||rhs||_2 (default 1e-8) */
   int restart;        /* FGMRES restart length m (default 50) */
   int maxit;          /* max outer iterations in total (default 2000) */
-  int precond;        /* -1: none, MNS_F64 or MNS_F32: precision of the Chebyshev vmults */
-  int cheb_degree;    /* Chebyshev polynomial degree (default 4) */
+  int precond;        /* -1: none; MNS_F64 or MNS_F32: one Jacobi-Chebyshev polynomial whose vmults run in
+                         that precision; MNS_PRECOND_MG: geometric multigrid V-cycle (below) */
+  int cheb_degree;    /* Chebyshev polynomial degree; smoothing degree per step in the V-cycle (default 4) */
   double cheb_range;  /* ratio lambda_max / lambda_min of the Chebyshev interval (default 30) */
   int eig_iters;      /* power iterations for lambda_max of D^-1 J (default 20) */
+  int mg_levels;      /* V-cycle: most levels including the mesh itself, 0 = as many as the mesh allows */
+  int mg_smooth_degree;     /* V-cycle: Chebyshev smoothing degree before and after the correction (default 2) */
+  double mg_smooth_range;   /* V-cycle: smoothing interval [lambda_max / range, lambda_max] (default 5) */
+  int mg_coarse_degree;     /* V-cycle: Chebyshev degree on the coarsest level (default 16) */
 } mns_solve_opts;
 
 typedef struct {
@@ -153,6 +160,28 @@ typedef struct {
 /* Fill opts with the defaults above. */
 void mns_default_solve_opts(mns_solve_opts* opts);
 
+/* Geometric multigrid preconditioner (precond = MNS_PRECOND_MG), for degree 2.
+ * Levels: the mesh itself and meshes with n_theta, n_r_rotor, n_r_stator
+ * (and n_z in 3D) halved while all stay even (nested polar meshes: every
+ * coarse cell is 2 x 2 (x 2) fine cells of the same map).  On every level:
+ * the operator of mns_apply_jacobian with mortar faces at the same rotor
+ * angle, linearized at the state injected from the finest level (coarse nodes
+ * are fine nodes); FP32 Jacobi-Chebyshev smoothing of degree
+ * mg_smooth_degree on [lambda_max / mg_smooth_range, lambda_max] of D^-1 J
+ * before and after the coarse correction; Chebyshev of degree
+ * mg_coarse_degree on the coarsest level.  Transfers: prolongation = the
+ * coarse Q_2 field evaluated at the fine nodes, restriction = its transpose;
+ * constrained entries are zero after each transfer.  The hierarchy is built on
+ * the first V-cycle solve and relinearized when the state or the angle
+ * changed. */
+int mns_mg_levels(mns_handle* h, int* levels);
+
+/* y = P_level x: prolongation from multigrid level `level`+1 to `level`
+ * (level 0 = the mesh of h); x has the coarse level's n_total doubles, y the
+ * fine level's.  For inspection and tests; builds the hierarchy if needed.
+ * Errors: INVALID_ARG (no such level), UNSUPPORTED (degree != 2), HIP. */
+int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void* stream);
+
 /* Solve J x = rhs with flexible GMRES in FP64 (classical Gram-Schmidt with one
  * reorthogonalization), right-preconditioned by a Jacobi-Chebyshev polynomial
  * of D^-1 J whose vmults run in the precision opts->precond.  x holds the
@@ -164,6 +193,48 @@ void mns_default_solve_opts(mns_solve_opts* opts);
  * Errors: NOT_LINEARIZED, INVALID_ARG, NOT_CONVERGED (report filled), HIP. */
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
               void* stream);
+
+/* One implicit time step of the transient ALE problem (Sec. 2.2 with the
+ * rotor rotation of Sec. 3.1): BDF2 with constant step dt (from the mesh
+ * description, which must be transient) and Newton's method on the nodal
+ * residual, every linear step solved by mns_solve.
+ *   1. the rotor is rotated to theta_next (mns_rotate_rotor semantics);
+ *   2. history term h = (-4 u_n + u_nm1) / (2 dt), so that c_t u + h is the
+ *      BDF2 derivative with c_t = 3 / (2 dt).  With u_nm1 == NULL the first
+ *      step uses h = -(3 / (2 dt)) u_n: backward Euler with step 2 dt / 3.
+ *      Rotor nodes keep their material numbering, so the history needs no
+ *      remapping after the rotation;
+ *   3. u = u_next (initial guess; it must hold the Dirichlet values); repeat:
+ *      linearize at u, R = residual(u) (constrained rows 0), stop when
+ *      ||R||_2 <= max(newton_atol, newton_rtol ||R(u_0)||_2), else solve
+ *      J d = -R and set u += d (constrained entries of d are 0).
+ * u_n, u_nm1, force and u_next are device vectors of n_total doubles; u_next
+ * is overwritten with the last iterate.  The Jacobian freezes tau at the
+ * current iterate (the operator of mns_apply_jacobian).  The first call
+ * allocates four work vectors.  Synchronizes the stream.
+ * Errors: INVALID_ARG (steady mesh, bad pointers or options), HIP,
+ * NOT_CONVERGED (max_newton reached or a linear solve failed; u_next holds
+ * the last iterate and the report is filled). */
+typedef struct {
+  double newton_rtol;     /* default 1e-8 */
+  double newton_atol;     /* default 1e-13 */
+  int max_newton;         /* default 8 */
+  mns_solve_opts linear;  /* default mns_default_solve_opts with rtol 1e-6 */
+} mns_step_opts;
+
+typedef struct {
+  int newton_iterations;  /* linear solves taken */
+  int linear_iterations;  /* FGMRES iterations summed over the solves */
+  int status;             /* MNS_OK or MNS_ERR_NOT_CONVERGED */
+  double residual0;       /* ||R||_2 at the initial guess */
+  double residual;        /* ||R||_2 at the returned iterate */
+  double seconds;         /* wall time of the call */
+} mns_step_report;
+
+void mns_default_step_opts(mns_step_opts* opts);
+int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* u_n, const double* u_nm1,
+                  const double* force, double* u_next, const mns_step_opts* opts, mns_step_report* report,
+                  void* stream);
 
 /* Kernel configuration of the Jacobian application (tuning knobs; every
  * setting computes the same product).  fused_launch = 1 (default): volume

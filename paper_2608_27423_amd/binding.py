@@ -20,11 +20,14 @@ MNS_ERR_UNSUPPORTED = -5
 MNS_ERR_NO_ROTATION = -6
 MNS_F64 = 0
 MNS_F32 = 1
+MNS_PRECOND_MG = 2
+_PRECOND = {"none": -1, "f64": MNS_F64, "f32": MNS_F32, "mg": MNS_PRECOND_MG}
 
 EXPORTED = [
     "mns_setup_mesh", "mns_n_dofs", "mns_rotate_rotor", "mns_set_linearization", "mns_apply_jacobian",
     "mns_apply_residual", "mns_compute_diagonal", "mns_default_solve_opts", "mns_solve", "mns_enable_timing",
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
+    "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate",
 ]
 
 
@@ -43,6 +46,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
         ("cheb_degree", ctypes.c_int), ("cheb_range", ctypes.c_double), ("eig_iters", ctypes.c_int),
+        ("mg_levels", ctypes.c_int), ("mg_smooth_degree", ctypes.c_int), ("mg_smooth_range", ctypes.c_double),
+        ("mg_coarse_degree", ctypes.c_int),
     ]
 
 
@@ -51,6 +56,23 @@ class SolveReport(ctypes.Structure):
         ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("status", ctypes.c_int),
         ("rel_residual", ctypes.c_double), ("lambda_max", ctypes.c_double), ("seconds", ctypes.c_double),
         ("vmults_f64", ctypes.c_int), ("vmults_f32", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [
+        ("newton_rtol", ctypes.c_double), ("newton_atol", ctypes.c_double), ("max_newton", ctypes.c_int),
+        ("linear", SolveOpts),
+    ]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [
+        ("newton_iterations", ctypes.c_int), ("linear_iterations", ctypes.c_int), ("status", ctypes.c_int),
+        ("residual0", ctypes.c_double), ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -96,6 +118,12 @@ def lib():
         L.mns_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
         L.mns_set_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
         L.mns_get_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
+        L.mns_default_step_opts.argtypes = [ctypes.POINTER(StepOpts)]
+        L.mns_default_step_opts.restype = None
+        L.mns_bdf2_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, ctypes.POINTER(StepOpts),
+                                    ctypes.POINTER(StepReport), vp]
+        L.mns_mg_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.mns_mg_prolongate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_last_error.argtypes = [vp]
         L.mns_last_error.restype = ctypes.c_char_p
         L.mns_destroy.argtypes = [vp]
@@ -216,7 +244,7 @@ class Operator:
         o = self.default_solve_opts()
         for k, v in opts.items():
             if k == "precond" and isinstance(v, str):
-                v = {"none": -1, "f64": MNS_F64, "f32": MNS_F32}[v]
+                v = _PRECOND[v]
             setattr(o, k, v)
         if x is None:
             x = torch.zeros_like(rhs)
@@ -227,6 +255,38 @@ class Operator:
         d = rep.as_dict()
         d["rc"] = rc
         return x, d
+
+    def bdf2_step(self, theta_next, omega, u_n, u_next, u_nm1=None, force=None, check=True, linear=None, **opts):
+        """One BDF2 + Newton time step (mns_bdf2_step); u_next holds the initial
+        guess and receives the solution.  Returns the report as a dict."""
+        o = StepOpts()
+        self._L.mns_default_step_opts(ctypes.byref(o))
+        for k2, v in opts.items():
+            setattr(o, k2, v)
+        for k2, v in (linear or {}).items():
+            if k2 == "precond" and isinstance(v, str):
+                v = _PRECOND[v]
+            setattr(o.linear, k2, v)
+        for t in (u_n, u_next, u_nm1, force):
+            if t is not None and (t.numel() != self.n_dofs or t.dtype.itemsize != 8):
+                raise ValueError("vectors must be float64 of length n_dofs")
+        rep = StepReport()
+        rc = self._L.mns_bdf2_step(self._h, float(theta_next), float(omega), _ptr(u_n), _ptr(u_nm1), _ptr(force),
+                                   _ptr(u_next), ctypes.byref(o), ctypes.byref(rep), _stream())
+        if check and rc != MNS_OK:
+            raise MnsError(rc, self.last_error())
+        d = rep.as_dict()
+        d["rc"] = rc
+        return d
+
+    def mg_levels(self):
+        n = ctypes.c_int()
+        self._check(self._L.mns_mg_levels(self._h, ctypes.byref(n)))
+        return n.value
+
+    def mg_prolongate(self, level, x, y):
+        """y = P x from multigrid level `level`+1 to `level` (FP64 device vectors)."""
+        return self._check(self._L.mns_mg_prolongate(self._h, int(level), _ptr(x), _ptr(y), _stream()))
 
     def set_kernel_config(self, **kw):
         c = KernelConfig()

@@ -28,10 +28,11 @@ static void free_events(mns_handle* h) {
 
 static void free_all(mns_handle* h) {
   free_events(h);
+  mns::mg_free(h);
   void* ptrs[] = {h->d_hcell64, h->d_hcell32, h->d_trig64, h->d_trig32, h->d_mtab64, h->d_mtab32, h->d_mtrig64,
                   h->d_mtrig32, h->d_cons, h->d_lin64, h->d_lin32, h->d_hist, h->d_force, h->ws64, h->ws32,
                   h->d_E64, h->d_E32, h->d_Em64, h->d_Em32,
-                  h->d_diag64, h->d_diag32, h->d_red};
+                  h->d_diag64, h->d_diag32, h->d_red, h->d_step, h->d_state};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->h_red) (void)hipHostFree(h->h_red);
@@ -105,6 +106,7 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega) {
     rc = set_error(h, MNS_ERR_HIP, "exception in rotate");
   }
   h->rotated = rc == MNS_OK;
+  ++h->lin_version;
   h->linearized = false;
   h->diag_valid = false;
   return rc;
@@ -142,6 +144,12 @@ int mns_set_linearization(mns_handle* h, const double* state, const double* u_hi
       *dsts[i] = nullptr;
     }
   }
+  // the state is kept for the multigrid hierarchy (injected to coarse levels)
+  if (!h->d_state && (e = hipMalloc((void**)&h->d_state, h->ndofs * sizeof(double))) != hipSuccess)
+    return set_error(h, MNS_ERR_HIP, std::string("hipMalloc state: ") + hipGetErrorString(e));
+  if ((e = hipMemcpyAsync(h->d_state, state, h->ndofs * sizeof(double), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return set_error(h, MNS_ERR_HIP, std::string("copy state: ") + hipGetErrorString(e));
+  ++h->lin_version;
   int rc = launch_linearize<double>(h, state, h->desc.steady ? nullptr : h->d_hist, h->d_force, h->d_lin64, s);
   if (rc) return rc;
   rc = mns::launch_cast_f64_f32(h->d_lin64, h->d_lin32, (int64_t)nlin, s);
@@ -209,6 +217,10 @@ void mns_default_solve_opts(mns_solve_opts* o) {
   o->cheb_degree = 4;
   o->cheb_range = 30.0;
   o->eig_iters = 20;
+  o->mg_levels = 0;
+  o->mg_smooth_degree = 2;
+  o->mg_smooth_range = 5.0;
+  o->mg_coarse_degree = 16;
 }
 
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
@@ -222,7 +234,9 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
   if (opts) o = *opts;
   if (!(o.rtol > 0) || o.restart < 1 || o.restart > 1000 || o.maxit < 1 || o.cheb_degree < 1 ||
       o.cheb_degree > 100 || !(o.cheb_range > 1) || o.eig_iters < 1 ||
-      (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32))
+      (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32 && o.precond != MNS_PRECOND_MG) ||
+      o.mg_levels < 0 || o.mg_levels > 16 || o.mg_coarse_degree < 1 || o.mg_coarse_degree > 1000 ||
+      o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
   mns_solve_report rep{};
   int rc;
@@ -233,6 +247,64 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
   }
   if (report) *report = rep;
   return rc;
+}
+
+void mns_default_step_opts(mns_step_opts* o) {
+  if (!o) return;
+  o->newton_rtol = 1e-8;
+  o->newton_atol = 1e-13;
+  o->max_newton = 8;
+  mns_default_solve_opts(&o->linear);
+  o->linear.rtol = 1e-6;
+}
+
+int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* u_n, const double* u_nm1,
+                  const double* force, double* u_next, const mns_step_opts* opts, mns_step_report* report,
+                  void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (h->ndofs == 0) return set_error(h, MNS_ERR_INVALID_ARG, "handle was not set up");
+  if (h->desc.steady) return set_error(h, MNS_ERR_INVALID_ARG, "the mesh description is steady (no time step)");
+  if (!aligned(u_n, 8) || !aligned(u_next, 8) || (u_nm1 && !aligned(u_nm1, 8)) || (force && !aligned(force, 8)) ||
+      u_next == u_n || u_next == u_nm1 || u_next == force)
+    return set_error(h, MNS_ERR_INVALID_ARG, "vectors must be 8-byte aligned and u_next distinct from the inputs");
+  if (!std::isfinite(theta_next) || !std::isfinite(omega))
+    return set_error(h, MNS_ERR_INVALID_ARG, "theta and omega must be finite");
+  mns_step_opts o;
+  mns_default_step_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.newton_rtol >= 0) || !(o.newton_atol >= 0) || o.max_newton < 1 || o.max_newton > 100)
+    return set_error(h, MNS_ERR_INVALID_ARG, "invalid step options");
+  mns_step_report rep{};
+  int rc;
+  try {
+    rc = mns_bdf2_step_impl(h, theta_next, omega, u_n, u_nm1, force, u_next, &o, &rep, as_stream(stream));
+  } catch (...) {
+    rc = set_error(h, MNS_ERR_HIP, "exception in time step");
+  }
+  if (report) *report = rep;
+  return rc;
+}
+
+int mns_mg_levels(mns_handle* h, int* levels) {
+  if (!h || !levels) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  try {
+    return mns::mg_levels(h, levels, h->stream);
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in mg_levels");
+  }
+}
+
+int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (!aligned(x, 8) || !aligned(y, 8) || x == y)
+    return set_error(h, MNS_ERR_INVALID_ARG, "x/y must be distinct 8-byte aligned pointers");
+  try {
+    return mns::mg_prolongate64(h, level, x, y, as_stream(stream));
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in mg_prolongate");
+  }
 }
 
 int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg) {

@@ -125,6 +125,10 @@ struct mns_handle {
   double* d_diag64 = nullptr;
   float* d_diag32 = nullptr;
   double* d_red = nullptr;      // reduction scratch
+  double* d_step = nullptr;     // time-step work vectors (history, residual, rhs, increment, partials)
+  double* d_state = nullptr;    // copy of the linearization state (multigrid injects it)
+  long long lin_version = 0;    // incremented by every rotation and linearization
+  void* mg = nullptr;           // multigrid hierarchy (mns_solver.hip)
   double* h_red = nullptr;      // pinned host mirror
   int red_cap = 0;
   bool diag_valid = false;
@@ -158,6 +162,11 @@ int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real dia
                        hipStream_t s);
 
 // vector casts (mns_solver.hip)
+void mg_free(mns_handle* h);
+int mg_levels(mns_handle* h, int* levels, hipStream_t s);
+int mg_prolongate64(mns_handle* h, int level, const double* x, double* y, hipStream_t s);
+int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const double* un, const double* unm1,
+                       const double* force, double* u, const mns_step_opts* o, mns_step_report* rep, hipStream_t s);
 int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s);
 int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
 

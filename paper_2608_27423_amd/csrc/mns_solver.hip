@@ -16,6 +16,8 @@
 
 #include "mns_internal.hpp"
 
+int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h);
+
 namespace mns {
 
 constexpr int kRedBlocks = 1024;  // partial-sum blocks of the reductions
@@ -185,9 +187,13 @@ using namespace mns;
 
 namespace {
 
+struct MG;
+int mg_vcycle(MG* mg, const mns_solve_opts* o, const double* v, double* z, hipStream_t s);
+
 struct Solver {
   mns_handle* h;
   hipStream_t s;
+  MG* mg = nullptr;
   long long n;
   int m;
   double *V, *Z, *w, *r, *t64a, *t64b;  // FP64 workspace
@@ -305,6 +311,7 @@ struct Solver {
 
   int precondition(const mns_solve_opts* o, double lmax, const double* v, double* z) {
     const unsigned g = grid_for(n);
+    if (o->precond == MNS_PRECOND_MG) return mg_vcycle(mg, o, v, z, s);
     if (o->precond == -1) {
       hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, z, n);
       return MNS_OK;
@@ -355,14 +362,9 @@ int ensure_workspace(mns_handle* h, int m) {
   return MNS_OK;
 }
 
-}  // namespace
-
-int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* rep,
-                   hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
-  const int m = o->restart;
-  int rc = ensure_workspace(h, m);
-  if (rc) return rc;
+// Solver view of a handle's workspace (restart m as allocated by
+// ensure_workspace)
+Solver make_solver(mns_handle* h, hipStream_t s, int m) {
   Solver S;
   S.h = h;
   S.s = s;
@@ -384,9 +386,418 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
   S.r32 = S.x32 + n;
   S.d32 = S.r32 + n;
   S.t32 = S.d32 + n;
+  return S;
+}
+
+// ---------------------------------------------------------------------------
+// Geometric multigrid on nested polar meshes (degree 2)
+// ---------------------------------------------------------------------------
+
+// 1D transfer tables of one direction between a fine and a coarse node line:
+// prolongation rows (k + 1 coarse nodes per fine node) and restriction rows
+// (at most 2k + 1 fine nodes per coarse node).
+struct Tx1D {
+  std::vector<int> pidx, ridx;
+  std::vector<double> pw, rw;
+};
+
+// Coarse cell c holds fine cells 2c, 2c+1; fine node j of fine cell cf sits at
+// coarse reference coordinate ((cf mod 2) + x_j) / 2, where the coarse Q_k
+// field is sum_a L_a(xi) u_(k c + a).
+static Tx1D build_tx1d(int k, int ncc, bool periodic, const std::vector<double>& gll) {
+  Tx1D T;
+  const int K1 = k + 1, KR = 2 * k + 1;
+  const int nf = periodic ? 2 * k * ncc : 2 * k * ncc + 1;
+  const int nc = periodic ? k * ncc : k * ncc + 1;
+  T.pidx.assign((size_t)nf * K1, 0);
+  T.pw.assign((size_t)nf * K1, 0.0);
+  std::vector<std::vector<std::pair<int, double>>> rows(nc);
+  std::vector<double> L(K1), dL(K1), d2L(K1);
+  for (int f = 0; f < nf; ++f) {
+    int cf = f / k, j = f % k;
+    if (cf == 2 * ncc) {  // last node of an open line
+      cf = 2 * ncc - 1;
+      j = k;
+    }
+    const int c = cf / 2;
+    const double xi = ((cf % 2) + gll[j]) / 2.0;
+    lagrange_1d(gll, xi, L.data(), dL.data(), d2L.data());
+    for (int a = 0; a < K1; ++a) {
+      double w = L[a];
+      if (std::fabs(w) < 1e-13) w = 0.0;
+      if (std::fabs(w - 1.0) < 1e-13) w = 1.0;
+      int idx = k * c + a;
+      if (periodic) idx %= nc;
+      T.pidx[(size_t)f * K1 + a] = idx;
+      T.pw[(size_t)f * K1 + a] = w;
+      if (w != 0.0) rows[idx].push_back({f, w});
+    }
+  }
+  T.ridx.assign((size_t)nc * KR, 0);
+  T.rw.assign((size_t)nc * KR, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    if ((int)rows[c].size() > KR) throw std::runtime_error("restriction row too long");
+    for (size_t i = 0; i < rows[c].size(); ++i) {
+      T.ridx[(size_t)c * KR + i] = rows[c][i].first;
+      T.rw[(size_t)c * KR + i] = rows[c][i].second;
+    }
+  }
+  return T;
+}
+
+// device view of the transfer between level l (fine) and l + 1 (coarse)
+struct TxView {
+  int k, nc;                    // degree, components
+  int ntf, ntc, nzf, nzc;       // theta and z node counts (fine, coarse)
+  int nrf[2], nrc[2];           // radial node rows per domain
+  long long off1f, off1c;       // first stator node
+  const int* idx;
+  const double* w;
+  long long pt, pr[2], pz, rt, rr[2], rz;  // table offsets (entries)
+};
+
+template <typename Real>
+__global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __restrict__ fine, long long nnf,
+                             int add) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nnf) return;
+  const int dom = g >= X.off1f;
+  const long long l = g - (dom ? X.off1f : 0);
+  const int it = (int)(l % X.ntf);
+  const long long l2 = l / X.ntf;
+  const int nrf = dom ? X.nrf[1] : X.nrf[0];
+  const int nrc = dom ? X.nrc[1] : X.nrc[0];
+  const int ir = (int)(l2 % nrf), iz = (int)(l2 / nrf);
+  const int K1 = X.k + 1;
+  const long long ot = X.pt + (long long)it * K1, orr = (dom ? X.pr[1] : X.pr[0]) + (long long)ir * K1,
+                  oz = X.pz + (long long)iz * K1;
+  const long long cbase = dom ? X.off1c : 0;
+  Real acc[4] = {0, 0, 0, 0};
+  for (int a = 0; a < K1; ++a) {
+    const double wt = X.w[ot + a];
+    if (wt == 0.0) continue;
+    for (int b = 0; b < K1; ++b) {
+      const double wr = X.w[orr + b];
+      if (wr == 0.0) continue;
+      for (int c = 0; c < K1; ++c) {
+        const double wz = X.w[oz + c];
+        if (wz == 0.0) continue;
+        const long long node = cbase + X.idx[ot + a] + (long long)X.ntc * (X.idx[orr + b] + (long long)nrc * X.idx[oz + c]);
+        const Real ww = (Real)(wt * wr * wz);
+        for (int m = 0; m < X.nc; ++m) acc[m] += ww * coarse[node * X.nc + m];
+      }
+    }
+  }
+  for (int m = 0; m < X.nc; ++m) fine[g * X.nc + m] = (add ? fine[g * X.nc + m] : Real(0)) + acc[m];
+}
+
+template <typename Real>
+__global__ void k_mg_restrict(TxView X, const Real* __restrict__ fine, Real* __restrict__ coarse, long long nnc) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nnc) return;
+  const int dom = g >= X.off1c;
+  const long long l = g - (dom ? X.off1c : 0);
+  const int it = (int)(l % X.ntc);
+  const long long l2 = l / X.ntc;
+  const int nrf = dom ? X.nrf[1] : X.nrf[0];
+  const int nrc = dom ? X.nrc[1] : X.nrc[0];
+  const int ir = (int)(l2 % nrc), iz = (int)(l2 / nrc);
+  const int KR = 2 * X.k + 1;
+  const long long ot = X.rt + (long long)it * KR, orr = (dom ? X.rr[1] : X.rr[0]) + (long long)ir * KR,
+                  oz = X.rz + (long long)iz * KR;
+  const long long fbase = dom ? X.off1f : 0;
+  Real acc[4] = {0, 0, 0, 0};
+  for (int a = 0; a < KR; ++a) {
+    const double wt = X.w[ot + a];
+    if (wt == 0.0) continue;
+    for (int b = 0; b < KR; ++b) {
+      const double wr = X.w[orr + b];
+      if (wr == 0.0) continue;
+      for (int c = 0; c < KR; ++c) {
+        const double wz = X.w[oz + c];
+        if (wz == 0.0) continue;
+        const long long node = fbase + X.idx[ot + a] + (long long)X.ntf * (X.idx[orr + b] + (long long)nrf * X.idx[oz + c]);
+        const Real ww = (Real)(wt * wr * wz);
+        for (int m = 0; m < X.nc; ++m) acc[m] += ww * fine[node * X.nc + m];
+      }
+    }
+  }
+  for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = acc[m];
+}
+
+// coarse node (i, j, l) is fine node (2i, 2j, 2l) for degree 2
+__global__ void k_mg_inject(TxView X, const double* __restrict__ fine, double* __restrict__ coarse, long long nnc) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nnc) return;
+  const int dom = g >= X.off1c;
+  const long long l = g - (dom ? X.off1c : 0);
+  const int it = (int)(l % X.ntc);
+  const long long l2 = l / X.ntc;
+  const int nrf = dom ? X.nrf[1] : X.nrf[0];
+  const int nrc = dom ? X.nrc[1] : X.nrc[0];
+  const int ir = (int)(l2 % nrc), iz = (int)(l2 / nrc);
+  const long long f = (dom ? X.off1f : 0) + 2 * it + (long long)X.ntf * (2 * ir + (long long)nrf * (X.nzc > 1 ? 2 * iz : 0));
+  for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = fine[f * X.nc + m];
+}
+
+// out = a + beta * b
+template <typename Real>
+__global__ void k_mg_axpy(const Real* __restrict__ a, Real beta, const Real* __restrict__ b, Real* __restrict__ out,
+                          long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = a[i] + beta * b[i];
+}
+
+struct MGLevel {
+  mns_handle* h = nullptr;  // level 0: the caller's handle (not owned)
+  long long n = 0;
+  float *b = nullptr, *x = nullptr, *r = nullptr;  // V-cycle vectors
+  double* inj = nullptr;                           // injected state, history, force (coarse levels)
+  double lmax = 0;
+};
+
+struct MG {
+  std::vector<MGLevel> L;
+  std::vector<TxView> T;        // T[l]: level l <-> l + 1
+  std::vector<void*> tables;    // device allocations of the tables
+  long long version = -1;
+  int max_levels = 0;           // level limit the hierarchy was built with
+};
+
+static int mg_err(mns_handle* h, hipError_t e, const char* what) {
+  return set_error(h, MNS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static TxView make_tx(mns_handle* f, mns_handle* c, std::vector<void*>& keep, int* rc) {
+  TxView X{};
+  const int k = f->k;
+  X.k = k;
+  X.nc = f->nc;
+  X.ntf = f->ntn;
+  X.ntc = c->ntn;
+  X.nzf = f->nzn;
+  X.nzc = c->nzn;
+  for (int d = 0; d < 2; ++d) {
+    X.nrf[d] = f->nrn[d];
+    X.nrc[d] = c->nrn[d];
+  }
+  X.off1f = f->node_off1;
+  X.off1c = c->node_off1;
+  Tx1D tt = build_tx1d(k, c->desc.n_theta, true, f->gll);
+  Tx1D tr0 = build_tx1d(k, c->desc.n_r_rotor, false, f->gll);
+  Tx1D tr1 = build_tx1d(k, c->desc.n_r_stator, false, f->gll);
+  Tx1D tz;
+  if (f->dim == 3) {
+    tz = build_tx1d(k, c->desc.n_z, false, f->gll);
+  } else {  // one node plane: identity
+    tz.pidx.assign(k + 1, 0);
+    tz.pw.assign(k + 1, 0.0);
+    tz.pw[0] = 1.0;
+    tz.ridx.assign(2 * k + 1, 0);
+    tz.rw.assign(2 * k + 1, 0.0);
+    tz.rw[0] = 1.0;
+  }
+  std::vector<int> idx;
+  std::vector<double> w;
+  auto put = [&](const std::vector<int>& i, const std::vector<double>& v) {
+    const long long off = (long long)idx.size();
+    idx.insert(idx.end(), i.begin(), i.end());
+    w.insert(w.end(), v.begin(), v.end());
+    return off;
+  };
+  X.pt = put(tt.pidx, tt.pw);
+  X.pr[0] = put(tr0.pidx, tr0.pw);
+  X.pr[1] = put(tr1.pidx, tr1.pw);
+  X.pz = put(tz.pidx, tz.pw);
+  X.rt = put(tt.ridx, tt.rw);
+  X.rr[0] = put(tr0.ridx, tr0.rw);
+  X.rr[1] = put(tr1.ridx, tr1.rw);
+  X.rz = put(tz.ridx, tz.rw);
+  int* di = nullptr;
+  double* dw = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&di, idx.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc((void**)&dw, w.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMemcpy(di, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+    *rc = mg_err(f, e, "multigrid tables");
+  }
+  keep.push_back(di);
+  keep.push_back(dw);
+  X.idx = di;
+  X.w = dw;
+  return X;
+}
+
+static bool can_halve(const mns_mesh_desc& d) {
+  const bool z = d.dim == 2 || d.n_z % 2 == 0;
+  return d.n_theta % 2 == 0 && d.n_theta / 2 >= 4 && d.n_r_rotor % 2 == 0 && d.n_r_stator % 2 == 0 && z;
+}
+
+// levels and tables (once per handle)
+static int mg_build(mns_handle* h, int max_levels, MG** out) {
+  if (h->mg) {
+    MG* old = (MG*)h->mg;
+    if (old->max_levels == max_levels) {
+      *out = old;
+      return MNS_OK;
+    }
+    mg_free(h);  // another level count was asked for
+  }
+  if (h->k != 2) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs degree 2 (nested nodes)");
+  MG* mg = new MG();
+  mg->max_levels = max_levels;
+  h->mg = mg;
+  MGLevel L0;
+  L0.h = h;
+  L0.n = h->ndofs;
+  mg->L.push_back(L0);
+  mns_mesh_desc d = h->desc;
+  while (can_halve(d) && (max_levels == 0 || (int)mg->L.size() < max_levels)) {
+    d.n_theta /= 2;
+    d.n_r_rotor /= 2;
+    d.n_r_stator /= 2;
+    if (d.dim == 3) d.n_z /= 2;
+    mns_handle* hc = new mns_handle();
+    int rc = mns_build_handle(&d, h->stream, hc);
+    if (rc) {
+      const std::string msg = hc->err;
+      mns_destroy(hc);
+      return set_error(h, rc, "multigrid level: " + msg);
+    }
+    MGLevel Lc;
+    Lc.h = hc;
+    Lc.n = hc->ndofs;
+    mg->L.push_back(Lc);
+  }
+  int rc = MNS_OK;
+  for (size_t l = 0; l + 1 < mg->L.size(); ++l) {
+    mg->T.push_back(make_tx(mg->L[l].h, mg->L[l + 1].h, mg->tables, &rc));
+    if (rc) return rc;
+  }
+  hipError_t e;
+  for (size_t l = 0; l < mg->L.size(); ++l) {
+    MGLevel& Lv = mg->L[l];
+    if ((e = hipMalloc((void**)&Lv.b, 3 * (size_t)Lv.n * sizeof(float))) != hipSuccess) return mg_err(h, e, "hipMalloc mg");
+    Lv.x = Lv.b + Lv.n;
+    Lv.r = Lv.x + Lv.n;
+    if (l > 0 && (e = hipMalloc((void**)&Lv.inj, 3 * (size_t)Lv.n * sizeof(double))) != hipSuccess)
+      return mg_err(h, e, "hipMalloc mg");
+  }
+  *out = mg;
+  return MNS_OK;
+}
+
+// coarse operators at the current angle and state, diagonals and spectra
+static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t s) {
+  if (mg->version == h->lin_version) return MNS_OK;
+  int rc;
+  for (size_t l = 1; l < mg->L.size(); ++l) {
+    MGLevel& Lv = mg->L[l];
+    mns_handle* hc = Lv.h;
+    mns_handle* hf = mg->L[l - 1].h;
+    const TxView& X = mg->T[l - 1];
+    const long long nnc = hc->nnodes;
+    const unsigned g = (unsigned)((nnc + 255) / 256);
+    const double* fsrc[3] = {hf->d_state, hf->d_hist, hf->d_force};
+    double* cdst[3] = {Lv.inj, Lv.inj + Lv.n, Lv.inj + 2 * Lv.n};
+    for (int i = 0; i < 3; ++i)
+      if (fsrc[i]) hipLaunchKernelGGL(k_mg_inject, dim3(g), dim3(256), 0, s, X, fsrc[i], cdst[i], nnc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mg_err(h, e, "injection");
+    if ((rc = mns_rotate_rotor(hc, h->theta, h->omega))) return set_error(h, rc, "coarse rotate: " + hc->err);
+    if ((rc = mns_set_linearization(hc, cdst[0], fsrc[1] ? cdst[1] : nullptr, fsrc[2] ? cdst[2] : nullptr, s)))
+      return set_error(h, rc, "coarse linearization: " + hc->err);
+  }
+  for (size_t l = 0; l < mg->L.size(); ++l) {
+    MGLevel& Lv = mg->L[l];
+    mns_handle* hl = Lv.h;
+    if ((rc = ensure_workspace(hl, l == 0 ? hl->ws_restart : 1))) return l ? set_error(h, rc, hl->err) : rc;
+    if (!hl->diag_valid) {
+      if ((rc = launch_diagonal<double>(hl, hl->d_diag64, s))) return set_error(h, rc, "diagonal: " + hl->err);
+      if ((rc = launch_cast_f64_f32(hl->d_diag64, hl->d_diag32, (int64_t)hl->ndofs, s))) return set_error(h, rc, "cast");
+      hl->diag_valid = true;
+    }
+    Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+    if ((rc = S.estimate_lambda(o->eig_iters, &Lv.lmax))) return l ? set_error(h, rc, hl->err) : rc;
+  }
+  mg->version = h->lin_version;
+  return MNS_OK;
+}
+
+// x = Chebyshev smoothing of J x = b at level l (from x = 0 when zero)
+static int mg_smooth(MG* mg, size_t l, const float* b, float* x, bool zero, int deg, double range, hipStream_t s) {
+  MGLevel& Lv = mg->L[l];
+  mns_handle* hl = Lv.h;
+  Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+  const unsigned g = grid_for(Lv.n);
+  if (zero) return S.chebyshev<float>(b, x, S.r32, S.d32, S.t32, hl->d_diag32, deg, Lv.lmax, range);
+  int rc = launch_jacobian<float>(hl, x, S.t32, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, b, -1.0f, (const float*)S.t32, Lv.r, Lv.n);
+  if ((rc = S.chebyshev<float>(Lv.r, S.x32, S.r32, S.d32, S.t32, hl->d_diag32, deg, Lv.lmax, range))) return rc;
+  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, (const float*)x, 1.0f, (const float*)S.x32, x, Lv.n);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
+  MGLevel& Lv = mg->L[l];
+  mns_handle* hl = Lv.h;
+  int rc;
+  if (l + 1 == mg->L.size()) return mg_smooth(mg, l, Lv.b, Lv.x, true, o->mg_coarse_degree, o->mg_smooth_range, s);
+  if ((rc = mg_smooth(mg, l, Lv.b, Lv.x, true, o->mg_smooth_degree, o->mg_smooth_range, s))) return rc;
+  // residual, restricted with constrained rows zero on both levels
+  Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+  if ((rc = launch_jacobian<float>(hl, Lv.x, S.t32, s))) return rc;
+  const unsigned g = grid_for(Lv.n);
+  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, (const float*)Lv.b, -1.0f, (const float*)S.t32, Lv.r,
+                     Lv.n);
+  if ((rc = launch_constraints<float>(hl, Lv.r, Lv.r, 0.0f, 1, s))) return rc;
+  MGLevel& Lc = mg->L[l + 1];
+  const TxView& X = mg->T[l];
+  hipLaunchKernelGGL(k_mg_restrict<float>, dim3((unsigned)((Lc.h->nnodes + 255) / 256)), dim3(256), 0, s, X,
+                     (const float*)Lv.r, Lc.b, (long long)Lc.h->nnodes);
+  if ((rc = launch_constraints<float>(Lc.h, Lc.b, Lc.b, 0.0f, 1, s))) return rc;
+  if ((rc = mg_cycle(mg, l + 1, o, s))) return rc;
+  // x += P x_c (constrained rows of the correction zero)
+  hipLaunchKernelGGL(k_mg_prolong<float>, dim3((unsigned)((hl->nnodes + 255) / 256)), dim3(256), 0, s, X,
+                     (const float*)Lc.x, Lv.r, (long long)hl->nnodes, 0);
+  if ((rc = launch_constraints<float>(hl, Lv.r, Lv.r, 0.0f, 1, s))) return rc;
+  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, (const float*)Lv.x, 1.0f, (const float*)Lv.r, Lv.x,
+                     Lv.n);
+  if (hipGetLastError() != hipSuccess) return set_error(mg->L[0].h, MNS_ERR_HIP, "multigrid kernels");
+  return mg_smooth(mg, l, Lv.b, Lv.x, false, o->mg_smooth_degree, o->mg_smooth_range, s);
+}
+
+int mg_vcycle(MG* mg, const mns_solve_opts* o, const double* v, double* z, hipStream_t s) {
+  MGLevel& L0 = mg->L[0];
+  const unsigned g = grid_for(L0.n);
+  hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, L0.b, L0.n);
+  int rc = mg_cycle(mg, 0, o, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const float*)L0.x, z, L0.n);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+}  // namespace
+
+int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* rep,
+                   hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int m = o->restart;
+  int rc = ensure_workspace(h, m);
+  if (rc) return rc;
+  Solver S = make_solver(h, s, h->ws_restart);
+  const size_t n = (size_t)h->ndofs;
 
   double lmax = 0;
-  if (o->precond != -1) {
+  if (o->precond == MNS_PRECOND_MG) {
+    MG* mg = nullptr;
+    if ((rc = mg_build(h, o->mg_levels, &mg))) return rc;
+    if ((rc = mg_setup(h, mg, o, s))) return rc;
+    S.mg = mg;
+    lmax = mg->L[0].lmax;
+  } else if (o->precond != -1) {
     if (!h->diag_valid) {
       if ((rc = launch_diagonal<double>(h, h->d_diag64, s))) return rc;
       if ((rc = launch_cast_f64_f32(h->d_diag64, h->d_diag32, (int64_t)n, s))) return set_error(h, rc, "cast");
@@ -496,3 +907,42 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
   if (!converged) return set_error(h, MNS_ERR_NOT_CONVERGED, "FGMRES reached maxit");
   return MNS_OK;
 }
+
+namespace mns {
+
+void mg_free(mns_handle* h) {
+  MG* mg = (MG*)h->mg;
+  if (!mg) return;
+  for (size_t l = 0; l < mg->L.size(); ++l) {
+    MGLevel& Lv = mg->L[l];
+    if (Lv.b) (void)hipFree(Lv.b);
+    if (Lv.inj) (void)hipFree(Lv.inj);
+    if (l > 0 && Lv.h) mns_destroy(Lv.h);
+  }
+  for (void* p : mg->tables)
+    if (p) (void)hipFree(p);
+  delete mg;
+  h->mg = nullptr;
+}
+
+int mg_levels(mns_handle* h, int* levels, hipStream_t) {
+  MG* mg = nullptr;
+  int rc = mg_build(h, 0, &mg);
+  if (rc) return rc;
+  *levels = (int)mg->L.size();
+  return MNS_OK;
+}
+
+int mg_prolongate64(mns_handle* h, int level, const double* x, double* y, hipStream_t s) {
+  MG* mg = nullptr;
+  int rc = mg_build(h, 0, &mg);
+  if (rc) return rc;
+  if (level < 0 || level + 1 >= (int)mg->L.size()) return set_error(h, MNS_ERR_INVALID_ARG, "no such multigrid level");
+  mns_handle* hf = mg->L[level].h;
+  hipLaunchKernelGGL(k_mg_prolong<double>, dim3((unsigned)((hf->nnodes + 255) / 256)), dim3(256), 0, s,
+                     mg->T[level], x, y, (long long)hf->nnodes, 0);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNS_OK : set_error(h, MNS_ERR_HIP, std::string("prolongation: ") + hipGetErrorString(e));
+}
+
+}  // namespace mns

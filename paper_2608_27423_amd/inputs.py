@@ -134,3 +134,25 @@ def state_for(name):
 
 def vector_for(name):
     return uniform(n_dofs(WORKLOADS[name]), VECTOR_SEED[name])
+
+
+def transient_start(m, seed):
+    """Start level of a transient run: the smooth field scaled to max |.| = 1
+    with the no-slip walls (r_in, r_out and, in 3D, z = 0 and z = H) and the
+    pinned pressure node (stator, theta index 0, outermost ring, z index 0)
+    set to zero, so that it satisfies the Dirichlet data of the problem."""
+    u = smooth_field(m, seed)
+    u /= np.abs(u).max()
+    ntn, nrr, nrs, nzn = node_grid(m)
+    nc = m["dim"] + 1
+    v = u.reshape(-1, nc)
+    rot = v[: ntn * nrr * nzn].reshape(nzn, nrr, ntn, nc)
+    sta = v[ntn * nrr * nzn:].reshape(nzn, nrs, ntn, nc)
+    rot[:, 0, :, : m["dim"]] = 0.0
+    sta[:, -1, :, : m["dim"]] = 0.0
+    if m["dim"] == 3:
+        for blk in (rot, sta):
+            blk[0, :, :, : m["dim"]] = 0.0
+            blk[-1, :, :, : m["dim"]] = 0.0
+    sta[0, -1, 0, m["dim"]] = 0.0
+    return u

@@ -1,0 +1,102 @@
+"""Geometric multigrid (mns_solve with MNS_PRECOND_MG).
+
+* Prolongation: a field in the coarse Q2 space (the coarse Q2 interpolant of
+  sin(theta) times a quadratic in r and z) prolongated to the fine mesh equals
+  that field at the fine nodes; the expected values come from numpy's
+  quadratic fit through the three coarse nodes of each coarse cell and the
+  oracle's node coordinates, not from the library's tables.
+* Solve: the V-cycle-preconditioned FGMRES solution equals a direct sparse
+  solve of the oracle's assembled Jacobian.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle
+from paper_2608_27423_amd import binding, inputs
+from tests.helpers import oracle_cfg, relmax, small_mesh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float64)
+
+
+def _halved(mesh):
+    c = dict(mesh)
+    for key in ("n_theta", "n_r_rotor", "n_r_stator"):
+        c[key] //= 2
+    if mesh["dim"] == 3:
+        c["n_z"] //= 2
+    return c
+
+
+def _field(mesh, coarse_mesh, xyz):
+    """theta part: coarse Q2 interpolant of sin(theta) (per coarse cell, the
+    parabola through its three theta nodes); r, z part: a quadratic."""
+    dth = 2 * math.pi / coarse_mesh["n_theta"]
+    th = np.mod(np.arctan2(xyz[:, 1], xyz[:, 0]), 2 * math.pi)
+    cell = np.minimum(np.floor(th / dth + 1e-9).astype(int), coarse_mesh["n_theta"] - 1)
+    g = np.empty_like(th)
+    for c in np.unique(cell):
+        nodes = c * dth + np.array([0.0, 0.5, 1.0]) * dth
+        coef = np.polyfit(nodes, np.sin(nodes), 2)
+        sel = cell == c
+        g[sel] = np.polyval(coef, th[sel])
+    r = np.hypot(xyz[:, 0], xyz[:, 1])
+    z = xyz[:, 2]
+    return g * (1.0 + r * r + 3.0 * z * z - r * z + 0.5 * z)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_prolongation_reproduces_coarse_q2_fields(dim):
+    mesh = small_mesh(dim, 2, n_theta=16, n_r_rotor=2, n_r_stator=4, n_z=4)
+    coarse = _halved(mesh)
+    nc = dim + 1
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(0.0, 0.0)
+        op.set_linearization(torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda"))
+        assert op.mg_levels() >= 2
+        xyz_c = oracle.node_coords(oracle_cfg(coarse, 0.0, 0.0))
+        xyz_f = oracle.node_coords(oracle_cfg(mesh, 0.0, 0.0))
+        fc, ff = _field(mesh, coarse, xyz_c), _field(mesh, coarse, xyz_f)
+        xc = np.repeat(fc[:, None], nc, axis=1) * (1.0 + np.arange(nc))[None, :]
+        yf = np.repeat(ff[:, None], nc, axis=1) * (1.0 + np.arange(nc))[None, :]
+        y = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+        op.mg_prolongate(0, _dev(xc.ravel()), y)
+        err = relmax(y.cpu().numpy(), yf.ravel())
+    print(f"dim={dim}: prolongation error {err:.2e}")
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_multigrid_solve_matches_direct_solve(dim):
+    """Transient operator (the V-cycle's target) at a smooth state."""
+    mesh = small_mesh(dim, 2, n_theta=16, n_r_rotor=4, n_r_stator=4, n_z=4, steady=0, dt=0.02, nu=0.005)
+    n = inputs.n_dofs(mesh)
+    g = np.random.default_rng(500 + dim)
+    state = inputs.transient_start(mesh, 600 + dim)
+    hist = g.uniform(-1, 1, n)
+    b = g.uniform(-1, 1, n)
+    theta, omega = 1.234, 0.7
+    A = oracle.assemble(oracle_cfg(mesh, theta, omega), state, hist).tocsc()
+    xo = spla.spsolve(A, b)
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, omega)
+        op.set_linearization(_dev(state), None if hist is None else _dev(hist))
+        levels = op.mg_levels()
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        _, rep = op.solve(_dev(b), x, rtol=1e-11, restart=100, maxit=2000, precond="mg")
+        xg = x.cpu().numpy()
+        x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        _, rep1 = op.solve(_dev(b), x1, check=False, rtol=1e-11, restart=100, maxit=2000, precond="f32",
+                           cheb_degree=6)
+    err = relmax(xg, xo)
+    print(f"dim={dim}: levels {levels}, V-cycle its {rep['iterations']}, "
+          f"single-level its {rep1['iterations']} (rc {rep1['rc']}), |x - x_direct| / |x| = {err:.2e}")
+    assert levels >= 2
+    assert err < 1e-8
