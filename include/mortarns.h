@@ -207,11 +207,13 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
  *   3. u = u_next (initial guess; it must hold the Dirichlet values); repeat:
  *      linearize at u, R = residual(u) (constrained rows 0), stop when
  *      ||R||_2 <= max(newton_atol, newton_rtol ||R(u_0)||_2), else solve
- *      J d = -R and set u += d (constrained entries of d are 0).
+ *      J d = -R (constrained entries of d are 0) and set u += a d with the
+ *      first a in 1, 1/2, ..., 1/256 for which ||R(u + a d)||_2 <=
+ *      (1 - 1e-4 a) ||R(u)||_2 (the smallest when none is).
  * u_n, u_nm1, force and u_next are device vectors of n_total doubles; u_next
  * is overwritten with the last iterate.  The Jacobian freezes tau at the
  * current iterate (the operator of mns_apply_jacobian).  The first call
- * allocates four work vectors.  Synchronizes the stream.
+ * allocates five work vectors.  Synchronizes the stream.
  * Errors: INVALID_ARG (steady mesh, bad pointers or options), HIP,
  * NOT_CONVERGED (max_newton reached or a linear solve failed; u_next holds
  * the last iterate and the report is filled). */
@@ -229,6 +231,7 @@ typedef struct {
   double residual0;       /* ||R||_2 at the initial guess */
   double residual;        /* ||R||_2 at the returned iterate */
   double seconds;         /* wall time of the call */
+  int line_search_halvings; /* step halvings summed over the Newton iterations */
 } mns_step_report;
 
 void mns_default_step_opts(mns_step_opts* opts);

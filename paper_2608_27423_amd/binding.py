@@ -73,6 +73,7 @@ class StepReport(ctypes.Structure):
     _fields_ = [
         ("newton_iterations", ctypes.c_int), ("linear_iterations", ctypes.c_int), ("status", ctypes.c_int),
         ("residual0", ctypes.c_double), ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("line_search_halvings", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -68,14 +68,15 @@ int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const dou
   const long long n = h->ndofs;
   hipError_t e;
   if (!h->d_step) {
-    if ((e = hipMalloc((void**)&h->d_step, (4 * (size_t)n + kStepBlocks) * sizeof(double))) != hipSuccess)
+    if ((e = hipMalloc((void**)&h->d_step, (5 * (size_t)n + kStepBlocks) * sizeof(double))) != hipSuccess)
       return step_err(h, e, "hipMalloc step workspace");
   }
   double* hist = h->d_step;
   double* res = hist + n;
   double* rhs = res + n;
   double* d = rhs + n;
-  double* part = d + n;
+  double* trial = d + n;
+  double* part = trial + n;
   const unsigned blocks = kStepBlocks;
 
   int rc = mns_rotate_rotor(h, theta_next, omega);
@@ -88,14 +89,16 @@ int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const dou
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return status;
   };
-  double r0 = 0;
+  // Newton with a backtracking line search on ||R||_2: the step u + a d is
+  // accepted for the first a in 1, 1/2, 1/4, ... that reduces the norm by the
+  // factor (1 - 1e-4 a); after max halvings the smallest step is taken
+  constexpr int kMaxHalvings = 8;
+  if ((rc = mns_set_linearization(h, u, hist, force, s))) return rc;
+  if ((rc = mns_apply_residual(h, u, res, s))) return rc;
+  double rn;
+  if ((rc = norm2(h, res, part, s, &rn))) return rc;
+  const double r0 = rep->residual0 = rep->residual = rn;
   for (int it = 0;; ++it) {
-    if ((rc = mns_set_linearization(h, u, hist, force, s))) return rc;
-    if ((rc = mns_apply_residual(h, u, res, s))) return rc;
-    double rn;
-    if ((rc = norm2(h, res, part, s, &rn))) return rc;
-    if (it == 0) r0 = rep->residual0 = rn;
-    rep->residual = rn;
     if (!std::isfinite(rn)) return done(set_error(h, MNS_ERR_NOT_CONVERGED, "residual is not finite"));
     if (rn <= std::fmax(o->newton_atol, o->newton_rtol * r0)) return done(MNS_OK);
     if (it >= o->max_newton) return done(set_error(h, MNS_ERR_NOT_CONVERGED, "Newton iteration limit reached"));
@@ -109,8 +112,21 @@ int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const dou
     rep->linear_iterations += sr.iterations;
     if (rc == MNS_ERR_NOT_CONVERGED) return done(rc);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_axpy, dim3(blocks), dim3(256), 0, s, 1.0, d, u, n, 1);
+    double a = 1.0, rt = 0.0;
+    for (int ls = 0;; ++ls) {
+      hipLaunchKernelGGL(k_axpy, dim3(blocks), dim3(256), 0, s, 1.0, u, trial, n, 0);
+      hipLaunchKernelGGL(k_axpy, dim3(blocks), dim3(256), 0, s, a, d, trial, n, 1);
+      if ((e = hipGetLastError()) != hipSuccess) return step_err(h, e, "update kernel");
+      if ((rc = mns_apply_residual(h, trial, res, s))) return rc;
+      if ((rc = norm2(h, res, part, s, &rt))) return rc;
+      if ((std::isfinite(rt) && rt <= (1.0 - 1e-4 * a) * rn) || ls == kMaxHalvings) break;
+      a *= 0.5;
+      ++rep->line_search_halvings;
+    }
+    hipLaunchKernelGGL(k_axpy, dim3(blocks), dim3(256), 0, s, 1.0, trial, u, n, 0);
     if ((e = hipGetLastError()) != hipSuccess) return step_err(h, e, "update kernel");
+    rn = rep->residual = rt;
+    if ((rc = mns_set_linearization(h, u, hist, force, s))) return rc;
   }
 }
 
