@@ -240,9 +240,12 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
                   void* stream);
 
 /* Kernel configuration of the Jacobian application (tuning knobs; every
- * setting computes the same product).  fused_launch = 1 (default): volume
- * cells and mortar faces are integrated in one launch whose first blocks take
- * the mortar faces; 0: two launches.  volume_layout = 1 (default): in 3D
+ * setting computes the same product).  fused_launch = 1: volume cells and
+ * mortar faces are integrated in one launch whose first blocks take the
+ * mortar faces; 0: two launches on the caller's stream; 2: two launches, the
+ * mortar kernel on a second stream of the library (default priority) joined
+ * back to the caller's stream before the gather; -1 (default): 1 below
+ * 524,288 cells, 2 from there on.  volume_layout = 1 (default): in 3D
  * with degree <= 3 a quad of four lanes owns a cell and the theta
  * contractions exchange values between lanes without LDS; 0: nine (degree
  * 2) or sixteen (degree 3) lanes per cell with the r and theta contractions

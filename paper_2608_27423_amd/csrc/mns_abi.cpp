@@ -28,6 +28,9 @@ static void free_events(mns_handle* h) {
 
 static void free_all(mns_handle* h) {
   free_events(h);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   mns::mg_free(h);
   void* ptrs[] = {h->d_hcell64, h->d_hcell32, h->d_trig64, h->d_trig32, h->d_mtab64, h->d_mtab32, h->d_mtrig64,
                   h->d_mtrig32, h->d_cons, h->d_lin64, h->d_lin32, h->d_hist, h->d_force, h->ws64, h->ws32,
@@ -309,8 +312,8 @@ int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void
 
 int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg) {
   if (!h || !cfg) return MNS_ERR_INVALID_ARG;
-  if (cfg->fused_launch != 0 && cfg->fused_launch != 1)
-    return set_error(h, MNS_ERR_INVALID_ARG, "fused_launch must be 0 or 1");
+  if (cfg->fused_launch < -1 || cfg->fused_launch > 2)
+    return set_error(h, MNS_ERR_INVALID_ARG, "fused_launch must be -1, 0, 1 or 2");
   if (cfg->volume_layout != 0 && cfg->volume_layout != 1)
     return set_error(h, MNS_ERR_INVALID_ARG, "volume_layout must be 0 or 1");
   h->fused = cfg->fused_launch;
@@ -369,7 +372,7 @@ const char* mns_last_error(const mns_handle* h) { return h ? h->err.c_str() : "n
 void mns_destroy(mns_handle* h) {
   if (!h) return;
   if (h->d_cons) {  // the handle reached the device: drain its work first
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->stream && !h->aux) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
   }
   free_all(h);

@@ -133,7 +133,10 @@ struct mns_handle {
   int red_cap = 0;
   bool diag_valid = false;
   // kernel configuration (mns_set_kernel_config): fused volume + mortar launch
-  int fused = 1;
+  int fused = -1;
+  // second stream and events of the concurrent launch (fused == 2)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // volume layout: 1 = lane quad per cell (3D, degree <= 3), 0 = LDS planes
   int quad = 1;
   hipStream_t stream = nullptr;

@@ -24,7 +24,7 @@ def _dev(a, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=1, layout=1):
+def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=-1, layout=1):
     with binding.Operator(mesh) as op:
         op.set_kernel_config(fused_launch=fused, volume_layout=layout)
         op.rotate_rotor(theta, omega)
@@ -38,7 +38,7 @@ def _gpu_apply(mesh, theta, omega, state, x, hist=None, force=None, fused=1, lay
 
 CASES = [(2, 2), (2, 3), (2, 4), (2, 5), (3, 2), (3, 3), (3, 4)]
 # kernel configurations: (fused launch, volume layout)
-KCONF = [(1, 1), (0, 1), (1, 0), (0, 0)]
+KCONF = [(1, 1), (0, 1), (2, 1), (-1, 1), (1, 0), (0, 0), (2, 0)]
 
 
 @pytest.mark.parametrize("dim,k", CASES)
@@ -62,7 +62,7 @@ def test_jacobian_small(dim, k, angle, fused, layout):
 
 @pytest.mark.parametrize("n_theta", [16, 32])
 @pytest.mark.parametrize("angle", ["random", "aligned"])
-@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("fused", [1, 0, 2])
 def test_jacobian_strip_layout(n_theta, angle, fused):
     """3D Q2 with a ring length that is a multiple of 16: the quad kernel sums
     the shared theta faces of its 16 cells before storing (strip layout) and
