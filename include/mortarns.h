@@ -64,7 +64,7 @@ enum {
 
 enum { MNS_F64 = 0, MNS_F32 = 1 };
 /* preconditioner choice of mns_solve_opts.precond besides -1 / MNS_F64 / MNS_F32 */
-enum { MNS_PRECOND_MG = 2 };
+enum { MNS_PRECOND_MG = 2, MNS_PRECOND_MG64 = 3 };
 
 typedef struct mns_handle mns_handle;
 
@@ -137,7 +137,8 @@ typedef struct {
   int restart;        /* FGMRES restart length m (default 50) */
   int maxit;          /* max outer iterations in total (default 2000) */
   int precond;        /* -1: none; MNS_F64 or MNS_F32: one Jacobi-Chebyshev polynomial whose vmults run in
-                         that precision; MNS_PRECOND_MG: geometric multigrid V-cycle (below) */
+                         that precision; MNS_PRECOND_MG: geometric multigrid V-cycle (below) with FP32
+                         smoothing; MNS_PRECOND_MG64: the same V-cycle entirely in FP64 */
   int cheb_degree;    /* Chebyshev polynomial degree; smoothing degree per step in the V-cycle (default 4) */
   double cheb_range;  /* ratio lambda_max / lambda_min of the Chebyshev interval (default 30) */
   int eig_iters;      /* power iterations for lambda_max of D^-1 J (default 20) */
@@ -160,17 +161,18 @@ typedef struct {
 /* Fill opts with the defaults above. */
 void mns_default_solve_opts(mns_solve_opts* opts);
 
-/* Geometric multigrid preconditioner (precond = MNS_PRECOND_MG), for degree 2.
- * Levels: the mesh itself and meshes with n_theta, n_r_rotor, n_r_stator
- * (and n_z in 3D) halved while all stay even (nested polar meshes: every
- * coarse cell is 2 x 2 (x 2) fine cells of the same map).  On every level:
+/* Multigrid preconditioner (precond = MNS_PRECOND_MG or MNS_PRECOND_MG64),
+ * degree 2 or 3.  Levels: the mesh itself; for degree 3 then the degree-2
+ * space on the same mesh (polynomial level); then degree-2 meshes with
+ * n_theta, n_r_rotor, n_r_stator (and n_z in 3D) halved while all stay even
+ * (nested polar meshes: every coarse cell is 2 x 2 (x 2) fine cells of the
+ * same map).  On every level:
  * the operator of mns_apply_jacobian with mortar faces at the same rotor
- * angle, linearized at the state injected from the finest level (coarse nodes
- * are fine nodes); FP32 Jacobi-Chebyshev smoothing of degree
+ * angle, linearized at the finest state evaluated at the level's nodes; FP32 Jacobi-Chebyshev smoothing of degree
  * mg_smooth_degree on [lambda_max / mg_smooth_range, lambda_max] of D^-1 J
  * before and after the coarse correction; Chebyshev of degree
  * mg_coarse_degree on the coarsest level.  Transfers: prolongation = the
- * coarse Q_2 field evaluated at the fine nodes, restriction = its transpose;
+ * coarse field evaluated at the fine nodes, restriction = its transpose;
  * constrained entries are zero after each transfer.  The hierarchy is built on
  * the first V-cycle solve and relinearized when the state or the angle
  * changed. */
@@ -179,7 +181,7 @@ int mns_mg_levels(mns_handle* h, int* levels);
 /* y = P_level x: prolongation from multigrid level `level`+1 to `level`
  * (level 0 = the mesh of h); x has the coarse level's n_total doubles, y the
  * fine level's.  For inspection and tests; builds the hierarchy if needed.
- * Errors: INVALID_ARG (no such level), UNSUPPORTED (degree != 2), HIP. */
+ * Errors: INVALID_ARG (no such level), UNSUPPORTED (degree not 2 or 3), HIP. */
 int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void* stream);
 
 /* Solve J x = rhs with flexible GMRES in FP64 (classical Gram-Schmidt with one

@@ -21,7 +21,8 @@ MNS_ERR_NO_ROTATION = -6
 MNS_F64 = 0
 MNS_F32 = 1
 MNS_PRECOND_MG = 2
-_PRECOND = {"none": -1, "f64": MNS_F64, "f32": MNS_F32, "mg": MNS_PRECOND_MG}
+MNS_PRECOND_MG64 = 3
+_PRECOND = {"none": -1, "f64": MNS_F64, "f32": MNS_F32, "mg": MNS_PRECOND_MG, "mg64": MNS_PRECOND_MG64}
 
 EXPORTED = [
     "mns_setup_mesh", "mns_n_dofs", "mns_rotate_rotor", "mns_set_linearization", "mns_apply_jacobian",

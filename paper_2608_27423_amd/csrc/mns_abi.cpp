@@ -237,7 +237,8 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
   if (opts) o = *opts;
   if (!(o.rtol > 0) || o.restart < 1 || o.restart > 1000 || o.maxit < 1 || o.cheb_degree < 1 ||
       o.cheb_degree > 100 || !(o.cheb_range > 1) || o.eig_iters < 1 ||
-      (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32 && o.precond != MNS_PRECOND_MG) ||
+      (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32 && o.precond != MNS_PRECOND_MG &&
+       o.precond != MNS_PRECOND_MG64) ||
       o.mg_levels < 0 || o.mg_levels > 16 || o.mg_coarse_degree < 1 || o.mg_coarse_degree > 1000 ||
       o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");

@@ -311,7 +311,7 @@ struct Solver {
 
   int precondition(const mns_solve_opts* o, double lmax, const double* v, double* z) {
     const unsigned g = grid_for(n);
-    if (o->precond == MNS_PRECOND_MG) return mg_vcycle(mg, o, v, z, s);
+    if (o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64) return mg_vcycle(mg, o, v, z, s);
     if (o->precond == -1) {
       hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, z, n);
       return MNS_OK;
@@ -393,53 +393,79 @@ Solver make_solver(mns_handle* h, hipStream_t s, int m) {
 // Geometric multigrid on nested polar meshes (degree 2)
 // ---------------------------------------------------------------------------
 
-// 1D transfer tables of one direction between a fine and a coarse node line:
-// prolongation rows (k + 1 coarse nodes per fine node) and restriction rows
-// (at most 2k + 1 fine nodes per coarse node).
+// 1D transfer tables of one direction between a fine and a coarse node line
+// (degrees kf, kc; every coarse cell holds `refine` fine cells):
+// prolongation rows (kc + 1 coarse nodes per fine node), restriction rows
+// (the transposed entries, padded to a common width) and evaluation rows
+// (kf + 1 fine nodes per coarse node: the fine field at the coarse nodes).
 struct Tx1D {
-  std::vector<int> pidx, ridx;
-  std::vector<double> pw, rw;
+  std::vector<int> pidx, ridx, eidx;
+  std::vector<double> pw, rw, ew;
+  int rwidth = 0;
 };
 
-// Coarse cell c holds fine cells 2c, 2c+1; fine node j of fine cell cf sits at
-// coarse reference coordinate ((cf mod 2) + x_j) / 2, where the coarse Q_k
-// field is sum_a L_a(xi) u_(k c + a).
-static Tx1D build_tx1d(int k, int ncc, bool periodic, const std::vector<double>& gll) {
+static double snap(double w) {
+  if (std::fabs(w) < 1e-13) return 0.0;
+  if (std::fabs(w - 1.0) < 1e-13) return 1.0;
+  return w;
+}
+
+static Tx1D build_tx1d(int kf, int kc, int ncc, int refine, bool periodic, const std::vector<double>& gf,
+                       const std::vector<double>& gc, int rwidth) {
   Tx1D T;
-  const int K1 = k + 1, KR = 2 * k + 1;
-  const int nf = periodic ? 2 * k * ncc : 2 * k * ncc + 1;
-  const int nc = periodic ? k * ncc : k * ncc + 1;
-  T.pidx.assign((size_t)nf * K1, 0);
-  T.pw.assign((size_t)nf * K1, 0.0);
+  const int nfc = refine * ncc;
+  const int nf = periodic ? kf * nfc : kf * nfc + 1;
+  const int nc = periodic ? kc * ncc : kc * ncc + 1;
+  const int PW = kc + 1, EW = kf + 1;
+  T.pidx.assign((size_t)nf * PW, 0);
+  T.pw.assign((size_t)nf * PW, 0.0);
   std::vector<std::vector<std::pair<int, double>>> rows(nc);
-  std::vector<double> L(K1), dL(K1), d2L(K1);
+  std::vector<double> L(std::max(PW, EW)), dL(L.size()), d2L(L.size());
   for (int f = 0; f < nf; ++f) {
-    int cf = f / k, j = f % k;
-    if (cf == 2 * ncc) {  // last node of an open line
-      cf = 2 * ncc - 1;
-      j = k;
+    int cf = f / kf, j = f % kf;
+    if (cf == nfc) {  // last node of an open line
+      cf = nfc - 1;
+      j = kf;
     }
-    const int c = cf / 2;
-    const double xi = ((cf % 2) + gll[j]) / 2.0;
-    lagrange_1d(gll, xi, L.data(), dL.data(), d2L.data());
-    for (int a = 0; a < K1; ++a) {
-      double w = L[a];
-      if (std::fabs(w) < 1e-13) w = 0.0;
-      if (std::fabs(w - 1.0) < 1e-13) w = 1.0;
-      int idx = k * c + a;
+    const int c = cf / refine;
+    const double xi = ((cf % refine) + gf[j]) / refine;
+    lagrange_1d(gc, xi, L.data(), dL.data(), d2L.data());
+    for (int a = 0; a < PW; ++a) {
+      const double w = snap(L[a]);
+      int idx = kc * c + a;
       if (periodic) idx %= nc;
-      T.pidx[(size_t)f * K1 + a] = idx;
-      T.pw[(size_t)f * K1 + a] = w;
+      T.pidx[(size_t)f * PW + a] = idx;
+      T.pw[(size_t)f * PW + a] = w;
       if (w != 0.0) rows[idx].push_back({f, w});
     }
   }
-  T.ridx.assign((size_t)nc * KR, 0);
-  T.rw.assign((size_t)nc * KR, 0.0);
-  for (int c = 0; c < nc; ++c) {
-    if ((int)rows[c].size() > KR) throw std::runtime_error("restriction row too long");
+  for (auto& r : rows) T.rwidth = std::max(T.rwidth, (int)r.size());
+  const int RW = std::max(rwidth, T.rwidth);
+  T.ridx.assign((size_t)nc * RW, 0);
+  T.rw.assign((size_t)nc * RW, 0.0);
+  for (int c = 0; c < nc; ++c)
     for (size_t i = 0; i < rows[c].size(); ++i) {
-      T.ridx[(size_t)c * KR + i] = rows[c][i].first;
-      T.rw[(size_t)c * KR + i] = rows[c][i].second;
+      T.ridx[(size_t)c * RW + i] = rows[c][i].first;
+      T.rw[(size_t)c * RW + i] = rows[c][i].second;
+    }
+  T.eidx.assign((size_t)nc * EW, 0);
+  T.ew.assign((size_t)nc * EW, 0.0);
+  for (int i = 0; i < nc; ++i) {
+    int c = i / kc, a = i % kc;
+    if (c == ncc) {
+      c = ncc - 1;
+      a = kc;
+    }
+    const double xc = gc[a] * refine;  // position in units of fine cells of coarse cell c
+    int sub = (int)std::floor(xc);
+    if (sub >= refine) sub = refine - 1;
+    const int cf = c * refine + sub;
+    lagrange_1d(gf, xc - sub, L.data(), dL.data(), d2L.data());
+    for (int b = 0; b < EW; ++b) {
+      int idx = kf * cf + b;
+      if (periodic) idx %= nf;
+      T.eidx[(size_t)i * EW + b] = idx;
+      T.ew[(size_t)i * EW + b] = snap(L[b]);
     }
   }
   return T;
@@ -447,13 +473,14 @@ static Tx1D build_tx1d(int k, int ncc, bool periodic, const std::vector<double>&
 
 // device view of the transfer between level l (fine) and l + 1 (coarse)
 struct TxView {
-  int k, nc;                    // degree, components
+  int pw, rw, ew;               // row widths of the prolongation, restriction, evaluation tables
+  int nc;                       // components
   int ntf, ntc, nzf, nzc;       // theta and z node counts (fine, coarse)
   int nrf[2], nrc[2];           // radial node rows per domain
   long long off1f, off1c;       // first stator node
   const int* idx;
   const double* w;
-  long long pt, pr[2], pz, rt, rr[2], rz;  // table offsets (entries)
+  long long pt, pr[2], pz, rt, rr[2], rz, et, er[2], ez;  // table offsets (entries)
 };
 
 template <typename Real>
@@ -468,7 +495,7 @@ __global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __
   const int nrf = dom ? X.nrf[1] : X.nrf[0];
   const int nrc = dom ? X.nrc[1] : X.nrc[0];
   const int ir = (int)(l2 % nrf), iz = (int)(l2 / nrf);
-  const int K1 = X.k + 1;
+  const int K1 = X.pw;
   const long long ot = X.pt + (long long)it * K1, orr = (dom ? X.pr[1] : X.pr[0]) + (long long)ir * K1,
                   oz = X.pz + (long long)iz * K1;
   const long long cbase = dom ? X.off1c : 0;
@@ -502,7 +529,7 @@ __global__ void k_mg_restrict(TxView X, const Real* __restrict__ fine, Real* __r
   const int nrf = dom ? X.nrf[1] : X.nrf[0];
   const int nrc = dom ? X.nrc[1] : X.nrc[0];
   const int ir = (int)(l2 % nrc), iz = (int)(l2 / nrc);
-  const int KR = 2 * X.k + 1;
+  const int KR = X.rw;
   const long long ot = X.rt + (long long)it * KR, orr = (dom ? X.rr[1] : X.rr[0]) + (long long)ir * KR,
                   oz = X.rz + (long long)iz * KR;
   const long long fbase = dom ? X.off1f : 0;
@@ -525,8 +552,9 @@ __global__ void k_mg_restrict(TxView X, const Real* __restrict__ fine, Real* __r
   for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = acc[m];
 }
 
-// coarse node (i, j, l) is fine node (2i, 2j, 2l) for degree 2
-__global__ void k_mg_inject(TxView X, const double* __restrict__ fine, double* __restrict__ coarse, long long nnc) {
+// coarse nodal values of a fine field: the fine field evaluated at the
+// coarse nodes (for nested degree-2 meshes a coarse node is a fine node)
+__global__ void k_mg_eval(TxView X, const double* __restrict__ fine, double* __restrict__ coarse, long long nnc) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nnc) return;
   const int dom = g >= X.off1c;
@@ -536,8 +564,27 @@ __global__ void k_mg_inject(TxView X, const double* __restrict__ fine, double* _
   const int nrf = dom ? X.nrf[1] : X.nrf[0];
   const int nrc = dom ? X.nrc[1] : X.nrc[0];
   const int ir = (int)(l2 % nrc), iz = (int)(l2 / nrc);
-  const long long f = (dom ? X.off1f : 0) + 2 * it + (long long)X.ntf * (2 * ir + (long long)nrf * (X.nzc > 1 ? 2 * iz : 0));
-  for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = fine[f * X.nc + m];
+  const int KE = X.ew;
+  const long long ot = X.et + (long long)it * KE, orr = (dom ? X.er[1] : X.er[0]) + (long long)ir * KE,
+                  oz = X.ez + (long long)iz * KE;
+  const long long fbase = dom ? X.off1f : 0;
+  double acc[4] = {0, 0, 0, 0};
+  for (int a = 0; a < KE; ++a) {
+    const double wt = X.w[ot + a];
+    if (wt == 0.0) continue;
+    for (int b = 0; b < KE; ++b) {
+      const double wr = X.w[orr + b];
+      if (wr == 0.0) continue;
+      for (int c = 0; c < KE; ++c) {
+        const double wz = X.w[oz + c];
+        if (wz == 0.0) continue;
+        const long long node = fbase + X.idx[ot + a] + (long long)X.ntf * (X.idx[orr + b] + (long long)nrf * X.idx[oz + c]);
+        const double ww = wt * wr * wz;
+        for (int m = 0; m < X.nc; ++m) acc[m] += ww * fine[node * X.nc + m];
+      }
+    }
+  }
+  for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = acc[m];
 }
 
 // out = a + beta * b
@@ -551,8 +598,8 @@ __global__ void k_mg_axpy(const Real* __restrict__ a, Real beta, const Real* __r
 struct MGLevel {
   mns_handle* h = nullptr;  // level 0: the caller's handle (not owned)
   long long n = 0;
-  float *b = nullptr, *x = nullptr, *r = nullptr;  // V-cycle vectors
-  double* inj = nullptr;                           // injected state, history, force (coarse levels)
+  void* b = nullptr;        // V-cycle vectors b, x, r (FP32 or FP64, room for FP64)
+  double* inj = nullptr;    // injected state, history, force (coarse levels)
   double lmax = 0;
 };
 
@@ -570,8 +617,8 @@ static int mg_err(mns_handle* h, hipError_t e, const char* what) {
 
 static TxView make_tx(mns_handle* f, mns_handle* c, std::vector<void*>& keep, int* rc) {
   TxView X{};
-  const int k = f->k;
-  X.k = k;
+  const int kf = f->k, kc = c->k;
+  const int refine = f->desc.n_theta == c->desc.n_theta ? 1 : 2;
   X.nc = f->nc;
   X.ntf = f->ntn;
   X.ntc = c->ntn;
@@ -583,49 +630,70 @@ static TxView make_tx(mns_handle* f, mns_handle* c, std::vector<void*>& keep, in
   }
   X.off1f = f->node_off1;
   X.off1c = c->node_off1;
-  Tx1D tt = build_tx1d(k, c->desc.n_theta, true, f->gll);
-  Tx1D tr0 = build_tx1d(k, c->desc.n_r_rotor, false, f->gll);
-  Tx1D tr1 = build_tx1d(k, c->desc.n_r_stator, false, f->gll);
-  Tx1D tz;
-  if (f->dim == 3) {
-    tz = build_tx1d(k, c->desc.n_z, false, f->gll);
-  } else {  // one node plane: identity
-    tz.pidx.assign(k + 1, 0);
-    tz.pw.assign(k + 1, 0.0);
-    tz.pw[0] = 1.0;
-    tz.ridx.assign(2 * k + 1, 0);
-    tz.rw.assign(2 * k + 1, 0.0);
-    tz.rw[0] = 1.0;
-  }
-  std::vector<int> idx;
-  std::vector<double> w;
-  auto put = [&](const std::vector<int>& i, const std::vector<double>& v) {
-    const long long off = (long long)idx.size();
-    idx.insert(idx.end(), i.begin(), i.end());
-    w.insert(w.end(), v.begin(), v.end());
-    return off;
+  auto tx = [&](int ncc, bool periodic, int rwidth) {
+    return build_tx1d(kf, kc, ncc, refine, periodic, f->gll, c->gll, rwidth);
   };
-  X.pt = put(tt.pidx, tt.pw);
-  X.pr[0] = put(tr0.pidx, tr0.pw);
-  X.pr[1] = put(tr1.pidx, tr1.pw);
-  X.pz = put(tz.pidx, tz.pw);
-  X.rt = put(tt.ridx, tt.rw);
-  X.rr[0] = put(tr0.ridx, tr0.rw);
-  X.rr[1] = put(tr1.ridx, tr1.rw);
-  X.rz = put(tz.ridx, tz.rw);
-  int* di = nullptr;
-  double* dw = nullptr;
-  hipError_t e;
-  if ((e = hipMalloc((void**)&di, idx.size() * sizeof(int))) != hipSuccess ||
-      (e = hipMalloc((void**)&dw, w.size() * sizeof(double))) != hipSuccess ||
-      (e = hipMemcpy(di, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
-    *rc = mg_err(f, e, "multigrid tables");
+  // a first pass finds the widest restriction row of all directions
+  int rw = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    Tx1D tt = tx(c->desc.n_theta, true, rw), tr0 = tx(c->desc.n_r_rotor, false, rw),
+         tr1 = tx(c->desc.n_r_stator, false, rw);
+    Tx1D tz;
+    if (f->dim == 3) {
+      tz = tx(c->desc.n_z, false, rw);
+    } else {  // one node plane: identity
+      tz.pidx.assign(kc + 1, 0);
+      tz.pw.assign(kc + 1, 0.0);
+      tz.pw[0] = 1.0;
+      tz.eidx.assign(kf + 1, 0);
+      tz.ew.assign(kf + 1, 0.0);
+      tz.ew[0] = 1.0;
+      tz.rwidth = 1;
+      tz.ridx.assign(std::max(rw, 1), 0);
+      tz.rw.assign(std::max(rw, 1), 0.0);
+      tz.rw[0] = 1.0;
+    }
+    if (pass == 0) {
+      rw = std::max(std::max(tt.rwidth, tr0.rwidth), std::max(tr1.rwidth, tz.rwidth));
+      continue;
+    }
+    X.pw = kc + 1;
+    X.rw = rw;
+    X.ew = kf + 1;
+    std::vector<int> idx;
+    std::vector<double> w;
+    auto put = [&](const std::vector<int>& i, const std::vector<double>& v) {
+      const long long off = (long long)idx.size();
+      idx.insert(idx.end(), i.begin(), i.end());
+      w.insert(w.end(), v.begin(), v.end());
+      return off;
+    };
+    X.pt = put(tt.pidx, tt.pw);
+    X.pr[0] = put(tr0.pidx, tr0.pw);
+    X.pr[1] = put(tr1.pidx, tr1.pw);
+    X.pz = put(tz.pidx, tz.pw);
+    X.rt = put(tt.ridx, tt.rw);
+    X.rr[0] = put(tr0.ridx, tr0.rw);
+    X.rr[1] = put(tr1.ridx, tr1.rw);
+    X.rz = put(tz.ridx, tz.rw);
+    X.et = put(tt.eidx, tt.ew);
+    X.er[0] = put(tr0.eidx, tr0.ew);
+    X.er[1] = put(tr1.eidx, tr1.ew);
+    X.ez = put(tz.eidx, tz.ew);
+    int* di = nullptr;
+    double* dw = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc((void**)&di, idx.size() * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&dw, w.size() * sizeof(double))) != hipSuccess ||
+        (e = hipMemcpy(di, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+      *rc = mg_err(f, e, "multigrid tables");
+    }
+    keep.push_back(di);
+    keep.push_back(dw);
+    X.idx = di;
+    X.w = dw;
   }
-  keep.push_back(di);
-  keep.push_back(dw);
-  X.idx = di;
-  X.w = dw;
   return X;
 }
 
@@ -644,7 +712,7 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
     }
     mg_free(h);  // another level count was asked for
   }
-  if (h->k != 2) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs degree 2 (nested nodes)");
+  if (h->k != 2 && h->k != 3) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs degree 2 or 3");
   MG* mg = new MG();
   mg->max_levels = max_levels;
   h->mg = mg;
@@ -653,11 +721,18 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
   L0.n = h->ndofs;
   mg->L.push_back(L0);
   mns_mesh_desc d = h->desc;
-  while (can_halve(d) && (max_levels == 0 || (int)mg->L.size() < max_levels)) {
-    d.n_theta /= 2;
-    d.n_r_rotor /= 2;
-    d.n_r_stator /= 2;
-    if (d.dim == 3) d.n_z /= 2;
+  // degree 3: first a degree-2 level on the same mesh, then halved meshes
+  bool poly = d.degree == 3;
+  while ((poly || can_halve(d)) && (max_levels == 0 || (int)mg->L.size() < max_levels)) {
+    if (poly) {
+      d.degree = 2;
+      poly = false;
+    } else {
+      d.n_theta /= 2;
+      d.n_r_rotor /= 2;
+      d.n_r_stator /= 2;
+      if (d.dim == 3) d.n_z /= 2;
+    }
     mns_handle* hc = new mns_handle();
     int rc = mns_build_handle(&d, h->stream, hc);
     if (rc) {
@@ -678,9 +753,7 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
   hipError_t e;
   for (size_t l = 0; l < mg->L.size(); ++l) {
     MGLevel& Lv = mg->L[l];
-    if ((e = hipMalloc((void**)&Lv.b, 3 * (size_t)Lv.n * sizeof(float))) != hipSuccess) return mg_err(h, e, "hipMalloc mg");
-    Lv.x = Lv.b + Lv.n;
-    Lv.r = Lv.x + Lv.n;
+    if ((e = hipMalloc(&Lv.b, 3 * (size_t)Lv.n * sizeof(double))) != hipSuccess) return mg_err(h, e, "hipMalloc mg");
     if (l > 0 && (e = hipMalloc((void**)&Lv.inj, 3 * (size_t)Lv.n * sizeof(double))) != hipSuccess)
       return mg_err(h, e, "hipMalloc mg");
   }
@@ -702,7 +775,7 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
     const double* fsrc[3] = {hf->d_state, hf->d_hist, hf->d_force};
     double* cdst[3] = {Lv.inj, Lv.inj + Lv.n, Lv.inj + 2 * Lv.n};
     for (int i = 0; i < 3; ++i)
-      if (fsrc[i]) hipLaunchKernelGGL(k_mg_inject, dim3(g), dim3(256), 0, s, X, fsrc[i], cdst[i], nnc);
+      if (fsrc[i]) hipLaunchKernelGGL(k_mg_eval, dim3(g), dim3(256), 0, s, X, fsrc[i], cdst[i], nnc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mg_err(h, e, "injection");
     if ((rc = mns_rotate_rotor(hc, h->theta, h->omega))) return set_error(h, rc, "coarse rotate: " + hc->err);
@@ -726,56 +799,102 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
 }
 
 // x = Chebyshev smoothing of J x = b at level l (from x = 0 when zero)
-static int mg_smooth(MG* mg, size_t l, const float* b, float* x, bool zero, int deg, double range, hipStream_t s) {
+// FP32 or FP64 views of a level's work vectors and its Chebyshev buffers
+template <typename Real>
+struct MGVec {
+  Real *b, *x, *r;           // V-cycle vectors of the level
+  Real *cr, *cd, *ct, *cx;   // Chebyshev buffers of the level's solver workspace
+  const Real* diag;
+};
+
+template <typename Real>
+static MGVec<Real> mg_vec(MGLevel& Lv, const Solver& S) {
+  MGVec<Real> v;
+  Real* base = (Real*)Lv.b;
+  v.b = base;
+  v.x = base + Lv.n;
+  v.r = base + 2 * Lv.n;
+  if constexpr (sizeof(Real) == 4) {
+    v.cr = S.r32;
+    v.cd = S.d32;
+    v.ct = S.t32;
+    v.cx = S.x32;
+    v.diag = Lv.h->d_diag32;
+  } else {
+    v.cr = S.r64c;
+    v.cd = S.d64c;
+    v.ct = S.t64b;
+    v.cx = S.d64c + Lv.n;  // the spare vector after the Chebyshev buffers
+    v.diag = Lv.h->d_diag64;
+  }
+  return v;
+}
+
+// x = Chebyshev smoothing of J x = b at level l (from x = 0 when zero)
+template <typename Real>
+static int mg_smooth(MG* mg, size_t l, const Real* b, Real* x, bool zero, int deg, double range, hipStream_t s) {
   MGLevel& Lv = mg->L[l];
   mns_handle* hl = Lv.h;
   Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+  MGVec<Real> v = mg_vec<Real>(Lv, S);
   const unsigned g = grid_for(Lv.n);
-  if (zero) return S.chebyshev<float>(b, x, S.r32, S.d32, S.t32, hl->d_diag32, deg, Lv.lmax, range);
-  int rc = launch_jacobian<float>(hl, x, S.t32, s);
+  if (zero) return S.chebyshev<Real>(b, x, v.cr, v.cd, v.ct, v.diag, deg, Lv.lmax, range);
+  int rc = launch_jacobian<Real>(hl, x, v.ct, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, b, -1.0f, (const float*)S.t32, Lv.r, Lv.n);
-  if ((rc = S.chebyshev<float>(Lv.r, S.x32, S.r32, S.d32, S.t32, hl->d_diag32, deg, Lv.lmax, range))) return rc;
-  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, (const float*)x, 1.0f, (const float*)S.x32, x, Lv.n);
+  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, b, Real(-1), (const Real*)v.ct, v.r, Lv.n);
+  if ((rc = S.chebyshev<Real>(v.r, v.cx, v.cr, v.cd, v.ct, v.diag, deg, Lv.lmax, range))) return rc;
+  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)x, Real(1), (const Real*)v.cx, x, Lv.n);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 
+template <typename Real>
 static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   MGLevel& Lv = mg->L[l];
   mns_handle* hl = Lv.h;
-  int rc;
-  if (l + 1 == mg->L.size()) return mg_smooth(mg, l, Lv.b, Lv.x, true, o->mg_coarse_degree, o->mg_smooth_range, s);
-  if ((rc = mg_smooth(mg, l, Lv.b, Lv.x, true, o->mg_smooth_degree, o->mg_smooth_range, s))) return rc;
-  // residual, restricted with constrained rows zero on both levels
   Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
-  if ((rc = launch_jacobian<float>(hl, Lv.x, S.t32, s))) return rc;
+  MGVec<Real> v = mg_vec<Real>(Lv, S);
+  int rc;
+  if (l + 1 == mg->L.size()) return mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_coarse_degree, o->mg_smooth_range, s);
+  if ((rc = mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_smooth_degree, o->mg_smooth_range, s))) return rc;
+  // residual, restricted with constrained rows zero on both levels
+  if ((rc = launch_jacobian<Real>(hl, v.x, v.ct, s))) return rc;
   const unsigned g = grid_for(Lv.n);
-  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, (const float*)Lv.b, -1.0f, (const float*)S.t32, Lv.r,
+  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.b, Real(-1), (const Real*)v.ct, v.r,
                      Lv.n);
-  if ((rc = launch_constraints<float>(hl, Lv.r, Lv.r, 0.0f, 1, s))) return rc;
+  if ((rc = launch_constraints<Real>(hl, v.r, v.r, Real(0), 1, s))) return rc;
   MGLevel& Lc = mg->L[l + 1];
+  Solver Sc = make_solver(Lc.h, s, 1);
+  MGVec<Real> vc = mg_vec<Real>(Lc, Sc);
   const TxView& X = mg->T[l];
-  hipLaunchKernelGGL(k_mg_restrict<float>, dim3((unsigned)((Lc.h->nnodes + 255) / 256)), dim3(256), 0, s, X,
-                     (const float*)Lv.r, Lc.b, (long long)Lc.h->nnodes);
-  if ((rc = launch_constraints<float>(Lc.h, Lc.b, Lc.b, 0.0f, 1, s))) return rc;
-  if ((rc = mg_cycle(mg, l + 1, o, s))) return rc;
+  hipLaunchKernelGGL(k_mg_restrict<Real>, dim3((unsigned)((Lc.h->nnodes + 255) / 256)), dim3(256), 0, s, X,
+                     (const Real*)v.r, vc.b, (long long)Lc.h->nnodes);
+  if ((rc = launch_constraints<Real>(Lc.h, vc.b, vc.b, Real(0), 1, s))) return rc;
+  if ((rc = mg_cycle<Real>(mg, l + 1, o, s))) return rc;
   // x += P x_c (constrained rows of the correction zero)
-  hipLaunchKernelGGL(k_mg_prolong<float>, dim3((unsigned)((hl->nnodes + 255) / 256)), dim3(256), 0, s, X,
-                     (const float*)Lc.x, Lv.r, (long long)hl->nnodes, 0);
-  if ((rc = launch_constraints<float>(hl, Lv.r, Lv.r, 0.0f, 1, s))) return rc;
-  hipLaunchKernelGGL(k_mg_axpy<float>, dim3(g), dim3(256), 0, s, (const float*)Lv.x, 1.0f, (const float*)Lv.r, Lv.x,
+  hipLaunchKernelGGL(k_mg_prolong<Real>, dim3((unsigned)((hl->nnodes + 255) / 256)), dim3(256), 0, s, X,
+                     (const Real*)vc.x, v.r, (long long)hl->nnodes, 0);
+  if ((rc = launch_constraints<Real>(hl, v.r, v.r, Real(0), 1, s))) return rc;
+  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.x, Real(1), (const Real*)v.r, v.x,
                      Lv.n);
   if (hipGetLastError() != hipSuccess) return set_error(mg->L[0].h, MNS_ERR_HIP, "multigrid kernels");
-  return mg_smooth(mg, l, Lv.b, Lv.x, false, o->mg_smooth_degree, o->mg_smooth_range, s);
+  return mg_smooth<Real>(mg, l, v.b, v.x, false, o->mg_smooth_degree, o->mg_smooth_range, s);
 }
 
 int mg_vcycle(MG* mg, const mns_solve_opts* o, const double* v, double* z, hipStream_t s) {
   MGLevel& L0 = mg->L[0];
   const unsigned g = grid_for(L0.n);
-  hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, L0.b, L0.n);
-  int rc = mg_cycle(mg, 0, o, s);
-  if (rc) return rc;
-  hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const float*)L0.x, z, L0.n);
+  int rc;
+  if (o->precond == MNS_PRECOND_MG64) {
+    double* b = (double*)L0.b;
+    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, b, L0.n);
+    if ((rc = mg_cycle<double>(mg, 0, o, s))) return rc;
+    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, (const double*)(b + L0.n), 1.0, z, L0.n);
+  } else {
+    float* b = (float*)L0.b;
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, b, L0.n);
+    if ((rc = mg_cycle<float>(mg, 0, o, s))) return rc;
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const float*)(b + L0.n), z, L0.n);
+  }
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 
@@ -791,7 +910,7 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
   const size_t n = (size_t)h->ndofs;
 
   double lmax = 0;
-  if (o->precond == MNS_PRECOND_MG) {
+  if (o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64) {
     MG* mg = nullptr;
     if ((rc = mg_build(h, o->mg_levels, &mg))) return rc;
     if ((rc = mg_setup(h, mg, o, s))) return rc;

@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--workload", default="annulus3d_q2_64x8x32")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--fused", type=int, default=1)
+    ap.add_argument("--fused", type=int, default=-1)
     ap.add_argument("--volume-layout", type=int, default=1)
     ap.add_argument("--summarize", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
     args = ap.parse_args()

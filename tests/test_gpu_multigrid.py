@@ -28,6 +28,9 @@ def _dev(a):
 
 def _halved(mesh):
     c = dict(mesh)
+    if mesh["degree"] == 3:  # polynomial level: same mesh, degree 2
+        c["degree"] = 2
+        return c
     for key in ("n_theta", "n_r_rotor", "n_r_stator"):
         c[key] //= 2
     if mesh["dim"] == 3:
@@ -52,9 +55,11 @@ def _field(mesh, coarse_mesh, xyz):
     return g * (1.0 + r * r + 3.0 * z * z - r * z + 0.5 * z)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_prolongation_reproduces_coarse_q2_fields(dim):
-    mesh = small_mesh(dim, 2, n_theta=16, n_r_rotor=2, n_r_stator=4, n_z=4)
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (2, 3), (3, 3)])
+def test_prolongation_reproduces_coarse_q2_fields(dim, k):
+    """Degree 2: coarse mesh with halved cell counts; degree 3: the degree-2
+    space on the same mesh (polynomial level)."""
+    mesh = small_mesh(dim, k, n_theta=16, n_r_rotor=2, n_r_stator=4, n_z=4)
     coarse = _halved(mesh)
     nc = dim + 1
     with binding.Operator(mesh) as op:
@@ -69,14 +74,15 @@ def test_prolongation_reproduces_coarse_q2_fields(dim):
         y = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
         op.mg_prolongate(0, _dev(xc.ravel()), y)
         err = relmax(y.cpu().numpy(), yf.ravel())
-    print(f"dim={dim}: prolongation error {err:.2e}")
+    print(f"dim={dim} k={k}: prolongation error {err:.2e}")
     assert err < 1e-13
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_multigrid_solve_matches_direct_solve(dim):
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3)])
+def test_multigrid_solve_matches_direct_solve(dim, k):
     """Transient operator (the V-cycle's target) at a smooth state."""
-    mesh = small_mesh(dim, 2, n_theta=16, n_r_rotor=4, n_r_stator=4, n_z=4, steady=0, dt=0.02, nu=0.005)
+    mesh = small_mesh(dim, k, n_theta=16, n_r_rotor=4, n_r_stator=4, n_z=4 if k == 2 else 2, steady=0, dt=0.02,
+                      nu=0.005)
     n = inputs.n_dofs(mesh)
     g = np.random.default_rng(500 + dim)
     state = inputs.transient_start(mesh, 600 + dim)
@@ -92,11 +98,15 @@ def test_multigrid_solve_matches_direct_solve(dim):
         x = torch.zeros(n, dtype=torch.float64, device="cuda")
         _, rep = op.solve(_dev(b), x, rtol=1e-11, restart=100, maxit=2000, precond="mg")
         xg = x.cpu().numpy()
+        x2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        _, rep2 = op.solve(_dev(b), x2, rtol=1e-11, restart=100, maxit=2000, precond="mg64")
+        x2g = x2.cpu().numpy()
         x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
         _, rep1 = op.solve(_dev(b), x1, check=False, rtol=1e-11, restart=100, maxit=2000, precond="f32",
                            cheb_degree=6)
     err = relmax(xg, xo)
-    print(f"dim={dim}: levels {levels}, V-cycle its {rep['iterations']}, "
+    assert relmax(x2g, xo) < 1e-8
+    print(f"dim={dim} k={k}: levels {levels}, V-cycle its {rep['iterations']} (FP64 smoothing {rep2['iterations']}), "
           f"single-level its {rep1['iterations']} (rc {rep1['rc']}), |x - x_direct| / |x| = {err:.2e}")
     assert levels >= 2
     assert err < 1e-8
