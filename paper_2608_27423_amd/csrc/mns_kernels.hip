@@ -1553,19 +1553,22 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
 template <typename Real, int DIM, int N>
 __global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                      const Real* __restrict__ lin, Real* __restrict__ diag) {
+  // one thread per (cell, node): the basis function, its physical derivatives
+  // and the point data are shared by the node's d + 1 components
   using S = Shape<Real, DIM, N>;
   using LL = LinLayout<DIM>;
   constexpr int NZ = S::NZ, NC = S::NC;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)G.ncells * S::NPT * NC;
+  const long long total = (long long)G.ncells * S::NPT;
   if (gid >= total) return;
-  const int comp = gid % NC;
-  const int node = (gid / NC) % S::NPT;
-  const int cell = gid / (NC * S::NPT);
+  const int node = gid % S::NPT;
+  const int cell = gid / S::NPT;
   const int a0 = node % N, a1 = (node / N) % N, a2 = node / S::PLANE;
   const CellId C = decode_cell(G, cell);
   const Real nu = G.nu, ct = G.ct;
-  Real acc = 0;
+  Real acc[NC];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) acc[m] = 0;
   for (int q = 0; q < NZ; ++q)
     for (int qj = 0; qj < N; ++qj)
       for (int qi = 0; qi < N; ++qi) {
@@ -1594,21 +1597,21 @@ __global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N
           adg += lp[LL::A + e] * gphi[e];
           g2 += gphi[e] * gphi[e];
         }
-        Real val;
-        if (comp < DIM) {
+#pragma unroll
+        for (int comp = 0; comp < DIM; ++comp) {
           // trial phi e_c tested with phi e_c (Sec. 2.3, A-hat diagonal)
           const Real guc = lp[LL::GU + comp * DIM + comp];
           const Real Rpc = (ct + guc) * phi + adg - nu * lphi;
-          val = phi * phi * (ct + guc) + phi * adg + nu * g2 + tau * Rpc * adg + lp[LL::TR + comp] * phi * gphi[comp];
-        } else {
-          // D-hat diagonal: tau |grad psi|^2
-          val = tau * g2;
+          acc[comp] += g.jxw * (phi * phi * (ct + guc) + phi * adg + nu * g2 + tau * Rpc * adg +
+                                lp[LL::TR + comp] * phi * gphi[comp]);
         }
-        acc += g.jxw * val;
+        // D-hat diagonal: tau |grad psi|^2
+        acc[DIM] += g.jxw * tau * g2;
       }
   int it, ir, iz;
   const long long nd = node_of<Real, DIM>(G, k, C, a0, a1, a2, it, ir, iz);
-  atomic_add(diag + nd * NC + comp, acc);
+#pragma unroll
+  for (int m = 0; m < NC; ++m) atomic_add(diag + nd * NC + m, acc[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2290,7 +2293,7 @@ static int do_diag(mns_handle* h, Real* diag, hipStream_t s) {
   const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
   int rc = launch_fill<Real>(diag, Real(0), h->ndofs, s);
   if (rc) return set_error(h, rc, "fill");
-  const long long total = (long long)G.ncells * S::NPT * S::NC;
+  const long long total = (long long)G.ncells * S::NPT;
   hipLaunchKernelGGL((k_diag_volume<Real, DIM, N>), dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, G, T,
                      h->k, lin, diag);
   rc = hip_check(h, "diagonal kernel");
