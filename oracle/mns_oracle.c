@@ -14,7 +14,10 @@
  *   - SUPG/PSPG stabilization and Tezduyar tau: Sec. 2.2, Eqs.
  *     Eq-NSweakComplete, Eq-strong-residual, Eq-stab-param;
  *   - Newton Jacobian blocks: Sec. 2.3, Eqs. Eq-Newton-method, Eq-Newton-matrix
- *     and the stabilized/Galerkin block definitions (Eq-discrete-1..4);
+ *     and the stabilized/Galerkin block definitions (Eq-discrete-1..4); as an
+ *     option (picard = 1) the same blocks with the derivative of the
+ *     convection velocity and of the SUPG weight left out (the Oseen operator
+ *     that the multigrid preconditioner approximates);
  *   - rigid rotor rotation x = R x0: Sec. 3.1;
  *   - mortar segments with one reference quadrature mapped into each segment and
  *     det J = R * (segment angle) * (layer height): Sec. 3.2, Eq. Eq-Jacobian;
@@ -65,6 +68,10 @@ typedef struct {
   int pin_pressure;  /* 1: pin one pressure DoF */
   int mms;           /* 1: analytic forcing of the 2D manufactured solution */
   int nthreads;
+  int picard;        /* 1: Jacobian of the Picard (Oseen) linearization: the
+                        convection velocity and the SUPG weight are frozen at
+                        the state, so the reaction term (du . grad) u and the
+                        SUPG weight derivative are absent */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -638,9 +645,12 @@ static void pw_jacobian(const mesh_t *M, const field_t *S, const double hist[3],
       reac += S->gu[m][e] * T->u[e];
       conv += T->gu[m][e] * a[e];
     }
+    if (M->P.picard) reac = 0.0;
     C->gv[m] = ct * T->u[m] + reac + conv;
     Rp[m] = ct * T->u[m] + reac + conv - nu * T->lu[m] + T->gp[m];
   }
+  if (M->P.picard)
+    for (int m = 0; m < d; ++m) R[m] = 0.0; /* no SUPG weight derivative */
   for (int m = 0; m < d; ++m)
     for (int e = 0; e < d; ++e) {
       C->Gv[m][e] = nu * T->gu[m][e] - (m == e ? T->p : 0.0);

@@ -82,6 +82,14 @@ MUTANTS = [
      "C->gq = -0.5 * jn;",
      "C->gq = -jn;",
      [(pins.test_galerkin_saddle_structure, dict(dim=2))]),
+    ("Picard option keeping the reaction term",
+     "    if (M->P.picard) reac = 0.0;\n",
+     "\n",
+     [(pins.test_picard_jacobian_applied_to_state_is_residual, dict(dim=2, steady=1))]),
+    ("Picard option keeping the SUPG weight derivative",
+     "for (int m = 0; m < d; ++m) R[m] = 0.0; /* no SUPG weight derivative */",
+     "(void)0;",
+     [(pins.test_picard_jacobian_applied_to_state_is_residual, dict(dim=2, steady=1))]),
     ("mortar pressure average taken from the own side only",
      "double pbar = 0.5 * (Fs->p + Fo->p);",
      "double pbar = Fs->p;",

@@ -364,6 +364,28 @@ def test_jacobian_is_derivative_of_residual(dim, steady):
     assert errs[0] / errs[1] > 60  # O(eps^2)
 
 
+@pytest.mark.parametrize("dim,steady", [(2, 1), (2, 0), (3, 1)])
+def test_picard_jacobian_applied_to_state_is_residual(dim, steady):
+    """Picard (Oseen) option: every term of the residual is linear in u once the
+    convection velocity u - u_ALE and the SUPG weight are frozen, so with no
+    history and no forcing J_picard(u) u = R(u) (tau frozen at u).  The Newton
+    Jacobian differs by the reaction term (du . grad) u and the SUPG weight
+    derivative, which are nonzero here."""
+    cfg = _cfg(dim=dim, steady=steady, dt=0.05, theta_rot=0.9)
+    n = oracle.n_dofs(cfg)
+    u = np.random.default_rng(11).uniform(-1, 1, n)
+    u[oracle.constrained(cfg)] = 0
+    r = oracle.residual(cfg, u)
+    yp = oracle.apply_jacobian(dict(cfg, picard=1), u, u)
+    yn = oracle.apply_jacobian(cfg, u, u)
+    assert np.abs(r).max() > 1e-2
+    assert np.abs(yp - r).max() < 1e-13 * np.abs(r).max()
+    assert np.abs(yn - r).max() > 1e-2 * np.abs(r).max()
+    # at u = 0 (convection by -u_ALE only) both linearizations coincide
+    z = np.zeros(n)
+    assert np.array_equal(oracle.apply_jacobian(dict(cfg, picard=1), z, u), oracle.apply_jacobian(cfg, z, u))
+
+
 # ------------------------------------------------------ exact invariants --
 
 @pytest.mark.parametrize("dim", [2, 3])
