@@ -65,6 +65,8 @@ enum {
 enum { MNS_F64 = 0, MNS_F32 = 1 };
 /* preconditioner choice of mns_solve_opts.precond besides -1 / MNS_F64 / MNS_F32 */
 enum { MNS_PRECOND_MG = 2, MNS_PRECOND_MG64 = 3 };
+/* linearization kind (mns_set_linearization_kind, mns_solve_opts.mg_coarse_linearization) */
+enum { MNS_LIN_NEWTON = 0, MNS_LIN_PICARD = 1 };
 
 typedef struct mns_handle mns_handle;
 
@@ -114,6 +116,18 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega);
 int mns_set_linearization(mns_handle* h, const double* state, const double* u_hist, const double* force,
                           void* stream);
 
+/* Kind of the linearization that the next mns_set_linearization builds.
+ * MNS_LIN_NEWTON (default): the Newton Jacobian of Sec. 2.3.  MNS_LIN_PICARD:
+ * the Picard (Oseen) operator of the same residual, i.e. the Newton blocks
+ * without the derivative of the convection velocity (the reaction term
+ * (du . grad) u) and without the derivative of the SUPG weight (tau R . (du .
+ * grad) v); a = u - u_ALE, tau_u and the mortar terms are unchanged.  With no
+ * history and no force, J_picard(u) u equals the residual R(u).  The multigrid
+ * preconditioner may linearize its coarse levels this way
+ * (mns_solve_opts.mg_coarse_linearization).
+ * Errors: INVALID_ARG (unknown kind). */
+int mns_set_linearization_kind(mns_handle* h, int kind);
+
 /* dst = J src: the stabilized Jacobian of Sec. 2.3 with the mortar face terms
  * of Sec. 2.1 at the current angle and linearization.  Constrained columns
  * read as zero; constrained rows give dst = src.  precision MNS_F64: src and
@@ -146,6 +160,10 @@ typedef struct {
   int mg_smooth_degree;     /* V-cycle: Chebyshev smoothing degree before and after the correction (default 2) */
   double mg_smooth_range;   /* V-cycle: smoothing interval [lambda_max / range, lambda_max] (default 5) */
   int mg_coarse_degree;     /* V-cycle: Chebyshev degree on the coarsest level (default 16) */
+  int mg_coarse_linearization; /* V-cycle: MNS_LIN_NEWTON (default) or MNS_LIN_PICARD for levels 1, 2, ... */
+  int mg_fine_linearization;   /* V-cycle on the mesh's own level: MNS_LIN_NEWTON (default) smooths with the
+                                  handle's operator; MNS_LIN_PICARD with a Picard copy of it at the same state
+                                  (one more set of per-point data).  FGMRES always applies the handle's operator */
 } mns_solve_opts;
 
 typedef struct {
@@ -168,7 +186,9 @@ void mns_default_solve_opts(mns_solve_opts* opts);
  * (nested polar meshes: every coarse cell is 2 x 2 (x 2) fine cells of the
  * same map).  On every level:
  * the operator of mns_apply_jacobian with mortar faces at the same rotor
- * angle, linearized at the finest state evaluated at the level's nodes; FP32 Jacobi-Chebyshev smoothing of degree
+ * angle, linearized at the finest state evaluated at the level's nodes (Newton
+ * or, with mg_coarse_linearization = MNS_LIN_PICARD, Picard on the coarse
+ * levels); FP32 Jacobi-Chebyshev smoothing of degree
  * mg_smooth_degree on [lambda_max / mg_smooth_range, lambda_max] of D^-1 J
  * before and after the coarse correction; Chebyshev of degree
  * mg_coarse_degree on the coarsest level.  Transfers: prolongation = the

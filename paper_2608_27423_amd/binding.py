@@ -23,12 +23,15 @@ MNS_F32 = 1
 MNS_PRECOND_MG = 2
 MNS_PRECOND_MG64 = 3
 _PRECOND = {"none": -1, "f64": MNS_F64, "f32": MNS_F32, "mg": MNS_PRECOND_MG, "mg64": MNS_PRECOND_MG64}
+MNS_LIN_NEWTON = 0
+MNS_LIN_PICARD = 1
+_LIN = {"newton": MNS_LIN_NEWTON, "picard": MNS_LIN_PICARD}
 
 EXPORTED = [
     "mns_setup_mesh", "mns_n_dofs", "mns_rotate_rotor", "mns_set_linearization", "mns_apply_jacobian",
     "mns_apply_residual", "mns_compute_diagonal", "mns_default_solve_opts", "mns_solve", "mns_enable_timing",
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
-    "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate",
+    "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
 ]
 
 
@@ -48,7 +51,8 @@ class SolveOpts(ctypes.Structure):
         ("rtol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
         ("cheb_degree", ctypes.c_int), ("cheb_range", ctypes.c_double), ("eig_iters", ctypes.c_int),
         ("mg_levels", ctypes.c_int), ("mg_smooth_degree", ctypes.c_int), ("mg_smooth_range", ctypes.c_double),
-        ("mg_coarse_degree", ctypes.c_int),
+        ("mg_coarse_degree", ctypes.c_int), ("mg_coarse_linearization", ctypes.c_int),
+        ("mg_fine_linearization", ctypes.c_int),
     ]
 
 
@@ -110,6 +114,7 @@ def lib():
         L.mns_n_dofs.argtypes = [vp, i64p, i64p]
         L.mns_rotate_rotor.argtypes = [vp, ctypes.c_double, ctypes.c_double]
         L.mns_set_linearization.argtypes = [vp, vp, vp, vp, vp]
+        L.mns_set_linearization_kind.argtypes = [vp, ctypes.c_int]
         L.mns_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_residual.argtypes = [vp, vp, vp, vp]
         L.mns_compute_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
@@ -196,7 +201,10 @@ class Operator:
     def rotate_rotor(self, theta, omega):
         return self._check(self._L.mns_rotate_rotor(self._h, float(theta), float(omega)))
 
-    def set_linearization(self, state, hist=None, force=None):
+    def set_linearization(self, state, hist=None, force=None, kind=None):
+        """kind: None (keep), "newton" or "picard" (mns_set_linearization_kind)."""
+        if kind is not None:
+            self._check(self._L.mns_set_linearization_kind(self._h, _LIN[kind] if isinstance(kind, str) else kind))
         self._keep = (state, hist, force)
         return self._check(self._L.mns_set_linearization(self._h, _ptr(state), _ptr(hist), _ptr(force), _stream()))
 
@@ -247,6 +255,8 @@ class Operator:
         for k, v in opts.items():
             if k == "precond" and isinstance(v, str):
                 v = _PRECOND[v]
+            if k in ("mg_coarse_linearization", "mg_fine_linearization") and isinstance(v, str):
+                v = _LIN[v]
             setattr(o, k, v)
         if x is None:
             x = torch.zeros_like(rhs)
@@ -268,6 +278,8 @@ class Operator:
         for k2, v in (linear or {}).items():
             if k2 == "precond" and isinstance(v, str):
                 v = _PRECOND[v]
+            if k2 in ("mg_coarse_linearization", "mg_fine_linearization") and isinstance(v, str):
+                v = _LIN[v]
             setattr(o.linear, k2, v)
         for t in (u_n, u_next, u_nm1, force):
             if t is not None and (t.numel() != self.n_dofs or t.dtype.itemsize != 8):

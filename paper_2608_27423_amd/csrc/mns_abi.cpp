@@ -115,6 +115,14 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega) {
   return rc;
 }
 
+int mns_set_linearization_kind(mns_handle* h, int kind) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (kind != MNS_LIN_NEWTON && kind != MNS_LIN_PICARD)
+    return set_error(h, MNS_ERR_INVALID_ARG, "kind must be MNS_LIN_NEWTON or MNS_LIN_PICARD");
+  h->picard = kind == MNS_LIN_PICARD;
+  return MNS_OK;
+}
+
 int mns_set_linearization(mns_handle* h, const double* state, const double* u_hist, const double* force,
                           void* stream) {
   if (!h) return MNS_ERR_INVALID_ARG;
@@ -224,6 +232,8 @@ void mns_default_solve_opts(mns_solve_opts* o) {
   o->mg_smooth_degree = 2;
   o->mg_smooth_range = 5.0;
   o->mg_coarse_degree = 16;
+  o->mg_coarse_linearization = MNS_LIN_NEWTON;
+  o->mg_fine_linearization = MNS_LIN_NEWTON;
 }
 
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
@@ -240,7 +250,9 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
       (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32 && o.precond != MNS_PRECOND_MG &&
        o.precond != MNS_PRECOND_MG64) ||
       o.mg_levels < 0 || o.mg_levels > 16 || o.mg_coarse_degree < 1 || o.mg_coarse_degree > 1000 ||
-      o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1))
+      o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1) ||
+      (o.mg_coarse_linearization != MNS_LIN_NEWTON && o.mg_coarse_linearization != MNS_LIN_PICARD) ||
+      (o.mg_fine_linearization != MNS_LIN_NEWTON && o.mg_fine_linearization != MNS_LIN_PICARD))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
   mns_solve_report rep{};
   int rc;

@@ -139,6 +139,7 @@ struct mns_handle {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // volume layout: 1 = lane quad per cell (3D, degree <= 3), 0 = LDS planes
   int quad = 1;
+  int picard = 0;               // linearization kind of the next mns_set_linearization (MNS_LIN_*)
   hipStream_t stream = nullptr;
   std::string err;
   // optional kernel timing (mns_enable_timing): event pairs per kernel class

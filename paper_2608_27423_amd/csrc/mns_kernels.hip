@@ -1388,7 +1388,7 @@ template <int DIM, int N, bool RES>
 __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T, int k,
                                               const double* __restrict__ state, const double* __restrict__ hist,
                                               const double* __restrict__ force, double* __restrict__ lin,
-                                              double* __restrict__ res) {
+                                              double* __restrict__ res, int picard) {
   using Real = double;
   using S = Shape<Real, DIM, N>;
   using LL = LinLayout<DIM>;
@@ -1507,10 +1507,12 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
         double* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + tb * N + ta) * LL::SIZE;
 #pragma unroll
         for (int m = 0; m < DIM; ++m) {
+          // Picard (Oseen) linearization: no reaction term (zero velocity
+          // gradient) and no SUPG weight derivative (zero tau R)
           lp[LL::A + m] = a[m];
-          lp[LL::TR + m] = tau * R[m];
+          lp[LL::TR + m] = picard ? 0.0 : tau * R[m];
 #pragma unroll
-          for (int e = 0; e < DIM; ++e) lp[LL::GU + m * DIM + e] = gu[m][e];
+          for (int e = 0; e < DIM; ++e) lp[LL::GU + m * DIM + e] = picard ? 0.0 : gu[m][e];
         }
         lp[LL::TAU] = tau;
       } else {
@@ -2261,7 +2263,7 @@ static int do_state(mns_handle* h, const double* state, const double* hist, cons
   const Tab1D<double, N> T = make_tab<double, N>(h);
   const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
   hipLaunchKernelGGL((k_state<DIM, N, RES>), dim3(blocks), dim3(64), 0, s, G, T, h->k, state, hist, force, lin,
-                     res);
+                     res, RES ? 0 : h->picard);
   return hip_check(h, RES ? "residual kernel" : "linearization kernel");
 }
 

@@ -595,6 +595,11 @@ __global__ void k_mg_axpy(const Real* __restrict__ a, Real beta, const Real* __r
     out[i] = a[i] + beta * b[i];
 }
 
+// restart length of a level's workspace: the caller's handle keeps its Krylov
+// workspace, every other level (including a Picard copy of level 0) has
+// restart 1, which holds the Chebyshev buffers
+static int ws_of(mns_handle* hl, size_t l) { return (l == 0 && hl->ws_restart > 1) ? hl->ws_restart : 1; }
+
 struct MGLevel {
   mns_handle* h = nullptr;  // level 0: the caller's handle (not owned)
   long long n = 0;
@@ -609,6 +614,9 @@ struct MG {
   std::vector<void*> tables;    // device allocations of the tables
   long long version = -1;
   int max_levels = 0;           // level limit the hierarchy was built with
+  int coarse_lin = -1;          // linearization kind of the coarse levels at the last setup
+  int fine_lin = -1;            // and of the mesh's own level
+  mns_handle* fine = nullptr;   // Picard copy of the mesh's own level (owned; level 0 when in use)
 };
 
 static int mg_err(mns_handle* h, hipError_t e, const char* what) {
@@ -763,8 +771,33 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
 
 // coarse operators at the current angle and state, diagonals and spectra
 static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t s) {
-  if (mg->version == h->lin_version) return MNS_OK;
+  if (mg->version == h->lin_version && mg->coarse_lin == o->mg_coarse_linearization &&
+      mg->fine_lin == o->mg_fine_linearization)
+    return MNS_OK;
   int rc;
+  // level 0: the caller's handle, or a copy of its mesh with the Picard
+  // linearization at the same state (the outer FGMRES keeps the caller's)
+  if (o->mg_fine_linearization == MNS_LIN_PICARD) {
+    if (!mg->fine) {
+      mns_handle* hf = new mns_handle();
+      if ((rc = mns_build_handle(&h->desc, h->stream, hf))) {
+        const std::string msg = hf->err;
+        mns_destroy(hf);
+        return set_error(h, rc, "multigrid fine copy: " + msg);
+      }
+      mg->fine = hf;
+    }
+    mns_handle* hf = mg->fine;
+    hf->fused = h->fused;
+    hf->quad = h->quad;
+    if ((rc = mns_rotate_rotor(hf, h->theta, h->omega))) return set_error(h, rc, "fine copy rotate: " + hf->err);
+    hf->picard = 1;
+    if ((rc = mns_set_linearization(hf, h->d_state, h->d_hist, h->d_force, s)))
+      return set_error(h, rc, "fine copy linearization: " + hf->err);
+    mg->L[0].h = hf;
+  } else {
+    mg->L[0].h = h;
+  }
   for (size_t l = 1; l < mg->L.size(); ++l) {
     MGLevel& Lv = mg->L[l];
     mns_handle* hc = Lv.h;
@@ -779,22 +812,25 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mg_err(h, e, "injection");
     if ((rc = mns_rotate_rotor(hc, h->theta, h->omega))) return set_error(h, rc, "coarse rotate: " + hc->err);
+    hc->picard = o->mg_coarse_linearization == MNS_LIN_PICARD;
     if ((rc = mns_set_linearization(hc, cdst[0], fsrc[1] ? cdst[1] : nullptr, fsrc[2] ? cdst[2] : nullptr, s)))
       return set_error(h, rc, "coarse linearization: " + hc->err);
   }
   for (size_t l = 0; l < mg->L.size(); ++l) {
     MGLevel& Lv = mg->L[l];
     mns_handle* hl = Lv.h;
-    if ((rc = ensure_workspace(hl, l == 0 ? hl->ws_restart : 1))) return l ? set_error(h, rc, hl->err) : rc;
+    if ((rc = ensure_workspace(hl, ws_of(hl, l)))) return l ? set_error(h, rc, hl->err) : rc;
     if (!hl->diag_valid) {
       if ((rc = launch_diagonal<double>(hl, hl->d_diag64, s))) return set_error(h, rc, "diagonal: " + hl->err);
       if ((rc = launch_cast_f64_f32(hl->d_diag64, hl->d_diag32, (int64_t)hl->ndofs, s))) return set_error(h, rc, "cast");
       hl->diag_valid = true;
     }
-    Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+    Solver S = make_solver(hl, s, ws_of(hl, l));
     if ((rc = S.estimate_lambda(o->eig_iters, &Lv.lmax))) return l ? set_error(h, rc, hl->err) : rc;
   }
   mg->version = h->lin_version;
+  mg->coarse_lin = o->mg_coarse_linearization;
+  mg->fine_lin = o->mg_fine_linearization;
   return MNS_OK;
 }
 
@@ -835,7 +871,7 @@ template <typename Real>
 static int mg_smooth(MG* mg, size_t l, const Real* b, Real* x, bool zero, int deg, double range, hipStream_t s) {
   MGLevel& Lv = mg->L[l];
   mns_handle* hl = Lv.h;
-  Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+  Solver S = make_solver(hl, s, ws_of(hl, l));
   MGVec<Real> v = mg_vec<Real>(Lv, S);
   const unsigned g = grid_for(Lv.n);
   if (zero) return S.chebyshev<Real>(b, x, v.cr, v.cd, v.ct, v.diag, deg, Lv.lmax, range);
@@ -851,7 +887,7 @@ template <typename Real>
 static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   MGLevel& Lv = mg->L[l];
   mns_handle* hl = Lv.h;
-  Solver S = make_solver(hl, s, l == 0 ? hl->ws_restart : 1);
+  Solver S = make_solver(hl, s, ws_of(hl, l));
   MGVec<Real> v = mg_vec<Real>(Lv, S);
   int rc;
   if (l + 1 == mg->L.size()) return mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_coarse_degree, o->mg_smooth_range, s);
@@ -1038,6 +1074,7 @@ void mg_free(mns_handle* h) {
     if (Lv.inj) (void)hipFree(Lv.inj);
     if (l > 0 && Lv.h) mns_destroy(Lv.h);
   }
+  if (mg->fine) mns_destroy(mg->fine);
   for (void* p : mg->tables)
     if (p) (void)hipFree(p);
   delete mg;

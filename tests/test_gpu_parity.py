@@ -93,6 +93,37 @@ def test_jacobian_transient_with_history_and_force(dim):
     assert relmax(y64, yo) <= TOL64
 
 
+@pytest.mark.parametrize("dim,k,steady", [(2, 2, 1), (2, 3, 0), (3, 2, 1), (3, 2, 0), (3, 3, 1)])
+def test_picard_linearization(dim, k, steady):
+    """MNS_LIN_PICARD against the oracle's Picard option (no reaction term, no
+    SUPG weight derivative): Jacobian in FP64 and FP32, and the diagonal; then
+    the handle switches back to the Newton linearization."""
+    mesh = small_mesh(dim, k, steady=steady, dt=0.05)
+    g = np.random.default_rng(40 + 10 * dim + k)
+    n = inputs.n_dofs(mesh)
+    state, x, hist, force = (g.uniform(-1, 1, n) for _ in range(4))
+    hist = None if steady else hist
+    cfg = oracle_cfg(mesh, 1.9, 0.7)
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(1.9, 0.7)
+        op.set_linearization(_dev(state), None if hist is None else _dev(hist), _dev(force), kind="picard")
+        y64 = op.apply_jacobian(_dev(x)).cpu().numpy()
+        y32 = op.apply_jacobian(_dev(x, torch.float32)).double().cpu().numpy()
+        d64 = op.compute_diagonal(torch.float64).cpu().numpy()
+        op.set_linearization(_dev(state), None if hist is None else _dev(hist), _dev(force), kind="newton")
+        yn = op.apply_jacobian(_dev(x)).cpu().numpy()
+    yo = oracle.apply_jacobian(dict(cfg, picard=1), state, x, hist=hist, force=force)
+    do = oracle.diagonal(dict(cfg, picard=1), state, hist=hist, force=force)
+    yno = oracle.apply_jacobian(cfg, state, x, hist=hist, force=force)
+    print(f"picard dim={dim} k={k} steady={steady}: fp64 {relmax(y64, yo):.2e} fp32 {relmax(y32, yo):.2e} "
+          f"diag {relmax(d64, do):.2e}; newton after {relmax(yn, yno):.2e}")
+    assert relmax(yo, yno) > 1e-3
+    assert relmax(y64, yo) <= TOL64
+    assert relmax(y32, yo) <= TOL32
+    assert relmax(d64, do) <= TOL64
+    assert relmax(yn, yno) <= TOL64
+
+
 @pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2), (3, 3)])
 def test_residual(dim, k):
     mesh = small_mesh(dim, k, steady=0, dt=0.1)
