@@ -73,6 +73,9 @@ struct MortarTab {
   Real jxw[2][N][N];    // [seg][q_theta][q_z]: w R dtheta_seg (* w dz in 3D)
   Real tau_pen[2];      // penalty of the side's interface cells (Eq. EqPenalty)
   Real R;
+  Real inv_rdth;        // 1 / (R dtheta)
+  Real inv_dr[2];       // 1 / dr of the rotor and stator cells
+  Real inv_dz;          // 1 / dz (3D), 0 in 2D
   int seg_active[2];
   int m;                // pairing offset, in [0, n_theta)
 };

@@ -1799,58 +1799,62 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     }
   }
   __syncthreads();
-  // ---- phase B: face coefficients of the own side
+  // ---- phase B: face coefficients of the own side; one lane per (face,
+  // point) takes both pieces, so FPB * NQ <= 64 items run in one pass
   const Real nu = G.nu;
-  const Real inv_rdth = Real(1) / (M.R * G.dth);
-  const Real inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
-  for (int e = threadIdx.x; e < FPB * 2 * NQ; e += blockDim.x) {
-    const int fl = e / (2 * NQ), pc = (e / NQ) % 2, q = e % NQ;
+  const Real inv_rdth = M.inv_rdth;
+  const Real inv_dz = M.inv_dz;
+  for (int e = threadIdx.x; e < FPB * NQ; e += blockDim.x) {
+    const int fl = e / NQ, q = e % NQ;
     const int fs = mblock * FPB + fl;
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
     mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
     const int qt = q % N, qz = q / N;
-    const int seg = pc ? P[1].seg : P[0].seg;
-    const Real jxw = M.seg_active[seg] ? M.jxw[seg][qt][(DIM == 3) ? qz : 0] : Real(0);
-    const Real cth = trg[fl][pc][qt][0], sth = trg[fl][pc][qt][1];
-    Real n[DIM] = {};
-    n[0] = side == 0 ? cth : -cth;
-    n[1] = side == 0 ? sth : -sth;
-    const Real idr_o = Real(1) / (side == 0 ? G.dr[0] : G.dr[1]);
-    const Real idr_x = Real(1) / (side == 0 ? G.dr[1] : G.dr[0]);
-    const Real pbar = Real(0.5) * (ev[fl][pc][0][q][DIM][0] + ev[fl][pc][1][q][DIM][0]);
+    const Real idr_o = side == 0 ? M.inv_dr[0] : M.inv_dr[1];
+    const Real idr_x = side == 0 ? M.inv_dr[1] : M.inv_dr[0];
     const Real tau = side == 0 ? M.tau_pen[0] : M.tau_pen[1];
-    Real jn = 0;
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) {
-      const Real* eo = ev[fl][pc][0][q][m];
-      const Real* ex = ev[fl][pc][1][q][m];
-      const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
-      const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
-      Real gavg[DIM];
-      gavg[0] = Real(0.5) * ((cth * dro - sth * dto) + (cth * drx - sth * dtx));
-      gavg[1] = Real(0.5) * ((sth * dro + cth * dto) + (sth * drx + cth * dtx));
-      if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * inv_dz;
-      Real gn = 0;
+    for (int pc = 0; pc < 2; ++pc) {
+      const int seg = pc ? P[1].seg : P[0].seg;
+      const Real jxw = M.seg_active[seg] ? M.jxw[seg][qt][(DIM == 3) ? qz : 0] : Real(0);
+      const Real cth = trg[fl][pc][qt][0], sth = trg[fl][pc][qt][1];
+      Real n[DIM] = {};
+      n[0] = side == 0 ? cth : -cth;
+      n[1] = side == 0 ? sth : -sth;
+      const Real pbar = Real(0.5) * (ev[fl][pc][0][q][DIM][0] + ev[fl][pc][1][q][DIM][0]);
+      Real jn = 0;
 #pragma unroll
-      for (int d2 = 0; d2 < DIM; ++d2) gn += gavg[d2] * n[d2];
-      const Real j = eo[0] - ex[0];
-      jn += j * n[m];
-      const Real cv = pbar * n[m] - nu * gn + nu * tau * j;
-      Real Gm[DIM];
+      for (int m = 0; m < DIM; ++m) {
+        const Real* eo = ev[fl][pc][0][q][m];
+        const Real* ex = ev[fl][pc][1][q][m];
+        const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
+        const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
+        Real gavg[DIM];
+        gavg[0] = Real(0.5) * ((cth * dro - sth * dto) + (cth * drx - sth * dtx));
+        gavg[1] = Real(0.5) * ((sth * dro + cth * dto) + (sth * drx + cth * dtx));
+        if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * inv_dz;
+        Real gn = 0;
 #pragma unroll
-      for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
-      Real* cf = coef[fl][pc][q][m];
-      cf[0] = jxw * cv;
-      cf[1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
-      cf[2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
-      if constexpr (DIM == 3) cf[3] = jxw * Gm[2] * inv_dz;
+        for (int d2 = 0; d2 < DIM; ++d2) gn += gavg[d2] * n[d2];
+        const Real j = eo[0] - ex[0];
+        jn += j * n[m];
+        const Real cv = pbar * n[m] - nu * gn + nu * tau * j;
+        Real Gm[DIM];
+#pragma unroll
+        for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
+        Real* cf = coef[fl][pc][q][m];
+        cf[0] = jxw * cv;
+        cf[1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
+        cf[2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
+        if constexpr (DIM == 3) cf[3] = jxw * Gm[2] * inv_dz;
+      }
+      Real* cf = coef[fl][pc][q][DIM];
+      cf[0] = jxw * Real(-0.5) * jn;
+#pragma unroll
+      for (int j = 1; j < NE; ++j) cf[j] = 0;
     }
-    Real* cf = coef[fl][pc][q][DIM];
-    cf[0] = jxw * Real(-0.5) * jn;
-#pragma unroll
-    for (int j = 1; j < NE; ++j) cf[j] = 0;
   }
   __syncthreads();
   // ---- phase C: integration against the own cell's test functions

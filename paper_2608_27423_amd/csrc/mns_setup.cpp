@@ -276,6 +276,11 @@ static void fill_mortar_tab(const mns_handle* h, MortarTab<Real, N>& M, const do
   M.tau_pen[0] = (Real)h->tau_pen[0];
   M.tau_pen[1] = (Real)h->tau_pen[1];
   M.R = (Real)h->desc.r_interface;
+  const mns_mesh_desc& d = h->desc;
+  M.inv_rdth = (Real)(1.0 / (d.r_interface * h->dth));
+  M.inv_dr[0] = (Real)(1.0 / ((d.r_interface - d.r_in) / d.n_r_rotor));
+  M.inv_dr[1] = (Real)(1.0 / ((d.r_out - d.r_interface) / d.n_r_stator));
+  M.inv_dz = d.dim == 3 ? (Real)(1.0 / h->dz) : Real(0);
   M.seg_active[0] = active[0];
   M.seg_active[1] = active[1];
   M.m = h->m;

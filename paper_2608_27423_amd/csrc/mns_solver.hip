@@ -616,6 +616,7 @@ struct MG {
   int max_levels = 0;           // level limit the hierarchy was built with
   int coarse_lin = -1;          // linearization kind of the coarse levels at the last setup
   int fine_lin = -1;            // and of the mesh's own level
+  int eig_iters = -1;           // power iterations of the spectra at the last setup
   mns_handle* fine = nullptr;   // Picard copy of the mesh's own level (owned; level 0 when in use)
 };
 
@@ -772,7 +773,7 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
 // coarse operators at the current angle and state, diagonals and spectra
 static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t s) {
   if (mg->version == h->lin_version && mg->coarse_lin == o->mg_coarse_linearization &&
-      mg->fine_lin == o->mg_fine_linearization)
+      mg->fine_lin == o->mg_fine_linearization && mg->eig_iters == o->eig_iters)
     return MNS_OK;
   int rc;
   // level 0: the caller's handle, or a copy of its mesh with the Picard
@@ -831,6 +832,7 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
   mg->version = h->lin_version;
   mg->coarse_lin = o->mg_coarse_linearization;
   mg->fine_lin = o->mg_fine_linearization;
+  mg->eig_iters = o->eig_iters;
   return MNS_OK;
 }
 

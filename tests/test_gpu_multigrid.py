@@ -115,8 +115,9 @@ def test_multigrid_solve_matches_direct_solve(dim, k):
 def test_multigrid_picard_coarse_levels_steady():
     """Steady operator at a smooth state whose reaction term dominates the
     coarse levels (negative diagonal entries there): V-cycles with Picard
-    coarse levels converge to the direct solution; the Newton-coarse V-cycle is
-    run alongside and reported."""
+    coarse levels (and with a Picard copy of the fine level for smoothing)
+    converge to the direct solution of the Newton system; the Newton-coarse
+    V-cycle is run alongside and reported."""
     mesh = small_mesh(3, 2, n_theta=16, n_r_rotor=4, n_r_stator=4, n_z=4, nu=0.01)
     n = inputs.n_dofs(mesh)
     s = inputs.smooth_field(mesh, 3)
@@ -131,11 +132,13 @@ def test_multigrid_picard_coarse_levels_steady():
         op.set_linearization(_dev(state))
         for name, kw in [("picard", dict(precond="mg", mg_coarse_linearization="picard")),
                          ("picard64", dict(precond="mg64", mg_coarse_linearization="picard")),
+                         ("picard_all", dict(precond="mg", mg_coarse_linearization="picard",
+                                             mg_fine_linearization="picard")),
                          ("newton", dict(precond="mg"))]:
             x = torch.zeros(n, dtype=torch.float64, device="cuda")
-            _, rep = op.solve(_dev(b), x, check=False, rtol=1e-11, restart=100, maxit=600, **kw)
+            _, rep = op.solve(_dev(b), x, check=False, rtol=1e-11, restart=100, maxit=1500, **kw)
             out[name] = (rep, relmax(x.cpu().numpy(), xo))
     print("; ".join(f"{k}: its {r['iterations']} rc {r['rc']} err {e:.1e}" for k, (r, e) in out.items()))
-    for k in ("picard", "picard64"):
+    for k in ("picard", "picard64", "picard_all"):
         assert out[k][0]["rc"] == 0
         assert out[k][1] < 1e-8
