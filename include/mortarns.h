@@ -164,6 +164,10 @@ typedef struct {
   int mg_fine_linearization;   /* V-cycle on the mesh's own level: MNS_LIN_NEWTON (default) smooths with the
                                   handle's operator; MNS_LIN_PICARD with a Picard copy of it at the same state
                                   (one more set of per-point data).  FGMRES always applies the handle's operator */
+  int use_graph;               /* 1 (default): the preconditioner's launches (Chebyshev polynomial or V-cycle,
+                                  between the copies of its input and output) are captured once per call into a
+                                  HIP graph on a library stream and replayed on `stream` every iteration; 0: launched
+                                  one by one.  Ignored while kernel timing is enabled.  Same arithmetic either way */
 } mns_solve_opts;
 
 typedef struct {
@@ -206,12 +210,14 @@ int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void
 
 /* Solve J x = rhs with flexible GMRES in FP64 (classical Gram-Schmidt with one
  * reorthogonalization), right-preconditioned by a Jacobi-Chebyshev polynomial
- * of D^-1 J whose vmults run in the precision opts->precond.  x holds the
+ * of D^-1 J whose vmults run in the precision opts->precond, or by the
+ * multigrid V-cycle.  x holds the
  * initial guess on entry and the iterate on return; rhs is any device vector
  * and, since constrained rows of J are identity rows, the constrained entries
  * of the solution equal those of rhs.  Synchronizes the stream.  The first
  * call (and any call with a larger restart) allocates the Krylov workspace
- * (2 * restart + 6 FP64 vectors plus 4 FP32 vectors).
+ * (2 * restart + 9 FP64 vectors plus 5 FP32 vectors); with use_graph each call
+ * instantiates and frees one graph of the preconditioner.
  * Errors: NOT_LINEARIZED, INVALID_ARG, NOT_CONVERGED (report filled), HIP. */
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
               void* stream);

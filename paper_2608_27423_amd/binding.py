@@ -52,7 +52,7 @@ class SolveOpts(ctypes.Structure):
         ("cheb_degree", ctypes.c_int), ("cheb_range", ctypes.c_double), ("eig_iters", ctypes.c_int),
         ("mg_levels", ctypes.c_int), ("mg_smooth_degree", ctypes.c_int), ("mg_smooth_range", ctypes.c_double),
         ("mg_coarse_degree", ctypes.c_int), ("mg_coarse_linearization", ctypes.c_int),
-        ("mg_fine_linearization", ctypes.c_int),
+        ("mg_fine_linearization", ctypes.c_int), ("use_graph", ctypes.c_int),
     ]
 
 

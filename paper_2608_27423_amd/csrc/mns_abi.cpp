@@ -31,6 +31,7 @@ static void free_all(mns_handle* h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   mns::mg_free(h);
   void* ptrs[] = {h->d_hcell64, h->d_hcell32, h->d_trig64, h->d_trig32, h->d_mtab64, h->d_mtab32, h->d_mtrig64,
                   h->d_mtrig32, h->d_cons, h->d_lin64, h->d_lin32, h->d_hist, h->d_force, h->ws64, h->ws32,
@@ -234,6 +235,7 @@ void mns_default_solve_opts(mns_solve_opts* o) {
   o->mg_coarse_degree = 16;
   o->mg_coarse_linearization = MNS_LIN_NEWTON;
   o->mg_fine_linearization = MNS_LIN_NEWTON;
+  o->use_graph = 1;
 }
 
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
@@ -252,7 +254,8 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
       o.mg_levels < 0 || o.mg_levels > 16 || o.mg_coarse_degree < 1 || o.mg_coarse_degree > 1000 ||
       o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1) ||
       (o.mg_coarse_linearization != MNS_LIN_NEWTON && o.mg_coarse_linearization != MNS_LIN_PICARD) ||
-      (o.mg_fine_linearization != MNS_LIN_NEWTON && o.mg_fine_linearization != MNS_LIN_PICARD))
+      (o.mg_fine_linearization != MNS_LIN_NEWTON && o.mg_fine_linearization != MNS_LIN_PICARD) ||
+      (o.use_graph != 0 && o.use_graph != 1))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
   mns_solve_report rep{};
   int rc;

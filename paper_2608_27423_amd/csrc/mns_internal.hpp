@@ -139,6 +139,7 @@ struct mns_handle {
   int fused = -1;
   // second stream and events of the concurrent launch (fused == 2)
   hipStream_t aux = nullptr;
+  hipStream_t cap = nullptr;      // capture stream of the solver's graphs (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // volume layout: 1 = lane quad per cell (3D, degree <= 3), 0 = LDS planes
   int quad = 1;

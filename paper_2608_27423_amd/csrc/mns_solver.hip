@@ -188,7 +188,9 @@ using namespace mns;
 namespace {
 
 struct MG;
-int mg_vcycle(MG* mg, const mns_solve_opts* o, const double* v, double* z, hipStream_t s);
+int mg_vcycle_in(MG* mg, const mns_solve_opts* o, const double* v, hipStream_t s);
+int mg_vcycle_body(MG* mg, const mns_solve_opts* o, hipStream_t s);
+int mg_vcycle_out(MG* mg, const mns_solve_opts* o, double* z, hipStream_t s);
 
 struct Solver {
   mns_handle* h;
@@ -309,20 +311,88 @@ struct Solver {
     return hipGetLastError() == hipSuccess ? MNS_OK : err(MNS_ERR_HIP, "chebyshev");
   }
 
+  // z = M^-1 v in three parts: v is copied (or cast) into a fixed input
+  // buffer, the body maps that buffer to a fixed output buffer, which is
+  // copied (or cast) to z.  The body's launches depend on neither v nor z, so
+  // with use_graph they are captured once per solve and replayed.
+  hipGraphExec_t gexec = nullptr;
+  int graph_vm64 = 0, graph_vm32 = 0;
+
+  int precond_body(const mns_solve_opts* o, double lmax, hipStream_t bs) {
+    Solver B = *this;
+    B.s = bs;
+    B.vm64 = B.vm32 = 0;
+    int rc;
+    if (o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64) rc = mg_vcycle_body(mg, o, bs);
+    else if (o->precond == MNS_F64)
+      rc = B.chebyshev<double>(b64c, d64c + n, r64c, d64c, t64b, h->d_diag64, o->cheb_degree, lmax, o->cheb_range);
+    else
+      rc = B.chebyshev<float>(b32, x32, r32, d32, t32, h->d_diag32, o->cheb_degree, lmax, o->cheb_range);
+    graph_vm64 = B.vm64;
+    graph_vm32 = B.vm32;
+    return rc;
+  }
+
+  int capture_body(const mns_solve_opts* o, double lmax) {
+    if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
+      return err(MNS_ERR_HIP, "capture stream");
+    hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
+    const int rc = precond_body(o, lmax, h->cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(h->cap, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      return err(MNS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return MNS_OK;
+  }
+
+  void release_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+
   int precondition(const mns_solve_opts* o, double lmax, const double* v, double* z) {
     const unsigned g = grid_for(n);
-    if (o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64) return mg_vcycle(mg, o, v, z, s);
     if (o->precond == -1) {
       hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, z, n);
       return MNS_OK;
     }
+    const bool mgp = o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64;
+    int rc;
+    if (mgp) {
+      if ((rc = mg_vcycle_in(mg, o, v, s))) return rc;
+    } else if (o->precond == MNS_F64) {
+      hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, b64c, n);
+    } else {
+      hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, b32, n);
+    }
+    // graphs need an untimed handle (timed launches record events)
+    if (o->use_graph && !h->timing_cap) {
+      if (!gexec && (rc = capture_body(o, lmax))) return rc;
+      hipError_t e = hipGraphLaunch(gexec, s);
+      if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+      vm64 += graph_vm64;
+      vm32 += graph_vm32;
+    } else {
+      if ((rc = precond_body(o, lmax, s))) return rc;
+      vm64 += graph_vm64;
+      vm32 += graph_vm32;
+    }
+    if (mgp) return mg_vcycle_out(mg, o, z, s);
     if (o->precond == MNS_F64)
-      return chebyshev<double>(v, z, r64c, d64c, t64b, h->d_diag64, o->cheb_degree, lmax, o->cheb_range);
-    hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, b32, n);
-    int rc = chebyshev<float>(b32, x32, r32, d32, t32, h->d_diag32, o->cheb_degree, lmax, o->cheb_range);
-    if (rc) return rc;
-    hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, x32, z, n);
-    return MNS_OK;
+      hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, (const double*)(d64c + n), 1.0, z, n);
+    else
+      hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, x32, z, n);
+    return hipGetLastError() == hipSuccess ? MNS_OK : err(MNS_ERR_HIP, "preconditioner copies");
   }
 
   // r = b - J x, returns ||r||
@@ -918,21 +988,30 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   return mg_smooth<Real>(mg, l, v.b, v.x, false, o->mg_smooth_degree, o->mg_smooth_range, s);
 }
 
-int mg_vcycle(MG* mg, const mns_solve_opts* o, const double* v, double* z, hipStream_t s) {
+// V-cycle z = B v in three parts (the middle one touches only the levels'
+// own vectors, so that it can be captured into a graph): v into level 0's
+// right-hand side, the cycle, level 0's iterate into z
+int mg_vcycle_in(MG* mg, const mns_solve_opts* o, const double* v, hipStream_t s) {
   MGLevel& L0 = mg->L[0];
   const unsigned g = grid_for(L0.n);
-  int rc;
-  if (o->precond == MNS_PRECOND_MG64) {
-    double* b = (double*)L0.b;
-    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, b, L0.n);
-    if ((rc = mg_cycle<double>(mg, 0, o, s))) return rc;
-    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, (const double*)(b + L0.n), 1.0, z, L0.n);
-  } else {
-    float* b = (float*)L0.b;
-    hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, b, L0.n);
-    if ((rc = mg_cycle<float>(mg, 0, o, s))) return rc;
-    hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const float*)(b + L0.n), z, L0.n);
-  }
+  if (o->precond == MNS_PRECOND_MG64)
+    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, (double*)L0.b, L0.n);
+  else
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, (float*)L0.b, L0.n);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+int mg_vcycle_body(MG* mg, const mns_solve_opts* o, hipStream_t s) {
+  return o->precond == MNS_PRECOND_MG64 ? mg_cycle<double>(mg, 0, o, s) : mg_cycle<float>(mg, 0, o, s);
+}
+
+int mg_vcycle_out(MG* mg, const mns_solve_opts* o, double* z, hipStream_t s) {
+  MGLevel& L0 = mg->L[0];
+  const unsigned g = grid_for(L0.n);
+  if (o->precond == MNS_PRECOND_MG64)
+    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, (const double*)L0.b + L0.n, 1.0, z, L0.n);
+  else
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const float*)L0.b + L0.n, z, L0.n);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 
@@ -945,6 +1024,14 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
   int rc = ensure_workspace(h, m);
   if (rc) return rc;
   Solver S = make_solver(h, s, h->ws_restart);
+  // the preconditioner graph lives for this call only
+  struct GraphGuard {
+    Solver& S;
+    ~GraphGuard() {
+      if (S.gexec) (void)hipStreamSynchronize(S.s);
+      S.release_graph();
+    }
+  } graph_guard{S};
   const size_t n = (size_t)h->ndofs;
 
   double lmax = 0;
