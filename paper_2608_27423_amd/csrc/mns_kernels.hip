@@ -1674,7 +1674,12 @@ struct MortarShape {
   static constexpr int NQ = N * NZ;   // mortar points per piece
   static constexpr int NE = DIM + 1;  // value + reference derivatives
   static constexpr int LPF = 4 * NC;  // lanes per face in phase A
-  static constexpr int PER_FACE = (2 * 2 * NQ * NC * NE + 2 * NQ * NC * NE) * (int)sizeof(Real);
+  // LDS row of one mortar point, padded by one value against bank conflicts.
+  // Degree 4 in 3D keeps unpadded rows: its separate mortar kernel sits at the
+  // register limit with several hundred scalar spills, and its padded FP64
+  // build returned wrong values (the fused kernel and FP32 were exact).
+  static constexpr int PQ = NC * NE + ((DIM == 3 && N >= 5) ? 0 : 1);
+  static constexpr int PER_FACE = (2 * 2 * NQ * PQ + 2 * NQ * PQ) * (int)sizeof(Real);
   static constexpr int FPB0 = 64 / LPF;
   static constexpr int FPB_LDS = 36000 / PER_FACE > 0 ? 36000 / PER_FACE : 1;
   static constexpr int FPB = FPB0 < FPB_LDS ? FPB0 : FPB_LDS;
@@ -1685,8 +1690,11 @@ struct MortarSmem {
   using MS = MortarShape<Real, DIM, N>;
   MortarTab<Real, N> M;
   Real trg[MS::FPB][2][N][2];
-  Real ev[MS::FPB][2][2][MS::NQ][MS::NC][MS::NE];  // [face][piece][own=0 / other=1][point][comp][quantity]
-  Real coef[MS::FPB][2][MS::NQ][MS::NC][MS::NE];
+  // [face][piece][own=0 / other=1][point][comp * NE + quantity]; each point's
+  // row is padded by one value so that lanes on consecutive points fall in
+  // different LDS banks
+  Real ev[MS::FPB][2][2][MS::NQ][MS::PQ];
+  Real coef[MS::FPB][2][MS::NQ][MS::PQ];
 };
 
 template <typename Real, int DIM, int N>
@@ -1789,7 +1797,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
             dr += vz * Gr[c];
             dz += dzv * G0[c];
           }
-          Real* e = ev[fl][pc][sd][qz * N + qt][m];
+          Real* e = &ev[fl][pc][sd][qz * N + qt][m * NE];
           e[0] = v;
           e[1] = dt;
           e[2] = dr;
@@ -1823,12 +1831,12 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
       Real n[DIM] = {};
       n[0] = side == 0 ? cth : -cth;
       n[1] = side == 0 ? sth : -sth;
-      const Real pbar = Real(0.5) * (ev[fl][pc][0][q][DIM][0] + ev[fl][pc][1][q][DIM][0]);
+      const Real pbar = Real(0.5) * (ev[fl][pc][0][q][DIM * NE] + ev[fl][pc][1][q][DIM * NE]);
       Real jn = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
-        const Real* eo = ev[fl][pc][0][q][m];
-        const Real* ex = ev[fl][pc][1][q][m];
+        const Real* eo = &ev[fl][pc][0][q][m * NE];
+        const Real* ex = &ev[fl][pc][1][q][m * NE];
         const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
         const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
         Real gavg[DIM];
@@ -1844,13 +1852,13 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         Real Gm[DIM];
 #pragma unroll
         for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
-        Real* cf = coef[fl][pc][q][m];
+        Real* cf = &coef[fl][pc][q][m * NE];
         cf[0] = jxw * cv;
         cf[1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
         cf[2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
         if constexpr (DIM == 3) cf[3] = jxw * Gm[2] * inv_dz;
       }
-      Real* cf = coef[fl][pc][q][DIM];
+      Real* cf = &coef[fl][pc][q][DIM * NE];
       cf[0] = jxw * Real(-0.5) * jn;
 #pragma unroll
       for (int j = 1; j < NE; ++j) cf[j] = 0;
@@ -1880,7 +1888,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         Real f0[NZ], ft[NZ], fr[NZ], fz[NZ];
 #pragma unroll
         for (int qz = 0; qz < NZ; ++qz) {
-          const Real* cf = coef[fl][pc][qz * N + qt][m];
+          const Real* cf = &coef[fl][pc][qz * N + qt][m * NE];
           f0[qz] = cf[0];
           ft[qz] = cf[1];
           fr[qz] = cf[2];
