@@ -1865,71 +1865,65 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     }
   }
   __syncthreads();
-  // ---- phase C: integration against the own cell's test functions
-  for (int e = threadIdx.x; e < FPB * NC * N; e += blockDim.x) {
-    const int fl = e / (NC * N), m = (e / N) % NC, b2 = e % N;
+  // ---- phase C: integration against the own cell's test functions; lane =
+  // (face, component, z node c): z reverse for its c, theta reverse, then the
+  // r expansion to all N rows of the face's cell layer
+  for (int e = threadIdx.x; e < FPB * NC * NZ; e += blockDim.x) {
+    const int fl = e / (NC * NZ), m = (e / NZ) % NC, c = e % NZ;
     const int fs = mblock * FPB + fl;
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
     mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
-    const Real fv = M.FV[side][b2], fd = M.FD[side][b2];
-    Real out[NZ][N];
+    Real k0[N], k1[N];
 #pragma unroll
-    for (int c = 0; c < NZ; ++c)
+    for (int a2 = 0; a2 < N; ++a2) {
+      k0[a2] = 0;
+      k1[a2] = 0;
+    }
 #pragma unroll
-      for (int a2 = 0; a2 < N; ++a2) out[c][a2] = 0;
     for (int pc = 0; pc < 2; ++pc) {
       const int seg = pc ? P[1].seg : P[0].seg;
-      // z reverse: H0 (value + z-derivative terms), Ht, Hr at (c, qt)
-      Real H0[NZ][N], Ht[NZ][N], Hr[NZ][N];
+      // z reverse at node c: H0 (value + z-derivative terms), Ht, Hr per qt
+      Real H0[N], Ht[N], Hr[N];
 #pragma unroll
       for (int qt = 0; qt < N; ++qt) {
-        Real f0[NZ], ft[NZ], fr[NZ], fz[NZ];
+        Real h0 = 0, ht = 0, hr = 0;
 #pragma unroll
         for (int qz = 0; qz < NZ; ++qz) {
           const Real* cf = &coef[fl][pc][qz * N + qt][m * NE];
-          f0[qz] = cf[0];
-          ft[qz] = cf[1];
-          fr[qz] = cf[2];
-          fz[qz] = (DIM == 3) ? cf[3] : Real(0);
+          const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
+          const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
+          h0 += vz * cf[0] + ((DIM == 3) ? dzv * cf[3] : Real(0));
+          ht += vz * cf[1];
+          hr += vz * cf[2];
         }
-#pragma unroll
-        for (int c = 0; c < NZ; ++c) {
-          Real h0 = 0, ht = 0, hr = 0;
-#pragma unroll
-          for (int qz = 0; qz < NZ; ++qz) {
-            const Real vz = (DIM == 3) ? T.V[qz][c] : Real(1);
-            const Real dzv = (DIM == 3) ? T.D[qz][c] : Real(0);
-            h0 += vz * f0[qz] + dzv * fz[qz];
-            ht += vz * ft[qz];
-            hr += vz * fr[qz];
-          }
-          H0[c][qt] = h0;
-          Ht[c][qt] = ht;
-          Hr[c][qt] = hr;
-        }
+        H0[qt] = h0;
+        Ht[qt] = ht;
+        Hr[qt] = hr;
       }
-      // theta reverse and the r expansion for this lane's row b2
+      // theta reverse
 #pragma unroll
-      for (int c = 0; c < NZ; ++c)
+      for (int a2 = 0; a2 < N; ++a2) {
+        Real s0 = 0, s1 = 0;
 #pragma unroll
-        for (int a2 = 0; a2 < N; ++a2) {
-          Real k0 = 0, k1 = 0;
-#pragma unroll
-          for (int qt = 0; qt < N; ++qt) {
-            const Real mv = M.MV[side][seg][qt][a2], md = M.MD[side][seg][qt][a2];
-            k0 += mv * H0[c][qt] + md * Ht[c][qt];
-            k1 += mv * Hr[c][qt];
-          }
-          out[c][a2] += fv * k0 + fd * k1;
+        for (int qt = 0; qt < N; ++qt) {
+          const Real mv = M.MV[side][seg][qt][a2], md = M.MD[side][seg][qt][a2];
+          s0 += mv * H0[qt] + md * Ht[qt];
+          s1 += mv * Hr[qt];
         }
+        k0[a2] += s0;
+        k1[a2] += s1;
+      }
     }
+    // r expansion: row b2 takes the face value L_b2 and normal derivative L_b2'
 #pragma unroll
-    for (int c = 0; c < NZ; ++c)
+    for (int b2 = 0; b2 < N; ++b2) {
+      const Real fv = M.FV[side][b2], fd = M.FD[side][b2];
 #pragma unroll
       for (int a2 = 0; a2 < N; ++a2)
-        Em[(size_t)(m * S::NPT + c * S::PLANE + b2 * N + a2) * nsides + fs] = out[c][a2];
+        Em[(size_t)(m * S::NPT + c * S::PLANE + b2 * N + a2) * nsides + fs] = fv * k0[a2] + fd * k1[a2];
+    }
   }
 }
 
