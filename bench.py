@@ -9,7 +9,7 @@ The other rows of the hot path are timed in the same run and reported beside
 the metric: rotor rotation + mortar setup, linearization, the FP32 Jacobian,
 the diagonal, and the FGMRES solve (plain FP64 vs FP32-preconditioned).
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the library runs on one GPU.
 """
 import argparse
 import json
@@ -109,7 +109,7 @@ def timed(fn, sync):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding is design-only "
                                    "(axial slabs, see the design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
@@ -223,6 +223,27 @@ def main():
         solves["speedup_mixed_over_plain"] = (p["seconds"] / m["seconds"]) if m["seconds"] > 0 else None
         solves["state"] = "smooth manufactured field scaled to max |u| = 1"
         solves["preconditioner"] = f"Jacobi-Chebyshev degree {args.cheb_degree}, FGMRES({args.solve_restart})"
+        if mesh["degree"] in (2, 3):
+            # the same solves with the multigrid V-cycle (Picard levels); one
+            # untimed solve builds and linearizes the hierarchy first
+            mgo = dict(rtol=1e-8, restart=60, maxit=args.solve_maxit, mg_coarse_linearization="picard",
+                       mg_fine_linearization="picard", mg_smooth_degree=3, mg_smooth_range=10.0)
+            op.solve(rhs, torch.zeros_like(rhs), check=False, precond="mg", **dict(mgo, maxit=1))
+            mg = {}
+            for label, prec in (("plain_fp64", "mg64"), ("mixed_fp32", "mg")):
+                xs = torch.zeros_like(rhs)
+                sync()
+                _, info = op.solve(rhs, xs, check=False, precond=prec, **mgo)
+                chk = op.apply_jacobian(xs)
+                sync()
+                mg[label] = {"seconds": info["seconds"], "iterations": info["iterations"],
+                             "converged": info["rc"] == 0, "true_rel_residual": float((rhs - chk).norm() / rhs.norm())}
+            mg["speedup_mixed_over_plain"] = (mg["plain_fp64"]["seconds"] / mg["mixed_fp32"]["seconds"]
+                                              if mg["mixed_fp32"]["seconds"] > 0 else None)
+            mg["levels"] = op.mg_levels()
+            mg["preconditioner"] = ("geometric multigrid V-cycle, Picard-linearized levels, Jacobi-Chebyshev smoothing "
+                                    "degree 3 on [lambda/10, lambda] in FP32 (mixed) or FP64 (plain), FGMRES(60)")
+            solves["multigrid"] = mg
         rec["solve"] = solves
 
     if args.transient and not mesh.get("steady", 1):

@@ -58,7 +58,7 @@ enum {
   MNS_ERR_HIP = -2,           /* a HIP runtime call failed */
   MNS_ERR_NOT_LINEARIZED = -3,/* mns_set_linearization has not been called */
   MNS_ERR_NOT_CONVERGED = -4, /* mns_solve stopped at maxit; x holds the last iterate */
-  MNS_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement */
+  MNS_ERR_UNSUPPORTED = -5,   /* valid request the library does not implement */
   MNS_ERR_NO_ROTATION = -6    /* mns_rotate_rotor has not been called */
 };
 
@@ -266,6 +266,28 @@ void mns_default_step_opts(mns_step_opts* opts);
 int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* u_n, const double* u_nm1,
                   const double* force, double* u_next, const mns_step_opts* opts, mns_step_report* report,
                   void* stream);
+
+/* Batched Jacobian application (many rotor/stator instances at once).  A
+ * batch holds `count` handles of one dimension and degree (any mesh sizes,
+ * angles, viscosities, steady or transient), each rotated and linearized
+ * before mns_batch_create.  Vectors of a batch are the instances' vectors
+ * concatenated in handle order (mns_batch_n_dofs gives the total length).
+ * mns_batch_apply_jacobian computes dst_i = J_i src_i for every instance with
+ * one launch for all volume cells and mortar faces (mortar blocks first, the
+ * instance of a block found from block prefix sums) and one gather launch;
+ * the arithmetic is that of mns_apply_jacobian, so every slice equals the
+ * instance's own product.  Later rotations and linearizations of the handles
+ * are seen by later batch calls; a handle must outlive its batches.  The
+ * batch allocates its tables at creation and nothing per call.
+ * Errors: INVALID_ARG (null, mixed dimension or degree, misaligned vectors),
+ * NOT_LINEARIZED, UNSUPPORTED, HIP; creation errors are reported on
+ * handles[0], apply errors by mns_batch_last_error. */
+typedef struct mns_batch mns_batch;
+int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch);
+int mns_batch_n_dofs(const mns_batch* batch, int64_t* n_total);
+int mns_batch_apply_jacobian(mns_batch* batch, int precision, const void* src, void* dst, void* stream);
+const char* mns_batch_last_error(const mns_batch* batch);
+void mns_batch_destroy(mns_batch* batch);
 
 /* Kernel configuration of the Jacobian application (tuning knobs; every
  * setting computes the same product).  fused_launch = 1: volume cells and

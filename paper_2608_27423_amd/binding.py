@@ -32,6 +32,7 @@ EXPORTED = [
     "mns_apply_residual", "mns_compute_diagonal", "mns_default_solve_opts", "mns_solve", "mns_enable_timing",
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
+    "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
 ]
 
 
@@ -131,6 +132,13 @@ def lib():
                                     ctypes.POINTER(StepReport), vp]
         L.mns_mg_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.mns_mg_prolongate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mns_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
+        L.mns_batch_n_dofs.argtypes = [vp, i64p]
+        L.mns_batch_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mns_batch_last_error.argtypes = [vp]
+        L.mns_batch_last_error.restype = ctypes.c_char_p
+        L.mns_batch_destroy.argtypes = [vp]
+        L.mns_batch_destroy.restype = None
         L.mns_last_error.argtypes = [vp]
         L.mns_last_error.restype = ctypes.c_char_p
         L.mns_destroy.argtypes = [vp]
@@ -326,6 +334,64 @@ class Operator:
         if getattr(self, "_h", None):
             self._L.mns_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Instances of one dimension and degree applied together (mns_batch_*).
+    Vectors are the instances' vectors concatenated in the order of `ops`;
+    `offsets[i]` is where instance i starts."""
+
+    def __init__(self, ops):
+        self._L = lib()
+        self._ops = list(ops)  # the handles must outlive the batch
+        arr = (ctypes.c_void_p * len(self._ops))(*[op._h.value for op in self._ops])
+        self._b = ctypes.c_void_p()
+        rc = self._L.mns_batch_create(arr, len(self._ops), ctypes.byref(self._b))
+        if rc != MNS_OK:
+            raise MnsError(rc, self._ops[0].last_error() if self._ops else "")
+        n = ctypes.c_int64()
+        self._check(self._L.mns_batch_n_dofs(self._b, ctypes.byref(n)))
+        self.n_dofs = n.value
+        self.offsets = []
+        off = 0
+        for op in self._ops:
+            self.offsets.append(off)
+            off += op.n_dofs
+
+    def _check(self, rc):
+        if rc != MNS_OK:
+            raise MnsError(rc, self._L.mns_batch_last_error(self._b).decode())
+        return rc
+
+    def apply_jacobian(self, src, dst=None):
+        import torch
+
+        if dst is None:
+            dst = torch.empty_like(src)
+        prec = MNS_F64 if src.dtype == torch.float64 else MNS_F32
+        if src.dtype not in (torch.float64, torch.float32) or dst.dtype != src.dtype:
+            raise ValueError("src/dst must both be float64 or both float32")
+        if src.numel() != self.n_dofs or dst.numel() != self.n_dofs:
+            raise ValueError("vector length != batch n_dofs")
+        self._check(self._L.mns_batch_apply_jacobian(self._b, prec, _ptr(src), _ptr(dst), _stream()))
+        return dst
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self._L.mns_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -171,6 +171,87 @@ int mns_set_linearization(mns_handle* h, const double* state, const double* u_hi
   return MNS_OK;
 }
 
+int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch) {
+  if (!batch) return MNS_ERR_INVALID_ARG;
+  *batch = nullptr;
+  if (!handles || count < 1 || count > 65536) return MNS_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    mns_handle* h = handles[i];
+    if (!h) return MNS_ERR_INVALID_ARG;
+    if (!h->rotated || !h->linearized)
+      return set_error(h, MNS_ERR_NOT_LINEARIZED, "batch: rotate and linearize every handle first");
+    if (h->dim != handles[0]->dim || h->k != handles[0]->k)
+      return set_error(h, MNS_ERR_INVALID_ARG, "batch: all handles need the same dimension and degree");
+  }
+  auto* b = new mns_batch();
+  b->hs.assign(handles, handles + count);
+  b->dim = handles[0]->dim;
+  b->k = handles[0]->k;
+  for (int i = 0; i < count; ++i) {
+    b->offsets.push_back(b->ndofs);
+    b->ndofs += handles[i]->ndofs;
+  }
+  int rc;
+  try {
+    rc = mns::batch_build(b);
+  } catch (...) {
+    rc = MNS_ERR_HIP;
+    b->err = "exception in batch setup";
+  }
+  if (rc) {
+    (void)set_error(handles[0], rc, b->err);
+    mns_batch_destroy(b);
+    return rc;
+  }
+  *batch = b;
+  return MNS_OK;
+}
+
+int mns_batch_n_dofs(const mns_batch* b, int64_t* n_total) {
+  if (!b || !n_total) return MNS_ERR_INVALID_ARG;
+  *n_total = b->ndofs;
+  return MNS_OK;
+}
+
+int mns_batch_apply_jacobian(mns_batch* b, int precision, const void* src, void* dst, void* stream) {
+  if (!b) return MNS_ERR_INVALID_ARG;
+  if (src == dst) {
+    b->err = "src and dst must not overlap";
+    return MNS_ERR_INVALID_ARG;
+  }
+  try {
+    if (precision == MNS_F64) {
+      if (!aligned(src, 8) || !aligned(dst, 8)) {
+        b->err = "misaligned or null vector";
+        return MNS_ERR_INVALID_ARG;
+      }
+      return mns::launch_batch_jacobian<double>(b, (const double*)src, (double*)dst, as_stream(stream));
+    }
+    if (precision == MNS_F32) {
+      if (!aligned(src, 4) || !aligned(dst, 4)) {
+        b->err = "misaligned or null vector";
+        return MNS_ERR_INVALID_ARG;
+      }
+      return mns::launch_batch_jacobian<float>(b, (const float*)src, (float*)dst, as_stream(stream));
+    }
+  } catch (...) {
+    b->err = "exception in batch apply";
+    return MNS_ERR_HIP;
+  }
+  b->err = "precision must be MNS_F64 or MNS_F32";
+  return MNS_ERR_INVALID_ARG;
+}
+
+const char* mns_batch_last_error(const mns_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void mns_batch_destroy(mns_batch* b) {
+  if (!b) return;
+  if (b->d_items64) (void)hipFree(b->d_items64);
+  if (b->d_items32) (void)hipFree(b->d_items32);
+  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  delete b;
+}
+
 int mns_apply_jacobian(mns_handle* h, int precision, const void* src, void* dst, void* stream) {
   if (!h) return MNS_ERR_INVALID_ARG;
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");

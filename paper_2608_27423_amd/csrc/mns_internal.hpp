@@ -154,6 +154,44 @@ struct mns_handle {
 
 namespace mns {
 
+// One instance of a batched Jacobian application: its geometry and the
+// device arrays of its handle; vectors of all instances are concatenated, the
+// instance's slice starting at dof_off.
+template <typename Real>
+struct BatchItem {
+  Geom<Real> G;
+  const Real* lin;
+  Real* E;
+  Real* Em;
+  const void* mtab;   // MortarTab<Real, N> of the handle
+  const Real* mtrig;
+  long long dof_off;
+  int strip;          // local-result layout of the quad volume kernel
+};
+
+}  // namespace mns
+
+// Instances of equal dimension and degree applied together (mns_batch_*).
+struct mns_batch {
+  std::vector<mns_handle*> hs;
+  int dim = 0, k = 0;
+  long long ndofs = 0;
+  std::vector<long long> offsets;
+  // device: items (FP64, FP32), block prefix sums per precision: mortar,
+  // volume (count + 1 each), gather (count + 1, shared)
+  void* d_items64 = nullptr;
+  void* d_items32 = nullptr;
+  long long* d_prefix = nullptr;
+  long long mtot[2] = {0, 0}, vtot[2] = {0, 0}, gtot = 0;
+  std::string err;
+};
+
+namespace mns {
+
+int batch_build(mns_batch* b);
+template <typename Real>
+int launch_batch_jacobian(mns_batch* b, const Real* src, Real* dst, hipStream_t s);
+
 // kernel launchers (mns_kernels.hip)
 template <typename Real>
 int launch_linearize(mns_handle* h, const double* state, const double* hist, const double* force,

@@ -529,12 +529,11 @@ __device__ inline void integrate_store(const Tab1D<Real, N>& T, const Tab1D<Real
 // constrained rows: mode 0 dst = src, mode 1 dst = 0.  One lane per node.
 // ---------------------------------------------------------------------------
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real* __restrict__ E,
-                                                const Real* __restrict__ Em, const Real* __restrict__ src,
-                                                Real* __restrict__ dst, int mode, int strip) {
+__device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __restrict__ E,
+                                   const Real* __restrict__ Em, const Real* __restrict__ src,
+                                   Real* __restrict__ dst, int mode, int strip, long long g) {
   using S = Shape<Real, DIM, N>;
   constexpr int NC = S::NC;
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long nnodes = G.ndofs / NC;
   if (g >= nnodes) return;
   const int dom = g >= G.node_off1;
@@ -658,6 +657,13 @@ __global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real*
     const bool fixed = m < DIM ? vf : pf;
     d[m] = fixed ? (mode == 0 ? sv[m] : Real(0)) : acc[m];
   }
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(256) void k_gather(Geom<Real> G, int k, const Real* __restrict__ E,
+                                                const Real* __restrict__ Em, const Real* __restrict__ src,
+                                                Real* __restrict__ dst, int mode, int strip) {
+  gather_node<Real, DIM, N>(G, k, E, Em, src, dst, mode, strip, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // lane's nodal line of a vector (all components), constrained entries as zero
@@ -2254,6 +2260,204 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   }
   return do_gather<Real, DIM, N>(h, E, Em, src, dst, 0, s, strip);
 }
+
+// ---------------------------------------------------------------------------
+// Batched application: many instances of one dimension and degree in one
+// volume + mortar launch and one gather launch.  Blocks [0, mortar total)
+// integrate mortar faces, the rest volume cells; the instance of a block is
+// found by binary search in the block prefix sums.
+// ---------------------------------------------------------------------------
+__device__ inline int batch_item_of(const long long* __restrict__ start, int count, long long b) {
+  int lo = 0, hi = count - 1;  // last instance whose range starts at or before b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename Real, int N>
+__global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_batch_jacobian_quad(const BatchItem<Real>* __restrict__ items,
+                                                                          const long long* __restrict__ mstart,
+                                                                          const long long* __restrict__ vstart,
+                                                                          int count, Tab1D<Real, N> T, int k,
+                                                                          const Real* __restrict__ src) {
+  __shared__ MortarSmem<Real, 3, N> sm;
+  const long long mtot = mstart[count];
+  const long long b = blockIdx.x;
+  if (b < mtot) {
+    const int i = batch_item_of(mstart, count, b);
+    const Geom<Real> G = items[i].G;
+    mortar_block<Real, 3, N>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab, items[i].mtrig,
+                             src + items[i].dof_off, items[i].Em, 1, sm);
+  } else {
+    const int i = batch_item_of(vstart, count, b - mtot);
+    const Geom<Real> G = items[i].G;
+    volume_quad<Real, N>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off, items[i].E,
+                         items[i].strip != 0);
+  }
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_batch_jacobian(const BatchItem<Real>* __restrict__ items,
+                                                                    const long long* __restrict__ mstart,
+                                                                    const long long* __restrict__ vstart, int count,
+                                                                    Tab1D<Real, N> T, int k,
+                                                                    const Real* __restrict__ src) {
+  __shared__ FusedSmem<Real, DIM, N> sm;
+  const long long mtot = mstart[count];
+  const long long b = blockIdx.x;
+  if (b < mtot) {
+    const int i = batch_item_of(mstart, count, b);
+    const Geom<Real> G = items[i].G;
+    mortar_block<Real, DIM, N>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab,
+                               items[i].mtrig, src + items[i].dof_off, items[i].Em, 1, sm.m);
+  } else {
+    const int i = batch_item_of(vstart, count, b - mtot);
+    const Geom<Real> G = items[i].G;
+    volume_block<Real, DIM, N>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off,
+                               items[i].E, sm.v);
+  }
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(256) void k_batch_gather(const BatchItem<Real>* __restrict__ items,
+                                                      const long long* __restrict__ gstart, int count, int k,
+                                                      const Real* __restrict__ src, Real* __restrict__ dst) {
+  const long long b = blockIdx.x;
+  const int i = batch_item_of(gstart, count, b);
+  const Geom<Real> G = items[i].G;
+  const long long off = items[i].dof_off;
+  gather_node<Real, DIM, N>(G, k, items[i].E, items[i].Em, src + off, dst + off, 0, items[i].strip,
+                            (b - gstart[i]) * 256 + threadIdx.x);
+}
+
+// block counts of one instance in the batched launch (the layouts of
+// do_jacobian's default configuration: quad volume layout for 3D degree 2)
+template <typename Real, int DIM, int N>
+static void batch_blocks(const mns_handle* h, long long* nmb, long long* nvb, int* strip) {
+  using S = Shape<Real, DIM, N>;
+  constexpr bool kQuad = DIM == 3 && N == 3;
+  const int cpw = kQuad ? QuadShape<Real, N>::CPW : S::CPW;
+  *nvb = (h->ncells + cpw - 1) / cpw;
+  *nmb = (2LL * h->desc.n_theta * h->nz + MortarShape<Real, DIM, N>::FPB - 1) / MortarShape<Real, DIM, N>::FPB;
+  *strip = (kQuad && h->desc.n_theta % 16 == 0) ? 1 : 0;
+}
+
+template <typename Real, int DIM, int N>
+static void batch_items(mns_batch* b, std::vector<BatchItem<Real>>& items, std::vector<long long>& ms,
+                        std::vector<long long>& vs) {
+  const int count = (int)b->hs.size();
+  items.resize(count);
+  ms.assign(count + 1, 0);
+  vs.assign(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    mns_handle* h = b->hs[i];
+    BatchItem<Real>& it = items[i];
+    it.G = make_geom<Real>(h);
+    it.lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
+    it.E = sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32;
+    it.Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
+    it.mtab = sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32;
+    it.mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
+    it.dof_off = b->offsets[i];
+    long long nmb, nvb;
+    batch_blocks<Real, DIM, N>(h, &nmb, &nvb, &it.strip);
+    ms[i + 1] = ms[i] + nmb;
+    vs[i + 1] = vs[i] + nvb;
+  }
+}
+
+template <int DIM, int N>
+static int batch_build_t(mns_batch* b) {
+  std::vector<BatchItem<double>> i64;
+  std::vector<BatchItem<float>> i32;
+  std::vector<long long> ms64, vs64, ms32, vs32;
+  batch_items<double, DIM, N>(b, i64, ms64, vs64);
+  batch_items<float, DIM, N>(b, i32, ms32, vs32);
+  const int count = (int)b->hs.size();
+  std::vector<long long> gs(count + 1, 0);
+  for (int i = 0; i < count; ++i) gs[i + 1] = gs[i] + (b->hs[i]->nnodes + 255) / 256;
+  b->mtot[0] = ms64[count];
+  b->vtot[0] = vs64[count];
+  b->mtot[1] = ms32[count];
+  b->vtot[1] = vs32[count];
+  b->gtot = gs[count];
+  std::vector<long long> prefix;
+  for (const auto* v : {&ms64, &vs64, &ms32, &vs32, &gs}) prefix.insert(prefix.end(), v->begin(), v->end());
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_items64, i64.size() * sizeof(i64[0]))) != hipSuccess ||
+      (e = hipMalloc(&b->d_items32, i32.size() * sizeof(i32[0]))) != hipSuccess ||
+      (e = hipMalloc((void**)&b->d_prefix, prefix.size() * sizeof(long long))) != hipSuccess ||
+      (e = hipMemcpy(b->d_items64, i64.data(), i64.size() * sizeof(i64[0]), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_items32, i32.data(), i32.size() * sizeof(i32[0]), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
+    b->err = std::string("batch tables: ") + hipGetErrorString(e);
+    return MNS_ERR_HIP;
+  }
+  return MNS_OK;
+}
+
+int batch_build(mns_batch* b) {
+  switch (b->dim * 10 + b->k) {
+    case 22: return batch_build_t<2, 3>(b);
+    case 23: return batch_build_t<2, 4>(b);
+    case 24: return batch_build_t<2, 5>(b);
+    case 25: return batch_build_t<2, 6>(b);
+    case 32: return batch_build_t<3, 3>(b);
+    case 33: return batch_build_t<3, 4>(b);
+    case 34: return batch_build_t<3, 5>(b);
+    default: b->err = "degree not compiled"; return MNS_ERR_UNSUPPORTED;
+  }
+}
+
+template <typename Real, int DIM, int N>
+static int do_batch(mns_batch* b, const Real* src, Real* dst, hipStream_t s) {
+  const int count = (int)b->hs.size();
+  const int p = sizeof(Real) == 8 ? 0 : 1;
+  const auto* items = (const BatchItem<Real>*)(p == 0 ? b->d_items64 : b->d_items32);
+  const long long* ms = b->d_prefix + (size_t)p * 2 * (count + 1);
+  const long long* vs = ms + (count + 1);
+  const long long* gs = b->d_prefix + (size_t)4 * (count + 1);
+  const Tab1D<Real, N> T = make_tab<Real, N>(b->hs[0]);
+  const long long blocks = b->mtot[p] + b->vtot[p];
+  constexpr bool kQuad = DIM == 3 && N == 3;
+  if constexpr (kQuad)
+    hipLaunchKernelGGL((k_batch_jacobian_quad<Real, N>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs, count,
+                       T, b->k, src);
+  else
+    hipLaunchKernelGGL((k_batch_jacobian<Real, DIM, N>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs,
+                       count, T, b->k, src);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((k_batch_gather<Real, DIM, N>), dim3((unsigned)b->gtot), dim3(256), 0, s, items, gs, count,
+                       b->k, src, dst);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    b->err = std::string("batch kernels: ") + hipGetErrorString(e);
+    return MNS_ERR_HIP;
+  }
+  return MNS_OK;
+}
+
+template <typename Real>
+int launch_batch_jacobian(mns_batch* b, const Real* src, Real* dst, hipStream_t s) {
+  switch (b->dim * 10 + b->k) {
+    case 22: return do_batch<Real, 2, 3>(b, src, dst, s);
+    case 23: return do_batch<Real, 2, 4>(b, src, dst, s);
+    case 24: return do_batch<Real, 2, 5>(b, src, dst, s);
+    case 25: return do_batch<Real, 2, 6>(b, src, dst, s);
+    case 32: return do_batch<Real, 3, 3>(b, src, dst, s);
+    case 33: return do_batch<Real, 3, 4>(b, src, dst, s);
+    case 34: return do_batch<Real, 3, 5>(b, src, dst, s);
+    default: b->err = "degree not compiled"; return MNS_ERR_UNSUPPORTED;
+  }
+}
+template int launch_batch_jacobian<double>(mns_batch*, const double*, double*, hipStream_t);
+template int launch_batch_jacobian<float>(mns_batch*, const float*, float*, hipStream_t);
 
 template <typename Real>
 int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
