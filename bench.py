@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--fused", type=int, default=-1,
                     help="-1: automatic; 1: volume and mortar in one launch; 2: mortar on a second stream; 0: sequential")
     ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k <= 3); 0: LDS planes")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching leg (48 uneven instances)")
     ap.add_argument("--transient", action="store_true",
                     help="also time one BDF2 + Newton step (transient workloads; rotor advances omega * dt)")
     return ap.parse_args()
@@ -96,6 +97,82 @@ def measured_traffic(workload, kernel):
         return float(rec["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def batch_leg(args, dev, sync):
+    """48 uneven rotor/stator instances (half 2D, half 3D Q2; angles and
+    Reynolds numbers seeded): FP64 Jacobian of every instance, once as two
+    batched calls (one per dimension: one volume + mortar launch and one gather
+    launch each) and once as one mns_apply_jacobian per instance."""
+    import torch
+
+    from paper_2608_27423_amd import binding, inputs
+
+    insts = inputs.batch_instances()
+    ops = []
+    for mesh_i, th, om, seed in insts:
+        o = binding.Operator(mesh_i)
+        o.rotate_rotor(th, om)
+        o.set_linearization(torch.from_numpy(inputs.uniform(o.n_dofs, seed)).to(dev))
+        ops.append(o)
+    groups = [[o for o in ops if o.mesh["dim"] == d] for d in (2, 3)]
+    batches = [binding.Batch(gr) for gr in groups]
+    xs = [torch.from_numpy(inputs.uniform(b.n_dofs, 7 + i)).to(dev) for i, b in enumerate(batches)]
+    ys = [torch.empty_like(x) for x in xs]
+    total = sum(b.n_dofs for b in batches)
+    reps = max(args.steps // 2, 10)
+
+    def t_batched(dtype):
+        xx = [x.to(dtype) for x in xs]
+        yy = [y.to(dtype) for y in ys]
+        for _ in range(3):
+            for b, x, y in zip(batches, xx, yy):
+                b.apply_jacobian(x, y)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for b, x, y in zip(batches, xx, yy):
+                b.apply_jacobian(x, y)
+        sync()
+        return (time.perf_counter() - t0) / reps, yy
+
+    def t_single():
+        sl = []
+        for b, x, y in zip(batches, xs, ys):
+            for o, off in zip(b._ops, b.offsets):
+                sl.append((o, x[off:off + o.n_dofs], y[off:off + o.n_dofs]))
+        for _ in range(3):
+            for o, x, y in sl:
+                o.apply_jacobian(x, y)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for o, x, y in sl:
+                o.apply_jacobian(x, y)
+        sync()
+        return (time.perf_counter() - t0) / reps
+
+    tb, yb = t_batched(torch.float64)
+    ref = [y.clone() for y in yb]
+    ts = t_single()
+    same = all(bool(torch.equal(a, b)) for a, b in zip(ref, ys))
+    tb32, _ = t_batched(torch.float32)
+    out = {
+        "instances": len(ops), "instances_2d": len(groups[0]), "instances_3d": len(groups[1]), "dofs": total,
+        "dofs_2d": batches[0].n_dofs, "dofs_3d": batches[1].n_dofs,
+        "batched_ms": 1e3 * tb, "batched_dofs_per_s": total / tb,
+        "single_launches_ms": 1e3 * ts, "single_launches_dofs_per_s": total / ts,
+        "speedup_batched_over_single": ts / tb,
+        "batched_fp32_ms": 1e3 * tb32, "batched_fp32_dofs_per_s": total / tb32,
+        "batched_equals_single": same,
+        "recipe": "inputs.batch_instances(): 2D Q2 32x4..256x32, 3D Q2 16x4x8..64x8x16 per domain, "
+                  "angles U[0, 2pi), Re log-uniform in [1, 2000], steady, nodal-uniform states",
+    }
+    for b in batches:
+        b.close()
+    for o in ops:
+        o.close()
+    return out
 
 
 def timed(fn, sync):
@@ -245,6 +322,9 @@ def main():
                                     "degree 3 on [lambda/10, lambda] in FP32 (mixed) or FP64 (plain), FGMRES(60)")
             solves["multigrid"] = mg
         rec["solve"] = solves
+
+    if not args.no_batch:
+        rec["batch"] = batch_leg(args, dev, sync)
 
     if args.transient and not mesh.get("steady", 1):
         # two implicit time steps of a spin-up: fluid at rest, a smooth body

@@ -156,3 +156,28 @@ def transient_start(m, seed):
             blk[-1, :, :, : m["dim"]] = 0.0
     sta[0, -1, 0, m["dim"]] = 0.0
     return u
+
+
+# Batching workload: uneven rotor/stator instances of the 2D and 3D Q2 forms
+BATCH_SIZES_2D = [(32, 4), (64, 8), (128, 16), (256, 32)]          # n_theta x n_r per domain
+BATCH_SIZES_3D = [(16, 4, 8), (32, 4, 8), (32, 8, 16), (64, 8, 16)]  # n_theta x n_r x n_z per domain
+
+
+def batch_instances(count=48, seed=21):
+    """`count` instances, half 2D and half 3D Q2, mesh sizes drawn uniformly
+    from the lists above, rotor angle uniform in [0, 2 pi), Reynolds number
+    log-uniform in [1, 2000] (nu = 1 / Re, steady).  Returns a list of
+    (mesh, theta, omega, state seed)."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        if i % 2 == 0:
+            nt, nr = BATCH_SIZES_2D[int(g.integers(len(BATCH_SIZES_2D)))]
+            m = mesh("annulus2d_q2_32x4", n_theta=nt, n_r_rotor=nr, n_r_stator=nr)
+        else:
+            nt, nr, nz = BATCH_SIZES_3D[int(g.integers(len(BATCH_SIZES_3D)))]
+            m = mesh("annulus3d_q2_64x8x32", n_theta=nt, n_r_rotor=nr, n_r_stator=nr, n_z=nz)
+        re = float(np.exp(g.uniform(0.0, np.log(2000.0))))
+        m["nu"] = 1.0 / re
+        out.append((m, float(g.uniform(0.0, TWO_PI)), 1.0, 100 + i))
+    return out
