@@ -309,6 +309,17 @@ typedef struct {
 int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg);
 int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg);
 
+/* Autotuner of the launch configuration: times `reps` FP64 applications of
+ * every launch mode (fused_launch 0, 1, 2) and, in 3D with degree <= 3, both
+ * volume layouts, on the handle's own mesh and linearization, and sets the
+ * fastest (written to *chosen when non-null).  All configurations compute the
+ * same product; the choice depends on the mesh size (tail of the fused
+ * launch against the cost of a second stream).  Allocates two work vectors
+ * for the duration of the call and synchronizes the stream.
+ * Errors: INVALID_ARG (reps outside 1..1000, kernel timing enabled),
+ * NOT_LINEARIZED, HIP. */
+int mns_autotune_kernel_config(mns_handle* h, int reps, mns_kernel_config* chosen, void* stream);
+
 /* Kernel timing for measurement.  mns_enable_timing(h, capacity) makes every
  * later mns_apply_jacobian record a pair of HIP events around each of its
  * kernels on the launch stream (capacity = max recorded launches per kernel

@@ -33,6 +33,7 @@ EXPORTED = [
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
+    "mns_autotune_kernel_config",
 ]
 
 
@@ -126,6 +127,7 @@ def lib():
         L.mns_read_timing.argtypes = [vp, ctypes.POINTER(Timing)]
         L.mns_set_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
         L.mns_get_kernel_config.argtypes = [vp, ctypes.POINTER(KernelConfig)]
+        L.mns_autotune_kernel_config.argtypes = [vp, ctypes.c_int, ctypes.POINTER(KernelConfig), vp]
         L.mns_default_step_opts.argtypes = [ctypes.POINTER(StepOpts)]
         L.mns_default_step_opts.restype = None
         L.mns_bdf2_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, ctypes.POINTER(StepOpts),
@@ -316,6 +318,12 @@ class Operator:
         for k2, v in kw.items():
             setattr(c, k2, int(v))
         return self._check(self._L.mns_set_kernel_config(self._h, ctypes.byref(c)))
+
+    def autotune_kernel_config(self, reps=10):
+        """Time every launch configuration on this mesh and keep the fastest."""
+        c = KernelConfig()
+        self._check(self._L.mns_autotune_kernel_config(self._h, int(reps), ctypes.byref(c), _stream()))
+        return {"fused_launch": c.fused_launch, "volume_layout": c.volume_layout}
 
     def get_kernel_config(self):
         c = KernelConfig()

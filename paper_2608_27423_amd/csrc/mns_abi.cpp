@@ -425,6 +425,67 @@ int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg) {
   return MNS_OK;
 }
 
+int mns_autotune_kernel_config(mns_handle* h, int reps, mns_kernel_config* chosen, void* stream) {
+  if (!h || reps < 1 || reps > 1000) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (h->timing_cap) return set_error(h, MNS_ERR_INVALID_ARG, "disable kernel timing before autotuning");
+  hipStream_t s = as_stream(stream);
+  const size_t n = (size_t)h->ndofs;
+  double *x = nullptr, *y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  auto cleanup = [&]() {
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if ((e = hipMalloc((void**)&x, n * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&y, n * sizeof(double))) != hipSuccess ||
+      (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    cleanup();
+    return set_error(h, MNS_ERR_HIP, std::string("autotune buffers: ") + hipGetErrorString(e));
+  }
+  int rc = mns::launch_fill<double>(x, 1.0, (int64_t)n, s);
+  // candidates: every launch mode; both volume layouts where the quad layout
+  // exists (3D, degree <= 3)
+  const bool has_quad = h->dim == 3 && h->k <= 3;
+  const int saved_fused = h->fused, saved_quad = h->quad;
+  float best = -1.0f;
+  mns_kernel_config best_cfg{saved_fused, saved_quad};
+  for (int layout = has_quad ? 1 : saved_quad; rc == MNS_OK && layout >= (has_quad ? 0 : saved_quad); --layout)
+    for (int mode = 0; rc == MNS_OK && mode <= 2; ++mode) {
+      h->fused = mode;
+      h->quad = layout;
+      for (int i = 0; i < 2 && rc == MNS_OK; ++i) rc = mns::launch_jacobian<double>(h, x, y, s);
+      if (rc) break;
+      (void)hipEventRecord(e0, s);
+      for (int i = 0; i < reps && rc == MNS_OK; ++i) rc = mns::launch_jacobian<double>(h, x, y, s);
+      (void)hipEventRecord(e1, s);
+      if (rc || (e = hipEventSynchronize(e1)) != hipSuccess) {
+        if (!rc) rc = set_error(h, MNS_ERR_HIP, std::string("autotune sync: ") + hipGetErrorString(e));
+        break;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0 || ms < best) {
+        best = ms;
+        best_cfg.fused_launch = mode;
+        best_cfg.volume_layout = layout;
+      }
+    }
+  cleanup();
+  if (rc) {
+    h->fused = saved_fused;
+    h->quad = saved_quad;
+    return rc;
+  }
+  h->fused = best_cfg.fused_launch;
+  h->quad = best_cfg.volume_layout;
+  if (chosen) *chosen = best_cfg;
+  return MNS_OK;
+}
+
 int mns_enable_timing(mns_handle* h, int capacity) {
   if (!h || capacity < 0) return MNS_ERR_INVALID_ARG;
   hipError_t e = hipDeviceSynchronize();

@@ -248,3 +248,27 @@ def test_solve_2d_workload(precond):
           f" oracle {rel:.2e}")
     assert info["rc"] == 0
     assert rel <= 1.01e-8
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3)])
+def test_autotune_keeps_parity(dim, k):
+    """mns_autotune_kernel_config picks one of the launch configurations, sets
+    it on the handle, and the product is unchanged (oracle parity)."""
+    mesh = small_mesh(dim, k, n_theta=16)
+    g = np.random.default_rng(60 + dim + k)
+    n = inputs.n_dofs(mesh)
+    state, x = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
+    with binding.Operator(mesh) as op:
+        with pytest.raises(binding.MnsError):
+            op.autotune_kernel_config(3)
+        op.rotate_rotor(1.3, 0.6)
+        op.set_linearization(_dev(state))
+        chosen = op.autotune_kernel_config(5)
+        assert chosen == op.get_kernel_config()
+        assert chosen["fused_launch"] in (0, 1, 2)
+        if dim == 2:
+            assert chosen["volume_layout"] == 1  # unchanged where only one layout exists
+        y = op.apply_jacobian(_dev(x)).cpu().numpy()
+    yo = oracle.apply_jacobian(oracle_cfg(mesh, 1.3, 0.6), state, x)
+    print(f"autotune dim={dim} k={k}: {chosen}, fp64 {relmax(y, yo):.2e}")
+    assert relmax(y, yo) <= TOL64
