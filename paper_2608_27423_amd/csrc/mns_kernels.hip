@@ -121,17 +121,18 @@ __device__ inline long long node_of(const Geom<Real>& G, int k, const CellId& C,
   return base + it + (long long)G.ntn * (ir + (long long)pick(C.dom, G.nrn) * iz);
 }
 
+// constraint predicates, written with bitwise operators so that they
+// compile to selects rather than branches
 template <typename Real, int DIM>
 __device__ inline bool vel_fixed(const Geom<Real>& G, int dom, int ir, int iz) {
-  if (dom == 0 && ir == 0) return true;
-  if (dom == 1 && ir == G.nrn[1] - 1) return true;
-  if (DIM == 3 && (iz == 0 || iz == G.nzn - 1)) return true;
-  return false;
+  const bool wall_r = ((dom == 0) & (ir == 0)) | ((dom == 1) & (ir == G.nrn[1] - 1));
+  const bool wall_z = (DIM == 3) & ((iz == 0) | (iz == G.nzn - 1));
+  return wall_r | wall_z;
 }
 
 template <typename Real>
 __device__ inline bool p_fixed(const Geom<Real>& G, int dom, int it, int ir, int iz) {
-  return dom == 1 && it == 0 && ir == G.nrn[1] - 1 && iz == 0;
+  return (dom == 1) & (it == 0) & (ir == G.nrn[1] - 1) & (iz == 0);
 }
 
 template <typename T>
@@ -1718,10 +1719,23 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
   const int nfaces = G.n_theta * G.nz;
   const int nsides = 2 * nfaces;
   {
+    // table copy to LDS: all loads issued before the first store (a plain
+    // loop waits for every load in turn); blocks have 64 lanes
     const int* srcw = (const int*)Mp;
     int* dstw = (int*)&M;
     constexpr int NW = (int)(sizeof(MortarTab<Real, N>) / sizeof(int));
-    for (int i = threadIdx.x; i < NW; i += blockDim.x) dstw[i] = srcw[i];
+    constexpr int IT = (NW + 63) / 64;
+    int w[IT];
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int i = (int)threadIdx.x + 64 * j;
+      w[j] = i < NW ? srcw[i] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int i = (int)threadIdx.x + 64 * j;
+      if (i < NW) dstw[i] = w[j];
+    }
   }
   __syncthreads();
   // ---- phase A: evaluation
@@ -1766,7 +1780,8 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
           for (int a2 = 0; a2 < N; ++a2) {
             int it, ir, iz;
             const long long nd = node_of<Real, DIM>(G, k, C, a2, b2, c, it, ir, iz);
-            const bool fixed = mask && (m < DIM ? vel_fixed<Real, DIM>(G, C.dom, ir, iz) : p_fixed(G, C.dom, it, ir, iz));
+            const bool vfx = vel_fixed<Real, DIM>(G, C.dom, ir, iz), pfx = p_fixed(G, C.dom, it, ir, iz);
+            const bool fixed = (mask != 0) & ((m < DIM) ? vfx : pfx);
             const Real xv = src[nd * NC + m];
             const Real x = fixed ? Real(0) : xv;
             F0[c][a2] += fv * x;
