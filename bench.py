@@ -35,8 +35,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solve-maxit", type=int, default=4000)
-    ap.add_argument("--solve-restart", type=int, default=300)
-    ap.add_argument("--cheb-degree", type=int, default=8)
+    ap.add_argument("--solve-restart", type=int, default=30)
+    ap.add_argument("--cheb-degree", type=int, default=12)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused", type=int, default=-1,
                     help="-1: automatic; 1: volume and mortar in one launch; 2: mortar on a second stream; 0: sequential")
