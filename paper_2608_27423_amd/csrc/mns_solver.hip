@@ -29,15 +29,20 @@ __global__ void k_cast(const From* __restrict__ a, To* __restrict__ b, long long
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (To)a[i];
 }
 
-// block-level sum of K values per thread into out[blockIdx.x * K + i]
+// block-level sum of K values per thread into out[blockIdx.x * K + i]; the
+// loops run over the full register array with a predicate, so that the
+// array stays in registers (a loop bounded by K indexes it dynamically)
 template <int MAXK>
 __device__ inline void block_sum_store(double (&v)[MAXK], int K, double* out) {
   __shared__ double s[kRedThreads / 64][MAXK];
   const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-  for (int i = 0; i < K; ++i) {
-    double x = v[i];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) s[wid][i] = x;
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    if (i < K) {
+      double x = v[i];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) s[wid][i] = x;
+    }
   }
   __syncthreads();
   if (threadIdx.x < K) {
@@ -47,33 +52,90 @@ __device__ inline void block_sum_store(double (&v)[MAXK], int K, double* out) {
   }
 }
 
-// partial dots of w with V_0 .. V_{K-1} (contiguous, stride n), K <= 32 per launch
+constexpr int kDotK = 32;  // register width of the fused Gram-Schmidt kernels
+
+// partial dots of w with V_0 .. V_{K-1} (contiguous, stride n); with self,
+// entry K is w . w (K + self <= 32 per launch)
 __global__ __launch_bounds__(kRedThreads) void k_multidot(const double* __restrict__ V, long long n, int K,
-                                                          const double* __restrict__ w, double* __restrict__ part) {
-  double acc[32];
-  for (int i = 0; i < 32; ++i) acc[i] = 0;
+                                                          const double* __restrict__ w, double* __restrict__ part,
+                                                          int self) {
+  double acc[kDotK];
+#pragma unroll
+  for (int i = 0; i < kDotK; ++i) acc[i] = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
     const double wr = w[r];
-#pragma unroll 4
-    for (int i = 0; i < K; ++i) acc[i] += V[(long long)i * n + r] * wr;
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) {
+      if (i < K) acc[i] += V[(long long)i * n + r] * wr;
+      if (self && i == K) acc[i] += wr * wr;
+    }
   }
-  block_sum_store<32>(acc, K, part);
+  block_sum_store<kDotK>(acc, K + self, part);
 }
 
-// w -= sum_i h_i V_i ; partial ||w||^2
+// w -= sum_i h_i V_i ; partial ||w||^2 (coefficients in registers for K <= 32)
 __global__ __launch_bounds__(kRedThreads) void k_multiaxpy_norm(const double* __restrict__ V, long long n, int K,
                                                                 const double* __restrict__ hcoef,
                                                                 double* __restrict__ w, double* __restrict__ part) {
   double acc[1] = {0};
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-    double x = w[r];
-    for (int i = 0; i < K; ++i) x -= hcoef[i] * V[(long long)i * n + r];
-    w[r] = x;
-    acc[0] += x * x;
+  if (K <= kDotK) {
+    double hh[kDotK];
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) {
+      hh[i] = 0.0;
+      if (i < K) hh[i] = hcoef[i];
+    }
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double x = w[r];
+#pragma unroll
+      for (int i = 0; i < kDotK; ++i)
+        if (i < K) x -= hh[i] * V[(long long)i * n + r];
+      w[r] = x;
+      acc[0] += x * x;
+    }
+  } else {
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double x = w[r];
+      for (int i = 0; i < K; ++i) x -= hcoef[i] * V[(long long)i * n + r];
+      w[r] = x;
+      acc[0] += x * x;
+    }
   }
   block_sum_store<1>(acc, 1, part);
+}
+
+// fused Gram-Schmidt pass (K <= 31): w -= sum_i h_i V_i, then partial dots of
+// the updated w with V_0 .. V_{K-1} and w . w (entry K), reading V once
+__global__ __launch_bounds__(kRedThreads) void k_multiaxpy_dot(const double* __restrict__ V, long long n, int K,
+                                                               const double* __restrict__ hcoef,
+                                                               double* __restrict__ w, double* __restrict__ part) {
+  double hh[kDotK], acc[kDotK];
+#pragma unroll
+  for (int i = 0; i < kDotK; ++i) {
+    hh[i] = 0.0;
+    if (i < K) hh[i] = hcoef[i];
+    acc[i] = 0;
+  }
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    double v[kDotK];
+    double x = w[r];
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) {
+      v[i] = 0.0;
+      if (i < K) v[i] = V[(long long)i * n + r];
+      x -= hh[i] * v[i];
+    }
+    w[r] = x;
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) {
+      if (i < K) acc[i] += v[i] * x;
+      if (i == K) acc[i] += x * x;
+    }
+  }
+  block_sum_store<kDotK>(acc, K + 1, part);
 }
 
 // second stage: out[i] = sum over blocks of part[b * K + i], fixed order
@@ -228,7 +290,7 @@ struct Solver {
     for (int i0 = 0; i0 < K; i0 += 32) {
       const int kk = (K - i0) < 32 ? (K - i0) : 32;
       hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, Vb + (size_t)i0 * n, n, kk, wv,
-                         parts());
+                         parts(), 0);
       int rc = reduce(kk);
       if (rc) return rc;
       rc = sync_read(kk, host + i0);
@@ -1053,7 +1115,7 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
 
   // ||b||
   double bn;
-  hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, rhs, (long long)n, 1, rhs, S.parts());
+  hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, rhs, (long long)n, 1, rhs, S.parts(), 0);
   if ((rc = S.reduce(1)) || (rc = S.sync_read(1, &bn))) return rc;
   bn = std::sqrt(bn);
   if (!(bn > 0)) {
@@ -1083,21 +1145,42 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
       double* Zj = S.Z + (size_t)j * n;
       if ((rc = S.precondition(o, lmax, Vj, Zj))) return rc;
       if ((rc = S.jac64(Zj, S.w))) return rc;
-      double wn0;
-      {
+      // classical Gram-Schmidt with one reorthogonalization when the norm
+      // drops below 0.7 of its value before the projection
+      double wn0, wn;
+      if (j + 2 <= kDotK) {
+        // (1) h = V^T w and w . w in one pass; (2) w -= V h fused with
+        // h2 = V^T w and w . w in one pass; (3) only when needed, w -= V h2
+        const int K = j + 1;
+        double tmp[kDotK + 1];
+        hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, S.V, (long long)n, K, S.w,
+                           S.parts(), 1);
+        if ((rc = S.reduce(K + 1)) || (rc = S.sync_read(K + 1, tmp))) return rc;
+        for (int i = 0; i < K; ++i) hcol[i] = tmp[i];
+        wn0 = std::sqrt(tmp[K]);
+        if ((rc = S.h2d(hcol.data(), K))) return rc;
+        hipLaunchKernelGGL(k_multiaxpy_dot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, S.V, (long long)n, K,
+                           S.coefs(), S.w, S.parts());
+        if ((rc = S.reduce(K + 1)) || (rc = S.sync_read(K + 1, tmp))) return rc;
+        wn = std::sqrt(tmp[K]);
+        if (wn < 0.7 * wn0) {
+          for (int i = 0; i < K; ++i) h2[i] = tmp[i];
+          if ((rc = S.multiaxpy(S.V, K, h2.data(), S.w, &wn))) return rc;
+          for (int i = 0; i < K; ++i) hcol[i] += h2[i];
+        }
+      } else {
         double v;
         hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, S.w, (long long)n, 1, S.w,
-                           S.parts());
+                           S.parts(), 0);
         if ((rc = S.reduce(1)) || (rc = S.sync_read(1, &v))) return rc;
         wn0 = std::sqrt(v);
-      }
-      if ((rc = S.multidot(S.V, j + 1, S.w, hcol.data()))) return rc;
-      double wn;
-      if ((rc = S.multiaxpy(S.V, j + 1, hcol.data(), S.w, &wn))) return rc;
-      if (wn < 0.7 * wn0) {  // reorthogonalize once
-        if ((rc = S.multidot(S.V, j + 1, S.w, h2.data()))) return rc;
-        if ((rc = S.multiaxpy(S.V, j + 1, h2.data(), S.w, &wn))) return rc;
-        for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
+        if ((rc = S.multidot(S.V, j + 1, S.w, hcol.data()))) return rc;
+        if ((rc = S.multiaxpy(S.V, j + 1, hcol.data(), S.w, &wn))) return rc;
+        if (wn < 0.7 * wn0) {
+          if ((rc = S.multidot(S.V, j + 1, S.w, h2.data()))) return rc;
+          if ((rc = S.multiaxpy(S.V, j + 1, h2.data(), S.w, &wn))) return rc;
+          for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
+        }
       }
       hcol[j + 1] = wn;
       if (!std::isfinite(wn)) return set_error(h, MNS_ERR_HIP, "non-finite value in FGMRES");
