@@ -208,6 +208,12 @@ int mns_mg_levels(mns_handle* h, int* levels);
  * Errors: INVALID_ARG (no such level), UNSUPPORTED (degree not 2 or 3), HIP. */
 int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void* stream);
 
+/* y = P_level^T x: the restriction the V-cycle applies, from level `level` to
+ * `level`+1 (x has the fine level's n_total doubles, y the coarse level's),
+ * computed direction by direction (theta, r, z).  For inspection and tests;
+ * builds the hierarchy if needed.  Errors: as mns_mg_prolongate. */
+int mns_mg_restrict(mns_handle* h, int level, const double* x, double* y, void* stream);
+
 /* Solve J x = rhs with flexible GMRES in FP64 (classical Gram-Schmidt with one
  * reorthogonalization), right-preconditioned by a Jacobi-Chebyshev polynomial
  * of D^-1 J whose vmults run in the precision opts->precond, or by the

@@ -33,7 +33,7 @@ EXPORTED = [
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
-    "mns_autotune_kernel_config",
+    "mns_autotune_kernel_config", "mns_mg_restrict",
 ]
 
 
@@ -134,6 +134,7 @@ def lib():
                                     ctypes.POINTER(StepReport), vp]
         L.mns_mg_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.mns_mg_prolongate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mns_mg_restrict.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
         L.mns_batch_n_dofs.argtypes = [vp, i64p]
         L.mns_batch_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -311,6 +312,10 @@ class Operator:
     def mg_prolongate(self, level, x, y):
         """y = P x from multigrid level `level`+1 to `level` (FP64 device vectors)."""
         return self._check(self._L.mns_mg_prolongate(self._h, int(level), _ptr(x), _ptr(y), _stream()))
+
+    def mg_restrict(self, level, x, y):
+        """y = P^T x from multigrid level `level` to `level`+1 (FP64 device vectors)."""
+        return self._check(self._L.mns_mg_restrict(self._h, int(level), _ptr(x), _ptr(y), _stream()))
 
     def set_kernel_config(self, **kw):
         c = KernelConfig()

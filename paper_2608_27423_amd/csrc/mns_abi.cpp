@@ -407,6 +407,18 @@ int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void
   }
 }
 
+int mns_mg_restrict(mns_handle* h, int level, const double* x, double* y, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (!aligned(x, 8) || !aligned(y, 8) || x == y)
+    return set_error(h, MNS_ERR_INVALID_ARG, "x/y must be distinct 8-byte aligned pointers");
+  try {
+    return mns::mg_restrict64(h, level, x, y, as_stream(stream));
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in mg_restrict");
+  }
+}
+
 int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg) {
   if (!h || !cfg) return MNS_ERR_INVALID_ARG;
   if (cfg->fused_launch < -1 || cfg->fused_launch > 2)

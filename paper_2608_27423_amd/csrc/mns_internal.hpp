@@ -211,6 +211,7 @@ int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real dia
 void mg_free(mns_handle* h);
 int mg_levels(mns_handle* h, int* levels, hipStream_t s);
 int mg_prolongate64(mns_handle* h, int level, const double* x, double* y, hipStream_t s);
+int mg_restrict64(mns_handle* h, int level, const double* x, double* y, hipStream_t s);
 int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const double* un, const double* unm1,
                        const double* force, double* u, const mns_step_opts* o, mns_step_report* rep, hipStream_t s);
 int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s);

@@ -650,41 +650,74 @@ __global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __
   for (int m = 0; m < X.nc; ++m) fine[g * X.nc + m] = (add ? fine[g * X.nc + m] : Real(0)) + acc[m];
 }
 
+// One direction of the restriction (the transposed 1D prolongation rows):
+// the node grid of `in` has the coarse counts in the directions already
+// restricted and the fine counts in the others; `out` has the coarse count in
+// direction dir (0 theta, 1 r, 2 z).  Restricting theta, then r, then z reads
+// each value a few times instead of once per coarse node of its support.
+struct RestrictPass {
+  int dir;
+  int nt_in, nz_in, nr_in[2];
+  int nt_out, nz_out, nr_out[2];
+  long long off1_in, off1_out;  // first stator node of each grid
+};
+
 template <typename Real>
-__global__ void k_mg_restrict(TxView X, const Real* __restrict__ fine, Real* __restrict__ coarse, long long nnc) {
+__global__ void k_mg_restrict_dir(TxView X, RestrictPass P, const Real* __restrict__ in, Real* __restrict__ out,
+                                  long long nout) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nnc) return;
-  const int dom = g >= X.off1c;
-  const long long l = g - (dom ? X.off1c : 0);
-  const int it = (int)(l % X.ntc);
-  const long long l2 = l / X.ntc;
-  const int nrf = dom ? X.nrf[1] : X.nrf[0];
-  const int nrc = dom ? X.nrc[1] : X.nrc[0];
-  const int ir = (int)(l2 % nrc), iz = (int)(l2 / nrc);
-  const int KR = X.rw;
-  const long long ot = X.rt + (long long)it * KR, orr = (dom ? X.rr[1] : X.rr[0]) + (long long)ir * KR,
-                  oz = X.rz + (long long)iz * KR;
-  const long long fbase = dom ? X.off1f : 0;
+  if (g >= nout) return;
+  const int dom = g >= P.off1_out;
+  const long long l = g - (dom ? P.off1_out : 0);
+  const int it = (int)(l % P.nt_out);
+  const long long l2 = l / P.nt_out;
+  const int nro = dom ? P.nr_out[1] : P.nr_out[0];
+  const int nri = dom ? P.nr_in[1] : P.nr_in[0];
+  const int ir = (int)(l2 % nro), iz = (int)(l2 / nro);
+  const int io = P.dir == 0 ? it : (P.dir == 1 ? ir : iz);
+  const long long row = (P.dir == 0 ? X.rt : (P.dir == 1 ? (dom ? X.rr[1] : X.rr[0]) : X.rz)) + (long long)io * X.rw;
+  const long long base = dom ? P.off1_in : 0;
   Real acc[4] = {0, 0, 0, 0};
-  for (int a = 0; a < KR; ++a) {
-    const double wt = X.w[ot + a];
-    if (wt == 0.0) continue;
-    for (int b = 0; b < KR; ++b) {
-      const double wr = X.w[orr + b];
-      if (wr == 0.0) continue;
-      for (int c = 0; c < KR; ++c) {
-        const double wz = X.w[oz + c];
-        if (wz == 0.0) continue;
-        const long long node = fbase + X.idx[ot + a] + (long long)X.ntf * (X.idx[orr + b] + (long long)nrf * X.idx[oz + c]);
-        const Real ww = (Real)(wt * wr * wz);
-        for (int m = 0; m < X.nc; ++m) acc[m] += ww * fine[node * X.nc + m];
-      }
-    }
+  for (int a = 0; a < X.rw; ++a) {
+    const double wa = X.w[row + a];
+    if (wa == 0.0) continue;
+    const int ii = X.idx[row + a];
+    const int jt = P.dir == 0 ? ii : it, jr = P.dir == 1 ? ii : ir, jz = P.dir == 2 ? ii : iz;
+    const long long node = base + jt + (long long)P.nt_in * (jr + (long long)nri * jz);
+    for (int m = 0; m < X.nc; ++m) acc[m] += (Real)wa * in[node * X.nc + m];
   }
-  for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = acc[m];
+  for (int m = 0; m < X.nc; ++m) out[g * X.nc + m] = acc[m];
 }
 
+
 // coarse nodal values of a fine field: the fine field evaluated at the
+// node counts of the two intermediate grids of the three-pass restriction
+static long long restrict_tmp_nodes(const TxView& X) {
+  return (long long)X.ntc * X.nzf * (X.nrf[0] + X.nrf[1] + X.nrc[0] + X.nrc[1]);
+}
+
+// coarse = P^T fine: theta, then r, then z (tmp holds the intermediate grids)
+template <typename Real>
+static int mg_restrict(const TxView& X, void* tmp, const Real* fine, Real* coarse, hipStream_t s) {
+  Real* t1 = (Real*)tmp;
+  const long long n1 = (long long)X.ntc * X.nzf * (X.nrf[0] + X.nrf[1]);
+  Real* t2 = t1 + n1 * X.nc;
+  const long long n2 = (long long)X.ntc * X.nzf * (X.nrc[0] + X.nrc[1]);
+  const long long n3 = (long long)X.ntc * X.nzc * (X.nrc[0] + X.nrc[1]);
+  const RestrictPass p1{0, X.ntf, X.nzf, {X.nrf[0], X.nrf[1]}, X.ntc, X.nzf, {X.nrf[0], X.nrf[1]}, X.off1f,
+                        (long long)X.ntc * X.nrf[0] * X.nzf};
+  const RestrictPass p2{1, X.ntc, X.nzf, {X.nrf[0], X.nrf[1]}, X.ntc, X.nzf, {X.nrc[0], X.nrc[1]}, p1.off1_out,
+                        (long long)X.ntc * X.nrc[0] * X.nzf};
+  const RestrictPass p3{2, X.ntc, X.nzf, {X.nrc[0], X.nrc[1]}, X.ntc, X.nzc, {X.nrc[0], X.nrc[1]}, p2.off1_out,
+                        X.off1c};
+  hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, X, p1, fine, t1, n1);
+  hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, X, p2,
+                     (const Real*)t1, t2, n2);
+  hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, X, p3,
+                     (const Real*)t2, coarse, n3);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
 // coarse nodes (for nested degree-2 meshes a coarse node is a fine node)
 __global__ void k_mg_eval(TxView X, const double* __restrict__ fine, double* __restrict__ coarse, long long nnc) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -737,6 +770,7 @@ struct MGLevel {
   long long n = 0;
   void* b = nullptr;        // V-cycle vectors b, x, r (FP32 or FP64, room for FP64)
   double* inj = nullptr;    // injected state, history, force (coarse levels)
+  void* tr = nullptr;       // intermediate grids of the three-pass restriction to the next level
   double lmax = 0;
 };
 
@@ -897,6 +931,9 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
     if ((e = hipMalloc(&Lv.b, 3 * (size_t)Lv.n * sizeof(double))) != hipSuccess) return mg_err(h, e, "hipMalloc mg");
     if (l > 0 && (e = hipMalloc((void**)&Lv.inj, 3 * (size_t)Lv.n * sizeof(double))) != hipSuccess)
       return mg_err(h, e, "hipMalloc mg");
+    if (l + 1 < mg->L.size() &&
+        (e = hipMalloc(&Lv.tr, (size_t)restrict_tmp_nodes(mg->T[l]) * Lv.h->nc * sizeof(double))) != hipSuccess)
+      return mg_err(h, e, "hipMalloc mg");
   }
   *out = mg;
   return MNS_OK;
@@ -1036,8 +1073,8 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   Solver Sc = make_solver(Lc.h, s, 1);
   MGVec<Real> vc = mg_vec<Real>(Lc, Sc);
   const TxView& X = mg->T[l];
-  hipLaunchKernelGGL(k_mg_restrict<Real>, dim3((unsigned)((Lc.h->nnodes + 255) / 256)), dim3(256), 0, s, X,
-                     (const Real*)v.r, vc.b, (long long)Lc.h->nnodes);
+  if ((rc = mg_restrict<Real>(X, Lv.tr, (const Real*)v.r, vc.b, s)))
+    return set_error(mg->L[0].h, rc, "multigrid restriction");
   if ((rc = launch_constraints<Real>(Lc.h, vc.b, vc.b, Real(0), 1, s))) return rc;
   if ((rc = mg_cycle<Real>(mg, l + 1, o, s))) return rc;
   // x += P x_c (constrained rows of the correction zero)
@@ -1244,6 +1281,7 @@ void mg_free(mns_handle* h) {
     MGLevel& Lv = mg->L[l];
     if (Lv.b) (void)hipFree(Lv.b);
     if (Lv.inj) (void)hipFree(Lv.inj);
+    if (Lv.tr) (void)hipFree(Lv.tr);
     if (l > 0 && Lv.h) mns_destroy(Lv.h);
   }
   if (mg->fine) mns_destroy(mg->fine);
@@ -1258,6 +1296,16 @@ int mg_levels(mns_handle* h, int* levels, hipStream_t) {
   int rc = mg_build(h, 0, &mg);
   if (rc) return rc;
   *levels = (int)mg->L.size();
+  return MNS_OK;
+}
+
+int mg_restrict64(mns_handle* h, int level, const double* x, double* y, hipStream_t s) {
+  MG* mg = nullptr;
+  int rc = mg_build(h, 0, &mg);
+  if (rc) return rc;
+  if (level < 0 || level + 1 >= (int)mg->L.size()) return set_error(h, MNS_ERR_INVALID_ARG, "no such multigrid level");
+  if ((rc = mg_restrict<double>(mg->T[level], mg->L[level].tr, x, y, s)))
+    return set_error(h, MNS_ERR_HIP, "restriction");
   return MNS_OK;
 }
 

@@ -142,3 +142,30 @@ def test_multigrid_picard_coarse_levels_steady():
     for k in ("picard", "picard64", "picard_all"):
         assert out[k][0]["rc"] == 0
         assert out[k][1] < 1e-8
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3)])
+def test_restriction_is_transposed_prolongation(dim, k):
+    """The three-pass restriction of the V-cycle equals P^T: y . (P x) =
+    (P^T y) . x for random x (coarse) and y (fine), on every level pair."""
+    mesh = small_mesh(dim, k, n_theta=16, n_r_rotor=2, n_r_stator=4, n_z=4)
+    g = np.random.default_rng(70 + 10 * dim + k)
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(0.4, 1.0)
+        op.set_linearization(torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda"))
+        levels = op.mg_levels()
+        assert levels >= 2
+        meshes = [mesh]
+        for _ in range(levels - 1):
+            meshes.append(_halved(meshes[-1]))
+        for lv in range(levels - 1):
+            nf, nc = inputs.n_dofs(meshes[lv]), inputs.n_dofs(meshes[lv + 1])
+            x, y = g.uniform(-1, 1, nc), g.uniform(-1, 1, nf)
+            px = torch.zeros(nf, dtype=torch.float64, device="cuda")
+            ry = torch.zeros(nc, dtype=torch.float64, device="cuda")
+            op.mg_prolongate(lv, _dev(x), px)
+            op.mg_restrict(lv, _dev(y), ry)
+            a = float(np.dot(y, px.cpu().numpy()))
+            b = float(np.dot(ry.cpu().numpy(), x))
+            print(f"dim={dim} k={k} level {lv}: y.Px = {a:.15e}, (P^T y).x = {b:.15e}")
+            assert abs(a - b) <= 1e-12 * (abs(a) + np.abs(y).sum())
