@@ -144,6 +144,7 @@ struct mns_handle {
   // volume layout: 1 = lane quad per cell (3D, degree <= 3), 0 = LDS planes
   int quad = 1;
   int picard = 0;               // linearization kind of the next mns_set_linearization (MNS_LIN_*)
+  long long ws_gen = 0;         // incremented whenever the Krylov workspace is reallocated
   hipStream_t stream = nullptr;
   std::string err;
   // optional kernel timing (mns_enable_timing): event pairs per kernel class

@@ -330,12 +330,17 @@ struct Solver {
   }
 
   // Power iteration for the dominant eigenvalue magnitude of D^-1 J (FP64).
-  int estimate_lambda(int iters, double* lam) {
-    // deterministic start vector: 1 on every DoF
-    int rc = launch_fill<double>(t64a, 1.0, n, s);
-    if (rc) return err(rc, "fill");
-    double nrm = std::sqrt((double)n), val = 0;
-    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, t64a, 1.0 / nrm, t64a, n);
+  // warm: t64a already holds a normalized iterate of an earlier estimate
+  // (of a nearby operator), which is continued instead of restarting from 1
+  int estimate_lambda(int iters, double* lam, bool warm = false) {
+    int rc;
+    double nrm = 0, val = 0;
+    if (!warm) {
+      // deterministic start vector: 1 on every DoF
+      if ((rc = launch_fill<double>(t64a, 1.0, n, s))) return err(rc, "fill");
+      nrm = std::sqrt((double)n);
+      hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, t64a, 1.0 / nrm, t64a, n);
+    }
     for (int it = 0; it < iters; ++it) {
       if ((rc = jac64(t64a, t64b))) return rc;
       hipLaunchKernelGGL(k_power_step, dim3(kRedBlocks), dim3(kRedThreads), 0, s, t64b, h->d_diag64, t64a, n,
@@ -478,6 +483,7 @@ int ensure_workspace(mns_handle* h, int m) {
     if ((e = hipMalloc((void**)&h->ws64, (size_t)(2 * m + 9) * n * sizeof(double))) != hipSuccess)
       return set_error(h, MNS_ERR_HIP, std::string("hipMalloc krylov: ") + hipGetErrorString(e));
     h->ws_restart = m;
+    ++h->ws_gen;
   }
   if (!h->ws32 && (e = hipMalloc((void**)&h->ws32, 5 * n * sizeof(float))) != hipSuccess)
     return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -771,6 +777,9 @@ struct MGLevel {
   void* b = nullptr;        // V-cycle vectors b, x, r (FP32 or FP64, room for FP64)
   double* inj = nullptr;    // injected state, history, force (coarse levels)
   void* tr = nullptr;       // intermediate grids of the three-pass restriction to the next level
+  const double* eig_vec = nullptr;  // workspace vector holding the last power-iteration iterate
+  const mns_handle* eig_h = nullptr; // handle whose operator it belongs to
+  long long eig_gen = -1;           // workspace generation of that handle
   double lmax = 0;
 };
 
@@ -996,7 +1005,15 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
       hl->diag_valid = true;
     }
     Solver S = make_solver(hl, s, ws_of(hl, l));
-    if ((rc = S.estimate_lambda(o->eig_iters, &Lv.lmax))) return l ? set_error(h, rc, hl->err) : rc;
+    // spectra after a relinearization or rotation: continue the previous
+    // power iteration of the level (same workspace) for a quarter of the
+    // iterations; a first setup starts from the constant vector
+    const bool warm = Lv.eig_vec == S.t64a && Lv.eig_h == hl && Lv.eig_gen == hl->ws_gen;
+    const int iters = warm ? std::max(4, o->eig_iters / 4) : o->eig_iters;
+    if ((rc = S.estimate_lambda(iters, &Lv.lmax, warm))) return l ? set_error(h, rc, hl->err) : rc;
+    Lv.eig_vec = S.t64a;
+    Lv.eig_h = hl;
+    Lv.eig_gen = hl->ws_gen;
   }
   mg->version = h->lin_version;
   mg->coarse_lin = o->mg_coarse_linearization;
