@@ -293,6 +293,24 @@ int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch);
 int mns_batch_n_dofs(const mns_batch* batch, int64_t* n_total);
 int mns_batch_apply_jacobian(mns_batch* batch, int precision, const void* src, void* dst, void* stream);
 const char* mns_batch_last_error(const mns_batch* batch);
+
+/* Batched FGMRES: solve J_i x_i = rhs_i for every instance of the batch at
+ * once (concatenated vectors, as mns_batch_apply_jacobian).  The instances run
+ * in lockstep: every iteration is one batched preconditioner application, one
+ * batched FP64 Jacobian application and batched Gram-Schmidt reductions
+ * (blocks of one instance each, per-instance sums in a fixed order); the
+ * Hessenberg and Givens updates run per instance on the host.  Preconditioner:
+ * opts->precond -1, MNS_F64 or MNS_F32 (Jacobi-Chebyshev of degree
+ * cheb_degree <= 32 on [lambda_i / cheb_range, lambda_i], lambda_i by power
+ * iteration per instance); restart <= 31.  An instance that has converged
+ * keeps its iterate while the others continue.  reports (count entries, or
+ * NULL) receive per-instance iterations, relative residuals and lambda_max.
+ * The first call allocates (2 * restart + 10) FP64 and 6 FP32 batch vectors.
+ * Synchronizes the stream.
+ * Errors: INVALID_ARG, UNSUPPORTED (multigrid), NOT_CONVERGED (some instance
+ * reached maxit), HIP. */
+int mns_batch_solve(mns_batch* batch, const double* rhs, double* x, const mns_solve_opts* opts,
+                    mns_solve_report* reports, void* stream);
 void mns_batch_destroy(mns_batch* batch);
 
 /* Kernel configuration of the Jacobian application (tuning knobs; every

@@ -33,7 +33,7 @@ EXPORTED = [
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
-    "mns_autotune_kernel_config", "mns_mg_restrict",
+    "mns_autotune_kernel_config", "mns_mg_restrict", "mns_batch_solve",
 ]
 
 
@@ -141,6 +141,7 @@ def lib():
         L.mns_batch_last_error.argtypes = [vp]
         L.mns_batch_last_error.restype = ctypes.c_char_p
         L.mns_batch_destroy.argtypes = [vp]
+        L.mns_batch_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveReport), vp]
         L.mns_batch_destroy.restype = None
         L.mns_last_error.argtypes = [vp]
         L.mns_last_error.restype = ctypes.c_char_p
@@ -400,6 +401,25 @@ class Batch:
             raise ValueError("vector length != batch n_dofs")
         self._check(self._L.mns_batch_apply_jacobian(self._b, prec, _ptr(src), _ptr(dst), _stream()))
         return dst
+
+    def solve(self, rhs, x=None, check=True, **opts):
+        """Batched FGMRES (mns_batch_solve); returns (x, rc, list of per-instance report dicts)."""
+        import torch
+
+        o = Operator.default_solve_opts()
+        for k, v in opts.items():
+            if k == "precond" and isinstance(v, str):
+                v = _PRECOND[v]
+            setattr(o, k, v)
+        if x is None:
+            x = torch.zeros_like(rhs)
+        if rhs.numel() != self.n_dofs or x.numel() != self.n_dofs:
+            raise ValueError("vector length != batch n_dofs")
+        reps = (SolveReport * len(self._ops))()
+        rc = self._L.mns_batch_solve(self._b, _ptr(rhs), _ptr(x), ctypes.byref(o), reps, _stream())
+        if check and rc != MNS_OK:
+            raise MnsError(rc, self._L.mns_batch_last_error(self._b).decode())
+        return x, rc, [r.as_dict() for r in reps]
 
     def close(self):
         if getattr(self, "_b", None):

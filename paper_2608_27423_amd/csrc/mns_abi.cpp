@@ -244,8 +244,36 @@ int mns_batch_apply_jacobian(mns_batch* b, int precision, const void* src, void*
 
 const char* mns_batch_last_error(const mns_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
+int mns_batch_solve(mns_batch* b, const double* rhs, double* x, const mns_solve_opts* opts,
+                    mns_solve_report* reports, void* stream) {
+  if (!b) return MNS_ERR_INVALID_ARG;
+  if (!aligned(rhs, 8) || !aligned(x, 8) || rhs == x) {
+    b->err = "rhs/x must be distinct 8-byte aligned pointers";
+    return MNS_ERR_INVALID_ARG;
+  }
+  mns_solve_opts o;
+  mns_default_solve_opts(&o);
+  if (opts) o = *opts;
+  if (o.precond == MNS_PRECOND_MG || o.precond == MNS_PRECOND_MG64) {
+    b->err = "the batched solver has no multigrid preconditioner";
+    return MNS_ERR_UNSUPPORTED;
+  }
+  if (!(o.rtol > 0) || o.restart < 1 || o.restart > 31 || o.maxit < 1 || o.cheb_degree < 1 || o.cheb_degree > 32 ||
+      !(o.cheb_range > 1) || o.eig_iters < 1 || (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32)) {
+    b->err = "invalid batch solve options (restart 1..31, Chebyshev degree 1..32)";
+    return MNS_ERR_INVALID_ARG;
+  }
+  try {
+    return mns::batch_solve_impl(b, rhs, x, &o, reports, as_stream(stream));
+  } catch (...) {
+    b->err = "exception in batch solve";
+    return MNS_ERR_HIP;
+  }
+}
+
 void mns_batch_destroy(mns_batch* b) {
   if (!b) return;
+  mns::batch_solver_free(b);
   if (b->d_items64) (void)hipFree(b->d_items64);
   if (b->d_items32) (void)hipFree(b->d_items32);
   if (b->d_prefix) (void)hipFree(b->d_prefix);

@@ -184,12 +184,23 @@ struct mns_batch {
   void* d_items32 = nullptr;
   long long* d_prefix = nullptr;
   long long mtot[2] = {0, 0}, vtot[2] = {0, 0}, gtot = 0;
+  // batched solver (mns_batch_solve): vector-block segmentation, workspace
+  long long* d_seg = nullptr;   // block prefix per instance (count + 1), then dof offsets (count + 1)
+  long long nvblk = 0;
+  double* ws = nullptr;         // Krylov and Chebyshev vectors, diagonal
+  float* ws32 = nullptr;
+  int ws_m = 0;
+  double* d_small = nullptr;    // partial sums, per-instance results and coefficients
+  double* h_small = nullptr;    // pinned mirror
   std::string err;
 };
 
 namespace mns {
 
 int batch_build(mns_batch* b);
+int batch_solve_impl(mns_batch* b, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* reps,
+                     hipStream_t s);
+void batch_solver_free(mns_batch* b);
 template <typename Real>
 int launch_batch_jacobian(mns_batch* b, const Real* src, Real* dst, hipStream_t s);
 

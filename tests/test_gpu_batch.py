@@ -86,3 +86,61 @@ def test_batch_rejects_mixed_degrees():
     finally:
         a.close()
         c.close()
+
+
+def _solve_instances(dim):
+    """Transient instances (dt = 0.05) at the smooth state scaled to max 0.5,
+    where the single-level Jacobi-Chebyshev FGMRES converges in tens to a few
+    hundred iterations: uneven sizes in 3D, one size with different angles
+    and viscosities in 2D."""
+    out = []
+    sizes = [(16, 2, 3, 1)] * 3 if dim == 2 else [(16, 2, 2, 2), (8, 1, 2, 3), (12, 2, 1, 2)]
+    for j, (nt, nr, ns, nz) in enumerate(sizes):
+        mesh = small_mesh(dim, 2, n_theta=nt, n_r_rotor=nr, n_r_stator=ns, n_z=nz, nu=0.05 * (1 + 0.3 * j), steady=0,
+                          dt=0.05)
+        s = inputs.smooth_field(mesh, 30 + j)
+        out.append((mesh, 0.3 + 1.7 * j, 0.8, 0.5 * s / np.abs(s).max()))
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precond", ["f32", "f64"])
+def test_batch_solve_matches_direct_solves(dim, precond):
+    """mns_batch_solve on uneven instances: every instance reaches the
+    requested residual, its solution equals the direct sparse solve of the
+    oracle's assembled Jacobian, and its iteration count is that of its own
+    mns_solve within two (only the reduction order of the dots differs)."""
+    import scipy.sparse.linalg as spla
+
+    inst = _solve_instances(dim)
+    ops = []
+    try:
+        rhs, direct = [], []
+        g = np.random.default_rng(50 + dim)
+        for mesh, theta, omega, state in inst:
+            op = binding.Operator(mesh)
+            op.rotate_rotor(theta, omega)
+            hist = np.zeros(op.n_dofs)
+            op.set_linearization(_dev(state), _dev(hist))
+            ops.append(op)
+            b = g.uniform(-1, 1, op.n_dofs)
+            rhs.append(b)
+            direct.append(spla.spsolve(oracle.assemble(oracle_cfg(mesh, theta, omega), state, hist).tocsc(), b))
+        opts = dict(rtol=1e-10, restart=30, maxit=1500, precond=precond, cheb_degree=6)
+        with binding.Batch(ops) as bt:
+            x, rc, reps = bt.solve(_dev(np.concatenate(rhs)), check=False, **opts)
+            xb = x.cpu().numpy()
+            for i, op in enumerate(ops):
+                xs, rep1 = op.solve(_dev(rhs[i]), check=False, **opts)
+                sl = slice(bt.offsets[i], bt.offsets[i] + op.n_dofs)
+                err = relmax(xb[sl], direct[i])
+                print(f"dim={dim} {precond} instance {i} ({op.n_dofs} DoFs): batch its {reps[i]['iterations']} "
+                      f"(single {rep1['iterations']}), rel res {reps[i]['rel_residual']:.1e}, "
+                      f"|x - x_direct| / |x| = {err:.1e}")
+                assert reps[i]["status"] == 0 and reps[i]["rel_residual"] <= 1e-10
+                assert err < 1e-7
+                assert abs(reps[i]["iterations"] - rep1["iterations"]) <= 2
+        assert rc == 0
+    finally:
+        for op in ops:
+            op.close()
