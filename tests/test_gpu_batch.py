@@ -144,3 +144,40 @@ def test_batch_solve_matches_direct_solves(dim, precond):
     finally:
         for op in ops:
             op.close()
+
+
+def test_batch_solve_edge_cases():
+    """One instance with a zero right-hand side (x = 0, converged at once)
+    next to one that iterates; a one-instance batch equals its single solve;
+    unsupported options are rejected."""
+    inst = _solve_instances(3)[:2]
+    ops = []
+    try:
+        for mesh, theta, omega, state in inst:
+            op = binding.Operator(mesh)
+            op.rotate_rotor(theta, omega)
+            op.set_linearization(_dev(state), _dev(np.zeros(op.n_dofs)))
+            ops.append(op)
+        opts = dict(rtol=1e-10, restart=30, maxit=1500, precond="f32", cheb_degree=6)
+        with binding.Batch(ops) as bt:
+            b = np.random.default_rng(8).uniform(-1, 1, bt.n_dofs)
+            b[: ops[0].n_dofs] = 0.0
+            x0 = _dev(np.ones(bt.n_dofs))  # the zero-rhs instance must return exactly 0
+            x, rc, reps = bt.solve(_dev(b), x0, check=False, **opts)
+            xb = x.cpu().numpy()
+            assert rc == 0
+            assert np.all(xb[: ops[0].n_dofs] == 0.0) and reps[0]["iterations"] == 0
+            assert reps[1]["status"] == 0 and reps[1]["rel_residual"] <= 1e-10
+            for bad, code in ((dict(restart=32), binding.MNS_ERR_INVALID_ARG),
+                              (dict(precond="mg"), binding.MNS_ERR_UNSUPPORTED),
+                              (dict(cheb_degree=33), binding.MNS_ERR_INVALID_ARG)):
+                _, rc2, _ = bt.solve(_dev(b), check=False, **dict(opts, **bad))
+                assert rc2 == code
+        with binding.Batch(ops[1:]) as one:
+            b1 = np.random.default_rng(9).uniform(-1, 1, one.n_dofs)
+            _, rc, reps = one.solve(_dev(b1), check=False, **opts)
+            _, rep1 = ops[1].solve(_dev(b1), check=False, **opts)
+            assert rc == 0 and reps[0]["iterations"] == rep1["iterations"]
+    finally:
+        for op in ops:
+            op.close()
