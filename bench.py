@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 METRIC = "DoFs/s of stabilized NS Jacobian vmult (FP64 vs FP32) + GMRES solve time to 1e-8"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# FP64 flops that the quad-layout volume kernel executes per 3D Q2 cell, from
+# its SQ_INSTS_VALU_{FMA,MUL,ADD}_F64 counters on the 32,768-cell mesh
+# (64 lanes x (2 FMA + MUL + ADD) per dispatch / cells); the fourth lane of a
+# quad repeats the third slice, so a quarter of them is duplicate work
+QUAD_Q2_FLOP_PER_CELL = 19048
 
 
 def parse():
@@ -64,7 +69,7 @@ def dominant_kernel(mesh, fused, layout, real="double"):
     dim, k = mesh["dim"], mesh["degree"]
     if fused < 0:
         cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * (mesh["n_z"] if dim == 3 else 1)
-        fused = 2 if cells >= (1 << 19) else 1
+        fused = 2 if cells >= (1 << 18) else 1
     fused = 1 if fused == 1 else 0
     quad = layout == 1 and dim == 3 and k == 2
     if quad:
@@ -205,6 +210,29 @@ def batch_leg(args, dev, sync):
     return out
 
 
+def copy_bandwidth(dev, sync, nbytes=1 << 30, reps=20):
+    """Device-to-device copy rate (bytes read + written per second) of a
+    buffer far larger than the 256 MB Infinity Cache: the practical HBM
+    ceiling beside the 8 TB/s spec figure."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sync()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    sync()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
+
+
 def timed(fn, sync):
     sync()
     t0 = time.perf_counter()
@@ -298,6 +326,13 @@ def main():
     kname = dominant_kernel(mesh, args.fused, args.volume_layout)
     tb = measured_traffic(name, kname)
     traffic = None if tb is None else tb / (vol_ms64 * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth(dev, sync)
+    valu = None
+    if "_quad<" in kname and mesh["dim"] == 3 and mesh["degree"] == 2:
+        tflops = QUAD_Q2_FLOP_PER_CELL * cells / (vol_ms64 * 1e-3) / 1e12
+        valu = {"fp64_flop_per_cell": QUAD_Q2_FLOP_PER_CELL, "achieved_TFLOPs": tflops,
+                "peak_TFLOPs": FP64_PEAK_TFLOPS, "frac": tflops / FP64_PEAK_TFLOPS,
+                "note": "FP64 VALU flops executed by the volume part (counters), over the dominant kernel's time"}
     rec["fp64"] = {"ms_per_vmult": ms64, "dofs_per_s": n / (ms64 * 1e-3), "volume_kernel_ms": vol_ms64,
                    "mortar_kernel_ms": t64["ms_mortar"] / max(1, t64["n_mortar"]),
                    "other_kernels_ms": t64["ms_other"] / max(1, t64["n_volume"])}
@@ -435,7 +470,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": tb, "traffic_source": f"profiles/traffic_{name}.txt" if tb else None,
                      "kernel": kname, "kernel_ms": vol_ms64,
-                     "algorithmic_bytes_per_launch": bytes64},
+                     "algorithmic_bytes_per_launch": bytes64,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
+                     "fp64_valu": valu},
         "cpu_baseline": cpu,
         "hot_path": rec,
     }

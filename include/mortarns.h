@@ -319,7 +319,7 @@ void mns_batch_destroy(mns_batch* batch);
  * mortar faces; 0: two launches on the caller's stream; 2: two launches, the
  * mortar kernel on a second stream of the library (default priority) joined
  * back to the caller's stream before the gather; -1 (default): 1 below
- * 524,288 cells, 2 from there on.  volume_layout = 1 (default): in 3D
+ * 262,144 cells, 2 from there on.  volume_layout = 1 (default): in 3D
  * with degree <= 3 a quad of four lanes owns a cell and the theta
  * contractions exchange values between lanes without LDS; 0: nine (degree
  * 2) or sixteen (degree 3) lanes per cell with the r and theta contractions

@@ -583,6 +583,7 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
   for (int m = 0; m < NC; ++m) acc[m] = 0;
   const int cbase = dom ? (int)G.cell_off1 : 0;
   const size_t cstride = (size_t)S::NPT * G.ncells;
+  Real cv[2][2][2][NC];  // candidate contributions [z][r][theta][comp]
   if (strip) {
     // strip layout of the quad volume kernel: batches of 16 theta-consecutive
     // cells, 16 k + 1 node columns per (comp, z, r) node position; a node on a
@@ -598,12 +599,18 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
     sb[1] = (sb[0] == 0 ? nbt : sb[0]) - 1;
     sj[1] = S16;
     sv[1] = sj[0] == 0;
+    // every candidate's loads are issued before any of them is summed (an
+    // accumulation inside each candidate's branch waits for that branch's
+    // loads, one memory round trip per candidate); the sum keeps the fixed
+    // candidate order
 #pragma unroll
     for (int z = 0; z < 2; ++z)
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
+#pragma unroll
+          for (int m = 0; m < NC; ++m) cv[z][r][t][m] = 0;
           if (!(zv[z] && rv[r] && sv[t])) continue;
           const int ring = (cbase + G.n_theta * (rc[r] + nrd * zc[z])) / 16;
           const size_t pos = (size_t)(zb[z] * N + rb[r]);
@@ -611,7 +618,7 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
           const Real* e = t == 0 ? E + pos * pstride + (size_t)(ring + sb[0]) * S16 + sj[0]
                                  : Eb + pos * nblk + (ring + sb[1]);
 #pragma unroll
-          for (int m = 0; m < NC; ++m) acc[m] += e[(size_t)m * N * N * st];
+          for (int m = 0; m < NC; ++m) cv[z][r][t][m] = e[(size_t)m * N * N * st];
         }
   } else {
 #pragma unroll
@@ -620,12 +627,14 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
+#pragma unroll
+          for (int m = 0; m < NC; ++m) cv[z][r][t][m] = 0;
           if (!(zv[z] && rv[r] && tv[t])) continue;
           const int cell = cbase + tc[t] + G.n_theta * (rc[r] + nrd * zc[z]);
           const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + rb[r] * N + ta[t];
           const Real* e = E + (size_t)loc * G.ncells + cell;
 #pragma unroll
-          for (int m = 0; m < NC; ++m) acc[m] += e[m * cstride];
+          for (int m = 0; m < NC; ++m) cv[z][r][t][m] = e[m * cstride];
         }
   }
   // mortar cell sides: every node of a rotor outer-ring cell or a stator
@@ -633,6 +642,13 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
   int bm = -1;
   if (dom == 0 && ir >= k * (G.nr[0] - 1)) bm = ir - k * (G.nr[0] - 1);
   if (dom == 1 && ir <= k) bm = ir;
+  Real mv[2][2][NC];  // mortar contributions [z][theta][comp], loaded before any sum
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int m = 0; m < NC; ++m) mv[z][t][m] = 0;
   if (bm >= 0 && Em) {
     const int nfaces = G.n_theta * G.nz;
     const int nsides = 2 * nfaces;
@@ -646,9 +662,23 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
         const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + bm * N + ta[t];
         const Real* e = Em + (size_t)loc * nsides + cs;
 #pragma unroll
-        for (int m = 0; m < NC; ++m) acc[m] += e[m * mstride];
+        for (int m = 0; m < NC; ++m) mv[z][t][m] = e[m * mstride];
       }
   }
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int m = 0; m < NC; ++m) acc[m] += cv[z][r][t][m];
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int m = 0; m < NC; ++m) acc[m] += mv[z][t][m];
   const bool vf = vel_fixed<Real, DIM>(G, dom, ir, iz);
   const bool pf = p_fixed(G, dom, it, ir, iz);
   Real* d = dst + g * NC;
@@ -1638,7 +1668,7 @@ struct Piece {
 };
 
 template <typename Real, int DIM, int N>
-__device__ inline void mortar_pieces(const Geom<Real>& G, const MortarTab<Real, N>& M, int side, int ct, int cz,
+__device__ inline void mortar_pieces(const Geom<Real>& G, int mstep, int side, int ct, int cz,
                                      Piece<Real, DIM, N> (&p)[2]) {
   const int nt = G.n_theta;
   if (side == 1) {
@@ -1647,11 +1677,11 @@ __device__ inline void mortar_pieces(const Geom<Real>& G, const MortarTab<Real, 
     p[0].jface = j;
     p[1].seg = 1;
     p[1].jface = j;
-    p[0].other = CellId{0, ((j - M.m - 1) % nt + nt) % nt, G.nr[0] - 1, cz};
-    p[1].other = CellId{0, ((j - M.m) % nt + nt) % nt, G.nr[0] - 1, cz};
+    p[0].other = CellId{0, ((j - mstep - 1) % nt + nt) % nt, G.nr[0] - 1, cz};
+    p[1].other = CellId{0, ((j - mstep) % nt + nt) % nt, G.nr[0] - 1, cz};
   } else {
     const int i = ct;
-    const int j0 = (M.m + i) % nt, j1 = (M.m + i + 1) % nt;
+    const int j0 = (mstep + i) % nt, j1 = (mstep + i + 1) % nt;
     p[0].seg = 1;
     p[0].jface = j0;
     p[1].seg = 0;
@@ -1718,19 +1748,63 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
   auto& coef = sm.coef;
   const int nfaces = G.n_theta * G.nz;
   const int nsides = 2 * nfaces;
-  {
-    // table copy to LDS: all loads issued before the first store (a plain
-    // loop waits for every load in turn); blocks have 64 lanes
-    const int* srcw = (const int*)Mp;
-    int* dstw = (int*)&M;
-    constexpr int NW = (int)(sizeof(MortarTab<Real, N>) / sizeof(int));
-    constexpr int IT = (NW + 63) / 64;
-    int w[IT];
+  // ---- phase A: evaluation.  Lane = (face, piece, side, component).  The
+  // table copy's loads go first; the pairing of faces needs only the offset
+  // m (read from the table in global memory), so the point angles and, when
+  // they fit in registers, the lane's nodal values are loaded next, all
+  // before the first wait.  Lanes past the last face read a valid face and
+  // store nothing.
+  constexpr bool EARLY = NZ * N * N <= 32;
+  const int* srcw = (const int*)Mp;
+  constexpr int NW = (int)(sizeof(MortarTab<Real, N>) / sizeof(int));
+  constexpr int IT = (NW + 63) / 64;
+  int w[IT];
 #pragma unroll
-    for (int j = 0; j < IT; ++j) {
-      const int i = (int)threadIdx.x + 64 * j;
-      w[j] = i < NW ? srcw[i] : 0;
-    }
+  for (int j = 0; j < IT; ++j) {
+    const int i = (int)threadIdx.x + 64 * j;
+    w[j] = i < NW ? srcw[i] : 0;
+  }
+  const int fl = threadIdx.x / MS::LPF;
+  const int lr = threadIdx.x % MS::LPF;
+  const int m = lr % NC, sd = (lr / NC) % 2, pc = lr / (2 * NC);
+  const int fs0 = mblock * FPB + fl;  // face-side index: side * nfaces + face
+  const bool act = fl < FPB && fs0 < nsides;
+  const int fs = act ? fs0 : nsides - 1;
+  const int side = fs / nfaces, f = fs % nfaces;
+  const int ct = f % G.n_theta, cz = f / G.n_theta;
+  Piece<Real, DIM, N> P[2];
+  mortar_pieces<Real, DIM, N>(G, Mp->m, side, ct, cz, P);
+  // lane-dependent piece picked by selects (an indexed access would put the
+  // two pieces in private memory)
+  const int seg = pc ? P[1].seg : P[0].seg;
+  const int jface = pc ? P[1].jface : P[0].jface;
+  const CellId other = pc ? P[1].other : P[0].other;
+  const CellId C = sd == 0 ? CellId{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz} : other;
+  const int cside = sd == 0 ? side : 1 - side;
+  Real tg[N][2];  // cos, sin at the piece's points
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) tg[q][c2] = mtrig[(((size_t)jface * 2 + seg) * N + q) * 2 + c2];
+  Real X[EARLY ? NZ : 1][N][N];
+  unsigned fixbits = 0;  // constrained entries, applied after the barrier
+  if constexpr (EARLY) {
+#pragma unroll
+    for (int c = 0; c < NZ; ++c)
+#pragma unroll
+      for (int b2 = 0; b2 < N; ++b2)
+#pragma unroll
+        for (int a2 = 0; a2 < N; ++a2) {
+          int it, ir, iz;
+          const long long nd = node_of<Real, DIM>(G, k, C, a2, b2, c, it, ir, iz);
+          const bool vfx = vel_fixed<Real, DIM>(G, C.dom, ir, iz), pfx = p_fixed(G, C.dom, it, ir, iz);
+          const bool fixed = (mask != 0) & ((m < DIM) ? vfx : pfx);
+          X[c][b2][a2] = src[nd * NC + m];
+          fixbits |= (fixed ? 1u : 0u) << ((c * N + b2) * N + a2);
+        }
+  }
+  {
+    int* dstw = (int*)&M;
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
       const int i = (int)threadIdx.x + 64 * j;
@@ -1738,29 +1812,14 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     }
   }
   __syncthreads();
-  // ---- phase A: evaluation
   {
-    const int fl = threadIdx.x / MS::LPF;
-    const int r = threadIdx.x % MS::LPF;
-    const int m = r % NC, sd = (r / NC) % 2, pc = r / (2 * NC);
-    const int fs = mblock * FPB + fl;  // face-side index: side * nfaces + face
-    if (fl < FPB && fs < nsides) {
-      const int side = fs / nfaces, f = fs % nfaces;
-      const int ct = f % G.n_theta, cz = f / G.n_theta;
-      Piece<Real, DIM, N> P[2];
-      mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
-      // lane-dependent piece picked by selects (an indexed access would put
-      // the two pieces in private memory)
-      const int seg = pc ? P[1].seg : P[0].seg;
-      const int jface = pc ? P[1].jface : P[0].jface;
-      const CellId other = pc ? P[1].other : P[0].other;
-      const CellId C = sd == 0 ? CellId{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz} : other;
-      const int cside = sd == 0 ? side : 1 - side;
+    if (act) {
       if (sd == 0 && m == 0) {
         // point angles of this piece (one lane per face and piece)
+#pragma unroll
         for (int q = 0; q < N; ++q)
-          for (int c2 = 0; c2 < 2; ++c2)
-            trg[fl][pc][q][c2] = mtrig[(((size_t)jface * 2 + seg) * N + q) * 2 + c2];
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2) trg[fl][pc][q][c2] = tg[q][c2];
       }
       // r reduction at the interface: F0 = face value, F1 = normal derivative
       Real F0[NZ][N], F1[NZ][N];
@@ -1778,12 +1837,17 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
           const Real fv = M.FV[cside][b2], fd = M.FD[cside][b2];
 #pragma unroll
           for (int a2 = 0; a2 < N; ++a2) {
-            int it, ir, iz;
-            const long long nd = node_of<Real, DIM>(G, k, C, a2, b2, c, it, ir, iz);
-            const bool vfx = vel_fixed<Real, DIM>(G, C.dom, ir, iz), pfx = p_fixed(G, C.dom, it, ir, iz);
-            const bool fixed = (mask != 0) & ((m < DIM) ? vfx : pfx);
-            const Real xv = src[nd * NC + m];
-            const Real x = fixed ? Real(0) : xv;
+            Real x;
+            if constexpr (EARLY) {
+              x = ((fixbits >> ((c * N + b2) * N + a2)) & 1u) ? Real(0) : X[c][b2][a2];
+            } else {
+              int it, ir, iz;
+              const long long nd = node_of<Real, DIM>(G, k, C, a2, b2, c, it, ir, iz);
+              const bool vfx = vel_fixed<Real, DIM>(G, C.dom, ir, iz), pfx = p_fixed(G, C.dom, it, ir, iz);
+              const bool fixed = (mask != 0) & ((m < DIM) ? vfx : pfx);
+              const Real xv = src[nd * NC + m];
+              x = fixed ? Real(0) : xv;
+            }
             F0[c][a2] += fv * x;
             F1[c][a2] += fd * x;
           }
@@ -1839,7 +1903,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
-    mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
+    mortar_pieces<Real, DIM, N>(G, M.m, side, f % G.n_theta, f / G.n_theta, P);
     const int qt = q % N, qz = q / N;
     const Real idr_o = side == 0 ? M.inv_dr[0] : M.inv_dr[1];
     const Real idr_x = side == 0 ? M.inv_dr[1] : M.inv_dr[0];
@@ -1895,7 +1959,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
-    mortar_pieces<Real, DIM, N>(G, M, side, f % G.n_theta, f / G.n_theta, P);
+    mortar_pieces<Real, DIM, N>(G, M.m, side, f % G.n_theta, f / G.n_theta, P);
     Real k0[N], k1[N];
 #pragma unroll
     for (int a2 = 0; a2 < N; ++a2) {
@@ -2006,7 +2070,7 @@ __global__ __launch_bounds__(64) void k_mortar_diag(Geom<Real> G, Tab1D<Real, N>
   const int ct = f % G.n_theta, cz = f / G.n_theta;
   const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
   Piece<Real, DIM, N> P[2];
-  mortar_pieces<Real, DIM, N>(G, M, side, ct, cz, P);
+  mortar_pieces<Real, DIM, N>(G, M.m, side, ct, cz, P);
   const Real nu = G.nu, tau = M.tau_pen[side];
   for (int node = threadIdx.x; node < NPT; node += blockDim.x) {
     const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
@@ -2123,8 +2187,9 @@ static Geom<Real> make_geom(const mns_handle* h) {
 static int hip_check(mns_handle* h, const char* what);
 
 // cell count from which the automatic launch mode runs the mortar kernel on a
-// second stream (measured: slower at 32k cells, faster at 2M cells)
-constexpr long long kConcurrentCells = 1 << 19;
+// second stream (measured on 3D Q2 meshes: slower at 32k cells, faster at
+// 262k, 524k and 2M cells)
+constexpr long long kConcurrentCells = 1 << 18;
 
 // second stream (default priority) and fork/join events, created on first use
 static int ensure_aux_stream(mns_handle* h) {
