@@ -47,6 +47,7 @@ def parse():
                     help="-1: automatic; 1: volume and mortar in one launch; 2: mortar on a second stream; 0: sequential")
     ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k <= 3); 0: LDS planes")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching leg (48 uneven instances)")
+    ap.add_argument("--no-copy-bandwidth", action="store_true", help="skip the device-copy bandwidth measurement")
     ap.add_argument("--transient", action="store_true",
                     help="also time one BDF2 + Newton step (transient workloads; rotor advances omega * dt)")
     return ap.parse_args()
@@ -326,7 +327,7 @@ def main():
     kname = dominant_kernel(mesh, args.fused, args.volume_layout)
     tb = measured_traffic(name, kname)
     traffic = None if tb is None else tb / (vol_ms64 * 1e-3) / 1e9
-    copy_gbs = copy_bandwidth(dev, sync)
+    copy_gbs = None if args.no_copy_bandwidth else copy_bandwidth(dev, sync)
     valu = None
     if "_quad<" in kname and mesh["dim"] == 3 and mesh["degree"] == 2:
         tflops = QUAD_Q2_FLOP_PER_CELL * cells / (vol_ms64 * 1e-3) / 1e12
@@ -471,7 +472,7 @@ def main():
                      "traffic_bytes_per_launch": tb, "traffic_source": f"profiles/traffic_{name}.txt" if tb else None,
                      "kernel": kname, "kernel_ms": vol_ms64,
                      "algorithmic_bytes_per_launch": bytes64,
-                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
                      "fp64_valu": valu},
         "cpu_baseline": cpu,
         "hot_path": rec,
