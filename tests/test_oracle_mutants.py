@@ -36,7 +36,8 @@ MUTANTS = [
     ("mesh velocity rotating the wrong way",
      "w[0] = -M->P.omega * x[1];",
      "w[0] = M->P.omega * x[1];",
-     [(pins.test_ale_convection_of_rigid_rotation, {})]),
+     [(pins.test_ale_convection_of_rigid_rotation, {}),
+      (pins.test_taylor_green_transient_with_rotating_rotor, {})]),
     ("mapping term missing from the physical Hessian",
      "for (int m = 0; m < d; ++m) s -= gp[m] * X2[m][p][q];",
      "(void)X2;",
@@ -44,7 +45,8 @@ MUTANTS = [
     ("BDF2 coefficient 1/dt instead of 3/(2 dt)",
      "return M->P.steady ? 0.0 : 1.5 / M->P.dt;",
      "return M->P.steady ? 0.0 : 1.0 / M->P.dt;",
-     [(pins.test_mass_and_viscous_coefficients, dict(steady=0))]),
+     [(pins.test_mass_and_viscous_coefficients, dict(steady=0)),
+      (pins.test_taylor_green_transient_with_rotating_rotor, {})]),
     ("tau: viscous factor 3 instead of 9",
      "9.0 * (4.0 * nu / (h * h))",
      "3.0 * (4.0 * nu / (h * h))",
