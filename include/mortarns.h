@@ -168,6 +168,11 @@ typedef struct {
                                   between the copies of its input and output) are captured once per call into a
                                   HIP graph on a library stream and replayed on `stream` every iteration; 0: launched
                                   one by one.  Ignored while kernel timing is enabled.  Same arithmetic either way */
+  double cheb_lambda_factor;   /* Jacobi-Chebyshev polynomial preconditioner (here and in mns_batch_solve): upper end
+                                  of the interval = this factor times the power-iteration estimate of lambda_max,
+                                  lower end = upper / cheb_range.  The estimate converges from below; a factor a
+                                  little above 1 keeps the top of the spectrum inside the interval (default 1.05;
+                                  valid range [1, 4]).  The V-cycle smoothers use the estimate itself */
 } mns_solve_opts;
 
 typedef struct {
@@ -175,7 +180,7 @@ typedef struct {
   int restarts;
   int status;             /* MNS_OK or MNS_ERR_NOT_CONVERGED */
   double rel_residual;    /* true ||rhs - J x||_2 / ||rhs||_2, recomputed in FP64 */
-  double lambda_max;      /* estimate used by the Chebyshev preconditioner */
+  double lambda_max;      /* power-iteration estimate (before cheb_lambda_factor) */
   double seconds;         /* wall time of the call */
   int vmults_f64, vmults_f32;
 } mns_solve_report;

@@ -55,7 +55,22 @@ class SolveOpts(ctypes.Structure):
         ("mg_levels", ctypes.c_int), ("mg_smooth_degree", ctypes.c_int), ("mg_smooth_range", ctypes.c_double),
         ("mg_coarse_degree", ctypes.c_int), ("mg_coarse_linearization", ctypes.c_int),
         ("mg_fine_linearization", ctypes.c_int), ("use_graph", ctypes.c_int),
+        ("cheb_lambda_factor", ctypes.c_double),
     ]
+
+
+def _set_fields(struct, opts):
+    """Set ctypes fields by name; unknown names are errors (a plain setattr
+    would add a Python attribute that the library never sees)."""
+    names = {f for f, _ in struct._fields_}
+    for k, v in opts.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r} for {type(struct).__name__}")
+        if k == "precond" and isinstance(v, str):
+            v = _PRECOND[v]
+        if k in ("mg_coarse_linearization", "mg_fine_linearization") and isinstance(v, str):
+            v = _LIN[v]
+        setattr(struct, k, v)
 
 
 class SolveReport(ctypes.Structure):
@@ -264,12 +279,7 @@ class Operator:
         import torch
 
         o = self.default_solve_opts()
-        for k, v in opts.items():
-            if k == "precond" and isinstance(v, str):
-                v = _PRECOND[v]
-            if k in ("mg_coarse_linearization", "mg_fine_linearization") and isinstance(v, str):
-                v = _LIN[v]
-            setattr(o, k, v)
+        _set_fields(o, opts)
         if x is None:
             x = torch.zeros_like(rhs)
         rep = SolveReport()
@@ -285,14 +295,8 @@ class Operator:
         guess and receives the solution.  Returns the report as a dict."""
         o = StepOpts()
         self._L.mns_default_step_opts(ctypes.byref(o))
-        for k2, v in opts.items():
-            setattr(o, k2, v)
-        for k2, v in (linear or {}).items():
-            if k2 == "precond" and isinstance(v, str):
-                v = _PRECOND[v]
-            if k2 in ("mg_coarse_linearization", "mg_fine_linearization") and isinstance(v, str):
-                v = _LIN[v]
-            setattr(o.linear, k2, v)
+        _set_fields(o, opts)
+        _set_fields(o.linear, linear or {})
         for t in (u_n, u_next, u_nm1, force):
             if t is not None and (t.numel() != self.n_dofs or t.dtype.itemsize != 8):
                 raise ValueError("vectors must be float64 of length n_dofs")
@@ -407,10 +411,7 @@ class Batch:
         import torch
 
         o = Operator.default_solve_opts()
-        for k, v in opts.items():
-            if k == "precond" and isinstance(v, str):
-                v = _PRECOND[v]
-            setattr(o, k, v)
+        _set_fields(o, opts)
         if x is None:
             x = torch.zeros_like(rhs)
         if rhs.numel() != self.n_dofs or x.numel() != self.n_dofs:

@@ -259,7 +259,8 @@ int mns_batch_solve(mns_batch* b, const double* rhs, double* x, const mns_solve_
     return MNS_ERR_UNSUPPORTED;
   }
   if (!(o.rtol > 0) || o.restart < 1 || o.restart > 31 || o.maxit < 1 || o.cheb_degree < 1 || o.cheb_degree > 32 ||
-      !(o.cheb_range > 1) || o.eig_iters < 1 || (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32)) {
+      !(o.cheb_range > 1) || o.eig_iters < 1 || (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32) ||
+      !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0)) {
     b->err = "invalid batch solve options (restart 1..31, Chebyshev degree 1..32)";
     return MNS_ERR_INVALID_ARG;
   }
@@ -345,6 +346,7 @@ void mns_default_solve_opts(mns_solve_opts* o) {
   o->mg_coarse_linearization = MNS_LIN_NEWTON;
   o->mg_fine_linearization = MNS_LIN_NEWTON;
   o->use_graph = 1;
+  o->cheb_lambda_factor = 1.05;
 }
 
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
@@ -364,7 +366,7 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
       o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1) ||
       (o.mg_coarse_linearization != MNS_LIN_NEWTON && o.mg_coarse_linearization != MNS_LIN_PICARD) ||
       (o.mg_fine_linearization != MNS_LIN_NEWTON && o.mg_fine_linearization != MNS_LIN_PICARD) ||
-      (o.use_graph != 0 && o.use_graph != 1))
+      (o.use_graph != 0 && o.use_graph != 1) || !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
   mns_solve_report rep{};
   int rc;

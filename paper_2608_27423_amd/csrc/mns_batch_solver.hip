@@ -402,7 +402,7 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   const int deg = o->cheb_degree;
   std::vector<double> inv_theta(count), cheb((size_t)deg * count * 2);
   for (int i = 0; i < count; ++i) {
-    const double beta = lam[i], alpha = lam[i] / o->cheb_range;
+    const double beta = lam[i] * o->cheb_lambda_factor, alpha = beta / o->cheb_range;
     const double theta = 0.5 * (beta + alpha), delta = 0.5 * (beta - alpha), sigma = theta / delta;
     inv_theta[i] = 1.0 / theta;
     double rho = 1.0 / sigma;

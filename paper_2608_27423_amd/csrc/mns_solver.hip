@@ -1197,7 +1197,7 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
     for (; j < m && total < o->maxit; ++j, ++total) {
       double* Vj = S.V + (size_t)j * n;
       double* Zj = S.Z + (size_t)j * n;
-      if ((rc = S.precondition(o, lmax, Vj, Zj))) return rc;
+      if ((rc = S.precondition(o, lmax * o->cheb_lambda_factor, Vj, Zj))) return rc;
       if ((rc = S.jac64(Zj, S.w))) return rc;
       // classical Gram-Schmidt with one reorthogonalization when the norm
       // drops below 0.7 of its value before the projection

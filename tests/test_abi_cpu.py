@@ -53,3 +53,16 @@ def test_null_arguments():
     assert L.mns_rotate_rotor(None, 0.0, 0.0) == binding.MNS_ERR_INVALID_ARG
     assert L.mns_apply_jacobian(None, 0, None, None, None) == binding.MNS_ERR_INVALID_ARG
     assert L.mns_last_error(None) == b"null handle"
+
+
+def test_solve_options_are_checked_by_name():
+    """Options reach the library only through the struct's own fields: an
+    unknown name is an error (a plain setattr would be silently ignored), and
+    the string forms map to the header's constants."""
+    o = binding.Operator.default_solve_opts()
+    assert o.cheb_lambda_factor == pytest.approx(1.05)
+    with pytest.raises(TypeError):
+        binding._set_fields(o, {"cheb_degre": 8})
+    binding._set_fields(o, {"precond": "mg64", "mg_coarse_linearization": "picard", "cheb_degree": 9})
+    assert (o.precond, o.mg_coarse_linearization, o.cheb_degree) == (
+        binding.MNS_PRECOND_MG64, binding.MNS_LIN_PICARD, 9)

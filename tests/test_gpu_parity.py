@@ -250,6 +250,39 @@ def test_solve_2d_workload(precond):
     assert rel <= 1.01e-8
 
 
+def test_chebyshev_interval_factor():
+    """mns_solve_opts.cheb_lambda_factor widens the top of the Chebyshev
+    interval: the reported lambda_max (the power-iteration estimate) does not
+    depend on it, both settings reach 1e-8 against the oracle's operator, and
+    factors outside [1, 4] are rejected."""
+    name = "annulus2d_q2_32x4"
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    st = inputs.state_for(name)
+    st = st / np.abs(st).max()
+    n = st.size
+    cfg = oracle_cfg(mesh, theta, mesh["omega"])
+    b = oracle.apply_jacobian(cfg, st, inputs.uniform(n, inputs.SOLUTION_SEED[name]))
+    reps = {}
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, mesh["omega"])
+        op.set_linearization(_dev(st))
+        for fac in (1.0, 1.05, 1.3):
+            x, info = op.solve(_dev(b), restart=250, maxit=2000, precond="f32", cheb_degree=4,
+                               cheb_lambda_factor=fac)
+            r = b - oracle.apply_jacobian(cfg, st, x.cpu().numpy())
+            assert info["rc"] == 0 and np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
+            reps[fac] = info
+        for bad in (0.99, 4.5):
+            _, info = op.solve(_dev(b), check=False, cheb_lambda_factor=bad)
+            assert info["rc"] == binding.MNS_ERR_INVALID_ARG
+        with pytest.raises(TypeError):
+            op.solve(_dev(b), cheb_lambda_fact=1.1)
+    print({f: (i["iterations"], i["lambda_max"]) for f, i in reps.items()})
+    assert reps[1.0]["lambda_max"] == reps[1.05]["lambda_max"] == reps[1.3]["lambda_max"]
+    assert reps[1.0]["iterations"] != reps[1.3]["iterations"]
+
+
 @pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3)])
 def test_autotune_keeps_parity(dim, k):
     """mns_autotune_kernel_config picks one of the launch configurations, sets
