@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused", type=int, default=-1,
                     help="-1: automatic; 1: volume and mortar in one launch; 2: mortar on a second stream; 0: sequential")
-    ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k <= 3); 0: LDS planes")
+    ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k = 2); 0: LDS planes")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching leg (48 uneven instances)")
     ap.add_argument("--no-copy-bandwidth", action="store_true", help="skip the device-copy bandwidth measurement")
     ap.add_argument("--transient", action="store_true",

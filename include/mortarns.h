@@ -325,10 +325,11 @@ void mns_batch_destroy(mns_batch* batch);
  * mortar kernel on a second stream of the library (default priority) joined
  * back to the caller's stream before the gather; -1 (default): 1 below
  * 262,144 cells, 2 from there on.  volume_layout = 1 (default): in 3D
- * with degree <= 3 a quad of four lanes owns a cell and the theta
- * contractions exchange values between lanes without LDS; 0: nine (degree
- * 2) or sixteen (degree 3) lanes per cell with the r and theta contractions
- * staged through LDS (the only layout in 2D and for degree >= 4).  Takes
+ * with degree 2 a quad of four lanes owns a cell and the theta
+ * contractions exchange values between lanes without LDS; 0: (k+1)^2 lanes
+ * per cell (nine for degree 2, sixteen for degree 3) with the r and theta
+ * contractions staged through LDS, the layout used in 2D and for degree >= 3
+ * whatever the setting.  Takes
  * effect on the next apply call.
  * Errors: INVALID_ARG. */
 typedef struct {
@@ -339,7 +340,7 @@ int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg);
 int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg);
 
 /* Autotuner of the launch configuration: times `reps` FP64 applications of
- * every launch mode (fused_launch 0, 1, 2) and, in 3D with degree <= 3, both
+ * every launch mode (fused_launch 0, 1, 2) and, in 3D with degree 2, both
  * volume layouts, on the handle's own mesh and linearization, and sets the
  * fastest (written to *chosen when non-null).  All configurations compute the
  * same product; the choice depends on the mesh size (tail of the fused
