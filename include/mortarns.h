@@ -168,11 +168,12 @@ typedef struct {
                                   between the copies of its input and output) are captured once per call into a
                                   HIP graph on a library stream and replayed on `stream` every iteration; 0: launched
                                   one by one.  Ignored while kernel timing is enabled.  Same arithmetic either way */
-  double cheb_lambda_factor;   /* Jacobi-Chebyshev polynomial preconditioner (here and in mns_batch_solve): upper end
-                                  of the interval = this factor times the power-iteration estimate of lambda_max,
-                                  lower end = upper / cheb_range.  The estimate converges from below; a factor a
-                                  little above 1 keeps the top of the spectrum inside the interval (default 1.05;
-                                  valid range [1, 4]).  The V-cycle smoothers use the estimate itself */
+  double cheb_lambda_factor;   /* every Chebyshev interval (the polynomial preconditioner here and in mns_batch_solve,
+                                  the V-cycle smoothers and coarse polynomial): upper end = this factor times the
+                                  power-iteration estimate of lambda_max, lower end = upper / (cheb_range or
+                                  mg_smooth_range).  The estimate converges from below; a factor a little above 1
+                                  keeps the top of the spectrum inside the interval (default 1.05; valid range
+                                  [1, 4]) */
 } mns_solve_opts;
 
 typedef struct {

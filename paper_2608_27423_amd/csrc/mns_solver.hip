@@ -1056,17 +1056,19 @@ static MGVec<Real> mg_vec(MGLevel& Lv, const Solver& S) {
 
 // x = Chebyshev smoothing of J x = b at level l (from x = 0 when zero)
 template <typename Real>
-static int mg_smooth(MG* mg, size_t l, const Real* b, Real* x, bool zero, int deg, double range, hipStream_t s) {
+static int mg_smooth(MG* mg, size_t l, const Real* b, Real* x, bool zero, int deg, double range, double fac,
+                     hipStream_t s) {
   MGLevel& Lv = mg->L[l];
+  const double lmax = fac * Lv.lmax;
   mns_handle* hl = Lv.h;
   Solver S = make_solver(hl, s, ws_of(hl, l));
   MGVec<Real> v = mg_vec<Real>(Lv, S);
   const unsigned g = grid_for(Lv.n);
-  if (zero) return S.chebyshev<Real>(b, x, v.cr, v.cd, v.ct, v.diag, deg, Lv.lmax, range);
+  if (zero) return S.chebyshev<Real>(b, x, v.cr, v.cd, v.ct, v.diag, deg, lmax, range);
   int rc = launch_jacobian<Real>(hl, x, v.ct, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, b, Real(-1), (const Real*)v.ct, v.r, Lv.n);
-  if ((rc = S.chebyshev<Real>(v.r, v.cx, v.cr, v.cd, v.ct, v.diag, deg, Lv.lmax, range))) return rc;
+  if ((rc = S.chebyshev<Real>(v.r, v.cx, v.cr, v.cd, v.ct, v.diag, deg, lmax, range))) return rc;
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)x, Real(1), (const Real*)v.cx, x, Lv.n);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
@@ -1078,8 +1080,11 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   Solver S = make_solver(hl, s, ws_of(hl, l));
   MGVec<Real> v = mg_vec<Real>(Lv, S);
   int rc;
-  if (l + 1 == mg->L.size()) return mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_coarse_degree, o->mg_smooth_range, s);
-  if ((rc = mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_smooth_degree, o->mg_smooth_range, s))) return rc;
+  if (l + 1 == mg->L.size())
+    return mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_coarse_degree, o->mg_smooth_range, o->cheb_lambda_factor, s);
+  if ((rc = mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_smooth_degree, o->mg_smooth_range, o->cheb_lambda_factor,
+                            s)))
+    return rc;
   // residual, restricted with constrained rows zero on both levels
   if ((rc = launch_jacobian<Real>(hl, v.x, v.ct, s))) return rc;
   const unsigned g = grid_for(Lv.n);
@@ -1101,7 +1106,7 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.x, Real(1), (const Real*)v.r, v.x,
                      Lv.n);
   if (hipGetLastError() != hipSuccess) return set_error(mg->L[0].h, MNS_ERR_HIP, "multigrid kernels");
-  return mg_smooth<Real>(mg, l, v.b, v.x, false, o->mg_smooth_degree, o->mg_smooth_range, s);
+  return mg_smooth<Real>(mg, l, v.b, v.x, false, o->mg_smooth_degree, o->mg_smooth_range, o->cheb_lambda_factor, s);
 }
 
 // V-cycle z = B v in three parts (the middle one touches only the levels'

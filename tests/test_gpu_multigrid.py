@@ -169,3 +169,34 @@ def test_restriction_is_transposed_prolongation(dim, k):
             b = float(np.dot(ry.cpu().numpy(), x))
             print(f"dim={dim} k={k} level {lv}: y.Px = {a:.15e}, (P^T y).x = {b:.15e}")
             assert abs(a - b) <= 1e-12 * (abs(a) + np.abs(y).sum())
+
+
+def test_multigrid_degree3_workload_time_step_jacobian():
+    """The 7.3M-DoF degree-3 workload: the Jacobian of one BDF2 step (dt =
+    0.01, history of a state at rest in time) at the smooth state is solved to
+    1e-8 by FGMRES(30) with the V-cycle (degree 3 -> 2, then halved meshes,
+    Picard coarse levels, smoothing intervals from 60 power iterations), with
+    FP32 and with FP64 smoothing; the true residual is recomputed in FP64 with
+    the handle's operator."""
+    name = "annulus3d_q3_64x16x32"
+    dt = 0.01
+    mesh = dict(inputs.mesh(name), steady=0, dt=dt)
+    theta = inputs.rotor_angle(name)
+    s = inputs.smooth_field(mesh, inputs.STATE_SEED[name])
+    s /= np.abs(s).max()
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, mesh["omega"])
+        st = _dev(s)
+        op.set_linearization(st, hist=-1.5 / dt * st)
+        rhs = op.apply_jacobian(_dev(inputs.uniform(op.n_dofs, inputs.SOLUTION_SEED[name])))
+        its = {}
+        for prec in ("mg", "mg64"):
+            x = torch.zeros_like(rhs)
+            _, info = op.solve(rhs, x, rtol=1e-8, restart=30, maxit=300, precond=prec,
+                               mg_coarse_linearization="picard", eig_iters=60)
+            true = float((rhs - op.apply_jacobian(x)).norm() / rhs.norm())
+            print(f"{prec}: {info['iterations']} its, {info['seconds']:.3f} s, true residual {true:.2e}, "
+                  f"levels {op.mg_levels()}")
+            assert info["rc"] == 0 and true <= 1.01e-8
+            its[prec] = info["iterations"]
+    assert abs(its["mg"] - its["mg64"]) <= 2
