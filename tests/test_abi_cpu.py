@@ -66,3 +66,16 @@ def test_solve_options_are_checked_by_name():
     binding._set_fields(o, {"precond": "mg64", "mg_coarse_linearization": "picard", "cheb_degree": 9})
     assert (o.precond, o.mg_coarse_linearization, o.cheb_degree) == (
         binding.MNS_PRECOND_MG64, binding.MNS_LIN_PICARD, 9)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message instead of running."""
+    import json
+    import subprocess
+    import sys
+
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    msg = json.loads(p.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
