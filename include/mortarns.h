@@ -326,11 +326,12 @@ void mns_batch_destroy(mns_batch* batch);
  * mortar kernel on a second stream of the library (default priority) joined
  * back to the caller's stream before the gather; -1 (default): 1 below
  * 262,144 cells, 2 from there on.  volume_layout = 1 (default): in 3D
- * with degree 2 a quad of four lanes owns a cell and the theta
- * contractions exchange values between lanes without LDS; 0: (k+1)^2 lanes
- * per cell (nine for degree 2, sixteen for degree 3) with the r and theta
- * contractions staged through LDS, the layout used in 2D and for degree >= 3
- * whatever the setting.  Takes
+ * with degree 2 (both precisions) and degree 3 (FP32) a quad of four lanes
+ * owns a cell and the theta contractions exchange values between lanes
+ * without LDS; 0: (k+1)^2 lanes per cell (nine for degree 2, sixteen for
+ * degree 3) with the r and theta contractions staged through LDS, the layout
+ * used in 2D, for degree >= 4 and for FP64 at degree 3 whatever the
+ * setting.  Takes
  * effect on the next apply call.
  * Errors: INVALID_ARG. */
 typedef struct {

@@ -1119,7 +1119,7 @@ __device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
 // transposed CD applied along r, z and, across the quad, theta) and finally
 // interpolated back to the nodes.
 template <typename Real, int N>
-__device__ inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
+__device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                    const Real* __restrict__ lin, const Real* __restrict__ src,
                                    Real* __restrict__ E, bool strip) {
   constexpr int DIM = 3, NC = 4, NT = 4;
@@ -2272,6 +2272,11 @@ static int do_gather(mns_handle* h, const Real* E, const Real* Em, const Real* s
   return hip_check(h, "gather kernel");
 }
 
+// the quad volume layout exists for 3D degree 2 and, in FP32, degree 3 (the
+// FP64 instance of degree 3 would need more registers than a lane holds)
+template <typename Real, int DIM, int N>
+constexpr bool kQuadLayout = DIM == 3 && (N == 3 || (N == 4 && sizeof(Real) == 4));
+
 template <typename Real, int DIM, int N>
 static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
   using S = Shape<Real, DIM, N>;
@@ -2280,7 +2285,7 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
   Real* E = sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32;
   Real* Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
-  constexpr bool kQuad = DIM == 3 && N == 3;
+  constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   const bool quad = kQuad && h->quad;
   // strip layout of the local results: batches of 16 cells stay inside one
   // ring when the ring length is a multiple of 16
@@ -2414,11 +2419,11 @@ __global__ __launch_bounds__(256) void k_batch_gather(const BatchItem<Real>* __r
 }
 
 // block counts of one instance in the batched launch (the layouts of
-// do_jacobian's default configuration: quad volume layout for 3D degree 2)
+// do_jacobian's default configuration: quad volume layout where it exists)
 template <typename Real, int DIM, int N>
 static void batch_blocks(const mns_handle* h, long long* nmb, long long* nvb, int* strip) {
   using S = Shape<Real, DIM, N>;
-  constexpr bool kQuad = DIM == 3 && N == 3;
+  constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   const int cpw = kQuad ? QuadShape<Real, N>::CPW : S::CPW;
   *nvb = (h->ncells + cpw - 1) / cpw;
   *nmb = (2LL * h->desc.n_theta * h->nz + MortarShape<Real, DIM, N>::FPB - 1) / MortarShape<Real, DIM, N>::FPB;
@@ -2503,7 +2508,7 @@ static int do_batch(mns_batch* b, const Real* src, Real* dst, hipStream_t s) {
   const long long* gs = b->d_prefix + (size_t)4 * (count + 1);
   const Tab1D<Real, N> T = make_tab<Real, N>(b->hs[0]);
   const long long blocks = b->mtot[p] + b->vtot[p];
-  constexpr bool kQuad = DIM == 3 && N == 3;
+  constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   if constexpr (kQuad)
     hipLaunchKernelGGL((k_batch_jacobian_quad<Real, N>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs, count,
                        T, b->k, src);
