@@ -28,7 +28,7 @@ FP64_PEAK_TFLOPS = 78.6
 # its SQ_INSTS_VALU_{FMA,MUL,ADD}_F64 counters on the 32,768-cell mesh
 # (64 lanes x (2 FMA + MUL + ADD) per dispatch / cells); the fourth lane of a
 # quad repeats the third slice, so a quarter of them is duplicate work
-QUAD_Q2_FLOP_PER_CELL = 19048
+QUAD_Q2_FLOP_PER_CELL = 19160
 
 
 def parse():
@@ -70,11 +70,11 @@ def algorithmic_bytes_volume(mesh, n_dofs, real_bytes):
 def dominant_kernel(mesh, fused, layout, real="double"):
     """Name of the launch that the volume timer brackets."""
     dim, k = mesh["dim"], mesh["degree"]
+    quad = layout == 1 and dim == 3 and (k == 2 or (k == 3 and real == "float"))
     if fused < 0:
         cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * (mesh["n_z"] if dim == 3 else 1)
-        fused = 2 if cells >= (1 << 18) else 1
+        fused = 2 if cells >= (1 << 18) else (0 if quad and real == "double" and cells >= (1 << 15) else 1)
     fused = 1 if fused == 1 else 0
-    quad = layout == 1 and dim == 3 and k == 2
     if quad:
         return f"mns::k_jacobian_{'fused' if fused else 'volume'}_quad<{real}, {k + 1}>"
     return f"mns::k_jacobian_{'fused' if fused else 'volume'}<{real}, {dim}, {k + 1}>"

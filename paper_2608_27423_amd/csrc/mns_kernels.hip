@@ -1118,7 +1118,13 @@ __device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
 // coefficients of every point are accumulated in the collocation basis (the
 // transposed CD applied along r, z and, across the quad, theta) and finally
 // interpolated back to the nodes.
-template <typename Real, int N>
+//
+// ULDS: the field values at the Gauss points are kept in LDS (18 KB per
+// FP64 wavefront) instead of registers and the linearization data of each
+// point is loaded when the point starts (no prefetch ring).  That takes the
+// FP64 kernel from about 370 registers per lane to under 256, i.e. from one
+// to two wavefronts per SIMD, which hide each other's memory latency.
+template <typename Real, int N, bool ULDS = false>
 __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                    const Real* __restrict__ lin, const Real* __restrict__ src,
                                    Real* __restrict__ E, bool strip) {
@@ -1145,14 +1151,17 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
     trc = tr[0];
     trs = tr[1];
   }
-  constexpr int PF = MNS_QUAD_PREFETCH > 0 ? MNS_QUAD_PREFETCH : 1;
+  constexpr int PF = ULDS ? 1 : (MNS_QUAD_PREFETCH > 0 ? MNS_QUAD_PREFETCH : 1);
   const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
   Real ring[PF][LL::SIZE];
+  if constexpr (!ULDS) {
 #pragma unroll
-  for (int i = 0; i < PF; ++i)
-    if (i < Q::PL) load_lin<Real, LL::SIZE>(lbase + ((i / N) * Q::PL + (i % N) * N) * LL::SIZE, ring[i]);
+    for (int i = 0; i < PF; ++i)
+      if (i < Q::PL) load_lin<Real, LL::SIZE>(lbase + ((i / N) * Q::PL + (i % N) * N) * LL::SIZE, ring[i]);
+  }
 
   // nodal values of the slice, constrained entries read as zero
+  __shared__ Real Us[ULDS ? NC : 1][ULDS ? N : 1][ULDS ? N : 1][64];  // point values (ULDS), lane-owned columns
   Real U[NC][N][N];  // [comp][r][z]
   {
     int it = k * C.ct + ts;
@@ -1207,7 +1216,9 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
           for (int b = 0; b < N; ++b) v += T.V[qj][b] * A[b][q];
           Real xs[N];
           quad_rotate<N>(v, xs);
-          U[m][qj][q] = quad_dot<N>(cV, xs);
+          const Real uq = quad_dot<N>(cV, xs);
+          if constexpr (ULDS) Us[m][qj][q][lane] = uq;
+          else U[m][qj][q] = uq;
         }
 #if MNS_QUAD_SCHED_BARRIER
       __builtin_amdgcn_sched_barrier(0);
@@ -1266,29 +1277,45 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
 #pragma unroll
     for (int qj = 0; qj < N; ++qj) {
       const int pt = q * N + qj;
+      if constexpr (ULDS) {
+        load_lin<Real, LL::SIZE>(lbase + ((pt / N) * Q::PL + (pt % N) * N) * LL::SIZE, lv);
+      } else {
 #pragma unroll
-      for (int j = 0; j < LL::SIZE; ++j) lv[j] = ring[0][j];
+        for (int j = 0; j < LL::SIZE; ++j) lv[j] = ring[0][j];
 #pragma unroll
-      for (int i = 0; i + 1 < PF; ++i)
+        for (int i = 0; i + 1 < PF; ++i)
 #pragma unroll
-        for (int j = 0; j < LL::SIZE; ++j) ring[i][j] = ring[i + 1][j];
-      if (pt + PF < Q::PL)
-        load_lin<Real, LL::SIZE>(lbase + (((pt + PF) / N) * Q::PL + ((pt + PF) % N) * N) * LL::SIZE, ring[PF - 1]);
+          for (int j = 0; j < LL::SIZE; ++j) ring[i][j] = ring[i + 1][j];
+        if (pt + PF < Q::PL)
+          load_lin<Real, LL::SIZE>(lbase + (((pt + PF) / N) * Q::PL + ((pt + PF) % N) * N) * LL::SIZE, ring[PF - 1]);
+      }
       RefVal<Real, DIM> rv[DIM], rp;
 #pragma unroll
       for (int m = 0; m < NC; ++m) {
         const bool vel = m < DIM;
         RefVal<Real, DIM>& R = vel ? rv[m] : rp;
-        const Real v = U[m][qj][q];
-        Real d1 = T.CD[qj][0] * U[m][0][q], e1 = T.CD[q][0] * U[m][qj][0];
-        Real d2 = vel ? T.CDD[qj][0] * U[m][0][q] : Real(0), e2 = vel ? T.CDD[q][0] * U[m][qj][0] : Real(0);
+        // point values of this component along r (at q) and z (at qj)
+        Real ur[N], uz[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          if constexpr (ULDS) {
+            ur[j] = Us[m][j][q][lane];
+            uz[j] = Us[m][qj][j][lane];
+          } else {
+            ur[j] = U[m][j][q];
+            uz[j] = U[m][qj][j];
+          }
+        }
+        const Real v = ur[qj];
+        Real d1 = T.CD[qj][0] * ur[0], e1 = T.CD[q][0] * uz[0];
+        Real d2 = vel ? T.CDD[qj][0] * ur[0] : Real(0), e2 = vel ? T.CDD[q][0] * uz[0] : Real(0);
 #pragma unroll
         for (int j = 1; j < N; ++j) {
-          d1 += T.CD[qj][j] * U[m][j][q];
-          e1 += T.CD[q][j] * U[m][qj][j];
+          d1 += T.CD[qj][j] * ur[j];
+          e1 += T.CD[q][j] * uz[j];
           if (vel) {
-            d2 += T.CDD[qj][j] * U[m][j][q];
-            e2 += T.CDD[q][j] * U[m][qj][j];
+            d2 += T.CDD[qj][j] * ur[j];
+            e2 += T.CDD[q][j] * uz[j];
           }
         }
         Real xs[N];
@@ -1415,7 +1442,7 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_volume_quad(Geom<
                                                              const Real* __restrict__ lin,
                                                              const Real* __restrict__ src, Real* __restrict__ E,
                                                              int strip) {
-  volume_quad<Real, N>(G, T, k, blockIdx.x, lin, src, E, strip != 0);
+  volume_quad<Real, N, sizeof(Real) == 8>(G, T, k, blockIdx.x, lin, src, E, strip != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -2190,6 +2217,11 @@ static int hip_check(mns_handle* h, const char* what);
 // second stream (measured on 3D Q2 meshes: slower at 32k cells, faster at
 // 262k, 524k and 2M cells)
 constexpr long long kConcurrentCells = 1 << 18;
+// cell count from which the automatic mode launches the FP64 quad volume
+// kernel separately (its LDS-staged form) below kConcurrentCells (measured:
+// 45.9 against 48.9 us per vmult at 32,768 cells; the multigrid levels below
+// it are faster fused)
+constexpr long long kSeparateQuad64Cells = 1 << 15;
 
 // second stream (default priority) and fork/join events, created on first use
 static int ensure_aux_stream(mns_handle* h) {
@@ -2293,9 +2325,14 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   const int cpw = quad ? QuadShape<Real, N>::CPW : S::CPW;
   const unsigned blocks = (unsigned)((G.ncells + cpw - 1) / cpw);
   int rc;
-  // launch mode; automatic: one fused launch for small meshes (the mortar
-  // work is a latency tail there), the concurrent second stream for large ones
-  const int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
+  // launch mode; automatic: the concurrent second stream for large meshes;
+  // below that one fused launch (the mortar work is a latency tail there),
+  // except for the FP64 quad layout from 32,768 cells on, whose separate
+  // volume kernel keeps its point values in LDS and runs two wavefronts per
+  // SIMD (the fused kernel cannot: its mortar blocks need the LDS); on
+  // smaller meshes the third launch costs more than the occupancy gains
+  const bool sep64 = quad && sizeof(Real) == 8 && G.ncells >= kSeparateQuad64Cells;
+  const int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : (sep64 ? 0 : 1));
   if (mode == 1) {
     // one launch: mortar face blocks first, then volume cell blocks
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);

@@ -1,8 +1,9 @@
 """Batched Jacobian application (mns_batch_*): instances of uneven sizes,
 angles, viscosities, steady and transient, in one volume + mortar launch and
 one gather launch.  Every slice must equal the instance's own
-mns_apply_jacobian product bit for bit (same arithmetic, FP64 and FP32), and
-the FP64 slices match the oracle to the parity bar."""
+mns_apply_jacobian product in the same launch form (fused_launch = 1) bit for
+bit (same arithmetic, FP64 and FP32), agree with the default launch to
+rounding, and the FP64 slices match the oracle to the parity bar."""
 import math
 
 import numpy as np
@@ -54,8 +55,16 @@ def test_batch_equals_single_applications(dim, k):
             y32 = b.apply_jacobian(_dev(x, torch.float32)).cpu().numpy()
             for i, op in enumerate(ops):
                 sl = slice(b.offsets[i], b.offsets[i] + op.n_dofs)
+                # default launch (for FP64 degree 2 in 3D: separate volume
+                # kernel with its point values in LDS) agrees to rounding
+                d64 = op.apply_jacobian(_dev(x[sl])).cpu().numpy()
+                assert relmax(y64[sl], d64) <= 1e-15, f"instance {i} FP64 default launch"
+                # the batch's own launch form (volume and mortar blocks in one
+                # launch) gives the same bits
+                op.set_kernel_config(fused_launch=1)
                 s64 = op.apply_jacobian(_dev(x[sl])).cpu().numpy()
                 s32 = op.apply_jacobian(_dev(x[sl], torch.float32)).cpu().numpy()
+                op.set_kernel_config(fused_launch=-1)
                 assert np.array_equal(y64[sl], s64), f"instance {i} FP64"
                 assert np.array_equal(y32[sl], s32), f"instance {i} FP32"
                 mesh, theta, omega = inst[i]
@@ -68,6 +77,7 @@ def test_batch_equals_single_applications(dim, k):
             ops[1].set_linearization(_dev(states[1]), None if hists[1] is None else _dev(hists[1]))
             y64b = b.apply_jacobian(_dev(x)).cpu().numpy()
             sl = slice(b.offsets[1], b.offsets[1] + ops[1].n_dofs)
+            ops[1].set_kernel_config(fused_launch=1)
             assert np.array_equal(y64b[sl], ops[1].apply_jacobian(_dev(x[sl])).cpu().numpy())
     finally:
         for op in ops:
