@@ -73,8 +73,10 @@ def dominant_kernel(mesh, fused, layout, real="double"):
     quad = layout == 1 and dim == 3 and (k == 2 or (k == 3 and real == "float"))
     if fused < 0:
         cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * (mesh["n_z"] if dim == 3 else 1)
-        fused = 2 if cells >= (1 << 18) else (0 if quad and real == "double" and cells >= (1 << 15) else 1)
+        fused = 2 if cells >= (1 << 18) else 1
     fused = 1 if fused == 1 else 0
+    if quad and fused and real == "double" and k == 2:
+        return "mns::k_jacobian_fused_quad_lds<3>"
     if quad:
         return f"mns::k_jacobian_{'fused' if fused else 'volume'}_quad<{real}, {k + 1}>"
     return f"mns::k_jacobian_{'fused' if fused else 'volume'}<{real}, {dim}, {k + 1}>"
@@ -382,7 +384,7 @@ def main():
     traffic = None if tb is None else tb / (vol_ms64 * 1e-3) / 1e9
     copy_gbs = None if args.no_copy_bandwidth else copy_bandwidth(dev, sync)
     valu = None
-    if "_quad<" in kname and mesh["dim"] == 3 and mesh["degree"] == 2:
+    if "_quad" in kname and mesh["dim"] == 3 and mesh["degree"] == 2:
         tflops = QUAD_Q2_FLOP_PER_CELL * cells / (vol_ms64 * 1e-3) / 1e12
         valu = {"fp64_flop_per_cell": QUAD_Q2_FLOP_PER_CELL, "achieved_TFLOPs": tflops,
                 "peak_TFLOPs": FP64_PEAK_TFLOPS, "frac": tflops / FP64_PEAK_TFLOPS,
@@ -452,6 +454,20 @@ def main():
     ms_tuned, _ = run(x64, y64, max(args.steps // 2, 10), 3)
     rec["autotune"] = {"default": default_cfg, "chosen": chosen, "ms_per_vmult_chosen": ms_tuned}
     op.set_kernel_config(**default_cfg)
+
+    # the volume kernel on its own (separate launches, fused_launch = 0): its
+    # roofline without the mortar blocks that share the fused launch
+    if mesh["dim"] == 3 and args.fused < 0:
+        op.set_kernel_config(fused_launch=0, volume_layout=args.volume_layout)
+        ms_sep, t_sep = run(x64, y64, args.steps, min(args.warmup, 20))
+        op.set_kernel_config(**default_cfg)
+        vol_sep = t_sep["ms_volume"] / max(1, t_sep["n_volume"])
+        ach_sep = bytes64 / (vol_sep * 1e-3) / 1e9
+        rec["separate_volume_launch"] = {
+            "kernel": dominant_kernel(mesh, 0, args.volume_layout), "ms_per_vmult": ms_sep, "kernel_ms": vol_sep,
+            "achieved_GBs": ach_sep, "frac_of_8TBs": ach_sep / HBM_PEAK_GBS,
+            "frac_of_measured_copy": ach_sep / copy_gbs if copy_gbs else None,
+            "mortar_kernel_ms": t_sep["ms_mortar"] / max(1, t_sep["n_mortar"])}
 
     if not args.no_batch:
         rec["batch"] = batch_leg(args, dev, sync)

@@ -324,10 +324,11 @@ void mns_batch_destroy(mns_batch* batch);
  * mortar faces are integrated in one launch whose first blocks take the
  * mortar faces; 0: two launches on the caller's stream; 2: two launches, the
  * mortar kernel on a second stream of the library (default priority) joined
- * back to the caller's stream before the gather; -1 (default): 2 from
- * 262,144 cells on; below that 0 for the FP64 quad layout from 32,768 cells
- * on (its separate volume kernel keeps the point values in LDS and runs two
- * wavefronts per SIMD) and 1 otherwise.  volume_layout = 1 (default): in 3D
+ * back to the caller's stream before the gather; -1 (default): 1 below
+ * 262,144 cells, 2 from there on.  In FP64 with the quad layout the volume
+ * blocks of every mode keep their Gauss-point values in LDS (two wavefronts
+ * per SIMD); in the fused launch the mortar blocks then take fewer faces so
+ * that both kinds fit the same LDS.  volume_layout = 1 (default): in 3D
  * with degree 2 (both precisions) and degree 3 (FP32) a quad of four lanes
  * owns a cell and the theta contractions exchange values between lanes
  * without LDS; 0: (k+1)^2 lanes per cell (nine for degree 2, sixteen for

@@ -1127,7 +1127,7 @@ __device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
 template <typename Real, int N, bool ULDS = false>
 __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                    const Real* __restrict__ lin, const Real* __restrict__ src,
-                                   Real* __restrict__ E, bool strip) {
+                                   Real* __restrict__ E, bool strip, Real* __restrict__ us = nullptr) {
   constexpr int DIM = 3, NC = 4, NT = 4;
   using Q = QuadShape<Real, N>;
   using LL = LinLayout<DIM>;
@@ -1161,7 +1161,8 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
   }
 
   // nodal values of the slice, constrained entries read as zero
-  __shared__ Real Us[ULDS ? NC : 1][ULDS ? N : 1][ULDS ? N : 1][64];  // point values (ULDS), lane-owned columns
+  // ULDS: point values in LDS at us[((comp * N + r) * N + z) * 64 + lane]
+  // (lane-owned columns, 4 N^2 values per lane)
   Real U[NC][N][N];  // [comp][r][z]
   {
     int it = k * C.ct + ts;
@@ -1217,7 +1218,7 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
           Real xs[N];
           quad_rotate<N>(v, xs);
           const Real uq = quad_dot<N>(cV, xs);
-          if constexpr (ULDS) Us[m][qj][q][lane] = uq;
+          if constexpr (ULDS) us[((m * N + qj) * N + q) * 64 + lane] = uq;
           else U[m][qj][q] = uq;
         }
 #if MNS_QUAD_SCHED_BARRIER
@@ -1299,8 +1300,8 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           if constexpr (ULDS) {
-            ur[j] = Us[m][j][q][lane];
-            uz[j] = Us[m][qj][j][lane];
+            ur[j] = us[((m * N + j) * N + q) * 64 + lane];
+            uz[j] = us[((m * N + qj) * N + j) * 64 + lane];
           } else {
             ur[j] = U[m][j][q];
             uz[j] = U[m][qj][j];
@@ -1442,7 +1443,9 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_volume_quad(Geom<
                                                              const Real* __restrict__ lin,
                                                              const Real* __restrict__ src, Real* __restrict__ E,
                                                              int strip) {
-  volume_quad<Real, N, sizeof(Real) == 8>(G, T, k, blockIdx.x, lin, src, E, strip != 0);
+  constexpr bool kLds = sizeof(Real) == 8;
+  __shared__ Real us[kLds ? 4 * N * N * 64 : 1];
+  volume_quad<Real, N, kLds>(G, T, k, blockIdx.x, lin, src, E, strip != 0, us);
 }
 
 // ---------------------------------------------------------------------------
@@ -1731,7 +1734,7 @@ __device__ inline void mortar_pieces(const Geom<Real>& G, int mstep, int side, i
 //   Phase C, lane = (face, component, radial node row): the transposed sum
 //     factorization integrates the coefficients against the own cell's test
 //     functions; the result is stored as Em[comp][local node][face].
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, int BUDGET = 36000>
 struct MortarShape {
   static constexpr int NZ = (DIM == 3) ? N : 1;
   static constexpr int NC = DIM + 1;
@@ -1745,13 +1748,13 @@ struct MortarShape {
   static constexpr int PQ = NC * NE + ((DIM == 3 && N >= 5) ? 0 : 1);
   static constexpr int PER_FACE = (2 * 2 * NQ * PQ + 2 * NQ * PQ) * (int)sizeof(Real);
   static constexpr int FPB0 = 64 / LPF;
-  static constexpr int FPB_LDS = 36000 / PER_FACE > 0 ? 36000 / PER_FACE : 1;
+  static constexpr int FPB_LDS = BUDGET / PER_FACE > 0 ? BUDGET / PER_FACE : 1;
   static constexpr int FPB = FPB0 < FPB_LDS ? FPB0 : FPB_LDS;
 };
 
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, int BUDGET = 36000>
 struct MortarSmem {
-  using MS = MortarShape<Real, DIM, N>;
+  using MS = MortarShape<Real, DIM, N, BUDGET>;
   MortarTab<Real, N> M;
   Real trg[MS::FPB][2][N][2];
   // [face][piece][own=0 / other=1][point][comp * NE + quantity]; each point's
@@ -1761,13 +1764,13 @@ struct MortarSmem {
   Real coef[MS::FPB][2][MS::NQ][MS::PQ];
 };
 
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, int BUDGET = 36000>
 __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int mblock,
                                     const MortarTab<Real, N>* __restrict__ Mp, const Real* __restrict__ mtrig,
                                     const Real* __restrict__ src, Real* __restrict__ Em, int mask,
-                                    MortarSmem<Real, DIM, N>& sm) {
+                                    MortarSmem<Real, DIM, N, BUDGET>& sm) {
   using S = Shape<Real, DIM, N>;
-  using MS = MortarShape<Real, DIM, N>;
+  using MS = MortarShape<Real, DIM, N, BUDGET>;
   constexpr int NC = MS::NC, NZ = MS::NZ, NQ = MS::NQ, NE = MS::NE, FPB = MS::FPB;
   MortarTab<Real, N>& M = sm.M;
   auto& trg = sm.trg;
@@ -2081,6 +2084,31 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_fused_quad(Geom<R
   else volume_quad<Real, N>(G, T, k, blockIdx.x - nmb, lin, src, E, strip != 0);
 }
 
+// Fused launch of the FP64 quad layout with LDS-staged volume blocks: the
+// volume blocks keep their point values in the block's LDS and the mortar
+// blocks take fewer faces per block, so that both fit the LDS of two
+// wavefronts per SIMD (the kernel's registers allow two).
+constexpr int kLdsQuadBytes = 4 * 3 * 3 * 64 * 8;  // 3D Q2 FP64 point values
+template <int N>
+__global__ __launch_bounds__(64) void k_jacobian_fused_quad_lds(Geom<double> G, Tab1D<double, N> T, int k, int nmb,
+                                                                const double* __restrict__ lin,
+                                                                const MortarTab<double, N>* __restrict__ Mp,
+                                                                const double* __restrict__ mtrig,
+                                                                const double* __restrict__ src,
+                                                                double* __restrict__ E, double* __restrict__ Em,
+                                                                int strip) {
+  using MSm = MortarSmem<double, 3, N, kLdsQuadBytes>;
+  constexpr int UB = 4 * N * N * 64 * (int)sizeof(double);
+  constexpr int SB = (int)sizeof(MSm) > UB ? (int)sizeof(MSm) : UB;
+  __shared__ __align__(16) unsigned char smem[SB];
+  if ((int)blockIdx.x < nmb)
+    mortar_block<double, 3, N, kLdsQuadBytes>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1,
+                                              *reinterpret_cast<MSm*>(smem));
+  else
+    volume_quad<double, N, true>(G, T, k, blockIdx.x - nmb, lin, src, E, strip != 0,
+                                 reinterpret_cast<double*>(smem));
+}
+
 // Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
 // i (other side zero) gives, tested with the same basis function,
 // nu tau phi^2 - nu phi (grad phi . n) for velocity rows and 0 for pressure rows.
@@ -2217,11 +2245,6 @@ static int hip_check(mns_handle* h, const char* what);
 // second stream (measured on 3D Q2 meshes: slower at 32k cells, faster at
 // 262k, 524k and 2M cells)
 constexpr long long kConcurrentCells = 1 << 18;
-// cell count from which the automatic mode launches the FP64 quad volume
-// kernel separately (its LDS-staged form) below kConcurrentCells (measured:
-// 45.9 against 48.9 us per vmult at 32,768 cells; the multigrid levels below
-// it are faster fused)
-constexpr long long kSeparateQuad64Cells = 1 << 15;
 
 // second stream (default priority) and fork/join events, created on first use
 static int ensure_aux_stream(mns_handle* h) {
@@ -2325,14 +2348,9 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   const int cpw = quad ? QuadShape<Real, N>::CPW : S::CPW;
   const unsigned blocks = (unsigned)((G.ncells + cpw - 1) / cpw);
   int rc;
-  // launch mode; automatic: the concurrent second stream for large meshes;
-  // below that one fused launch (the mortar work is a latency tail there),
-  // except for the FP64 quad layout from 32,768 cells on, whose separate
-  // volume kernel keeps its point values in LDS and runs two wavefronts per
-  // SIMD (the fused kernel cannot: its mortar blocks need the LDS); on
-  // smaller meshes the third launch costs more than the occupancy gains
-  const bool sep64 = quad && sizeof(Real) == 8 && G.ncells >= kSeparateQuad64Cells;
-  const int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : (sep64 ? 0 : 1));
+  // launch mode; automatic: one fused launch for small meshes (the mortar
+  // work is a latency tail there), the concurrent second stream for large ones
+  const int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
   if (mode == 1) {
     // one launch: mortar face blocks first, then volume cell blocks
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
@@ -2340,9 +2358,17 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
     const int nmb = (int)((2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                           MortarShape<Real, DIM, N>::FPB);
     if constexpr (kQuad) {
-      if (quad)
-        launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb,
-                 lin, M, mtrig, src, E, Em, strip);
+      if (quad) {
+        if constexpr (sizeof(Real) == 8 && N == 3) {
+          using MSL = MortarShape<Real, DIM, N, kLdsQuadBytes>;
+          const int nml = (int)((2u * (unsigned)(G.n_theta * G.nz) + MSL::FPB - 1) / MSL::FPB);
+          launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad_lds<N>, dim3(blocks + nml), dim3(64), s, G, T, h->k, nml,
+                   lin, M, mtrig, src, E, Em, strip);
+        } else {
+          launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k,
+                   nmb, lin, M, mtrig, src, E, Em, strip);
+        }
+      }
     }
     if (!quad)
       launch_k(h, TIMER_VOLUME, k_jacobian_fused<Real, DIM, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb, lin,
