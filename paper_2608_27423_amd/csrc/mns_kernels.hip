@@ -2431,19 +2431,27 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_batch_jacobian_quad(const 
                                                                           const long long* __restrict__ vstart,
                                                                           int count, Tab1D<Real, N> T, int k,
                                                                           const Real* __restrict__ src) {
-  __shared__ MortarSmem<Real, 3, N> sm;
+  // FP64 degree 2: the layout of k_jacobian_fused_quad_lds (volume blocks
+  // with their point values in LDS, two-face mortar blocks, one 18 KB buffer)
+  constexpr bool kLds = sizeof(Real) == 8 && N == 3;
+  constexpr int BUD = kLds ? kLdsQuadBytes : 36000;
+  using MSm = MortarSmem<Real, 3, N, BUD>;
+  constexpr int UB = kLds ? 4 * N * N * 64 * (int)sizeof(Real) : 0;
+  constexpr int SB = (int)sizeof(MSm) > UB ? (int)sizeof(MSm) : UB;
+  __shared__ __align__(16) unsigned char smem[SB];
   const long long mtot = mstart[count];
   const long long b = blockIdx.x;
   if (b < mtot) {
     const int i = batch_item_of(mstart, count, b);
     const Geom<Real> G = items[i].G;
-    mortar_block<Real, 3, N>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab, items[i].mtrig,
-                             src + items[i].dof_off, items[i].Em, 1, sm);
+    mortar_block<Real, 3, N, BUD>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab,
+                                  items[i].mtrig, src + items[i].dof_off, items[i].Em, 1,
+                                  *reinterpret_cast<MSm*>(smem));
   } else {
     const int i = batch_item_of(vstart, count, b - mtot);
     const Geom<Real> G = items[i].G;
-    volume_quad<Real, N>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off, items[i].E,
-                         items[i].strip != 0);
+    volume_quad<Real, N, kLds>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off,
+                               items[i].E, items[i].strip != 0, reinterpret_cast<Real*>(smem));
   }
 }
 
@@ -2489,7 +2497,11 @@ static void batch_blocks(const mns_handle* h, long long* nmb, long long* nvb, in
   constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   const int cpw = kQuad ? QuadShape<Real, N>::CPW : S::CPW;
   *nvb = (h->ncells + cpw - 1) / cpw;
-  *nmb = (2LL * h->desc.n_theta * h->nz + MortarShape<Real, DIM, N>::FPB - 1) / MortarShape<Real, DIM, N>::FPB;
+  // faces per mortar block: two in the FP64 degree-2 quad launch (its LDS is
+  // shared with the LDS-staged volume blocks), the default otherwise
+  constexpr int FPB = (kQuad && sizeof(Real) == 8 && N == 3) ? MortarShape<Real, DIM, N, kLdsQuadBytes>::FPB
+                                                             : MortarShape<Real, DIM, N>::FPB;
+  *nmb = (2LL * h->desc.n_theta * h->nz + FPB - 1) / FPB;
   *strip = (kQuad && h->desc.n_theta % 16 == 0) ? 1 : 0;
 }
 
