@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused", type=int, default=-1,
                     help="-1: automatic; 1: volume and mortar in one launch; 2: mortar on a second stream; 0: sequential")
-    ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k = 2); 0: LDS planes")
+    ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k = 2, 3); 0: LDS planes")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching leg (48 uneven instances)")
     ap.add_argument("--no-copy-bandwidth", action="store_true", help="skip the device-copy bandwidth measurement")
     ap.add_argument("--transient", action="store_true",
@@ -70,7 +70,7 @@ def algorithmic_bytes_volume(mesh, n_dofs, real_bytes):
 def dominant_kernel(mesh, fused, layout, real="double"):
     """Name of the launch that the volume timer brackets."""
     dim, k = mesh["dim"], mesh["degree"]
-    quad = layout == 1 and dim == 3 and (k == 2 or (k == 3 and real == "float"))
+    quad = layout == 1 and dim == 3 and k in (2, 3)
     if fused < 0:
         cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * (mesh["n_z"] if dim == 3 else 1)
         fused = 2 if cells >= (1 << 18) else 1

@@ -325,17 +325,15 @@ void mns_batch_destroy(mns_batch* batch);
  * mortar faces; 0: two launches on the caller's stream; 2: two launches, the
  * mortar kernel on a second stream of the library (default priority) joined
  * back to the caller's stream before the gather; -1 (default): 1 below
- * 262,144 cells, 2 from there on.  In FP64 with the quad layout the volume
- * blocks of every mode keep their Gauss-point values in LDS (two wavefronts
- * per SIMD); in the fused launch the mortar blocks then take fewer faces so
- * that both kinds fit the same LDS.  volume_layout = 1 (default): in 3D
- * with degree 2 (both precisions) and degree 3 (FP32) a quad of four lanes
- * owns a cell and the theta contractions exchange values between lanes
- * without LDS; 0: (k+1)^2 lanes per cell (nine for degree 2, sixteen for
- * degree 3) with the r and theta contractions staged through LDS, the layout
- * used in 2D, for degree >= 4 and for FP64 at degree 3 whatever the
- * setting.  Takes
- * effect on the next apply call.
+ * 262,144 cells, 2 from there on.  In FP64 at degree 2 with the quad
+ * layout the volume blocks of every mode keep their Gauss-point values in
+ * LDS (two wavefronts per SIMD); in the fused launch the mortar blocks then
+ * take fewer faces so that both kinds fit the same LDS.  volume_layout = 1
+ * (default): in 3D with degree 2 or 3 a quad of four lanes owns a cell and
+ * the theta contractions exchange values between lanes without LDS; 0:
+ * (k+1)^2 lanes per cell (nine for degree 2, sixteen for degree 3) with the
+ * r and theta contractions staged through LDS, the layout used in 2D and for
+ * degree >= 4 whatever the setting.  Takes effect on the next apply call.
  * Errors: INVALID_ARG. */
 typedef struct {
   int fused_launch;
@@ -345,7 +343,7 @@ int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg);
 int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg);
 
 /* Autotuner of the launch configuration: times `reps` FP64 applications of
- * every launch mode (fused_launch 0, 1, 2) and, in 3D with degree 2, both
+ * every launch mode (fused_launch 0, 1, 2) and, in 3D with degree 2 or 3, both
  * volume layouts, on the handle's own mesh and linearization, and sets the
  * fastest (written to *chosen when non-null).  All configurations compute the
  * same product; the choice depends on the mesh size (tail of the fused

@@ -490,8 +490,8 @@ int mns_autotune_kernel_config(mns_handle* h, int reps, mns_kernel_config* chose
   }
   int rc = mns::launch_fill<double>(x, 1.0, (int64_t)n, s);
   // candidates: every launch mode; both volume layouts where the quad layout
-  // exists (3D, degree 2)
-  const bool has_quad = h->dim == 3 && h->k == 2;
+  // exists (3D, degrees 2 and 3)
+  const bool has_quad = h->dim == 3 && (h->k == 2 || h->k == 3);
   const int saved_fused = h->fused, saved_quad = h->quad;
   float best = -1.0f;
   mns_kernel_config best_cfg{saved_fused, saved_quad};

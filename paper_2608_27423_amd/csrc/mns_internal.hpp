@@ -141,7 +141,7 @@ struct mns_handle {
   hipStream_t aux = nullptr;
   hipStream_t cap = nullptr;      // capture stream of the solver's graphs (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // volume layout: 1 = lane quad per cell (3D: degree 2, and degree 3 in FP32), 0 = LDS planes
+  // volume layout: 1 = lane quad per cell (3D, degrees 2 and 3), 0 = LDS planes
   int quad = 1;
   int picard = 0;               // linearization kind of the next mns_set_linearization (MNS_LIN_*)
   long long ws_gen = 0;         // incremented whenever the Krylov workspace is reallocated
