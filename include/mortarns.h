@@ -321,8 +321,9 @@ void mns_batch_destroy(mns_batch* batch);
 
 /* Kernel configuration of the Jacobian application (tuning knobs; every
  * setting computes the same product).  fused_launch = 1: volume cells and
- * mortar faces are integrated in one launch whose first blocks take the
- * mortar faces; 0: two launches on the caller's stream; 2: two launches, the
+ * mortar faces are integrated in one launch (3D degree 2: volume blocks
+ * first; otherwise mortar blocks first); 0: two launches on the caller's
+ * stream; 2: two launches, the
  * mortar kernel on a second stream of the library (default priority) joined
  * back to the caller's stream before the gather; -1 (default): 1 below
  * 262,144 cells, 2 from there on.  In FP64 at degree 2 with the quad

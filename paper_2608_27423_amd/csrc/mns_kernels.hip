@@ -2080,8 +2080,13 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_fused_quad(Geom<R
                                                             const Real* __restrict__ src, Real* __restrict__ E,
                                                             Real* __restrict__ Em, int strip) {
   __shared__ MortarSmem<Real, 3, N> sm;
-  if ((int)blockIdx.x < nmb) mortar_block<Real, 3, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1, sm);
-  else volume_quad<Real, N>(G, T, k, blockIdx.x - nmb, lin, src, E, strip != 0);
+  // degree 2: volume blocks first, mortar blocks last (FP32 vmult 32.3 ->
+  // 28.0 us at 1.1M DoFs); degree 3: mortar blocks first (2 % faster there)
+  constexpr bool kVolumeFirst = N == 3;
+  const int nvb = (int)gridDim.x - nmb;
+  const bool mortar = kVolumeFirst ? (int)blockIdx.x >= nvb : (int)blockIdx.x < nmb;
+  if (mortar) mortar_block<Real, 3, N>(G, T, k, kVolumeFirst ? blockIdx.x - nvb : blockIdx.x, Mp, mtrig, src, Em, 1, sm);
+  else volume_quad<Real, N>(G, T, k, kVolumeFirst ? blockIdx.x : blockIdx.x - nmb, lin, src, E, strip != 0);
 }
 
 // Fused launch of the FP64 quad layout with LDS-staged volume blocks: the
@@ -2101,12 +2106,14 @@ __global__ __launch_bounds__(64) void k_jacobian_fused_quad_lds(Geom<double> G, 
   constexpr int UB = 4 * N * N * 64 * (int)sizeof(double);
   constexpr int SB = (int)sizeof(MSm) > UB ? (int)sizeof(MSm) : UB;
   __shared__ __align__(16) unsigned char smem[SB];
-  if ((int)blockIdx.x < nmb)
-    mortar_block<double, 3, N, kLdsQuadBytes>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1,
+  // volume blocks first, the mortar blocks last (measured faster than mortar
+  // first or alternating)
+  const int nvb = (int)gridDim.x - nmb;
+  if ((int)blockIdx.x >= nvb)
+    mortar_block<double, 3, N, kLdsQuadBytes>(G, T, k, blockIdx.x - nvb, Mp, mtrig, src, Em, 1,
                                               *reinterpret_cast<MSm*>(smem));
   else
-    volume_quad<double, N, true>(G, T, k, blockIdx.x - nmb, lin, src, E, strip != 0,
-                                 reinterpret_cast<double*>(smem));
+    volume_quad<double, N, true>(G, T, k, blockIdx.x, lin, src, E, strip != 0, reinterpret_cast<double*>(smem));
 }
 
 // Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
@@ -2353,7 +2360,7 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
   // work is a latency tail there), the concurrent second stream for large ones
   const int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
   if (mode == 1) {
-    // one launch: mortar face blocks first, then volume cell blocks
+    // one launch of volume cell blocks and mortar face blocks
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
     const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
     const int nmb = (int)((2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
