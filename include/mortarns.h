@@ -285,8 +285,9 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
  * before mns_batch_create.  Vectors of a batch are the instances' vectors
  * concatenated in handle order (mns_batch_n_dofs gives the total length).
  * mns_batch_apply_jacobian computes dst_i = J_i src_i for every instance with
- * one launch for all volume cells and mortar faces (mortar blocks first, the
- * instance of a block found from block prefix sums) and one gather launch;
+ * one launch for all volume cells and mortar faces (in the block order of the
+ * single-instance fused launch, the instance of a block found from block
+ * prefix sums) and one gather launch;
  * the arithmetic is that of mns_apply_jacobian, so every slice equals the
  * instance's own product.  Later rotations and linearizations of the handles
  * are seen by later batch calls; a handle must outlive its batches.  The

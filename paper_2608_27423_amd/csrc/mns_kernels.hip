@@ -1119,11 +1119,12 @@ __device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
 // transposed CD applied along r, z and, across the quad, theta) and finally
 // interpolated back to the nodes.
 //
-// ULDS: the field values at the Gauss points are kept in LDS (18 KB per
-// FP64 wavefront) instead of registers and the linearization data of each
-// point is loaded when the point starts (no prefetch ring).  That takes the
-// FP64 kernel from about 370 registers per lane to under 256, i.e. from one
-// to two wavefronts per SIMD, which hide each other's memory latency.
+// ULDS: the field values at the Gauss points are kept in LDS (4 (k+1)^2
+// values per lane: 18 KB per FP64 wavefront at degree 2, 32 KB at degree 3)
+// instead of registers and the linearization data of each point is loaded
+// when the point starts (no prefetch ring).  That takes the FP64 degree-2
+// kernel from about 370 registers per lane to under 256, i.e. from one to two
+// wavefronts per SIMD, which hide each other's memory latency.
 template <typename Real, int N, bool ULDS = false>
 __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                    const Real* __restrict__ lin, const Real* __restrict__ src,
@@ -2419,9 +2420,10 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // Batched application: many instances of one dimension and degree in one
-// volume + mortar launch and one gather launch.  Blocks [0, mortar total)
-// integrate mortar faces, the rest volume cells; the instance of a block is
-// found by binary search in the block prefix sums.
+// volume + mortar launch and one gather launch.  One range of blocks
+// integrates mortar faces, the other volume cells (which comes first follows
+// the single-instance fused launch); the instance of a block is found by
+// binary search in the block prefix sums.
 // ---------------------------------------------------------------------------
 __device__ inline int batch_item_of(const long long* __restrict__ start, int count, long long b) {
   int lo = 0, hi = count - 1;  // last instance whose range starts at or before b
@@ -2447,18 +2449,24 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_batch_jacobian_quad(const 
   constexpr int UB = kLds ? 4 * N * N * 64 * (int)sizeof(Real) : 0;
   constexpr int SB = (int)sizeof(MSm) > UB ? (int)sizeof(MSm) : UB;
   __shared__ __align__(16) unsigned char smem[SB];
-  const long long mtot = mstart[count];
+  // volume blocks first, then the mortar blocks (degree 2; mortar first for
+  // degree 3), as in the single-instance fused launches
+  constexpr bool kVolumeFirst = N == 3;
+  const long long mtot = mstart[count], vtot = vstart[count];
   const long long b = blockIdx.x;
-  if (b < mtot) {
-    const int i = batch_item_of(mstart, count, b);
+  const bool mortar = kVolumeFirst ? b >= vtot : b < mtot;
+  if (mortar) {
+    const long long bm = kVolumeFirst ? b - vtot : b;
+    const int i = batch_item_of(mstart, count, bm);
     const Geom<Real> G = items[i].G;
-    mortar_block<Real, 3, N, BUD>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab,
+    mortar_block<Real, 3, N, BUD>(G, T, k, (int)(bm - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab,
                                   items[i].mtrig, src + items[i].dof_off, items[i].Em, 1,
                                   *reinterpret_cast<MSm*>(smem));
   } else {
-    const int i = batch_item_of(vstart, count, b - mtot);
+    const long long bv = kVolumeFirst ? b : b - mtot;
+    const int i = batch_item_of(vstart, count, bv);
     const Geom<Real> G = items[i].G;
-    volume_quad<Real, N, kLds>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off,
+    volume_quad<Real, N, kLds>(G, T, k, (int)(bv - vstart[i]), items[i].lin, src + items[i].dof_off,
                                items[i].E, items[i].strip != 0, reinterpret_cast<Real*>(smem));
   }
 }
