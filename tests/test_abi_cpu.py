@@ -79,3 +79,31 @@ def test_bench_refuses_more_than_one_gpu():
     assert p.returncode == 2
     msg = json.loads(p.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_bench_roofline_bookkeeping():
+    """The bench's roofline bookkeeping on the workloads: algorithmic bytes per
+    launch (src + dst once, 16 FP64 values per Gauss point) and the name of the
+    launch its volume timer brackets under the automatic launch mode (fused
+    below 262,144 cells, the volume kernel beside a second-stream mortar
+    launch from there on; degree-2 FP64 fused launch in its LDS-staged form)."""
+    import sys
+
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2608_27423_amd import inputs
+
+    c2 = inputs.mesh("annulus3d_q2_64x8x32")
+    b, cells = bench.algorithmic_bytes_volume(c2, inputs.n_dofs(c2), 8)
+    assert (b, cells) == (131350528, 32768)
+    assert bench.dominant_kernel(c2, -1, 1) == "mns::k_jacobian_fused_quad_lds<3>"
+    assert bench.dominant_kernel(c2, -1, 1, "float") == "mns::k_jacobian_fused_quad<float, 3>"
+    assert bench.dominant_kernel(c2, 0, 1) == "mns::k_jacobian_volume_quad<double, 3>"
+    assert bench.dominant_kernel(c2, -1, 0) == "mns::k_jacobian_fused<double, 3, 3>"
+    c5 = inputs.mesh("annulus3d_q2_256x32x128")
+    assert bench.algorithmic_bytes_volume(c5, inputs.n_dofs(c5), 8)[0] == 8342536192
+    assert bench.dominant_kernel(c5, -1, 1) == "mns::k_jacobian_volume_quad<double, 3>"
+    c3 = inputs.mesh("annulus3d_q3_64x16x32")
+    assert bench.dominant_kernel(c3, -1, 1) == "mns::k_jacobian_fused_quad<double, 4>"
+    c1 = inputs.mesh("annulus2d_q2_32x4")
+    assert bench.dominant_kernel(c1, -1, 1) == "mns::k_jacobian_fused<double, 2, 3>"
