@@ -32,11 +32,20 @@
  *
  * Memory and streams: every vector pointer is DEVICE memory on the current HIP
  * device, contiguous, 8-byte aligned (double) or 4-byte aligned (float).  The
- * caller owns all vectors; the library owns the handle and its workspace,
- * which is allocated in mns_setup_mesh, mns_rotate_rotor, mns_set_linearization
- * and on the first mns_solve, never in mns_apply_*.  Work is enqueued on the
- * stream argument (a hipStream_t, NULL = default stream) in stream order;
- * nothing synchronizes the host except mns_solve and mns_n_dofs-like queries.
+ * caller owns all vectors; the library owns the handle and its workspace.
+ * mns_setup_mesh allocates the geometry and angle tables, the per-point
+ * linearization store, the local-result buffers and a second stream with its
+ * events; mns_set_linearization allocates only on the first call that passes
+ * a history or force vector; the first mns_solve allocates the Krylov
+ * workspace.  mns_rotate_rotor, mns_set_linearization (after that first call)
+ * and mns_apply_* allocate nothing.  Work is enqueued on the stream argument
+ * (a hipStream_t, NULL = default stream) in stream order; the calls that take
+ * a stream neither synchronize the host nor the device, except mns_solve,
+ * mns_bdf2_step, mns_batch_solve and mns_autotune_kernel_config, which
+ * synchronize their stream.  A handle's tables are rewritten in the order of
+ * the stream passed to mns_rotate_rotor / mns_set_linearization: work on
+ * another stream that reads the handle must be ordered against those calls by
+ * the caller (events), as for any buffer shared between streams.
  *
  * Errors: every int-returning call returns MNS_OK (0) or a negative MNS_ERR_*
  * code; the handle keeps a message readable with mns_last_error.  No C++
@@ -101,9 +110,13 @@ int mns_n_dofs(const mns_handle* h, int64_t* n_total, int64_t* n_rotor);
  * u_ALE = omega e_z x x in rotor cells.  Rebuilds the mortar segments of every
  * stator face (one when aligned to 1e-12 of a cell angle, else two), the
  * mapped quadrature tables of Sec. 3.2 and the rotated geometry tables, all in
- * FP64 (cast copies for FP32).  Invalidates the linearization.
+ * FP64 (cast copies for FP32), with one kernel enqueued on `stream`: work
+ * enqueued earlier on `stream` still sees the old tables, later work the new
+ * ones.  Allocates nothing and does not synchronize, so it can be captured
+ * into a graph (the angle is a kernel argument).  Invalidates the
+ * linearization (the next apply needs mns_set_linearization).
  * Errors: INVALID_ARG (non-finite theta or omega), HIP. */
-int mns_rotate_rotor(mns_handle* h, double theta, double omega);
+int mns_rotate_rotor(mns_handle* h, double theta, double omega, void* stream);
 
 /* Fix the state (u, p) at which the Jacobian is taken (Eq. Eq-Newton-method)
  * and precompute per quadrature point the convective velocity a = u - u_ALE,
@@ -111,7 +124,9 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega);
  * FP64 and FP32.  u_hist: BDF2 history term (-4 u^n + u^(n-1)) / (2 dt) in the
  * vector layout (pressure slots ignored), or NULL; ignored when steady.
  * force: body force f in the vector layout, or NULL.  The arrays are read on
- * `stream` before return of the enqueued work; the library keeps copies.
+ * `stream` by the enqueued work; the library keeps copies (a history buffer
+ * and a force buffer are allocated by the first call that passes them and
+ * kept; every other call allocates nothing).
  * Errors: NO_ROTATION, INVALID_ARG (null or misaligned state), HIP. */
 int mns_set_linearization(mns_handle* h, const double* state, const double* u_hist, const double* force,
                           void* stream);
@@ -174,6 +189,11 @@ typedef struct {
                                   mg_smooth_range).  The estimate converges from below; a factor a little above 1
                                   keeps the top of the spectrum inside the interval (default 1.05; valid range
                                   [1, 4]) */
+  int mg_coarse_direct;        /* V-cycle, coarsest level (always FP64): 1 (default): direct solve with the level's
+                                  matrix reconstructed column by column from its Jacobian (Alg. Alg-matrix, mortar
+                                  columns included) and inverted by LU with partial pivoting on the device, when the
+                                  level has at most 8,192 DoFs (a Chebyshev polynomial otherwise); 0: Chebyshev of
+                                  degree mg_coarse_degree */
 } mns_solve_opts;
 
 typedef struct {

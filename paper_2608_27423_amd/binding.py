@@ -55,7 +55,7 @@ class SolveOpts(ctypes.Structure):
         ("mg_levels", ctypes.c_int), ("mg_smooth_degree", ctypes.c_int), ("mg_smooth_range", ctypes.c_double),
         ("mg_coarse_degree", ctypes.c_int), ("mg_coarse_linearization", ctypes.c_int),
         ("mg_fine_linearization", ctypes.c_int), ("use_graph", ctypes.c_int),
-        ("cheb_lambda_factor", ctypes.c_double),
+        ("cheb_lambda_factor", ctypes.c_double), ("mg_coarse_direct", ctypes.c_int),
     ]
 
 
@@ -129,7 +129,7 @@ def lib():
         vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
         L.mns_setup_mesh.argtypes = [ctypes.POINTER(MeshDesc), vp, ctypes.POINTER(vp)]
         L.mns_n_dofs.argtypes = [vp, i64p, i64p]
-        L.mns_rotate_rotor.argtypes = [vp, ctypes.c_double, ctypes.c_double]
+        L.mns_rotate_rotor.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
         L.mns_set_linearization.argtypes = [vp, vp, vp, vp, vp]
         L.mns_set_linearization_kind.argtypes = [vp, ctypes.c_int]
         L.mns_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -226,7 +226,7 @@ class Operator:
         return rc
 
     def rotate_rotor(self, theta, omega):
-        return self._check(self._L.mns_rotate_rotor(self._h, float(theta), float(omega)))
+        return self._check(self._L.mns_rotate_rotor(self._h, float(theta), float(omega), _stream()))
 
     def set_linearization(self, state, hist=None, force=None, kind=None):
         """kind: None (keep), "newton" or "picard" (mns_set_linearization_kind)."""

@@ -13,7 +13,7 @@
 using namespace mns;
 
 int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h);
-int mns_rotate_tables(mns_handle* h, double theta, double omega);
+int mns_rotate_tables(mns_handle* h, double theta, double omega, hipStream_t s);
 int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* rep,
                    hipStream_t s);
 
@@ -32,19 +32,39 @@ static void free_all(mns_handle* h) {
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);
   if (h->cap) (void)hipStreamDestroy(h->cap);
+  h->ev_fork = h->ev_join = nullptr;
+  h->aux = h->cap = nullptr;
   mns::mg_free(h);
-  void* ptrs[] = {h->d_hcell64, h->d_hcell32, h->d_trig64, h->d_trig32, h->d_mtab64, h->d_mtab32, h->d_mtrig64,
-                  h->d_mtrig32, h->d_cons, h->d_lin64, h->d_lin32, h->d_hist, h->d_force, h->ws64, h->ws32,
-                  h->d_E64, h->d_E32, h->d_Em64, h->d_Em32,
-                  h->d_diag64, h->d_diag32, h->d_red, h->d_step, h->d_state};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  void** ptrs[] = {(void**)&h->d_hcell64, (void**)&h->d_hcell32, (void**)&h->d_trig64, (void**)&h->d_trig32,
+                   &h->d_mtab64, &h->d_mtab32, (void**)&h->d_mtrig64, (void**)&h->d_mtrig32, (void**)&h->d_cons,
+                   (void**)&h->d_lin64, (void**)&h->d_lin32, (void**)&h->d_hist_buf, (void**)&h->d_force_buf,
+                   (void**)&h->ws64, (void**)&h->ws32, (void**)&h->d_E64, (void**)&h->d_E32, (void**)&h->d_Em64,
+                   (void**)&h->d_Em32, (void**)&h->d_diag64, (void**)&h->d_diag32, (void**)&h->d_red, (void**)&h->d_gm,
+                   (void**)&h->d_step, (void**)&h->d_state};
+  for (void** p : ptrs) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  h->d_hist = h->d_force = nullptr;
   if (h->h_red) (void)hipHostFree(h->h_red);
+  h->h_red = nullptr;
 }
 
 static bool aligned(const void* p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
 
 static hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// every instance must hold a linearization at its current angle: a rotation
+// of a member handle after mns_batch_create clears it until it is relinearized
+static int batch_check_linearized(mns_batch* b) {
+  for (size_t i = 0; i < b->hs.size(); ++i)
+    if (!b->hs[i]->rotated || !b->hs[i]->linearized) {
+      b->err = "batch: instance " + std::to_string(i) +
+               " has no linearization at its current angle (call mns_set_linearization after mns_rotate_rotor)";
+      return MNS_ERR_NOT_LINEARIZED;
+    }
+  return MNS_OK;
+}
 
 extern "C" {
 
@@ -60,27 +80,8 @@ int mns_setup_mesh(const mns_mesh_desc* desc, void* stream, mns_handle** out) {
     rc = MNS_ERR_HIP;
   }
   if (rc != MNS_OK) {
-    // keep the handle so the caller can read the message; it holds no rotation
+    // keep the handle so the caller can read the message; it holds no device memory
     free_all(h);
-    h->d_hcell64 = nullptr;
-    h->d_hcell32 = nullptr;
-    h->d_cons = nullptr;
-    h->d_trig64 = nullptr;
-    h->d_trig32 = nullptr;
-    h->d_mtab64 = h->d_mtab32 = nullptr;
-    h->d_mtrig64 = nullptr;
-    h->d_mtrig32 = nullptr;
-    h->d_lin64 = nullptr;
-    h->d_lin32 = nullptr;
-    h->d_hist = h->d_force = nullptr;
-    h->d_E64 = h->d_Em64 = nullptr;
-    h->d_E32 = h->d_Em32 = nullptr;
-    h->ws64 = nullptr;
-    h->ws32 = nullptr;
-    h->d_diag64 = nullptr;
-    h->d_diag32 = nullptr;
-    h->d_red = nullptr;
-    h->h_red = nullptr;
     *out = h;
     return rc;
   }
@@ -95,17 +96,14 @@ int mns_n_dofs(const mns_handle* h, int64_t* n_total, int64_t* n_rotor) {
   return MNS_OK;
 }
 
-int mns_rotate_rotor(mns_handle* h, double theta, double omega) {
+int mns_rotate_rotor(mns_handle* h, double theta, double omega, void* stream) {
   if (!h) return MNS_ERR_INVALID_ARG;
-  if (h->ndofs == 0) return set_error(h, MNS_ERR_INVALID_ARG, "handle was not set up");
+  if (h->ndofs == 0 || !h->d_mtab64) return set_error(h, MNS_ERR_INVALID_ARG, "handle was not set up");
   if (!std::isfinite(theta) || !std::isfinite(omega))
     return set_error(h, MNS_ERR_INVALID_ARG, "theta and omega must be finite");
-  // the tables are rewritten in place: drain every stream that may read them
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return set_error(h, MNS_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
   int rc;
   try {
-    rc = mns_rotate_tables(h, theta, omega);
+    rc = mns_rotate_tables(h, theta, omega, as_stream(stream));
   } catch (...) {
     rc = set_error(h, MNS_ERR_HIP, "exception in rotate");
   }
@@ -135,30 +133,24 @@ int mns_set_linearization(mns_handle* h, const double* state, const double* u_hi
   const int LS = h->dim == 3 ? LinLayout<3>::SIZE : LinLayout<2>::SIZE;
   const size_t nlin = (size_t)h->ncells * (size_t)(h->dim == 3 ? h->n * h->n * h->n : h->n * h->n) * LS;
   hipError_t e;
-  if (!h->d_lin64) {
-    if ((e = hipMalloc((void**)&h->d_lin64, nlin * sizeof(double))) != hipSuccess)
-      return set_error(h, MNS_ERR_HIP, std::string("hipMalloc lin: ") + hipGetErrorString(e));
-    if ((e = hipMalloc((void**)&h->d_lin32, nlin * sizeof(float))) != hipSuccess)
-      return set_error(h, MNS_ERR_HIP, std::string("hipMalloc lin32: ") + hipGetErrorString(e));
-  }
-  // keep copies of the history and force for mns_apply_residual
+  // keep copies of the history and force for mns_apply_residual; their
+  // buffers are allocated by the first call that passes them and kept
   const double* srcs[2] = {u_hist, force};
+  double** bufs[2] = {&h->d_hist_buf, &h->d_force_buf};
   double** dsts[2] = {&h->d_hist, &h->d_force};
   for (int i = 0; i < 2; ++i) {
     if (srcs[i]) {
-      if (!*dsts[i] && (e = hipMalloc((void**)dsts[i], h->ndofs * sizeof(double))) != hipSuccess)
+      if (!*bufs[i] && (e = hipMalloc((void**)bufs[i], h->ndofs * sizeof(double))) != hipSuccess)
         return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
-      if ((e = hipMemcpyAsync(*dsts[i], srcs[i], h->ndofs * sizeof(double), hipMemcpyDeviceToDevice, s)) !=
+      if ((e = hipMemcpyAsync(*bufs[i], srcs[i], h->ndofs * sizeof(double), hipMemcpyDeviceToDevice, s)) !=
           hipSuccess)
         return set_error(h, MNS_ERR_HIP, std::string("copy: ") + hipGetErrorString(e));
-    } else if (*dsts[i]) {
-      (void)hipFree(*dsts[i]);
+      *dsts[i] = *bufs[i];
+    } else {
       *dsts[i] = nullptr;
     }
   }
   // the state is kept for the multigrid hierarchy (injected to coarse levels)
-  if (!h->d_state && (e = hipMalloc((void**)&h->d_state, h->ndofs * sizeof(double))) != hipSuccess)
-    return set_error(h, MNS_ERR_HIP, std::string("hipMalloc state: ") + hipGetErrorString(e));
   if ((e = hipMemcpyAsync(h->d_state, state, h->ndofs * sizeof(double), hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return set_error(h, MNS_ERR_HIP, std::string("copy state: ") + hipGetErrorString(e));
   ++h->lin_version;
@@ -215,6 +207,7 @@ int mns_batch_n_dofs(const mns_batch* b, int64_t* n_total) {
 
 int mns_batch_apply_jacobian(mns_batch* b, int precision, const void* src, void* dst, void* stream) {
   if (!b) return MNS_ERR_INVALID_ARG;
+  if (int rc = batch_check_linearized(b)) return rc;
   if (src == dst) {
     b->err = "src and dst must not overlap";
     return MNS_ERR_INVALID_ARG;
@@ -247,6 +240,7 @@ const char* mns_batch_last_error(const mns_batch* b) { return b ? b->err.c_str()
 int mns_batch_solve(mns_batch* b, const double* rhs, double* x, const mns_solve_opts* opts,
                     mns_solve_report* reports, void* stream) {
   if (!b) return MNS_ERR_INVALID_ARG;
+  if (int rc = batch_check_linearized(b)) return rc;
   if (!aligned(rhs, 8) || !aligned(x, 8) || rhs == x) {
     b->err = "rhs/x must be distinct 8-byte aligned pointers";
     return MNS_ERR_INVALID_ARG;
@@ -347,6 +341,7 @@ void mns_default_solve_opts(mns_solve_opts* o) {
   o->mg_fine_linearization = MNS_LIN_NEWTON;
   o->use_graph = 1;
   o->cheb_lambda_factor = 1.05;
+  o->mg_coarse_direct = 1;
 }
 
 int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* opts, mns_solve_report* report,
@@ -366,7 +361,8 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
       o.mg_smooth_degree < 1 || o.mg_smooth_degree > 100 || !(o.mg_smooth_range > 1) ||
       (o.mg_coarse_linearization != MNS_LIN_NEWTON && o.mg_coarse_linearization != MNS_LIN_PICARD) ||
       (o.mg_fine_linearization != MNS_LIN_NEWTON && o.mg_fine_linearization != MNS_LIN_PICARD) ||
-      (o.use_graph != 0 && o.use_graph != 1) || !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0))
+      (o.use_graph != 0 && o.use_graph != 1) || !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0) ||
+      (o.mg_coarse_direct != 0 && o.mg_coarse_direct != 1))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
   mns_solve_report rep{};
   int rc;

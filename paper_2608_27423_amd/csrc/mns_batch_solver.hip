@@ -2,7 +2,7 @@
 // lockstep, every iteration one batched preconditioner application, one
 // batched FP64 Jacobian application and batched Gram-Schmidt reductions over
 // the concatenated vectors.  The arithmetic of each instance is that of
-// mns_solve with the Jacobi-Chebyshev preconditioner (Sec. 3.3 smoother
+// mns_solve with the Jacobi-Chebyshev preconditioner (Sec. 3.4 smoother
 // polynomial with the diagonal of Alg. Alg-diagonal); only the reduction
 // order of the dot products differs.  Vector kernels work on blocks that never
 // straddle two instances, so per-instance scalars are read once per block.

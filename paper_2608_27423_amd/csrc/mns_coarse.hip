@@ -1,0 +1,560 @@
+// Direct FP64 solve on the coarsest multigrid level (Sec. 3.4: a direct
+// coarse-grid solver, with the level's matrix reconstructed column by column
+// as in Alg. Alg-matrix, mortar columns included).
+//
+// Reconstruction: columns are recovered in groups from the matrix-free
+// Jacobian itself.  Two columns whose row supports are disjoint can share one
+// probe vector; the supports follow from the structure (all nodes of a cell
+// couple, and all nodes of a rotor interface cell couple with all nodes of the
+// stator interface cells that overlap it at the current angle), so a greedy
+// distance-2 colouring of the nodes on the host gives the groups.  One probe
+// per colour and component: J p, and every row of the result belongs to the
+// one probed node that it couples to.  Constrained rows and columns come out
+// as the identity, as in mns_apply_jacobian.
+//
+// Factorization: right-looking blocked LU with partial pivoting (panel of 64
+// columns factored by one workgroup, triangular solve of the panel rows, FP64
+// tiled update of the trailing matrix), then the explicit inverse from
+// P A = L U by the same blocked triangular solves with the identity as right-hand
+// side.  Each coarse solve is then one FP64 matrix-vector product (two-stage,
+// fixed order), which runs on many workgroups, unlike a triangular solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "mns_internal.hpp"
+
+namespace mns {
+
+constexpr int kNB = 64;        // panel width of the LU and of the blocked triangular solves
+constexpr int kGemvRows = 256; // rows per workgroup of the matrix-vector product
+constexpr int kGemvCols = 128; // columns per workgroup (partial sums, summed in a second pass)
+
+// ---------------------------------------------------------------------------
+// Probing
+// ---------------------------------------------------------------------------
+
+// p = 1 on component `comp` of the nodes of colour `color`, 0 elsewhere
+__global__ void k_probe(const int* __restrict__ node_color, int color, int comp, int nc, long long nnodes,
+                        double* __restrict__ p) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes * nc) return;
+  const long long node = i / nc;
+  p[i] = (node_color[node] == color && (int)(i % nc) == comp) ? 1.0 : 0.0;
+}
+
+// A(row, col(row)) = y(row), col(row) = the probed node coupled to the row's
+// node (owner table of the colour; -1: none) and the probed component
+__global__ void k_probe_scatter(const int* __restrict__ owner, int comp, int nc, long long nnodes,
+                                const double* __restrict__ y, double* __restrict__ A, long long lda) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nnodes * nc) return;
+  const int a = owner[r / nc];
+  if (a < 0) return;
+  A[r + ((long long)a * nc + comp) * lda] = y[r];
+}
+
+__global__ void k_fill_mat(double* __restrict__ A, long long count, double v) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) A[i] = v;
+}
+
+__global__ void k_identity(double* __restrict__ X, int n, long long ldx) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long count = (long long)n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const long long c = i / n, r = i % n;
+    X[r + c * ldx] = r == c ? 1.0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked LU with partial pivoting, column-major A (lda), in place
+// ---------------------------------------------------------------------------
+
+// Panel [k, k + nb) factored by one workgroup: per column the pivot (largest
+// magnitude, smallest row index among equals), the swap of the two whole
+// rows (all n columns, so the rows left and right of the panel follow), the
+// scaling of the column below the diagonal and the rank-1 update of the rest
+// of the panel.  piv[c] = pivot row of column c; *info = first zero pivot + 1.
+__global__ __launch_bounds__(1024) void k_lu_panel(double* __restrict__ A, int n, long long lda, int k, int nb,
+                                                   int* __restrict__ piv, int* __restrict__ info) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int c = k; c < k + nb; ++c) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = c + t; i < n; i += T) {
+      const double v = fabs(A[i + (long long)c * lda]);
+      if (v > best || (v == best && i < bi)) {
+        best = v;
+        bi = i;
+      }
+    }
+    sv[t] = best;
+    si[t] = bi;
+    __syncthreads();
+    for (int off = T / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        const double v = sv[t + off];
+        const int ii = si[t + off];
+        if (v > sv[t] || (v == sv[t] && ii < si[t])) {
+          sv[t] = v;
+          si[t] = ii;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    const double pv = sv[0];
+    __syncthreads();
+    if (t == 0) {
+      piv[c] = p;
+      if (!(pv > 0.0) && *info == 0) *info = c + 1;
+    }
+    if (p != c)
+      for (int j = t; j < n; j += T) {
+        const double a = A[c + (long long)j * lda], b = A[p + (long long)j * lda];
+        A[c + (long long)j * lda] = b;
+        A[p + (long long)j * lda] = a;
+      }
+    __syncthreads();
+    const double d = A[c + (long long)c * lda];
+    const double inv = d != 0.0 ? 1.0 / d : 0.0;
+    for (int i = c + 1 + t; i < n; i += T) A[i + (long long)c * lda] *= inv;
+    __syncthreads();
+    for (int i = c + 1 + t; i < n; i += T) {
+      const double l = A[i + (long long)c * lda];
+      for (int j = c + 1; j < k + nb; ++j) A[i + (long long)j * lda] -= l * A[c + (long long)j * lda];
+    }
+    __syncthreads();
+  }
+}
+
+// Triangular solve with the nb x nb diagonal block D of a factor held in F
+// (rows/cols [k, k + nb)): X[k .. k + nb, j] = D^-1 X[k .. k + nb, j] for every
+// column j in [j0, j1) of X (ldx).  lower: D unit lower triangular (forward);
+// otherwise D upper triangular with its diagonal (backward).  One thread per
+// column, D in LDS.
+__global__ __launch_bounds__(256) void k_trsm_block(const double* __restrict__ F, long long ldf, int k, int nb,
+                                                    double* __restrict__ X, long long ldx, int j0, int j1,
+                                                    int lower) {
+  __shared__ double D[kNB][kNB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int r = e % nb, c = e / nb;
+    D[r][c] = F[(k + r) + (long long)(k + c) * ldf];
+  }
+  __syncthreads();
+  const int j = j0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= j1) return;
+  double x[kNB];
+  double* col = X + (long long)j * ldx + k;
+#pragma unroll
+  for (int r = 0; r < kNB; ++r) x[r] = r < nb ? col[r] : 0.0;
+  if (lower) {
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) {
+      double s = x[r];
+#pragma unroll
+      for (int q = 0; q < kNB; ++q)
+        if (q < r) s -= D[r][q] * x[q];
+      if (r < nb) x[r] = s;
+    }
+  } else {
+#pragma unroll
+    for (int r = kNB - 1; r >= 0; --r) {
+      if (r >= nb) continue;
+      double s = x[r];
+#pragma unroll
+      for (int q = 0; q < kNB; ++q)
+        if (q > r && q < nb) s -= D[r][q] * x[q];
+      x[r] = s / D[r][r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kNB; ++r)
+    if (r < nb) col[r] = x[r];
+}
+
+// C[m x nn] -= L[m x kk] * U[kk x nn] (column-major, kk <= 64), 64 x 64 output
+// tiles per workgroup of 256 threads, 4 x 4 outputs per thread
+__global__ __launch_bounds__(256) void k_gemm_sub(const double* __restrict__ L, long long ldl,
+                                                  const double* __restrict__ U, long long ldu, double* __restrict__ C,
+                                                  long long ldc, int m, int nn, int kk) {
+  __shared__ double Ls[kNB][kNB + 1];
+  __shared__ double Us[kNB][kNB + 1];
+  const int i0 = blockIdx.x * kNB, j0 = blockIdx.y * kNB;
+  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
+    const int r = e % kNB, c = e / kNB;
+    Ls[r][c] = (i0 + r < m && c < kk) ? L[(i0 + r) + (long long)c * ldl] : 0.0;
+    Us[r][c] = (r < kk && j0 + c < nn) ? U[r + (long long)(j0 + c) * ldu] : 0.0;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int q = 0; q < kk; ++q) {
+    double l[4], u[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) l[a] = Ls[tr + 16 * a][q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) u[b] = Us[q][tc + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += l[a] * u[b];
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = j0 + tc + 16 * b;
+    if (j >= nn) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + tr + 16 * a;
+      if (i < m) C[i + (long long)j * ldc] -= acc[a][b];
+    }
+  }
+}
+
+// row interchanges of the factorization applied to X (every column), in order
+__global__ void k_apply_pivots(const int* __restrict__ piv, int n, double* __restrict__ X, long long ldx, int ncols) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  double* col = X + (long long)j * ldx;
+  for (int c = 0; c < n; ++c) {
+    const int p = piv[c];
+    if (p != c) {
+      const double a = col[c];
+      col[c] = col[p];
+      col[p] = a;
+    }
+  }
+}
+
+// y = Ainv b in two stages: partial sums over column blocks of kGemvCols,
+// then their sum in a fixed order (deterministic)
+template <typename Real>
+__global__ __launch_bounds__(kGemvRows) void k_gemv_part(const double* __restrict__ Ainv, long long lda, int n,
+                                                         const Real* __restrict__ b, double* __restrict__ part) {
+  const int i = blockIdx.x * kGemvRows + threadIdx.x;
+  const int c0 = blockIdx.y * kGemvCols;
+  __shared__ double bs[kGemvCols];
+  for (int e = threadIdx.x; e < kGemvCols; e += blockDim.x) bs[e] = c0 + e < n ? (double)b[c0 + e] : 0.0;
+  __syncthreads();
+  if (i >= n) return;
+  double s = 0.0;
+  const int c1 = c0 + kGemvCols < n ? c0 + kGemvCols : n;
+  for (int c = c0; c < c1; ++c) s += Ainv[i + (long long)c * lda] * bs[c - c0];
+  part[(long long)blockIdx.y * n + i] = s;
+}
+
+template <typename Real>
+__global__ void k_gemv_sum(const double* __restrict__ part, int n, int nparts, Real* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += part[(long long)p * n + i];
+  y[i] = (Real)s;
+}
+
+// r = A x - y (check of the reconstruction), partial max |r| and max |y| per block
+__global__ void k_check(const double* __restrict__ A, long long lda, int n, const double* __restrict__ x,
+                        const double* __restrict__ y, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double se[256], sy[256];
+  double e = 0.0, m = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += A[i + (long long)c * lda] * x[c];
+    e = fabs(s - y[i]);
+    m = fabs(y[i]);
+  }
+  se[threadIdx.x] = e;
+  sy[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      se[threadIdx.x] = fmax(se[threadIdx.x], se[threadIdx.x + off]);
+      sy[threadIdx.x] = fmax(sy[threadIdx.x], sy[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = se[0];
+    out[2 * blockIdx.x + 1] = sy[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+// node index of (domain, theta, r, z) on handle h
+static long long node_id(const mns_handle* h, int dom, int it, int ir, int iz) {
+  return (dom ? h->node_off1 : 0) + it + (long long)h->ntn * (ir + (long long)h->nrn[dom] * iz);
+}
+
+// nodes of cell (dom, ct, cr, cz)
+static void cell_nodes(const mns_handle* h, int dom, int ct, int cr, int cz, std::vector<long long>& out) {
+  out.clear();
+  const int k = h->k, nzl = h->dim == 3 ? k + 1 : 1;
+  for (int c = 0; c < nzl; ++c)
+    for (int b = 0; b <= k; ++b)
+      for (int a = 0; a <= k; ++a) {
+        int it = k * ct + a;
+        if (it >= h->ntn) it -= h->ntn;
+        out.push_back(node_id(h, dom, it, k * cr + b, h->dim == 3 ? k * cz + c : 0));
+      }
+}
+
+static int cfail(mns_handle* h, hipError_t e, const char* what) {
+  return set_error(h, MNS_ERR_HIP, std::string("coarse solve ") + what + ": " + hipGetErrorString(e));
+}
+
+struct CoarseDirect {
+  int n = 0;              // DoFs of the level
+  long long lda = 0;
+  double* A = nullptr;    // reconstructed matrix, then its LU factors (column-major)
+  double* Ainv = nullptr; // explicit inverse
+  double* part = nullptr; // partial sums of the matrix-vector product / check
+  double* work = nullptr; // probe and result vectors
+  int* piv = nullptr;
+  int* info = nullptr;
+  int* colors = nullptr;  // node colour
+  int* owners = nullptr;  // [colour][node]: probed node coupled to the node, or -1
+  int ncolors = 0;
+  double check_err = 0;   // max |A x - J x| / max |J x| of the last reconstruction
+};
+
+void coarse_free(void* p) {
+  auto* C = (CoarseDirect*)p;
+  if (!C) return;
+  for (void* q : {(void*)C->A, (void*)C->Ainv, (void*)C->part, (void*)C->work, (void*)C->piv, (void*)C->info,
+                  (void*)C->colors, (void*)C->owners})
+    if (q) (void)hipFree(q);
+  delete C;
+}
+
+// greedy distance-2 colouring of the nodes: two nodes share a colour only if
+// no node couples to both (couplings: cell sharing, and mortar pairs of
+// interface cells at the handle's current angle)
+static void colour_nodes(const mns_handle* h, std::vector<int>& color, std::vector<int>& owners, int* ncolors) {
+  const long long nn = h->nnodes;
+  std::vector<std::vector<long long>> adj(nn);
+  std::vector<long long> na, nb;
+  const mns_mesh_desc& d = h->desc;
+  const int nz = h->nz;
+  auto couple = [&](const std::vector<long long>& x, const std::vector<long long>& y) {
+    for (long long a : x) adj[a].insert(adj[a].end(), y.begin(), y.end());
+  };
+  for (int dom = 0; dom < 2; ++dom) {
+    const int nr = dom ? d.n_r_stator : d.n_r_rotor;
+    for (int cz = 0; cz < nz; ++cz)
+      for (int cr = 0; cr < nr; ++cr)
+        for (int ct = 0; ct < d.n_theta; ++ct) {
+          cell_nodes(h, dom, ct, cr, cz, na);
+          couple(na, na);
+        }
+  }
+  // stator face j meets rotor faces j - m - 1 (when the offset is not zero) and j - m
+  for (int cz = 0; cz < nz; ++cz)
+    for (int j = 0; j < d.n_theta; ++j) {
+      cell_nodes(h, 1, j, 0, cz, na);
+      for (int s = 0; s < 2; ++s) {
+        if (s == 0 && !(h->phi > 0.0)) continue;
+        const int rt = (((j - h->m - (s == 0 ? 1 : 0)) % d.n_theta) + d.n_theta) % d.n_theta;
+        cell_nodes(h, 0, rt, d.n_r_rotor - 1, cz, nb);
+        couple(na, nb);
+        couple(nb, na);
+      }
+    }
+  for (auto& v : adj) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  color.assign(nn, -1);
+  std::vector<std::vector<int>> claimed;  // [colour][node] = probed node coupled to it, or -1
+  for (long long a = 0; a < nn; ++a) {
+    int c = 0;
+    for (;; ++c) {
+      if (c == (int)claimed.size()) claimed.emplace_back(nn, -1);
+      bool ok = true;
+      for (long long b : adj[a])
+        if (claimed[c][b] >= 0) {
+          ok = false;
+          break;
+        }
+      if (ok) break;
+    }
+    color[a] = c;
+    for (long long b : adj[a]) claimed[c][b] = (int)a;
+  }
+  *ncolors = (int)claimed.size();
+  owners.clear();
+  for (auto& v : claimed) owners.insert(owners.end(), v.begin(), v.end());
+}
+
+// blocked LU of C->A in place, then C->Ainv = A^-1 from P A = L U
+static int lu_invert(mns_handle* h, CoarseDirect* C, hipStream_t s) {
+  const int n = C->n;
+  const long long lda = C->lda;
+  hipLaunchKernelGGL(k_fill_mat, dim3(1), dim3(64), 0, s, (double*)C->info, 1, 0.0);  // zero the info word
+  for (int k = 0; k < n; k += kNB) {
+    const int nb = std::min(kNB, n - k);
+    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, C->A, n, lda, k, nb, C->piv, C->info);
+    const int rest = n - k - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_trsm_block, dim3((rest + 255) / 256), dim3(256), 0, s, (const double*)C->A, lda, k, nb,
+                         C->A, lda, k + nb, n, 1);
+      hipLaunchKernelGGL(k_gemm_sub, dim3((rest + kNB - 1) / kNB, (rest + kNB - 1) / kNB), dim3(256), 0, s,
+                         (const double*)(C->A + (k + nb) + (long long)k * lda), lda,
+                         (const double*)(C->A + k + (long long)(k + nb) * lda), lda,
+                         C->A + (k + nb) + (long long)(k + nb) * lda, lda, rest, rest, nb);
+    }
+  }
+  // X = P I, then L Y = X (forward, blocked), then U Ainv = Y (backward, blocked)
+  double* X = C->Ainv;
+  hipLaunchKernelGGL(k_identity, dim3(1024), dim3(256), 0, s, X, n, lda);
+  hipLaunchKernelGGL(k_apply_pivots, dim3((n + 255) / 256), dim3(256), 0, s, (const int*)C->piv, n, X, lda, n);
+  const unsigned gcols = (unsigned)((n + 255) / 256);
+  for (int k = 0; k < n; k += kNB) {
+    const int nb = std::min(kNB, n - k);
+    hipLaunchKernelGGL(k_trsm_block, dim3(gcols), dim3(256), 0, s, (const double*)C->A, lda, k, nb, X, lda, 0, n, 1);
+    const int rest = n - k - nb;
+    if (rest > 0)
+      hipLaunchKernelGGL(k_gemm_sub, dim3((rest + kNB - 1) / kNB, (n + kNB - 1) / kNB), dim3(256), 0, s,
+                         (const double*)(C->A + (k + nb) + (long long)k * lda), lda, (const double*)(X + k), lda,
+                         X + (k + nb), lda, rest, n, nb);
+  }
+  const int last = ((n - 1) / kNB) * kNB;
+  for (int k = last; k >= 0; k -= kNB) {
+    const int nb = std::min(kNB, n - k);
+    hipLaunchKernelGGL(k_trsm_block, dim3(gcols), dim3(256), 0, s, (const double*)C->A, lda, k, nb, X, lda, 0, n, 0);
+    if (k > 0)
+      hipLaunchKernelGGL(k_gemm_sub, dim3((k + kNB - 1) / kNB, (n + kNB - 1) / kNB), dim3(256), 0, s,
+                         (const double*)(C->A + (long long)k * lda), lda, (const double*)(X + k), lda, X, lda, k, n,
+                         nb);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNS_OK : cfail(h, e, "factorization");
+}
+
+// Reconstruct the level's operator (handle hc, rotated and linearized) by
+// probing, check it against one matrix-free product, and invert it.  The
+// check reads two values back (synchronizes the stream).
+int coarse_setup(mns_handle* hc, void** state, hipStream_t s, int max_dofs) {
+  const long long n64 = hc->ndofs;
+  if (n64 > max_dofs) return set_error(hc, MNS_ERR_UNSUPPORTED, "coarsest level too large for the direct solve");
+  const int n = (int)n64;
+  auto* C = (CoarseDirect*)*state;
+  hipError_t e;
+  if (!C || C->n != n) {
+    coarse_free(C);
+    *state = nullptr;
+    C = new CoarseDirect();
+    C->n = n;
+    C->lda = n;
+    const size_t nn = (size_t)n * n;
+    const int parts = (n + kGemvCols - 1) / kGemvCols;
+    if ((e = hipMalloc((void**)&C->A, nn * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->Ainv, nn * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->part, ((size_t)parts * n + 1024) * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->work, 3 * (size_t)n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->piv, (size_t)n * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->info, 2 * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->colors, (size_t)hc->nnodes * sizeof(int))) != hipSuccess) {
+      coarse_free(C);
+      return cfail(hc, e, "allocation");
+    }
+    *state = C;
+  }
+  // colouring at the current angle (mortar pairs move with it)
+  std::vector<int> color, owners;
+  int ncol = 0;
+  colour_nodes(hc, color, owners, &ncol);
+  if (C->owners && C->ncolors != ncol) {
+    (void)hipFree(C->owners);
+    C->owners = nullptr;
+  }
+  if (!C->owners && (e = hipMalloc((void**)&C->owners, owners.size() * sizeof(int))) != hipSuccess)
+    return cfail(hc, e, "allocation");
+  C->ncolors = ncol;
+  if ((e = hipMemcpyAsync(C->colors, color.data(), color.size() * sizeof(int), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(C->owners, owners.data(), owners.size() * sizeof(int), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)  // the host vectors go out of scope
+    return cfail(hc, e, "tables");
+  const long long nnodes = hc->nnodes;
+  const int nc = hc->nc;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_fill_mat, dim3(1024), dim3(256), 0, s, C->A, (long long)n * n, 0.0);
+  double* p = C->work;
+  double* y = C->work + n;
+  int rc;
+  for (int c = 0; c < ncol; ++c)
+    for (int comp = 0; comp < nc; ++comp) {
+      hipLaunchKernelGGL(k_probe, dim3(g), dim3(256), 0, s, (const int*)C->colors, c, comp, nc, nnodes, p);
+      if ((rc = launch_jacobian<double>(hc, p, y, s))) return rc;
+      hipLaunchKernelGGL(k_probe_scatter, dim3(g), dim3(256), 0, s, (const int*)(C->owners + (size_t)c * nnodes),
+                         comp, nc, nnodes, (const double*)y, C->A, C->lda);
+    }
+  if ((e = hipGetLastError()) != hipSuccess) return cfail(hc, e, "probing");
+  // check: A x = J x for x = (1, 2, ..., n) / n (every column in play)
+  {
+    std::vector<double> xh(n);
+    for (int i = 0; i < n; ++i) xh[i] = (double)(i % 97 + 1) / 97.0 - 0.5;
+    double* xv = C->work + 2 * (size_t)n;
+    if ((e = hipMemcpyAsync(xv, xh.data(), n * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+      return cfail(hc, e, "check");
+    if ((rc = launch_jacobian<double>(hc, xv, y, s))) return rc;
+    hipLaunchKernelGGL(k_check, dim3(g), dim3(256), 0, s, (const double*)C->A, C->lda, n, (const double*)xv,
+                       (const double*)y, C->part);
+    std::vector<double> out(2 * g);
+    if ((e = hipMemcpyAsync(out.data(), C->part, out.size() * sizeof(double), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return cfail(hc, e, "check");
+    double em = 0, ym = 0;
+    for (unsigned b = 0; b < g; ++b) {
+      em = std::max(em, out[2 * b]);
+      ym = std::max(ym, out[2 * b + 1]);
+    }
+    C->check_err = ym > 0 ? em / ym : em;
+    if (!(C->check_err < 1e-10))
+      return set_error(hc, MNS_ERR_HIP, "coarse matrix reconstruction does not reproduce the operator (" +
+                                            std::to_string(C->check_err) + ")");
+  }
+  if ((rc = lu_invert(hc, C, s))) return rc;
+  int info = 0;
+  if ((e = hipMemcpyAsync(&info, C->info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return cfail(hc, e, "factorization");
+  if (info) return set_error(hc, MNS_ERR_HIP, "coarse matrix is singular (zero pivot " + std::to_string(info) + ")");
+  return MNS_OK;
+}
+
+double coarse_check_error(const void* state) { return state ? ((const CoarseDirect*)state)->check_err : -1.0; }
+
+// x = A^-1 b in FP64 (b, x in the cycle's precision)
+template <typename Real>
+int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s) {
+  const auto* C = (const CoarseDirect*)state;
+  const int n = C->n;
+  const int parts = (n + kGemvCols - 1) / kGemvCols;
+  hipLaunchKernelGGL(k_gemv_part<Real>, dim3((n + kGemvRows - 1) / kGemvRows, parts), dim3(kGemvRows), 0, s,
+                     (const double*)C->Ainv, C->lda, n, b, C->part);
+  hipLaunchKernelGGL(k_gemv_sum<Real>, dim3((n + 255) / 256), dim3(256), 0, s, (const double*)C->part, n, parts, x);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+template int coarse_apply<double>(const void*, const double*, double*, hipStream_t);
+template int coarse_apply<float>(const void*, const float*, float*, hipStream_t);
+
+}  // namespace mns

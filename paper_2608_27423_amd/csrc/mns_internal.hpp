@@ -119,8 +119,10 @@ struct mns_handle {
   float* d_E32 = nullptr;
   double* d_Em64 = nullptr;     // mortar cell-side local results [comp][local node][side*faces + face]
   float* d_Em32 = nullptr;
-  double* d_hist = nullptr;     // copies of the BDF2 history / force (or null)
+  double* d_hist = nullptr;     // BDF2 history / force of the current linearization (null when not given)
   double* d_force = nullptr;
+  double* d_hist_buf = nullptr; // their buffers, allocated by the first linearization that passes them
+  double* d_force_buf = nullptr;
   // solver workspace
   int ws_restart = 0;
   double* ws64 = nullptr;
@@ -128,6 +130,8 @@ struct mns_handle {
   double* d_diag64 = nullptr;
   float* d_diag32 = nullptr;
   double* d_red = nullptr;      // reduction scratch
+  double* d_gm = nullptr;       // FGMRES state on the device: partial sums, Hessenberg, rotations, scalars
+  int gm_m = 0;                 // restart length d_gm was sized for
   double* d_step = nullptr;     // time-step work vectors (history, residual, rhs, increment, partials)
   double* d_state = nullptr;    // copy of the linearization state (multigrid injects it)
   long long lin_version = 0;    // incremented by every rotation and linearization
@@ -137,7 +141,7 @@ struct mns_handle {
   bool diag_valid = false;
   // kernel configuration (mns_set_kernel_config): fused volume + mortar launch
   int fused = -1;
-  // second stream and events of the concurrent launch (fused == 2)
+  // second stream and events of the concurrent launch (fused == 2), created at setup
   hipStream_t aux = nullptr;
   hipStream_t cap = nullptr;      // capture stream of the solver's graphs (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -218,6 +222,14 @@ int launch_fill(Real* x, Real v, int64_t n, hipStream_t s);
 template <typename Real>
 int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real diag_value, int mode,
                        hipStream_t s);
+
+// direct FP64 solve on the coarsest multigrid level (mns_coarse.hip):
+// reconstruct the level's matrix by probing, factor and invert it
+int coarse_setup(mns_handle* hc, void** state, hipStream_t s, int max_dofs);
+void coarse_free(void* state);
+double coarse_check_error(const void* state);
+template <typename Real>
+int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s);
 
 // vector casts (mns_solver.hip)
 void mg_free(mns_handle* h);

@@ -20,39 +20,6 @@
 
 namespace mns {
 
-#ifndef MNS_LDS_INTERLEAVE
-#define MNS_LDS_INTERLEAVE 0
-#endif
-#ifndef MNS_LDS_CPAD
-#define MNS_LDS_CPAD 0
-#endif
-#ifndef MNS_LDS_PAD
-#define MNS_LDS_PAD 0
-#endif
-#ifndef MNS_PL_TRANSPOSE
-#define MNS_PL_TRANSPOSE 1
-#endif
-// occupancy hint for the volume kernel: the LDS footprint already limits it
-// to about two wavefronts per SIMD, so the scheduler may spend registers on ILP
-#ifndef MNS_VOL_WAVES
-#define MNS_VOL_WAVES 0
-#endif
-// quad volume kernel: prefetch the next point's linearization data, fence
-// the scheduler between points, waves per SIMD requested from the compiler
-#ifndef MNS_QUAD_PREFETCH
-#define MNS_QUAD_PREFETCH 1
-#endif
-#ifndef MNS_QUAD_SCHED_BARRIER
-#define MNS_QUAD_SCHED_BARRIER 1
-#endif
-#ifndef MNS_QUAD_WAVES
-#define MNS_QUAD_WAVES 0
-#endif
-#if MNS_VOL_WAVES > 0
-#define MNS_VOL_ATTR __attribute__((amdgpu_waves_per_eu(MNS_VOL_WAVES, MNS_VOL_WAVES)))
-#else
-#define MNS_VOL_ATTR
-#endif
 
 template <typename Real, int DIM, int N>
 struct Shape {
@@ -68,19 +35,13 @@ struct Shape {
   static constexpr int EVAL_SLOTS = DIM * NYV + NYP;
   static constexpr int TEST_SLOTS = NC * NT;
   static constexpr int SLOTS = (EVAL_SLOTS > TEST_SLOTS) ? EVAL_SLOTS : TEST_SLOTS;
-  // LDS layout of the per-cell work arrays.  Interleaved (default): element e
-  // of cell c at e * ES + c, so the cells of a wavefront touching the same
-  // element hit adjacent banks.  Blocked: cell c owns [c * REGION, ...).
-#if MNS_LDS_INTERLEAVE
-  static constexpr int ES = CPW + MNS_LDS_CPAD;
-  static constexpr int REGION = 1;
-#else
+  // LDS layout of the per-cell work arrays: cell c owns [c * REGION, ...),
+  // element stride ES = 1
   static constexpr int ES = 1;
-  static constexpr int REGION = SLOTS * NPT + MNS_LDS_PAD;
-#endif
+  static constexpr int REGION = SLOTS * NPT;
   template <int NSLOTS>
   static constexpr int lds_size() {
-    return MNS_LDS_INTERLEAVE ? NSLOTS * NPT * ES : (CPW - 1) * (NSLOTS * NPT + MNS_LDS_PAD) + NSLOTS * NPT;
+    return (CPW - 1) * (NSLOTS * NPT) + NSLOTS * NPT;
   }
 };
 
@@ -730,7 +691,7 @@ struct PlaneShape {
   static constexpr int XS = (DIM + 1) * ((DIM == 3) ? 3 : 2);       // theta-transposed test arrays
   static constexpr int A = (ZS > TS ? ZS : TS) * N * N;             // doubles per cell in buffer A
   static constexpr int B = (YS > XS ? YS : XS) * N * N;             // doubles per cell in buffer B
-  static constexpr int REGION = A + B + MNS_LDS_PAD;
+  static constexpr int REGION = A + B;
 };
 
 // Jacobian vmult with stored linearization, volume part (Sec. 2.3 blocks).
@@ -772,7 +733,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
   const int me = tb * N + ta;  // this lane's position in a plane
   // z-stage outputs and theta-transposed test arrays are written transposed
   // (theta index major) so that every later LDS read is contiguous
-  const int meT = MNS_PL_TRANSPOSE ? ta * N + tb : me;
+  const int meT = ta * N + tb;
 
   Real u[NC][NZ];
   if (active) gather_line<Real, DIM, N>(G, k, C, ta, tb, src, true, u);
@@ -822,7 +783,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
 #pragma unroll
       for (int arr = 0; arr < P::ZS; ++arr)
 #pragma unroll
-        for (int b = 0; b < N; ++b) zin[arr][b] = A[arr * PL + (MNS_PL_TRANSPOSE ? ta * N + b : b * N + ta)];
+        for (int b = 0; b < N; ++b) zin[arr][b] = A[arr * PL + ta * N + b];
       Real yout[P::YS];
 #pragma unroll
       for (int m = 0; m < NC; ++m) {
@@ -958,7 +919,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         Real y0 = 0, yz = 0;
 #pragma unroll
         for (int qj = 0; qj < N; ++qj) {
-          const int xi = MNS_PL_TRANSPOSE ? ta * N + qj : qj * N + ta;
+          const int xi = ta * N + qj;
           y0 += sT.V[qj][tb] * B[(m * NX + 0) * PL + xi] + sT.D[qj][tb] * B[(m * NX + 1) * PL + xi];
           if constexpr (DIM == 3) yz += sT.V[qj][tb] * B[(m * NX + 2) * PL + xi];
         }
@@ -980,7 +941,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
 }
 
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
+__global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                                      const Real* __restrict__ lin,
                                                                      const Real* __restrict__ src,
                                                                      Real* __restrict__ E) {
@@ -1143,16 +1104,15 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
 
   // every load that does not depend on arithmetic is issued here, before the
   // nodal values are used, so that their latencies overlap: the cos/sin of the
-  // lane's theta point, the linearization data of the first MNS_QUAD_PREFETCH
-  // points (then kept that many points ahead through a register ring, points
-  // in (q, qj) order) and the nodal values
+  // lane's theta point, the linearization data of the first point (then kept
+  // one point ahead, points in (q, qj) order) and the nodal values
   Real trc, trs;
   {
     const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + ts) * 2;
     trc = tr[0];
     trs = tr[1];
   }
-  constexpr int PF = ULDS ? 1 : (MNS_QUAD_PREFETCH > 0 ? MNS_QUAD_PREFETCH : 1);
+  constexpr int PF = 1;
   const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
   Real ring[PF][LL::SIZE];
   if constexpr (!ULDS) {
@@ -1222,9 +1182,7 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
           if constexpr (ULDS) us[((m * N + qj) * N + q) * 64 + lane] = uq;
           else U[m][qj][q] = uq;
         }
-#if MNS_QUAD_SCHED_BARRIER
       __builtin_amdgcn_sched_barrier(0);
-#endif
     }
   }
 
@@ -1351,7 +1309,6 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
           F[m][qj][j] += T.CD[q][j] * tc[m][3];
         }
       }
-#if MNS_QUAD_SCHED_BARRIER
       // pin the accumulators at the end of every point (otherwise the
       // additions are deferred and every product stays live), and keep the
       // scheduler from interleaving points
@@ -1362,7 +1319,6 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
 #pragma unroll
           for (int c = 0; c < N; ++c) asm volatile("" : "+v"(F[m][b][c]));
       __builtin_amdgcn_sched_barrier(0);
-#endif
     }
 
   // back to the nodes: transposed interpolation across the quad (theta),
@@ -1427,20 +1383,12 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
           Ec[(size_t)(m * Q::NPT + c * Q::PL + b * N + ts) * G.ncells] = v;
         }
       }
-#if MNS_QUAD_SCHED_BARRIER
     __builtin_amdgcn_sched_barrier(0);
-#endif
   }
 }
 
-#if MNS_QUAD_WAVES
-#define MNS_QUAD_ATTR __attribute__((amdgpu_waves_per_eu(MNS_QUAD_WAVES, MNS_QUAD_WAVES)))
-#else
-#define MNS_QUAD_ATTR
-#endif
-
 template <typename Real, int N>
-__global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_volume_quad(Geom<Real> G, Tab1D<Real, N> T, int k,
+__global__ __launch_bounds__(64) void k_jacobian_volume_quad(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                              const Real* __restrict__ lin,
                                                              const Real* __restrict__ src, Real* __restrict__ E,
                                                              int strip) {
@@ -1476,7 +1424,7 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
   const int ta = t % N, tb = t / N;
   const int cell = blockIdx.x * S::CPW + cl;
   const bool active = cl < S::CPW && cell < G.ncells;
-  Real* L = lds + (active ? cl : 0) * (S::ES == 1 ? SL * S::NPT + MNS_LDS_PAD : 1);
+  Real* L = lds + (active ? cl : 0) * (SL * S::NPT);
   CellId C = decode_cell(G, active ? cell : 0);
   const bool has_hist = hist != nullptr, has_force = force != nullptr;
 
@@ -2061,7 +2009,7 @@ union FusedSmem {
 };
 
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_fused(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
+__global__ __launch_bounds__(64) void k_jacobian_fused(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
                                                                     const Real* __restrict__ lin,
                                                                     const MortarTab<Real, N>* __restrict__ Mp,
                                                                     const Real* __restrict__ mtrig,
@@ -2074,7 +2022,7 @@ __global__ __launch_bounds__(64) MNS_VOL_ATTR void k_jacobian_fused(Geom<Real> G
 
 // fused launch with the quad volume layout (3D)
 template <typename Real, int N>
-__global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_jacobian_fused_quad(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
+__global__ __launch_bounds__(64) void k_jacobian_fused_quad(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
                                                             const Real* __restrict__ lin,
                                                             const MortarTab<Real, N>* __restrict__ Mp,
                                                             const Real* __restrict__ mtrig,
@@ -2254,14 +2202,10 @@ static int hip_check(mns_handle* h, const char* what);
 // 262k, 524k and 2M cells)
 constexpr long long kConcurrentCells = 1 << 18;
 
-// second stream (default priority) and fork/join events, created on first use
+// second stream (default priority) and fork/join events, created at setup
 static int ensure_aux_stream(mns_handle* h) {
-  if (h->aux) return MNS_OK;
-  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
-    return hip_check(h, "second stream");
-  return MNS_OK;
+  if (h->aux && h->ev_fork && h->ev_join) return MNS_OK;
+  return set_error(h, MNS_ERR_HIP, "second stream missing (handle not set up)");
 }
 
 static int hip_check(mns_handle* h, const char* what) {
@@ -2436,7 +2380,7 @@ __device__ inline int batch_item_of(const long long* __restrict__ start, int cou
 }
 
 template <typename Real, int N>
-__global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_batch_jacobian_quad(const BatchItem<Real>* __restrict__ items,
+__global__ __launch_bounds__(64) void k_batch_jacobian_quad(const BatchItem<Real>* __restrict__ items,
                                                                           const long long* __restrict__ mstart,
                                                                           const long long* __restrict__ vstart,
                                                                           int count, Tab1D<Real, N> T, int k,
@@ -2472,7 +2416,7 @@ __global__ __launch_bounds__(64) MNS_QUAD_ATTR void k_batch_jacobian_quad(const 
 }
 
 template <typename Real, int DIM, int N>
-__global__ __launch_bounds__(64) MNS_VOL_ATTR void k_batch_jacobian(const BatchItem<Real>* __restrict__ items,
+__global__ __launch_bounds__(64) void k_batch_jacobian(const BatchItem<Real>* __restrict__ items,
                                                                     const long long* __restrict__ mstart,
                                                                     const long long* __restrict__ vstart, int count,
                                                                     Tab1D<Real, N> T, int k,
@@ -2640,6 +2584,7 @@ int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
   MNS_DISPATCH(h->dim, h->k, return (do_jacobian<Real, DIM, N>(h, src, dst, s)));
   return MNS_OK;
 }
+
 
 template <int DIM, int N, bool RES>
 static int do_state(mns_handle* h, const double* state, const double* hist, const double* force, double* lin,

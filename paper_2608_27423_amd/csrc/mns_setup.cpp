@@ -251,63 +251,188 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
   if ((e = hipMalloc((void**)&h->d_E32, nE * sizeof(float))) != hipSuccess) return hipfail(h, e, "hipMalloc E");
   if ((e = hipMalloc((void**)&h->d_Em64, nEm * sizeof(double))) != hipSuccess) return hipfail(h, e, "hipMalloc Em");
   if ((e = hipMalloc((void**)&h->d_Em32, nEm * sizeof(float))) != hipSuccess) return hipfail(h, e, "hipMalloc Em");
+  // per-angle tables (written by mns_rotate_rotor), the per-point
+  // linearization store and the state copy (written by
+  // mns_set_linearization): allocated here so that those calls allocate
+  // nothing and stay stream-ordered
+  const size_t ntrig = (size_t)2 * d->n_theta * h->n * 2, nmtrig = (size_t)d->n_theta * 2 * h->n * 2;
+  size_t mtab64 = 0, mtab32 = 0;
+  switch (h->n) {
+    case 3: mtab64 = sizeof(MortarTab<double, 3>); mtab32 = sizeof(MortarTab<float, 3>); break;
+    case 4: mtab64 = sizeof(MortarTab<double, 4>); mtab32 = sizeof(MortarTab<float, 4>); break;
+    case 5: mtab64 = sizeof(MortarTab<double, 5>); mtab32 = sizeof(MortarTab<float, 5>); break;
+    case 6: mtab64 = sizeof(MortarTab<double, 6>); mtab32 = sizeof(MortarTab<float, 6>); break;
+  }
+  const int LS = d->dim == 3 ? LinLayout<3>::SIZE : LinLayout<2>::SIZE;
+  const size_t nlin = (size_t)h->ncells * npt * LS;
+  if ((e = hipMalloc((void**)&h->d_trig64, ntrig * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&h->d_trig32, ntrig * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc((void**)&h->d_mtrig64, nmtrig * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&h->d_mtrig32, nmtrig * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&h->d_mtab64, mtab64)) != hipSuccess || (e = hipMalloc(&h->d_mtab32, mtab32)) != hipSuccess)
+    return hipfail(h, e, "hipMalloc angle tables");
+  if ((e = hipMalloc((void**)&h->d_lin64, nlin * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&h->d_lin32, nlin * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc((void**)&h->d_state, (size_t)h->ndofs * sizeof(double))) != hipSuccess)
+    return hipfail(h, e, "hipMalloc linearization store");
+  // second stream (default priority) and fork/join events of the concurrent
+  // launch mode, created here so that no apply call creates them
+  if ((e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming)) != hipSuccess)
+    return hipfail(h, e, "second stream");
   return MNS_OK;
 }
 
-template <typename Real, int N>
-static void fill_mortar_tab(const mns_handle* h, MortarTab<Real, N>& M, const double* MV, const double* MD,
-                            const double* FV, const double* FD, const double* jxw, const int* active) {
-  std::memset(&M, 0, sizeof(M));
-  for (int side = 0; side < 2; ++side)
-    for (int s = 0; s < 2; ++s)
-      for (int q = 0; q < N; ++q)
-        for (int a = 0; a < N; ++a) {
-          M.MV[side][s][q][a] = (Real)MV[((side * 2 + s) * N + q) * N + a];
-          M.MD[side][s][q][a] = (Real)MD[((side * 2 + s) * N + q) * N + a];
-        }
-  for (int side = 0; side < 2; ++side)
-    for (int b = 0; b < N; ++b) {
-      M.FV[side][b] = (Real)FV[side * N + b];
-      M.FD[side][b] = (Real)FD[side * N + b];
+// ---------------------------------------------------------------------------
+// Per-angle tables (Sec. 3.1 rotation, Sec. 3.2 mortar segments), built on
+// the device by one small kernel so that a rotation is ordered on the
+// caller's stream like every other call, synchronizes nothing and can be
+// captured into a graph (its arguments are plain values).
+// ---------------------------------------------------------------------------
+struct RotArgs {
+  double theta, phi, dth, R, dz;
+  int nt, dim, m;
+  double gll[kMaxN], gx[kMaxN], gw[kMaxN];
+  double tau_pen[2], inv_dr[2];
+};
+
+// Lagrange basis on the N nodes, value and first derivative at t (product
+// rule, one linear factor at a time)
+template <int N>
+__device__ inline void lagrange_dev(const double (&nodes)[kMaxN], double t, double (&L)[N], double (&dL)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double p = 1.0, dp = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (q == j) continue;
+      const double inv = 1.0 / (nodes[j] - nodes[q]);
+      const double f = (t - nodes[q]) * inv;
+      dp = dp * f + p * inv;
+      p = p * f;
     }
-  for (int s = 0; s < 2; ++s)
+    L[j] = p;
+    dL[j] = dp;
+  }
+}
+
+// Work items, in order: (domain, cell, Gauss point) cos/sin of the volume
+// points; (stator face, segment, point) cos/sin of the mortar points; (side,
+// segment, point) rows of the mortar value/derivative tables; (side) rows of
+// the face tables; one item for the weights and scalars.  Segment 0 of stator
+// face j spans [j dth, j dth + phi], segment 1 [j dth + phi, (j+1) dth]; the
+// theta coordinate of mortar point t on each side:
+//   stator: seg 0 xi = t phi/dth,               seg 1 xi = phi/dth + t (1 - phi/dth)
+//   rotor:  seg 0 xi = 1 - phi/dth + t phi/dth,  seg 1 xi = t (1 - phi/dth)
+template <int N>
+__global__ void k_rotate_tables(RotArgs A, double* __restrict__ trig64, float* __restrict__ trig32,
+                                double* __restrict__ mtrig64, float* __restrict__ mtrig32,
+                                MortarTab<double, N>* __restrict__ M64, MortarTab<float, N>* __restrict__ M32) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nt = A.nt;
+  const long long n_trig = 2LL * nt * N, n_mtrig = (long long)nt * 2 * N;
+  const double len[2] = {A.phi, A.dth - A.phi};
+  const double start[2] = {0.0, A.phi};
+  if (i < n_trig) {
+    const int dom = (int)(i / ((long long)nt * N));
+    const int ct = (int)((i / N) % nt), q = (int)(i % N);
+    const double ang = (dom == 0 ? A.theta : 0.0) + (ct + A.gx[q]) * A.dth;
+    const double c = cos(ang), sn = sin(ang);
+    trig64[2 * i] = c;
+    trig64[2 * i + 1] = sn;
+    trig32[2 * i] = (float)c;
+    trig32[2 * i + 1] = (float)sn;
+    return;
+  }
+  long long j = i - n_trig;
+  if (j < n_mtrig) {
+    const int face = (int)(j / (2 * N)), sg = (int)((j / N) % 2), q = (int)(j % N);
+    const double ang = face * A.dth + start[sg] + A.gx[q] * len[sg];
+    const double c = cos(ang), sn = sin(ang);
+    mtrig64[2 * j] = c;
+    mtrig64[2 * j + 1] = sn;
+    mtrig32[2 * j] = (float)c;
+    mtrig32[2 * j + 1] = (float)sn;
+    return;
+  }
+  j -= n_mtrig;
+  const double f = A.phi / A.dth;
+  if (j < 4 * N) {
+    const int side = (int)(j / (2 * N)), sg = (int)((j / N) % 2), q = (int)(j % N);
+    const double t = A.gx[q];
+    const double xi = side == 1 ? (sg == 0 ? t * f : f + t * (1.0 - f)) : (sg == 0 ? 1.0 - f + t * f : t * (1.0 - f));
+    double L[N], dL[N];
+    lagrange_dev<N>(A.gll, xi, L, dL);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      M64->MV[side][sg][q][a] = L[a];
+      M64->MD[side][sg][q][a] = dL[a];
+      M32->MV[side][sg][q][a] = (float)L[a];
+      M32->MD[side][sg][q][a] = (float)dL[a];
+    }
+    return;
+  }
+  j -= 4 * N;
+  if (j < 2) {
+    const int side = (int)j;
+    double L[N], dL[N];
+    lagrange_dev<N>(A.gll, side == 0 ? 1.0 : 0.0, L, dL);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      M64->FV[side][b] = L[b];
+      M64->FD[side][b] = dL[b];
+      M32->FV[side][b] = (float)L[b];
+      M32->FD[side][b] = (float)dL[b];
+    }
+    return;
+  }
+  if (j != 2) return;
+  // Eq. Eq-Jacobian with the segment angle: JxW = w_t R dtheta_seg (w_z dz)
+#pragma unroll
+  for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
     for (int qt = 0; qt < N; ++qt)
-      for (int qz = 0; qz < N; ++qz) M.jxw[s][qt][qz] = (Real)jxw[(s * N + qt) * N + qz];
-  M.tau_pen[0] = (Real)h->tau_pen[0];
-  M.tau_pen[1] = (Real)h->tau_pen[1];
-  M.R = (Real)h->desc.r_interface;
-  const mns_mesh_desc& d = h->desc;
-  M.inv_rdth = (Real)(1.0 / (d.r_interface * h->dth));
-  M.inv_dr[0] = (Real)(1.0 / ((d.r_interface - d.r_in) / d.n_r_rotor));
-  M.inv_dr[1] = (Real)(1.0 / ((d.r_out - d.r_interface) / d.n_r_stator));
-  M.inv_dz = d.dim == 3 ? (Real)(1.0 / h->dz) : Real(0);
-  M.seg_active[0] = active[0];
-  M.seg_active[1] = active[1];
-  M.m = h->m;
+#pragma unroll
+      for (int qz = 0; qz < N; ++qz) {
+        double w = A.gw[qt] * A.R * len[sg];
+        if (A.dim == 3) w *= A.gw[qz] * A.dz;
+        else if (qz > 0) w = 0.0;
+        M64->jxw[sg][qt][qz] = w;
+        M32->jxw[sg][qt][qz] = (float)w;
+      }
+  const double inv_rdth = 1.0 / (A.R * A.dth), inv_dz = A.dim == 3 ? 1.0 / A.dz : 0.0;
+  for (int sd = 0; sd < 2; ++sd) {
+    M64->tau_pen[sd] = A.tau_pen[sd];
+    M32->tau_pen[sd] = (float)A.tau_pen[sd];
+    M64->inv_dr[sd] = A.inv_dr[sd];
+    M32->inv_dr[sd] = (float)A.inv_dr[sd];
+  }
+  M64->R = A.R;
+  M32->R = (float)A.R;
+  M64->inv_rdth = inv_rdth;
+  M32->inv_rdth = (float)inv_rdth;
+  M64->inv_dz = inv_dz;
+  M32->inv_dz = (float)inv_dz;
+  const int act0 = A.phi > 0.0 ? 1 : 0;
+  M64->seg_active[0] = M32->seg_active[0] = act0;
+  M64->seg_active[1] = M32->seg_active[1] = 1;
+  M64->m = M32->m = A.m;
 }
 
 template <int N>
-static int upload_mortar(mns_handle* h, const double* MV, const double* MD, const double* FV, const double* FD,
-                         const double* jxw, const int* active) {
-  MortarTab<double, N> M64;
-  MortarTab<float, N> M32;
-  fill_mortar_tab<double, N>(h, M64, MV, MD, FV, FD, jxw, active);
-  fill_mortar_tab<float, N>(h, M32, MV, MD, FV, FD, jxw, active);
-  hipError_t e;
-  if (!h->d_mtab64) {
-    if ((e = hipMalloc(&h->d_mtab64, sizeof(M64))) != hipSuccess) return hipfail(h, e, "hipMalloc");
-    if ((e = hipMalloc(&h->d_mtab32, sizeof(M32))) != hipSuccess) return hipfail(h, e, "hipMalloc");
-  }
-  if ((e = hipMemcpy(h->d_mtab64, &M64, sizeof(M64), hipMemcpyHostToDevice)) != hipSuccess)
-    return hipfail(h, e, "hipMemcpy");
-  if ((e = hipMemcpy(h->d_mtab32, &M32, sizeof(M32), hipMemcpyHostToDevice)) != hipSuccess)
-    return hipfail(h, e, "hipMemcpy");
-  return MNS_OK;
+static int launch_rotate(mns_handle* h, const RotArgs& A, hipStream_t s) {
+  const long long items = 2LL * A.nt * N + (long long)A.nt * 2 * N + 4 * N + 3;
+  const unsigned blocks = (unsigned)((items + 255) / 256);
+  hipLaunchKernelGGL(k_rotate_tables<N>, dim3(blocks), dim3(256), 0, s, A, h->d_trig64, h->d_trig32, h->d_mtrig64,
+                     h->d_mtrig32, (MortarTab<double, N>*)h->d_mtab64, (MortarTab<float, N>*)h->d_mtab32);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MNS_OK : hipfail(h, e, "rotate kernel");
 }
 
 // Rotation x = R(theta) x0 of the rotor (Sec. 3.1) and the mortar tables of
-// Sec. 3.2 for that angle.
-int mns_rotate_tables(mns_handle* h, double theta, double omega) {
+// Sec. 3.2 for that angle, enqueued on stream s.
+int mns_rotate_tables(mns_handle* h, double theta, double omega, hipStream_t s) {
   const mns_mesh_desc& d = h->desc;
   const int N = h->n, nt = d.n_theta;
   const double dth = h->dth;
@@ -325,74 +450,29 @@ int mns_rotate_tables(mns_handle* h, double theta, double omega) {
   h->omega = omega;
   h->m = (int)m;
   h->phi = phi;
-
-  // volume geometry: cos, sin of the physical angle at each Gauss point
-  std::vector<double> trig((size_t)2 * nt * N * 2);
-  for (int dom = 0; dom < 2; ++dom)
-    for (int ct = 0; ct < nt; ++ct)
-      for (int q = 0; q < N; ++q) {
-        const double ang = (dom == 0 ? theta : 0.0) + (ct + h->gx[q]) * dth;
-        trig[(((size_t)dom * nt + ct) * N + q) * 2 + 0] = std::cos(ang);
-        trig[(((size_t)dom * nt + ct) * N + q) * 2 + 1] = std::sin(ang);
-      }
-  // mortar segments of stator face j: [j dth, j dth + phi], [j dth + phi, (j+1) dth]
-  const double len[2] = {phi, dth - phi};
-  const double start[2] = {0.0, phi};
-  const int active[2] = {phi > 0.0 ? 1 : 0, 1};
-  std::vector<double> mtrig((size_t)nt * 2 * N * 2);
-  for (int j = 0; j < nt; ++j)
-    for (int s = 0; s < 2; ++s)
-      for (int q = 0; q < N; ++q) {
-        const double ang = j * dth + start[s] + h->gx[q] * len[s];
-        mtrig[(((size_t)j * 2 + s) * N + q) * 2 + 0] = std::cos(ang);
-        mtrig[(((size_t)j * 2 + s) * N + q) * 2 + 1] = std::sin(ang);
-      }
-  // theta coordinates of the mortar points on each side
-  //   stator: seg 0 xi = t phi/dth,          seg 1 xi = phi/dth + t (1 - phi/dth)
-  //   rotor:  seg 0 xi = 1 - phi/dth + t phi/dth, seg 1 xi = t (1 - phi/dth)
-  const double f = phi / dth;
-  std::vector<double> MV(2 * 2 * N * N), MD(2 * 2 * N * N), L(N), dL(N), d2L(N);
-  for (int side = 0; side < 2; ++side)
-    for (int s = 0; s < 2; ++s)
-      for (int q = 0; q < N; ++q) {
-        const double t = h->gx[q];
-        double xi;
-        if (side == 1) xi = s == 0 ? t * f : f + t * (1.0 - f);
-        else xi = s == 0 ? 1.0 - f + t * f : t * (1.0 - f);
-        lagrange_1d(h->gll, xi, L.data(), dL.data(), d2L.data());
-        for (int a = 0; a < N; ++a) {
-          MV[((side * 2 + s) * N + q) * N + a] = L[a];
-          MD[((side * 2 + s) * N + q) * N + a] = dL[a];
-        }
-      }
-  std::vector<double> FV(2 * N), FD(2 * N);
-  for (int side = 0; side < 2; ++side) {
-    lagrange_1d(h->gll, side == 0 ? 1.0 : 0.0, L.data(), dL.data(), d2L.data());
-    for (int b = 0; b < N; ++b) {
-      FV[side * N + b] = L[b];
-      FD[side * N + b] = dL[b];
-    }
+  RotArgs A{};
+  A.theta = theta;
+  A.phi = phi;
+  A.dth = dth;
+  A.R = d.r_interface;
+  A.dz = h->dz;
+  A.nt = nt;
+  A.dim = d.dim;
+  A.m = (int)m;
+  for (int q = 0; q < N; ++q) {
+    A.gll[q] = h->gll[q];
+    A.gx[q] = h->gx[q];
+    A.gw[q] = h->gw[q];
   }
-  // Eq. Eq-Jacobian with the segment angle: JxW = w_t R dtheta_seg (w_z dz)
-  std::vector<double> jxw(2 * N * N, 0.0);
-  for (int s = 0; s < 2; ++s)
-    for (int qt = 0; qt < N; ++qt)
-      for (int qz = 0; qz < N; ++qz) {
-        double w = h->gw[qt] * d.r_interface * len[s];
-        if (d.dim == 3) w *= h->gw[qz] * h->dz;
-        else if (qz > 0) w = 0.0;
-        jxw[(s * N + qt) * N + qz] = w;
-      }
-  int rc = upload(h, &h->d_trig64, trig);
-  if (!rc) rc = upload(h, &h->d_trig32, to_f32(trig));
-  if (!rc) rc = upload(h, &h->d_mtrig64, mtrig);
-  if (!rc) rc = upload(h, &h->d_mtrig32, to_f32(mtrig));
-  if (rc) return rc;
+  A.tau_pen[0] = h->tau_pen[0];
+  A.tau_pen[1] = h->tau_pen[1];
+  A.inv_dr[0] = 1.0 / ((d.r_interface - d.r_in) / d.n_r_rotor);
+  A.inv_dr[1] = 1.0 / ((d.r_out - d.r_interface) / d.n_r_stator);
   switch (N) {
-    case 3: return upload_mortar<3>(h, MV.data(), MD.data(), FV.data(), FD.data(), jxw.data(), active);
-    case 4: return upload_mortar<4>(h, MV.data(), MD.data(), FV.data(), FD.data(), jxw.data(), active);
-    case 5: return upload_mortar<5>(h, MV.data(), MD.data(), FV.data(), FD.data(), jxw.data(), active);
-    case 6: return upload_mortar<6>(h, MV.data(), MD.data(), FV.data(), FD.data(), jxw.data(), active);
+    case 3: return launch_rotate<3>(h, A, s);
+    case 4: return launch_rotate<4>(h, A, s);
+    case 5: return launch_rotate<5>(h, A, s);
+    case 6: return launch_rotate<6>(h, A, s);
   }
   return set_error(h, MNS_ERR_UNSUPPORTED, "degree");
 }

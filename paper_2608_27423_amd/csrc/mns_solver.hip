@@ -74,70 +74,6 @@ __global__ __launch_bounds__(kRedThreads) void k_multidot(const double* __restri
   block_sum_store<kDotK>(acc, K + self, part);
 }
 
-// w -= sum_i h_i V_i ; partial ||w||^2 (coefficients in registers for K <= 32)
-__global__ __launch_bounds__(kRedThreads) void k_multiaxpy_norm(const double* __restrict__ V, long long n, int K,
-                                                                const double* __restrict__ hcoef,
-                                                                double* __restrict__ w, double* __restrict__ part) {
-  double acc[1] = {0};
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  if (K <= kDotK) {
-    double hh[kDotK];
-#pragma unroll
-    for (int i = 0; i < kDotK; ++i) {
-      hh[i] = 0.0;
-      if (i < K) hh[i] = hcoef[i];
-    }
-    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-      double x = w[r];
-#pragma unroll
-      for (int i = 0; i < kDotK; ++i)
-        if (i < K) x -= hh[i] * V[(long long)i * n + r];
-      w[r] = x;
-      acc[0] += x * x;
-    }
-  } else {
-    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-      double x = w[r];
-      for (int i = 0; i < K; ++i) x -= hcoef[i] * V[(long long)i * n + r];
-      w[r] = x;
-      acc[0] += x * x;
-    }
-  }
-  block_sum_store<1>(acc, 1, part);
-}
-
-// fused Gram-Schmidt pass (K <= 31): w -= sum_i h_i V_i, then partial dots of
-// the updated w with V_0 .. V_{K-1} and w . w (entry K), reading V once
-__global__ __launch_bounds__(kRedThreads) void k_multiaxpy_dot(const double* __restrict__ V, long long n, int K,
-                                                               const double* __restrict__ hcoef,
-                                                               double* __restrict__ w, double* __restrict__ part) {
-  double hh[kDotK], acc[kDotK];
-#pragma unroll
-  for (int i = 0; i < kDotK; ++i) {
-    hh[i] = 0.0;
-    if (i < K) hh[i] = hcoef[i];
-    acc[i] = 0;
-  }
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-    double v[kDotK];
-    double x = w[r];
-#pragma unroll
-    for (int i = 0; i < kDotK; ++i) {
-      v[i] = 0.0;
-      if (i < K) v[i] = V[(long long)i * n + r];
-      x -= hh[i] * v[i];
-    }
-    w[r] = x;
-#pragma unroll
-    for (int i = 0; i < kDotK; ++i) {
-      if (i < K) acc[i] += v[i] * x;
-      if (i == K) acc[i] += x * x;
-    }
-  }
-  block_sum_store<kDotK>(acc, K + 1, part);
-}
-
 // second stage: out[i] = sum over blocks of part[b * K + i], fixed order
 __global__ void k_reduce_parts(const double* __restrict__ part, int nblocks, int K, double* __restrict__ out) {
   __shared__ double s[256];
@@ -226,6 +162,328 @@ __global__ __launch_bounds__(kRedThreads) void k_power_step(const double* __rest
   block_sum_store<1>(acc, 1, part);
 }
 
+// ---------------------------------------------------------------------------
+// FGMRES iteration on the device.  The Gram-Schmidt coefficients, the
+// Hessenberg column, the Givens rotations, the residual estimate and the
+// convergence flag live in device memory, and every kernel of an iteration
+// reads the column index j from there, so one iteration is the same sequence
+// of launches for every j: it is captured once per solve into a graph and
+// replayed, and the host reads the state back once per chunk of iterations.
+// Layout of the state (doubles, restart m, P = m + 2): partial sums
+// [kRedBlocks][P], hcol[P], h2[P], cs[m], sn[m], g[m + 1], H[(m + 1) m]
+// (row-major, H[i m + j]), y[m], misc[16].
+// ---------------------------------------------------------------------------
+enum {
+  GM_J = 0,       // column of the next iteration
+  GM_DONE = 1,    // 1 once the residual estimate met the target or w vanished
+  GM_BROKEN = 2,  // 1 when a non-finite norm appeared
+  GM_TARGET = 3,  // absolute residual target
+  GM_ITS = 4,     // iterations taken in this cycle
+  GM_RES = 5,     // |g[j]| after the last iteration
+  GM_INVWN = 6,   // 1 / ||w|| of the last iteration (0 when it vanished)
+  GM_NRM2 = 7,    // ||w||^2 of the optional third projection pass
+  GM_MISC = 16
+};
+
+struct GmView {
+  double* part;
+  int P, m;
+  double *hcol, *h2, *cs, *sn, *g, *H, *y, *misc;
+};
+
+static size_t gm_doubles(int m) {
+  const size_t P = (size_t)m + 2;
+  return (size_t)kRedBlocks * P + 2 * P + 2 * (size_t)m + (m + 1) + (size_t)(m + 1) * m + m + GM_MISC;
+}
+
+static GmView gm_view(double* base, int m) {
+  GmView G;
+  G.P = m + 2;
+  G.m = m;
+  G.part = base;
+  G.hcol = G.part + (size_t)kRedBlocks * G.P;
+  G.h2 = G.hcol + G.P;
+  G.cs = G.h2 + G.P;
+  G.sn = G.cs + m;
+  G.g = G.sn + m;
+  G.H = G.g + (m + 1);
+  G.y = G.H + (size_t)(m + 1) * m;
+  G.misc = G.y + m;
+  return G;
+}
+
+__device__ inline int gm_j(const GmView& G) { return (int)G.misc[GM_J]; }
+__device__ inline bool gm_done(const GmView& G) { return G.misc[GM_DONE] != 0.0; }
+
+// block sum of cnt <= MAXK values per thread into out[0 .. cnt) (same order
+// as block_sum_store); ends with a barrier so that it can run in a loop
+template <int MAXK>
+__device__ inline void block_sum_row(double (&v)[MAXK], int cnt, double* out) {
+  __shared__ double s[kRedThreads / 64][MAXK];
+  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+#pragma unroll
+  for (int i = 0; i < MAXK; ++i) {
+    if (i < cnt) {
+      double x = v[i];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) s[wid][i] = x;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    double t = 0;
+    for (int w = 0; w < kRedThreads / 64; ++w) t += s[w][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// partial dots of w with V_0 .. V_{K-1} and w . w (entry K), K = j + 1, in
+// groups of kDotK entries
+__global__ __launch_bounds__(kRedThreads) void k_gm_dots(GmView G, const double* __restrict__ V, long long n,
+                                                         const double* __restrict__ w) {
+  if (gm_done(G)) return;
+  const int K = gm_j(G) + 1, cnt = K + 1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (int g0 = 0; g0 < cnt; g0 += kDotK) {
+    double acc[kDotK];
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) acc[i] = 0;
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      const double wr = w[r];
+#pragma unroll
+      for (int i = 0; i < kDotK; ++i) {
+        const int ii = g0 + i;
+        if (ii < K) acc[i] += V[(long long)ii * n + r] * wr;
+        if (ii == K) acc[i] += wr * wr;
+      }
+    }
+    block_sum_row<kDotK>(acc, cnt - g0 < kDotK ? cnt - g0 : kDotK, G.part + (size_t)blockIdx.x * G.P + g0);
+  }
+}
+
+// w -= sum_i hcol_i V_i (i < K), then partial dots of the new w with V_0 ..
+// V_{K-1} and w . w (entry K).  For K < kDotK one pass with the row of V in
+// registers; otherwise the update first, then the dots in groups.
+__global__ __launch_bounds__(kRedThreads) void k_gm_axpy_dots(GmView G, const double* __restrict__ V, long long n,
+                                                              double* __restrict__ w) {
+  if (gm_done(G)) return;
+  const int K = gm_j(G) + 1, cnt = K + 1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const double* hc = G.hcol;
+  if (K < kDotK) {
+    double hh[kDotK], acc[kDotK];
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) {
+      hh[i] = 0.0;
+      if (i < K) hh[i] = hc[i];
+      acc[i] = 0;
+    }
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double v[kDotK];
+      double x = w[r];
+#pragma unroll
+      for (int i = 0; i < kDotK; ++i) {
+        v[i] = 0.0;
+        if (i < K) v[i] = V[(long long)i * n + r];
+        x -= hh[i] * v[i];
+      }
+      w[r] = x;
+#pragma unroll
+      for (int i = 0; i < kDotK; ++i) {
+        if (i < K) acc[i] += v[i] * x;
+        if (i == K) acc[i] += x * x;
+      }
+    }
+    block_sum_row<kDotK>(acc, cnt, G.part + (size_t)blockIdx.x * G.P);
+    return;
+  }
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    double x = w[r];
+    for (int i = 0; i < K; ++i) x -= hc[i] * V[(long long)i * n + r];
+    w[r] = x;
+  }
+  for (int g0 = 0; g0 < cnt; g0 += kDotK) {
+    double acc[kDotK];
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) acc[i] = 0;
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      const double x = w[r];  // this thread's own rows, updated above
+#pragma unroll
+      for (int i = 0; i < kDotK; ++i) {
+        const int ii = g0 + i;
+        if (ii < K) acc[i] += V[(long long)ii * n + r] * x;
+        if (ii == K) acc[i] += x * x;
+      }
+    }
+    block_sum_row<kDotK>(acc, cnt - g0 < kDotK ? cnt - g0 : kDotK, G.part + (size_t)blockIdx.x * G.P + g0);
+  }
+}
+
+// reorthogonalization (DGKS): when the projected norm dropped below 0.7 of
+// the norm before the projection, w -= sum_i h2_i V_i and partial ||w||^2
+__device__ inline bool gm_reorth(const GmView& G, int K) { return sqrt(G.h2[K]) < 0.7 * sqrt(G.hcol[K]); }
+
+__global__ __launch_bounds__(kRedThreads) void k_gm_reorth(GmView G, const double* __restrict__ V, long long n,
+                                                           double* __restrict__ w) {
+  if (gm_done(G)) return;
+  const int K = gm_j(G) + 1;
+  if (!gm_reorth(G, K)) return;
+  double acc[1] = {0};
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const double* hc = G.h2;
+  if (K <= kDotK) {
+    double hh[kDotK];
+#pragma unroll
+    for (int i = 0; i < kDotK; ++i) {
+      hh[i] = 0.0;
+      if (i < K) hh[i] = hc[i];
+    }
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double x = w[r];
+#pragma unroll
+      for (int i = 0; i < kDotK; ++i)
+        if (i < K) x -= hh[i] * V[(long long)i * n + r];
+      w[r] = x;
+      acc[0] += x * x;
+    }
+  } else {
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+      double x = w[r];
+      for (int i = 0; i < K; ++i) x -= hc[i] * V[(long long)i * n + r];
+      w[r] = x;
+      acc[0] += x * x;
+    }
+  }
+  block_sum_row<1>(acc, 1, G.part + (size_t)blockIdx.x * G.P);
+}
+
+// second stage of the reductions (fixed order, as k_reduce_parts): which 0:
+// hcol[0 .. K], 1: h2[0 .. K], 2: the third pass's ||w||^2 (only when it ran)
+__global__ void k_gm_reduce(GmView G, int which, int nblocks) {
+  if (gm_done(G)) return;
+  const int K = gm_j(G) + 1;
+  if (which == 2 && !gm_reorth(G, K)) return;
+  const int cnt = which == 2 ? 1 : K + 1;
+  double* out = which == 0 ? G.hcol : which == 1 ? G.h2 : G.misc + GM_NRM2;
+  __shared__ double s[256];
+  for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+    double t = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) t += G.part[(long long)b * G.P + i];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = s[0];
+    __syncthreads();
+  }
+}
+
+// Hessenberg column, Givens rotations and the residual estimate of column j
+// (one thread; products are not contracted, as on the host)
+__global__ void k_gm_givens(GmView G) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || blockIdx.x != 0 || gm_done(G)) return;
+  const int j = gm_j(G), K = j + 1, m = G.m;
+  double* hcol = G.hcol;
+  double wn;
+  if (gm_reorth(G, K)) {
+    wn = sqrt(G.misc[GM_NRM2]);
+    for (int i = 0; i < K; ++i) hcol[i] += G.h2[i];
+  } else {
+    wn = sqrt(G.h2[K]);
+  }
+  hcol[j + 1] = wn;
+  if (!isfinite(wn)) {
+    G.misc[GM_BROKEN] = 1.0;
+    G.misc[GM_DONE] = 1.0;
+    G.misc[GM_INVWN] = 0.0;
+    return;
+  }
+  for (int i = 0; i < j; ++i) {
+    const double a = G.cs[i] * hcol[i] + G.sn[i] * hcol[i + 1];
+    const double b = -G.sn[i] * hcol[i] + G.cs[i] * hcol[i + 1];
+    hcol[i] = a;
+    hcol[i + 1] = b;
+  }
+  const double den = hypot(hcol[j], hcol[j + 1]);
+  G.cs[j] = den > 0 ? hcol[j] / den : 1.0;
+  G.sn[j] = den > 0 ? hcol[j + 1] / den : 0.0;
+  hcol[j] = den;
+  hcol[j + 1] = 0.0;
+  G.g[j + 1] = -G.sn[j] * G.g[j];
+  G.g[j] = G.cs[j] * G.g[j];
+  for (int i = 0; i <= j; ++i) G.H[(size_t)i * m + j] = hcol[i];
+  G.misc[GM_INVWN] = wn > 0 ? 1.0 / wn : 0.0;
+  G.misc[GM_RES] = fabs(G.g[j + 1]);
+  G.misc[GM_ITS] += 1.0;
+  G.misc[GM_J] = (double)(j + 1);
+  if (fabs(G.g[j + 1]) <= G.misc[GM_TARGET] || wn == 0) G.misc[GM_DONE] = 1.0;
+}
+
+// next basis vector V_{j+1} = w / ||w|| (j already advanced by k_gm_givens;
+// skipped after a breakdown)
+__global__ void k_gm_next(GmView G, double* __restrict__ V, long long n, const double* __restrict__ w) {
+  if (G.misc[GM_BROKEN] != 0.0) return;
+  const int j = gm_j(G);
+  const double s = G.misc[GM_INVWN];
+  double* vj = V + (long long)j * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) vj[i] = s * w[i];
+}
+
+// preconditioner input: V_j (cast to the preconditioner's precision)
+template <typename To>
+__global__ void k_gm_in(GmView G, const double* __restrict__ V, long long n, To* __restrict__ dst) {
+  if (gm_done(G)) return;
+  const double* vj = V + (long long)gm_j(G) * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (To)vj[i];
+}
+
+// preconditioner output -> Z_j and the fixed FP64 input of the Jacobian
+template <typename From>
+__global__ void k_gm_out(GmView G, const From* __restrict__ src, long long n, double* __restrict__ Z,
+                         double* __restrict__ zbuf) {
+  if (gm_done(G)) return;
+  double* zj = Z + (long long)gm_j(G) * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double z = (double)src[i];
+    zj[i] = z;
+    zbuf[i] = z;
+  }
+}
+
+// start of a cycle: V_0 = r / ||r||, g = (||r||, 0, ...), j = 0
+__global__ void k_gm_start(GmView G, const double* __restrict__ r, double rnorm, double target, double* __restrict__ V,
+                           long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const double s = 1.0 / rnorm;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) V[i] = s * r[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = 0; i < GM_MISC; ++i) G.misc[i] = 0.0;
+    G.misc[GM_TARGET] = target;
+    G.misc[GM_RES] = rnorm;
+    for (int i = 0; i <= G.m; ++i) G.g[i] = 0.0;
+    G.g[0] = rnorm;
+  }
+}
+
+// y = H^-1 g (upper triangular, jj columns), one thread, as on the host
+__global__ void k_gm_backsub(GmView G, int jj) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int m = G.m;
+  for (int i = jj - 1; i >= 0; --i) {
+    double sum = G.g[i];
+    for (int k2 = i + 1; k2 < jj; ++k2) sum -= G.H[(size_t)i * m + k2] * G.y[k2];
+    G.y[i] = G.H[(size_t)i * m + i] != 0 ? sum / G.H[(size_t)i * m + i] : 0.0;
+  }
+}
+
 static unsigned grid_for(long long n) {
   long long b = (n + 255) / 256;
   if (b > 8192) b = 8192;
@@ -250,9 +508,9 @@ using namespace mns;
 namespace {
 
 struct MG;
-int mg_vcycle_in(MG* mg, const mns_solve_opts* o, const double* v, hipStream_t s);
 int mg_vcycle_body(MG* mg, const mns_solve_opts* o, hipStream_t s);
-int mg_vcycle_out(MG* mg, const mns_solve_opts* o, double* z, hipStream_t s);
+void* mg_io(MG* mg, bool out, bool f32);
+void mg_count(MG* mg, int* v64, int* v32);
 
 struct Solver {
   mns_handle* h;
@@ -283,41 +541,6 @@ struct Solver {
   int reduce(int K) {
     hipLaunchKernelGGL(k_reduce_parts, dim3(K < 64 ? K : 64), dim3(256), 0, s, parts(), kRedBlocks, K, outs());
     return hipGetLastError() == hipSuccess ? MNS_OK : err(MNS_ERR_HIP, "reduce");
-  }
-
-  // dots of w with V_0..V_{K-1} -> host
-  int multidot(const double* Vb, int K, const double* wv, double* host) {
-    for (int i0 = 0; i0 < K; i0 += 32) {
-      const int kk = (K - i0) < 32 ? (K - i0) : 32;
-      hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, Vb + (size_t)i0 * n, n, kk, wv,
-                         parts(), 0);
-      int rc = reduce(kk);
-      if (rc) return rc;
-      rc = sync_read(kk, host + i0);
-      if (rc) return rc;
-    }
-    return MNS_OK;
-  }
-
-  // host coefficients -> device through the pinned staging half of h_red; the
-  // staging area is reused only after a later stream synchronization
-  int h2d(const double* host, int K) {
-    std::memcpy(h->h_red + 1024, host, K * sizeof(double));
-    hipError_t e = hipMemcpyAsync(coefs(), h->h_red + 1024, K * sizeof(double), hipMemcpyHostToDevice, s);
-    return e == hipSuccess ? MNS_OK : err(MNS_ERR_HIP, "h2d coefs");
-  }
-
-  // w -= V h (h on host), returns ||w||
-  int multiaxpy(const double* Vb, int K, const double* hh, double* wv, double* norm) {
-    int rc0 = h2d(hh, K);
-    if (rc0) return rc0;
-    hipLaunchKernelGGL(k_multiaxpy_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, s, Vb, n, K, coefs(), wv, parts());
-    int rc = reduce(1);
-    if (rc) return rc;
-    double v;
-    rc = sync_read(1, &v);
-    *norm = std::sqrt(v);
-    return rc;
   }
 
   int jac64(const double* src, double* dst) {
@@ -378,34 +601,59 @@ struct Solver {
     return hipGetLastError() == hipSuccess ? MNS_OK : err(MNS_ERR_HIP, "chebyshev");
   }
 
-  // z = M^-1 v in three parts: v is copied (or cast) into a fixed input
-  // buffer, the body maps that buffer to a fixed output buffer, which is
-  // copied (or cast) to z.  The body's launches depend on neither v nor z, so
-  // with use_graph they are captured once per solve and replayed.
+  // One FGMRES iteration as a fixed sequence of launches: V_j (j read from
+  // the device state) is copied or cast into the preconditioner's fixed input
+  // buffer, the preconditioner body maps it to its fixed output buffer, which
+  // is copied to Z_j and to the fixed input zbuf of the FP64 Jacobian, then
+  // the Gram-Schmidt passes, the Givens update and the next basis vector.
+  // No launch depends on j or on the host, so with use_graph the iteration
+  // is captured once per solve and replayed.
   hipGraphExec_t gexec = nullptr;
-  int graph_vm64 = 0, graph_vm32 = 0;
+  GmView G{};
+  double* zbuf = nullptr;
+  int it_vm64 = 0, it_vm32 = 0;  // Jacobian applications of one iteration
 
-  int precond_body(const mns_solve_opts* o, double lmax, hipStream_t bs) {
+  int precond_body(const mns_solve_opts* o, double lmax, hipStream_t bs, int* v64, int* v32);
+
+  int iteration(const mns_solve_opts* o, double lmax, hipStream_t st) {
     Solver B = *this;
-    B.s = bs;
+    B.s = st;
     B.vm64 = B.vm32 = 0;
+    const unsigned g = grid_for(n);
+    const bool mgp = o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64;
+    const bool f32in = o->precond == MNS_F32 || o->precond == MNS_PRECOND_MG;
+    void* in = mgp ? mg_io(mg, false, f32in) : (o->precond == MNS_F32 ? (void*)b32 : (void*)b64c);
+    const void* out = mgp ? mg_io(mg, true, f32in)
+                          : (o->precond == MNS_F32 ? (const void*)x32
+                                                   : (o->precond == MNS_F64 ? (const void*)(d64c + n) : (const void*)b64c));
+    if (f32in) hipLaunchKernelGGL(k_gm_in<float>, dim3(g), dim3(256), 0, st, G, V, n, (float*)in);
+    else hipLaunchKernelGGL(k_gm_in<double>, dim3(g), dim3(256), 0, st, G, V, n, (double*)in);
     int rc;
-    if (o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64) rc = mg_vcycle_body(mg, o, bs);
-    else if (o->precond == MNS_F64)
-      rc = B.chebyshev<double>(b64c, d64c + n, r64c, d64c, t64b, h->d_diag64, o->cheb_degree, lmax, o->cheb_range);
-    else
-      rc = B.chebyshev<float>(b32, x32, r32, d32, t32, h->d_diag32, o->cheb_degree, lmax, o->cheb_range);
-    graph_vm64 = B.vm64;
-    graph_vm32 = B.vm32;
-    return rc;
+    if (o->precond != -1 && (rc = precond_body(o, lmax, st, &B.vm64, &B.vm32))) return rc;
+    if (f32in) hipLaunchKernelGGL(k_gm_out<float>, dim3(g), dim3(256), 0, st, G, (const float*)out, n, Z, zbuf);
+    else hipLaunchKernelGGL(k_gm_out<double>, dim3(g), dim3(256), 0, st, G, (const double*)out, n, Z, zbuf);
+    if ((rc = B.jac64(zbuf, w))) return rc;
+    hipLaunchKernelGGL(k_gm_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, st, G, (const double*)V, n, (const double*)w);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(64), dim3(256), 0, st, G, 0, kRedBlocks);
+    hipLaunchKernelGGL(k_gm_axpy_dots, dim3(kRedBlocks), dim3(kRedThreads), 0, st, G, (const double*)V, n, w);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(64), dim3(256), 0, st, G, 1, kRedBlocks);
+    hipLaunchKernelGGL(k_gm_reorth, dim3(kRedBlocks), dim3(kRedThreads), 0, st, G, (const double*)V, n, w);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, st, G, 2, kRedBlocks);
+    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(64), 0, st, G);
+    hipLaunchKernelGGL(k_gm_next, dim3(g), dim3(256), 0, st, G, V, n, (const double*)w);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("FGMRES iteration: ") + hipGetErrorString(e));
+    it_vm64 = B.vm64;
+    it_vm32 = B.vm32;
+    return MNS_OK;
   }
 
-  int capture_body(const mns_solve_opts* o, double lmax) {
+  int capture_iteration(const mns_solve_opts* o, double lmax) {
     if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
       return err(MNS_ERR_HIP, "capture stream");
     hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
-    const int rc = precond_body(o, lmax, h->cap);
+    const int rc = iteration(o, lmax, h->cap);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(h->cap, &graph);
     if (rc) {
@@ -427,39 +675,30 @@ struct Solver {
     gexec = nullptr;
   }
 
-  int precondition(const mns_solve_opts* o, double lmax, const double* v, double* z) {
-    const unsigned g = grid_for(n);
-    if (o->precond == -1) {
-      hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, z, n);
+  // `count` iterations on the solver's stream (graph replays when enabled;
+  // graphs need an untimed handle, since timed launches record events)
+  int iterations(const mns_solve_opts* o, double lmax, int count) {
+    int rc;
+    if (o->use_graph && !h->timing_cap) {
+      if (!gexec && (rc = capture_iteration(o, lmax))) return rc;
+      for (int i = 0; i < count; ++i) {
+        const hipError_t e = hipGraphLaunch(gexec, s);
+        if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+      }
       return MNS_OK;
     }
-    const bool mgp = o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64;
-    int rc;
-    if (mgp) {
-      if ((rc = mg_vcycle_in(mg, o, v, s))) return rc;
-    } else if (o->precond == MNS_F64) {
-      hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, b64c, n);
-    } else {
-      hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, b32, n);
-    }
-    // graphs need an untimed handle (timed launches record events)
-    if (o->use_graph && !h->timing_cap) {
-      if (!gexec && (rc = capture_body(o, lmax))) return rc;
-      hipError_t e = hipGraphLaunch(gexec, s);
-      if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
-      vm64 += graph_vm64;
-      vm32 += graph_vm32;
-    } else {
-      if ((rc = precond_body(o, lmax, s))) return rc;
-      vm64 += graph_vm64;
-      vm32 += graph_vm32;
-    }
-    if (mgp) return mg_vcycle_out(mg, o, z, s);
-    if (o->precond == MNS_F64)
-      hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, (const double*)(d64c + n), 1.0, z, n);
-    else
-      hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, x32, z, n);
-    return hipGetLastError() == hipSuccess ? MNS_OK : err(MNS_ERR_HIP, "preconditioner copies");
+    for (int i = 0; i < count; ++i)
+      if ((rc = iteration(o, lmax, s))) return rc;
+    return MNS_OK;
+  }
+
+  // device state -> host (one synchronization)
+  int read_state(double* misc) {
+    hipError_t e = hipMemcpyAsync(h->h_red, G.misc, GM_MISC * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return err(MNS_ERR_HIP, std::string("readback: ") + hipGetErrorString(e));
+    std::memcpy(misc, h->h_red, GM_MISC * sizeof(double));
+    return MNS_OK;
   }
 
   // r = b - J x, returns ||r||
@@ -473,6 +712,31 @@ struct Solver {
     return MNS_OK;
   }
 };
+
+// preconditioner body on stream bs: Chebyshev polynomial between the fixed
+// buffers, or the V-cycle between level 0's vectors; adds its Jacobian
+// applications to *v64 / *v32
+int Solver::precond_body(const mns_solve_opts* o, double lmax, hipStream_t bs, int* v64, int* v32) {
+  Solver B = *this;
+  B.s = bs;
+  B.vm64 = B.vm32 = 0;
+  int rc;
+  if (o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64) {
+    int a = 0, b = 0, c = 0, d = 0;
+    mg_count(mg, &a, &b);
+    rc = mg_vcycle_body(mg, o, bs);
+    mg_count(mg, &c, &d);
+    B.vm64 = c - a;
+    B.vm32 = d - b;
+  } else if (o->precond == MNS_F64) {
+    rc = B.chebyshev<double>(b64c, d64c + n, r64c, d64c, t64b, h->d_diag64, o->cheb_degree, lmax, o->cheb_range);
+  } else {
+    rc = B.chebyshev<float>(b32, x32, r32, d32, t32, h->d_diag32, o->cheb_degree, lmax, o->cheb_range);
+  }
+  *v64 += B.vm64;
+  *v32 += B.vm32;
+  return rc;
+}
 
 int ensure_workspace(mns_handle* h, int m) {
   const size_t n = (size_t)h->ndofs;
@@ -491,6 +755,14 @@ int ensure_workspace(mns_handle* h, int m) {
     return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
   if (!h->d_diag32 && (e = hipMalloc((void**)&h->d_diag32, n * sizeof(float))) != hipSuccess)
     return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (h->gm_m < m) {
+    if (h->d_gm) (void)hipFree(h->d_gm);
+    h->d_gm = nullptr;
+    h->gm_m = 0;
+    if ((e = hipMalloc((void**)&h->d_gm, gm_doubles(m) * sizeof(double))) != hipSuccess)
+      return set_error(h, MNS_ERR_HIP, std::string("hipMalloc FGMRES state: ") + hipGetErrorString(e));
+    h->gm_m = m;
+  }
   if (!h->d_red) {
     if ((e = hipMalloc((void**)&h->d_red, ((size_t)kRedBlocks * 32 + 2048) * sizeof(double))) != hipSuccess)
       return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -793,7 +1065,28 @@ struct MG {
   int fine_lin = -1;            // and of the mesh's own level
   int eig_iters = -1;           // power iterations of the spectra at the last setup
   mns_handle* fine = nullptr;   // Picard copy of the mesh's own level (owned; level 0 when in use)
+  int vm64 = 0, vm32 = 0;       // Jacobian applications launched by the cycles (all levels)
+  void* coarse = nullptr;       // direct solve of the coarsest level (mns_coarse.hip)
+  bool coarse_ready = false;    // it holds the inverse of the current coarsest operator
+  int coarse_direct = -1;       // mg_coarse_direct at the last setup
 };
+
+// level 0's right-hand side b (out = false) or iterate x (out = true) in the
+// cycle's precision (FP32 or FP64; the buffer holds room for FP64)
+void* mg_io(MG* mg, bool out, bool f32) {
+  MGLevel& L0 = mg->L[0];
+  if (!out) return L0.b;
+  return f32 ? (void*)((float*)L0.b + L0.n) : (void*)((double*)L0.b + L0.n);
+}
+
+void mg_count(MG* mg, int* v64, int* v32) {
+  *v64 = mg->vm64;
+  *v32 = mg->vm32;
+}
+
+// largest coarsest level solved directly (its dense matrix and inverse take
+// 2 x 8 bytes x n^2: 1 GiB at this size)
+constexpr int kCoarseDirectMax = 8192;
 
 static int mg_err(mns_handle* h, hipError_t e, const char* what) {
   return set_error(h, MNS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -951,7 +1244,8 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
 // coarse operators at the current angle and state, diagonals and spectra
 static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t s) {
   if (mg->version == h->lin_version && mg->coarse_lin == o->mg_coarse_linearization &&
-      mg->fine_lin == o->mg_fine_linearization && mg->eig_iters == o->eig_iters)
+      mg->fine_lin == o->mg_fine_linearization && mg->eig_iters == o->eig_iters &&
+      mg->coarse_direct == o->mg_coarse_direct)
     return MNS_OK;
   int rc;
   // level 0: the caller's handle, or a copy of its mesh with the Picard
@@ -969,7 +1263,7 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
     mns_handle* hf = mg->fine;
     hf->fused = h->fused;
     hf->quad = h->quad;
-    if ((rc = mns_rotate_rotor(hf, h->theta, h->omega))) return set_error(h, rc, "fine copy rotate: " + hf->err);
+    if ((rc = mns_rotate_rotor(hf, h->theta, h->omega, s))) return set_error(h, rc, "fine copy rotate: " + hf->err);
     hf->picard = 1;
     if ((rc = mns_set_linearization(hf, h->d_state, h->d_hist, h->d_force, s)))
       return set_error(h, rc, "fine copy linearization: " + hf->err);
@@ -990,7 +1284,7 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
       if (fsrc[i]) hipLaunchKernelGGL(k_mg_eval, dim3(g), dim3(256), 0, s, X, fsrc[i], cdst[i], nnc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mg_err(h, e, "injection");
-    if ((rc = mns_rotate_rotor(hc, h->theta, h->omega))) return set_error(h, rc, "coarse rotate: " + hc->err);
+    if ((rc = mns_rotate_rotor(hc, h->theta, h->omega, s))) return set_error(h, rc, "coarse rotate: " + hc->err);
     hc->picard = o->mg_coarse_linearization == MNS_LIN_PICARD;
     if ((rc = mns_set_linearization(hc, cdst[0], fsrc[1] ? cdst[1] : nullptr, fsrc[2] ? cdst[2] : nullptr, s)))
       return set_error(h, rc, "coarse linearization: " + hc->err);
@@ -1015,6 +1309,17 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
     Lv.eig_h = hl;
     Lv.eig_gen = hl->ws_gen;
   }
+  // coarsest level of a hierarchy of two or more levels: its matrix,
+  // reconstructed and inverted in FP64 (too large a level keeps the FP64
+  // Chebyshev polynomial)
+  mg->coarse_ready = false;
+  if (o->mg_coarse_direct && mg->L.size() >= 2) {
+    mns_handle* hc = mg->L.back().h;
+    rc = coarse_setup(hc, &mg->coarse, s, kCoarseDirectMax);
+    if (rc == MNS_OK) mg->coarse_ready = true;
+    else if (rc != MNS_ERR_UNSUPPORTED) return set_error(h, rc, "coarse direct solve: " + hc->err);
+  }
+  mg->coarse_direct = o->mg_coarse_direct;
   mg->version = h->lin_version;
   mg->coarse_lin = o->mg_coarse_linearization;
   mg->fine_lin = o->mg_fine_linearization;
@@ -1064,12 +1369,37 @@ static int mg_smooth(MG* mg, size_t l, const Real* b, Real* x, bool zero, int de
   Solver S = make_solver(hl, s, ws_of(hl, l));
   MGVec<Real> v = mg_vec<Real>(Lv, S);
   const unsigned g = grid_for(Lv.n);
-  if (zero) return S.chebyshev<Real>(b, x, v.cr, v.cd, v.ct, v.diag, deg, lmax, range);
+  int& count = sizeof(Real) == 8 ? mg->vm64 : mg->vm32;
+  if (zero) {
+    const int rc = S.chebyshev<Real>(b, x, v.cr, v.cd, v.ct, v.diag, deg, lmax, range);
+    count += S.vm64 + S.vm32;
+    return rc;
+  }
   int rc = launch_jacobian<Real>(hl, x, v.ct, s);
   if (rc) return rc;
+  ++count;
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, b, Real(-1), (const Real*)v.ct, v.r, Lv.n);
-  if ((rc = S.chebyshev<Real>(v.r, v.cx, v.cr, v.cd, v.ct, v.diag, deg, lmax, range))) return rc;
+  rc = S.chebyshev<Real>(v.r, v.cx, v.cr, v.cd, v.ct, v.diag, deg, lmax, range);
+  count += S.vm64 + S.vm32;
+  if (rc) return rc;
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)x, Real(1), (const Real*)v.cx, x, Lv.n);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+// coarsest-level solve in FP64 for an FP32 cycle: b (FP32) -> FP64, Chebyshev
+// of degree mg_coarse_degree with FP64 Jacobian applications, x (FP32) <- FP64
+static int mg_coarse_f64(MG* mg, size_t l, const float* b, float* x, const mns_solve_opts* o, hipStream_t s) {
+  MGLevel& Lv = mg->L[l];
+  mns_handle* hl = Lv.h;
+  Solver S = make_solver(hl, s, ws_of(hl, l));
+  const unsigned g = grid_for(Lv.n);
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, b, S.w, (long long)Lv.n);
+  const double lmax = o->cheb_lambda_factor * Lv.lmax;
+  int rc = S.chebyshev<double>(S.w, S.r, S.r64c, S.d64c, S.t64b, hl->d_diag64, o->mg_coarse_degree, lmax,
+                               o->mg_smooth_range);
+  mg->vm64 += S.vm64;
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, (const double*)S.r, x, (long long)Lv.n);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 
@@ -1080,13 +1410,24 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   Solver S = make_solver(hl, s, ws_of(hl, l));
   MGVec<Real> v = mg_vec<Real>(Lv, S);
   int rc;
-  if (l + 1 == mg->L.size())
+  if (l + 1 == mg->L.size()) {
+    // coarsest level: in FP64 whatever the smoothers' precision (the FP32
+    // right-hand side is widened into the level's FP64 work vectors w, r,
+    // which no coarse level otherwise uses, and the result narrowed back);
+    // a hierarchy of one level keeps the smoothers' precision
+    if (mg->coarse_ready && l > 0) {
+      const int rc2 = coarse_apply<Real>(mg->coarse, v.b, v.x, s);
+      return rc2 ? set_error(mg->L[0].h, rc2, "coarse direct solve") : MNS_OK;
+    }
+    if (sizeof(Real) == 4 && l > 0) return mg_coarse_f64(mg, l, (const float*)v.b, (float*)v.x, o, s);
     return mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_coarse_degree, o->mg_smooth_range, o->cheb_lambda_factor, s);
+  }
   if ((rc = mg_smooth<Real>(mg, l, v.b, v.x, true, o->mg_smooth_degree, o->mg_smooth_range, o->cheb_lambda_factor,
                             s)))
     return rc;
   // residual, restricted with constrained rows zero on both levels
   if ((rc = launch_jacobian<Real>(hl, v.x, v.ct, s))) return rc;
+  ++(sizeof(Real) == 8 ? mg->vm64 : mg->vm32);
   const unsigned g = grid_for(Lv.n);
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.b, Real(-1), (const Real*)v.ct, v.r,
                      Lv.n);
@@ -1109,31 +1450,8 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   return mg_smooth<Real>(mg, l, v.b, v.x, false, o->mg_smooth_degree, o->mg_smooth_range, o->cheb_lambda_factor, s);
 }
 
-// V-cycle z = B v in three parts (the middle one touches only the levels'
-// own vectors, so that it can be captured into a graph): v into level 0's
-// right-hand side, the cycle, level 0's iterate into z
-int mg_vcycle_in(MG* mg, const mns_solve_opts* o, const double* v, hipStream_t s) {
-  MGLevel& L0 = mg->L[0];
-  const unsigned g = grid_for(L0.n);
-  if (o->precond == MNS_PRECOND_MG64)
-    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, v, 1.0, (double*)L0.b, L0.n);
-  else
-    hipLaunchKernelGGL((k_cast<double, float>), dim3(g), dim3(256), 0, s, v, (float*)L0.b, L0.n);
-  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
-}
-
 int mg_vcycle_body(MG* mg, const mns_solve_opts* o, hipStream_t s) {
   return o->precond == MNS_PRECOND_MG64 ? mg_cycle<double>(mg, 0, o, s) : mg_cycle<float>(mg, 0, o, s);
-}
-
-int mg_vcycle_out(MG* mg, const mns_solve_opts* o, double* z, hipStream_t s) {
-  MGLevel& L0 = mg->L[0];
-  const unsigned g = grid_for(L0.n);
-  if (o->precond == MNS_PRECOND_MG64)
-    hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, s, (const double*)L0.b + L0.n, 1.0, z, L0.n);
-  else
-    hipLaunchKernelGGL((k_cast<float, double>), dim3(g), dim3(256), 0, s, (const float*)L0.b + L0.n, z, L0.n);
-  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 
 }  // namespace
@@ -1185,9 +1503,11 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
     return MNS_OK;
   }
   const double target = o->rtol * bn;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 1), h2(m + 1), y(m);
+  S.G = gm_view(h->d_gm, h->gm_m);
+  S.zbuf = S.r;  // free during a cycle: the residual is read into V_0 at its start
+  const double lam = lmax * o->cheb_lambda_factor;
   int total = 0, restarts = 0;
-  double rnorm = 0;
+  double rnorm = 0, misc[GM_MISC];
   bool converged = false;
   while (total < o->maxit) {
     if ((rc = S.true_residual(rhs, x, S.r, &rnorm))) return rc;
@@ -1195,86 +1515,41 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
       converged = true;
       break;
     }
-    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, S.r, 1.0 / rnorm, S.V, (long long)n);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = rnorm;
-    int j = 0;
-    for (; j < m && total < o->maxit; ++j, ++total) {
-      double* Vj = S.V + (size_t)j * n;
-      double* Zj = S.Z + (size_t)j * n;
-      if ((rc = S.precondition(o, lmax * o->cheb_lambda_factor, Vj, Zj))) return rc;
-      if ((rc = S.jac64(Zj, S.w))) return rc;
-      // classical Gram-Schmidt with one reorthogonalization when the norm
-      // drops below 0.7 of its value before the projection
-      double wn0, wn;
-      if (j + 2 <= kDotK) {
-        // (1) h = V^T w and w . w in one pass; (2) w -= V h fused with
-        // h2 = V^T w and w . w in one pass; (3) only when needed, w -= V h2
-        const int K = j + 1;
-        double tmp[kDotK + 1];
-        hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, S.V, (long long)n, K, S.w,
-                           S.parts(), 1);
-        if ((rc = S.reduce(K + 1)) || (rc = S.sync_read(K + 1, tmp))) return rc;
-        for (int i = 0; i < K; ++i) hcol[i] = tmp[i];
-        wn0 = std::sqrt(tmp[K]);
-        if ((rc = S.h2d(hcol.data(), K))) return rc;
-        hipLaunchKernelGGL(k_multiaxpy_dot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, S.V, (long long)n, K,
-                           S.coefs(), S.w, S.parts());
-        if ((rc = S.reduce(K + 1)) || (rc = S.sync_read(K + 1, tmp))) return rc;
-        wn = std::sqrt(tmp[K]);
-        if (wn < 0.7 * wn0) {
-          for (int i = 0; i < K; ++i) h2[i] = tmp[i];
-          if ((rc = S.multiaxpy(S.V, K, h2.data(), S.w, &wn))) return rc;
-          for (int i = 0; i < K; ++i) hcol[i] += h2[i];
-        }
-      } else {
-        double v;
-        hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(kRedThreads), 0, s, S.w, (long long)n, 1, S.w,
-                           S.parts(), 0);
-        if ((rc = S.reduce(1)) || (rc = S.sync_read(1, &v))) return rc;
-        wn0 = std::sqrt(v);
-        if ((rc = S.multidot(S.V, j + 1, S.w, hcol.data()))) return rc;
-        if ((rc = S.multiaxpy(S.V, j + 1, hcol.data(), S.w, &wn))) return rc;
-        if (wn < 0.7 * wn0) {
-          if ((rc = S.multidot(S.V, j + 1, S.w, h2.data()))) return rc;
-          if ((rc = S.multiaxpy(S.V, j + 1, h2.data(), S.w, &wn))) return rc;
-          for (int i = 0; i <= j; ++i) hcol[i] += h2[i];
-        }
+    hipLaunchKernelGGL(k_gm_start, dim3(grid_for(n)), dim3(256), 0, s, S.G, (const double*)S.r, rnorm, target, S.V,
+                       (long long)n);
+    // iterations in chunks between readbacks of the device state; the chunk
+    // follows the observed convergence rate so that few iterations run past
+    // convergence (they leave the state unchanged)
+    const int cycle = std::min(m, o->maxit - total);
+    int launched = 0, its = 0;
+    double res0 = rnorm, res = rnorm;
+    bool done = false;
+    while (launched < cycle && !done) {
+      int chunk = 1;
+      if (its > 0 && res < res0 && res > target) {
+        const double rate = std::log(res / res0) / its;  // < 0
+        const double left = std::log(target / res) / rate;
+        chunk = (int)std::max(1.0, std::min(8.0, std::floor(0.5 * left)));
       }
-      hcol[j + 1] = wn;
-      if (!std::isfinite(wn)) return set_error(h, MNS_ERR_HIP, "non-finite value in FGMRES");
-      // apply earlier rotations, then a new one
-      for (int i = 0; i < j; ++i) {
-        const double a = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
-        const double b = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
-        hcol[i] = a;
-        hcol[i + 1] = b;
-      }
-      const double den = std::hypot(hcol[j], hcol[j + 1]);
-      cs[j] = den > 0 ? hcol[j] / den : 1.0;
-      sn[j] = den > 0 ? hcol[j + 1] / den : 0.0;
-      hcol[j] = den;
-      hcol[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
-      if (wn > 0)
-        hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, S.w, 1.0 / wn, S.V + (size_t)(j + 1) * n,
-                           (long long)n);
-      if (std::fabs(g[j + 1]) <= target || wn == 0) {
-        ++j;
-        ++total;
-        break;
-      }
+      chunk = std::min(chunk, cycle - launched);
+      if ((rc = S.iterations(o, lam, chunk))) return rc;
+      launched += chunk;
+      if ((rc = S.read_state(misc))) return rc;
+      if (misc[GM_BROKEN] != 0.0) return set_error(h, MNS_ERR_HIP, "non-finite value in FGMRES");
+      its = (int)misc[GM_ITS];
+      res = misc[GM_RES];
+      done = misc[GM_DONE] != 0.0;
     }
-    // y = H^-1 g (upper triangular j x j)
-    for (int i = j - 1; i >= 0; --i) {
-      double sum = g[i];
-      for (int k2 = i + 1; k2 < j; ++k2) sum -= H[(size_t)i * m + k2] * y[k2];
-      y[i] = H[(size_t)i * m + i] != 0 ? sum / H[(size_t)i * m + i] : 0.0;
-    }
-    if ((rc = S.h2d(y.data(), j))) return rc;
-    hipLaunchKernelGGL(k_update_x, dim3(grid_for(n)), dim3(256), 0, s, S.Z, (long long)n, j, S.coefs(), x);
+    const int jj = (int)misc[GM_J];
+    if (its < 1 || jj < 1) return set_error(h, MNS_ERR_HIP, "FGMRES cycle made no progress");
+    total += its;
+    S.vm64 += its * S.it_vm64;
+    S.vm32 += its * S.it_vm32;
+    // y = H^-1 g on the device, x += Z y
+    hipLaunchKernelGGL(k_gm_backsub, dim3(1), dim3(64), 0, s, S.G, jj);
+    hipLaunchKernelGGL(k_update_x, dim3(grid_for(n)), dim3(256), 0, s, (const double*)S.Z, (long long)n, jj,
+                       (const double*)S.G.y, x);
+    if (hipGetLastError() != hipSuccess) return set_error(h, MNS_ERR_HIP, "FGMRES update");
     ++restarts;
   }
   if (!converged) {
@@ -1307,6 +1582,7 @@ void mg_free(mns_handle* h) {
     if (l > 0 && Lv.h) mns_destroy(Lv.h);
   }
   if (mg->fine) mns_destroy(mg->fine);
+  coarse_free(mg->coarse);
   for (void* p : mg->tables)
     if (p) (void)hipFree(p);
   delete mg;

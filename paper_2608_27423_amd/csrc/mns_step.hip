@@ -79,7 +79,7 @@ int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const dou
   double* part = trial + n;
   const unsigned blocks = kStepBlocks;
 
-  int rc = mns_rotate_rotor(h, theta_next, omega);
+  int rc = mns_rotate_rotor(h, theta_next, omega, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_bdf2_history, dim3(blocks), dim3(256), 0, s, un, unm1, hist, 1.0 / (2.0 * h->desc.dt), n);
   if ((e = hipGetLastError()) != hipSuccess) return step_err(h, e, "history kernel");

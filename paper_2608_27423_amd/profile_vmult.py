@@ -10,7 +10,10 @@ dispatch give the scale from FETCH_SIZE / WRITE_SIZE to bytes.
         --workload annulus3d_q2_64x8x32
 
 `--summarize DIR_FETCH DIR_WRITE` reads the two counter CSV files and prints
-the per-dispatch bytes of every kernel of the run (scaled by the copy).
+the per-dispatch bytes of every kernel of the run (scaled by the copy); with
+`--traffic-out FILE` it also writes the summary that bench.py reads: the
+bytes of every kernel dispatched once per vmult (`--reps` dispatches) and
+their sum per vmult, tagged with the digest of the kernel source.
 """
 import argparse
 import csv
@@ -65,7 +68,7 @@ def _totals(path):
     return out
 
 
-def summarize(dfetch, dwrite):
+def summarize(dfetch, dwrite, traffic_out=None, reps=3, workload=""):
     f, w = _totals(dfetch), _totals(dwrite)
     copy_f = [v for k, c, v in f.values() if "copyBuffer" in k and v > 1e5]
     copy_w = [v for k, c, v in w.values() if "copyBuffer" in k and v > 1e5]
@@ -84,10 +87,35 @@ def summarize(dfetch, dwrite):
         per.setdefault(short, []).append((f[d][2] * 1024 * sf, w[d][2] * 1024 * sw))
     print("| kernel | dispatches | read MB / dispatch | write MB / dispatch | total MB / dispatch |")
     print("|---|---|---|---|---|")
+    rows = []
     for k, v in per.items():
-        rd = sum(a for a, _ in v) / len(v) / 1e6
-        wr = sum(b for _, b in v) / len(v) / 1e6
-        print(f"| `{k}` | {len(v)} | {rd:.2f} | {wr:.2f} | {rd + wr:.2f} |")
+        rd = sum(a for a, _ in v) / len(v)
+        wr = sum(b for _, b in v) / len(v)
+        rows.append((k, len(v), rd, wr))
+        print(f"| `{k}` | {len(v)} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {(rd + wr) / 1e6:.2f} |")
+    if traffic_out:
+        import hashlib
+
+        src = os.path.join(HERE, "csrc", "mns_kernels.hip")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        vm = [r for r in rows if r[1] % reps == 0 and r[1] // reps >= 1 and "k_state" not in r[0]
+              and "k_cast" not in r[0] and "k_rotate" not in r[0]]
+        with open(traffic_out, "w") as f:
+            f.write(f"# HBM bytes of the FP64 vmult kernels, {workload} (read by bench.py); FETCH_SIZE and\n"
+                    f"# WRITE_SIZE passes of profile_vmult.py, scaled by the {COPY_BYTES >> 20} MiB copy "
+                    f"calibration (fetch x {sf:.4f}, write x {sw:.4f})\n")
+            f.write(f"kernel_source_sha256: {digest}\n")
+            tot_r = tot_w = 0.0
+            for k, cnt, rd, wr in vm:
+                per_call = cnt // reps
+                tot_r += per_call * rd
+                tot_w += per_call * wr
+                f.write(f"bytes_per_launch {k}: {rd + wr:.0f}\n")
+                f.write(f"read_write_per_launch {k}: {rd:.0f} {wr:.0f}\n")
+            f.write(f"vmult_read_bytes_per_call: {tot_r:.0f}\n")
+            f.write(f"vmult_write_bytes_per_call: {tot_w:.0f}\n")
+            f.write(f"vmult_bytes_per_call: {tot_r + tot_w:.0f}\n")
+        print(f"wrote {traffic_out}")
 
 
 def main():
@@ -98,9 +126,10 @@ def main():
     ap.add_argument("--fused", type=int, default=-1)
     ap.add_argument("--volume-layout", type=int, default=1)
     ap.add_argument("--summarize", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
+    ap.add_argument("--traffic-out", default=None)
     args = ap.parse_args()
     if args.summarize:
-        summarize(*args.summarize)
+        summarize(*args.summarize, traffic_out=args.traffic_out, reps=args.reps, workload=args.workload)
     else:
         run(args)
 

@@ -50,7 +50,7 @@ def test_invalid_mesh_rejected(bad):
 def test_null_arguments():
     L = binding.lib()
     assert L.mns_setup_mesh(None, None, None) == binding.MNS_ERR_INVALID_ARG
-    assert L.mns_rotate_rotor(None, 0.0, 0.0) == binding.MNS_ERR_INVALID_ARG
+    assert L.mns_rotate_rotor(None, 0.0, 0.0, None) == binding.MNS_ERR_INVALID_ARG
     assert L.mns_apply_jacobian(None, 0, None, None, None) == binding.MNS_ERR_INVALID_ARG
     assert L.mns_last_error(None) == b"null handle"
 

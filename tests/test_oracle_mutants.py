@@ -97,6 +97,12 @@ MUTANTS = [
      "double pbar = Fs->p;",
      [(pins.test_galerkin_saddle_structure, dict(dim=2)),
       (pins.test_aligned_mortar_reduces_to_conforming_cg, dict(dim=2))]),
+    ("inward interface normals in the face coefficients (n = -n_outward on both sides)",
+     "static void mortar_coef(const mesh_t *M, int side, const field_t *Fs, const field_t *Fo, const double ns[3],\n"
+     "                        testcoef_t *C) {\n",
+     "static void mortar_coef(const mesh_t *M, int side, const field_t *Fs, const field_t *Fo, const double nso[3],\n"
+     "                        testcoef_t *C) {\n  const double ns[3] = {-nso[0], -nso[1], -nso[2]};\n",
+     [(pins.test_discrete_mass_conservation, dict(dim=2)), (pins.test_pressure_nullspace_up_to_quadrature, {})]),
 ]
 
 

@@ -534,6 +534,60 @@ def test_pressure_nullspace_up_to_quadrature():
     assert r1 > 4.5 and r2 > 5.0, errs
 
 
+def _two_sided_field(cfg, seed):
+    """Increment for the mass pin: on each side an independent smooth random
+    velocity field (cosine modes of x, y up to wavenumber 2), zero on every
+    wall, so that the interface jump is O(1); random smooth pressure."""
+    n, n_rot = oracle.sizes(cfg)[:2]
+    nc = cfg["dim"] + 1
+    X = oracle.node_coords(cfg)
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    r = np.hypot(x, y)
+    rotor = np.arange(n // nc) < n_rot // nc
+    wall = np.where(rotor, r - cfg["r_in"], cfg["r_out"] - r)
+    if cfg["dim"] == 3:
+        wall = wall * z * (cfg["height"] - z)
+    g = np.random.default_rng(seed)
+    out = np.zeros(n)
+    for c in range(nc):
+        fr, fs = np.zeros_like(r), np.zeros_like(r)
+        for a in range(3):
+            for b in range(3):
+                cr, cs = g.uniform(-1, 1, 2)
+                mode = np.cos(a * np.pi * x + b * np.pi * y + g.uniform(0, 2 * np.pi))
+                fr += cr * mode
+                fs += cs * mode
+        f = np.where(rotor, fr, fs)
+        out[c::nc] = f * wall if c < cfg["dim"] else f
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_discrete_mass_conservation(dim):
+    """Eq. EqMortarMass (strong-DG mass term): the sum of all pressure rows of
+    J x is the pressure test function q = 1, for which the PSPG term vanishes
+    and the volume term integrates div(du) over both domains; by the
+    divergence theorem that is the flux through the walls (zero here: x
+    vanishes there) plus, on the interface, (du_rotor - du_stator) . e_r,
+    which the two sides' mass terms -(1/2) j_s . n_s cancel exactly.  So the
+    sum is zero up to the Gauss quadrature of the polar map, whose error falls
+    by more than 2^6 per refinement; an O(1) interface jump that the face
+    terms did not cancel would stay O(1)."""
+    errs, scale = [], []
+    for nt in (8, 16, 32):
+        c = max(1, nt // 8)
+        cfg = _cfg(dim=dim, n_theta=nt, n_r_rotor=c, n_r_stator=c, n_z=c, pin_pressure=0)
+        n = oracle.n_dofs(cfg)
+        u = np.random.default_rng(3).uniform(-1, 1, n)
+        y = oracle.apply_jacobian(cfg, u, _two_sided_field(cfg, 4))
+        pr = np.arange(n) % (dim + 1) == dim
+        errs.append(abs(y[pr].sum()))
+        scale.append(np.abs(y[pr]).max())
+    r1, r2 = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    assert r1 > 6.0 and r2 > 6.0, errs
+    assert errs[-1] < 1e-8 * scale[-1], (errs, scale)
+
+
 def _solve_mms(cfg, iters=8):
     import scipy.sparse.linalg as spla
 
