@@ -151,6 +151,24 @@ int mns_set_linearization_kind(mns_handle* h, int kind);
  * Errors: NOT_LINEARIZED, INVALID_ARG, HIP. */
 int mns_apply_jacobian(mns_handle* h, int precision, const void* src, void* dst, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the product of
+ * mns_apply_jacobian (same arguments, same result bit for bit) whose volume
+ * and mortar kernels keep their local results in one library-owned device
+ * array of MNS_NOALLOC_SCRATCH_BYTES instead of the handle's buffers.  The
+ * array is part of the library's code object: every GPU that the library
+ * runs on holds its own copy until the process ends, and this call allocates
+ * nothing.  Meshes whose local results exceed the array are refused
+ * (UNSUPPORTED): the local results take 4 (k+1)^3 values per 3D cell plus
+ * the same per interface face side, so in FP64 the 32,768-cell degree-2
+ * workload (64 x 8 x 32 cells per domain, 31.9 MB) fits.  Every call
+ * on one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap in time on one GPU (different streams or threads) race
+ * and must be serialized by the caller.
+ * Errors: NOT_LINEARIZED, INVALID_ARG, UNSUPPORTED (mesh too large), HIP. */
+#define MNS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int mns_apply_jacobian_noalloc(mns_handle* h, int precision, const void* src, void* dst, void* stream);
+
 /* res = R(state): the discrete nonlinear residual of Eq. Eq-NSweakWmortar plus
  * the SUPG/PSPG terms of Eq. Eq-NSweakComplete (tau_u from `state`), with the
  * history and force given at the last mns_set_linearization; constrained rows

@@ -33,7 +33,7 @@ EXPORTED = [
     "mns_read_timing", "mns_set_kernel_config", "mns_get_kernel_config", "mns_last_error", "mns_destroy",
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
-    "mns_autotune_kernel_config", "mns_mg_restrict", "mns_batch_solve",
+    "mns_autotune_kernel_config", "mns_mg_restrict", "mns_batch_solve", "mns_apply_jacobian_noalloc",
 ]
 
 
@@ -133,6 +133,7 @@ def lib():
         L.mns_set_linearization.argtypes = [vp, vp, vp, vp, vp]
         L.mns_set_linearization_kind.argtypes = [vp, ctypes.c_int]
         L.mns_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.mns_apply_jacobian_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_residual.argtypes = [vp, vp, vp, vp]
         L.mns_compute_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
         L.mns_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -246,6 +247,19 @@ class Operator:
         if src.numel() != self.n_dofs or dst.numel() != self.n_dofs:
             raise ValueError("vector length != n_dofs")
         self._check(self._L.mns_apply_jacobian(self._h, prec, _ptr(src), _ptr(dst), _stream()))
+        return dst
+
+    def apply_jacobian_noalloc(self, src, dst):
+        """dst = J src through the allocation-free entry point (local results
+        in the library's scratch array); dst must be given."""
+        import torch
+
+        prec = MNS_F64 if src.dtype == torch.float64 else MNS_F32
+        if src.dtype not in (torch.float64, torch.float32) or dst.dtype != src.dtype:
+            raise ValueError("src/dst must both be float64 or both float32")
+        if src.numel() != self.n_dofs or dst.numel() != self.n_dofs:
+            raise ValueError("vector length != n_dofs")
+        self._check(self._L.mns_apply_jacobian_noalloc(self._h, prec, _ptr(src), _ptr(dst), _stream()))
         return dst
 
     def apply_residual(self, state, res=None):

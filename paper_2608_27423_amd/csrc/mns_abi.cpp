@@ -85,6 +85,11 @@ int mns_setup_mesh(const mns_mesh_desc* desc, void* stream, mns_handle** out) {
     *out = h;
     return rc;
   }
+  // device address of the allocation-free apply's scratch array on this
+  // device (looked up once per device; a failure here is reported by that
+  // entry point, which tries again)
+  void* scratch = nullptr;
+  (void)mns::scratch_pointer(&scratch, nullptr);
   *out = h;
   return MNS_OK;
 }
@@ -290,6 +295,25 @@ int mns_apply_jacobian(mns_handle* h, int precision, const void* src, void* dst,
     }
   } catch (...) {
     return set_error(h, MNS_ERR_HIP, "exception in apply_jacobian");
+  }
+  return set_error(h, MNS_ERR_INVALID_ARG, "precision must be MNS_F64 or MNS_F32");
+}
+
+int mns_apply_jacobian_noalloc(mns_handle* h, int precision, const void* src, void* dst, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (src == dst) return set_error(h, MNS_ERR_INVALID_ARG, "src and dst must not overlap");
+  try {
+    if (precision == MNS_F64) {
+      if (!aligned(src, 8) || !aligned(dst, 8)) return set_error(h, MNS_ERR_INVALID_ARG, "misaligned or null vector");
+      return launch_jacobian_noalloc<double>(h, (const double*)src, (double*)dst, as_stream(stream));
+    }
+    if (precision == MNS_F32) {
+      if (!aligned(src, 4) || !aligned(dst, 4)) return set_error(h, MNS_ERR_INVALID_ARG, "misaligned or null vector");
+      return launch_jacobian_noalloc<float>(h, (const float*)src, (float*)dst, as_stream(stream));
+    }
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in apply_jacobian_noalloc");
   }
   return set_error(h, MNS_ERR_INVALID_ARG, "precision must be MNS_F64 or MNS_F32");
 }

@@ -214,6 +214,11 @@ int launch_linearize(mns_handle* h, const double* state, const double* hist, con
                      Real* lin, hipStream_t s);
 template <typename Real>
 int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s);
+// the same product with E and Em in the library's file-scope scratch array
+template <typename Real>
+int launch_jacobian_noalloc(mns_handle* h, const Real* src, Real* dst, hipStream_t s);
+// device address (current device) and size of that array
+int scratch_pointer(void** out, size_t* bytes);
 int launch_residual(mns_handle* h, const double* state, double* res, hipStream_t s);
 template <typename Real>
 int launch_diagonal(mns_handle* h, Real* diag, hipStream_t s);

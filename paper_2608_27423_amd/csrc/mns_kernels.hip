@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include <hip/hip_ext.h>
 
@@ -2286,13 +2288,15 @@ template <typename Real, int DIM, int N>
 constexpr bool kQuadLayout = DIM == 3 && (N == 3 || N == 4);
 
 template <typename Real, int DIM, int N>
-static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
+static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s, Real* E_ws = nullptr,
+                       Real* Em_ws = nullptr) {
   using S = Shape<Real, DIM, N>;
   const Geom<Real> G = make_geom<Real>(h);
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
   const Real* lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
-  Real* E = sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32;
-  Real* Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
+  // local-result buffers: the handle's, or the caller's workspace
+  Real* E = E_ws ? E_ws : (sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32);
+  Real* Em = Em_ws ? Em_ws : (sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32);
   constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   const bool quad = kQuad && h->quad;
   // strip layout of the local results: batches of 16 cells stay inside one
@@ -2585,6 +2589,68 @@ int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
   return MNS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free Jacobian application.  The local-result buffers of the
+// volume and mortar kernels (E, Em) come from one file-scope device array of
+// kScratchBytes instead of the handle's buffers; every GPU that the library
+// runs on holds its own copy until the process ends.  In host code the
+// array's name is only a stand-in: its device address on the current device
+// is looked up with hipGetSymbolAddress (once per device, at handle setup or
+// on the entry point's first call there) and only that address is passed to
+// kernels.  Nothing needs clearing between calls: every entry of E and Em
+// that the gather reads is written by the same call.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_pointer(void** out, size_t* bytes) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MNS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return MNS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  if (bytes) *bytes = kScratchBytes;
+  return MNS_OK;
+}
+
+// bytes of E and Em of one application in precision Real (E rounded up to
+// 256 bytes so that Em starts aligned)
+template <typename Real>
+size_t jacobian_scratch_bytes(const mns_handle* h) {
+  const size_t npt = (size_t)(h->dim == 3 ? h->n * h->n * h->n : h->n * h->n);
+  const size_t e = ((size_t)h->ncells * h->nc * npt * sizeof(Real) + 255) / 256 * 256;
+  const size_t em = (size_t)2 * h->desc.n_theta * h->nz * h->nc * npt * sizeof(Real);
+  return e + em;
+}
+
+template <typename Real>
+int launch_jacobian_noalloc(mns_handle* h, const Real* src, Real* dst, hipStream_t s) {
+  void* base = nullptr;
+  size_t cap = 0;
+  if (scratch_pointer(&base, &cap) != MNS_OK)
+    return set_error(h, MNS_ERR_HIP, "device address of the scratch array not available");
+  const size_t need = jacobian_scratch_bytes<Real>(h);
+  if (need > cap)
+    return set_error(h, MNS_ERR_UNSUPPORTED,
+                     "mesh too large for the allocation-free apply: its local results need " + std::to_string(need) +
+                         " bytes, the scratch array holds " + std::to_string(cap));
+  const size_t npt = (size_t)(h->dim == 3 ? h->n * h->n * h->n : h->n * h->n);
+  Real* E = (Real*)base;
+  Real* Em = (Real*)((unsigned char*)base + ((size_t)h->ncells * h->nc * npt * sizeof(Real) + 255) / 256 * 256);
+  MNS_DISPATCH(h->dim, h->k, return (do_jacobian<Real, DIM, N>(h, src, dst, s, E, Em)));
+  return MNS_OK;
+}
+template int launch_jacobian_noalloc<double>(mns_handle*, const double*, double*, hipStream_t);
+template int launch_jacobian_noalloc<float>(mns_handle*, const float*, float*, hipStream_t);
 
 template <int DIM, int N, bool RES>
 static int do_state(mns_handle* h, const double* state, const double* hist, const double* force, double* lin,
