@@ -169,6 +169,18 @@ int mns_apply_jacobian(mns_handle* h, int precision, const void* src, void* dst,
 #define MNS_NOALLOC_SCRATCH_BYTES (32u << 20)
 int mns_apply_jacobian_noalloc(mns_handle* h, int precision, const void* src, void* dst, void* stream);
 
+/* A = J as a dense matrix (column-major, n = n_total rows and columns,
+ * leading dimension lda >= n, device memory of the caller): every column of
+ * the current Jacobian, mortar columns included, reconstructed from the
+ * matrix-free product (Alg. Alg-matrix): nodes are coloured so that no row
+ * couples to two nodes of one colour, and one product per colour and
+ * component yields all their columns.  Constrained rows and columns are
+ * those of the identity.  This is the reconstruction behind the direct
+ * coarse-grid solve of the multigrid preconditioner; meant for small meshes
+ * (n <= 32,768) and tests.  Allocates temporary tables and synchronizes the
+ * stream.  Errors: NOT_LINEARIZED, INVALID_ARG, UNSUPPORTED (n too large), HIP. */
+int mns_assemble_matrix(mns_handle* h, double* A, int64_t lda, void* stream);
+
 /* res = R(state): the discrete nonlinear residual of Eq. Eq-NSweakWmortar plus
  * the SUPG/PSPG terms of Eq. Eq-NSweakComplete (tau_u from `state`), with the
  * history and force given at the last mns_set_linearization; constrained rows

@@ -34,6 +34,7 @@ EXPORTED = [
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
     "mns_autotune_kernel_config", "mns_mg_restrict", "mns_batch_solve", "mns_apply_jacobian_noalloc",
+    "mns_assemble_matrix",
 ]
 
 
@@ -135,6 +136,7 @@ def lib():
         L.mns_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_jacobian_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_residual.argtypes = [vp, vp, vp, vp]
+        L.mns_assemble_matrix.argtypes = [vp, vp, ctypes.c_int64, vp]
         L.mns_compute_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
         L.mns_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
         L.mns_default_solve_opts.restype = None
@@ -261,6 +263,15 @@ class Operator:
             raise ValueError("vector length != n_dofs")
         self._check(self._L.mns_apply_jacobian_noalloc(self._h, prec, _ptr(src), _ptr(dst), _stream()))
         return dst
+
+    def assemble_matrix(self):
+        """Dense Jacobian (n x n, float64 tensor, row-major view of the
+        column-major device matrix transposed back) by mns_assemble_matrix."""
+        import torch
+
+        A = torch.empty((self.n_dofs, self.n_dofs), dtype=torch.float64, device="cuda")
+        self._check(self._L.mns_assemble_matrix(self._h, _ptr(A), self.n_dofs, _stream()))
+        return A.t()  # column-major storage: A_cm[col][row]
 
     def apply_residual(self, state, res=None):
         import torch

@@ -318,6 +318,18 @@ int mns_apply_jacobian_noalloc(mns_handle* h, int precision, const void* src, vo
   return set_error(h, MNS_ERR_INVALID_ARG, "precision must be MNS_F64 or MNS_F32");
 }
 
+int mns_assemble_matrix(mns_handle* h, double* A, int64_t lda, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (!aligned(A, 8) || lda < h->ndofs) return set_error(h, MNS_ERR_INVALID_ARG, "A must be aligned with lda >= n");
+  if (h->ndofs > 32768) return set_error(h, MNS_ERR_UNSUPPORTED, "dense assembly is limited to 32,768 DoFs");
+  try {
+    return mns::assemble_matrix(h, A, (long long)lda, as_stream(stream));
+  } catch (...) {
+    return set_error(h, MNS_ERR_HIP, "exception in assemble_matrix");
+  }
+}
+
 int mns_apply_residual(mns_handle* h, const double* state, double* res, void* stream) {
   if (!h) return MNS_ERR_INVALID_ARG;
   if (!h->rotated) return set_error(h, MNS_ERR_NO_ROTATION, "call mns_rotate_rotor first");

@@ -62,6 +62,13 @@ __global__ void k_fill_mat(double* __restrict__ A, long long count, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) A[i] = v;
 }
 
+__global__ void k_zero_mat(double* __restrict__ X, int n, long long ldx) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long count = (long long)n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    X[i % n + (i / n) * ldx] = 0.0;
+}
+
 __global__ void k_identity(double* __restrict__ X, int n, long long ldx) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long count = (long long)n * n;
@@ -401,6 +408,50 @@ static void colour_nodes(const mns_handle* h, std::vector<int>& color, std::vect
   for (auto& v : claimed) owners.insert(owners.end(), v.begin(), v.end());
 }
 
+// Dense reconstruction of the handle's Jacobian (rotated and linearized) into
+// A (n x n, column-major, lda >= n): Alg. Alg-matrix by coloured probing.
+// work: 2 n doubles; *colors / *owners: device tables (allocated here when
+// null, reallocated when the colour count changes).  Enqueued on s; the
+// tables are uploaded with a synchronization of s.
+int assemble_dense(mns_handle* hc, double* A, long long lda, double* work, int** colors, int** owners, int* ncolors,
+                   hipStream_t s) {
+  const int n = (int)hc->ndofs;
+  hipError_t e;
+  std::vector<int> color, own;
+  int ncol = 0;
+  colour_nodes(hc, color, own, &ncol);
+  if (!*colors && (e = hipMalloc((void**)colors, (size_t)hc->nnodes * sizeof(int))) != hipSuccess)
+    return cfail(hc, e, "allocation");
+  if (*owners && *ncolors != ncol) {
+    (void)hipFree(*owners);
+    *owners = nullptr;
+  }
+  if (!*owners && (e = hipMalloc((void**)owners, own.size() * sizeof(int))) != hipSuccess)
+    return cfail(hc, e, "allocation");
+  *ncolors = ncol;
+  if ((e = hipMemcpyAsync(*colors, color.data(), color.size() * sizeof(int), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(*owners, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)  // the host vectors go out of scope
+    return cfail(hc, e, "tables");
+  const long long nnodes = hc->nnodes;
+  const int nc = hc->nc;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_zero_mat, dim3(1024), dim3(256), 0, s, A, n, lda);
+  double* p = work;
+  double* y = work + n;
+  int rc;
+  for (int c = 0; c < ncol; ++c)
+    for (int comp = 0; comp < nc; ++comp) {
+      hipLaunchKernelGGL(k_probe, dim3(g), dim3(256), 0, s, (const int*)*colors, c, comp, nc, nnodes, p);
+      if ((rc = launch_jacobian<double>(hc, p, y, s))) return rc;
+      hipLaunchKernelGGL(k_probe_scatter, dim3(g), dim3(256), 0, s, (const int*)(*owners + (size_t)c * nnodes),
+                         comp, nc, nnodes, (const double*)y, A, lda);
+    }
+  if ((e = hipGetLastError()) != hipSuccess) return cfail(hc, e, "probing");
+  return MNS_OK;
+}
+
 // blocked LU of C->A in place, then C->Ainv = A^-1 from P A = L U
 static int lu_invert(mns_handle* h, CoarseDirect* C, hipStream_t s) {
   const int n = C->n;
@@ -475,39 +526,11 @@ int coarse_setup(mns_handle* hc, void** state, hipStream_t s, int max_dofs) {
     }
     *state = C;
   }
-  // colouring at the current angle (mortar pairs move with it)
-  std::vector<int> color, owners;
-  int ncol = 0;
-  colour_nodes(hc, color, owners, &ncol);
-  if (C->owners && C->ncolors != ncol) {
-    (void)hipFree(C->owners);
-    C->owners = nullptr;
-  }
-  if (!C->owners && (e = hipMalloc((void**)&C->owners, owners.size() * sizeof(int))) != hipSuccess)
-    return cfail(hc, e, "allocation");
-  C->ncolors = ncol;
-  if ((e = hipMemcpyAsync(C->colors, color.data(), color.size() * sizeof(int), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(C->owners, owners.data(), owners.size() * sizeof(int), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)  // the host vectors go out of scope
-    return cfail(hc, e, "tables");
-  const long long nnodes = hc->nnodes;
-  const int nc = hc->nc;
-  const unsigned g = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_fill_mat, dim3(1024), dim3(256), 0, s, C->A, (long long)n * n, 0.0);
-  double* p = C->work;
+  int rc = assemble_dense(hc, C->A, C->lda, C->work, &C->colors, &C->owners, &C->ncolors, s);
+  if (rc) return rc;
   double* y = C->work + n;
-  int rc;
-  for (int c = 0; c < ncol; ++c)
-    for (int comp = 0; comp < nc; ++comp) {
-      hipLaunchKernelGGL(k_probe, dim3(g), dim3(256), 0, s, (const int*)C->colors, c, comp, nc, nnodes, p);
-      if ((rc = launch_jacobian<double>(hc, p, y, s))) return rc;
-      hipLaunchKernelGGL(k_probe_scatter, dim3(g), dim3(256), 0, s, (const int*)(C->owners + (size_t)c * nnodes),
-                         comp, nc, nnodes, (const double*)y, C->A, C->lda);
-    }
-  if ((e = hipGetLastError()) != hipSuccess) return cfail(hc, e, "probing");
-  // check: A x = J x for x = (1, 2, ..., n) / n (every column in play)
+  const unsigned g = (unsigned)((n + 255) / 256);
+  // check: A x = J x for one vector with every entry nonzero
   {
     std::vector<double> xh(n);
     for (int i = 0; i < n; ++i) xh[i] = (double)(i % 97 + 1) / 97.0 - 0.5;
@@ -542,6 +565,22 @@ int coarse_setup(mns_handle* hc, void** state, hipStream_t s, int max_dofs) {
 }
 
 double coarse_check_error(const void* state) { return state ? ((const CoarseDirect*)state)->check_err : -1.0; }
+
+// dense reconstruction for the C-ABI (mns_assemble_matrix): temporary tables
+// and work vectors, synchronizes the stream
+int assemble_matrix(mns_handle* h, double* A, long long lda, hipStream_t s) {
+  double* work = nullptr;
+  int *colors = nullptr, *owners = nullptr, ncol = 0;
+  hipError_t e = hipMalloc((void**)&work, 2 * (size_t)h->ndofs * sizeof(double));
+  if (e != hipSuccess) return cfail(h, e, "allocation");
+  int rc = assemble_dense(h, A, lda, work, &colors, &owners, &ncol, s);
+  e = hipStreamSynchronize(s);
+  if (!rc && e != hipSuccess) rc = cfail(h, e, "assembly");
+  (void)hipFree(work);
+  if (colors) (void)hipFree(colors);
+  if (owners) (void)hipFree(owners);
+  return rc;
+}
 
 // x = A^-1 b in FP64 (b, x in the cycle's precision)
 template <typename Real>

@@ -233,6 +233,7 @@ int launch_constraints(const mns_handle* h, const Real* src, Real* dst, Real dia
 int coarse_setup(mns_handle* hc, void** state, hipStream_t s, int max_dofs);
 void coarse_free(void* state);
 double coarse_check_error(const void* state);
+int assemble_matrix(mns_handle* h, double* A, long long lda, hipStream_t s);
 template <typename Real>
 int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s);
 

@@ -200,3 +200,56 @@ def test_multigrid_degree3_workload_time_step_jacobian():
             assert info["rc"] == 0 and true <= 1.01e-8
             its[prec] = info["iterations"]
     assert abs(its["mg"] - its["mg64"]) <= 2
+
+
+@pytest.mark.parametrize("dim,k,theta", [(2, 2, 0.3), (2, 3, 1.1), (3, 2, 2.0), (3, 2, 0.0), (3, 3, 0.77)])
+def test_assembled_matrix_equals_oracle(dim, k, theta):
+    """Alg. Alg-matrix on the device (mns_assemble_matrix: every column of the
+    Jacobian, mortar columns included, from coloured probes of the matrix-free
+    product) against the oracle's matrix assembled from element and mortar
+    matrices; misaligned and aligned rotor angles."""
+    mesh = small_mesh(dim, k, n_theta=8, n_r_rotor=2, n_r_stator=2, n_z=2, nu=0.03)
+    n = inputs.n_dofs(mesh)
+    state = inputs.uniform(n, 900 + dim)
+    Ao = oracle.assemble(oracle_cfg(mesh, theta, 0.8), state).toarray()
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, 0.8)
+        op.set_linearization(_dev(state))
+        Ag = op.assemble_matrix().cpu().numpy()
+    err = np.abs(Ag - Ao).max() / np.abs(Ao).max()
+    print(f"dim={dim} k={k} theta={theta}: n={n}, dense matrix rel max-norm error {err:.2e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (3, 3)])
+def test_coarse_direct_solve(dim, k):
+    """V-cycle with the coarsest level solved directly (its matrix reconstructed
+    and inverted on the device, FP64) against the same cycle with a Chebyshev
+    polynomial there: both solve the system to the oracle's direct solution;
+    the direct coarse solve needs no more FGMRES iterations."""
+    mesh = small_mesh(dim, k, n_theta=16, n_r_rotor=4, n_r_stator=4, n_z=4 if k == 2 else 2, steady=0, dt=0.02,
+                      nu=0.005)
+    n = inputs.n_dofs(mesh)
+    g = np.random.default_rng(700 + dim)
+    state = inputs.transient_start(mesh, 710 + dim)
+    hist = g.uniform(-1, 1, n)
+    b = g.uniform(-1, 1, n)
+    theta, omega = 0.456, 0.9
+    xo = spla.spsolve(oracle.assemble(oracle_cfg(mesh, theta, omega), state, hist).tocsc(), b)
+    its = {}
+    with binding.Operator(mesh) as op:
+        op.rotate_rotor(theta, omega)
+        op.set_linearization(_dev(state), _dev(hist))
+        for direct in (1, 0):
+            for prec in ("mg", "mg64"):
+                x = torch.zeros(n, dtype=torch.float64, device="cuda")
+                _, rep = op.solve(_dev(b), x, rtol=1e-11, restart=100, maxit=2000, precond=prec,
+                                  mg_coarse_direct=direct)
+                err = relmax(x.cpu().numpy(), xo)
+                its[(direct, prec)] = rep["iterations"]
+                print(f"dim={dim} k={k} {prec} coarse_direct={direct}: its {rep['iterations']}, "
+                      f"vmults f64 {rep['vmults_f64']} f32 {rep['vmults_f32']}, err {err:.2e}")
+                assert err < 1e-8
+                if prec == "mg":
+                    assert rep["vmults_f32"] > 0  # smoother applications are counted
+    assert its[(1, "mg64")] <= its[(0, "mg64")]
