@@ -72,6 +72,11 @@ typedef struct {
                         convection velocity and the SUPG weight are frozen at
                         the state, so the reaction term (du . grad) u and the
                         SUPG weight derivative are absent */
+  int n_theta_stator; /* cells per ring of the stator; 0: n_theta (the equal
+                         interface counts of Sec. 2.1 / Sec. 3.1).  Unequal
+                         counts are the extension named in Sec. 3.1 and Sec. 5:
+                         a face may then meet more than two faces of the other
+                         side, every intersection being one mortar segment */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -186,10 +191,13 @@ typedef struct {
   int d, k, n, nd, nc;
   int ndom;
   int nr[2];
+  int nth[2];          /* cells per ring of each storage domain */
+  int ntd[2];          /* theta node positions per ring of each domain */
   int ntn, nrn[2], nzn;
   long noff[2];
   long nnodes, ndofs;
-  double dth, dz;
+  double dth, dz;      /* dth: cell angle of the rotor (domain 0) */
+  double dthd[2];      /* cell angle of each domain */
   double gll[MAXN], gx[MAXN], gw[MAXN];
   long ncell_dom[2], coff[2], ncells;
   cell_t *cells;
@@ -226,10 +234,11 @@ static void cell_radial(const mesh_t *M, int dom, int cr, double *r0, double *dr
 
 /* global node id of local node (a0,a1,a2) of cell c */
 static long cell_node(const mesh_t *M, const cell_t *c, int a0, int a1, int a2) {
-  long it = (M->k * (long)c->ct + a0) % M->ntn;
+  const long ntn = M->ntd[c->dom];
+  long it = (M->k * (long)c->ct + a0) % ntn;
   long ir = M->k * (long)c->cr + a1;
   long iz = (M->d == 3) ? (M->k * (long)c->cz + a2) : 0;
-  return M->noff[c->dom] + it + M->ntn * (ir + (long)M->nrn[c->dom] * iz);
+  return M->noff[c->dom] + it + ntn * (ir + (long)M->nrn[c->dom] * iz);
 }
 
 static void local_idx(const mesh_t *M, int a, int *a0, int *a1, int *a2) {
@@ -415,6 +424,7 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
   if (P->n_theta < 3 || P->n_r_rotor < 1 || P->n_r_stator < 1) return -1;
   if (P->dim == 3 && (P->n_z < 1 || !(P->height > 0))) return -1;
   if (P->merged && P->theta_rot != 0.0) return -1;
+  if (P->n_theta_stator != 0 && (P->n_theta_stator < 3 || (P->merged && P->n_theta_stator != P->n_theta))) return -1;
   M->d = P->dim;
   M->k = P->degree;
   M->n = P->degree + 1;
@@ -431,6 +441,12 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
   M->ntn = M->k * P->n_theta;
   M->nzn = (M->d == 3) ? M->k * nz + 1 : 1;
   M->dth = 2.0 * M_PI / P->n_theta;
+  M->nth[0] = P->n_theta;
+  M->nth[1] = P->n_theta_stator > 0 ? P->n_theta_stator : P->n_theta;
+  for (int dm = 0; dm < 2; ++dm) {
+    M->ntd[dm] = M->k * M->nth[dm];
+    M->dthd[dm] = 2.0 * M_PI / M->nth[dm];
+  }
   M->dz = (M->d == 3) ? P->height / nz : 1.0;
   lobatto01(M->n, M->gll);
   gauss01(M->n, M->gx, M->gw);
@@ -438,8 +454,8 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
   for (int dm = 0; dm < M->ndom; ++dm) {
     M->nrn[dm] = M->k * M->nr[dm] + 1;
     M->noff[dm] = off;
-    off += (long)M->ntn * M->nrn[dm] * M->nzn;
-    M->ncell_dom[dm] = (long)P->n_theta * M->nr[dm] * nz;
+    off += (long)M->ntd[dm] * M->nrn[dm] * M->nzn;
+    M->ncell_dom[dm] = (long)M->nth[dm] * M->nr[dm] * nz;
     M->coff[dm] = coff;
     coff += M->ncell_dom[dm];
   }
@@ -451,16 +467,16 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
   for (int dm = 0; dm < M->ndom; ++dm)
     for (int cz = 0; cz < nz; ++cz)
       for (int cr = 0; cr < M->nr[dm]; ++cr)
-        for (int ct = 0; ct < P->n_theta; ++ct) {
-          cell_t *c = &M->cells[M->coff[dm] + ct + (long)P->n_theta * (cr + (long)M->nr[dm] * cz)];
+        for (int ct = 0; ct < M->nth[dm]; ++ct) {
+          cell_t *c = &M->cells[M->coff[dm] + ct + (long)M->nth[dm] * (cr + (long)M->nr[dm] * cz)];
           c->dom = dm;
           c->ct = ct;
           c->cr = cr;
           c->cz = cz;
           cell_radial(M, dm, cr, &c->r0, &c->dr, &c->rotor);
-          c->dth = M->dth;
+          c->dth = M->dthd[dm];
           /* x = R(theta_rot) x0 on every rotor node (Sec. 3.1) */
-          c->th0 = ct * M->dth + ((!P->merged && dm == 0) ? P->theta_rot : 0.0);
+          c->th0 = ct * c->dth + ((!P->merged && dm == 0) ? P->theta_rot : 0.0);
           c->z0 = cz * M->dz;
           c->dz = M->dz;
           c->iface = !P->merged && ((dm == 0 && cr == M->nr[0] - 1) || (dm == 1 && cr == 0));
@@ -477,7 +493,7 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
         }
   if (!P->merged) {
     /* all rotor interface cells share one tau, all stator interface cells another */
-    M->tau_side[0] = M->cells[M->coff[0] + (long)P->n_theta * (M->nr[0] - 1)].tau_pen;
+    M->tau_side[0] = M->cells[M->coff[0] + (long)M->nth[0] * (M->nr[0] - 1)].tau_pen;
     M->tau_side[1] = M->cells[M->coff[1]].tau_pen;
     if (P->penalty_rule == 1) {
       double t = fmax(M->tau_side[0], M->tau_side[1]);
@@ -485,19 +501,20 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
     }
     /* mortar segments: intersect every stator interface face with every rotor
      * interface face on the circle (Sec. 2.1, Sec. 3.2) */
-    long cap = 4L * P->n_theta * nz + 8;
+    long cap = 4L * (M->nth[0] + M->nth[1]) * nz + 8;
     M->segs = (seg_t *)calloc((size_t)cap, sizeof(seg_t));
     if (!M->segs) return -2;
     long ns = 0;
+    const double dts = M->dthd[1], dtr = M->dthd[0], tol = 1e-12 * fmin(dts, dtr);
     for (int cz = 0; cz < nz; ++cz)
-      for (int js = 0; js < P->n_theta; ++js) {
-        double lo_s = js * M->dth, hi_s = lo_s + M->dth;
-        for (int ir = 0; ir < P->n_theta; ++ir) {
-          double lo_r0 = P->theta_rot + ir * M->dth;
+      for (int js = 0; js < M->nth[1]; ++js) {
+        double lo_s = js * dts, hi_s = lo_s + dts;
+        for (int ir = 0; ir < M->nth[0]; ++ir) {
+          double lo_r0 = P->theta_rot + ir * dtr;
           for (int sh = -3; sh <= 3; ++sh) {
-            double lo_r = lo_r0 + 2.0 * M_PI * sh, hi_r = lo_r + M->dth;
+            double lo_r = lo_r0 + 2.0 * M_PI * sh, hi_r = lo_r + dtr;
             double lo = fmax(lo_s, lo_r), hi = fmin(hi_s, hi_r);
-            if (hi - lo > 1e-12 * M->dth) {
+            if (hi - lo > tol) {
               if (ns >= cap) return -3;
               M->segs[ns].cz = cz;
               M->segs[ns].ct_rotor = ir;
@@ -517,8 +534,8 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
   for (int dm = 0; dm < M->ndom; ++dm)
     for (long iz = 0; iz < M->nzn; ++iz)
       for (long ir = 0; ir < M->nrn[dm]; ++ir)
-        for (long it = 0; it < M->ntn; ++it) {
-          long node = M->noff[dm] + it + M->ntn * (ir + M->nrn[dm] * iz);
+        for (long it = 0; it < M->ntd[dm]; ++it) {
+          long node = M->noff[dm] + it + M->ntd[dm] * (ir + M->nrn[dm] * iz);
           int wall = 0;
           if (ir == 0 && (P->merged || dm == 0)) wall = 1;                 /* r = r_in */
           if (ir == M->nrn[dm] - 1 && (P->merged || dm == 1)) wall = 1;    /* r = r_out */
@@ -528,7 +545,7 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
         }
   if (P->pin_pressure) {
     int dm = M->ndom - 1;
-    long node = M->noff[dm] + 0 + M->ntn * (M->nrn[dm] - 1);
+    long node = M->noff[dm] + 0 + M->ntd[dm] * (M->nrn[dm] - 1);
     M->cons[node * M->nc + M->d] = 1;
   }
   return 0;
@@ -816,7 +833,7 @@ static int color_of(const mesh_t *M, const cell_t *c) {
 
 static void volume_loop(const mesh_t *M, const inputs_t *in, int mode, const unsigned char *cell_mask, double *y) {
   int ndl = M->nd * M->nc;
-  int par = (M->P.n_theta % 2 == 0) && M->P.nthreads != 1;
+  int par = (M->nth[0] % 2 == 0) && (M->nth[1] % 2 == 0) && M->P.nthreads != 1;
 #ifdef _OPENMP
   if (M->P.nthreads > 0) omp_set_num_threads(M->P.nthreads);
 #endif
@@ -858,7 +875,7 @@ static void volume_loop(const mesh_t *M, const inputs_t *in, int mode, const uns
 
 static const cell_t *iface_cell(const mesh_t *M, int side, int ct, int cz) {
   int cr = (side == 0) ? M->nr[0] - 1 : 0;
-  return &M->cells[M->coff[side] + ct + (long)M->P.n_theta * (cr + (long)M->nr[side] * cz)];
+  return &M->cells[M->coff[side] + ct + (long)M->nth[side] * (cr + (long)M->nr[side] * cz)];
 }
 
 /* reference coordinates on `side` of the physical mortar point (theta, z) */

@@ -193,6 +193,106 @@ def test_mortar_segments(dim):
             assert rot_lo < 1e-9 or rot_lo > 2 * math.pi - dth - 1e-9
 
 
+# ------------------------------ unequal interface counts (Sec. 3.1, Sec. 5) --
+# The rotor and stator rings may hold different cell counts; a face then meets
+# more than two faces of the other side and every intersection is a mortar
+# segment with its own mapped quadrature.
+
+UNEQUAL = [(6, 8), (8, 12), (12, 8), (5, 7)]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("ntr,nts", UNEQUAL)
+def test_mortar_segments_unequal_counts(dim, ntr, nts):
+    """Segments are the intersections of rotor and stator faces: the breakpoints
+    of both rings (the union minus coincidences) split each layer into
+    segments; the mapped quadrature integrates the interface exactly at every
+    angle (sum JxW = 2 pi R [H]) and each face of either side exactly
+    (R dtheta_side [dz]); every segment lies inside both of its faces."""
+    nz = 3
+    dr_, ds_ = 2 * math.pi / ntr, 2 * math.pi / nts
+    for theta in [0.0, 0.3 * dr_, 2.9, dr_ * 3 + 1e-3, -0.7]:
+        cfg = _cfg(dim=dim, n_theta=ntr, n_theta_stator=nts, n_z=nz, theta_rot=theta)
+        ids, lohi, jxw = oracle.segments(cfg)
+        layers = nz if dim == 3 else 1
+        H = cfg["height"] if dim == 3 else 1.0
+        # breakpoints on the circle, in [0, 2 pi)
+        pts = sorted({round((j * ds_) % (2 * math.pi), 10) for j in range(nts)} |
+                     {round((theta + i * dr_) % (2 * math.pi), 10) for i in range(ntr)})
+        merged = [p for i, p in enumerate(pts) if i == 0 or p - pts[i - 1] > 1e-9]
+        if len(merged) > 1 and merged[-1] - merged[0] > 2 * math.pi - 1e-9:
+            merged.pop()
+        assert len(ids) == len(merged) * layers
+        assert abs(jxw.sum() - 2 * math.pi * cfg["r_if"] * H) < 1e-12
+        per = jxw.reshape(len(ids), -1).sum(axis=1)
+        st, rt = np.zeros((layers, nts)), np.zeros((layers, ntr))
+        np.add.at(st, (ids[:, 0], ids[:, 2]), per)
+        np.add.at(rt, (ids[:, 0], ids[:, 1]), per)
+        np.testing.assert_allclose(st, cfg["r_if"] * ds_ * H / layers, rtol=1e-13)
+        np.testing.assert_allclose(rt, cfg["r_if"] * dr_ * H / layers, rtol=1e-13)
+        for (cz, ir, js), (lo, hi) in zip(ids, lohi):
+            assert js * ds_ - 1e-12 <= lo < hi <= (js + 1) * ds_ + 1e-12
+            off = (lo - theta - ir * dr_ + math.pi) % (2 * math.pi) - math.pi  # signed, in [-pi, pi)
+            assert -1e-9 <= off and off + (hi - lo) <= dr_ + 1e-9
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("ntr,nts", [(6, 8), (8, 6)])
+def test_unequal_counts_structure(dim, ntr, nts):
+    """With unequal interface counts: matrix-free = assembled (Alg. Alg-matrix),
+    Alg. Alg-diagonal = assembled diagonal, Newton consistency with the
+    residual (O(eps^2)), B = -C^T with stabilization off, and SIPG symmetry
+    with equal penalties."""
+    cfg = _cfg(dim=dim, n_theta=ntr, n_theta_stator=nts, n_z=2, theta_rot=0.61, steady=0, dt=0.05)
+    n = oracle.n_dofs(cfg)
+    g = np.random.default_rng(31)
+    u, x = g.uniform(-1, 1, n), g.uniform(-1, 1, n)
+    hist = g.uniform(-1, 1, n)
+    A = oracle.assemble(cfg, u, hist)
+    y = oracle.apply_jacobian(cfg, u, x, hist=hist)
+    assert np.abs(A @ x - y).max() <= 1e-13 * np.abs(y).max()
+    np.testing.assert_allclose(oracle.diagonal(cfg, u, hist), A.diagonal(), rtol=1e-12, atol=1e-14)
+    cons = oracle.constrained(cfg)
+    xm = x.copy()
+    xm[cons] = 0
+    ym = oracle.apply_jacobian(cfg, u, xm, hist=hist)
+    errs = []
+    for eps in (1e-3, 1e-4):
+        fd = (oracle.residual(cfg, u + eps * xm, hist, tau_state=u) -
+              oracle.residual(cfg, u - eps * xm, hist, tau_state=u)) / (2 * eps)
+        errs.append(np.abs(fd - ym)[~cons].max() / np.abs(ym).max())
+    assert errs[1] < 3e-8 and errs[0] / errs[1] > 60
+    c0 = dict(cfg, stabilization=0, pin_pressure=0, steady=1)
+    A0 = oracle.assemble(c0, np.zeros(n)).toarray()
+    vel, pr = _blocks(c0)
+    B, C = A0[np.ix_(vel, pr)], A0[np.ix_(pr, vel)]
+    assert np.abs(B).max() > 1e-2 and np.abs(B + C.T).max() < 1e-14
+    c1 = dict(cfg, stabilization=0, omega=0.0, penalty_rule=1, steady=1)
+    Avv = oracle.assemble(c1, np.zeros(n)).toarray()[np.ix_(vel, vel)]
+    assert np.abs(Avv - Avv.T).max() < 1e-14 * np.abs(Avv).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_discrete_mass_conservation_unequal_counts(dim):
+    """The mass balance of the pressure rows (Eq. EqMortarMass) with stator
+    rings of 3/2 the rotor's cell count: quadrature-level zero, decaying
+    under refinement."""
+    errs, scale = [], []
+    for nt in (8, 16, 32):
+        c = max(1, nt // 8)
+        cfg = _cfg(dim=dim, n_theta=nt, n_theta_stator=3 * nt // 2, n_r_rotor=c, n_r_stator=c, n_z=c,
+                   pin_pressure=0)
+        n = oracle.n_dofs(cfg)
+        u = np.random.default_rng(3).uniform(-1, 1, n)
+        yv = oracle.apply_jacobian(cfg, u, _two_sided_field(cfg, 4))
+        pr = np.arange(n) % (dim + 1) == dim
+        errs.append(abs(yv[pr].sum()))
+        scale.append(np.abs(yv[pr]).max())
+    r1, r2 = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    assert r1 > 5.0 and r2 > 5.0, errs  # 7.6 and 5.9 in 2D: the finest level nears round-off
+    assert errs[-1] < 1e-8 * scale[-1], (errs, scale)
+
+
 # ----------------------------------- closed forms on one interior cell (2D) --
 # Rows of J at the interior node of one cell couple only that cell's nodes, so
 # special increments and states reduce them to integrals of the basis over the
@@ -620,6 +720,27 @@ def test_mms_convergence_q2(theta):
                        merged=1)
     eg = oracle.mms_errors(cg, _solve_mms(cg))
     assert abs(errs[1][0] / eg[0] - 1) < 0.05 and abs(errs[1][1] / eg[1] - 1) < 0.05
+
+
+@pytest.mark.slow
+def test_mms_convergence_q2_unequal_counts():
+    """Whole discretization with unequal interface counts (stator rings 3/2 the
+    rotor's): the 2D manufactured solution converges at the optimal Q2 rates
+    and its error stays within a few percent of the equal-count mesh with
+    the same rotor ring."""
+    errs = []
+    for nt, nr in ((32, 4), (64, 8)):
+        cfg = oracle.params(dim=2, degree=2, n_theta=nt, n_theta_stator=3 * nt // 2, n_r_rotor=nr, n_r_stator=nr,
+                            nu=1.0, omega=0.0, theta_rot=0.05, mms=1, nthreads=0)
+        errs.append(oracle.mms_errors(cfg, _solve_mms(cfg)))
+    ru = math.log2(errs[0][0] / errs[1][0])
+    rp = math.log2(errs[0][1] / errs[1][1])
+    assert ru > 3.0 - 0.25 and rp > 2.0 - 0.25, (ru, rp)
+    ce = oracle.params(dim=2, degree=2, n_theta=64, n_r_rotor=8, n_r_stator=8, nu=1.0, omega=0.0,
+                       theta_rot=0.05, mms=1)
+    ee = oracle.mms_errors(ce, _solve_mms(ce))
+    print(errs, ee)
+    assert errs[1][0] < 1.5 * ee[0] and errs[1][1] < 1.5 * ee[1]
 
 
 @pytest.mark.slow
