@@ -80,9 +80,10 @@ enum { MNS_LIN_NEWTON = 0, MNS_LIN_PICARD = 1 };
 typedef struct mns_handle mns_handle;
 
 /* Mesh and physics description (Sec. 2, Sec. 3.1).  Rotor annulus
- * r_in < r < r_interface, stator annulus r_interface < r < r_out, each with
- * n_theta azimuthal cells (equal on both sides, Sec. 2.1 / Sec. 3.1), n_r_rotor
- * resp. n_r_stator radial cells, and in 3D n_z axial layers on [0, height]. */
+ * r_in < r < r_interface, stator annulus r_interface < r < r_out, with n_theta
+ * azimuthal cells in the rotor ring and n_theta_stator (default: n_theta) in
+ * the stator ring, n_r_rotor resp. n_r_stator radial cells, and in 3D n_z
+ * axial layers on [0, height] (equal on both sides). */
 typedef struct {
   int dim;               /* 2 or 3 */
   int degree;            /* k >= 2: 2..5 in 2D, 2..4 in 3D */
@@ -94,6 +95,12 @@ typedef struct {
   int penalty_side_rule; /* 0: each side its own cell tau_k; 1: max of both sides */
   int steady;            /* 1: no time derivative; 0: BDF2 with constant dt */
   double dt;             /* time step (transient only) */
+  int n_theta_stator;    /* cells per ring of the stator; 0 (or n_theta): the equal interface counts of
+                            Sec. 2.1 / Sec. 3.1.  Another count lifts that restriction (the extension named
+                            in Sec. 3.1 and Sec. 5): a face may then meet several faces of the other side,
+                            every intersection being one mortar segment (at most 4:1 either way).  Such meshes
+                            support the Jacobian, residual, diagonal and mns_solve with the Jacobi-Chebyshev
+                            preconditioner; multigrid, batching and the fused launch need equal counts */
 } mns_mesh_desc;
 
 /* Create a handle: validates the description, builds the 1D tables, the

@@ -45,7 +45,7 @@ class MeshDesc(ctypes.Structure):
         ("height", ctypes.c_double),
         ("n_theta", ctypes.c_int), ("n_r_rotor", ctypes.c_int), ("n_r_stator", ctypes.c_int), ("n_z", ctypes.c_int),
         ("nu", ctypes.c_double), ("penalty_F", ctypes.c_double), ("penalty_side_rule", ctypes.c_int),
-        ("steady", ctypes.c_int), ("dt", ctypes.c_double),
+        ("steady", ctypes.c_int), ("dt", ctypes.c_double), ("n_theta_stator", ctypes.c_int),
     ]
 
 
@@ -183,7 +183,7 @@ def mesh_desc(mesh):
         n_theta=int(mesh["n_theta"]), n_r_rotor=int(mesh["n_r_rotor"]), n_r_stator=int(mesh["n_r_stator"]),
         n_z=int(mesh.get("n_z", 1)), nu=float(mesh["nu"]), penalty_F=float(mesh.get("penalty_F", 1.0)),
         penalty_side_rule=int(mesh.get("penalty_rule", 0)), steady=int(mesh.get("steady", 1)),
-        dt=float(mesh.get("dt", 1.0)),
+        dt=float(mesh.get("dt", 1.0)), n_theta_stator=int(mesh.get("n_theta_stator", 0)),
     )
 
 

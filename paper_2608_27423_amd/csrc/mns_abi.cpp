@@ -179,6 +179,8 @@ int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch) {
       return set_error(h, MNS_ERR_NOT_LINEARIZED, "batch: rotate and linearize every handle first");
     if (h->dim != handles[0]->dim || h->k != handles[0]->k)
       return set_error(h, MNS_ERR_INVALID_ARG, "batch: all handles need the same dimension and degree");
+    if (!h->equal_rings)
+      return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need equal interface cell counts");
   }
   auto* b = new mns_batch();
   b->hs.assign(handles, handles + count);

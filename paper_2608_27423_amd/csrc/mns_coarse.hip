@@ -305,7 +305,7 @@ __global__ void k_check(const double* __restrict__ A, long long lda, int n, cons
 
 // node index of (domain, theta, r, z) on handle h
 static long long node_id(const mns_handle* h, int dom, int it, int ir, int iz) {
-  return (dom ? h->node_off1 : 0) + it + (long long)h->ntn * (ir + (long long)h->nrn[dom] * iz);
+  return (dom ? h->node_off1 : 0) + it + (long long)h->ntd[dom] * (ir + (long long)h->nrn[dom] * iz);
 }
 
 // nodes of cell (dom, ct, cr, cz)
@@ -316,7 +316,7 @@ static void cell_nodes(const mns_handle* h, int dom, int ct, int cr, int cz, std
     for (int b = 0; b <= k; ++b)
       for (int a = 0; a <= k; ++a) {
         int it = k * ct + a;
-        if (it >= h->ntn) it -= h->ntn;
+        if (it >= h->ntd[dom]) it -= h->ntd[dom];
         out.push_back(node_id(h, dom, it, k * cr + b, h->dim == 3 ? k * cz + c : 0));
       }
 }
@@ -365,19 +365,33 @@ static void colour_nodes(const mns_handle* h, std::vector<int>& color, std::vect
     const int nr = dom ? d.n_r_stator : d.n_r_rotor;
     for (int cz = 0; cz < nz; ++cz)
       for (int cr = 0; cr < nr; ++cr)
-        for (int ct = 0; ct < d.n_theta; ++ct) {
+        for (int ct = 0; ct < h->nth[dom]; ++ct) {
           cell_nodes(h, dom, ct, cr, cz, na);
           couple(na, na);
         }
   }
-  // stator face j meets rotor faces j - m - 1 (when the offset is not zero) and j - m
+  // mortar pairs: a stator face and a rotor face whose angle ranges overlap
+  // by more than the alignment tolerance (equal counts: stator face j meets
+  // rotor faces j - m - 1, when the offset is not zero, and j - m)
+  const double two_pi = 2.0 * M_PI, dts = h->dthd[1], dtr = h->dthd[0];
+  const double tol = 1e-12 * std::min(dts, dtr);
+  const double th = std::fmod(h->theta, two_pi) + (h->theta < 0 ? two_pi : 0.0);
   for (int cz = 0; cz < nz; ++cz)
-    for (int j = 0; j < d.n_theta; ++j) {
+    for (int j = 0; j < h->nth[1]; ++j) {
       cell_nodes(h, 1, j, 0, cz, na);
-      for (int s = 0; s < 2; ++s) {
-        if (s == 0 && !(h->phi > 0.0)) continue;
-        const int rt = (((j - h->m - (s == 0 ? 1 : 0)) % d.n_theta) + d.n_theta) % d.n_theta;
-        cell_nodes(h, 0, rt, d.n_r_rotor - 1, cz, nb);
+      for (int i = 0; i < h->nth[0]; ++i) {
+        bool meet = false;
+        if (h->equal_rings) {
+          meet = i == (((j - h->m) % h->nth[0]) + h->nth[0]) % h->nth[0] ||
+                 (h->phi > 0.0 && i == (((j - h->m - 1) % h->nth[0]) + h->nth[0]) % h->nth[0]);
+        } else {
+          for (int sh = -1; sh <= 1 && !meet; ++sh) {
+            const double r0 = th + i * dtr + sh * two_pi;
+            meet = std::min((j + 1) * dts, r0 + dtr) - std::max(j * dts, r0) > tol;
+          }
+        }
+        if (!meet) continue;
+        cell_nodes(h, 0, i, d.n_r_rotor - 1, cz, nb);
         couple(na, nb);
         couple(nb, na);
       }

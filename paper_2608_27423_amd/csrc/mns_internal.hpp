@@ -47,18 +47,18 @@ struct Geom {
   long long cell_off1;  // first stator cell
   long long node_off1;  // first stator node
   long long ndofs;
-  int n_theta, nz;      // cells per ring, axial layers (1 in 2D)
-  int ntn, nzn;         // nodes per ring, axial node planes (1 in 2D)
+  int nth[2], nz;       // cells per ring of each domain, axial layers (1 in 2D)
+  int ntd[2], nzn;      // theta node positions per ring of each domain, axial node planes (1 in 2D)
   int nr[2], nrn[2];    // radial cells / node rows per domain
   Real r0[2], dr[2];    // inner radius and radial cell size per domain
-  Real dth, dz;         // cell angle, layer height (1 in 2D)
+  Real dthd[2], dz;     // cell angle of each domain, layer height (1 in 2D)
   Real nu, omega;
   Real ct;              // BDF2 coefficient 3/(2 dt), 0 when steady
   Real ctau2;           // (1/dt)^2 in tau_u, 0 when steady
   Real h[2];            // element size per domain for each radial layer: see hcell
   const Real* hcell;    // [2][hstride] element size by (domain, radial layer)
   int hstride;
-  const Real* trig;     // [2][n_theta][N][2]: cos, sin of theta at (domain, cell, Gauss point)
+  const Real* trig;     // [nth[0] + nth[1]][N][2]: cos, sin of theta at (ring cell, Gauss point), rotor first
 };
 
 // Mortar quadrature tables for the current rotor angle (Sec. 3.2).  Segment 0
@@ -80,6 +80,18 @@ struct MortarTab {
   int m;                // pairing offset, in [0, n_theta)
 };
 
+// Interface data of the general mortar kernels (unequal ring counts): every
+// mortar segment is found and mapped inside the kernel from these values.
+struct MortarGen {
+  double theta_rot;                   // rotor angle
+  double R;                           // interface radius
+  double tau_pen[2];                  // penalty of the rotor and stator interface cells (Eq. EqPenalty)
+  double inv_dr[2];                   // 1 / dr of the rotor and stator cells
+  double inv_dz;                      // 1 / dz (3D), 0 in 2D
+  double gll[kMaxN];                  // Gauss-Lobatto nodes on [0, 1]
+  double FV[2][kMaxN], FD[2][kMaxN];  // L_b, L_b' at the interface (xi_r = 1 rotor, 0 stator)
+};
+
 struct Buffers {
   void* p = nullptr;
   size_t bytes = 0;
@@ -90,7 +102,11 @@ struct Buffers {
 struct mns_handle {
   mns_mesh_desc desc{};
   int dim = 0, k = 0, n = 0, nc = 0;
-  int ntn = 0, nzn = 0, nz = 0;
+  int ntn = 0, nzn = 0, nz = 0;  // ntn: theta node positions of the rotor ring (= ntd[0])
+  int nth[2] = {0, 0};           // cells per ring of each domain (equal unless n_theta_stator is set)
+  int ntd[2] = {0, 0};           // theta node positions per ring of each domain
+  double dthd[2] = {0, 0};       // cell angle of each domain
+  bool equal_rings = true;       // nth[0] == nth[1]: two mortar segments per face at most
   int nrn[2] = {0, 0};
   int64_t ncells = 0, cell_off1 = 0, node_off1 = 0, nnodes = 0, ndofs = 0;
   double dth = 0, dz = 0;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 #include <mutex>
 #include <string>
 
@@ -63,8 +64,9 @@ __device__ inline CellId decode_cell(const Geom<Real>& G, int cell) {
   CellId c;
   c.dom = cell >= (int)G.cell_off1;
   int l = cell - (c.dom ? (int)G.cell_off1 : 0);
-  c.ct = l % G.n_theta;
-  l /= G.n_theta;
+  const int nt = pick(c.dom, G.nth);
+  c.ct = l % nt;
+  l /= nt;
   const int nr = pick(c.dom, G.nr);
   c.cr = l % nr;
   c.cz = l / nr;
@@ -77,11 +79,12 @@ template <typename Real, int DIM>
 __device__ inline long long node_of(const Geom<Real>& G, int k, const CellId& C, int a, int b, int c, int& it,
                                     int& ir, int& iz) {
   it = k * C.ct + a;
-  if (it >= G.ntn) it -= G.ntn;
+  const int ntn = pick(C.dom, G.ntd);
+  if (it >= ntn) it -= ntn;
   ir = k * C.cr + b;
   iz = (DIM == 3) ? k * C.cz + c : 0;
   long long base = C.dom ? G.node_off1 : 0;
-  return base + it + (long long)G.ntn * (ir + (long long)pick(C.dom, G.nrn) * iz);
+  return base + it + (long long)ntn * (ir + (long long)pick(C.dom, G.nrn) * iz);
 }
 
 // constraint predicates, written with bitwise operators so that they
@@ -318,16 +321,17 @@ template <typename Real, int DIM, int N>
 __device__ inline PtGeom<Real> point_geom(const Geom<Real>& G, const Tab1D<Real, N>& T, const CellId& C, int tqi,
                                           int tqj, int q) {
   PtGeom<Real> g;
-  const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + tqi) * 2;
+  const Real* tr = G.trig + (((size_t)(C.dom ? G.nth[0] : 0) + C.ct) * N + tqi) * 2;
   g.c = tr[0];
   g.s = tr[1];
   const Real dr = pick(C.dom, G.dr);
   g.r = pick(C.dom, G.r0) + dr * (Real(C.cr) + T.x[tqj]);
   g.inv_r = Real(1) / g.r;
   g.inv_dr = Real(1) / dr;
-  g.inv_rdth = g.inv_r / G.dth;
+  const Real dth = pick(C.dom, G.dthd);
+  g.inv_rdth = g.inv_r / dth;
   g.inv_dz = (DIM == 3) ? Real(1) / G.dz : Real(0);
-  Real w = T.w[tqi] * T.w[tqj] * g.r * G.dth * dr;
+  Real w = T.w[tqi] * T.w[tqj] * g.r * dth * dr;
   if constexpr (DIM == 3) w *= T.w[q] * G.dz;
   g.jxw = w;
   g.complete();
@@ -502,8 +506,9 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
   if (g >= nnodes) return;
   const int dom = g >= G.node_off1;
   const long long l = g - (dom ? G.node_off1 : 0);
-  const int it = (int)(l % G.ntn);
-  const long long l2 = l / G.ntn;
+  const int ntn = pick(dom, G.ntd), ntc = pick(dom, G.nth);
+  const int it = (int)(l % ntn);
+  const long long l2 = l / ntn;
   const int nrn = pick(dom, G.nrn), nrd = pick(dom, G.nr);
   const int ir = (int)(l2 % nrn);
   const int iz = (int)(l2 / nrn);
@@ -515,7 +520,7 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
   tc[0] = it / k;
   ta[0] = it % k;
   tv[0] = true;
-  tc[1] = (tc[0] == 0 ? G.n_theta : tc[0]) - 1;
+  tc[1] = (tc[0] == 0 ? ntc : tc[0]) - 1;
   ta[1] = k;
   tv[1] = ta[0] == 0;
   int rc[2], rb[2];
@@ -551,7 +556,7 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
     // strip layout of the quad volume kernel: batches of 16 theta-consecutive
     // cells, 16 k + 1 node columns per (comp, z, r) node position; a node on a
     // batch boundary appears in two batches (last column of the earlier one)
-    const int S16 = 16 * k, nbt = G.n_theta / 16;
+    const int S16 = 16 * k, nbt = ntc / 16;
     const size_t nblk = (size_t)(G.ncells / 16), pstride = nblk * S16;
     const Real* Eb = E + (size_t)N * N * NC * pstride;  // last columns of the batches
     int sb[2], sj[2];
@@ -575,7 +580,7 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
 #pragma unroll
           for (int m = 0; m < NC; ++m) cv[z][r][t][m] = 0;
           if (!(zv[z] && rv[r] && sv[t])) continue;
-          const int ring = (cbase + G.n_theta * (rc[r] + nrd * zc[z])) / 16;
+          const int ring = (cbase + ntc * (rc[r] + nrd * zc[z])) / 16;
           const size_t pos = (size_t)(zb[z] * N + rb[r]);
           const size_t st = t == 0 ? pstride : nblk;
           const Real* e = t == 0 ? E + pos * pstride + (size_t)(ring + sb[0]) * S16 + sj[0]
@@ -593,7 +598,7 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
 #pragma unroll
           for (int m = 0; m < NC; ++m) cv[z][r][t][m] = 0;
           if (!(zv[z] && rv[r] && tv[t])) continue;
-          const int cell = cbase + tc[t] + G.n_theta * (rc[r] + nrd * zc[z]);
+          const int cell = cbase + tc[t] + ntc * (rc[r] + nrd * zc[z]);
           const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + rb[r] * N + ta[t];
           const Real* e = E + (size_t)loc * G.ncells + cell;
 #pragma unroll
@@ -613,15 +618,16 @@ __device__ inline void gather_node(const Geom<Real>& G, int k, const Real* __res
 #pragma unroll
       for (int m = 0; m < NC; ++m) mv[z][t][m] = 0;
   if (bm >= 0 && Em) {
-    const int nfaces = G.n_theta * G.nz;
-    const int nsides = 2 * nfaces;
+    // face sides: the rotor's n_theta[0] n_z faces, then the stator's
+    const int nf0 = G.nth[0] * G.nz;
+    const int nsides = nf0 + G.nth[1] * G.nz;
     const size_t mstride = (size_t)S::NPT * nsides;
 #pragma unroll
     for (int z = 0; z < 2; ++z)
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         if (!(zv[z] && tv[t])) continue;
-        const int cs = dom * nfaces + tc[t] + G.n_theta * zc[z];
+        const int cs = (dom ? nf0 : 0) + tc[t] + ntc * zc[z];
         const int loc = (DIM == 3 ? zb[z] * S::PLANE : 0) + bm * N + ta[t];
         const Real* e = Em + (size_t)loc * nsides + cs;
 #pragma unroll
@@ -1110,7 +1116,7 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
   // one point ahead, points in (q, qj) order) and the nodal values
   Real trc, trs;
   {
-    const Real* tr = G.trig + (((size_t)C.dom * G.n_theta + C.ct) * N + ts) * 2;
+    const Real* tr = G.trig + (((size_t)(C.dom ? G.nth[0] : 0) + C.ct) * N + ts) * 2;
     trc = tr[0];
     trs = tr[1];
   }
@@ -1129,15 +1135,16 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
   Real U[NC][N][N];  // [comp][r][z]
   {
     int it = k * C.ct + ts;
-    it = it >= G.ntn ? it - G.ntn : it;
+    const int ntn = pick(C.dom, G.ntd);
+    it = it >= ntn ? it - ntn : it;
     const int nrn = pick(C.dom, G.nrn);
-    const long long nbase = (C.dom ? G.node_off1 : 0) + it + (long long)G.ntn * (k * C.cr + (long long)nrn * k * C.cz);
+    const long long nbase = (C.dom ? G.node_off1 : 0) + it + (long long)ntn * (k * C.cr + (long long)nrn * k * C.cz);
 #pragma unroll
     for (int b = 0; b < N; ++b)
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         const int ir = k * C.cr + b, iz = k * C.cz + c;
-        const long long node = nbase + (long long)G.ntn * (b + (long long)nrn * c);
+        const long long node = nbase + (long long)ntn * (b + (long long)nrn * c);
         Real w[4];
         load_node4<Real>(src + node * NC, w);
         const bool outer = (C.dom == 0) ? (ir == 0) : (ir == G.nrn[1] - 1);
@@ -1214,9 +1221,10 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
   const Real dr = pick(C.dom, G.dr), r0 = pick(C.dom, G.r0);
   g.inv_dr = Real(1) / dr;
   g.inv_dz = Real(1) / G.dz;
-  const Real wt = lane_select<N>(ts, T.w) * G.dth * dr * G.dz;
+  const Real dth_c = pick(C.dom, G.dthd);
+  const Real wt = lane_select<N>(ts, T.w) * dth_c * dr * G.dz;
   const Real nu = G.nu, ct = G.ct;
-  const Real inv_dth = Real(1) / G.dth;
+  const Real inv_dth = Real(1) / dth_c;
   Real rq[N], inv_rq[N];
 #pragma unroll
   for (int qj = 0; qj < N; ++qj) {
@@ -1651,7 +1659,7 @@ struct Piece {
 template <typename Real, int DIM, int N>
 __device__ inline void mortar_pieces(const Geom<Real>& G, int mstep, int side, int ct, int cz,
                                      Piece<Real, DIM, N> (&p)[2]) {
-  const int nt = G.n_theta;
+  const int nt = G.nth[0];  // equal counts on both sides
   if (side == 1) {
     const int j = ct;
     p[0].seg = 0;
@@ -1727,7 +1735,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
   auto& trg = sm.trg;
   auto& ev = sm.ev;
   auto& coef = sm.coef;
-  const int nfaces = G.n_theta * G.nz;
+  const int nfaces = G.nth[0] * G.nz;  // equal counts on both sides
   const int nsides = 2 * nfaces;
   // ---- phase A: evaluation.  Lane = (face, piece, side, component).  The
   // table copy's loads go first; the pairing of faces needs only the offset
@@ -1752,7 +1760,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
   const bool act = fl < FPB && fs0 < nsides;
   const int fs = act ? fs0 : nsides - 1;
   const int side = fs / nfaces, f = fs % nfaces;
-  const int ct = f % G.n_theta, cz = f / G.n_theta;
+  const int ct = f % G.nth[0], cz = f / G.nth[0];
   Piece<Real, DIM, N> P[2];
   mortar_pieces<Real, DIM, N>(G, Mp->m, side, ct, cz, P);
   // lane-dependent piece picked by selects (an indexed access would put the
@@ -1884,7 +1892,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
-    mortar_pieces<Real, DIM, N>(G, M.m, side, f % G.n_theta, f / G.n_theta, P);
+    mortar_pieces<Real, DIM, N>(G, M.m, side, f % G.nth[0], f / G.nth[0], P);
     const int qt = q % N, qz = q / N;
     const Real idr_o = side == 0 ? M.inv_dr[0] : M.inv_dr[1];
     const Real idr_x = side == 0 ? M.inv_dr[1] : M.inv_dr[0];
@@ -1940,7 +1948,7 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     if (fs >= nsides) continue;
     const int side = fs / nfaces, f = fs % nfaces;
     Piece<Real, DIM, N> P[2];
-    mortar_pieces<Real, DIM, N>(G, M.m, side, f % G.n_theta, f / G.n_theta, P);
+    mortar_pieces<Real, DIM, N>(G, M.m, side, f % G.nth[0], f / G.nth[0], P);
     Real k0[N], k1[N];
 #pragma unroll
     for (int a2 = 0; a2 < N; ++a2) {
@@ -2077,10 +2085,10 @@ __global__ __launch_bounds__(64) void k_mortar_diag(Geom<Real> G, Tab1D<Real, N>
   using S = Shape<Real, DIM, N>;
   constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ;
   const MortarTab<Real, N>& M = *Mp;
-  const int nfaces = G.n_theta * G.nz;
+  const int nfaces = G.nth[0] * G.nz;  // equal counts on both sides
   const int side = blockIdx.x / nfaces;
   const int f = blockIdx.x % nfaces;
-  const int ct = f % G.n_theta, cz = f / G.n_theta;
+  const int ct = f % G.nth[0], cz = f / G.nth[0];
   const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
   Piece<Real, DIM, N> P[2];
   mortar_pieces<Real, DIM, N>(G, M.m, side, ct, cz, P);
@@ -2111,6 +2119,286 @@ __global__ __launch_bounds__(64) void k_mortar_diag(Geom<Real> G, Tab1D<Real, N>
     const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
 #pragma unroll
     for (int m = 0; m < DIM; ++m) atomic_add(diag + nd * NC + m, acc[m]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mortar face terms with unequal interface counts (the restriction of
+// Sec. 3.1 lifted, as Sec. 5 proposes): a face of one side meets every face
+// of the other side that overlaps it, and each intersection is one segment
+// with the Gauss rule of Sec. 3.2 mapped into it (JxW = w R dtheta_seg dz).
+// One 64-lane block per interface face side (rotor faces first); for every
+// segment of its face:
+//   - the other cell's nodal values join the own cell's in LDS;
+//   - lane per (point, component, side): value and reference derivatives at
+//     the point, by direct sums over the cell's nodes (the theta basis at the
+//     segment's points evaluated in FP64 from the Gauss-Lobatto nodes);
+//   - lane per point: the own side's face coefficients (jump = own - other,
+//     n = own outward normal) times JxW;
+//   - lane per (own local node, component): the test integrals, summed over
+//     the segments in registers and stored once, Em[comp][local node][face side].
+// Segments shorter than 1e-12 of the smaller cell angle are dropped (the
+// alignment rule of the equal-count tables).
+// ---------------------------------------------------------------------------
+constexpr int kMaxPieces = 6;  // segments per face: ceil(4) + 2 for ring counts at most 4:1 apart
+
+template <int N>
+__device__ inline void lagrange_gll(const double (&nodes)[kMaxN], double t, double (&L)[N], double (&dL)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double p = 1.0, dp = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (q == j) continue;
+      const double inv = 1.0 / (nodes[j] - nodes[q]);
+      const double f = (t - nodes[q]) * inv;
+      dp = dp * f + p * inv;
+      p = p * f;
+    }
+    L[j] = p;
+    dL[j] = dp;
+  }
+}
+
+// the face of side `side` with ring index ct: cell angle, start angle and
+// the position of its start in the other side's ring, reduced to [0, 2 pi)
+struct GenFace {
+  double dth_s, dth_o, start, delta, tol;
+  int nto, f0;
+};
+
+template <typename Real>
+__device__ inline GenFace gen_face(const Geom<Real>& G, const MortarGen& MG, int side, int ct) {
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  GenFace F;
+  const int nts = pick(side, G.nth);
+  F.nto = pick(1 - side, G.nth);
+  F.dth_s = kTwoPi / nts;
+  F.dth_o = kTwoPi / F.nto;
+  const double th0_s = side == 0 ? MG.theta_rot : 0.0, th0_o = side == 0 ? 0.0 : MG.theta_rot;
+  F.start = th0_s + ct * F.dth_s;
+  double delta = fmod(F.start - th0_o, kTwoPi);
+  if (delta < 0) delta += kTwoPi;
+  F.delta = delta;
+  F.tol = 1e-12 * fmin(F.dth_s, F.dth_o);
+  F.f0 = (int)floor(delta / F.dth_o);
+  return F;
+}
+
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real, N> T, int k, MortarGen MG,
+                                                       const Real* __restrict__ src, Real* __restrict__ Em,
+                                                       int mask) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ, NQ = N * NZ, NE = DIM + 1;
+  constexpr int NI = (NPT * NC + 63) / 64;
+  __shared__ Real U[2][NC][NPT];    // nodal values: own cell (0), other cell (1)
+  __shared__ Real ev[2][NQ][NC][NE];// value, d/dxi_theta, d/dxi_r, d/dxi_z at the points
+  __shared__ Real cf[NQ][NC][NE];   // own-side test coefficients times JxW
+  __shared__ Real Lo[N][N], dLo[N][N];  // own theta basis at the segment's points [qt][a]
+  const int tid = threadIdx.x;
+  const int nf0 = G.nth[0] * G.nz;
+  const int nsides = nf0 + G.nth[1] * G.nz;
+  const int fs = blockIdx.x;
+  const int side = fs >= nf0;
+  const int f = side ? fs - nf0 : fs;
+  const int nts = pick(side, G.nth);
+  const int ct = f % nts, cz = f / nts;
+  const int cr_own = side == 0 ? G.nr[0] - 1 : 0, cr_oth = side == 0 ? 0 : G.nr[0] - 1;
+  const CellId own{side, ct, cr_own, cz};
+  const GenFace F = gen_face(G, MG, side, ct);
+  auto load_cell = [&](const CellId& C, int slot) {
+    for (int e = tid; e < NPT * NC; e += 64) {
+      const int node = e / NC, m = e % NC;
+      const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+      int it, ir, iz;
+      const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
+      const bool fixed = (mask != 0) & ((m < DIM) ? vel_fixed<Real, DIM>(G, C.dom, ir, iz) : p_fixed(G, C.dom, it, ir, iz));
+      U[slot][m][node] = fixed ? Real(0) : src[nd * NC + m];
+    }
+  };
+  load_cell(own, 0);
+  Real acc[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) acc[i] = 0;
+  const Real nu = G.nu;
+  const double R = MG.R;
+  const double idr_s = MG.inv_dr[side], idr_o = MG.inv_dr[1 - side];
+  const double irdth_s = 1.0 / (R * F.dth_s), irdth_o = 1.0 / (R * F.dth_o);
+  const double tau = MG.tau_pen[side];
+  for (int p = 0; p < kMaxPieces; ++p) {
+    const int fo = F.f0 + p;
+    const double a_f = fo * F.dth_o - F.delta;  // other face start, in the own face's local angle
+    if (a_f >= F.dth_s - F.tol) break;
+    const double lo = fmax(0.0, a_f), hi = fmin(F.dth_s, a_f + F.dth_o);
+    if (hi - lo <= F.tol) continue;
+    const int ofc = ((fo % F.nto) + F.nto) % F.nto;
+    const CellId oth{1 - side, ofc, cr_oth, cz};
+    __syncthreads();  // the previous segment is done with U[1], ev, cf, Lo
+    load_cell(oth, 1);
+    for (int qt = tid; qt < N; qt += 64) {
+      double L[N], dL[N];
+      lagrange_gll<N>(MG.gll, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        Lo[qt][a] = (Real)L[a];
+        dLo[qt][a] = (Real)dL[a];
+      }
+    }
+    __syncthreads();
+    // evaluation at the segment's points
+    for (int e = tid; e < 2 * NQ * NC; e += 64) {
+      const int sd = e / (NQ * NC), q = (e / NC) % NQ, m = e % NC;
+      const int qt = q % N, qz = q / N;
+      const double sl = lo + (double)T.x[qt] * (hi - lo);
+      double L[N], dL[N];
+      lagrange_gll<N>(MG.gll, sd == 0 ? sl / F.dth_s : (sl - a_f) / F.dth_o, L, dL);
+      const int cs = sd == 0 ? side : 1 - side;
+      Real v = 0, dt = 0, dr = 0, dz = 0;
+#pragma unroll
+      for (int c = 0; c < NZ; ++c) {
+        const Real lz = (DIM == 3) ? T.V[qz][c] : Real(1);
+        const Real dlz = (DIM == 3) ? T.D[qz][c] : Real(0);
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          const Real fv = (Real)MG.FV[cs][b], fd = (Real)MG.FD[cs][b];
+          Real s0 = 0, s1 = 0;
+#pragma unroll
+          for (int a = 0; a < N; ++a) {
+            const Real u = U[sd][m][(c * N + b) * N + a];
+            s0 += (Real)L[a] * u;
+            s1 += (Real)dL[a] * u;
+          }
+          v += lz * fv * s0;
+          dt += lz * fv * s1;
+          dr += lz * fd * s0;
+          dz += dlz * fv * s0;
+        }
+      }
+      Real* o = ev[sd][q][m];
+      o[0] = v;
+      o[1] = dt;
+      o[2] = dr;
+      if constexpr (DIM == 3) o[3] = dz;
+    }
+    __syncthreads();
+    // the own side's face coefficients at every point
+    for (int q = tid; q < NQ; q += 64) {
+      const int qt = q % N, qz = q / N;
+      const double sl = lo + (double)T.x[qt] * (hi - lo);
+      double sth, cth;
+      sincos(F.start + sl, &sth, &cth);
+      double jxw = (double)T.w[qt] * R * (hi - lo);
+      if constexpr (DIM == 3) jxw *= (double)T.w[qz] / MG.inv_dz;
+      const Real c = (Real)cth, sn = (Real)sth, J = (Real)jxw;
+      Real n[DIM] = {};
+      n[0] = side == 0 ? c : -c;
+      n[1] = side == 0 ? sn : -sn;
+      const Real pbar = Real(0.5) * (ev[0][q][DIM][0] + ev[1][q][DIM][0]);
+      Real jn = 0;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        const Real* eo = ev[0][q][m];
+        const Real* ex = ev[1][q][m];
+        const Real dro = eo[2] * (Real)idr_s, dto = eo[1] * (Real)irdth_s;
+        const Real drx = ex[2] * (Real)idr_o, dtx = ex[1] * (Real)irdth_o;
+        Real gavg[DIM];
+        gavg[0] = Real(0.5) * ((c * dro - sn * dto) + (c * drx - sn * dtx));
+        gavg[1] = Real(0.5) * ((sn * dro + c * dto) + (sn * drx + c * dtx));
+        if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * (Real)MG.inv_dz;
+        Real gn = 0;
+#pragma unroll
+        for (int d2 = 0; d2 < DIM; ++d2) gn += gavg[d2] * n[d2];
+        const Real j = eo[0] - ex[0];
+        jn += j * n[m];
+        const Real cv = pbar * n[m] - nu * gn + nu * (Real)tau * j;
+        Real Gm[DIM];
+#pragma unroll
+        for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
+        Real* o = cf[q][m];
+        o[0] = J * cv;
+        o[1] = J * (-sn * Gm[0] + c * Gm[1]) * (Real)irdth_s;
+        o[2] = J * (c * Gm[0] + sn * Gm[1]) * (Real)idr_s;
+        if constexpr (DIM == 3) o[3] = J * Gm[2] * (Real)MG.inv_dz;
+      }
+      Real* o = cf[q][DIM];
+      o[0] = J * Real(-0.5) * jn;
+#pragma unroll
+      for (int j = 1; j < NE; ++j) o[j] = 0;
+    }
+    __syncthreads();
+    // test integrals of the own cell's basis functions
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const int e = tid + 64 * ii;
+      const int node = (e < NPT * NC ? e : 0) / NC, m = e % NC;
+      const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+      const Real fv = (Real)MG.FV[side][b], fd = (Real)MG.FD[side][b];
+      Real sum = 0;
+      for (int q = 0; q < NQ; ++q) {
+        const int qt = q % N, qz = q / N;
+        const Real lz = (DIM == 3) ? T.V[qz][c] : Real(1);
+        const Real dlz = (DIM == 3) ? T.D[qz][c] : Real(0);
+        const Real lt = Lo[qt][a], dlt = dLo[qt][a];
+        const Real* o = cf[q][m];
+        sum += o[0] * lt * fv * lz + o[1] * dlt * fv * lz + o[2] * lt * fd * lz;
+        if constexpr (DIM == 3) sum += o[3] * lt * fv * dlz;
+      }
+      acc[ii] += sum;
+    }
+  }
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int e = tid + 64 * ii;
+    const int node = e / NC, m = e % NC;
+    if (e < NPT * NC) Em[(size_t)(m * NPT + node) * nsides + fs] = acc[ii];
+  }
+}
+
+// Mortar part of the diagonal with unequal interface counts (Alg.
+// Alg-diagonal): the unit vector of own DoF i (other side zero) tested with
+// the same basis function gives nu tau phi^2 - nu phi (grad phi . n) for
+// velocity rows, 0 for pressure rows, summed over the face's segments.
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_mortar_diag_general(Geom<Real> G, Tab1D<Real, N> T, int k, MortarGen MG,
+                                                            Real* __restrict__ diag) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ;
+  const int nf0 = G.nth[0] * G.nz;
+  const int fs = blockIdx.x;
+  const int side = fs >= nf0;
+  const int f = side ? fs - nf0 : fs;
+  const int nts = pick(side, G.nth);
+  const int ct = f % nts, cz = f / nts;
+  const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
+  const GenFace F = gen_face(G, MG, side, ct);
+  const double nu = (double)G.nu, tau = MG.tau_pen[side], idr = MG.inv_dr[side];
+  for (int node = threadIdx.x; node < NPT; node += blockDim.x) {
+    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+    const double fv = MG.FV[side][b], fd = MG.FD[side][b];
+    double acc = 0;
+    for (int p = 0; p < kMaxPieces; ++p) {
+      const double a_f = (F.f0 + p) * F.dth_o - F.delta;
+      if (a_f >= F.dth_s - F.tol) break;
+      const double lo = fmax(0.0, a_f), hi = fmin(F.dth_s, a_f + F.dth_o);
+      if (hi - lo <= F.tol) continue;
+      for (int qz = 0; qz < NZ; ++qz)
+        for (int qt = 0; qt < N; ++qt) {
+          double L[N], dL[N];
+          lagrange_gll<N>(MG.gll, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
+          const double vz = (DIM == 3) ? (double)T.V[qz][c] : 1.0;
+          double jxw = (double)T.w[qt] * MG.R * (hi - lo);
+          if (DIM == 3) jxw *= (double)T.w[qz] / MG.inv_dz;
+          const double phi = L[a] * fv * vz;
+          const double dr = L[a] * fd * vz * idr;
+          const double gn = side == 0 ? dr : -dr;  // grad phi . n, n = +-e_r
+          acc += jxw * (nu * tau * phi * phi - nu * phi * gn);
+        }
+    }
+    int it, ir, iz;
+    const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) atomic_add(diag + nd * NC + m, (Real)acc);
   }
 }
 
@@ -2167,9 +2455,11 @@ static Geom<Real> make_geom(const mns_handle* h) {
   G.cell_off1 = h->cell_off1;
   G.node_off1 = h->node_off1;
   G.ndofs = h->ndofs;
-  G.n_theta = d.n_theta;
+  G.nth[0] = h->nth[0];
+  G.nth[1] = h->nth[1];
+  G.ntd[0] = h->ntd[0];
+  G.ntd[1] = h->ntd[1];
   G.nz = h->nz;
-  G.ntn = h->ntn;
   G.nzn = h->nzn;
   G.nr[0] = d.n_r_rotor;
   G.nr[1] = d.n_r_stator;
@@ -2179,7 +2469,8 @@ static Geom<Real> make_geom(const mns_handle* h) {
   G.r0[1] = (Real)d.r_interface;
   G.dr[0] = (Real)((d.r_interface - d.r_in) / d.n_r_rotor);
   G.dr[1] = (Real)((d.r_out - d.r_interface) / d.n_r_stator);
-  G.dth = (Real)h->dth;
+  G.dthd[0] = (Real)h->dthd[0];
+  G.dthd[1] = (Real)h->dthd[1];
   G.dz = (Real)h->dz;
   G.nu = (Real)d.nu;
   G.omega = (Real)h->omega;
@@ -2195,6 +2486,29 @@ static Geom<Real> make_geom(const mns_handle* h) {
     G.trig = (const Real*)h->d_trig32;
   }
   return G;
+}
+
+// interface data of the general mortar kernels (unequal ring counts)
+static MortarGen make_mortar_gen(const mns_handle* h) {
+  MortarGen M{};
+  const mns_mesh_desc& d = h->desc;
+  M.theta_rot = h->theta;
+  M.R = d.r_interface;
+  M.tau_pen[0] = h->tau_pen[0];
+  M.tau_pen[1] = h->tau_pen[1];
+  M.inv_dr[0] = 1.0 / ((d.r_interface - d.r_in) / d.n_r_rotor);
+  M.inv_dr[1] = 1.0 / ((d.r_out - d.r_interface) / d.n_r_stator);
+  M.inv_dz = d.dim == 3 ? 1.0 / h->dz : 0.0;
+  std::vector<double> L(h->n), dL(h->n), d2L(h->n);
+  for (int i = 0; i < h->n; ++i) M.gll[i] = h->gll[i];
+  for (int side = 0; side < 2; ++side) {
+    lagrange_1d(h->gll, side == 0 ? 1.0 : 0.0, L.data(), dL.data(), d2L.data());
+    for (int b = 0; b < h->n; ++b) {
+      M.FV[side][b] = L[b];
+      M.FD[side][b] = dL[b];
+    }
+  }
+  return M;
 }
 
 static int hip_check(mns_handle* h, const char* what);
@@ -2263,9 +2577,15 @@ template <typename Real, int DIM, int N>
 static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStream_t s) {
   const Geom<Real> G = make_geom<Real>(h);
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
+  if (!h->equal_rings) {
+    const unsigned nfs = (unsigned)((h->nth[0] + h->nth[1]) * G.nz);
+    launch_k(h, TIMER_MORTAR, k_mortar_general<Real, DIM, N>, dim3(nfs), dim3(64), s, G, T, h->k, make_mortar_gen(h),
+             src, Em, mask);
+    return hip_check(h, "general mortar kernel");
+  }
   const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
   const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
-  const unsigned blocks = (2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
+  const unsigned blocks = (2u * (unsigned)(G.nth[0] * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                          MortarShape<Real, DIM, N>::FPB;
   launch_k(h, TIMER_MORTAR, k_mortar<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, M, mtrig, src, Em, mask);
   return hip_check(h, "mortar kernel");
@@ -2301,24 +2621,26 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
   const bool quad = kQuad && h->quad;
   // strip layout of the local results: batches of 16 cells stay inside one
   // ring when the ring length is a multiple of 16
-  const int strip = (quad && h->desc.n_theta % 16 == 0) ? 1 : 0;
+  const int strip = (quad && h->nth[0] % 16 == 0 && h->nth[1] % 16 == 0) ? 1 : 0;
   const int cpw = quad ? QuadShape<Real, N>::CPW : S::CPW;
   const unsigned blocks = (unsigned)((G.ncells + cpw - 1) / cpw);
   int rc;
   // launch mode; automatic: one fused launch for small meshes (the mortar
   // work is a latency tail there), the concurrent second stream for large ones
-  const int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
+  int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
+  // unequal ring counts: the general mortar kernel runs as its own launch
+  if (!h->equal_rings && mode == 1) mode = 0;
   if (mode == 1) {
     // one launch of volume cell blocks and mortar face blocks
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
     const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
-    const int nmb = (int)((2u * (unsigned)(G.n_theta * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
+    const int nmb = (int)((2u * (unsigned)(G.nth[0] * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                           MortarShape<Real, DIM, N>::FPB);
     if constexpr (kQuad) {
       if (quad) {
         if constexpr (sizeof(Real) == 8 && N == 3) {
           using MSL = MortarShape<Real, DIM, N, kLdsQuadBytes>;
-          const int nml = (int)((2u * (unsigned)(G.n_theta * G.nz) + MSL::FPB - 1) / MSL::FPB);
+          const int nml = (int)((2u * (unsigned)(G.nth[0] * G.nz) + MSL::FPB - 1) / MSL::FPB);
           launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad_lds<N>, dim3(blocks + nml), dim3(64), s, G, T, h->k, nml,
                    lin, M, mtrig, src, E, Em, strip);
         } else {
@@ -2465,8 +2787,8 @@ static void batch_blocks(const mns_handle* h, long long* nmb, long long* nvb, in
   // shared with the LDS-staged volume blocks), the default otherwise
   constexpr int FPB = (kQuad && sizeof(Real) == 8 && N == 3) ? MortarShape<Real, DIM, N, kLdsQuadBytes>::FPB
                                                              : MortarShape<Real, DIM, N>::FPB;
-  *nmb = (2LL * h->desc.n_theta * h->nz + FPB - 1) / FPB;
-  *strip = (kQuad && h->desc.n_theta % 16 == 0) ? 1 : 0;
+  *nmb = (2LL * h->nth[0] * h->nz + FPB - 1) / FPB;  // batches hold equal ring counts only
+  *strip = (kQuad && h->nth[0] % 16 == 0) ? 1 : 0;
 }
 
 template <typename Real, int DIM, int N>
@@ -2628,7 +2950,7 @@ template <typename Real>
 size_t jacobian_scratch_bytes(const mns_handle* h) {
   const size_t npt = (size_t)(h->dim == 3 ? h->n * h->n * h->n : h->n * h->n);
   const size_t e = ((size_t)h->ncells * h->nc * npt * sizeof(Real) + 255) / 256 * 256;
-  const size_t em = (size_t)2 * h->desc.n_theta * h->nz * h->nc * npt * sizeof(Real);
+  const size_t em = (size_t)(h->nth[0] + h->nth[1]) * h->nz * h->nc * npt * sizeof(Real);
   return e + em;
 }
 
@@ -2697,10 +3019,15 @@ static int do_diag(mns_handle* h, Real* diag, hipStream_t s) {
                      h->k, lin, diag);
   rc = hip_check(h, "diagonal kernel");
   if (rc) return rc;
-  const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
-  const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
-  hipLaunchKernelGGL((k_mortar_diag<Real, DIM, N>), dim3(2u * (unsigned)(G.n_theta * G.nz)), dim3(64), 0, s, G, T,
-                     h->k, M, mtrig, diag);
+  if (h->equal_rings) {
+    const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
+    const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
+    hipLaunchKernelGGL((k_mortar_diag<Real, DIM, N>), dim3(2u * (unsigned)(G.nth[0] * G.nz)), dim3(64), 0, s, G, T,
+                       h->k, M, mtrig, diag);
+  } else {
+    hipLaunchKernelGGL((k_mortar_diag_general<Real, DIM, N>), dim3((unsigned)((h->nth[0] + h->nth[1]) * G.nz)),
+                       dim3(64), 0, s, G, T, h->k, make_mortar_gen(h), diag);
+  }
   rc = hip_check(h, "mortar diagonal kernel");
   if (rc) return rc;
   rc = launch_constraints<Real>(h, diag, diag, Real(1), 2, s);

@@ -165,6 +165,13 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
     return set_error(h, MNS_ERR_INVALID_ARG, "radii must satisfy 0 < r_in < r_interface < r_out");
   if (d->n_theta < 3 || d->n_r_rotor < 1 || d->n_r_stator < 1)
     return set_error(h, MNS_ERR_INVALID_ARG, "need n_theta >= 3 and at least one radial cell per domain");
+  if (d->n_theta_stator != 0 && d->n_theta_stator < 3)
+    return set_error(h, MNS_ERR_INVALID_ARG, "n_theta_stator must be 0 (same as n_theta) or >= 3");
+  {
+    const int nts = d->n_theta_stator > 0 ? d->n_theta_stator : d->n_theta;
+    if (nts > 4 * d->n_theta || d->n_theta > 4 * nts)
+      return set_error(h, MNS_ERR_UNSUPPORTED, "interface cell counts more than 4:1 apart");
+  }
   if (d->dim == 3 && (d->n_z < 1 || !(d->height > 0)))
     return set_error(h, MNS_ERR_INVALID_ARG, "3D needs n_z >= 1 and height > 0");
   if (!(d->nu > 0) || !std::isfinite(d->nu)) return set_error(h, MNS_ERR_INVALID_ARG, "nu must be > 0");
@@ -178,17 +185,24 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
   h->n = k + 1;
   h->nc = d->dim + 1;
   h->nz = d->dim == 3 ? d->n_z : 1;
-  h->ntn = k * d->n_theta;
+  h->nth[0] = d->n_theta;
+  h->nth[1] = d->n_theta_stator > 0 ? d->n_theta_stator : d->n_theta;
+  h->equal_rings = h->nth[0] == h->nth[1];
+  for (int dom = 0; dom < 2; ++dom) {
+    h->ntd[dom] = k * h->nth[dom];
+    h->dthd[dom] = 2.0 * M_PI / h->nth[dom];
+  }
+  h->ntn = h->ntd[0];
   h->nzn = d->dim == 3 ? k * d->n_z + 1 : 1;
   h->nrn[0] = k * d->n_r_rotor + 1;
   h->nrn[1] = k * d->n_r_stator + 1;
-  h->node_off1 = (int64_t)h->ntn * h->nrn[0] * h->nzn;
-  h->nnodes = h->node_off1 + (int64_t)h->ntn * h->nrn[1] * h->nzn;
+  h->node_off1 = (int64_t)h->ntd[0] * h->nrn[0] * h->nzn;
+  h->nnodes = h->node_off1 + (int64_t)h->ntd[1] * h->nrn[1] * h->nzn;
   h->ndofs = h->nnodes * h->nc;
-  h->cell_off1 = (int64_t)d->n_theta * d->n_r_rotor * h->nz;
-  h->ncells = h->cell_off1 + (int64_t)d->n_theta * d->n_r_stator * h->nz;
+  h->cell_off1 = (int64_t)h->nth[0] * d->n_r_rotor * h->nz;
+  h->ncells = h->cell_off1 + (int64_t)h->nth[1] * d->n_r_stator * h->nz;
   if (h->ncells >= (int64_t)1 << 30) return set_error(h, MNS_ERR_UNSUPPORTED, "more than 2^30 cells");
-  h->dth = 2.0 * M_PI / d->n_theta;
+  h->dth = h->dthd[0];
   h->dz = d->dim == 3 ? d->height / d->n_z : 1.0;
   rules_1d(h->n, h->gll, h->gx, h->gw);
 
@@ -201,7 +215,7 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
   for (int dom = 0; dom < 2; ++dom)
     for (int cr = 0; cr < nr[dom]; ++cr) {
       const double ra = r0[dom] + cr * dr[dom], rb = ra + dr[dom];
-      const double V = 0.5 * (rb * rb - ra * ra) * h->dth * h->dz;
+      const double V = 0.5 * (rb * rb - ra * ra) * h->dthd[dom] * h->dz;
       h->hcell[dom * h->hstride + cr] = d->dim == 2 ? 2.0 * std::sqrt(V / M_PI) : std::cbrt(6.0 * V / M_PI);
     }
   // Hillewaert penalty of the interface cells (Eq. EqPenalty), exact polar measures
@@ -209,10 +223,11 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
     const double ra = side == 0 ? d->r_interface - dr[0] : d->r_interface;
     const double rb = side == 0 ? d->r_interface : d->r_interface + dr[1];
     const double other_arc = side == 0 ? ra : rb;
-    const double V = 0.5 * (rb * rb - ra * ra) * h->dth * h->dz;
-    const double A_m = d->r_interface * h->dth * h->dz;
-    double A_o = other_arc * h->dth * h->dz + 2.0 * dr[side] * h->dz;
-    if (d->dim == 3) A_o += 2.0 * 0.5 * (rb * rb - ra * ra) * h->dth;
+    const double dts = h->dthd[side];
+    const double V = 0.5 * (rb * rb - ra * ra) * dts * h->dz;
+    const double A_m = d->r_interface * dts * h->dz;
+    double A_o = other_arc * dts * h->dz + 2.0 * dr[side] * h->dz;
+    if (d->dim == 3) A_o += 2.0 * 0.5 * (rb * rb - ra * ra) * dts;
     h->tau_pen[side] = d->penalty_F * (k + 1.0) * (k + 1.0) * (0.5 * A_o + A_m) / V;
   }
   if (d->penalty_side_rule == 1) h->tau_pen[0] = h->tau_pen[1] = std::max(h->tau_pen[0], h->tau_pen[1]);
@@ -226,8 +241,8 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
       for (int ir = 0; ir < h->nrn[dom]; ++ir) {
         const bool wall = (dom == 0 && ir == 0) || (dom == 1 && ir == h->nrn[1] - 1) ||
                           (d->dim == 3 && (iz == 0 || iz == h->nzn - 1));
-        for (int it = 0; it < h->ntn; ++it) {
-          const int64_t node = base + it + (int64_t)h->ntn * (ir + (int64_t)h->nrn[dom] * iz);
+        for (int it = 0; it < h->ntd[dom]; ++it) {
+          const int64_t node = base + it + (int64_t)h->ntd[dom] * (ir + (int64_t)h->nrn[dom] * iz);
           if (wall)
             for (int c = 0; c < d->dim; ++c) cons.push_back(node * h->nc + c);
           if (dom == 1 && it == 0 && ir == h->nrn[1] - 1 && iz == 0) cons.push_back(node * h->nc + d->dim);
@@ -245,7 +260,7 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
   // local-result buffers of the volume and mortar kernels (summed by the gather kernel)
   const size_t npt = (size_t)(d->dim == 3 ? h->n * h->n * h->n : h->n * h->n);
   const size_t nE = (size_t)h->ncells * h->nc * npt;
-  const size_t nEm = (size_t)2 * d->n_theta * h->nz * h->nc * npt;
+  const size_t nEm = (size_t)(h->nth[0] + h->nth[1]) * h->nz * h->nc * npt;
   hipError_t e;
   if ((e = hipMalloc((void**)&h->d_E64, nE * sizeof(double))) != hipSuccess) return hipfail(h, e, "hipMalloc E");
   if ((e = hipMalloc((void**)&h->d_E32, nE * sizeof(float))) != hipSuccess) return hipfail(h, e, "hipMalloc E");
@@ -255,7 +270,7 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
   // linearization store and the state copy (written by
   // mns_set_linearization): allocated here so that those calls allocate
   // nothing and stay stream-ordered
-  const size_t ntrig = (size_t)2 * d->n_theta * h->n * 2, nmtrig = (size_t)d->n_theta * 2 * h->n * 2;
+  const size_t ntrig = (size_t)(h->nth[0] + h->nth[1]) * h->n * 2, nmtrig = (size_t)h->nth[1] * 2 * h->n * 2;
   size_t mtab64 = 0, mtab32 = 0;
   switch (h->n) {
     case 3: mtab64 = sizeof(MortarTab<double, 3>); mtab32 = sizeof(MortarTab<float, 3>); break;
@@ -291,8 +306,10 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
 // captured into a graph (its arguments are plain values).
 // ---------------------------------------------------------------------------
 struct RotArgs {
-  double theta, phi, dth, R, dz;
+  double theta, phi, dth, R, dz;  // dth, nt: cell angle and ring count of the stator (mortar tables)
+  double dthr;                    // cell angle of the rotor ring
   int nt, dim, m;
+  int ntr;                        // cells per rotor ring
   double gll[kMaxN], gx[kMaxN], gw[kMaxN];
   double tau_pen[2], inv_dr[2];
 };
@@ -317,8 +334,8 @@ __device__ inline void lagrange_dev(const double (&nodes)[kMaxN], double t, doub
   }
 }
 
-// Work items, in order: (domain, cell, Gauss point) cos/sin of the volume
-// points; (stator face, segment, point) cos/sin of the mortar points; (side,
+// Work items, in order: (ring cell, Gauss point) cos/sin of the volume
+// points, rotor cells first; (stator face, segment, point) cos/sin of the mortar points; (side,
 // segment, point) rows of the mortar value/derivative tables; (side) rows of
 // the face tables; one item for the weights and scalars.  Segment 0 of stator
 // face j spans [j dth, j dth + phi], segment 1 [j dth + phi, (j+1) dth]; the
@@ -331,13 +348,14 @@ __global__ void k_rotate_tables(RotArgs A, double* __restrict__ trig64, float* _
                                 MortarTab<double, N>* __restrict__ M64, MortarTab<float, N>* __restrict__ M32) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int nt = A.nt;
-  const long long n_trig = 2LL * nt * N, n_mtrig = (long long)nt * 2 * N;
+  const long long n_trig = (long long)(A.ntr + nt) * N, n_mtrig = (long long)nt * 2 * N;
   const double len[2] = {A.phi, A.dth - A.phi};
   const double start[2] = {0.0, A.phi};
   if (i < n_trig) {
-    const int dom = (int)(i / ((long long)nt * N));
-    const int ct = (int)((i / N) % nt), q = (int)(i % N);
-    const double ang = (dom == 0 ? A.theta : 0.0) + (ct + A.gx[q]) * A.dth;
+    const long long row = i / N;
+    const int dom = row >= A.ntr;
+    const int ct = (int)(dom ? row - A.ntr : row), q = (int)(i % N);
+    const double ang = dom == 0 ? A.theta + (ct + A.gx[q]) * A.dthr : (ct + A.gx[q]) * A.dth;
     const double c = cos(ang), sn = sin(ang);
     trig64[2 * i] = c;
     trig64[2 * i + 1] = sn;
@@ -422,7 +440,7 @@ __global__ void k_rotate_tables(RotArgs A, double* __restrict__ trig64, float* _
 
 template <int N>
 static int launch_rotate(mns_handle* h, const RotArgs& A, hipStream_t s) {
-  const long long items = 2LL * A.nt * N + (long long)A.nt * 2 * N + 4 * N + 3;
+  const long long items = (long long)(A.ntr + A.nt) * N + (long long)A.nt * 2 * N + 4 * N + 3;
   const unsigned blocks = (unsigned)((items + 255) / 256);
   hipLaunchKernelGGL(k_rotate_tables<N>, dim3(blocks), dim3(256), 0, s, A, h->d_trig64, h->d_trig32, h->d_mtrig64,
                      h->d_mtrig32, (MortarTab<double, N>*)h->d_mtab64, (MortarTab<float, N>*)h->d_mtab32);
@@ -434,8 +452,8 @@ static int launch_rotate(mns_handle* h, const RotArgs& A, hipStream_t s) {
 // Sec. 3.2 for that angle, enqueued on stream s.
 int mns_rotate_tables(mns_handle* h, double theta, double omega, hipStream_t s) {
   const mns_mesh_desc& d = h->desc;
-  const int N = h->n, nt = d.n_theta;
-  const double dth = h->dth;
+  const int N = h->n, nt = h->nth[1];
+  const double dth = h->dthd[1];
   // theta = m dth + phi with 0 <= phi < dth; snap to alignment within 1e-12 dth
   double mf = std::floor(theta / dth);
   double phi = theta - mf * dth;
@@ -454,6 +472,8 @@ int mns_rotate_tables(mns_handle* h, double theta, double omega, hipStream_t s) 
   A.theta = theta;
   A.phi = phi;
   A.dth = dth;
+  A.dthr = h->dthd[0];
+  A.ntr = h->nth[0];
   A.R = d.r_interface;
   A.dz = h->dz;
   A.nt = nt;

@@ -1190,6 +1190,7 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
     mg_free(h);  // another level count was asked for
   }
   if (h->k != 2 && h->k != 3) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs degree 2 or 3");
+  if (!h->equal_rings) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs equal interface cell counts");
   MG* mg = new MG();
   mg->max_levels = max_levels;
   h->mg = mg;
@@ -1198,6 +1199,7 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
   L0.n = h->ndofs;
   mg->L.push_back(L0);
   mns_mesh_desc d = h->desc;
+  d.n_theta_stator = 0;  // equal ring counts on every level
   // degree 3: first a degree-2 level on the same mesh, then halved meshes
   bool poly = d.degree == 3;
   while ((poly || can_halve(d)) && (max_levels == 0 || (int)mg->L.size() < max_levels)) {

@@ -69,16 +69,18 @@ def node_grid(m):
 
 def n_dofs(m):
     ntn, nrr, nrs, nzn = node_grid(m)
-    return ntn * (nrr + nrs) * nzn * (m["dim"] + 1)
+    nts = m["degree"] * m["n_theta_stator"] if m.get("n_theta_stator") else ntn  # stator ring, when it differs
+    return (ntn * nrr + nts * nrs) * nzn * (m["dim"] + 1)
 
 
 def _index_coords(m):
     """Approximate node positions from the node indices alone (theta, r, z equally
     spaced per domain, rotor at zero angle); smooth-field inputs only."""
     ntn, nrr, nrs, nzn = node_grid(m)
+    nts = m["degree"] * m["n_theta_stator"] if m.get("n_theta_stator") else ntn
     out = []
-    for nr_nodes, r0, r1 in ((nrr, m["r_in"], m["r_if"]), (nrs, m["r_if"], m["r_out"])):
-        th = TWO_PI * np.arange(ntn) / ntn
+    for nt_nodes, nr_nodes, r0, r1 in ((ntn, nrr, m["r_in"], m["r_if"]), (nts, nrs, m["r_if"], m["r_out"])):
+        th = TWO_PI * np.arange(nt_nodes) / nt_nodes
         r = np.linspace(r0, r1, nr_nodes)
         z = np.linspace(0.0, m["height"], nzn) if m["dim"] == 3 else np.zeros(1)
         Z, R, T = np.meshgrid(z, r, th, indexing="ij")

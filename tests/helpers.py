@@ -6,7 +6,7 @@ import oracle
 
 def oracle_cfg(mesh, theta, omega, **kw):
     keys = ("dim", "degree", "r_in", "r_if", "r_out", "height", "n_theta", "n_r_rotor", "n_r_stator", "n_z", "nu",
-            "penalty_F", "penalty_rule", "steady", "dt")
+            "penalty_F", "penalty_rule", "steady", "dt", "n_theta_stator")
     cfg = {k: mesh[k] for k in keys if k in mesh}
     cfg.update(theta_rot=float(theta), omega=float(omega))
     cfg.update(kw)
