@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-copy-bandwidth", action="store_true", help="skip the device-copy bandwidth measurement")
     ap.add_argument("--transient", action="store_true",
                     help="also time one BDF2 + Newton step (transient workloads; rotor advances omega * dt)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 7.3M- and 68M-DoF legs (vmults, degree-3 multigrid solve, 68M-DoF time step)")
     return ap.parse_args()
 
 
@@ -281,13 +283,152 @@ def degree3_solve_leg(args, mesh, name, theta, omega, dev, sync):
         out["levels"] = sop.mg_levels()
     p, m = out["plain_fp64"], out["mixed_fp32"]
     out["speedup_mixed_over_plain"] = p["seconds"] / m["seconds"] if m["seconds"] > 0 else None
-    out["operator"] = f"Jacobian of one BDF2 step, dt = {dt}, history of a state at rest in time"
+    out["operator"] = (f"Jacobian of one BDF2 step, dt = {dt}, history of a state at rest in time (not the "
+                       f"steady operator: see steady_attempt)")
     out["state"] = "smooth manufactured field scaled to max |u| = 1"
     out["preconditioner"] = ("geometric/polynomial multigrid V-cycle (degree 3 -> 2, then halved meshes), "
                              "Picard-linearized coarse levels, Jacobi-Chebyshev smoothing degree 2 on "
                              "[1.05 lambda/5, 1.05 lambda] (lambda by 60 power iterations) in FP32 (mixed) or FP64 "
                              "(plain), FGMRES(30)")
     return {"multigrid": out}
+
+
+def vmult_leg(name, dev, sync, steps=100, warmup=10):
+    """FP64 and FP32 Jacobian of a workload: per-application time from HIP
+    events on the launch stream over `steps` back-to-back applications, the
+    dominant launch's time from its own dispatch events, and the HBM roofline
+    of the whole application (algorithmic bytes over its time)."""
+    import torch
+
+    from paper_2608_27423_amd import binding, inputs
+
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    op = binding.Operator(mesh)
+    op.rotate_rotor(theta, mesh["omega"])
+    op.set_linearization(torch.from_numpy(inputs.state_for(name)).to(dev))
+    x = torch.from_numpy(inputs.vector_for(name)).to(dev)
+    n = x.numel()
+    out = {"workload": name, "dofs": n}
+    for label, xx in (("fp64", x), ("fp32", x.float())):
+        y = torch.empty_like(xx)
+        for _ in range(warmup):
+            op.apply_jacobian(xx, y)
+        sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            op.apply_jacobian(xx, y)
+        e1.record()
+        sync()
+        ms = e0.elapsed_time(e1) / steps
+        op.enable_timing(steps)
+        for _ in range(steps):
+            op.apply_jacobian(xx, y)
+        sync()
+        t = op.read_timing()
+        op.enable_timing(0)
+        nbytes, _ = algorithmic_bytes_volume(mesh, n, 8 if label == "fp64" else 4)
+        vol_ms = t["ms_volume"] / max(1, t["n_volume"])
+        out[label] = {"ms_per_vmult": ms, "dofs_per_s": n / (ms * 1e-3), "volume_kernel_ms": vol_ms,
+                      "mortar_kernel_ms": t["ms_mortar"] / max(1, t["n_mortar"]),
+                      "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+                      "frac_of_8TBs": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "volume_launch_frac_of_8TBs": nbytes / (vol_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "volume_kernel": dominant_kernel(mesh, -1, 1, "double" if label == "fp64" else "float")}
+        del y
+    out["fp32_speedup_over_fp64"] = out["fp64"]["ms_per_vmult"] / out["fp32"]["ms_per_vmult"]
+    return op, mesh, theta, out
+
+
+def transient_leg(op, mesh, name, theta, dev, sync):
+    """Two implicit time steps of a spin-up: fluid at rest, a smooth body
+    force (the workload's smooth field, max 1) switched on, the rotor
+    advancing omega dt per step; the second step is timed with the FP32 and
+    with the FP64 V-cycle."""
+    import torch
+
+    from paper_2608_27423_amd import inputs
+
+    omega, dt = mesh["omega"], mesh["dt"]
+    force = torch.from_numpy(inputs.transient_start(mesh, inputs.STATE_SEED[name])).to(dev)
+    u0 = torch.zeros_like(force)
+    u1 = u0.clone()
+    lin_opts = dict(rtol=1e-6, restart=30, maxit=600, precond="mg")
+    op.bdf2_step(theta + omega * dt, omega, u0, u1, u_nm1=None, force=force, newton_rtol=1e-8, max_newton=10,
+                 linear=lin_opts)
+    steps = {}
+    for label, prec in (("mixed_fp32_multigrid", "mg"), ("plain_fp64_multigrid", "mg64")):
+        u = u1.clone()
+        sync()
+        info = op.bdf2_step(theta + 2 * omega * dt, omega, u1, u, u_nm1=u0, force=force, check=False,
+                            newton_rtol=1e-8, max_newton=10, linear=dict(lin_opts, precond=prec))
+        steps[label] = {"seconds": info["seconds"], "newton_iterations": info["newton_iterations"],
+                        "linear_iterations": info["linear_iterations"], "converged": info["rc"] == 0,
+                        "residual0": info["residual0"], "residual": info["residual"],
+                        "line_search_halvings": info["line_search_halvings"]}
+        del u
+    m_, p_ = steps["mixed_fp32_multigrid"], steps["plain_fp64_multigrid"]
+    del force, u0, u1
+    return {**steps, "speedup_mixed_over_plain": p_["seconds"] / m_["seconds"] if m_["seconds"] > 0 else None,
+            "dt": dt, "rotation_rad": omega * dt,
+            "scenario": "spin-up from rest under a smooth body force; second BDF2 step timed",
+            "newton_rtol": 1e-8,
+            "linear": "FGMRES(30) FP64 to 1e-6, geometric multigrid V-cycle with an FP64 direct coarse solve, "
+                      "Jacobi-Chebyshev smoothing in FP32 (mixed) or FP64 (plain)"}
+
+
+def steady_degree3_attempt(mesh, name, theta, dev, sync, maxit=300):
+    """The steady degree-3 operator itself (Re = 1/nu, no time derivative) at
+    the smooth state: FGMRES(30) with the FP32 V-cycle (Picard coarse levels,
+    FP64 direct coarse solve), stopped at `maxit` iterations; the reached
+    relative residual is reported whether or not 1e-8 is met."""
+    import numpy as np
+    import torch
+
+    from paper_2608_27423_amd import binding, inputs
+
+    with binding.Operator(mesh) as sop:
+        sop.rotate_rotor(theta, mesh["omega"])
+        s = inputs.smooth_field(mesh, inputs.STATE_SEED[name])
+        s /= np.abs(s).max()
+        sop.set_linearization(torch.from_numpy(s).to(dev))
+        rhs = sop.apply_jacobian(torch.from_numpy(inputs.uniform(sop.n_dofs, inputs.SOLUTION_SEED[name])).to(dev))
+        xs = torch.zeros_like(rhs)
+        sync()
+        _, info = sop.solve(rhs, xs, check=False, rtol=1e-8, restart=30, maxit=maxit, precond="mg",
+                            mg_coarse_linearization="picard", mg_fine_linearization="picard", eig_iters=60,
+                            mg_smooth_degree=3, mg_smooth_range=10.0)
+        chk = sop.apply_jacobian(xs)
+        sync()
+        return {"converged": info["rc"] == 0, "iterations": info["iterations"], "seconds": info["seconds"],
+                "true_rel_residual": float((rhs - chk).norm() / rhs.norm()), "maxit": maxit,
+                "operator": f"steady Jacobian, nu = {mesh['nu']}, smooth state (max |u| = 1)",
+                "preconditioner": "FGMRES(30), FP32 V-cycle: Picard levels, smoothing degree 3 on "
+                                  "[1.05 lambda/10, 1.05 lambda], FP64 direct solve on the coarsest level"}
+
+
+def large_workloads_leg(args, dev, sync):
+    """The degree-3 7.3M-DoF and degree-2 68M-DoF workloads in the default run:
+    vmults in FP64 and FP32, the degree-3 multigrid solve (and the steady
+    degree-3 attempt), one BDF2 + Newton step at 68M DoFs."""
+    import torch
+
+    out = {}
+    name = "annulus3d_q3_64x16x32"
+    op, mesh, theta, rec = vmult_leg(name, dev, sync)
+    op.close()
+    rec.update(degree3_solve_leg(args, mesh, name, theta, mesh["omega"], dev, sync))
+    rec["steady_attempt"] = steady_degree3_attempt(mesh, name, theta, dev, sync)
+    out[name] = rec
+    torch.cuda.empty_cache()
+    name = "annulus3d_q2_256x32x128"
+    op, mesh, theta, rec = vmult_leg(name, dev, sync, steps=50, warmup=5)
+    rec["transient_step"] = transient_leg(op, mesh, name, theta, dev, sync)
+    op.close()
+    out[name] = rec
+    torch.cuda.empty_cache()
+    return out
 
 
 def timed(fn, sync):
@@ -490,6 +631,10 @@ def main():
 
     if not args.no_batch:
         rec["batch"] = batch_leg(args, dev, sync)
+
+    if not args.no_large and name == "annulus3d_q2_64x8x32":
+        # free the 1.1M-DoF handle's Krylov workspace first
+        rec["large_workloads"] = large_workloads_leg(args, dev, sync)
 
     if args.transient and not mesh.get("steady", 1):
         # two implicit time steps of a spin-up: fluid at rest, a smooth body

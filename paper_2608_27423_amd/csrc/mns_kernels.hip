@@ -1700,11 +1700,10 @@ struct MortarShape {
   static constexpr int NQ = N * NZ;   // mortar points per piece
   static constexpr int NE = DIM + 1;  // value + reference derivatives
   static constexpr int LPF = 4 * NC;  // lanes per face in phase A
-  // LDS row of one mortar point, padded by one value against bank conflicts.
-  // Degree 4 in 3D keeps unpadded rows: its separate mortar kernel sits at the
-  // register limit with several hundred scalar spills, and its padded FP64
-  // build returned wrong values (the fused kernel and FP32 were exact).
-  static constexpr int PQ = NC * NE + ((DIM == 3 && N >= 5) ? 0 : 1);
+  // LDS row of one mortar point, padded by one value against bank conflicts
+  // (every degree; rows hold NC * NE <= 16 values, so index NC * NE - 1 is
+  // the last one a lane writes or reads)
+  static constexpr int PQ = NC * NE + 1;
   static constexpr int PER_FACE = (2 * 2 * NQ * PQ + 2 * NQ * PQ) * (int)sizeof(Real);
   static constexpr int FPB0 = 64 / LPF;
   static constexpr int FPB_LDS = BUDGET / PER_FACE > 0 ? BUDGET / PER_FACE : 1;
