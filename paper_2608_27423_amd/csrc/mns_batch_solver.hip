@@ -6,6 +6,15 @@
 // polynomial with the diagonal of Alg. Alg-diagonal); only the reduction
 // order of the dot products differs.  Vector kernels work on blocks that never
 // straddle two instances, so per-instance scalars are read once per block.
+//
+// The whole solver state lives on the device: per-instance Gram-Schmidt
+// coefficients, Hessenberg columns, Givens rotations, residual estimates and
+// convergence flags, plus the column j shared by the lockstep.  One iteration
+// is therefore a fixed sequence of launches that reads j from the device; it
+// is captured once per call into a HIP graph and replayed, and the host reads
+// the state back once per chunk of iterations.  Instances that have converged
+// are skipped by the Gram-Schmidt kernels and their next basis vectors are
+// zero, so the preconditioner and the Jacobian map them to zero.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +32,7 @@ namespace {
 constexpr int kBT = 256;           // threads per block
 constexpr int kBChunk = kBT * 8;   // vector entries per block
 constexpr int kBK = 32;            // register width of the dot kernels (restart <= 31)
+constexpr int kBP = kBK + 1;       // stride of the rows of partial and per-instance sums
 
 struct BSeg {
   const long long* bstart;  // first block of each instance (count + 1)
@@ -42,106 +52,142 @@ __device__ inline void bseg_range(const BSeg& S, long long b, int& i, long long&
   hi = lo + kBChunk < S.off[a + 1] ? lo + kBChunk : S.off[a + 1];
 }
 
-// per-block sums of K thread values into part[blockIdx.x * K + k]
+// ---------------------------------------------------------------------------
+// Device state (doubles; count instances, restart m, Chebyshev degree deg):
+// part[nblk][kBP] partial sums, hc[count][kBP] first projection (and w . w
+// before it), h2[count][kBP] second projection (and w . w after the first),
+// n3[count] w . w after the optional third pass, cs/sn[count][m],
+// g[count][m + 1], H[count][m + 1][m], y[count][m], sc[count] scale factors,
+// cheb[deg][count][2], inv_theta[count], inst[count][BI_N], misc[BG_MISC].
+// ---------------------------------------------------------------------------
+enum {
+  BG_J = 0,        // column of the next iteration (shared by the lockstep)
+  BG_ALLDONE = 1,  // 1 once every instance met its target or broke down
+  BG_BROKEN = 2,   // 1 after a non-finite norm (power iteration or Arnoldi)
+  BG_WORST = 3,    // max over the unconverged instances of residual estimate / target
+  BG_MISC = 8
+};
+enum {
+  BI_DONE = 0,    // this cycle: residual estimate met the target (or w vanished)
+  BI_TARGET = 1,  // rtol ||b_i||
+  BI_BN = 2,      // ||b_i||
+  BI_ITS = 3,     // iterations taken, all cycles
+  BI_RES = 4,     // residual estimate |g_j| (true residual at a cycle start)
+  BI_INVWN = 5,   // scale of the next basis vector (0 when done)
+  BI_JN = 6,      // columns of this cycle
+  BI_LAM = 7,     // power-iteration estimate of lambda_max
+  BI_N = 8
+};
+
+struct BState {
+  double *part, *hc, *h2, *n3, *cs, *sn, *g, *H, *y, *sc, *cheb, *inv_theta, *inst, *misc;
+  int count, m;
+};
+
+size_t bstate_doubles(long long nblk, int count, int m, int deg) {
+  const size_t c = (size_t)count;
+  return (size_t)nblk * kBP + 2 * c * kBP + c + 2 * c * m + c * (m + 1) + c * (m + 1) * m + c * m + c +
+         (size_t)deg * c * 2 + c + c * BI_N + BG_MISC;
+}
+
+BState bstate_view(double* base, long long nblk, int count, int m, int deg) {
+  BState G;
+  G.count = count;
+  G.m = m;
+  const size_t c = (size_t)count;
+  G.part = base;
+  G.hc = G.part + (size_t)nblk * kBP;
+  G.h2 = G.hc + c * kBP;
+  G.n3 = G.h2 + c * kBP;
+  G.cs = G.n3 + c;
+  G.sn = G.cs + c * m;
+  G.g = G.sn + c * m;
+  G.H = G.g + c * (m + 1);
+  G.y = G.H + c * (m + 1) * m;
+  G.sc = G.y + c * m;
+  G.cheb = G.sc + c;
+  G.inv_theta = G.cheb + (size_t)deg * c * 2;
+  G.inst = G.inv_theta + c;
+  G.misc = G.inst + c * BI_N;  // misc follows inst, so that one copy reads both
+  return G;
+}
+
+__device__ inline double& inst_at(const BState& G, int i, int f) { return G.inst[(size_t)i * BI_N + f]; }
+__device__ inline bool all_done(const BState& G) { return G.misc[BG_ALLDONE] != 0.0; }
+__device__ inline int col_j(const BState& G) { return (int)G.misc[BG_J]; }
+
+// per-block sums of cnt thread values into part[blockIdx.x * kBP + k]
 template <int MAXK>
-__device__ inline void bsum_store(double (&v)[MAXK], int K, double* part) {
+__device__ inline void bsum_store(double (&v)[MAXK], int cnt, double* part) {
   __shared__ double red[kBT / 64][MAXK];
   const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
-    if (k < K) {
+    if (k < cnt) {
       double x = v[k];
       for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
       if (lane == 0) red[wid][k] = x;
     }
   }
   __syncthreads();
-  if ((int)threadIdx.x < K) {
+  if ((int)threadIdx.x < cnt) {
     double t = 0;
     for (int w = 0; w < kBT / 64; ++w) t += red[w][threadIdx.x];
-    part[(long long)blockIdx.x * K + threadIdx.x] = t;
+    part[(long long)blockIdx.x * kBP + threadIdx.x] = t;
   }
 }
 
-// dots of w with V_0 .. V_{K-1} (stride N) and, with self, w . w (entry K)
-__global__ __launch_bounds__(kBT) void k_bdots(BSeg S, const double* __restrict__ V, long long N, int K,
-                                               const double* __restrict__ w, int self, double* __restrict__ part) {
-  int i;
-  long long lo, hi;
-  bseg_range(S, blockIdx.x, i, lo, hi);
-  double acc[kBK];
-#pragma unroll
-  for (int k = 0; k < kBK; ++k) acc[k] = 0;
-  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
-    const double wr = w[r];
-#pragma unroll
-    for (int k = 0; k < kBK; ++k) {
-      if (k < K) acc[k] += V[(long long)k * N + r] * wr;
-      if (self && k == K) acc[k] += wr * wr;
-    }
-  }
-  bsum_store<kBK>(acc, K + self, part);
-}
-
-// out[i * Kp + k] = sum of the partial sums of instance i's blocks (fixed order)
-__global__ __launch_bounds__(kBT) void k_bsum(BSeg S, const double* __restrict__ part, int Kp,
-                                              double* __restrict__ out) {
+// sums over instance i's blocks of part[.][0 .. cnt) in a fixed order, stored
+// by thread 0 into out[0 .. cnt); ends with a barrier, so that shared-memory
+// results are visible to every thread of the block
+__device__ inline void instance_sums(const BSeg& S, const double* part, int i, int cnt, double* out) {
   __shared__ double red[kBT];
-  const int i = blockIdx.x;
   const long long b0 = S.bstart[i], b1 = S.bstart[i + 1];
-  for (int k = 0; k < Kp; ++k) {
+  for (int k = 0; k < cnt; ++k) {
     double t = 0;
-    for (long long b = b0 + threadIdx.x; b < b1; b += kBT) t += part[b * Kp + k];
+    for (long long b = b0 + threadIdx.x; b < b1; b += kBT) t += part[b * kBP + k];
     red[threadIdx.x] = t;
     __syncthreads();
     for (int off = kBT / 2; off > 0; off >>= 1) {
       if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[(long long)i * Kp + k] = red[0];
+    if (threadIdx.x == 0) out[k] = red[0];
     __syncthreads();
   }
 }
 
-// w -= sum_k h[i][k] V_k (h: count x K); with dots, then the dots of the new
-// w with V_k (entries 0..K-1) and w . w (entry K), else w . w only
-__global__ __launch_bounds__(kBT) void k_baxpy(BSeg S, const double* __restrict__ V, long long N, int K,
-                                               const double* __restrict__ h, double* __restrict__ w, int dots,
-                                               double* __restrict__ part) {
+// ---- set-up kernels --------------------------------------------------------
+
+// partial sums of w . w
+__global__ __launch_bounds__(kBT) void k_bnorm(BSeg S, const double* __restrict__ w, double* __restrict__ part) {
   int i;
   long long lo, hi;
   bseg_range(S, blockIdx.x, i, lo, hi);
-  double hh[kBK], acc[kBK];
-#pragma unroll
-  for (int k = 0; k < kBK; ++k) {
-    hh[k] = 0;
-    if (k < K) hh[k] = h[(long long)i * K + k];
-    acc[k] = 0;
-  }
-  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
-    double v[kBK];
-    double x = w[r];
-#pragma unroll
-    for (int k = 0; k < kBK; ++k) {
-      v[k] = 0;
-      if (k < K) v[k] = V[(long long)k * N + r];
-      x -= hh[k] * v[k];
-    }
-    w[r] = x;
-    if (dots) {
-#pragma unroll
-      for (int k = 0; k < kBK; ++k) {
-        if (k < K) acc[k] += v[k] * x;
-        if (k == K) acc[k] += x * x;
-      }
-    } else {
-      acc[0] += x * x;
-    }
-  }
-  bsum_store<kBK>(acc, dots ? K + 1 : 1, part);
+  double acc[1] = {0};
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) acc[0] += w[r] * w[r];
+  bsum_store<1>(acc, 1, part);
 }
 
-// y = s[i] x; x and y may be the same vector
+// ||b_i||, the target rtol ||b_i||, sc = 1 (0 for a zero right-hand side, so
+// that x_i = 0), iteration counts cleared
+__global__ __launch_bounds__(kBT) void k_bgm_init(BSeg S, BState G, double rtol) {
+  const int i = blockIdx.x;
+  __shared__ double s[1];
+  instance_sums(S, G.part, i, 1, s);
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(s[0]);
+    inst_at(G, i, BI_BN) = bn;
+    inst_at(G, i, BI_TARGET) = rtol * bn;
+    inst_at(G, i, BI_ITS) = 0.0;
+    inst_at(G, i, BI_LAM) = 1.0;
+    G.sc[i] = bn > 0 ? 1.0 : 0.0;
+    if (i == 0)
+      for (int k = 0; k < BG_MISC; ++k) G.misc[k] = 0.0;
+  }
+}
+
+// y = sc[i] x; x and y may be the same vector
 __global__ __launch_bounds__(kBT) void k_bscale(BSeg S, const double* x, const double* __restrict__ sc, double* y) {
   int i;
   long long lo, hi;
@@ -150,32 +196,10 @@ __global__ __launch_bounds__(kBT) void k_bscale(BSeg S, const double* x, const d
   for (long long r = lo + threadIdx.x; r < hi; r += kBT) y[r] = a * x[r];
 }
 
-// x += sum_k y[i][k] Z_k (y: count x K)
-__global__ __launch_bounds__(kBT) void k_bupdate(BSeg S, const double* __restrict__ Z, long long N, int K,
-                                                 const double* __restrict__ y, double* __restrict__ x) {
-  int i;
-  long long lo, hi;
-  bseg_range(S, blockIdx.x, i, lo, hi);
-  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
-    double a = x[r];
-    for (int k = 0; k < K; ++k) a += y[(long long)i * K + k] * Z[(long long)k * N + r];
-    x[r] = a;
-  }
-}
-
-// r = b - t, partial ||r||^2
-__global__ __launch_bounds__(kBT) void k_bresid(BSeg S, const double* __restrict__ b, const double* __restrict__ t,
-                                                double* __restrict__ r, double* __restrict__ part) {
-  int i;
-  long long lo, hi;
-  bseg_range(S, blockIdx.x, i, lo, hi);
-  double acc[1] = {0};
-  for (long long q = lo + threadIdx.x; q < hi; q += kBT) {
-    const double v = b[q] - t[q];
-    r[q] = v;
-    acc[0] += v * v;
-  }
-  bsum_store<1>(acc, 1, part);
+// start of the power iteration: sc = 1 / sqrt(n_i)
+__global__ void k_bpower_start(BSeg S, BState G) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S.count; i += gridDim.x * blockDim.x)
+    G.sc[i] = 1.0 / sqrt((double)(S.off[i + 1] - S.off[i]));
 }
 
 // y = D^-1 t (power iteration), partial ||y||^2
@@ -191,6 +215,39 @@ __global__ __launch_bounds__(kBT) void k_bpower(BSeg S, const double* __restrict
     acc[0] += v * v;
   }
   bsum_store<1>(acc, 1, part);
+}
+
+// lambda_i = ||D^-1 J v_i|| and sc = 1 / lambda_i; a breakdown sets BG_BROKEN
+__global__ __launch_bounds__(kBT) void k_bpower_norm(BSeg S, BState G) {
+  const int i = blockIdx.x;
+  __shared__ double s[1];
+  instance_sums(S, G.part, i, 1, s);
+  if (threadIdx.x == 0) {
+    const double lam = sqrt(s[0]);
+    const bool ok = lam > 0 && isfinite(lam);
+    inst_at(G, i, BI_LAM) = lam;
+    G.sc[i] = ok ? 1.0 / lam : 0.0;
+    if (!ok) G.misc[BG_BROKEN] = 1.0;
+  }
+}
+
+// Chebyshev scalars per instance from lambda_i: start 1/theta, step k (c1, c2)
+// (the recurrence of the single-instance polynomial; not contracted)
+__global__ void k_bcheb_coef(BState G, int deg, double lambda_factor, double range) {
+#pragma clang fp contract(off)
+  const int count = G.count;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const double beta = inst_at(G, i, BI_LAM) * lambda_factor, alpha = beta / range;
+    const double theta = 0.5 * (beta + alpha), delta = 0.5 * (beta - alpha), sigma = theta / delta;
+    G.inv_theta[i] = 1.0 / theta;
+    double rho = 1.0 / sigma;
+    for (int k = 0; k < deg; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      G.cheb[((size_t)k * count + i) * 2] = rn * rho;
+      G.cheb[((size_t)k * count + i) * 2 + 1] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
 }
 
 // Chebyshev polynomial of D^-1 J with per-instance scalars: start
@@ -229,17 +286,335 @@ __global__ __launch_bounds__(kBT) void k_bcheb_step(BSeg S, Real* __restrict__ r
   }
 }
 
+// ---- one cycle -------------------------------------------------------------
+
+// r = b - t, partial ||r||^2
+__global__ __launch_bounds__(kBT) void k_bresid(BSeg S, const double* __restrict__ b, const double* __restrict__ t,
+                                                double* __restrict__ r, double* __restrict__ part) {
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  double acc[1] = {0};
+  for (long long q = lo + threadIdx.x; q < hi; q += kBT) {
+    const double v = b[q] - t[q];
+    r[q] = v;
+    acc[0] += v * v;
+  }
+  bsum_store<1>(acc, 1, part);
+}
+
+// per instance at a cycle start: true residual norm, convergence, g = (||r||, 0, ...)
+__global__ __launch_bounds__(kBT) void k_bgm_cycle(BSeg S, BState G) {
+  const int i = blockIdx.x;
+  __shared__ double s[1];
+  instance_sums(S, G.part, i, 1, s);
+  const double rn = sqrt(s[0]);
+  const bool done = rn <= inst_at(G, i, BI_TARGET);
+  double* gi = G.g + (size_t)i * (G.m + 1);
+  for (int k = threadIdx.x; k <= G.m; k += kBT) gi[k] = (k == 0 && !done) ? rn : 0.0;
+  if (threadIdx.x == 0) {
+    inst_at(G, i, BI_RES) = rn;
+    inst_at(G, i, BI_DONE) = done ? 1.0 : 0.0;
+    inst_at(G, i, BI_JN) = 0.0;
+    inst_at(G, i, BI_INVWN) = done ? 0.0 : 1.0 / rn;
+  }
+}
+
+// the lockstep's flags from the per-instance ones: j = 0 at a cycle start
+// (start = 1), every instance done, the worst ratio of estimate to target
+__global__ __launch_bounds__(kBT) void k_bgm_flags(BState G, int start) {
+  __shared__ double worst[kBT];
+  int active = 0;
+  double wr = 0.0;
+  for (int i = threadIdx.x; i < G.count; i += kBT)
+    if (inst_at(G, i, BI_DONE) == 0.0) {
+      active = 1;
+      wr = fmax(wr, inst_at(G, i, BI_RES) / fmax(inst_at(G, i, BI_TARGET), 1e-300));
+    }
+  worst[threadIdx.x] = wr;
+  const int any = __syncthreads_or(active);
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    for (int t = 0; t < kBT; ++t) w = fmax(w, worst[t]);
+    if (start) G.misc[BG_J] = 0.0;
+    G.misc[BG_WORST] = w;
+    G.misc[BG_ALLDONE] = (!any || G.misc[BG_BROKEN] != 0.0) ? 1.0 : 0.0;
+  }
+}
+
+// next basis vector V_j = inst.invwn * w (j already advanced; zero for done
+// instances, so that the following preconditioner and Jacobian give zero)
+__global__ __launch_bounds__(kBT) void k_bgm_next(BSeg S, BState G, double* __restrict__ V, long long N,
+                                                  const double* __restrict__ w) {
+  if (all_done(G)) return;
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  const double a = inst_at(G, i, BI_INVWN);
+  double* vj = V + (long long)col_j(G) * N;
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) vj[r] = a != 0.0 ? a * w[r] : 0.0;
+}
+
+// preconditioner input: V_j (cast to its precision) into a fixed buffer
+template <typename To>
+__global__ __launch_bounds__(kBT) void k_bgm_in(BSeg S, BState G, const double* __restrict__ V, long long N,
+                                                To* __restrict__ dst) {
+  if (all_done(G)) return;
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  const double* vj = V + (long long)col_j(G) * N;
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) dst[r] = (To)vj[r];
+}
+
+// preconditioner output -> Z_j and the fixed FP64 input zbuf of the Jacobian
+template <typename From>
+__global__ __launch_bounds__(kBT) void k_bgm_out(BSeg S, BState G, const From* __restrict__ src, long long N,
+                                                 double* __restrict__ Z, double* __restrict__ zbuf) {
+  if (all_done(G)) return;
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  double* zj = Z + (long long)col_j(G) * N;
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+    const double z = (double)src[r];
+    zj[r] = z;
+    zbuf[r] = z;
+  }
+}
+
+// partial dots of w with V_0 .. V_{K-1} and w . w (entry K), K = j + 1
+__global__ __launch_bounds__(kBT) void k_bgm_dots(BSeg S, BState G, const double* __restrict__ V, long long N,
+                                                  const double* __restrict__ w) {
+  if (all_done(G)) return;
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  if (inst_at(G, i, BI_DONE) != 0.0) return;
+  const int K = col_j(G) + 1;
+  double acc[kBK];
+#pragma unroll
+  for (int k = 0; k < kBK; ++k) acc[k] = 0;
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+    const double wr = w[r];
+#pragma unroll
+    for (int k = 0; k < kBK; ++k) {
+      if (k < K) acc[k] += V[(long long)k * N + r] * wr;
+      if (k == K) acc[k] += wr * wr;
+    }
+  }
+  bsum_store<kBK>(acc, K + 1, G.part);
+}
+
+// w -= sum_k hc[i][k] V_k, then partial dots of the new w with V_k and w . w
+__global__ __launch_bounds__(kBT) void k_bgm_axpy_dots(BSeg S, BState G, const double* __restrict__ V, long long N,
+                                                       double* __restrict__ w) {
+  if (all_done(G)) return;
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  if (inst_at(G, i, BI_DONE) != 0.0) return;
+  const int K = col_j(G) + 1;
+  const double* hrow = G.hc + (size_t)i * kBP;
+  double hh[kBK], acc[kBK];
+#pragma unroll
+  for (int k = 0; k < kBK; ++k) {
+    hh[k] = 0;
+    if (k < K) hh[k] = hrow[k];
+    acc[k] = 0;
+  }
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+    double v[kBK];
+    double x = w[r];
+#pragma unroll
+    for (int k = 0; k < kBK; ++k) {
+      v[k] = 0;
+      if (k < K) v[k] = V[(long long)k * N + r];
+      x -= hh[k] * v[k];
+    }
+    w[r] = x;
+#pragma unroll
+    for (int k = 0; k < kBK; ++k) {
+      if (k < K) acc[k] += v[k] * x;
+      if (k == K) acc[k] += x * x;
+    }
+  }
+  bsum_store<kBK>(acc, K + 1, G.part);
+}
+
+// reorthogonalization (DGKS) where the projected norm dropped below 0.7 of the
+// norm before the projection: w -= sum_k h2[i][k] V_k, partial ||w||^2
+__device__ inline bool reorth(const BState& G, int i, int K) {
+  return sqrt(G.h2[(size_t)i * kBP + K]) < 0.7 * sqrt(G.hc[(size_t)i * kBP + K]);
+}
+
+__global__ __launch_bounds__(kBT) void k_bgm_reorth(BSeg S, BState G, const double* __restrict__ V, long long N,
+                                                    double* __restrict__ w) {
+  if (all_done(G)) return;
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  const int K = col_j(G) + 1;
+  if (inst_at(G, i, BI_DONE) != 0.0 || !reorth(G, i, K)) return;
+  const double* hrow = G.h2 + (size_t)i * kBP;
+  double hh[kBK];
+#pragma unroll
+  for (int k = 0; k < kBK; ++k) {
+    hh[k] = 0;
+    if (k < K) hh[k] = hrow[k];
+  }
+  double acc[1] = {0};
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+    double x = w[r];
+#pragma unroll
+    for (int k = 0; k < kBK; ++k)
+      if (k < K) x -= hh[k] * V[(long long)k * N + r];
+    w[r] = x;
+    acc[0] += x * x;
+  }
+  bsum_store<1>(acc, 1, G.part);
+}
+
+// per-instance sums of the partial sums (block i = instance i): which 0:
+// hc[i][0 .. K], 1: h2[i][0 .. K], 2: n3[i] (only where the third pass ran)
+__global__ __launch_bounds__(kBT) void k_bgm_reduce(BSeg S, BState G, int which) {
+  if (all_done(G)) return;
+  const int i = blockIdx.x;
+  if (inst_at(G, i, BI_DONE) != 0.0) return;
+  const int K = col_j(G) + 1;
+  if (which == 2 && !reorth(G, i, K)) return;
+  double* out = which == 0 ? G.hc + (size_t)i * kBP : which == 1 ? G.h2 + (size_t)i * kBP : G.n3 + i;
+  instance_sums(S, G.part, i, which == 2 ? 1 : K + 1, out);
+}
+
+// Hessenberg column, Givens rotations and residual estimate of column j for
+// every unconverged instance (one thread each; products not contracted, as
+// in the single-instance solver), then the lockstep advances j
+__global__ __launch_bounds__(kBT) void k_bgm_givens(BState G) {
+#pragma clang fp contract(off)
+  if (all_done(G)) return;
+  const int j = col_j(G), K = j + 1, m = G.m;
+  int broken = 0;
+  for (int i = threadIdx.x; i < G.count; i += kBT) {
+    if (inst_at(G, i, BI_DONE) != 0.0) continue;
+    double* hcol = G.hc + (size_t)i * kBP;
+    const double* h2 = G.h2 + (size_t)i * kBP;
+    double wn;
+    if (reorth(G, i, K)) {
+      wn = sqrt(G.n3[i]);
+      for (int k = 0; k < K; ++k) hcol[k] += h2[k];
+    } else {
+      wn = sqrt(h2[K]);
+    }
+    hcol[K] = wn;
+    if (!isfinite(wn)) {
+      broken = 1;
+      inst_at(G, i, BI_DONE) = 1.0;
+      inst_at(G, i, BI_INVWN) = 0.0;
+      continue;
+    }
+    double* cs = G.cs + (size_t)i * m;
+    double* sn = G.sn + (size_t)i * m;
+    double* g = G.g + (size_t)i * (m + 1);
+    for (int k = 0; k < j; ++k) {
+      const double a = cs[k] * hcol[k] + sn[k] * hcol[k + 1];
+      const double b = -sn[k] * hcol[k] + cs[k] * hcol[k + 1];
+      hcol[k] = a;
+      hcol[k + 1] = b;
+    }
+    const double den = hypot(hcol[j], hcol[j + 1]);
+    cs[j] = den > 0 ? hcol[j] / den : 1.0;
+    sn[j] = den > 0 ? hcol[j + 1] / den : 0.0;
+    hcol[j] = den;
+    hcol[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    double* H = G.H + (size_t)i * (m + 1) * m;
+    for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = hcol[k];
+    const double res = fabs(g[j + 1]);
+    const bool done = res <= inst_at(G, i, BI_TARGET) || wn == 0;
+    inst_at(G, i, BI_JN) = (double)(j + 1);
+    inst_at(G, i, BI_ITS) += 1.0;
+    inst_at(G, i, BI_RES) = res;
+    inst_at(G, i, BI_DONE) = done ? 1.0 : 0.0;
+    inst_at(G, i, BI_INVWN) = done ? 0.0 : 1.0 / wn;
+  }
+  __shared__ double worst[kBT];
+  int active = 0;
+  double wr = 0.0;
+  for (int i = threadIdx.x; i < G.count; i += kBT)
+    if (inst_at(G, i, BI_DONE) == 0.0) {
+      active = 1;
+      wr = fmax(wr, inst_at(G, i, BI_RES) / fmax(inst_at(G, i, BI_TARGET), 1e-300));
+    }
+  worst[threadIdx.x] = wr;
+  const int any = __syncthreads_or(active);
+  const int brk = __syncthreads_or(broken);
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    for (int t = 0; t < kBT; ++t) w = fmax(w, worst[t]);
+    G.misc[BG_WORST] = w;
+    G.misc[BG_J] = (double)(j + 1);
+    if (brk) G.misc[BG_BROKEN] = 1.0;
+    if (!any || brk) G.misc[BG_ALLDONE] = 1.0;
+  }
+}
+
+// y_i = H_i^-1 g_i (upper triangular, JN_i columns), one thread per instance
+__global__ void k_bgm_backsub(BState G) {
+#pragma clang fp contract(off)
+  const int m = G.m;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < G.count; i += gridDim.x * blockDim.x) {
+    const int jn = (int)inst_at(G, i, BI_JN);
+    const double* H = G.H + (size_t)i * (m + 1) * m;
+    const double* g = G.g + (size_t)i * (m + 1);
+    double* y = G.y + (size_t)i * m;
+    for (int a = jn - 1; a >= 0; --a) {
+      double sum = g[a];
+      for (int k = a + 1; k < jn; ++k) sum -= H[(size_t)a * m + k] * y[k];
+      const double d = H[(size_t)a * m + a];
+      y[a] = d != 0 ? sum / d : 0.0;
+    }
+  }
+}
+
+// x_i += sum_{k < JN_i} y_i[k] Z_k
+__global__ __launch_bounds__(kBT) void k_bgm_update(BSeg S, BState G, const double* __restrict__ Z, long long N,
+                                                    double* __restrict__ x) {
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  const int jn = (int)inst_at(G, i, BI_JN);
+  const double* y = G.y + (size_t)i * G.m;
+  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+    double a = x[r];
+    for (int k = 0; k < jn; ++k) a += y[k] * Z[(long long)k * N + r];
+    x[r] = a;
+  }
+}
+
+// final true residual norm per instance into inst.res
+__global__ __launch_bounds__(kBT) void k_bgm_final(BSeg S, BState G) {
+  const int i = blockIdx.x;
+  __shared__ double s[1];
+  instance_sums(S, G.part, i, 1, s);
+  if (threadIdx.x == 0) inst_at(G, i, BI_RES) = sqrt(s[0]);
+}
+
 struct BatchSolver {
   mns_batch* B;
   hipStream_t s;
   int count, m;
   long long N, nblk;
+  unsigned nb;
   BSeg S;
-  double *V, *Z, *w, *r, *t, *diag64, *cb, *cx, *cr, *cd, *ct;
+  BState G;
+  const mns_solve_opts* o;
+  double *V, *Z, *w, *r, *t, *diag64, *cb, *cr, *cd, *cx, *ct;
   float *b32, *x32, *r32, *d32, *t32, *diag32;
-  double *part, *out, *coef;  // device small buffers
-  double *h_out, *h_coef;     // pinned mirrors
   int vm64 = 0, vm32 = 0;
+  int it_vm64 = 0, it_vm32 = 0;  // Jacobian applications of one iteration
+  hipGraphExec_t gexec = nullptr;
 
   int fail(int code, const std::string& msg) {
     B->err = msg;
@@ -249,35 +624,125 @@ struct BatchSolver {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MNS_OK : fail(MNS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
   }
-  // per-instance sums (count x Kp) of the last partial sums -> host
-  int sums(int Kp, std::vector<double>& host) {
-    hipLaunchKernelGGL(k_bsum, dim3(count), dim3(kBT), 0, s, S, part, Kp, out);
-    hipError_t e = hipMemcpyAsync(h_out, out, (size_t)count * Kp * sizeof(double), hipMemcpyDeviceToHost, s);
+  int jac64(const double* src, double* dst, hipStream_t st) {
+    ++vm64;
+    return launch_batch_jacobian<double>(B, src, dst, st);
+  }
+  int jac32(const float* src, float* dst, hipStream_t st) {
+    ++vm32;
+    return launch_batch_jacobian<float>(B, src, dst, st);
+  }
+  // inst and misc -> host (one synchronization)
+  int read_state() {
+    const size_t cnt = (size_t)count * BI_N + BG_MISC;
+    hipError_t e = hipMemcpyAsync(B->h_small, G.inst, cnt * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return fail(MNS_ERR_HIP, std::string("batch readback: ") + hipGetErrorString(e));
-    host.assign(h_out, h_out + (size_t)count * Kp);
+    return e == hipSuccess ? MNS_OK : fail(MNS_ERR_HIP, std::string("batch readback: ") + hipGetErrorString(e));
+  }
+  double inst(int i, int f) const { return B->h_small[(size_t)i * BI_N + f]; }
+  double misc(int f) const { return B->h_small[(size_t)count * BI_N + f]; }
+
+  // the preconditioner between its fixed buffers (precond -1: copy)
+  int precondition(hipStream_t st) {
+    const int deg = o->cheb_degree;
+    int rc;
+    if (o->precond == -1) {
+      hipLaunchKernelGGL(k_bgm_in<double>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, cx);
+      return check("batch copy");
+    }
+    if (o->precond == MNS_F64) {
+      hipLaunchKernelGGL(k_bgm_in<double>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, cb);
+      hipLaunchKernelGGL(k_bcheb_init<double>, dim3(nb), dim3(kBT), 0, st, S, (const double*)cb,
+                         (const double*)diag64, (const double*)G.inv_theta, cr, cd, cx);
+      for (int k = 0; k < deg; ++k) {
+        if ((rc = jac64(cd, ct, st))) return rc;
+        hipLaunchKernelGGL(k_bcheb_step<double>, dim3(nb), dim3(kBT), 0, st, S, cr, (const double*)ct,
+                           (const double*)diag64, (const double*)(G.cheb + (size_t)k * count * 2), cd, cx);
+      }
+      return check("batch Chebyshev");
+    }
+    hipLaunchKernelGGL(k_bgm_in<float>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, b32);
+    hipLaunchKernelGGL(k_bcheb_init<float>, dim3(nb), dim3(kBT), 0, st, S, (const float*)b32, (const float*)diag32,
+                       (const double*)G.inv_theta, r32, d32, x32);
+    for (int k = 0; k < deg; ++k) {
+      if ((rc = jac32(d32, t32, st))) return rc;
+      hipLaunchKernelGGL(k_bcheb_step<float>, dim3(nb), dim3(kBT), 0, st, S, r32, (const float*)t32,
+                         (const float*)diag32, (const double*)(G.cheb + (size_t)k * count * 2), d32, x32);
+    }
+    return check("batch Chebyshev");
+  }
+
+  // One lockstep iteration as a fixed sequence of launches (j is read from
+  // the device): preconditioner, FP64 Jacobian, Gram-Schmidt with the
+  // optional reorthogonalization, Givens, next basis vector.
+  int iteration(hipStream_t st) {
+    const int v64 = vm64, v32 = vm32;
+    int rc = precondition(st);
+    if (rc) return rc;
+    double* zbuf = r;  // free during a cycle: the residual is read into V_0 at its start
+    if (o->precond == MNS_F32)
+      hipLaunchKernelGGL(k_bgm_out<float>, dim3(nb), dim3(kBT), 0, st, S, G, (const float*)x32, N, Z, zbuf);
+    else
+      hipLaunchKernelGGL(k_bgm_out<double>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)cx, N, Z, zbuf);
+    if ((rc = jac64(zbuf, w, st))) return rc;
+    hipLaunchKernelGGL(k_bgm_dots, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, (const double*)w);
+    hipLaunchKernelGGL(k_bgm_reduce, dim3(count), dim3(kBT), 0, st, S, G, 0);
+    hipLaunchKernelGGL(k_bgm_axpy_dots, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, w);
+    hipLaunchKernelGGL(k_bgm_reduce, dim3(count), dim3(kBT), 0, st, S, G, 1);
+    hipLaunchKernelGGL(k_bgm_reorth, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, w);
+    hipLaunchKernelGGL(k_bgm_reduce, dim3(count), dim3(kBT), 0, st, S, G, 2);
+    hipLaunchKernelGGL(k_bgm_givens, dim3(1), dim3(kBT), 0, st, G);
+    hipLaunchKernelGGL(k_bgm_next, dim3(nb), dim3(kBT), 0, st, S, G, V, N, (const double*)w);
+    if ((rc = check("batch FGMRES iteration"))) return rc;
+    it_vm64 = vm64 - v64;
+    it_vm32 = vm32 - v32;
+    vm64 = v64;  // counted by the caller per iteration that did work
+    vm32 = v32;
     return MNS_OK;
   }
-  // host values (count x K) -> coef on the device; the staging buffer is
-  // reused only after a later synchronization
-  int upload(const std::vector<double>& v) {
-    std::memcpy(h_coef, v.data(), v.size() * sizeof(double));
-    hipError_t e = hipMemcpyAsync(coef, h_coef, v.size() * sizeof(double), hipMemcpyHostToDevice, s);
-    return e == hipSuccess ? MNS_OK : fail(MNS_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+
+  int capture() {
+    if (!B->cap && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(MNS_ERR_HIP, "batch capture stream");
+    hipError_t e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(MNS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
+    const int rc = iteration(B->cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(B->cap, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(MNS_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      return fail(MNS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return MNS_OK;
   }
-  int jac64(const double* src, double* dst) {
-    ++vm64;
-    return launch_batch_jacobian<double>(B, src, dst, s);
+
+  int iterations(int n) {
+    int rc;
+    if (o->use_graph) {
+      if (!gexec && (rc = capture())) return rc;
+      for (int k = 0; k < n; ++k) {
+        const hipError_t e = hipGraphLaunch(gexec, s);
+        if (e != hipSuccess) return fail(MNS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+      }
+      return MNS_OK;
+    }
+    for (int k = 0; k < n; ++k)
+      if ((rc = iteration(s))) return rc;
+    return MNS_OK;
   }
-  int jac32(const float* src, float* dst) {
-    ++vm32;
-    return launch_batch_jacobian<float>(B, src, dst, s);
-  }
-  int scale(const double* x, const std::vector<double>& sc, double* y) {
-    int rc = upload(sc);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_bscale, dim3((unsigned)nblk), dim3(kBT), 0, s, S, x, coef, y);
-    return check("batch scale");
+
+  ~BatchSolver() {
+    if (gexec) {
+      (void)hipStreamSynchronize(s);
+      (void)hipGraphExecDestroy(gexec);
+    }
   }
 };
 
@@ -289,12 +754,15 @@ void batch_solver_free(mns_batch* b) {
   if (b->ws32) (void)hipFree(b->ws32);
   if (b->d_small) (void)hipFree(b->d_small);
   if (b->h_small) (void)hipHostFree(b->h_small);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   b->d_seg = nullptr;
   b->ws = nullptr;
   b->ws32 = nullptr;
   b->d_small = nullptr;
   b->h_small = nullptr;
+  b->cap = nullptr;
   b->ws_m = 0;
+  b->small_doubles = 0;
 }
 
 int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* reps,
@@ -302,8 +770,9 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   const auto t0 = std::chrono::steady_clock::now();
   const int count = (int)B->hs.size();
   const long long N = B->ndofs;
-  const int m = o->restart;
+  const int m = o->restart, deg = o->cheb_degree;
   hipError_t e;
+  if (m < 1 || m > kBK - 1) return MNS_ERR_INVALID_ARG;
   // segmentation of the concatenated vectors into blocks of one instance
   if (!B->d_seg) {
     std::vector<long long> seg(2 * (size_t)(count + 1), 0);
@@ -319,13 +788,22 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
       B->err = std::string("batch segments: ") + hipGetErrorString(e);
       return MNS_ERR_HIP;
     }
-    const size_t small = (size_t)B->nvblk * (kBK + 1) + (size_t)count * (kBK + 1) * 2 + 64 * (size_t)count;
-    if ((e = hipMalloc((void**)&B->d_small, small * sizeof(double))) != hipSuccess ||
-        (e = hipHostMalloc((void**)&B->h_small, (size_t)count * (kBK + 1) * 2 * sizeof(double) + 64 * (size_t)count *
-                                                    sizeof(double), hipHostMallocDefault)) != hipSuccess) {
-      B->err = std::string("batch buffers: ") + hipGetErrorString(e);
+  }
+  // solver state: sized for the largest restart and degree seen so far
+  const size_t need = bstate_doubles(B->nvblk, count, m, deg);
+  if (B->small_doubles < need) {
+    if (B->d_small) (void)hipFree(B->d_small);
+    if (B->h_small) (void)hipHostFree(B->h_small);
+    B->d_small = nullptr;
+    B->h_small = nullptr;
+    B->small_doubles = 0;
+    if ((e = hipMalloc((void**)&B->d_small, need * sizeof(double))) != hipSuccess ||
+        (e = hipHostMalloc((void**)&B->h_small, ((size_t)count * BI_N + BG_MISC) * sizeof(double),
+                           hipHostMallocDefault)) != hipSuccess) {
+      B->err = std::string("batch solver state: ") + hipGetErrorString(e);
       return MNS_ERR_HIP;
     }
+    B->small_doubles = need;
   }
   if (B->ws_m < m) {
     if (B->ws) (void)hipFree(B->ws);
@@ -343,11 +821,14 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   BatchSolver W;
   W.B = B;
   W.s = s;
+  W.o = o;
   W.count = count;
   W.m = m;
   W.N = N;
   W.nblk = B->nvblk;
+  W.nb = (unsigned)B->nvblk;
   W.S = BSeg{B->d_seg, B->d_seg + count + 1, count};
+  W.G = bstate_view(B->d_small, B->nvblk, count, m, deg);
   W.V = B->ws;
   W.Z = W.V + (size_t)(m + 1) * N;
   W.w = W.Z + (size_t)m * N;
@@ -365,235 +846,106 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   W.d32 = W.r32 + N;
   W.t32 = W.d32 + N;
   W.diag32 = W.t32 + N;
-  W.part = B->d_small;
-  W.out = W.part + (size_t)W.nblk * (kBK + 1);
-  W.coef = W.out + (size_t)count * (kBK + 1);
-  W.h_out = B->h_small;
-  W.h_coef = W.h_out + (size_t)count * (kBK + 1);
-  const unsigned nb = (unsigned)W.nblk;
+  const unsigned nb = W.nb;
+  const BSeg& S = W.S;
+  const BState& G = W.G;
   int rc;
 
-  // diagonals of every instance (Alg. Alg-diagonal), FP64 and FP32
-  for (int i = 0; i < count; ++i)
-    if ((rc = launch_diagonal<double>(B->hs[i], W.diag64 + B->offsets[i], s)))
-      return W.fail(rc, "batch diagonal: " + B->hs[i]->err);
-  if ((rc = launch_cast_f64_f32(W.diag64, W.diag32, N, s))) return W.fail(rc, "cast");
+  // ||b_i||, targets, x_i = 0 where b_i = 0
+  hipLaunchKernelGGL(k_bnorm, dim3(nb), dim3(kBT), 0, s, S, rhs, G.part);
+  hipLaunchKernelGGL(k_bgm_init, dim3(count), dim3(kBT), 0, s, S, G, o->rtol);
+  hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)x, (const double*)G.sc, x);
+  if ((rc = W.check("batch set-up"))) return rc;
 
-  std::vector<double> sums, sc(count);
-  // spectra: power iteration of D^-1 J per instance from the constant vector
-  std::vector<double> lam(count, 1.0);
+  // diagonals of every instance (Alg. Alg-diagonal), FP64 and FP32: each
+  // handle's cached diagonal, computed when its linearization changed
+  for (int i = 0; i < count; ++i) {
+    mns_handle* h = B->hs[i];
+    if ((rc = cached_diagonal(h, s))) return W.fail(rc, "batch diagonal: " + h->err);
+    if ((e = hipMemcpyAsync(W.diag64 + B->offsets[i], h->d_diag64, (size_t)h->ndofs * sizeof(double),
+                            hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(W.diag32 + B->offsets[i], h->d_diag32, (size_t)h->ndofs * sizeof(float),
+                            hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return W.fail(MNS_ERR_HIP, std::string("batch diagonal copy: ") + hipGetErrorString(e));
+  }
+
+  // lambda_max of D^-1 J per instance by power iteration from the constant
+  // vector, then the Chebyshev scalars, all on the device
   if (o->precond != -1) {
     if ((rc = launch_fill<double>(W.t, 1.0, N, s))) return W.fail(rc, "fill");
-    for (int i = 0; i < count; ++i) sc[i] = 1.0 / std::sqrt((double)B->hs[i]->ndofs);
-    if ((rc = W.scale(W.t, sc, W.cb))) return rc;
+    hipLaunchKernelGGL(k_bpower_start, dim3(1), dim3(kBT), 0, s, S, G);
+    hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.t, (const double*)G.sc, W.cb);
     for (int it = 0; it < o->eig_iters; ++it) {
-      if ((rc = W.jac64(W.cb, W.t))) return rc;
-      hipLaunchKernelGGL(k_bpower, dim3(nb), dim3(kBT), 0, s, W.S, W.t, W.diag64, W.cb, W.part);
-      if ((rc = W.check("power step")) || (rc = W.sums(1, sums))) return rc;
-      for (int i = 0; i < count; ++i) {
-        lam[i] = std::sqrt(sums[i]);
-        if (!(lam[i] > 0) || !std::isfinite(lam[i])) return W.fail(MNS_ERR_HIP, "batch power iteration broke down");
-        sc[i] = 1.0 / lam[i];
-      }
-      if ((rc = W.scale(W.cb, sc, W.cb))) return rc;
+      if ((rc = W.jac64(W.cb, W.t, s))) return rc;
+      hipLaunchKernelGGL(k_bpower, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.t, (const double*)W.diag64, W.cb,
+                         G.part);
+      hipLaunchKernelGGL(k_bpower_norm, dim3(count), dim3(kBT), 0, s, S, G);
+      hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.cb, (const double*)G.sc, W.cb);
     }
+    hipLaunchKernelGGL(k_bcheb_coef, dim3(1), dim3(kBT), 0, s, G, deg, o->cheb_lambda_factor, o->cheb_range);
+    if ((rc = W.check("batch power iteration"))) return rc;
   }
-  // Chebyshev scalars per instance: start 1/theta, step k (c1, c2)
-  const int deg = o->cheb_degree;
-  std::vector<double> inv_theta(count), cheb((size_t)deg * count * 2);
-  for (int i = 0; i < count; ++i) {
-    const double beta = lam[i] * o->cheb_lambda_factor, alpha = beta / o->cheb_range;
-    const double theta = 0.5 * (beta + alpha), delta = 0.5 * (beta - alpha), sigma = theta / delta;
-    inv_theta[i] = 1.0 / theta;
-    double rho = 1.0 / sigma;
-    for (int k = 0; k < deg; ++k) {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      cheb[((size_t)k * count + i) * 2] = rn * rho;
-      cheb[((size_t)k * count + i) * 2 + 1] = 2.0 * rn / delta;
-      rho = rn;
-    }
-  }
-  // the Chebyshev scalars stay on the device after the coefficient area
-  double* d_cheb = W.coef + (size_t)count * kBK;
-  double* d_inv_theta = d_cheb + (size_t)deg * count * 2;
-  {
-    std::vector<double> all(cheb);
-    all.insert(all.end(), inv_theta.begin(), inv_theta.end());
-    if (2 * deg + 1 > 65) return W.fail(MNS_ERR_INVALID_ARG, "Chebyshev degree above 32 in the batched solver");
-    if ((e = hipMemcpyAsync(d_cheb, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice, s)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-      return W.fail(MNS_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
-  }
-  // z = M^-1 v for every instance
-  auto precondition = [&](const double* v, double* z) -> int {
-    if (o->precond == -1) {
-      const hipError_t e2 = hipMemcpyAsync(z, v, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s);
-      return e2 == hipSuccess ? MNS_OK : W.fail(MNS_ERR_HIP, "batch copy");
-    }
-    int rc2;
-    if (o->precond == MNS_F64) {
-      hipLaunchKernelGGL(k_bcheb_init<double>, dim3(nb), dim3(kBT), 0, s, W.S, v, W.diag64, d_inv_theta, W.cr, W.cd,
-                         z);
-      for (int k = 0; k < deg; ++k) {
-        if ((rc2 = W.jac64(W.cd, W.ct))) return rc2;
-        hipLaunchKernelGGL(k_bcheb_step<double>, dim3(nb), dim3(kBT), 0, s, W.S, W.cr, W.ct, W.diag64,
-                           d_cheb + (size_t)k * count * 2, W.cd, z);
-      }
-      return W.check("batch Chebyshev");
-    }
-    if ((rc2 = launch_cast_f64_f32(v, W.b32, N, s))) return W.fail(rc2, "cast");
-    hipLaunchKernelGGL(k_bcheb_init<float>, dim3(nb), dim3(kBT), 0, s, W.S, W.b32, W.diag32, d_inv_theta, W.r32, W.d32,
-                       W.x32);
-    for (int k = 0; k < deg; ++k) {
-      if ((rc2 = W.jac32(W.d32, W.t32))) return rc2;
-      hipLaunchKernelGGL(k_bcheb_step<float>, dim3(nb), dim3(kBT), 0, s, W.S, W.r32, W.t32, W.diag32,
-                         d_cheb + (size_t)k * count * 2, W.d32, W.x32);
-    }
-    if ((rc2 = launch_cast_f32_f64(W.x32, z, N, s))) return W.fail(rc2, "cast");
-    return W.check("batch Chebyshev");
-  };
 
-  // ||b_i||
-  hipLaunchKernelGGL(k_bdots, dim3(nb), dim3(kBT), 0, s, W.S, rhs, N, 1, rhs, 0, W.part);
-  if ((rc = W.check("batch norm")) || (rc = W.sums(1, sums))) return rc;
-  std::vector<double> bn(count), target(count), rn(count, 0.0);
-  std::vector<int> its(count, 0), conv(count, 0);
-  for (int i = 0; i < count; ++i) {
-    bn[i] = std::sqrt(sums[i]);
-    target[i] = o->rtol * bn[i];
-    sc[i] = bn[i] > 0 ? 1.0 : 0.0;  // zero right-hand side: x = 0
-  }
-  if ((rc = W.scale(x, sc, x))) return rc;
-
-  std::vector<double> H((size_t)count * (m + 1) * m), cs((size_t)count * m), sn((size_t)count * m),
-      g((size_t)count * (m + 1)), hc((size_t)count * (m + 1)), y;
   int total = 0;
   while (total < o->maxit) {
     // true residuals; converged instances stop
-    if ((rc = W.jac64(x, W.t))) return rc;
-    hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, W.S, rhs, W.t, W.r, W.part);
-    if ((rc = W.check("batch residual")) || (rc = W.sums(1, sums))) return rc;
-    bool any = false;
-    std::vector<int> active(count, 0), done(count, 1), jn(count, 0);
-    for (int i = 0; i < count; ++i) {
-      rn[i] = std::sqrt(sums[i]);
-      conv[i] = rn[i] <= target[i];
-      active[i] = !conv[i];
-      done[i] = conv[i];
-      any = any || active[i];
-      sc[i] = active[i] ? 1.0 / rn[i] : 0.0;
+    if ((rc = W.jac64(x, W.t, s))) return rc;
+    hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, S, rhs, (const double*)W.t, W.r, G.part);
+    hipLaunchKernelGGL(k_bgm_cycle, dim3(count), dim3(kBT), 0, s, S, G);
+    hipLaunchKernelGGL(k_bgm_flags, dim3(1), dim3(kBT), 0, s, G, 1);
+    hipLaunchKernelGGL(k_bgm_next, dim3(nb), dim3(kBT), 0, s, S, G, W.V, N, (const double*)W.r);
+    if ((rc = W.check("batch cycle start")) || (rc = W.read_state())) return rc;
+    if (W.misc(BG_BROKEN) != 0.0) return W.fail(MNS_ERR_HIP, "non-finite value in the batched power iteration");
+    if (W.misc(BG_ALLDONE) != 0.0) break;
+    // iterations in chunks between readbacks; the chunk follows the observed
+    // convergence rate of the slowest instance (iterations past convergence
+    // leave the state unchanged)
+    const int cycle = std::min(m, o->maxit - total);
+    int launched = 0, jj = 0;
+    double worst0 = W.misc(BG_WORST), worst = worst0;
+    while (launched < cycle) {
+      int chunk = 1;
+      if (jj > 0 && worst < worst0 && worst > 1.0) {
+        const double rate = std::log(worst / worst0) / jj;  // < 0
+        const double left = std::log(1.0 / worst) / rate;
+        chunk = (int)std::max(1.0, std::min(8.0, std::floor(0.5 * left)));
+      }
+      chunk = std::min(chunk, cycle - launched);
+      if ((rc = W.iterations(chunk))) return rc;
+      launched += chunk;
+      if ((rc = W.read_state())) return rc;
+      if (W.misc(BG_BROKEN) != 0.0) return W.fail(MNS_ERR_HIP, "non-finite value in batched FGMRES");
+      jj = (int)W.misc(BG_J);
+      worst = W.misc(BG_WORST);
+      if (W.misc(BG_ALLDONE) != 0.0) break;
     }
-    if (!any) break;
-    if ((rc = W.scale(W.r, sc, W.V))) return rc;
-    std::fill(g.begin(), g.end(), 0.0);
-    for (int i = 0; i < count; ++i) g[(size_t)i * (m + 1)] = active[i] ? rn[i] : 0.0;
-    int j = 0;
-    for (; j < m && total < o->maxit; ++j, ++total) {
-      double* Vj = W.V + (size_t)j * N;
-      double* Zj = W.Z + (size_t)j * N;
-      if ((rc = precondition(Vj, Zj))) return rc;
-      if ((rc = W.jac64(Zj, W.w))) return rc;
-      const int K = j + 1;
-      // (1) h = V^T w and w . w; (2) w -= V h with h2 = V^T w and w . w;
-      // (3) where the norm dropped below 0.7 of its value, w -= V h2
-      hipLaunchKernelGGL(k_bdots, dim3(nb), dim3(kBT), 0, s, W.S, W.V, N, K, W.w, 1, W.part);
-      if ((rc = W.check("batch dots")) || (rc = W.sums(K + 1, sums))) return rc;
-      std::vector<double> h1((size_t)count * K), wn0(count);
-      for (int i = 0; i < count; ++i) {
-        for (int k = 0; k < K; ++k) h1[(size_t)i * K + k] = sums[(size_t)i * (K + 1) + k];
-        wn0[i] = std::sqrt(sums[(size_t)i * (K + 1) + K]);
-      }
-      if ((rc = W.upload(h1))) return rc;
-      hipLaunchKernelGGL(k_baxpy, dim3(nb), dim3(kBT), 0, s, W.S, W.V, N, K, W.coef, W.w, 1, W.part);
-      if ((rc = W.check("batch update")) || (rc = W.sums(K + 1, sums))) return rc;
-      std::vector<double> h2((size_t)count * K, 0.0), wn(count);
-      bool reorth = false;
-      for (int i = 0; i < count; ++i) {
-        wn[i] = std::sqrt(sums[(size_t)i * (K + 1) + K]);
-        if (wn[i] < 0.7 * wn0[i]) {
-          reorth = true;
-          for (int k = 0; k < K; ++k) h2[(size_t)i * K + k] = sums[(size_t)i * (K + 1) + k];
-        }
-      }
-      if (reorth) {
-        if ((rc = W.upload(h2))) return rc;
-        hipLaunchKernelGGL(k_baxpy, dim3(nb), dim3(kBT), 0, s, W.S, W.V, N, K, W.coef, W.w, 0, W.part);
-        if ((rc = W.check("batch update")) || (rc = W.sums(1, sums))) return rc;
-        for (int i = 0; i < count; ++i) wn[i] = std::sqrt(sums[i]);
-      }
-      bool all_done = true;
-      for (int i = 0; i < count; ++i) {
-        sc[i] = 0.0;
-        if (done[i]) continue;
-        double* hcol = &hc[(size_t)i * (m + 1)];
-        for (int k = 0; k < K; ++k) hcol[k] = h1[(size_t)i * K + k] + h2[(size_t)i * K + k];
-        hcol[K] = wn[i];
-        if (!std::isfinite(wn[i])) return W.fail(MNS_ERR_HIP, "non-finite value in batched FGMRES");
-        double* csi = &cs[(size_t)i * m];
-        double* sni = &sn[(size_t)i * m];
-        double* gi = &g[(size_t)i * (m + 1)];
-        for (int k = 0; k < j; ++k) {
-          const double a = csi[k] * hcol[k] + sni[k] * hcol[k + 1];
-          const double b2 = -sni[k] * hcol[k] + csi[k] * hcol[k + 1];
-          hcol[k] = a;
-          hcol[k + 1] = b2;
-        }
-        const double den = std::hypot(hcol[j], hcol[j + 1]);
-        csi[j] = den > 0 ? hcol[j] / den : 1.0;
-        sni[j] = den > 0 ? hcol[j + 1] / den : 0.0;
-        hcol[j] = den;
-        hcol[j + 1] = 0.0;
-        gi[j + 1] = -sni[j] * gi[j];
-        gi[j] = csi[j] * gi[j];
-        for (int k = 0; k <= j; ++k) H[((size_t)i * (m + 1) + k) * m + j] = hcol[k];
-        jn[i] = j + 1;
-        ++its[i];
-        if (std::fabs(gi[j + 1]) <= target[i] || wn[i] == 0) done[i] = 1;
-        else sc[i] = 1.0 / wn[i];
-        all_done = all_done && done[i];
-      }
-      if (j + 1 < m && !all_done && (rc = W.scale(W.w, sc, W.V + (size_t)(j + 1) * N))) return rc;
-      if (all_done) {
-        ++j;
-        ++total;
-        break;
-      }
-    }
-    // x_i += Z y_i with y_i = H_i^-1 g_i (upper triangular, order jn[i])
-    const int Kmax = std::max(1, j);
-    y.assign((size_t)count * Kmax, 0.0);
-    for (int i = 0; i < count; ++i) {
-      const int ji = active[i] ? jn[i] : 0;
-      for (int a = ji - 1; a >= 0; --a) {
-        double sum = g[(size_t)i * (m + 1) + a];
-        for (int k2 = a + 1; k2 < ji; ++k2) sum -= H[((size_t)i * (m + 1) + a) * m + k2] * y[(size_t)i * Kmax + k2];
-        const double d = H[((size_t)i * (m + 1) + a) * m + a];
-        y[(size_t)i * Kmax + a] = d != 0 ? sum / d : 0.0;
-      }
-    }
-    if ((rc = W.upload(y))) return rc;
-    hipLaunchKernelGGL(k_bupdate, dim3(nb), dim3(kBT), 0, s, W.S, W.Z, N, Kmax, W.coef, x);
+    if (jj < 1) return W.fail(MNS_ERR_HIP, "batched FGMRES cycle made no progress");
+    total += jj;
+    W.vm64 += jj * W.it_vm64;
+    W.vm32 += jj * W.it_vm32;
+    // x_i += Z y_i with y_i = H_i^-1 g_i
+    hipLaunchKernelGGL(k_bgm_backsub, dim3(1), dim3(kBT), 0, s, G);
+    hipLaunchKernelGGL(k_bgm_update, dim3(nb), dim3(kBT), 0, s, S, G, (const double*)W.Z, N, x);
     if ((rc = W.check("batch solution update"))) return rc;
-    (void)hipStreamSynchronize(s);  // the staging buffer is reused by the next cycle
   }
   // final true residuals
-  if ((rc = W.jac64(x, W.t))) return rc;
-  hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, W.S, rhs, W.t, W.r, W.part);
-  if ((rc = W.check("batch residual")) || (rc = W.sums(1, sums))) return rc;
+  if ((rc = W.jac64(x, W.t, s))) return rc;
+  hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, S, rhs, (const double*)W.t, W.r, G.part);
+  hipLaunchKernelGGL(k_bgm_final, dim3(count), dim3(kBT), 0, s, S, G);
+  if ((rc = W.check("batch residual")) || (rc = W.read_state())) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   bool all = true;
   for (int i = 0; i < count; ++i) {
-    const double r2 = std::sqrt(sums[i]);
-    const bool ok = r2 <= target[i];
+    const double r2 = W.inst(i, BI_RES), bn = W.inst(i, BI_BN);
+    const bool ok = r2 <= W.inst(i, BI_TARGET);
     all = all && ok;
     if (reps) {
       mns_solve_report& R = reps[i];
       R = mns_solve_report{};
-      R.iterations = its[i];
+      R.iterations = (int)W.inst(i, BI_ITS);
       R.status = ok ? MNS_OK : MNS_ERR_NOT_CONVERGED;
-      R.rel_residual = bn[i] > 0 ? r2 / bn[i] : 0.0;
-      R.lambda_max = lam[i];
+      R.rel_residual = bn > 0 ? r2 / bn : 0.0;
+      R.lambda_max = o->precond != -1 ? W.inst(i, BI_LAM) : 0.0;
       R.seconds = secs;
       R.vmults_f64 = W.vm64;
       R.vmults_f32 = W.vm32;

@@ -210,8 +210,10 @@ struct mns_batch {
   double* ws = nullptr;         // Krylov and Chebyshev vectors, diagonal
   float* ws32 = nullptr;
   int ws_m = 0;
-  double* d_small = nullptr;    // partial sums, per-instance results and coefficients
-  double* h_small = nullptr;    // pinned mirror
+  double* d_small = nullptr;    // solver state: partial sums, per-instance Arnoldi data and flags
+  double* h_small = nullptr;    // pinned mirror of the per-instance flags
+  size_t small_doubles = 0;     // capacity of d_small
+  hipStream_t cap = nullptr;    // capture stream of the iteration graph
   std::string err;
 };
 
@@ -261,6 +263,9 @@ int mg_restrict64(mns_handle* h, int level, const double* x, double* y, hipStrea
 int mns_bdf2_step_impl(mns_handle* h, double theta_next, double omega, const double* un, const double* unm1,
                        const double* force, double* u, const mns_step_opts* o, mns_step_report* rep, hipStream_t s);
 int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// h->d_diag64 / d_diag32 hold the diagonal of the current linearization
+// (allocated and computed on first use, reused until it changes)
+int cached_diagonal(mns_handle* h, hipStream_t s);
 int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
 
 // host setup (mns_setup.cpp)

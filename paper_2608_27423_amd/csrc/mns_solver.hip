@@ -491,6 +491,24 @@ static unsigned grid_for(long long n) {
   return (unsigned)b;
 }
 
+// the handle's diagonal in FP64 and FP32, computed once per linearization and
+// kept until the next rotation or linearization (the volume and mortar terms
+// are summed with atomics, so recomputing it may change its last bits)
+int cached_diagonal(mns_handle* h, hipStream_t s) {
+  const size_t n = (size_t)h->ndofs;
+  hipError_t e;
+  if (!h->d_diag64 && (e = hipMalloc((void**)&h->d_diag64, n * sizeof(double))) != hipSuccess)
+    return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (!h->d_diag32 && (e = hipMalloc((void**)&h->d_diag32, n * sizeof(float))) != hipSuccess)
+    return set_error(h, MNS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (h->diag_valid) return MNS_OK;
+  int rc = launch_diagonal<double>(h, h->d_diag64, s);
+  if (rc) return rc;
+  if ((rc = launch_cast_f64_f32(h->d_diag64, h->d_diag32, (int64_t)n, s))) return set_error(h, rc, "cast");
+  h->diag_valid = true;
+  return MNS_OK;
+}
+
 int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(256), 0, s, a, b, (long long)n);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
@@ -1483,11 +1501,7 @@ int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_
     S.mg = mg;
     lmax = mg->L[0].lmax;
   } else if (o->precond != -1) {
-    if (!h->diag_valid) {
-      if ((rc = launch_diagonal<double>(h, h->d_diag64, s))) return rc;
-      if ((rc = launch_cast_f64_f32(h->d_diag64, h->d_diag32, (int64_t)n, s))) return set_error(h, rc, "cast");
-      h->diag_valid = true;
-    }
+    if ((rc = cached_diagonal(h, s))) return rc;
     if ((rc = S.estimate_lambda(o->eig_iters, &lmax))) return rc;
   }
   rep->lambda_max = lmax;
