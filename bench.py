@@ -540,6 +540,9 @@ def main():
     # duration (it does not write the result vector: the gather launch does)
     achieved_kernel = bytes64 / (vol_ms64 * 1e-3) / 1e9
     copy_gbs = None if args.no_copy_bandwidth else copy_bandwidth(dev, sync)
+    # the practical ceiling: the library's own read-dominated stream kernel
+    # (2 GiB read, 1/6 of it written, as the Jacobian's read:write mix)
+    stream_gbs = None if args.no_copy_bandwidth else binding.stream_bandwidth(1 << 31, 6, 20)
     valu = None
     if "_quad" in kname and mesh["dim"] == 3 and mesh["degree"] == 2:
         tflops = QUAD_Q2_FLOP_PER_CELL * cells / (vol_ms64 * 1e-3) / 1e12
@@ -707,6 +710,8 @@ def main():
                      "traffic_bytes_per_call": tb, "traffic_source": f"profiles/traffic_{name}.txt" if tb else None,
                      "kernel": f"whole FP64 vmult ({kname} + gather)", "kernel_ms": ms64,
                      "algorithmic_bytes_per_launch": bytes64,
+                     "measured_stream_GBs": stream_gbs,
+                     "frac_of_measured_stream": achieved / stream_gbs if stream_gbs else None,
                      "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
                      "dominant_launch": {"kernel": kname, "kernel_ms": vol_ms64, "achieved_GBs": achieved_kernel,
                                          "frac_of_8TBs": achieved_kernel / HBM_PEAK_GBS,

@@ -216,10 +216,12 @@ typedef struct {
   int mg_fine_linearization;   /* V-cycle on the mesh's own level: MNS_LIN_NEWTON (default) smooths with the
                                   handle's operator; MNS_LIN_PICARD with a Picard copy of it at the same state
                                   (one more set of per-point data).  FGMRES always applies the handle's operator */
-  int use_graph;               /* 1 (default): the preconditioner's launches (Chebyshev polynomial or V-cycle,
-                                  between the copies of its input and output) are captured once per call into a
-                                  HIP graph on a library stream and replayed on `stream` every iteration; 0: launched
-                                  one by one.  Ignored while kernel timing is enabled.  Same arithmetic either way */
+  int use_graph;               /* 1 (default): one whole FGMRES iteration (preconditioner, FP64 Jacobian,
+                                  Gram-Schmidt passes, Hessenberg and Givens update, next basis vector; every
+                                  launch reads the column index from the device state) is captured once per call
+                                  into a HIP graph on a library stream and replayed on `stream`; the host reads
+                                  the state back once per chunk of iterations.  0: the same launches one by one.
+                                  Ignored by mns_solve while kernel timing is enabled.  Same arithmetic either way */
   double cheb_lambda_factor;   /* every Chebyshev interval (the polynomial preconditioner here and in mns_batch_solve,
                                   the V-cycle smoothers and coarse polynomial): upper end = this factor times the
                                   power-iteration estimate of lambda_max, lower end = upper / (cheb_range or
@@ -363,13 +365,21 @@ const char* mns_batch_last_error(const mns_batch* batch);
  * in lockstep: every iteration is one batched preconditioner application, one
  * batched FP64 Jacobian application and batched Gram-Schmidt reductions
  * (blocks of one instance each, per-instance sums in a fixed order); the
- * Hessenberg and Givens updates run per instance on the host.  Preconditioner:
+ * Hessenberg and Givens updates, the power iteration and the Chebyshev scalars
+ * run per instance on the device, so that with use_graph one iteration is a
+ * graph replay and the host synchronizes once per chunk of iterations and
+ * once per restart cycle.  Preconditioner:
  * opts->precond -1, MNS_F64 or MNS_F32 (Jacobi-Chebyshev of degree
  * cheb_degree <= 32 on [lambda_i / cheb_range, lambda_i], lambda_i by power
  * iteration per instance); restart <= 31.  An instance that has converged
  * keeps its iterate while the others continue.  reports (count entries, or
- * NULL) receive per-instance iterations, relative residuals and lambda_max.
- * The first call allocates (2 * restart + 10) FP64 and 6 FP32 batch vectors.
+ * NULL) receive per-instance iterations, relative residuals and lambda_max
+ * (0 without a preconditioner).
+ * The first call allocates (2 * restart + 10) FP64 and 6 FP32 batch vectors
+ * and the solver state (a few KB per instance); a call with a larger restart
+ * or degree grows them.  Each instance's diagonal is its handle's, computed
+ * (and on the first use allocated) once per linearization and shared with
+ * mns_solve, so repeated solves of one linearization give identical iterates.
  * Synchronizes the stream.
  * Errors: INVALID_ARG, UNSUPPORTED (multigrid), NOT_CONVERGED (some instance
  * reached maxit), HIP. */
@@ -426,6 +436,20 @@ typedef struct {
 } mns_timing;
 int mns_enable_timing(mns_handle* h, int capacity);
 int mns_read_timing(mns_handle* h, mns_timing* out);
+
+/* Measurement: rate of a read-dominated stream on the current device, the
+ * practical HBM ceiling for the roofline figures.  Reads read_bytes from src
+ * (seen as `ratio` contiguous blocks of 32-byte words) and writes
+ * read_bytes / ratio to dst (word o = sum of word o of every block), `reps`
+ * times after one untimed pass, timed with HIP events on `stream`, for each
+ * of eight launch shapes (1,024 to 8,192 workgroups of 256 threads, one or
+ * two words per thread and step); *gbs = the best (bytes read + bytes
+ * written) per second / 1e9.  src and dst are device
+ * buffers of at least read_bytes and read_bytes / ratio bytes, 32-byte
+ * aligned.  Synchronizes the stream.
+ * Errors: INVALID_ARG (sizes, alignment, ratio outside 1..64), HIP. */
+int mns_stream_bandwidth(const void* src, void* dst, int64_t read_bytes, int ratio, int reps, void* stream,
+                         double* gbs);
 
 /* Last error message of the handle ("" if none).  Never NULL. */
 const char* mns_last_error(const mns_handle* h);

@@ -34,7 +34,7 @@ EXPORTED = [
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
     "mns_autotune_kernel_config", "mns_mg_restrict", "mns_batch_solve", "mns_apply_jacobian_noalloc",
-    "mns_assemble_matrix",
+    "mns_assemble_matrix", "mns_stream_bandwidth",
 ]
 
 
@@ -137,6 +137,8 @@ def lib():
         L.mns_apply_jacobian_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_residual.argtypes = [vp, vp, vp, vp]
         L.mns_assemble_matrix.argtypes = [vp, vp, ctypes.c_int64, vp]
+        L.mns_stream_bandwidth.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp,
+                                           ctypes.POINTER(ctypes.c_double)]
         L.mns_compute_diagonal.argtypes = [vp, ctypes.c_int, vp, vp]
         L.mns_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
         L.mns_default_solve_opts.restype = None
@@ -167,6 +169,23 @@ def lib():
         L.mns_destroy.restype = None
         _lib = L
     return _lib
+
+
+def stream_bandwidth(read_bytes=1 << 31, ratio=6, reps=20):
+    """GB/s of the library's read-dominated stream kernel (mns_stream_bandwidth)
+    over device buffers allocated here."""
+    import torch
+
+    src = torch.ones(read_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty(read_bytes // 8 // max(int(ratio), 1) + 4, dtype=torch.float64, device="cuda")
+    g = ctypes.c_double()
+    rc = lib().mns_stream_bandwidth(_ptr(src), _ptr(dst), int(read_bytes), int(ratio), int(reps), _stream(),
+                                    ctypes.byref(g))
+    del src, dst
+    torch.cuda.empty_cache()
+    if rc != MNS_OK:
+        raise MnsError(rc, "stream bandwidth")
+    return g.value
 
 
 class MnsError(RuntimeError):

@@ -105,3 +105,16 @@ def test_batch_refuses_stale_member():
     finally:
         for op in ops:
             op.close()
+
+
+def test_stream_bandwidth_measurement():
+    """mns_stream_bandwidth: the read-dominated stream rate used as the
+    practical HBM ceiling is positive and below the HBM peak, and bad sizes
+    or ratios are refused before any launch."""
+    gbs = binding.stream_bandwidth(1 << 28, 6, 3)
+    print(f"stream kernel: {gbs:.0f} GB/s")
+    assert 100.0 < gbs < 8000.0
+    for rb, ratio in ((1 << 10, 6), (1 << 28, 0), (1 << 28, 65)):
+        with pytest.raises(binding.MnsError) as e:
+            binding.stream_bandwidth(rb, ratio, 1)
+        assert e.value.code == binding.MNS_ERR_INVALID_ARG
