@@ -57,31 +57,80 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes_volume(mesh, n_dofs, real_bytes):
-    """Minimum HBM bytes of one volume-kernel launch: read src once, write dst
-    once, read the per-point linearization data once (16 values per point in
-    3D, 9 in 2D)."""
+def algorithmic_bytes_volume(mesh, n_dofs, real_bytes, lin_source=0):
+    """Minimum HBM bytes of one application: read src once, write dst once,
+    read the per-point linearization data once (source B: 16 values per point
+    in 3D, 9 in 2D; source C: tau and tau R, 4 values per point, plus the
+    state's velocity once, 3/4 of a vector)."""
     dim, k = mesh["dim"], mesh["degree"]
     n = k + 1
     nz = mesh["n_z"] if dim == 3 else 1
     cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * nz
+    if lin_source == 1:
+        return (2.75 * n_dofs + 4 * n ** dim * cells) * real_bytes, cells
     lin = (16 if dim == 3 else 9) * n ** dim * cells
     return (2 * n_dofs + lin) * real_bytes, cells
 
 
-def dominant_kernel(mesh, fused, layout, real="double"):
+def has_source_c(mesh, real="double"):
+    """Linearization source C exists with the quad layout: 3D degree 2 in
+    both precisions, degree 3 in FP32."""
+    return mesh["dim"] == 3 and (mesh["degree"] == 2 or (mesh["degree"] == 3 and real == "float"))
+
+
+def dominant_kernel(mesh, fused, layout, real="double", lin_source=0):
     """Name of the launch that the volume timer brackets."""
     dim, k = mesh["dim"], mesh["degree"]
     quad = layout == 1 and dim == 3 and k in (2, 3)
+    c = "true" if (lin_source == 1 and has_source_c(mesh, real)) else "false"
     if fused < 0:
         cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * (mesh["n_z"] if dim == 3 else 1)
         fused = 2 if cells >= (1 << 18) else 1
     fused = 1 if fused == 1 else 0
     if quad and fused and real == "double" and k == 2:
-        return "mns::k_jacobian_fused_quad_lds<3>"
+        return f"mns::k_jacobian_fused_quad_lds<3, {c}>"
     if quad:
-        return f"mns::k_jacobian_{'fused' if fused else 'volume'}_quad<{real}, {k + 1}>"
+        return f"mns::k_jacobian_{'fused' if fused else 'volume'}_quad<{real}, {k + 1}, {c}>"
     return f"mns::k_jacobian_{'fused' if fused else 'volume'}<{real}, {dim}, {k + 1}>"
+
+
+def source_c_leg(op, mesh, x, sync, steps, warmup=5):
+    """The vmult with linearization source C (tau and tau R per point, a and
+    grad u evaluated from the state) next to source B, both precisions, in
+    the automatic launch mode: HIP-event time per application and the HBM
+    rate against each source's own algorithmic bytes."""
+    import torch
+
+    n = x.numel()
+    cfg = op.get_kernel_config()
+    out = {}
+    for label, xx, real, rb in (("fp64", x, "double", 8), ("fp32", x.float(), "float", 4)):
+        if not has_source_c(mesh, real):
+            continue
+        y = torch.empty_like(xx)
+        rec = {}
+        for src in (0, 1):
+            op.set_kernel_config(lin_source_f64=src, lin_source_f32=src)
+            for _ in range(warmup):
+                op.apply_jacobian(xx, y)
+            sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                op.apply_jacobian(xx, y)
+            e1.record()
+            sync()
+            ms = e0.elapsed_time(e1) / steps
+            nbytes, _ = algorithmic_bytes_volume(mesh, n, rb, src)
+            rec["BC"[src]] = {"ms_per_vmult": ms, "algorithmic_bytes": nbytes,
+                              "frac_of_8TBs": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "kernel": dominant_kernel(mesh, cfg["fused_launch"], 1, real, src)}
+        rec["faster"] = "C" if rec["C"]["ms_per_vmult"] < rec["B"]["ms_per_vmult"] else "B"
+        rec["speedup_C_over_B"] = rec["B"]["ms_per_vmult"] / rec["C"]["ms_per_vmult"]
+        out[label] = rec
+        del y
+    op.set_kernel_config(**cfg)
+    return out
 
 
 def kernel_source_digest():
@@ -338,6 +387,7 @@ def vmult_leg(name, dev, sync, steps=100, warmup=10):
                       "volume_kernel": dominant_kernel(mesh, -1, 1, "double" if label == "fp64" else "float")}
         del y
     out["fp32_speedup_over_fp64"] = out["fp64"]["ms_per_vmult"] / out["fp32"]["ms_per_vmult"]
+    out["lin_source_c"] = source_c_leg(op, mesh, x, sync, steps // 2 or 1)
     return op, mesh, theta, out
 
 
@@ -609,9 +659,12 @@ def main():
             solves["multigrid"] = mg
         rec["solve"] = solves
 
+    # linearization source C next to B (the timed region above used B)
+    op.set_linearization(state)
+    if has_source_c(mesh):
+        rec["lin_source_c"] = source_c_leg(op, mesh, x64, sync, max(args.steps // 2, 10))
     # launch configuration chosen by the library's autotuner on this mesh
     # (the timed region above used the automatic default)
-    op.set_linearization(state)
     default_cfg = op.get_kernel_config()
     chosen = op.autotune_kernel_config(20)
     ms_tuned, _ = run(x64, y64, max(args.steps // 2, 10), 3)

@@ -402,22 +402,38 @@ void mns_batch_destroy(mns_batch* batch);
  * the theta contractions exchange values between lanes without LDS; 0:
  * (k+1)^2 lanes per cell (nine for degree 2, sixteen for degree 3) with the
  * r and theta contractions staged through LDS, the layout used in 2D and for
- * degree >= 4 whatever the setting.  Takes effect on the next apply call.
+ * degree >= 4 whatever the setting.  lin_source_f64 / lin_source_f32: where
+ * the volume kernel takes the linearization data of a point (Sec. 2.3: the
+ * advection velocity a = u - w, grad u, tau and the strong residual R), per
+ * precision.  0 (default): source B, all 16 values per Gauss point from the
+ * store written by mns_set_linearization; 1: source C, only tau and tau R per
+ * point (4 values) from that store, a and grad u evaluated from the state
+ * inside the kernel like the increment (more arithmetic, a quarter of the
+ * per-point bytes).  Source C exists with the quad layout for 3D degree 2
+ * (both precisions) and degree 3 (FP32); elsewhere source B is used whatever
+ * the setting.  The two sources give the same operator up to rounding.
+ * Takes effect on the next apply call.
  * Errors: INVALID_ARG. */
 typedef struct {
   int fused_launch;
   int volume_layout;
+  int lin_source_f64;
+  int lin_source_f32;
 } mns_kernel_config;
 int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg);
 int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg);
 
 /* Autotuner of the launch configuration: times `reps` FP64 applications of
- * every launch mode (fused_launch 0, 1, 2) and, in 3D with degree 2 or 3, both
- * volume layouts, on the handle's own mesh and linearization, and sets the
- * fastest (written to *chosen when non-null).  All configurations compute the
- * same product; the choice depends on the mesh size (tail of the fused
- * launch against the cost of a second stream).  Allocates two work vectors
- * for the duration of the call and synchronizes the stream.
+ * every launch mode (fused_launch 0, 1, 2), in 3D with degree 2 or 3 both
+ * volume layouts, and with the quad layout both linearization sources where
+ * source C exists, on the handle's own mesh and linearization, and sets the
+ * fastest; then, with that launch mode and layout, times `reps` FP32
+ * applications with each FP32 linearization source and sets the faster
+ * (written to *chosen when non-null).  All configurations compute the same
+ * product up to rounding; the choice depends on the mesh size (tail of the
+ * fused launch against the cost of a second stream) and on the balance of
+ * memory traffic and arithmetic.  Allocates four work vectors for the
+ * duration of the call and synchronizes the stream.
  * Errors: INVALID_ARG (reps outside 1..1000, kernel timing enabled),
  * NOT_LINEARIZED, HIP. */
 int mns_autotune_kernel_config(mns_handle* h, int reps, mns_kernel_config* chosen, void* stream);

@@ -104,7 +104,8 @@ class StepReport(ctypes.Structure):
 
 
 class KernelConfig(ctypes.Structure):
-    _fields_ = [("fused_launch", ctypes.c_int), ("volume_layout", ctypes.c_int)]
+    _fields_ = [("fused_launch", ctypes.c_int), ("volume_layout", ctypes.c_int), ("lin_source_f64", ctypes.c_int),
+                ("lin_source_f32", ctypes.c_int)]
 
 
 class Timing(ctypes.Structure):
@@ -369,7 +370,10 @@ class Operator:
     def set_kernel_config(self, **kw):
         c = KernelConfig()
         self._check(self._L.mns_get_kernel_config(self._h, ctypes.byref(c)))
+        names = {f for f, _ in KernelConfig._fields_}
         for k2, v in kw.items():
+            if k2 not in names:
+                raise TypeError(f"unknown kernel configuration field {k2!r}")
             setattr(c, k2, int(v))
         return self._check(self._L.mns_set_kernel_config(self._h, ctypes.byref(c)))
 
@@ -377,7 +381,7 @@ class Operator:
         """Time every launch configuration on this mesh and keep the fastest."""
         c = KernelConfig()
         self._check(self._L.mns_autotune_kernel_config(self._h, int(reps), ctypes.byref(c), _stream()))
-        return {"fused_launch": c.fused_launch, "volume_layout": c.volume_layout}
+        return {k2: getattr(c, k2) for k2, _ in c._fields_}
 
     def get_kernel_config(self):
         c = KernelConfig()

@@ -40,7 +40,8 @@ static void free_all(mns_handle* h) {
                    (void**)&h->d_lin64, (void**)&h->d_lin32, (void**)&h->d_hist_buf, (void**)&h->d_force_buf,
                    (void**)&h->ws64, (void**)&h->ws32, (void**)&h->d_E64, (void**)&h->d_E32, (void**)&h->d_Em64,
                    (void**)&h->d_Em32, (void**)&h->d_diag64, (void**)&h->d_diag32, (void**)&h->d_red, (void**)&h->d_gm,
-                   (void**)&h->d_step, (void**)&h->d_state};
+                   (void**)&h->d_step, (void**)&h->d_state, (void**)&h->d_linc64, (void**)&h->d_linc32,
+                   (void**)&h->d_state32};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -163,6 +164,12 @@ int mns_set_linearization(mns_handle* h, const double* state, const double* u_hi
   if (rc) return rc;
   rc = mns::launch_cast_f64_f32(h->d_lin64, h->d_lin32, (int64_t)nlin, s);
   if (rc) return set_error(h, rc, "cast");
+  // linearization source C: tau and tau R per point, the state in FP32
+  if (h->d_linc64) {
+    if ((rc = mns::launch_lin_compact(h, s))) return rc;
+    if ((rc = mns::launch_cast_f64_f32(state, h->d_state32, h->ndofs, s))) return set_error(h, rc, "cast");
+  }
+  h->lin_picard = h->picard;
   h->linearized = true;
   h->diag_valid = false;
   return MNS_OK;
@@ -489,8 +496,12 @@ int mns_set_kernel_config(mns_handle* h, const mns_kernel_config* cfg) {
     return set_error(h, MNS_ERR_INVALID_ARG, "fused_launch must be -1, 0, 1 or 2");
   if (cfg->volume_layout != 0 && cfg->volume_layout != 1)
     return set_error(h, MNS_ERR_INVALID_ARG, "volume_layout must be 0 or 1");
+  if ((cfg->lin_source_f64 != 0 && cfg->lin_source_f64 != 1) || (cfg->lin_source_f32 != 0 && cfg->lin_source_f32 != 1))
+    return set_error(h, MNS_ERR_INVALID_ARG, "lin_source_f64 and lin_source_f32 must be 0 or 1");
   h->fused = cfg->fused_launch;
   h->quad = cfg->volume_layout;
+  h->lin_src[0] = cfg->lin_source_f64;
+  h->lin_src[1] = cfg->lin_source_f32;
   return MNS_OK;
 }
 
@@ -498,6 +509,8 @@ int mns_get_kernel_config(const mns_handle* h, mns_kernel_config* cfg) {
   if (!h || !cfg) return MNS_ERR_INVALID_ARG;
   cfg->fused_launch = h->fused;
   cfg->volume_layout = h->quad;
+  cfg->lin_source_f64 = h->lin_src[0];
+  cfg->lin_source_f32 = h->lin_src[1];
   return MNS_OK;
 }
 
@@ -508,56 +521,92 @@ int mns_autotune_kernel_config(mns_handle* h, int reps, mns_kernel_config* chose
   hipStream_t s = as_stream(stream);
   const size_t n = (size_t)h->ndofs;
   double *x = nullptr, *y = nullptr;
+  float *x32 = nullptr, *y32 = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
   auto cleanup = [&]() {
     if (x) (void)hipFree(x);
     if (y) (void)hipFree(y);
+    if (x32) (void)hipFree(x32);
+    if (y32) (void)hipFree(y32);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   };
   if ((e = hipMalloc((void**)&x, n * sizeof(double))) != hipSuccess ||
       (e = hipMalloc((void**)&y, n * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc((void**)&x32, n * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc((void**)&y32, n * sizeof(float))) != hipSuccess ||
       (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
     cleanup();
     return set_error(h, MNS_ERR_HIP, std::string("autotune buffers: ") + hipGetErrorString(e));
   }
   int rc = mns::launch_fill<double>(x, 1.0, (int64_t)n, s);
+  if (!rc) rc = mns::launch_fill<float>(x32, 1.0f, (int64_t)n, s);
+  // milliseconds of `reps` applications in precision f32 with the current
+  // configuration (two untimed first)
+  auto time_apply = [&](bool f32, float* out) -> int {
+    int r = MNS_OK;
+    for (int i = 0; i < 2 + reps && r == MNS_OK; ++i) {
+      if (i == 2) (void)hipEventRecord(e0, s);
+      r = f32 ? mns::launch_jacobian<float>(h, x32, y32, s) : mns::launch_jacobian<double>(h, x, y, s);
+    }
+    (void)hipEventRecord(e1, s);
+    if (r) return r;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess)
+      return set_error(h, MNS_ERR_HIP, std::string("autotune sync: ") + hipGetErrorString(e));
+    return hipEventElapsedTime(out, e0, e1) == hipSuccess ? MNS_OK : set_error(h, MNS_ERR_HIP, "autotune timing");
+  };
   // candidates: every launch mode; both volume layouts where the quad layout
-  // exists (3D, degrees 2 and 3)
+  // exists (3D, degrees 2 and 3); both linearization sources with the quad
+  // layout where source C exists
   const bool has_quad = h->dim == 3 && (h->k == 2 || h->k == 3);
-  const int saved_fused = h->fused, saved_quad = h->quad;
+  const bool c64 = h->d_linc64 && h->k == 2, c32 = h->d_linc64 != nullptr;
+  const mns_kernel_config saved{h->fused, h->quad, h->lin_src[0], h->lin_src[1]};
   float best = -1.0f;
-  mns_kernel_config best_cfg{saved_fused, saved_quad};
-  for (int layout = has_quad ? 1 : saved_quad; rc == MNS_OK && layout >= (has_quad ? 0 : saved_quad); --layout)
-    for (int mode = 0; rc == MNS_OK && mode <= 2; ++mode) {
-      h->fused = mode;
-      h->quad = layout;
-      for (int i = 0; i < 2 && rc == MNS_OK; ++i) rc = mns::launch_jacobian<double>(h, x, y, s);
-      if (rc) break;
-      (void)hipEventRecord(e0, s);
-      for (int i = 0; i < reps && rc == MNS_OK; ++i) rc = mns::launch_jacobian<double>(h, x, y, s);
-      (void)hipEventRecord(e1, s);
-      if (rc || (e = hipEventSynchronize(e1)) != hipSuccess) {
-        if (!rc) rc = set_error(h, MNS_ERR_HIP, std::string("autotune sync: ") + hipGetErrorString(e));
-        break;
+  mns_kernel_config best_cfg = saved;
+  for (int layout = has_quad ? 1 : saved.volume_layout; rc == MNS_OK && layout >= (has_quad ? 0 : saved.volume_layout);
+       --layout)
+    for (int mode = 0; rc == MNS_OK && mode <= 2; ++mode)
+      for (int src = 0; rc == MNS_OK && src <= ((layout == 1 && c64) ? 1 : 0); ++src) {
+        h->fused = mode;
+        h->quad = layout;
+        h->lin_src[0] = src;
+        float ms = 0;
+        if ((rc = time_apply(false, &ms))) break;
+        if (best < 0 || ms < best) {
+          best = ms;
+          best_cfg.fused_launch = mode;
+          best_cfg.volume_layout = layout;
+          best_cfg.lin_source_f64 = src;
+        }
       }
+  // FP32 source with the chosen launch mode and layout
+  if (rc == MNS_OK && c32 && best_cfg.volume_layout == 1) {
+    h->fused = best_cfg.fused_launch;
+    h->quad = best_cfg.volume_layout;
+    float best32 = -1.0f;
+    for (int src = 0; rc == MNS_OK && src <= 1; ++src) {
+      h->lin_src[1] = src;
       float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (best < 0 || ms < best) {
-        best = ms;
-        best_cfg.fused_launch = mode;
-        best_cfg.volume_layout = layout;
+      if ((rc = time_apply(true, &ms))) break;
+      if (best32 < 0 || ms < best32) {
+        best32 = ms;
+        best_cfg.lin_source_f32 = src;
       }
     }
+  }
   cleanup();
   if (rc) {
-    h->fused = saved_fused;
-    h->quad = saved_quad;
+    h->fused = saved.fused_launch;
+    h->quad = saved.volume_layout;
+    h->lin_src[0] = saved.lin_source_f64;
+    h->lin_src[1] = saved.lin_source_f32;
     return rc;
   }
   h->fused = best_cfg.fused_launch;
   h->quad = best_cfg.volume_layout;
+  h->lin_src[0] = best_cfg.lin_source_f64;
+  h->lin_src[1] = best_cfg.lin_source_f32;
   if (chosen) *chosen = best_cfg;
   return MNS_OK;
 }

@@ -150,6 +150,15 @@ struct mns_handle {
   int gm_m = 0;                 // restart length d_gm was sized for
   double* d_step = nullptr;     // time-step work vectors (history, residual, rhs, increment, partials)
   double* d_state = nullptr;    // copy of the linearization state (multigrid injects it)
+  // linearization source of the quad volume kernels, [0] FP64, [1] FP32:
+  // 0 = B, the full per-point store d_lin64 / d_lin32 (a, grad u, tau, tau R);
+  // 1 = C, tau and tau R per point (d_linc64 / d_linc32) with a and grad u
+  // evaluated from the state (d_state / d_state32) inside the kernel
+  int lin_src[2] = {0, 0};
+  double* d_linc64 = nullptr;   // [cell][point][tau, tau R_x, tau R_y, tau R_z] (3D, degrees 2 and 3)
+  float* d_linc32 = nullptr;
+  float* d_state32 = nullptr;
+  int lin_picard = 0;           // kind of the current linearization
   long long lin_version = 0;    // incremented by every rotation and linearization
   void* mg = nullptr;           // multigrid hierarchy (mns_solver.hip)
   double* h_red = nullptr;      // pinned host mirror
@@ -230,6 +239,8 @@ int launch_batch_jacobian(mns_batch* b, const Real* src, Real* dst, hipStream_t 
 template <typename Real>
 int launch_linearize(mns_handle* h, const double* state, const double* hist, const double* force,
                      Real* lin, hipStream_t s);
+// d_linc64 / d_linc32 from d_lin64 (no-op where source C does not exist)
+int launch_lin_compact(mns_handle* h, hipStream_t s);
 template <typename Real>
 int launch_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s);
 // the same product with E and Em in the library's file-scope scratch array

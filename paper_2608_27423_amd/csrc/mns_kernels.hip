@@ -1094,13 +1094,25 @@ __device__ inline void load_lin(const Real* p, Real (&w)[NV]) {
 // when the point starts (no prefetch ring).  That takes the FP64 degree-2
 // kernel from about 370 registers per lane to under 256, i.e. from one to two
 // wavefronts per SIMD, which hide each other's memory latency.
-template <typename Real, int N, bool ULDS = false>
+//
+// LINC: linearization source C.  Per point only tau and tau R are read (lin
+// then holds 4 values per point, in the point order of the full store); the
+// advection velocity a = u - w (w the mesh velocity of rotor cells) and the
+// velocity gradient grad u are evaluated from the state's nodal values with
+// the same collocation steps as the increment (picard: grad u = 0).  The
+// state's point values stay in registers, or in LDS after the increment's
+// (3 (k+1)^2 more values per lane) when ULDS is set.
+template <typename Real, int N, bool ULDS = false, bool LINC = false>
 __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                    const Real* __restrict__ lin, const Real* __restrict__ src,
-                                   Real* __restrict__ E, bool strip, Real* __restrict__ us = nullptr) {
+                                   Real* __restrict__ E, bool strip, Real* __restrict__ us = nullptr,
+                                   const Real* __restrict__ state = nullptr, int picard = 0) {
   constexpr int DIM = 3, NC = 4, NT = 4;
   using Q = QuadShape<Real, N>;
   using LL = LinLayout<DIM>;
+  constexpr int LW = LINC ? 4 : LL::SIZE;  // values read per point
+  Real* ss = nullptr;                      // state point values (ULDS and LINC)
+  if constexpr (ULDS && LINC) ss = us + NC * N * N * 64;
   static_assert(N <= 4, "quad layout holds at most four theta slices");
   const int lane = threadIdx.x & 63;
   const int t = lane & 3;
@@ -1121,18 +1133,19 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
     trs = tr[1];
   }
   constexpr int PF = 1;
-  const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LL::SIZE;
-  Real ring[PF][LL::SIZE];
+  const Real* lbase = lin + ((size_t)cell * Q::NPT + ts) * LW;
+  Real ring[PF][LW];
   if constexpr (!ULDS) {
 #pragma unroll
     for (int i = 0; i < PF; ++i)
-      if (i < Q::PL) load_lin<Real, LL::SIZE>(lbase + ((i / N) * Q::PL + (i % N) * N) * LL::SIZE, ring[i]);
+      if (i < Q::PL) load_lin<Real, LW>(lbase + ((i / N) * Q::PL + (i % N) * N) * LW, ring[i]);
   }
 
   // nodal values of the slice, constrained entries read as zero
   // ULDS: point values in LDS at us[((comp * N + r) * N + z) * 64 + lane]
   // (lane-owned columns, 4 N^2 values per lane)
   Real U[NC][N][N];  // [comp][r][z]
+  Real SP[LINC ? DIM : 1][N][N];  // LINC: state velocity, nodal then point values
   {
     int it = k * C.ct + ts;
     const int ntn = pick(C.dom, G.ntd);
@@ -1147,6 +1160,13 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
         const long long node = nbase + (long long)ntn * (b + (long long)nrn * c);
         Real w[4];
         load_node4<Real>(src + node * NC, w);
+        if constexpr (LINC) {
+          // the state enters with its boundary values (no constraint)
+          Real ws[4];
+          load_node4<Real>(state + node * NC, ws);
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) SP[m][b][c] = ws[m];
+        }
         const bool outer = (C.dom == 0) ? (ir == 0) : (ir == G.nrn[1] - 1);
         const bool vf = outer | (iz == 0) | (iz == G.nzn - 1);
         const bool pf = (C.dom == 1) & (it == 0) & (ir == G.nrn[1] - 1) & (iz == 0);
@@ -1192,6 +1212,35 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
           else U[m][qj][q] = uq;
         }
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (LINC) {
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        Real A[N][N];
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+          for (int q = 0; q < N; ++q) {
+            Real v = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) v += T.V[q][c] * SP[m][b][c];
+            A[b][q] = v;
+          }
+#pragma unroll
+        for (int qj = 0; qj < N; ++qj)
+#pragma unroll
+          for (int q = 0; q < N; ++q) {
+            Real v = 0;
+#pragma unroll
+            for (int b = 0; b < N; ++b) v += T.V[qj][b] * A[b][q];
+            Real xs[N];
+            quad_rotate<N>(v, xs);
+            const Real sq = quad_dot<N>(cV, xs);
+            if constexpr (ULDS) ss[((m * N + qj) * N + q) * 64 + lane] = sq;
+            else SP[m][qj][q] = sq;
+          }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
 
@@ -1247,17 +1296,26 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
 #pragma unroll
     for (int qj = 0; qj < N; ++qj) {
       const int pt = q * N + qj;
+      Real lw[LW];  // the point's stored values (all 16, or tau and tau R)
       if constexpr (ULDS) {
-        load_lin<Real, LL::SIZE>(lbase + ((pt / N) * Q::PL + (pt % N) * N) * LL::SIZE, lv);
+        load_lin<Real, LW>(lbase + ((pt / N) * Q::PL + (pt % N) * N) * LW, lw);
       } else {
 #pragma unroll
-        for (int j = 0; j < LL::SIZE; ++j) lv[j] = ring[0][j];
+        for (int j = 0; j < LW; ++j) lw[j] = ring[0][j];
 #pragma unroll
         for (int i = 0; i + 1 < PF; ++i)
 #pragma unroll
-          for (int j = 0; j < LL::SIZE; ++j) ring[i][j] = ring[i + 1][j];
+          for (int j = 0; j < LW; ++j) ring[i][j] = ring[i + 1][j];
         if (pt + PF < Q::PL)
-          load_lin<Real, LL::SIZE>(lbase + (((pt + PF) / N) * Q::PL + ((pt + PF) % N) * N) * LL::SIZE, ring[PF - 1]);
+          load_lin<Real, LW>(lbase + (((pt + PF) / N) * Q::PL + ((pt + PF) % N) * N) * LW, ring[PF - 1]);
+      }
+      if constexpr (!LINC) {
+#pragma unroll
+        for (int j = 0; j < LL::SIZE; ++j) lv[j] = lw[j];
+      } else {
+        lv[LL::TAU] = lw[0];
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) lv[LL::TR + m] = lw[1 + m];
       }
       RefVal<Real, DIM> rv[DIM], rp;
 #pragma unroll
@@ -1303,6 +1361,41 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
       g.inv_rdth = g.inv_r * inv_dth;
       g.jxw = wt * T.w[qj] * T.w[q] * g.r;
       g.complete();
+      if constexpr (LINC) {
+        // mesh velocity omega e_z x x in rotor cells
+        const Real w0 = C.dom == 0 ? -G.omega * g.r * g.s : Real(0);
+        const Real w1 = C.dom == 0 ? G.omega * g.r * g.c : Real(0);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          Real sr[N], sz[N];
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            if constexpr (ULDS) {
+              sr[j] = ss[((m * N + j) * N + q) * 64 + lane];
+              sz[j] = ss[((m * N + qj) * N + j) * 64 + lane];
+            } else {
+              sr[j] = SP[m][j][q];
+              sz[j] = SP[m][qj][j];
+            }
+          }
+          const Real v = sr[qj];
+          Real d1 = T.CD[qj][0] * sr[0], e1 = T.CD[q][0] * sz[0];
+#pragma unroll
+          for (int j = 1; j < N; ++j) {
+            d1 += T.CD[qj][j] * sr[j];
+            e1 += T.CD[q][j] * sz[j];
+          }
+          Real xs[N];
+          quad_rotate<N>(v, xs);
+          const Real d0 = quad_dot<N>(cD, xs);
+          lv[LL::A + m] = v - (m == 0 ? w0 : m == 1 ? w1 : Real(0));
+          // reference derivatives (theta d0, r d1, z e1) -> Cartesian gradient
+          const Real gx = g.a1 * d1 - g.b2 * d0, gy = g.a2 * d1 + g.b1 * d0, gz = e1 * g.inv_dz;
+          lv[LL::GU + m * DIM + 0] = picard ? Real(0) : gx;
+          lv[LL::GU + m * DIM + 1] = picard ? Real(0) : gy;
+          lv[LL::GU + m * DIM + 2] = picard ? Real(0) : gz;
+        }
+      }
       Real tc[NC][NT];
       pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
 #pragma unroll
@@ -1397,14 +1490,15 @@ __device__ __attribute__((always_inline)) inline void volume_quad(const Geom<Rea
   }
 }
 
-template <typename Real, int N>
+template <typename Real, int N, bool LINC = false>
 __global__ __launch_bounds__(64) void k_jacobian_volume_quad(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                              const Real* __restrict__ lin,
                                                              const Real* __restrict__ src, Real* __restrict__ E,
-                                                             int strip) {
+                                                             int strip, const Real* __restrict__ state,
+                                                             int picard) {
   constexpr bool kLds = sizeof(Real) == 8;
-  __shared__ Real us[kLds ? 4 * N * N * 64 : 1];
-  volume_quad<Real, N, kLds>(G, T, k, blockIdx.x, lin, src, E, strip != 0, us);
+  __shared__ Real us[kLds ? (LINC ? 7 : 4) * N * N * 64 : 1];
+  volume_quad<Real, N, kLds, LINC>(G, T, k, blockIdx.x, lin, src, E, strip != 0, us, state, picard);
 }
 
 // ---------------------------------------------------------------------------
@@ -2030,13 +2124,14 @@ __global__ __launch_bounds__(64) void k_jacobian_fused(Geom<Real> G, Tab1D<Real,
 }
 
 // fused launch with the quad volume layout (3D)
-template <typename Real, int N>
+template <typename Real, int N, bool LINC = false>
 __global__ __launch_bounds__(64) void k_jacobian_fused_quad(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
                                                             const Real* __restrict__ lin,
                                                             const MortarTab<Real, N>* __restrict__ Mp,
                                                             const Real* __restrict__ mtrig,
                                                             const Real* __restrict__ src, Real* __restrict__ E,
-                                                            Real* __restrict__ Em, int strip) {
+                                                            Real* __restrict__ Em, int strip,
+                                                            const Real* __restrict__ state, int picard) {
   __shared__ MortarSmem<Real, 3, N> sm;
   // degree 2: volume blocks first, mortar blocks last (FP32 vmult 32.3 ->
   // 28.0 us at 1.1M DoFs); degree 3: mortar blocks first (2 % faster there)
@@ -2044,7 +2139,8 @@ __global__ __launch_bounds__(64) void k_jacobian_fused_quad(Geom<Real> G, Tab1D<
   const int nvb = (int)gridDim.x - nmb;
   const bool mortar = kVolumeFirst ? (int)blockIdx.x >= nvb : (int)blockIdx.x < nmb;
   if (mortar) mortar_block<Real, 3, N>(G, T, k, kVolumeFirst ? blockIdx.x - nvb : blockIdx.x, Mp, mtrig, src, Em, 1, sm);
-  else volume_quad<Real, N>(G, T, k, kVolumeFirst ? blockIdx.x : blockIdx.x - nmb, lin, src, E, strip != 0);
+  else volume_quad<Real, N, false, LINC>(G, T, k, kVolumeFirst ? blockIdx.x : blockIdx.x - nmb, lin, src, E,
+                                         strip != 0, nullptr, state, picard);
 }
 
 // Fused launch of the FP64 quad layout with LDS-staged volume blocks: the
@@ -2052,16 +2148,17 @@ __global__ __launch_bounds__(64) void k_jacobian_fused_quad(Geom<Real> G, Tab1D<
 // blocks take fewer faces per block, so that both fit the LDS of two
 // wavefronts per SIMD (the kernel's registers allow two).
 constexpr int kLdsQuadBytes = 4 * 3 * 3 * 64 * 8;  // 3D Q2 FP64 point values
-template <int N>
+template <int N, bool LINC = false>
 __global__ __launch_bounds__(64) void k_jacobian_fused_quad_lds(Geom<double> G, Tab1D<double, N> T, int k, int nmb,
                                                                 const double* __restrict__ lin,
                                                                 const MortarTab<double, N>* __restrict__ Mp,
                                                                 const double* __restrict__ mtrig,
                                                                 const double* __restrict__ src,
                                                                 double* __restrict__ E, double* __restrict__ Em,
-                                                                int strip) {
+                                                                int strip, const double* __restrict__ state,
+                                                                int picard) {
   using MSm = MortarSmem<double, 3, N, kLdsQuadBytes>;
-  constexpr int UB = 4 * N * N * 64 * (int)sizeof(double);
+  constexpr int UB = (LINC ? 7 : 4) * N * N * 64 * (int)sizeof(double);
   constexpr int SB = (int)sizeof(MSm) > UB ? (int)sizeof(MSm) : UB;
   __shared__ __align__(16) unsigned char smem[SB];
   // volume blocks first, the mortar blocks last (measured faster than mortar
@@ -2071,7 +2168,8 @@ __global__ __launch_bounds__(64) void k_jacobian_fused_quad_lds(Geom<double> G, 
     mortar_block<double, 3, N, kLdsQuadBytes>(G, T, k, blockIdx.x - nvb, Mp, mtrig, src, Em, 1,
                                               *reinterpret_cast<MSm*>(smem));
   else
-    volume_quad<double, N, true>(G, T, k, blockIdx.x, lin, src, E, strip != 0, reinterpret_cast<double*>(smem));
+    volume_quad<double, N, true, LINC>(G, T, k, blockIdx.x, lin, src, E, strip != 0, reinterpret_cast<double*>(smem),
+                                       state, picard);
 }
 
 // Mortar part of the diagonal, Alg. Alg-diagonal: the unit vector of own DoF
@@ -2605,6 +2703,11 @@ static int do_gather(mns_handle* h, const Real* E, const Real* Em, const Real* s
 // and still runs 1.6x faster than the LDS-plane layout)
 template <typename Real, int DIM, int N>
 constexpr bool kQuadLayout = DIM == 3 && (N == 3 || N == 4);
+// linearization source C in the quad kernels: FP32 at degrees 2 and 3, FP64
+// at degree 2 (state point values in LDS next to the increment's, 32 KB per
+// wavefront; at degree 3 they would need 57 KB)
+template <typename Real, int DIM, int N>
+constexpr bool kLinCLayout = kQuadLayout<Real, DIM, N> && (sizeof(Real) == 4 || N == 3);
 
 template <typename Real, int DIM, int N>
 static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s, Real* E_ws = nullptr,
@@ -2618,6 +2721,13 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
   Real* Em = Em_ws ? Em_ws : (sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32);
   constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   const bool quad = kQuad && h->quad;
+  // linearization source C (tau and tau R per point, a and grad u from the
+  // state) where the quad kernels have it
+  constexpr bool kLinC = kLinCLayout<Real, DIM, N>;
+  const bool linc = kLinC && quad && h->lin_src[sizeof(Real) == 8 ? 0 : 1] == 1 && h->d_linc64;
+  const Real* state = sizeof(Real) == 8 ? (const Real*)h->d_state : (const Real*)h->d_state32;
+  if (linc) lin = sizeof(Real) == 8 ? (const Real*)h->d_linc64 : (const Real*)h->d_linc32;
+  const int picard = h->lin_picard;
   // strip layout of the local results: batches of 16 cells stay inside one
   // ring when the ring length is a multiple of 16
   const int strip = (quad && h->nth[0] % 16 == 0 && h->nth[1] % 16 == 0) ? 1 : 0;
@@ -2640,11 +2750,21 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
         if constexpr (sizeof(Real) == 8 && N == 3) {
           using MSL = MortarShape<Real, DIM, N, kLdsQuadBytes>;
           const int nml = (int)((2u * (unsigned)(G.nth[0] * G.nz) + MSL::FPB - 1) / MSL::FPB);
-          launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad_lds<N>, dim3(blocks + nml), dim3(64), s, G, T, h->k, nml,
-                   lin, M, mtrig, src, E, Em, strip);
+          if (linc)
+            launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad_lds<N, true>, dim3(blocks + nml), dim3(64), s, G, T, h->k,
+                     nml, lin, M, mtrig, src, E, Em, strip, state, picard);
+          else
+            launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad_lds<N, false>, dim3(blocks + nml), dim3(64), s, G, T,
+                     h->k, nml, lin, M, mtrig, src, E, Em, strip, state, picard);
         } else {
-          launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k,
-                   nmb, lin, M, mtrig, src, E, Em, strip);
+          if constexpr (kLinC) {
+            if (linc)
+              launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N, true>, dim3(blocks + nmb), dim3(64), s, G, T,
+                       h->k, nmb, lin, M, mtrig, src, E, Em, strip, state, picard);
+          }
+          if (!linc)
+            launch_k(h, TIMER_VOLUME, k_jacobian_fused_quad<Real, N, false>, dim3(blocks + nmb), dim3(64), s, G, T,
+                     h->k, nmb, lin, M, mtrig, src, E, Em, strip, state, picard);
         }
       }
     }
@@ -2668,9 +2788,14 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
       if (rc) return rc;
     }
     if constexpr (kQuad) {
-      if (quad)
-        launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E,
-                 strip);
+      if constexpr (kLinC) {
+        if (linc)
+          launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N, true>, dim3(blocks), dim3(64), s, G, T, h->k, lin,
+                   src, E, strip, state, picard);
+      }
+      if (quad && !linc)
+        launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N, false>, dim3(blocks), dim3(64), s, G, T, h->k, lin,
+                 src, E, strip, state, picard);
     }
     if (!quad)
       launch_k(h, TIMER_VOLUME, k_jacobian_volume<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E);
@@ -2972,6 +3097,33 @@ int launch_jacobian_noalloc(mns_handle* h, const Real* src, Real* dst, hipStream
 }
 template int launch_jacobian_noalloc<double>(mns_handle*, const double*, double*, hipStream_t);
 template int launch_jacobian_noalloc<float>(mns_handle*, const float*, float*, hipStream_t);
+
+// tau and tau R of every point (linearization source C) from the full store,
+// in FP64 and FP32
+__global__ void k_lin_compact(const double* __restrict__ lin, long long npts, double* __restrict__ c64,
+                              float* __restrict__ c32) {
+  using LL = LinLayout<3>;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
+    const double* l = lin + p * LL::SIZE;
+    const double v[4] = {l[LL::TAU], l[LL::TR], l[LL::TR + 1], l[LL::TR + 2]};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c64[p * 4 + j] = v[j];
+      c32[p * 4 + j] = (float)v[j];
+    }
+  }
+}
+
+int launch_lin_compact(mns_handle* h, hipStream_t s) {
+  if (!h->d_linc64) return MNS_OK;
+  const long long npts = (long long)h->ncells * h->n * h->n * h->n;
+  long long b = (npts + 255) / 256;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_lin_compact, dim3((unsigned)b), dim3(256), 0, s, (const double*)h->d_lin64, npts, h->d_linc64,
+                     h->d_linc32);
+  return hip_check(h, "linearization C kernel");
+}
 
 template <int DIM, int N, bool RES>
 static int do_state(mns_handle* h, const double* state, const double* hist, const double* force, double* lin,

@@ -290,6 +290,15 @@ int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h) 
       (e = hipMalloc((void**)&h->d_lin32, nlin * sizeof(float))) != hipSuccess ||
       (e = hipMalloc((void**)&h->d_state, (size_t)h->ndofs * sizeof(double))) != hipSuccess)
     return hipfail(h, e, "hipMalloc linearization store");
+  // linearization source C (3D, degrees 2 and 3): tau and tau R per point
+  // and an FP32 copy of the state
+  if (d->dim == 3 && (d->degree == 2 || d->degree == 3)) {
+    const size_t nc4 = (size_t)h->ncells * npt * 4;
+    if ((e = hipMalloc((void**)&h->d_linc64, nc4 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&h->d_linc32, nc4 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc((void**)&h->d_state32, (size_t)h->ndofs * sizeof(float))) != hipSuccess)
+      return hipfail(h, e, "hipMalloc linearization store C");
+  }
   // second stream (default priority) and fork/join events of the concurrent
   // launch mode, created here so that no apply call creates them
   if ((e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking)) != hipSuccess ||

@@ -44,7 +44,8 @@ def run(args):
     state = torch.from_numpy(inputs.state_for(name)).cuda()
     x = torch.from_numpy(inputs.vector_for(name)).cuda().to(dtype)
     with binding.Operator(mesh) as op:
-        op.set_kernel_config(fused_launch=args.fused, volume_layout=args.volume_layout)
+        op.set_kernel_config(fused_launch=args.fused, volume_layout=args.volume_layout,
+                             lin_source_f64=args.lin_source, lin_source_f32=args.lin_source)
         op.rotate_rotor(inputs.rotor_angle(name), mesh["omega"])
         op.set_linearization(state)
         y = torch.empty_like(x)
@@ -125,6 +126,9 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--fused", type=int, default=-1)
     ap.add_argument("--volume-layout", type=int, default=1)
+    ap.add_argument("--lin-source", type=int, default=0, choices=[0, 1],
+                    help="linearization source of the quad volume kernels: 0 = B (full per-point store), "
+                         "1 = C (tau and tau R per point, a and grad u from the state)")
     ap.add_argument("--summarize", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
     ap.add_argument("--traffic-out", default=None)
     args = ap.parse_args()

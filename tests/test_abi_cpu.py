@@ -83,7 +83,8 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_bench_roofline_bookkeeping():
     """The bench's roofline bookkeeping on the workloads: algorithmic bytes per
-    launch (src + dst once, 16 FP64 values per Gauss point) and the name of the
+    launch (src + dst once, 16 FP64 values per Gauss point; source C: 4 values
+    per point and the state's velocity) and the name of the
     launch its volume timer brackets under the automatic launch mode (fused
     below 262,144 cells, the volume kernel beside a second-stream mortar
     launch from there on; degree-2 FP64 fused launch in its LDS-staged form)."""
@@ -96,14 +97,21 @@ def test_bench_roofline_bookkeeping():
     c2 = inputs.mesh("annulus3d_q2_64x8x32")
     b, cells = bench.algorithmic_bytes_volume(c2, inputs.n_dofs(c2), 8)
     assert (b, cells) == (131350528, 32768)
-    assert bench.dominant_kernel(c2, -1, 1) == "mns::k_jacobian_fused_quad_lds<3>"
-    assert bench.dominant_kernel(c2, -1, 1, "float") == "mns::k_jacobian_fused_quad<float, 3>"
-    assert bench.dominant_kernel(c2, 0, 1) == "mns::k_jacobian_volume_quad<double, 3>"
+    assert bench.dominant_kernel(c2, -1, 1) == "mns::k_jacobian_fused_quad_lds<3, false>"
+    assert bench.dominant_kernel(c2, -1, 1, "double", 1) == "mns::k_jacobian_fused_quad_lds<3, true>"
+    assert bench.dominant_kernel(c2, -1, 1, "float") == "mns::k_jacobian_fused_quad<float, 3, false>"
+    assert bench.dominant_kernel(c2, 0, 1) == "mns::k_jacobian_volume_quad<double, 3, false>"
     assert bench.dominant_kernel(c2, -1, 0) == "mns::k_jacobian_fused<double, 3, 3>"
+    # source C: src + dst + the state's velocity once, 4 values per Gauss point
+    n2 = inputs.n_dofs(c2)
+    assert bench.algorithmic_bytes_volume(c2, n2, 8, 1)[0] == (2.75 * n2 + 4 * 27 * 32768) * 8
     c5 = inputs.mesh("annulus3d_q2_256x32x128")
     assert bench.algorithmic_bytes_volume(c5, inputs.n_dofs(c5), 8)[0] == 8342536192
-    assert bench.dominant_kernel(c5, -1, 1) == "mns::k_jacobian_volume_quad<double, 3>"
+    assert bench.dominant_kernel(c5, -1, 1) == "mns::k_jacobian_volume_quad<double, 3, false>"
     c3 = inputs.mesh("annulus3d_q3_64x16x32")
-    assert bench.dominant_kernel(c3, -1, 1) == "mns::k_jacobian_fused_quad<double, 4>"
+    assert bench.dominant_kernel(c3, -1, 1) == "mns::k_jacobian_fused_quad<double, 4, false>"
+    # degree 3 has source C in FP32 only
+    assert bench.dominant_kernel(c3, -1, 1, "double", 1) == "mns::k_jacobian_fused_quad<double, 4, false>"
+    assert bench.dominant_kernel(c3, -1, 1, "float", 1) == "mns::k_jacobian_fused_quad<float, 4, true>"
     c1 = inputs.mesh("annulus2d_q2_32x4")
     assert bench.dominant_kernel(c1, -1, 1) == "mns::k_jacobian_fused<double, 2, 3>"
