@@ -12,10 +12,14 @@
 // one probed node that it couples to.  Constrained rows and columns come out
 // as the identity, as in mns_apply_jacobian.
 //
-// Factorization: right-looking blocked LU with partial pivoting (panel of 64
-// columns factored by one workgroup, triangular solve of the panel rows, FP64
-// tiled update of the trailing matrix), then the explicit inverse from
-// P A = L U by the same blocked triangular solves with the identity as right-hand
+// Factorization: right-looking blocked LU with partial pivoting.  Blocks of
+// 64 columns; each block is factored as sub-panels of 8 (4 above 4,096 rows)
+// columns held in the registers of one 1024-thread workgroup, each followed
+// by its row interchanges on the rest of the block, the triangular solve of
+// its rows and the rank-8 update of the block's remaining columns; then the
+// block's interchanges on every other column, the triangular solve of its 64
+// rows and the FP64 tiled update of the trailing matrix.  The explicit inverse
+// follows from P A = L U by blocked triangular solves with P as right-hand
 // side.  Each coarse solve is then one FP64 matrix-vector product (two-stage,
 // fixed order), which runs on many workgroups, unlike a triangular solve.
 #include <hip/hip_runtime.h>
@@ -69,84 +73,149 @@ __global__ void k_zero_mat(double* __restrict__ X, int n, long long ldx) {
     X[i % n + (i / n) * ldx] = 0.0;
 }
 
-__global__ void k_identity(double* __restrict__ X, int n, long long ldx) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const long long count = (long long)n * n;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-    const long long c = i / n, r = i % n;
-    X[r + c * ldx] = r == c ? 1.0 : 0.0;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Blocked LU with partial pivoting, column-major A (lda), in place
 // ---------------------------------------------------------------------------
 
-// Panel [k, k + nb) factored by one workgroup: per column the pivot (largest
-// magnitude, smallest row index among equals), the swap of the two whole
-// rows (all n columns, so the rows left and right of the panel follow), the
-// scaling of the column below the diagonal and the rank-1 update of the rest
-// of the panel.  piv[c] = pivot row of column c; *info = first zero pivot + 1.
-__global__ __launch_bounds__(1024) void k_lu_panel(double* __restrict__ A, int n, long long lda, int k, int nb,
-                                                   int* __restrict__ piv, int* __restrict__ info) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  const int t = threadIdx.x, T = blockDim.x;
-  for (int c = k; c < k + nb; ++c) {
+// Sub-panel [c0, c0 + w) (w <= PW) of rows [c0, n) factored by one
+// workgroup of 1024 threads with the panel in registers: thread t owns rows
+// c0 + t + 1024 r (r < R).  Per column: the pivot (largest magnitude,
+// smallest row index among equals), the exchange of the two rows inside the
+// sub-panel through LDS, the scaling of the column below the diagonal by the
+// pivot's reciprocal and the rank-1 update of the sub-panel's later columns.
+// piv[c] = pivot row of column c; *info = first zero pivot + 1.  Rows are
+// exchanged only within the sub-panel; k_laswp applies the interchanges to
+// the other columns.
+constexpr int kLuThreads = 1024;
+
+template <int R, int PW>
+__global__ __launch_bounds__(kLuThreads) void k_lu_panel(double* __restrict__ A, int n, long long lda, int c0, int w,
+                                                         int* __restrict__ piv, int* __restrict__ info) {
+  __shared__ double wbest[kLuThreads / 64];
+  __shared__ int wrow[kLuThreads / 64];
+  __shared__ double prow[PW], srow[PW];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double a[R][PW];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = c0 + t + kLuThreads * r;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) a[r][j] = (i < n && j < w) ? A[i + (long long)(c0 + j) * lda] : 0.0;
+  }
+#pragma unroll
+  for (int cc = 0; cc < PW; ++cc) {
+    if (cc < w) {  // uniform across the workgroup
+    const int c = c0 + cc;
+    // pivot search over rows i >= c
     double best = -1.0;
     int bi = n;
-    for (int i = c + t; i < n; i += T) {
-      const double v = fabs(A[i + (long long)c * lda]);
-      if (v > best || (v == best && i < bi)) {
-        best = v;
-        bi = i;
-      }
-    }
-    sv[t] = best;
-    si[t] = bi;
-    __syncthreads();
-    for (int off = T / 2; off > 0; off >>= 1) {
-      if (t < off) {
-        const double v = sv[t + off];
-        const int ii = si[t + off];
-        if (v > sv[t] || (v == sv[t] && ii < si[t])) {
-          sv[t] = v;
-          si[t] = ii;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = c0 + t + kLuThreads * r;
+      if (i >= c && i < n) {
+        const double v = fabs(a[r][cc]);
+        if (v > best || (v == best && i < bi)) {
+          best = v;
+          bi = i;
         }
       }
-      __syncthreads();
     }
-    const int p = si[0];
-    const double pv = sv[0];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v = __shfl_xor(best, off, 64);
+      const int ii = __shfl_xor(bi, off, 64);
+      if (v > best || (v == best && ii < bi)) {
+        best = v;
+        bi = ii;
+      }
+    }
+    if (lane == 0) {
+      wbest[wv] = best;
+      wrow[wv] = bi;
+    }
     __syncthreads();
+    double pv = wbest[0];
+    int p = wrow[0];
+#pragma unroll
+    for (int q = 1; q < kLuThreads / 64; ++q)
+      if (wbest[q] > pv || (wbest[q] == pv && wrow[q] < p)) {
+        pv = wbest[q];
+        p = wrow[q];
+      }
+    if (p >= n) p = c;  // no comparable candidate (NaN column): keep the row; info flags it below
+    // exchange rows c and p inside the sub-panel
+    const int tc = (c - c0) % kLuThreads, rc = (c - c0) / kLuThreads;
+    const int tp = (p - c0) % kLuThreads, rp = (p - c0) / kLuThreads;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (t == tp && r == rp)
+#pragma unroll
+        for (int j = 0; j < PW; ++j) prow[j] = a[r][j];
+      if (t == tc && r == rc)
+#pragma unroll
+        for (int j = 0; j < PW; ++j) srow[j] = a[r][j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (t == tp && r == rp)
+#pragma unroll
+        for (int j = 0; j < PW; ++j) a[r][j] = srow[j];
+      if (t == tc && r == rc)  // after the line above, so that p == c keeps the row
+#pragma unroll
+        for (int j = 0; j < PW; ++j) a[r][j] = prow[j];
+    }
     if (t == 0) {
       piv[c] = p;
       if (!(pv > 0.0) && *info == 0) *info = c + 1;
     }
-    if (p != c)
-      for (int j = t; j < n; j += T) {
-        const double a = A[c + (long long)j * lda], b = A[p + (long long)j * lda];
-        A[c + (long long)j * lda] = b;
-        A[p + (long long)j * lda] = a;
-      }
-    __syncthreads();
-    const double d = A[c + (long long)c * lda];
+    // scale the column below the diagonal, update the later columns
+    const double d = prow[cc];
     const double inv = d != 0.0 ? 1.0 / d : 0.0;
-    for (int i = c + 1 + t; i < n; i += T) A[i + (long long)c * lda] *= inv;
-    __syncthreads();
-    for (int i = c + 1 + t; i < n; i += T) {
-      const double l = A[i + (long long)c * lda];
-      for (int j = c + 1; j < k + nb; ++j) A[i + (long long)j * lda] -= l * A[c + (long long)j * lda];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = c0 + t + kLuThreads * r;
+      if (i > c && i < n) {
+        const double l = a[r][cc] * inv;
+        a[r][cc] = l;
+#pragma unroll
+        for (int j = cc + 1; j < PW; ++j) a[r][j] -= l * prow[j];
+      }
     }
-    __syncthreads();
+    __syncthreads();  // prow, srow and the reduction slots are rewritten next column
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = c0 + t + kLuThreads * r;
+#pragma unroll
+    for (int j = 0; j < PW; ++j)
+      if (i < n && j < w) A[i + (long long)(c0 + j) * lda] = a[r][j];
   }
 }
 
-// Triangular solve with the nb x nb diagonal block D of a factor held in F
-// (rows/cols [k, k + nb)): X[k .. k + nb, j] = D^-1 X[k .. k + nb, j] for every
-// column j in [j0, j1) of X (ldx).  lower: D unit lower triangular (forward);
-// otherwise D upper triangular with its diagonal (backward).  One thread per
-// column, D in LDS.
+// the interchanges of columns [c0, c0 + w) (piv) applied, in order, to the
+// columns j in [j0, j1) outside [c0, c0 + w); one thread per column
+__global__ void k_laswp(double* __restrict__ A, long long lda, int c0, int w, const int* __restrict__ piv, int j0,
+                        int j1) {
+  const int j = j0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= j1 || (j >= c0 && j < c0 + w)) return;
+  double* col = A + (long long)j * lda;
+  for (int c = c0; c < c0 + w; ++c) {
+    const int p = piv[c];
+    if (p != c) {
+      const double x = col[c];
+      col[c] = col[p];
+      col[p] = x;
+    }
+  }
+}
+
+// Triangular solve with the nb x nb (nb <= 64) diagonal block D of a factor
+// held in F (rows/cols [k, k + nb)): X[k .. k + nb, j] = D^-1 X[k .. k + nb, j]
+// for every column j in [j0, j1) of X (ldx).  lower: D unit lower triangular
+// (forward); otherwise D upper triangular with its diagonal (backward).  One
+// wavefront per column (lane = row of the block, the solved entry broadcast
+// by a lane shuffle), D in LDS.
 __global__ __launch_bounds__(256) void k_trsm_block(const double* __restrict__ F, long long ldf, int k, int nb,
                                                     double* __restrict__ X, long long ldx, int j0, int j1,
                                                     int lower) {
@@ -156,35 +225,25 @@ __global__ __launch_bounds__(256) void k_trsm_block(const double* __restrict__ F
     D[r][c] = F[(k + r) + (long long)(k + c) * ldf];
   }
   __syncthreads();
-  const int j = j0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= j1) return;
-  double x[kNB];
-  double* col = X + (long long)j * ldx + k;
-#pragma unroll
-  for (int r = 0; r < kNB; ++r) x[r] = r < nb ? col[r] : 0.0;
-  if (lower) {
-#pragma unroll
-    for (int r = 0; r < kNB; ++r) {
-      double s = x[r];
-#pragma unroll
-      for (int q = 0; q < kNB; ++q)
-        if (q < r) s -= D[r][q] * x[q];
-      if (r < nb) x[r] = s;
+  const int lane = threadIdx.x & 63;
+  const int waves = blockDim.x >> 6;
+  for (int j = j0 + blockIdx.x * waves + (threadIdx.x >> 6); j < j1; j += gridDim.x * waves) {
+    double* col = X + (long long)j * ldx + k;
+    double x = lane < nb ? col[lane] : 0.0;
+    if (lower) {
+      for (int c = 0; c + 1 < nb; ++c) {
+        const double xc = __shfl(x, c, 64);
+        if (lane > c && lane < nb) x -= D[lane][c] * xc;
+      }
+    } else {
+      for (int c = nb - 1; c >= 0; --c) {
+        const double xc = __shfl(x, c, 64) / D[c][c];
+        if (lane == c) x = xc;
+        else if (lane < c) x -= D[lane][c] * xc;
+      }
     }
-  } else {
-#pragma unroll
-    for (int r = kNB - 1; r >= 0; --r) {
-      if (r >= nb) continue;
-      double s = x[r];
-#pragma unroll
-      for (int q = 0; q < kNB; ++q)
-        if (q > r && q < nb) s -= D[r][q] * x[q];
-      x[r] = s / D[r][r];
-    }
+    if (lane < nb) col[lane] = x;
   }
-#pragma unroll
-  for (int r = 0; r < kNB; ++r)
-    if (r < nb) col[r] = x[r];
 }
 
 // C[m x nn] -= L[m x kk] * U[kk x nn] (column-major, kk <= 64), 64 x 64 output
@@ -195,10 +254,11 @@ __global__ __launch_bounds__(256) void k_gemm_sub(const double* __restrict__ L, 
   __shared__ double Ls[kNB][kNB + 1];
   __shared__ double Us[kNB][kNB + 1];
   const int i0 = blockIdx.x * kNB, j0 = blockIdx.y * kNB;
-  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
-    const int r = e % kNB, c = e / kNB;
-    Ls[r][c] = (i0 + r < m && c < kk) ? L[(i0 + r) + (long long)c * ldl] : 0.0;
-    Us[r][c] = (r < kk && j0 + c < nn) ? U[r + (long long)(j0 + c) * ldu] : 0.0;
+  for (int e = threadIdx.x; e < kNB * kk; e += blockDim.x) {
+    const int r = e % kNB, c = e / kNB;  // L tile: row r, column c < kk
+    Ls[r][c] = i0 + r < m ? L[(i0 + r) + (long long)c * ldl] : 0.0;
+    const int ur = e % kk, uc = e / kk;  // U tile: row ur < kk, column uc
+    Us[ur][uc] = j0 + uc < nn ? U[ur + (long long)(j0 + uc) * ldu] : 0.0;
   }
   __syncthreads();
   const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
@@ -230,18 +290,31 @@ __global__ __launch_bounds__(256) void k_gemm_sub(const double* __restrict__ L, 
   }
 }
 
-// row interchanges of the factorization applied to X (every column), in order
-__global__ void k_apply_pivots(const int* __restrict__ piv, int n, double* __restrict__ X, long long ldx, int ncols) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncols) return;
-  double* col = X + (long long)j * ldx;
-  for (int c = 0; c < n; ++c) {
-    const int p = piv[c];
-    if (p != c) {
-      const double a = col[c];
-      col[c] = col[p];
-      col[p] = a;
+// the row interchanges of the factorization, in order, as one permutation:
+// row r of P A is row perm[r] of A (one workgroup; perm built in LDS)
+constexpr int kMaxCoarseN = 8192;
+__global__ __launch_bounds__(1024) void k_pivots_to_perm(const int* __restrict__ piv, int n, int* __restrict__ perm) {
+  __shared__ int pm[kMaxCoarseN];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) pm[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < n; ++c) {
+      const int p = piv[c];
+      const int x = pm[c];
+      pm[c] = pm[p];
+      pm[p] = x;
     }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = pm[i];
+}
+
+// X = P I: X(r, perm[r]) = 1, every other entry 0
+__global__ void k_perm_identity(const int* __restrict__ perm, int n, double* __restrict__ X, long long ldx) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long count = (long long)n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const long long c = i / n, r = i % n;
+    X[r + c * ldx] = perm[r] == c ? 1.0 : 0.0;
   }
 }
 
@@ -333,6 +406,7 @@ struct CoarseDirect {
   double* part = nullptr; // partial sums of the matrix-vector product / check
   double* work = nullptr; // probe and result vectors
   int* piv = nullptr;
+  int* perm = nullptr;    // the pivots as one row permutation
   int* info = nullptr;
   int* colors = nullptr;  // node colour
   int* owners = nullptr;  // [colour][node]: probed node coupled to the node, or -1
@@ -343,8 +417,8 @@ struct CoarseDirect {
 void coarse_free(void* p) {
   auto* C = (CoarseDirect*)p;
   if (!C) return;
-  for (void* q : {(void*)C->A, (void*)C->Ainv, (void*)C->part, (void*)C->work, (void*)C->piv, (void*)C->info,
-                  (void*)C->colors, (void*)C->owners})
+  for (void* q : {(void*)C->A, (void*)C->Ainv, (void*)C->part, (void*)C->work, (void*)C->piv, (void*)C->perm,
+                  (void*)C->info, (void*)C->colors, (void*)C->owners})
     if (q) (void)hipFree(q);
   delete C;
 }
@@ -466,29 +540,82 @@ int assemble_dense(mns_handle* hc, double* A, long long lda, double* work, int**
   return MNS_OK;
 }
 
+template <int R, int PW>
+static void launch_panel(CoarseDirect* C, int n, long long lda, int c0, int w, hipStream_t s) {
+  hipLaunchKernelGGL((k_lu_panel<R, PW>), dim3(1), dim3(kLuThreads), 0, s, C->A, n, lda, c0, w, C->piv, C->info);
+}
+
+// one sub-panel factorization: rows [c0, n) need R = ceil((n - c0) / 1024)
+// rows per thread; sub-panels are 8 columns wide up to 4,096 rows, 4 above
+static void panel(CoarseDirect* C, int n, long long lda, int c0, int w, int pw, hipStream_t s) {
+  const int R = (n - c0 + kLuThreads - 1) / kLuThreads;
+  if (pw == 8) {
+    switch (R) {
+      case 1: launch_panel<1, 8>(C, n, lda, c0, w, s); break;
+      case 2: launch_panel<2, 8>(C, n, lda, c0, w, s); break;
+      case 3: launch_panel<3, 8>(C, n, lda, c0, w, s); break;
+      default: launch_panel<4, 8>(C, n, lda, c0, w, s); break;
+    }
+  } else {
+    switch (R) {
+      case 1: launch_panel<1, 4>(C, n, lda, c0, w, s); break;
+      case 2: launch_panel<2, 4>(C, n, lda, c0, w, s); break;
+      case 3: launch_panel<3, 4>(C, n, lda, c0, w, s); break;
+      case 4: launch_panel<4, 4>(C, n, lda, c0, w, s); break;
+      case 5: launch_panel<5, 4>(C, n, lda, c0, w, s); break;
+      case 6: launch_panel<6, 4>(C, n, lda, c0, w, s); break;
+      case 7: launch_panel<7, 4>(C, n, lda, c0, w, s); break;
+      default: launch_panel<8, 4>(C, n, lda, c0, w, s); break;
+    }
+  }
+}
+
+static unsigned trsm_grid(int cols) { return (unsigned)std::max(1, std::min(4096, (cols + 3) / 4)); }
+
 // blocked LU of C->A in place, then C->Ainv = A^-1 from P A = L U
 static int lu_invert(mns_handle* h, CoarseDirect* C, hipStream_t s) {
   const int n = C->n;
   const long long lda = C->lda;
+  if (n > kMaxCoarseN) return set_error(h, MNS_ERR_UNSUPPORTED, "coarse level too large for the direct solve");
+  const int pw = n <= 4 * kLuThreads ? 8 : 4;
   hipLaunchKernelGGL(k_fill_mat, dim3(1), dim3(64), 0, s, (double*)C->info, 1, 0.0);  // zero the info word
   for (int k = 0; k < n; k += kNB) {
-    const int nb = std::min(kNB, n - k);
-    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, s, C->A, n, lda, k, nb, C->piv, C->info);
-    const int rest = n - k - nb;
+    const int kend = std::min(n, k + kNB), nb = kend - k;
+    // the block's columns, sub-panel by sub-panel
+    for (int c0 = k; c0 < kend; c0 += pw) {
+      const int w = std::min(pw, kend - c0), c1 = c0 + w;
+      panel(C, n, lda, c0, w, pw, s);
+      if (nb > w)
+        hipLaunchKernelGGL(k_laswp, dim3((nb + 63) / 64), dim3(64), 0, s, C->A, lda, c0, w, (const int*)C->piv, k,
+                           kend);
+      if (c1 < kend) {
+        hipLaunchKernelGGL(k_trsm_block, dim3(trsm_grid(kend - c1)), dim3(256), 0, s, (const double*)C->A, lda, c0,
+                           w, C->A, lda, c1, kend, 1);
+        if (n > c1)
+          hipLaunchKernelGGL(k_gemm_sub, dim3((n - c1 + kNB - 1) / kNB, (kend - c1 + kNB - 1) / kNB), dim3(256), 0, s,
+                             (const double*)(C->A + c1 + (long long)c0 * lda), lda,
+                             (const double*)(C->A + c0 + (long long)c1 * lda), lda, C->A + c1 + (long long)c1 * lda,
+                             lda, n - c1, kend - c1, w);
+      }
+    }
+    // the block's interchanges on every other column, then the trailing update
+    if (n > nb)
+      hipLaunchKernelGGL(k_laswp, dim3((n + 255) / 256), dim3(256), 0, s, C->A, lda, k, nb, (const int*)C->piv, 0, n);
+    const int rest = n - kend;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_trsm_block, dim3((rest + 255) / 256), dim3(256), 0, s, (const double*)C->A, lda, k, nb,
-                         C->A, lda, k + nb, n, 1);
+      hipLaunchKernelGGL(k_trsm_block, dim3(trsm_grid(rest)), dim3(256), 0, s, (const double*)C->A, lda, k, nb, C->A,
+                         lda, kend, n, 1);
       hipLaunchKernelGGL(k_gemm_sub, dim3((rest + kNB - 1) / kNB, (rest + kNB - 1) / kNB), dim3(256), 0, s,
-                         (const double*)(C->A + (k + nb) + (long long)k * lda), lda,
-                         (const double*)(C->A + k + (long long)(k + nb) * lda), lda,
-                         C->A + (k + nb) + (long long)(k + nb) * lda, lda, rest, rest, nb);
+                         (const double*)(C->A + kend + (long long)k * lda), lda,
+                         (const double*)(C->A + k + (long long)kend * lda), lda, C->A + kend + (long long)kend * lda,
+                         lda, rest, rest, nb);
     }
   }
   // X = P I, then L Y = X (forward, blocked), then U Ainv = Y (backward, blocked)
   double* X = C->Ainv;
-  hipLaunchKernelGGL(k_identity, dim3(1024), dim3(256), 0, s, X, n, lda);
-  hipLaunchKernelGGL(k_apply_pivots, dim3((n + 255) / 256), dim3(256), 0, s, (const int*)C->piv, n, X, lda, n);
-  const unsigned gcols = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_pivots_to_perm, dim3(1), dim3(1024), 0, s, (const int*)C->piv, n, C->perm);
+  hipLaunchKernelGGL(k_perm_identity, dim3(1024), dim3(256), 0, s, (const int*)C->perm, n, X, lda);
+  const unsigned gcols = trsm_grid(n);
   for (int k = 0; k < n; k += kNB) {
     const int nb = std::min(kNB, n - k);
     hipLaunchKernelGGL(k_trsm_block, dim3(gcols), dim3(256), 0, s, (const double*)C->A, lda, k, nb, X, lda, 0, n, 1);
@@ -533,6 +660,7 @@ int coarse_setup(mns_handle* hc, void** state, hipStream_t s, int max_dofs) {
         (e = hipMalloc((void**)&C->part, ((size_t)parts * n + 1024) * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&C->work, 3 * (size_t)n * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&C->piv, (size_t)n * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&C->perm, (size_t)n * sizeof(int))) != hipSuccess ||
         (e = hipMalloc((void**)&C->info, 2 * sizeof(int))) != hipSuccess ||
         (e = hipMalloc((void**)&C->colors, (size_t)hc->nnodes * sizeof(int))) != hipSuccess) {
       coarse_free(C);
