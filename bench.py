@@ -151,7 +151,7 @@ def measured_traffic(workload, kernel):
     rec = {}
     for line in open(path):
         if ":" in line and not line.startswith((" ", "#", "|")):
-            key, val = line.split(":", 1)
+            key, val = line.rsplit(":", 1)  # kernel names in the keys hold "::"
             rec[key.strip()] = val.strip()
     if rec.get("kernel_source_sha256") != kernel_source_digest():
         return None, None

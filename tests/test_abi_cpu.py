@@ -115,3 +115,30 @@ def test_bench_roofline_bookkeeping():
     assert bench.dominant_kernel(c3, -1, 1, "float", 1) == "mns::k_jacobian_fused_quad<float, 4, true>"
     c1 = inputs.mesh("annulus2d_q2_32x4")
     assert bench.dominant_kernel(c1, -1, 1) == "mns::k_jacobian_fused<double, 2, 3>"
+
+
+def test_bench_traffic_summary_parsing(tmp_path, monkeypatch):
+    """bench.measured_traffic reads the per-application and per-launch HBM
+    bytes of a counter summary whose keys hold kernel names with '::', and
+    returns nothing once the kernel source digest no longer matches."""
+    import sys
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    digest = bench.kernel_source_digest()
+    (prof / "traffic_w.txt").write_text(
+        "# comment: with a colon\n"
+        f"kernel_source_sha256: {digest}\n"
+        "bytes_per_launch mns::k_a<double, 3, false>: 1000\n"
+        "read_write_per_launch mns::k_a<double, 3, false>: 600 400\n"
+        "vmult_bytes_per_call: 1500\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: digest)
+    assert bench.measured_traffic("w", "mns::k_a<double, 3, false>") == (1500.0, 1000.0)
+    assert bench.measured_traffic("w", "mns::k_b") == (1500.0, None)
+    assert bench.measured_traffic("missing", "mns::k_a") == (None, None)
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "other")
+    assert bench.measured_traffic("w", "mns::k_a<double, 3, false>") == (None, None)
