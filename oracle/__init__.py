@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
         ("theta_rot", ctypes.c_double), ("omega", ctypes.c_double),
         ("merged", ctypes.c_int), ("stabilization", ctypes.c_int), ("pin_pressure", ctypes.c_int),
         ("mms", ctypes.c_int), ("nthreads", ctypes.c_int), ("picard", ctypes.c_int),
-        ("n_theta_stator", ctypes.c_int),
+        ("n_theta_stator", ctypes.c_int), ("iso", ctypes.c_int), ("perturb", ctypes.c_double),
     ]
 
 
@@ -56,6 +56,7 @@ _DEFAULTS = dict(
     dim=2, degree=2, r_in=0.25, r_if=0.5, r_out=1.0, height=1.0, n_theta=8, n_r_rotor=1,
     n_r_stator=1, n_z=1, nu=0.01, penalty_F=1.0, penalty_rule=0, steady=1, dt=1.0, theta_rot=0.0,
     omega=0.0, merged=0, stabilization=1, pin_pressure=1, mms=0, nthreads=0, picard=0, n_theta_stator=0,
+    iso=0, perturb=0.0,
 )
 
 

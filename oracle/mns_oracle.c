@@ -77,6 +77,19 @@ typedef struct {
                          counts are the extension named in Sec. 3.1 and Sec. 5:
                          a face may then meet more than two faces of the other
                          side, every intersection being one mortar segment */
+  int iso;           /* 1: iso-parametric geometry (the Q_k mapping the paper's
+                        meshes use, Sec. 2.1): every cell is the Q_k
+                        interpolant of its node positions, which are the polar
+                        Gauss-Lobatto nodes moved by the interior perturbation
+                        below; 0: the exact polar map */
+  double perturb;    /* iso = 1: amplitude of the node perturbation in cell
+                        sizes (radial, angular and axial displacements that
+                        vanish on the walls and on the interface, so that these
+                        stay circles / planes through their nodes); a mesh
+                        whose map folds (det J zero or of the wrong sign at a
+                        Gauss-Lobatto point of a cell) is refused: a Q2 mid
+                        node moved by a quarter cell already makes the map
+                        singular on a face */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -205,6 +218,7 @@ typedef struct {
   seg_t *segs;
   unsigned char *cons; /* constrained DoF flags */
   double tau_side[2];  /* penalty used by side 0 (rotor) and 1 (stator) */
+  double *xnode;       /* iso: physical node positions [node][3] (rotor rotated) */
 } mesh_t;
 
 static void cell_radial(const mesh_t *M, int dom, int cr, double *r0, double *dr, int *rotor) {
@@ -262,8 +276,15 @@ static void cell_dofs(const mesh_t *M, const cell_t *c, long *dofs) {
 /*   x = r cos theta, y = r sin theta, z                                     */
 /* ------------------------------------------------------------------------ */
 
+static void geom_iso(const mesh_t *M, const cell_t *c, const double xi[3], double x[3], double J[3][3],
+                     double X2[3][3][3]);
+
 static void geom(const mesh_t *M, const cell_t *c, const double xi[3], double x[3], double J[3][3],
                  double X2[3][3][3]) {
+  if (M->xnode) {
+    geom_iso(M, c, xi, x, J, X2);
+    return;
+  }
   double th = c->th0 + c->dth * xi[0];
   double r = c->r0 + c->dr * xi[1];
   double ct = cos(th), st = sin(th);
@@ -283,6 +304,83 @@ static void geom(const mesh_t *M, const cell_t *c, const double xi[3], double x[
   X2[1][0][0] = -r * st * c->dth * c->dth;
   X2[0][0][1] = X2[0][1][0] = -st * c->dth * c->dr;
   X2[1][0][1] = X2[1][1][0] = ct * c->dth * c->dr;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: iso-parametric Q_k map (orc_params.iso)                         */
+/*   x(xi) = sum_a X_a phi_a(xi), X_a the cell's node positions, phi_a the    */
+/*   tensor Lagrange basis on the Gauss-Lobatto nodes; J and the Hessian of   */
+/*   the map follow from the basis derivatives.                               */
+/* ------------------------------------------------------------------------ */
+
+static void geom_iso(const mesh_t *M, const cell_t *c, const double xi[3], double x[3], double J[3][3],
+                     double X2[3][3][3]) {
+  const int n = M->n, d = M->d;
+  double L[3][MAXN], dL[3][MAXN], d2L[3][MAXN];
+  for (int dir = 0; dir < 3; ++dir)
+    if (dir < d) lagrange(n, M->gll, xi[dir], L[dir], dL[dir], d2L[dir]);
+  memset(x, 0, sizeof(double) * 3);
+  memset(J, 0, sizeof(double) * 9);
+  memset(X2, 0, sizeof(double) * 27);
+  for (int a = 0; a < M->nd; ++a) {
+    int ai[3];
+    local_idx(M, a, &ai[0], &ai[1], &ai[2]);
+    const double *X = M->xnode + 3 * cell_node(M, c, ai[0], ai[1], ai[2]);
+    double val = 1.0, g[3] = {0, 0, 0}, H[3][3] = {{0}};
+    for (int dir = 0; dir < d; ++dir) val *= L[dir][ai[dir]];
+    for (int p = 0; p < d; ++p) {
+      double v = 1.0;
+      for (int dir = 0; dir < d; ++dir) v *= (dir == p) ? dL[dir][ai[dir]] : L[dir][ai[dir]];
+      g[p] = v;
+      for (int q = 0; q < d; ++q) {
+        double h = 1.0;
+        for (int dir = 0; dir < d; ++dir) {
+          if (p == q && dir == p) h *= d2L[dir][ai[dir]];
+          else if (dir == p || dir == q) h *= dL[dir][ai[dir]];
+          else h *= L[dir][ai[dir]];
+        }
+        H[p][q] = h;
+      }
+    }
+    for (int m = 0; m < d; ++m) {
+      x[m] += X[m] * val;
+      for (int p = 0; p < d; ++p) {
+        J[m][p] += X[m] * g[p];
+        for (int q = 0; q < d; ++q) X2[m][p][q] += X[m] * H[p][q];
+      }
+    }
+  }
+}
+
+/* Physical position of local node (a0, a1, a2) of cell c for the
+ * iso-parametric mesh: the polar Gauss-Lobatto node (r, theta, z), moved in
+ * the material frame by
+ *   dr     = e dr_c  s(r) cos(3 theta_m + 2 pi z / H)
+ *   dtheta = e dth_c s(r) sin(2 theta_m) (1 + cos(2 pi z / H) / 2)
+ *   dz     = e dz    s(r) sin(theta_m) sin(pi z / H)           (3D)
+ * with theta_m the material angle and s(r) = sin(pi (r - r_a) / (r_b - r_a))
+ * on the node's domain [r_a, r_b] (rotor [r_in, R], stator [R, r_out]), so
+ * that walls, interface and the planes z = 0, H keep their nodes; rotor
+ * nodes are then rotated by theta_rot (x = R(theta) x0, Sec. 3.1). */
+static void node_position(const mesh_t *M, const cell_t *c, int a0, int a1, int a2, double X[3]) {
+  const orc_params *P = &M->P;
+  const double e = P->perturb;
+  const double rot = (!P->merged && c->dom == 0) ? P->theta_rot : 0.0;
+  const double thm = c->th0 - rot + c->dth * M->gll[a0];
+  const double r = c->r0 + c->dr * M->gll[a1];
+  const double z = (M->d == 3) ? c->z0 + c->dz * M->gll[a2] : 0.0;
+  const double H = (M->d == 3) ? P->height : 1.0;
+  const int rotor_side = r < P->r_if || (r == P->r_if && c->rotor);
+  const double ra = rotor_side ? P->r_in : P->r_if, rb = rotor_side ? P->r_if : P->r_out;
+  const double s = sin(M_PI * (r - ra) / (rb - ra));
+  const double zr = (M->d == 3) ? 2.0 * M_PI * z / H : 0.0;
+  const double dr = e * c->dr * s * cos(3.0 * thm + zr);
+  const double dt = e * c->dth * s * sin(2.0 * thm) * (1.0 + 0.5 * cos(zr));
+  const double dz = (M->d == 3) ? e * c->dz * s * sin(thm) * sin(M_PI * z / H) : 0.0;
+  const double rr = r + dr, th = thm + dt + rot;
+  X[0] = rr * cos(th);
+  X[1] = rr * sin(th);
+  X[2] = z + dz;
 }
 
 static double inverse(int d, double J[3][3], double Ji[3][3]) {
@@ -480,6 +578,39 @@ static int mesh_build(const orc_params *P, mesh_t *M) {
           c->z0 = cz * M->dz;
           c->dz = M->dz;
           c->iface = !P->merged && ((dm == 0 && cr == M->nr[0] - 1) || (dm == 1 && cr == 0));
+        }
+  if (P->iso) {
+    /* node positions of the iso-parametric mesh (each node written by every
+     * cell that holds it, with the same value up to rounding) */
+    M->xnode = (double *)calloc((size_t)M->nnodes * 3, sizeof(double));
+    if (!M->xnode) return -2;
+    for (long ci = 0; ci < M->ncells; ++ci) {
+      const cell_t *c = &M->cells[ci];
+      for (int a = 0; a < M->nd; ++a) {
+        int a0, a1, a2;
+        local_idx(M, a, &a0, &a1, &a2);
+        node_position(M, c, a0, a1, a2, M->xnode + 3 * cell_node(M, c, a0, a1, a2));
+      }
+    }
+  }
+  for (int dm = 0; dm < M->ndom; ++dm)
+    for (int cz = 0; cz < nz; ++cz)
+      for (int cr = 0; cr < M->nr[dm]; ++cr)
+        for (int ct = 0; ct < M->nth[dm]; ++ct) {
+          cell_t *c = &M->cells[M->coff[dm] + ct + (long)M->nth[dm] * (cr + (long)M->nr[dm] * cz)];
+          if (M->xnode) {
+            /* an iso-parametric cell must map one-to-one: det J keeps the sign
+             * of the polar map at every Gauss-Lobatto point (faces and corners
+             * included); the reference axes (theta, r, z) are left-handed, so
+             * that sign is negative */
+            for (int a = 0; a < M->nd; ++a) {
+              int a0, a1, a2;
+              local_idx(M, a, &a0, &a1, &a2);
+              double xi[3] = {M->gll[a0], M->gll[a1], M->gll[a2]}, x[3], J[3][3], X2[3][3][3], Ji[3][3];
+              geom(M, c, xi, x, J, X2);
+              if (!(inverse(M->d, J, Ji) < 0.0)) return -4;
+            }
+          }
           double V = cell_measure(M, c);
           c->h = (M->d == 2) ? 2.0 * sqrt(V / M_PI) : cbrt(6.0 * V / M_PI);
           if (c->iface) {
@@ -555,6 +686,7 @@ static void mesh_free(mesh_t *M) {
   free(M->cells);
   free(M->segs);
   free(M->cons);
+  free(M->xnode);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -11,6 +11,7 @@ import os
 import pytest
 
 import oracle
+from tests import test_oracle_iso as iso
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "mns_oracle.c")
@@ -103,6 +104,23 @@ MUTANTS = [
      "static void mortar_coef(const mesh_t *M, int side, const field_t *Fs, const field_t *Fo, const double nso[3],\n"
      "                        testcoef_t *C) {\n  const double ns[3] = {-nso[0], -nso[1], -nso[2]};\n",
      [(pins.test_discrete_mass_conservation, dict(dim=2)), (pins.test_pressure_nullspace_up_to_quadrature, {})]),
+    ("iso-parametric map without its Hessian",
+     "for (int q = 0; q < d; ++q) X2[m][p][q] += X[m] * H[p][q];",
+     "(void)H;",
+     [(iso.test_affine_fields_are_exact, dict(dim=2, k=2))]),
+    ("iso-parametric Jacobian accumulated transposed",
+     "J[m][p] += X[m] * g[p];",
+     "J[p][m] += X[m] * g[p];",
+     [(iso.test_affine_fields_are_exact, dict(dim=2, k=2))]),
+    ("node perturbation that does not vanish on the rotor's side of the interface",
+     "const double ra = rotor_side ? P->r_in : P->r_if, rb = rotor_side ? P->r_if : P->r_out;",
+     "const double ra = rotor_side ? P->r_in : P->r_if, rb = rotor_side ? P->r_out : P->r_out;",
+     [(iso.test_node_perturbation_keeps_boundaries, {}),
+      (iso.test_aligned_mortar_reduces_to_conforming_cg_on_perturbed_mesh, dict(dim=2))]),
+    ("rotor nodes of the iso-parametric mesh left unrotated",
+     "const double rr = r + dr, th = thm + dt + rot;",
+     "const double rr = r + dr, th = thm + dt;",
+     [(iso.test_mass_balance_on_iso_mesh, dict(dim=2)), (iso.test_mms_convergence_q2_perturbed_iso, {})]),
 ]
 
 
