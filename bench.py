@@ -49,6 +49,7 @@ def parse():
                     help="-1: automatic; 1: volume and mortar in one launch; 2: mortar on a second stream; 0: sequential")
     ap.add_argument("--volume-layout", type=int, default=1, help="1: lane quad per cell (3D, k = 2, 3); 0: LDS planes")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching leg (48 uneven instances)")
+    ap.add_argument("--no-iso", action="store_true", help="skip the curved-mesh (iso-parametric) leg")
     ap.add_argument("--no-copy-bandwidth", action="store_true", help="skip the device-copy bandwidth measurement")
     ap.add_argument("--transient", action="store_true",
                     help="also time one BDF2 + Newton step (transient workloads; rotor advances omega * dt)")
@@ -391,6 +392,102 @@ def vmult_leg(name, dev, sync, steps=100, warmup=10):
     return op, mesh, theta, out
 
 
+ISO_PERTURB = 0.1  # interior node displacement of the curved mesh, in cell sizes
+
+
+def algorithmic_bytes_iso(mesh, n_dofs, real_bytes):
+    """Minimum HBM bytes of one application on iso-parametric cells: src read
+    and dst written once, per point the linearization data (16 values in 3D,
+    9 in 2D) and the metric (inverse Jacobian, JxW and the mapping term of
+    the Laplacian: 13 values in 3D, 7 in 2D) read once."""
+    dim, k = mesh["dim"], mesh["degree"]
+    nz = mesh["n_z"] if dim == 3 else 1
+    cells = mesh["n_theta"] * (mesh["n_r_rotor"] + mesh["n_r_stator"]) * nz
+    per_point = (16 + 13) if dim == 3 else (9 + 7)
+    return (2 * n_dofs + per_point * (k + 1) ** dim * cells) * real_bytes, cells
+
+
+def iso_leg(name, dev, sync, steps=100, warmup=10):
+    """The workload on a curved mesh (every interior node moved by up to
+    ISO_PERTURB cells, inputs.iso_node_positions; cells are the Q_k
+    interpolants of their nodes): set-up times, FP64 and FP32 vmult with the
+    HIP-event time per application and per kernel class, the HBM roofline
+    against the iso algorithmic bytes, and a mixed-precision Jacobi-Chebyshev
+    FGMRES solve to 1e-8 next to the same solve on the polar mesh."""
+    import numpy as np
+    import torch
+
+    from paper_2608_27423_amd import binding, inputs
+
+    mesh = inputs.mesh(name)
+    theta = inputs.rotor_angle(name)
+    xyz = inputs.iso_node_positions(mesh, ISO_PERTURB)
+    op = binding.Operator(mesh)
+    out = {"workload": name, "perturb_cells": ISO_PERTURB}
+    _, t = timed(lambda: op.set_node_positions(xyz), sync)
+    out["set_node_positions_ms"] = 1e3 * t
+    state = torch.from_numpy(inputs.state_for(name)).to(dev)
+    op.rotate_rotor(theta, mesh["omega"])
+    op.set_linearization(state)
+    _, t = timed(lambda: op.rotate_rotor(theta, mesh["omega"]), sync)
+    out["rotate_rotor_ms"] = 1e3 * t
+    _, t = timed(lambda: op.set_linearization(state), sync)
+    out["set_linearization_ms"] = 1e3 * t
+    x = torch.from_numpy(inputs.vector_for(name)).to(dev)
+    n = x.numel()
+    for label, xx in (("fp64", x), ("fp32", x.float())):
+        y = torch.empty_like(xx)
+        for _ in range(warmup):
+            op.apply_jacobian(xx, y)
+        sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            op.apply_jacobian(xx, y)
+        e1.record()
+        sync()
+        ms = e0.elapsed_time(e1) / steps
+        op.enable_timing(steps)
+        for _ in range(steps):
+            op.apply_jacobian(xx, y)
+        sync()
+        tt = op.read_timing()
+        op.enable_timing(0)
+        real = "double" if label == "fp64" else "float"
+        nbytes, _ = algorithmic_bytes_iso(mesh, n, 8 if label == "fp64" else 4)
+        vol_ms = tt["ms_volume"] / max(1, tt["n_volume"])
+        out[label] = {"ms_per_vmult": ms, "dofs_per_s": n / (ms * 1e-3), "volume_kernel_ms": vol_ms,
+                      "mortar_kernel_ms": tt["ms_mortar"] / max(1, tt["n_mortar"]),
+                      "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+                      "frac_of_8TBs": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "volume_launch_frac_of_8TBs": nbytes / (vol_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "volume_kernel": f"mns::k_jacobian_volume<{real}, {mesh['dim']}, {mesh['degree'] + 1}, true>"}
+        del y
+    out["fp32_speedup_over_fp64"] = out["fp64"]["ms_per_vmult"] / out["fp32"]["ms_per_vmult"]
+    # mixed-precision solve on the curved and on the polar mesh
+    sstate = inputs.smooth_field(mesh, inputs.STATE_SEED[name])
+    sstate = torch.from_numpy(sstate / np.abs(sstate).max()).to(dev)
+    xstar = torch.from_numpy(inputs.uniform(n, inputs.SOLUTION_SEED[name])).to(dev)
+    solves = {}
+    for label in ("curved", "polar"):
+        if label == "polar":
+            op.set_node_positions(None)
+            op.rotate_rotor(theta, mesh["omega"])
+        op.set_linearization(sstate)
+        rhs = op.apply_jacobian(xstar)
+        xs = torch.zeros_like(rhs)
+        sync()
+        _, info = op.solve(rhs, xs, check=False, rtol=1e-8, restart=50, maxit=2000, precond="f32", cheb_degree=6)
+        chk = op.apply_jacobian(xs)
+        sync()
+        solves[label] = {"seconds": info["seconds"], "iterations": info["iterations"], "converged": info["rc"] == 0,
+                         "true_rel_residual": float((rhs - chk).norm() / rhs.norm())}
+    solves["preconditioner"] = "Jacobi-Chebyshev degree 6 in FP32, FGMRES(50) in FP64"
+    out["solve"] = solves
+    op.close()
+    return out
+
+
 def transient_leg(op, mesh, name, theta, dev, sync):
     """Two implicit time steps of a spin-up: fluid at rest, a smooth body
     force (the workload's smooth field, max 1) switched on, the rotor
@@ -684,6 +781,9 @@ def main():
             "achieved_GBs": ach_sep, "frac_of_8TBs": ach_sep / HBM_PEAK_GBS,
             "frac_of_measured_copy": ach_sep / copy_gbs if copy_gbs else None,
             "mortar_kernel_ms": t_sep["ms_mortar"] / max(1, t_sep["n_mortar"])}
+
+    if not args.no_iso and mesh["dim"] == 3:
+        rec["iso_parametric"] = iso_leg(name, dev, sync, max(args.steps, 20), min(args.warmup, 10))
 
     if not args.no_batch:
         rec["batch"] = batch_leg(args, dev, sync)

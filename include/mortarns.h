@@ -138,6 +138,35 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega, void* stream);
 int mns_set_linearization(mns_handle* h, const double* state, const double* u_hist, const double* force,
                           void* stream);
 
+/* Iso-parametric geometry (the mesh mapping of Sec. 2.1: each cell is the
+ * Q_k interpolant of its Gauss-Lobatto node positions).  xyz: HOST array of
+ * n_nodes x 3 doubles (x, y, z; z ignored in 2D), one row per node in the
+ * node order of the vector layout, rotor nodes in the rotor's material frame
+ * (the rotation x = R(theta) x0 of Sec. 3.1 is applied by mns_rotate_rotor);
+ * the library copies it.  Interface nodes (rotor outermost and stator
+ * innermost node rows) must sit at their polar positions on the circle
+ * r = r_interface, where the mortar integrals stay (exact circle, exact
+ * normal, JxW = w R dtheta_seg dz of Eq. Eq-Jacobian); the gradients there go
+ * through each cell's interpolated map.  Volume integrals, element sizes
+ * (from the interpolated cell volumes) and the interface penalty (Eq.
+ * EqPenalty, from the interpolated measures of the ring-0, layer-0
+ * interface cell of each side) follow the interpolated cells.  xyz NULL
+ * returns to the exact polar geometry.  The Jacobian, residual, diagonal,
+ * matrix reconstruction, allocation-free apply, mns_solve and mns_bdf2_step
+ * with the Jacobi-Chebyshev preconditioner support this geometry; it always
+ * runs the LDS-plane volume layout with the mortar kernel in its own launch
+ * (mns_kernel_config's volume layout, fused launch and linearization source
+ * do not apply); multigrid and batching need the polar geometry
+ * (UNSUPPORTED).  Allocates the node and per-point metric tables on first
+ * use (13 values per Gauss point in 3D, 7 in 2D, FP64 and FP32) and
+ * synchronizes the stream.  Clears the rotation and the linearization (call
+ * mns_rotate_rotor and mns_set_linearization again).
+ * Errors: INVALID_ARG (n_nodes not the mesh's node count, non-finite values,
+ * an interface node off its polar position, a cell whose map folds: det J
+ * zero or of the wrong orientation at a Gauss-Lobatto point), UNSUPPORTED (a
+ * handle holding a multigrid hierarchy), HIP. */
+int mns_set_node_positions(mns_handle* h, const double* xyz, int64_t n_nodes, void* stream);
+
 /* Kind of the linearization that the next mns_set_linearization builds.
  * MNS_LIN_NEWTON (default): the Newton Jacobian of Sec. 2.3.  MNS_LIN_PICARD:
  * the Picard (Oseen) operator of the same residual, i.e. the Newton blocks

@@ -34,7 +34,7 @@ EXPORTED = [
     "mns_default_step_opts", "mns_bdf2_step", "mns_mg_levels", "mns_mg_prolongate", "mns_set_linearization_kind",
     "mns_batch_create", "mns_batch_n_dofs", "mns_batch_apply_jacobian", "mns_batch_last_error", "mns_batch_destroy",
     "mns_autotune_kernel_config", "mns_mg_restrict", "mns_batch_solve", "mns_apply_jacobian_noalloc",
-    "mns_assemble_matrix", "mns_stream_bandwidth",
+    "mns_assemble_matrix", "mns_stream_bandwidth", "mns_set_node_positions",
 ]
 
 
@@ -134,6 +134,7 @@ def lib():
         L.mns_rotate_rotor.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
         L.mns_set_linearization.argtypes = [vp, vp, vp, vp, vp]
         L.mns_set_linearization_kind.argtypes = [vp, ctypes.c_int]
+        L.mns_set_node_positions.argtypes = [vp, vp, ctypes.c_int64, vp]
         L.mns_apply_jacobian.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_jacobian_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.mns_apply_residual.argtypes = [vp, vp, vp, vp]
@@ -250,6 +251,21 @@ class Operator:
 
     def rotate_rotor(self, theta, omega):
         return self._check(self._L.mns_rotate_rotor(self._h, float(theta), float(omega), _stream()))
+
+    def set_node_positions(self, xyz):
+        """Iso-parametric geometry from node positions (host array, n_nodes x 3,
+        rotor nodes in the material frame); None returns to the polar geometry
+        (mns_set_node_positions).  Clears rotation and linearization."""
+        import numpy as np
+
+        if xyz is None:
+            return self._check(self._L.mns_set_node_positions(self._h, None, 0, _stream()))
+        a = np.ascontiguousarray(xyz, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != 3:
+            raise ValueError("node positions must be an (n_nodes, 3) array")
+        self._xyz = a
+        return self._check(self._L.mns_set_node_positions(self._h, ctypes.c_void_p(a.ctypes.data), a.shape[0],
+                                                          _stream()))
 
     def set_linearization(self, state, hist=None, force=None, kind=None):
         """kind: None (keep), "newton" or "picard" (mns_set_linearization_kind)."""

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmortarns.so")
 SOURCES = ["mns_kernels.hip", "mns_solver.hip", "mns_step.hip", "mns_batch_solver.hip", "mns_coarse.hip",
-           "mns_measure.hip", "mns_setup.cpp", "mns_abi.cpp"]
+           "mns_measure.hip", "mns_iso.hip", "mns_setup.cpp", "mns_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MNS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

@@ -41,7 +41,8 @@ static void free_all(mns_handle* h) {
                    (void**)&h->ws64, (void**)&h->ws32, (void**)&h->d_E64, (void**)&h->d_E32, (void**)&h->d_Em64,
                    (void**)&h->d_Em32, (void**)&h->d_diag64, (void**)&h->d_diag32, (void**)&h->d_red, (void**)&h->d_gm,
                    (void**)&h->d_step, (void**)&h->d_state, (void**)&h->d_linc64, (void**)&h->d_linc32,
-                   (void**)&h->d_state32};
+                   (void**)&h->d_state32, (void**)&h->d_xnode, (void**)&h->d_geo64, (void**)&h->d_geo32,
+                   (void**)&h->d_geox, (void**)&h->d_hiso, (void**)&h->d_iso_flag};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -110,10 +111,29 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega, void* stream) {
   int rc;
   try {
     rc = mns_rotate_tables(h, theta, omega, as_stream(stream));
+    if (rc == MNS_OK) rc = mns::iso_rotate(h, theta, as_stream(stream));
   } catch (...) {
     rc = set_error(h, MNS_ERR_HIP, "exception in rotate");
   }
   h->rotated = rc == MNS_OK;
+  ++h->lin_version;
+  h->linearized = false;
+  h->diag_valid = false;
+  return rc;
+}
+
+int mns_set_node_positions(mns_handle* h, const double* xyz, int64_t n_nodes, void* stream) {
+  if (!h) return MNS_ERR_INVALID_ARG;
+  if (h->ndofs == 0 || !h->d_mtab64) return set_error(h, MNS_ERR_INVALID_ARG, "handle was not set up");
+  if (h->mg) return set_error(h, MNS_ERR_UNSUPPORTED, "the handle holds a multigrid hierarchy");
+  int rc;
+  try {
+    rc = mns::iso_set_nodes(h, xyz, n_nodes, as_stream(stream));
+  } catch (...) {
+    rc = set_error(h, MNS_ERR_HIP, "exception in set_node_positions");
+  }
+  // the geometry changed: the next apply needs a rotation and a linearization
+  h->rotated = false;
   ++h->lin_version;
   h->linearized = false;
   h->diag_valid = false;
@@ -188,6 +208,7 @@ int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch) {
       return set_error(h, MNS_ERR_INVALID_ARG, "batch: all handles need the same dimension and degree");
     if (!h->equal_rings)
       return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need equal interface cell counts");
+    if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need the polar geometry");
   }
   auto* b = new mns_batch();
   b->hs.assign(handles, handles + count);
@@ -409,6 +430,8 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
       (o.use_graph != 0 && o.use_graph != 1) || !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0) ||
       (o.mg_coarse_direct != 0 && o.mg_coarse_direct != 1))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
+  if (h->iso && (o.precond == MNS_PRECOND_MG || o.precond == MNS_PRECOND_MG64))
+    return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry (coarse levels are polar meshes)");
   mns_solve_report rep{};
   int rc;
   try {
@@ -445,6 +468,8 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
   if (opts) o = *opts;
   if (!(o.newton_rtol >= 0) || !(o.newton_atol >= 0) || o.max_newton < 1 || o.max_newton > 100)
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid step options");
+  if (h->iso && (o.linear.precond == MNS_PRECOND_MG || o.linear.precond == MNS_PRECOND_MG64))
+    return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry (coarse levels are polar meshes)");
   mns_step_report rep{};
   int rc;
   try {
@@ -459,6 +484,7 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
 int mns_mg_levels(mns_handle* h, int* levels) {
   if (!h || !levels) return MNS_ERR_INVALID_ARG;
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
+  if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry");
   try {
     return mns::mg_levels(h, levels, h->stream);
   } catch (...) {
@@ -471,6 +497,7 @@ int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
   if (!aligned(x, 8) || !aligned(y, 8) || x == y)
     return set_error(h, MNS_ERR_INVALID_ARG, "x/y must be distinct 8-byte aligned pointers");
+  if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry");
   try {
     return mns::mg_prolongate64(h, level, x, y, as_stream(stream));
   } catch (...) {
@@ -483,6 +510,7 @@ int mns_mg_restrict(mns_handle* h, int level, const double* x, double* y, void* 
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
   if (!aligned(x, 8) || !aligned(y, 8) || x == y)
     return set_error(h, MNS_ERR_INVALID_ARG, "x/y must be distinct 8-byte aligned pointers");
+  if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry");
   try {
     return mns::mg_restrict64(h, level, x, y, as_stream(stream));
   } catch (...) {

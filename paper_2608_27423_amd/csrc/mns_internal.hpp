@@ -26,6 +26,20 @@ struct LinLayout {
   static constexpr int SIZE = TR + DIM;
 };
 
+// Per-quadrature-point metric of an iso-parametric cell (the Q_k
+// interpolant of its node positions): K[p][m] = d xi_p / d x_m (p-major),
+// JxW, and the mapping term of the Laplacian b_p = sum_m K[p][m] c_m with
+// c_m = sum_pq (K K^T)_pq d^2 x_m / d xi_p d xi_q, so that
+// lap u = sum_pq (K K^T)_pq d^2 u / d xi_p d xi_q - sum_p b_p d u / d xi_p.
+// 13 values in 3D, 7 in 2D.
+template <int DIM>
+struct IsoLayout {
+  static constexpr int K = 0;
+  static constexpr int JXW = DIM * DIM;
+  static constexpr int B = JXW + 1;
+  static constexpr int SIZE = B + DIM;
+};
+
 // 1D tables: Lagrange basis on N Gauss-Lobatto nodes of [0,1] evaluated at the
 // N Gauss points (the volume quadrature of every cell).
 template <typename Real, int N>
@@ -59,6 +73,12 @@ struct Geom {
   const Real* hcell;    // [2][hstride] element size by (domain, radial layer)
   int hstride;
   const Real* trig;     // [nth[0] + nth[1]][N][2]: cos, sin of theta at (ring cell, Gauss point), rotor first
+  // iso-parametric geometry (null on the polar path): per-point metric
+  // [cell][point][IsoLayout::SIZE], physical point positions [cell][point][3]
+  // and element sizes [cell] (the last two FP64, read by the state kernel)
+  const Real* geo;
+  const double* geox;
+  const double* hiso;
 };
 
 // Mortar quadrature tables for the current rotor angle (Sec. 3.2).  Segment 0
@@ -84,6 +104,7 @@ struct MortarTab {
 // mortar segment is found and mapped inside the kernel from these values.
 struct MortarGen {
   double theta_rot;                   // rotor angle
+  const double* xnode;                // iso-parametric node positions [node][3] (material frame), or null
   double R;                           // interface radius
   double tau_pen[2];                  // penalty of the rotor and stator interface cells (Eq. EqPenalty)
   double inv_dr[2];                   // 1 / dr of the rotor and stator cells
@@ -159,6 +180,16 @@ struct mns_handle {
   float* d_linc32 = nullptr;
   float* d_state32 = nullptr;
   int lin_picard = 0;           // kind of the current linearization
+  // iso-parametric geometry (mns_set_node_positions): node positions in the
+  // material frame and the per-point tables rebuilt at every rotation
+  bool iso = false;
+  double tau_pen_polar[2] = {0, 0};  // penalty of the polar interface cells (restored by a reset)
+  double* d_xnode = nullptr;    // [node][3]
+  double* d_geo64 = nullptr;    // [cell][point][IsoLayout::SIZE]
+  float* d_geo32 = nullptr;
+  double* d_geox = nullptr;     // [cell][point][3] physical positions of the Gauss points
+  double* d_hiso = nullptr;     // [cell] element size from the cell volume
+  int* d_iso_flag = nullptr;    // set by the metric kernel where det J >= 0
   long long lin_version = 0;    // incremented by every rotation and linearization
   void* mg = nullptr;           // multigrid hierarchy (mns_solver.hip)
   double* h_red = nullptr;      // pinned host mirror
@@ -278,6 +309,11 @@ int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s);
 // (allocated and computed on first use, reused until it changes)
 int cached_diagonal(mns_handle* h, hipStream_t s);
 int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
+
+// iso-parametric geometry (mns_iso.hip): node positions, fold check,
+// element sizes and penalty; the per-point tables at the current angle
+int iso_set_nodes(mns_handle* h, const double* xyz, int64_t n_nodes, hipStream_t s);
+int iso_rotate(mns_handle* h, double theta, hipStream_t s);
 
 // host setup (mns_setup.cpp)
 void rules_1d(int n, std::vector<double>& gll, std::vector<double>& gx, std::vector<double>& gw);

@@ -16,76 +16,14 @@
 #include <vector>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
+#include "mns_device.hpp"
 #include "mns_internal.hpp"
 
 namespace mns {
-
-
-template <typename Real, int DIM, int N>
-struct Shape {
-  static constexpr int NZ = (DIM == 3) ? N : 1;  // line length along z
-  static constexpr int PLANE = N * N;
-  static constexpr int TPC = N * N;              // lanes per cell
-  static constexpr int CPW = 64 / TPC;           // cells per wavefront
-  static constexpr int NPT = PLANE * NZ;         // nodes (= quadrature points) per cell
-  static constexpr int NC = DIM + 1;             // components
-  static constexpr int NYV = (DIM == 3) ? 5 : 3; // r-stage outputs per velocity component
-  static constexpr int NYP = (DIM == 3) ? 3 : 2; // r-stage outputs of the pressure
-  static constexpr int NT = DIM + 1;             // test coefficients per component
-  static constexpr int EVAL_SLOTS = DIM * NYV + NYP;
-  static constexpr int TEST_SLOTS = NC * NT;
-  static constexpr int SLOTS = (EVAL_SLOTS > TEST_SLOTS) ? EVAL_SLOTS : TEST_SLOTS;
-  // LDS layout of the per-cell work arrays: cell c owns [c * REGION, ...),
-  // element stride ES = 1
-  static constexpr int ES = 1;
-  static constexpr int REGION = SLOTS * NPT;
-  template <int NSLOTS>
-  static constexpr int lds_size() {
-    return (CPW - 1) * (NSLOTS * NPT) + NSLOTS * NPT;
-  }
-};
-
-struct CellId {
-  int dom, ct, cr, cz;
-};
-
-// per-domain parameter selected without indexing the kernel-argument block
-// by a lane-dependent value (which would turn into a vector memory load)
-template <typename T>
-__device__ inline T pick(int d, const T (&a)[2]) {
-  return d ? a[1] : a[0];
-}
-
-template <typename Real>
-__device__ inline CellId decode_cell(const Geom<Real>& G, int cell) {
-  CellId c;
-  c.dom = cell >= (int)G.cell_off1;
-  int l = cell - (c.dom ? (int)G.cell_off1 : 0);
-  const int nt = pick(c.dom, G.nth);
-  c.ct = l % nt;
-  l /= nt;
-  const int nr = pick(c.dom, G.nr);
-  c.cr = l % nr;
-  c.cz = l / nr;
-  return c;
-}
-
-// global node of local node (a, b, c) of cell C; also returns the node's
-// structured indices for the constraint predicates
-template <typename Real, int DIM>
-__device__ inline long long node_of(const Geom<Real>& G, int k, const CellId& C, int a, int b, int c, int& it,
-                                    int& ir, int& iz) {
-  it = k * C.ct + a;
-  const int ntn = pick(C.dom, G.ntd);
-  if (it >= ntn) it -= ntn;
-  ir = k * C.cr + b;
-  iz = (DIM == 3) ? k * C.cz + c : 0;
-  long long base = C.dom ? G.node_off1 : 0;
-  return base + it + (long long)ntn * (ir + (long long)pick(C.dom, G.nrn) * iz);
-}
 
 // constraint predicates, written with bitwise operators so that they
 // compile to selects rather than branches
@@ -363,16 +301,93 @@ __device__ inline void to_reference(const PtGeom<Real>& g, Real g0, const Real (
   if constexpr (DIM == 3) f[3] = g.jz * Gp[2];           // z
 }
 
+// Iso-parametric point geometry (metric of the Q_k interpolant of the node
+// positions, stored per point, IsoLayout): K[p][m] = d xi_p / d x_m, JxW,
+// the mapping term b of the Laplacian and G = K K^T formed here.
+template <typename Real, int DIM>
+struct IsoPt {
+  Real K[DIM][DIM];
+  Real jxw;
+  Real b[DIM];
+  Real G[DIM][DIM];
+
+  __device__ inline void load(const Real* p) {
+    using IL = IsoLayout<DIM>;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) K[a][m] = p[IL::K + a * DIM + m];
+    jxw = p[IL::JXW];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) b[a] = p[IL::B + a];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int c = a; c < DIM; ++c) {
+        Real t = 0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) t += K[a][m] * K[c][m];
+        G[a][c] = G[c][a] = t;
+      }
+  }
+};
+
+// reference values with the mixed second derivatives, which a general
+// metric couples: mx = {theta r, theta z, r z}
+template <typename Real, int DIM>
+struct RefValX {
+  Real v;
+  Real d[DIM];
+  Real dd[DIM];
+  Real mx[3];
+};
+
+// reference derivatives -> Cartesian gradient and Laplacian (general metric)
+template <typename Real, int DIM>
+__device__ inline void to_physical(const IsoPt<Real, DIM>& g, const Real*, const RefValX<Real, DIM>& rv,
+                                   Real (&grad)[DIM], Real& lap, bool want_lap) {
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) {
+    Real t = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) t += g.K[a][m] * rv.d[a];
+    grad[m] = t;
+  }
+  if (want_lap) {
+    Real l = 2 * g.G[0][1] * rv.mx[0];
+    if constexpr (DIM == 3) l += 2 * (g.G[0][2] * rv.mx[1] + g.G[1][2] * rv.mx[2]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) l += g.G[a][a] * rv.dd[a] - g.b[a] * rv.d[a];
+    lap = l;
+  }
+}
+
+// physical test coefficients -> reference ones times JxW (general metric)
+template <typename Real, int DIM>
+__device__ inline void to_reference(const IsoPt<Real, DIM>& g, Real g0, const Real (&Gp)[DIM], Real* f) {
+  f[0] = g.jxw * g0;
+  Real w[DIM];
+#pragma unroll
+  for (int m = 0; m < DIM; ++m) w[m] = g.jxw * Gp[m];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    Real t = 0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) t += g.K[a][m] * w[m];
+    f[1 + a] = t;
+  }
+}
+
 // Pointwise linearized operator at one volume point (Sec. 2.3 blocks):
 // reference values/derivatives of the increment (rv velocity, rp pressure)
 // and the stored linearization lv -> reference test coefficients times JxW,
 // tc[comp][{value, theta, r, z}].
 //   g_v = c_t du + (grad u) du + (grad du) a,   R' du = g_v - nu lap du + grad dp
 //   G_v = nu grad du - dp I + tau R' du (x) a + tau R (x) du,  g_q = div du,  G_q = tau R' du
-template <typename Real, int DIM>
-__device__ inline void pointwise_jacobian(const PtGeom<Real>& g, const RefVal<Real, DIM> (&rv)[DIM],
-                                          const RefVal<Real, DIM>& rp, const Real* lv, Real nu, Real ct,
-                                          Real (&tc)[DIM + 1][DIM + 1]) {
+// (GeoT, RV: polar PtGeom with RefVal, or IsoPt with RefValX.)
+template <typename Real, int DIM, typename GeoT, typename RV>
+__device__ inline void pointwise_jacobian(const GeoT& g, const RV (&rv)[DIM], const RV& rp, const Real* lv, Real nu,
+                                          Real ct, Real (&tc)[DIM + 1][DIM + 1]) {
   using LL = LinLayout<DIM>;
   Real du[DIM], gdu[DIM][DIM], ldu[DIM], gdp[DIM], dummy;
 #pragma unroll
@@ -691,10 +706,14 @@ __device__ inline void gather_line(const Geom<Real>& G, int k, const CellId& C, 
 // ---------------------------------------------------------------------------
 // Jacobian vmult with stored linearization (Sec. 2.3 blocks, volume part)
 // ---------------------------------------------------------------------------
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 struct PlaneShape {
   static constexpr int ZS = (DIM == 3) ? 3 * DIM + 2 : DIM + 1;  // z-stage arrays (velocity V,D,DD; pressure V,D)
-  static constexpr int YS = (DIM == 3) ? 5 * DIM + 3 : 3 * DIM + 2; // r-stage arrays
+  // r-stage outputs per velocity component: V, D, DD of the z value, V of the
+  // z derivative and second derivative, and (iso-parametric, 3D) D of the z
+  // derivative for the mixed r z derivative
+  static constexpr int NYV = (DIM == 3) ? (ISO ? 6 : 5) : 3;
+  static constexpr int YS = (DIM == 3) ? NYV * DIM + 3 : 3 * DIM + 2; // r-stage arrays
   static constexpr int TS = (DIM + 1) * (DIM + 1);                  // test coefficients
   static constexpr int XS = (DIM + 1) * ((DIM == 3) ? 3 : 2);       // theta-transposed test arrays
   static constexpr int A = (ZS > TS ? ZS : TS) * N * N;             // doubles per cell in buffer A
@@ -708,18 +727,21 @@ struct PlaneShape {
 // contractions through LDS, the pointwise operator, and the transposed theta
 // and r contractions; the z part of the integration accumulates in registers.
 // LDS holds one plane per cell in two ping-pong buffers.
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 struct VolumeSmem {
   Tab1D<Real, N> sT;
-  Real lds[Shape<Real, DIM, N>::CPW * PlaneShape<Real, DIM, N>::REGION];
+  Real lds[Shape<Real, DIM, N>::CPW * PlaneShape<Real, DIM, N, ISO>::REGION];
 };
 
-template <typename Real, int DIM, int N>
+// ISO: iso-parametric cells (per-point metric G.geo, mixed second
+// derivatives of the increment's velocity in the Laplacian)
+template <typename Real, int DIM, int N, bool ISO = false>
 __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                     const Real* __restrict__ lin, const Real* __restrict__ src,
-                                    Real* __restrict__ E, VolumeSmem<Real, DIM, N>& sm) {
+                                    Real* __restrict__ E, VolumeSmem<Real, DIM, N, ISO>& sm) {
   using S = Shape<Real, DIM, N>;
-  using P = PlaneShape<Real, DIM, N>;
+  using P = PlaneShape<Real, DIM, N, ISO>;
+  constexpr int NYV = P::NYV;
   using LL = LinLayout<DIM>;
   constexpr int NZ = S::NZ, NC = S::NC, PL = N * N;
   Real* lds = sm.lds;
@@ -797,8 +819,8 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
       for (int m = 0; m < NC; ++m) {
         const bool vel = m < DIM;
         const int zb = vel ? m * ZV : DIM * ZV;
-        const int yb = vel ? m * S::NYV : DIM * S::NYV;
-        Real vv = 0, dv = 0, ddv = 0, vd = 0, vdd = 0;
+        const int yb = vel ? m * NYV : DIM * NYV;
+        Real vv = 0, dv = 0, ddv = 0, vd = 0, vdd = 0, dvd = 0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
           const Real zv = zin[zb][b];
@@ -808,6 +830,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
           if constexpr (DIM == 3) {
             vd += sT.V[tb][b] * zin[zb + 1][b];
             if (vel) vdd += sT.V[tb][b] * zin[zb + 2][b];
+            if (ISO && vel) dvd += sT.D[tb][b] * zin[zb + 1][b];
           }
         }
         yout[yb + 0] = vv;
@@ -817,6 +840,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
             yout[yb + 2] = ddv;
             yout[yb + 3] = vd;
             yout[yb + 4] = vdd;
+            if constexpr (ISO) yout[yb + 5] = dvd;
           } else {
             yout[yb + 2] = vd;
           }
@@ -835,11 +859,12 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
 #pragma unroll
       for (int j = 0; j < LL::SIZE; ++j) lnext[j] = lbase[(q + 1) * PL * LL::SIZE + j];
     if (active) {
-      RefVal<Real, DIM> rv[DIM], rp;
+      using RV = std::conditional_t<ISO, RefValX<Real, DIM>, RefVal<Real, DIM>>;
+      RV rv[DIM], rp;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
-        const Real* y = B + m * S::NYV * PL + tb * N;
-        Real v = 0, dt = 0, ddt = 0, dr = 0, ddr = 0, dz = 0, ddz = 0;
+        const Real* y = B + m * NYV * PL + tb * N;
+        Real v = 0, dt = 0, ddt = 0, dr = 0, ddr = 0, dz = 0, ddz = 0, dtr = 0, dtz = 0, drz = 0;
 #pragma unroll
         for (int a2 = 0; a2 < N; ++a2) {
           const Real yvv = y[a2];
@@ -848,10 +873,20 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
           ddt += sT.DD[ta][a2] * yvv;
           dr += sT.V[ta][a2] * y[1 * PL + a2];
           ddr += sT.V[ta][a2] * y[2 * PL + a2];
+          if constexpr (ISO) dtr += sT.D[ta][a2] * y[1 * PL + a2];
           if constexpr (DIM == 3) {
             dz += sT.V[ta][a2] * y[3 * PL + a2];
             ddz += sT.V[ta][a2] * y[4 * PL + a2];
+            if constexpr (ISO) {
+              dtz += sT.D[ta][a2] * y[3 * PL + a2];
+              drz += sT.V[ta][a2] * y[5 * PL + a2];
+            }
           }
+        }
+        if constexpr (ISO) {
+          rv[m].mx[0] = dtr;
+          rv[m].mx[1] = dtz;
+          rv[m].mx[2] = drz;
         }
         rv[m].v = v;
         rv[m].d[0] = dt;
@@ -864,7 +899,7 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         }
       }
       {
-        const Real* y = B + DIM * S::NYV * PL + tb * N;
+        const Real* y = B + DIM * NYV * PL + tb * N;
         Real v = 0, dt = 0, dr = 0, dz = 0;
 #pragma unroll
         for (int a2 = 0; a2 < N; ++a2) {
@@ -879,10 +914,17 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         if constexpr (DIM == 3) rp.d[2] = dz;
 #pragma unroll
         for (int e = 0; e < DIM; ++e) rp.dd[e] = 0;
+        if constexpr (ISO) rp.mx[0] = rp.mx[1] = rp.mx[2] = 0;
       }
-      const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
       Real tc[NC][S::NT];
-      pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
+      if constexpr (ISO) {
+        IsoPt<Real, DIM> g;
+        g.load(G.geo + ((size_t)cell * S::NPT + q * PL + me) * IsoLayout<DIM>::SIZE);
+        pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
+      } else {
+        const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
+        pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
+      }
 #pragma unroll
       for (int m = 0; m < NC; ++m)
 #pragma unroll
@@ -948,13 +990,13 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
     for (int c = 0; c < NZ; ++c) Ec[(size_t)(m * S::NPT + c * PL + me) * G.ncells] = o[m][c];
 }
 
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(64) void k_jacobian_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                                      const Real* __restrict__ lin,
                                                                      const Real* __restrict__ src,
                                                                      Real* __restrict__ E) {
-  __shared__ VolumeSmem<Real, DIM, N> sm;
-  volume_block<Real, DIM, N>(G, T, k, blockIdx.x, lin, src, E, sm);
+  __shared__ VolumeSmem<Real, DIM, N, ISO> sm;
+  volume_block<Real, DIM, N, ISO>(G, T, k, blockIdx.x, lin, src, E, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1669,10 +1711,202 @@ __global__ __launch_bounds__(64) void k_state(Geom<double> G, Tab1D<double, N> T
 }
 
 // ---------------------------------------------------------------------------
+// State kernel on iso-parametric cells: the same outputs as k_state.  The
+// cell's nodal state (and history, force) is staged in LDS and every point is
+// evaluated directly from the tensor basis, mixed second derivatives
+// included; the metric comes from the per-point table (G.geo), the mesh
+// velocity from the point positions (G.geox), tau from the cell's h (G.hiso).
+// Not on the Jacobian's hot path: it runs once per linearization.
+// ---------------------------------------------------------------------------
+template <int DIM, int N, bool RES>
+__global__ __launch_bounds__(64) void k_state_iso(Geom<double> G, Tab1D<double, N> T, int k,
+                                                  const double* __restrict__ state, const double* __restrict__ hist,
+                                                  const double* __restrict__ force, double* __restrict__ lin,
+                                                  double* __restrict__ res, int picard) {
+  using Real = double;
+  using S = Shape<Real, DIM, N>;
+  using LL = LinLayout<DIM>;
+  constexpr int NZ = S::NZ, NC = S::NC, NPT = S::NPT, NU = NC + 2 * DIM;
+  __shared__ Real U[S::CPW][NU][NPT];                   // state, history, force at the cell's nodes
+  __shared__ Real L[S::CPW * S::TEST_SLOTS * NPT];       // test coefficients (residual)
+  __shared__ Tab1D<Real, N> sT;
+  const int lane = threadIdx.x;
+  {
+    constexpr int NW = (int)(sizeof(Tab1D<Real, N>) / sizeof(Real));
+    const Real* tw = (const Real*)&T;
+    for (int i = lane; i < NW; i += 64) ((Real*)&sT)[i] = tw[i];
+  }
+  const int cl = lane / S::TPC;
+  const int t = lane % S::TPC;
+  const int ta = t % N, tb = t / N;
+  const int cell = blockIdx.x * S::CPW + cl;
+  const bool active = cl < S::CPW && cell < G.ncells;
+  const CellId C = decode_cell(G, active ? cell : 0);
+  const bool has_hist = hist != nullptr, has_force = force != nullptr;
+  if (active) {
+    for (int node = t; node < NPT; node += S::TPC) {
+      const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+      int it, ir, iz;
+      const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
+#pragma unroll
+      for (int m = 0; m < NC; ++m) U[cl][m][node] = state[nd * NC + m];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        U[cl][NC + m][node] = has_hist ? hist[nd * NC + m] : 0.0;
+        U[cl][NC + DIM + m][node] = has_force ? force[nd * NC + m] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  Real* Lc = L + (active ? cl : 0) * (S::TEST_SLOTS * NPT);
+  if (active) {
+    const Real nu = G.nu, ct = G.ct;
+    const Real hc = G.hiso[cell];
+    const Real ih2 = 1.0 / (hc * hc);
+    const Real visc = 9.0 * (4.0 * nu * ih2) * (4.0 * nu * ih2);
+    for (int q = 0; q < NZ; ++q) {
+      const int pt = q * S::PLANE + tb * N + ta;
+      // values, reference gradients and Hessians of the velocity; values and
+      // gradients of the pressure; values of history and force
+      Real uv[DIM], ud[DIM][DIM], udd[DIM][DIM], umx[DIM][3], pv = 0, pd[DIM], hv[DIM], fv[DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        uv[m] = hv[m] = fv[m] = 0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) ud[m][e] = udd[m][e] = 0;
+        umx[m][0] = umx[m][1] = umx[m][2] = 0;
+        pd[m] = 0;
+      }
+      for (int c = 0; c < NZ; ++c) {
+        const Real z0 = DIM == 3 ? sT.V[q][c] : 1.0, z1 = DIM == 3 ? sT.D[q][c] : 0.0,
+                   z2 = DIM == 3 ? sT.DD[q][c] : 0.0;
+        for (int b = 0; b < N; ++b) {
+          const Real r0 = sT.V[tb][b], r1 = sT.D[tb][b], r2 = sT.DD[tb][b];
+#pragma unroll
+          for (int a = 0; a < N; ++a) {
+            const Real t0 = sT.V[ta][a], t1 = sT.D[ta][a], t2 = sT.DD[ta][a];
+            const int node = (c * N + b) * N + a;
+            const Real phi = t0 * r0 * z0;
+            const Real dphi[3] = {t1 * r0 * z0, t0 * r1 * z0, t0 * r0 * z1};
+            const Real ddphi[3] = {t2 * r0 * z0, t0 * r2 * z0, t0 * r0 * z2};
+            const Real mxphi[3] = {t1 * r1 * z0, t1 * r0 * z1, t0 * r1 * z1};
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) {
+              const Real u = U[cl][m][node];
+              uv[m] += phi * u;
+#pragma unroll
+              for (int e = 0; e < DIM; ++e) {
+                ud[m][e] += dphi[e] * u;
+                udd[m][e] += ddphi[e] * u;
+              }
+#pragma unroll
+              for (int e = 0; e < 3; ++e) umx[m][e] += mxphi[e] * u;
+              hv[m] += phi * U[cl][NC + m][node];
+              fv[m] += phi * U[cl][NC + DIM + m][node];
+            }
+            const Real p = U[cl][DIM][node];
+            pv += phi * p;
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) pd[e] += dphi[e] * p;
+          }
+        }
+      }
+      IsoPt<Real, DIM> g;
+      g.load(G.geo + ((size_t)cell * NPT + pt) * IsoLayout<DIM>::SIZE);
+      Real gu[DIM][DIM], lu[DIM], gp[DIM], dummy;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        RefValX<Real, DIM> rv;
+        rv.v = uv[m];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+          rv.d[e] = ud[m][e];
+          rv.dd[e] = udd[m][e];
+        }
+        rv.mx[0] = umx[m][0];
+        rv.mx[1] = umx[m][1];
+        rv.mx[2] = umx[m][2];
+        to_physical<Real, DIM>(g, nullptr, rv, gu[m], lu[m], true);
+        if (!(has_hist && ct != 0)) hv[m] = 0;
+      }
+      {
+        RefValX<Real, DIM> rp;
+        rp.v = pv;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+          rp.d[e] = pd[e];
+          rp.dd[e] = 0;
+        }
+        rp.mx[0] = rp.mx[1] = rp.mx[2] = 0;
+        to_physical<Real, DIM>(g, nullptr, rp, gp, dummy, false);
+      }
+      // mesh velocity omega e_z x x in rotor cells
+      const double* xp = G.geox + ((size_t)cell * NPT + pt) * 3;
+      Real w[DIM] = {};
+      if (C.dom == 0) {
+        w[0] = -G.omega * xp[1];
+        w[1] = G.omega * xp[0];
+      }
+      Real a[DIM], an2 = 0;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        a[m] = uv[m] - w[m];
+        an2 += a[m] * a[m];
+      }
+      const Real tau = 1.0 / sqrt(G.ctau2 + 4.0 * an2 * ih2 + visc);
+      Real R[DIM], conv[DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        Real s2 = 0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) s2 += gu[m][e] * a[e];
+        conv[m] = s2;
+        R[m] = ct * uv[m] + hv[m] + s2 + gp[m] - nu * lu[m] - fv[m];
+      }
+      if constexpr (!RES) {
+        double* lp = lin + ((size_t)cell * NPT + pt) * LL::SIZE;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          lp[LL::A + m] = a[m];
+          lp[LL::TR + m] = picard ? 0.0 : tau * R[m];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e) lp[LL::GU + m * DIM + e] = picard ? 0.0 : gu[m][e];
+        }
+        lp[LL::TAU] = tau;
+      } else {
+        Real tc[NC][S::NT];
+        Real divu = 0;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          divu += gu[m][m];
+          Real Gm[DIM];
+#pragma unroll
+          for (int e = 0; e < DIM; ++e) Gm[e] = nu * gu[m][e] + tau * R[m] * a[e];
+          Gm[m] -= pv;
+          to_reference<Real, DIM>(g, ct * uv[m] + hv[m] + conv[m] - fv[m], Gm, tc[m]);
+        }
+        Real Gq[DIM];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) Gq[e] = tau * R[e];
+        to_reference<Real, DIM>(g, divu, Gq, tc[DIM]);
+#pragma unroll
+        for (int m = 0; m < NC; ++m)
+#pragma unroll
+          for (int j = 0; j < S::NT; ++j) Lc[(m * S::NT + j) * NPT + pt] = tc[m][j];
+      }
+    }
+  }
+  if constexpr (RES) {
+    __syncthreads();
+    integrate_store<Real, DIM, N>(sT, T, Lc, ta, tb, active, cell, G.ncells, res);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Volume diagonal (column i of the element matrix, entry i) from stored
 // linearization data: one lane per (cell, local DoF), loop over points.
 // ---------------------------------------------------------------------------
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                      const Real* __restrict__ lin, Real* __restrict__ diag) {
   // one thread per (cell, node): the basis function, its physical derivatives
@@ -1694,11 +1928,11 @@ __global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N
   for (int q = 0; q < NZ; ++q)
     for (int qj = 0; qj < N; ++qj)
       for (int qi = 0; qi < N; ++qi) {
-        const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, qi, qj, q);
         const Real vz = (DIM == 3) ? T.V[q][a2] : Real(1);
         const Real dz_ = (DIM == 3) ? T.D[q][a2] : Real(0);
         const Real ddz = (DIM == 3) ? T.DD[q][a2] : Real(0);
-        RefVal<Real, DIM> rv;
+        using RV = std::conditional_t<ISO, RefValX<Real, DIM>, RefVal<Real, DIM>>;
+        RV rv;
         rv.v = T.V[qi][a0] * T.V[qj][a1] * vz;
         rv.d[0] = T.D[qi][a0] * T.V[qj][a1] * vz;
         rv.d[1] = T.V[qi][a0] * T.D[qj][a1] * vz;
@@ -1708,8 +1942,20 @@ __global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N
           rv.d[2] = T.V[qi][a0] * T.V[qj][a1] * dz_;
           rv.dd[2] = T.V[qi][a0] * T.V[qj][a1] * ddz;
         }
-        Real gphi[DIM], lphi;
-        to_physical<Real, DIM>(g, nullptr, rv, gphi, lphi, true);
+        Real gphi[DIM], lphi, jxw;
+        if constexpr (ISO) {
+          rv.mx[0] = T.D[qi][a0] * T.D[qj][a1] * vz;
+          rv.mx[1] = T.D[qi][a0] * T.V[qj][a1] * dz_;
+          rv.mx[2] = T.V[qi][a0] * T.D[qj][a1] * dz_;
+          IsoPt<Real, DIM> g;
+          g.load(G.geo + ((size_t)cell * S::NPT + q * S::PLANE + qj * N + qi) * IsoLayout<DIM>::SIZE);
+          to_physical<Real, DIM>(g, nullptr, rv, gphi, lphi, true);
+          jxw = g.jxw;
+        } else {
+          const PtGeom<Real> g = point_geom<Real, DIM, N>(G, T, C, qi, qj, q);
+          to_physical<Real, DIM>(g, nullptr, rv, gphi, lphi, true);
+          jxw = g.jxw;
+        }
         const Real phi = rv.v;
         const Real* lp = lin + ((size_t)cell * S::NPT + q * S::PLANE + qj * N + qi) * LL::SIZE;
         const Real tau = lp[LL::TAU];
@@ -1724,11 +1970,11 @@ __global__ __launch_bounds__(128) void k_diag_volume(Geom<Real> G, Tab1D<Real, N
           // trial phi e_c tested with phi e_c (Sec. 2.3, A-hat diagonal)
           const Real guc = lp[LL::GU + comp * DIM + comp];
           const Real Rpc = (ct + guc) * phi + adg - nu * lphi;
-          acc[comp] += g.jxw * (phi * phi * (ct + guc) + phi * adg + nu * g2 + tau * Rpc * adg +
-                                lp[LL::TR + comp] * phi * gphi[comp]);
+          acc[comp] += jxw * (phi * phi * (ct + guc) + phi * adg + nu * g2 + tau * Rpc * adg +
+                              lp[LL::TR + comp] * phi * gphi[comp]);
         }
         // D-hat diagonal: tau |grad psi|^2
-        acc[DIM] += g.jxw * tau * g2;
+        acc[DIM] += jxw * tau * g2;
       }
   int it, ir, iz;
   const long long nd = node_of<Real, DIM>(G, k, C, a0, a1, a2, it, ir, iz);
@@ -2282,18 +2528,63 @@ __device__ inline GenFace gen_face(const Geom<Real>& G, const MortarGen& MG, int
   return F;
 }
 
-template <typename Real, int DIM, int N>
+// inverse of the reference-to-physical Jacobian J[m][p] = d x_m / d xi_p:
+// K[p][m] = d xi_p / d x_m
+template <int DIM>
+__device__ inline void invert_jacobian(const double (&J)[DIM][DIM], double (&K)[DIM][DIM]) {
+  if constexpr (DIM == 2) {
+    const double id = 1.0 / (J[0][0] * J[1][1] - J[0][1] * J[1][0]);
+    K[0][0] = J[1][1] * id;
+    K[0][1] = -J[0][1] * id;
+    K[1][0] = -J[1][0] * id;
+    K[1][1] = J[0][0] * id;
+  } else {
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double id = 1.0 / (J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02);
+    K[0][0] = c00 * id;
+    K[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    K[1][0] = c01 * id;
+    K[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    K[2][0] = c02 * id;
+    K[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+  }
+}
+
+// position of node nd in the current configuration (rotor nodes rotated by
+// the rotor angle, Sec. 3.1)
+__device__ inline void node_position(const double* __restrict__ xnode, long long nd, bool rotor, double c, double s,
+                                     double (&x)[3]) {
+  const double x0 = xnode[nd * 3], y0 = xnode[nd * 3 + 1];
+  x[0] = rotor ? c * x0 - s * y0 : x0;
+  x[1] = rotor ? s * x0 + c * y0 : y0;
+  x[2] = xnode[nd * 3 + 2];
+}
+
+// ISO: iso-parametric cells; the gradients at the mortar points go through
+// the inverse Jacobian of each side's interpolated map there (the mortar
+// points, JxW and normals stay those of the exact circle)
+template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real, N> T, int k, MortarGen MG,
                                                        const Real* __restrict__ src, Real* __restrict__ Em,
                                                        int mask) {
   using S = Shape<Real, DIM, N>;
   constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ, NQ = N * NZ, NE = DIM + 1;
   constexpr int NI = (NPT * NC + 63) / 64;
+  constexpr int XI = ISO ? 2 : 1, XN = ISO ? NPT : 1, XQ = ISO ? NQ : 1;
   __shared__ Real U[2][NC][NPT];    // nodal values: own cell (0), other cell (1)
   __shared__ Real ev[2][NQ][NC][NE];// value, d/dxi_theta, d/dxi_r, d/dxi_z at the points
   __shared__ Real cf[NQ][NC][NE];   // own-side test coefficients times JxW
   __shared__ Real Lo[N][N], dLo[N][N];  // own theta basis at the segment's points [qt][a]
+  __shared__ double X[XI][3][XN];   // iso: node positions of both cells
+  __shared__ double Jq[XI][XQ][DIM][DIM];  // iso: d x_m / d xi_p at the points, both sides
   const int tid = threadIdx.x;
+  double crot = 1.0, srot = 0.0;
+  if constexpr (ISO) sincos(MG.theta_rot, &srot, &crot);
   const int nf0 = G.nth[0] * G.nz;
   const int nsides = nf0 + G.nth[1] * G.nz;
   const int fs = blockIdx.x;
@@ -2312,6 +2603,17 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
       const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
       const bool fixed = (mask != 0) & ((m < DIM) ? vel_fixed<Real, DIM>(G, C.dom, ir, iz) : p_fixed(G, C.dom, it, ir, iz));
       U[slot][m][node] = fixed ? Real(0) : src[nd * NC + m];
+    }
+    if constexpr (ISO) {
+      for (int node = tid; node < NPT; node += 64) {
+        const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+        int it, ir, iz;
+        const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
+        double x[3];
+        node_position(MG.xnode, nd, C.dom == 0, crot, srot, x);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) X[slot][m][node] = x[m];
+      }
     }
   };
   load_cell(own, 0);
@@ -2378,6 +2680,40 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
       o[2] = dr;
       if constexpr (DIM == 3) o[3] = dz;
     }
+    if constexpr (ISO) {
+      // Jacobian of both sides' maps at the points: the same contraction of
+      // the node positions
+      for (int e = tid; e < 2 * NQ * DIM; e += 64) {
+        const int sd = e / (NQ * DIM), q = (e / DIM) % NQ, m = e % DIM;
+        const int qt = q % N, qz = q / N;
+        const double sl = lo + (double)T.x[qt] * (hi - lo);
+        double L[N], dL[N];
+        lagrange_gll<N>(MG.gll, sd == 0 ? sl / F.dth_s : (sl - a_f) / F.dth_o, L, dL);
+        const int cs = sd == 0 ? side : 1 - side;
+        double dt = 0, dr = 0, dz = 0;
+#pragma unroll
+        for (int c = 0; c < NZ; ++c) {
+          const double lz = (DIM == 3) ? (double)T.V[qz][c] : 1.0;
+          const double dlz = (DIM == 3) ? (double)T.D[qz][c] : 0.0;
+#pragma unroll
+          for (int b = 0; b < N; ++b) {
+            double s0 = 0, s1 = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+              const double x = X[sd][m][(c * N + b) * N + a];
+              s0 += L[a] * x;
+              s1 += dL[a] * x;
+            }
+            dt += lz * MG.FV[cs][b] * s1;
+            dr += lz * MG.FD[cs][b] * s0;
+            dz += dlz * MG.FV[cs][b] * s0;
+          }
+        }
+        Jq[sd][q][m][0] = dt;
+        Jq[sd][q][m][1] = dr;
+        if constexpr (DIM == 3) Jq[sd][q][m][2] = dz;
+      }
+    }
     __syncthreads();
     // the own side's face coefficients at every point
     for (int q = tid; q < NQ; q += 64) {
@@ -2392,17 +2728,44 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
       n[0] = side == 0 ? c : -c;
       n[1] = side == 0 ? sn : -sn;
       const Real pbar = Real(0.5) * (ev[0][q][DIM][0] + ev[1][q][DIM][0]);
+      Real Ko[DIM][DIM], Kx[DIM][DIM];  // iso: inverse Jacobians of both sides
+      if constexpr (ISO) {
+        double K[DIM][DIM];
+        invert_jacobian<DIM>(Jq[0][q], K);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) Ko[a][m] = (Real)K[a][m];
+        invert_jacobian<DIM>(Jq[1][q], K);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) Kx[a][m] = (Real)K[a][m];
+      }
       Real jn = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
         const Real* eo = ev[0][q][m];
         const Real* ex = ev[1][q][m];
-        const Real dro = eo[2] * (Real)idr_s, dto = eo[1] * (Real)irdth_s;
-        const Real drx = ex[2] * (Real)idr_o, dtx = ex[1] * (Real)irdth_o;
         Real gavg[DIM];
-        gavg[0] = Real(0.5) * ((c * dro - sn * dto) + (c * drx - sn * dtx));
-        gavg[1] = Real(0.5) * ((sn * dro + c * dto) + (sn * drx + c * dtx));
-        if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * (Real)MG.inv_dz;
+        if constexpr (ISO) {
+#pragma unroll
+          for (int d2 = 0; d2 < DIM; ++d2) {
+            Real go = 0, gx = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              go += Ko[a][d2] * eo[1 + a];
+              gx += Kx[a][d2] * ex[1 + a];
+            }
+            gavg[d2] = Real(0.5) * (go + gx);
+          }
+        } else {
+          const Real dro = eo[2] * (Real)idr_s, dto = eo[1] * (Real)irdth_s;
+          const Real drx = ex[2] * (Real)idr_o, dtx = ex[1] * (Real)irdth_o;
+          gavg[0] = Real(0.5) * ((c * dro - sn * dto) + (c * drx - sn * dtx));
+          gavg[1] = Real(0.5) * ((sn * dro + c * dto) + (sn * drx + c * dtx));
+          if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * (Real)MG.inv_dz;
+        }
         Real gn = 0;
 #pragma unroll
         for (int d2 = 0; d2 < DIM; ++d2) gn += gavg[d2] * n[d2];
@@ -2414,9 +2777,19 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
         for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
         Real* o = cf[q][m];
         o[0] = J * cv;
-        o[1] = J * (-sn * Gm[0] + c * Gm[1]) * (Real)irdth_s;
-        o[2] = J * (c * Gm[0] + sn * Gm[1]) * (Real)idr_s;
-        if constexpr (DIM == 3) o[3] = J * Gm[2] * (Real)MG.inv_dz;
+        if constexpr (ISO) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            Real t = 0;
+#pragma unroll
+            for (int d2 = 0; d2 < DIM; ++d2) t += Ko[a][d2] * Gm[d2];
+            o[1 + a] = J * t;
+          }
+        } else {
+          o[1] = J * (-sn * Gm[0] + c * Gm[1]) * (Real)irdth_s;
+          o[2] = J * (c * Gm[0] + sn * Gm[1]) * (Real)idr_s;
+          if constexpr (DIM == 3) o[3] = J * Gm[2] * (Real)MG.inv_dz;
+        }
       }
       Real* o = cf[q][DIM];
       o[0] = J * Real(-0.5) * jn;
@@ -2499,6 +2872,127 @@ __global__ __launch_bounds__(64) void k_mortar_diag_general(Geom<Real> G, Tab1D<
   }
 }
 
+// The same on iso-parametric cells: grad phi . n through the inverse
+// Jacobian of the own cell's interpolated map at each mortar point, which is
+// formed once per point in LDS from the cell's node positions.
+template <typename Real, int DIM, int N>
+__global__ __launch_bounds__(64) void k_mortar_diag_iso(Geom<Real> G, Tab1D<Real, N> T, int k, MortarGen MG,
+                                                        Real* __restrict__ diag) {
+  using S = Shape<Real, DIM, N>;
+  constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ, NQ = N * NZ;
+  constexpr int NI = (NPT + 63) / 64;
+  __shared__ double X[3][NPT];
+  __shared__ double Kq[NQ][DIM][DIM];
+  __shared__ double Lq[NQ][N], dLq[NQ][N];  // own theta basis at the points
+  const int tid = threadIdx.x;
+  const int nf0 = G.nth[0] * G.nz;
+  const int fs = blockIdx.x;
+  const int side = fs >= nf0;
+  const int f = side ? fs - nf0 : fs;
+  const int nts = pick(side, G.nth);
+  const int ct = f % nts, cz = f / nts;
+  const CellId own{side, ct, side == 0 ? G.nr[0] - 1 : 0, cz};
+  const GenFace F = gen_face(G, MG, side, ct);
+  double crot, srot;
+  sincos(MG.theta_rot, &srot, &crot);
+  for (int node = tid; node < NPT; node += 64) {
+    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+    int it, ir, iz;
+    const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
+    double x[3];
+    node_position(MG.xnode, nd, side == 0, crot, srot, x);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) X[m][node] = x[m];
+  }
+  const double nu = (double)G.nu, tau = MG.tau_pen[side];
+  const double sgn = side == 0 ? 1.0 : -1.0;  // n = +-e_r
+  double acc[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) acc[i] = 0;
+  for (int p = 0; p < kMaxPieces; ++p) {
+    const double a_f = (F.f0 + p) * F.dth_o - F.delta;
+    if (a_f >= F.dth_s - F.tol) break;
+    const double lo = fmax(0.0, a_f), hi = fmin(F.dth_s, a_f + F.dth_o);
+    if (hi - lo <= F.tol) continue;
+    __syncthreads();  // X loaded; the previous piece is done with Kq, Lq
+    for (int q = tid; q < NQ; q += 64) {
+      const int qt = q % N, qz = q / N;
+      double L[N], dL[N];
+      lagrange_gll<N>(MG.gll, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
+      double J[DIM][DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        double dt = 0, dr = 0, dz = 0;
+        for (int c = 0; c < NZ; ++c) {
+          const double lz = (DIM == 3) ? (double)T.V[qz][c] : 1.0;
+          const double dlz = (DIM == 3) ? (double)T.D[qz][c] : 0.0;
+          for (int b = 0; b < N; ++b) {
+            double s0 = 0, s1 = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+              const double x = X[m][(c * N + b) * N + a];
+              s0 += L[a] * x;
+              s1 += dL[a] * x;
+            }
+            dt += lz * MG.FV[side][b] * s1;
+            dr += lz * MG.FD[side][b] * s0;
+            dz += dlz * MG.FV[side][b] * s0;
+          }
+        }
+        J[m][0] = dt;
+        J[m][1] = dr;
+        if constexpr (DIM == 3) J[m][2] = dz;
+      }
+      double K[DIM][DIM];
+      invert_jacobian<DIM>(J, K);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) Kq[q][a][m] = K[a][m];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        Lq[q][a] = L[a];
+        dLq[q][a] = dL[a];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const int node = tid + 64 * ii;
+      if (node >= NPT) continue;
+      const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+      const double fv = MG.FV[side][b], fd = MG.FD[side][b];
+      for (int q = 0; q < NQ; ++q) {
+        const int qt = q % N, qz = q / N;
+        const double vz = (DIM == 3) ? (double)T.V[qz][c] : 1.0;
+        const double dvz = (DIM == 3) ? (double)T.D[qz][c] : 0.0;
+        double jxw = (double)T.w[qt] * MG.R * (hi - lo);
+        if (DIM == 3) jxw *= (double)T.w[qz] / MG.inv_dz;
+        const double phi = Lq[q][a] * fv * vz;
+        double dref[3] = {dLq[q][a] * fv * vz, Lq[q][a] * fd * vz, Lq[q][a] * fv * dvz};
+        // grad phi . n with n = sgn (cos theta, sin theta) at the point
+        double sth, cth;
+        sincos(F.start + lo + (double)T.x[qt] * (hi - lo), &sth, &cth);
+        double gn = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < DIM; ++a2) gn += (Kq[q][a2][0] * cth + Kq[q][a2][1] * sth) * dref[a2];
+        gn *= sgn;
+        acc[ii] += jxw * (nu * tau * phi * phi - nu * phi * gn);
+      }
+    }
+  }
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const int node = tid + 64 * ii;
+    if (node >= NPT) continue;
+    const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+    int it, ir, iz;
+    const long long nd = node_of<Real, DIM>(G, k, own, a, b, c, it, ir, iz);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) atomic_add(diag + nd * NC + m, (Real)acc[ii]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // small vector kernels
 // ---------------------------------------------------------------------------
@@ -2578,10 +3072,14 @@ static Geom<Real> make_geom(const mns_handle* h) {
   if constexpr (sizeof(Real) == 8) {
     G.hcell = (const Real*)h->d_hcell64;
     G.trig = (const Real*)h->d_trig64;
+    G.geo = h->iso ? (const Real*)h->d_geo64 : nullptr;
   } else {
     G.hcell = (const Real*)h->d_hcell32;
     G.trig = (const Real*)h->d_trig32;
+    G.geo = h->iso ? (const Real*)h->d_geo32 : nullptr;
   }
+  G.geox = h->iso ? h->d_geox : nullptr;
+  G.hiso = h->iso ? h->d_hiso : nullptr;
   return G;
 }
 
@@ -2590,6 +3088,7 @@ static MortarGen make_mortar_gen(const mns_handle* h) {
   MortarGen M{};
   const mns_mesh_desc& d = h->desc;
   M.theta_rot = h->theta;
+  M.xnode = h->iso ? h->d_xnode : nullptr;
   M.R = d.r_interface;
   M.tau_pen[0] = h->tau_pen[0];
   M.tau_pen[1] = h->tau_pen[1];
@@ -2674,6 +3173,12 @@ template <typename Real, int DIM, int N>
 static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStream_t s) {
   const Geom<Real> G = make_geom<Real>(h);
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
+  if (h->iso) {
+    const unsigned nfs = (unsigned)((h->nth[0] + h->nth[1]) * G.nz);
+    launch_k(h, TIMER_MORTAR, k_mortar_general<Real, DIM, N, true>, dim3(nfs), dim3(64), s, G, T, h->k,
+             make_mortar_gen(h), src, Em, mask);
+    return hip_check(h, "iso-parametric mortar kernel");
+  }
   if (!h->equal_rings) {
     const unsigned nfs = (unsigned)((h->nth[0] + h->nth[1]) * G.nz);
     launch_k(h, TIMER_MORTAR, k_mortar_general<Real, DIM, N>, dim3(nfs), dim3(64), s, G, T, h->k, make_mortar_gen(h),
@@ -2720,7 +3225,10 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
   Real* E = E_ws ? E_ws : (sizeof(Real) == 8 ? (Real*)h->d_E64 : (Real*)h->d_E32);
   Real* Em = Em_ws ? Em_ws : (sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32);
   constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
-  const bool quad = kQuad && h->quad;
+  // iso-parametric cells: LDS-plane layout with the per-point metric,
+  // general mortar kernel in its own launch
+  const bool iso = h->iso;
+  const bool quad = kQuad && h->quad && !iso;
   // linearization source C (tau and tau R per point, a and grad u from the
   // state) where the quad kernels have it
   constexpr bool kLinC = kLinCLayout<Real, DIM, N>;
@@ -2737,8 +3245,9 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
   // launch mode; automatic: one fused launch for small meshes (the mortar
   // work is a latency tail there), the concurrent second stream for large ones
   int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
-  // unequal ring counts: the general mortar kernel runs as its own launch
-  if (!h->equal_rings && mode == 1) mode = 0;
+  // unequal ring counts and iso-parametric cells: the general mortar kernel
+  // runs as its own launch
+  if ((!h->equal_rings || iso) && mode == 1) mode = 0;
   if (mode == 1) {
     // one launch of volume cell blocks and mortar face blocks
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
@@ -2797,7 +3306,10 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
         launch_k(h, TIMER_VOLUME, k_jacobian_volume_quad<Real, N, false>, dim3(blocks), dim3(64), s, G, T, h->k, lin,
                  src, E, strip, state, picard);
     }
-    if (!quad)
+    if (iso)
+      launch_k(h, TIMER_VOLUME, k_jacobian_volume<Real, DIM, N, true>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src,
+               E);
+    else if (!quad)
       launch_k(h, TIMER_VOLUME, k_jacobian_volume<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, lin, src, E);
     rc = hip_check(h, "volume kernel");
     if (rc) return rc;
@@ -3132,8 +3644,12 @@ static int do_state(mns_handle* h, const double* state, const double* hist, cons
   const Geom<double> G = make_geom<double>(h);
   const Tab1D<double, N> T = make_tab<double, N>(h);
   const unsigned blocks = (unsigned)((G.ncells + S::CPW - 1) / S::CPW);
-  hipLaunchKernelGGL((k_state<DIM, N, RES>), dim3(blocks), dim3(64), 0, s, G, T, h->k, state, hist, force, lin,
-                     res, RES ? 0 : h->picard);
+  if (h->iso)
+    hipLaunchKernelGGL((k_state_iso<DIM, N, RES>), dim3(blocks), dim3(64), 0, s, G, T, h->k, state, hist, force, lin,
+                       res, RES ? 0 : h->picard);
+  else
+    hipLaunchKernelGGL((k_state<DIM, N, RES>), dim3(blocks), dim3(64), 0, s, G, T, h->k, state, hist, force, lin,
+                       res, RES ? 0 : h->picard);
   return hip_check(h, RES ? "residual kernel" : "linearization kernel");
 }
 
@@ -3166,11 +3682,18 @@ static int do_diag(mns_handle* h, Real* diag, hipStream_t s) {
   int rc = launch_fill<Real>(diag, Real(0), h->ndofs, s);
   if (rc) return set_error(h, rc, "fill");
   const long long total = (long long)G.ncells * S::NPT;
-  hipLaunchKernelGGL((k_diag_volume<Real, DIM, N>), dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, G, T,
-                     h->k, lin, diag);
+  if (h->iso)
+    hipLaunchKernelGGL((k_diag_volume<Real, DIM, N, true>), dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, G,
+                       T, h->k, lin, diag);
+  else
+    hipLaunchKernelGGL((k_diag_volume<Real, DIM, N>), dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, G, T,
+                       h->k, lin, diag);
   rc = hip_check(h, "diagonal kernel");
   if (rc) return rc;
-  if (h->equal_rings) {
+  if (h->iso) {
+    hipLaunchKernelGGL((k_mortar_diag_iso<Real, DIM, N>), dim3((unsigned)((h->nth[0] + h->nth[1]) * G.nz)), dim3(64),
+                       0, s, G, T, h->k, make_mortar_gen(h), diag);
+  } else if (h->equal_rings) {
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
     const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
     hipLaunchKernelGGL((k_mortar_diag<Real, DIM, N>), dim3(2u * (unsigned)(G.nth[0] * G.nz)), dim3(64), 0, s, G, T,

@@ -183,3 +183,62 @@ def batch_instances(count=48, seed=21):
         m["nu"] = 1.0 / re
         out.append((m, float(g.uniform(0.0, TWO_PI)), 1.0, 100 + i))
     return out
+
+
+def lobatto_nodes(k):
+    """The k + 1 Gauss-Lobatto nodes on [0, 1] (0, the roots of P_k', 1): where
+    a degree-k cell has its nodes along each direction."""
+    inner = np.sort(np.polynomial.legendre.Legendre.basis(k).deriv().roots().real)
+    return np.concatenate([[0.0], 0.5 * (inner + 1.0), [1.0]])
+
+
+def iso_node_positions(m, perturb):
+    """Node positions of a curved (iso-parametric) mesh: every Gauss-Lobatto
+    node of the annular mesh, at polar position (r, theta_m, z) in the
+    material frame, moved by
+        dr     = e dr_c  s cos(3 theta_m + 2 pi z / H)
+        dtheta = e dth_c s sin(2 theta_m) (1 + cos(2 pi z / H) / 2)
+        dz     = e dz_c  s sin(theta_m) sin(pi z / H)        (3D)
+    with e = perturb, dr_c, dth_c, dz_c the cell sizes of the node's domain and
+    s = sin(pi (r - r_a) / (r_b - r_a)) on that domain [r_a, r_b], so that the
+    nodes of the walls and of the interface keep their radius and angle.
+    Returns an (n_nodes, 3) array in the node order of the vector layout,
+    rotor nodes unrotated (z = 0 in 2D)."""
+    k, dim = m["degree"], m["dim"]
+    g = lobatto_nodes(k)
+    nz = m["n_z"] if dim == 3 else 1
+    H = m["height"] if dim == 3 else 1.0
+    dz_c = H / nz
+    nts = m.get("n_theta_stator") or m["n_theta"]
+    out = []
+    for nt, nr, ra, rb in ((m["n_theta"], m["n_r_rotor"], m["r_in"], m["r_if"]),
+                           (nts, m["n_r_stator"], m["r_if"], m["r_out"])):
+        dth_c, dr_c = TWO_PI / nt, (rb - ra) / nr
+        it = np.arange(k * nt)
+        ir = np.arange(k * nr + 1)
+        iz = np.arange(k * nz + 1) if dim == 3 else np.zeros(1, dtype=int)
+        th = (it // k + g[it % k]) * dth_c
+        r = ra + (ir // k + g[ir % k]) * dr_c
+        z = (iz // k + g[iz % k]) * dz_c if dim == 3 else np.zeros(1)
+        Z, R, T = np.meshgrid(z, r, th, indexing="ij")
+        s = np.sin(math.pi * (R - ra) / (rb - ra))
+        zr = 2.0 * math.pi * Z / H if dim == 3 else np.zeros_like(Z)
+        rr = R + perturb * dr_c * s * np.cos(3.0 * T + zr)
+        tt = T + perturb * dth_c * s * np.sin(2.0 * T) * (1.0 + 0.5 * np.cos(zr))
+        zz = Z + (perturb * dz_c * s * np.sin(T) * np.sin(math.pi * Z / H) if dim == 3 else 0.0)
+        out.append(np.stack([(rr * np.cos(tt)).ravel(), (rr * np.sin(tt)).ravel(), np.broadcast_to(zz, rr.shape).ravel()],
+                            axis=1))
+    return np.concatenate(out, axis=0)
+
+
+def rotate_rotor_nodes(m, xyz, theta):
+    """Node positions with the rotor block rotated by theta about the z axis
+    (x = R(theta) x0): the current configuration of the mesh."""
+    ntn, nrr, _, nzn = node_grid(m)
+    n_rot = ntn * nrr * nzn
+    out = np.array(xyz, dtype=np.float64, copy=True)
+    c, s = math.cos(theta), math.sin(theta)
+    x, y = out[:n_rot, 0].copy(), out[:n_rot, 1].copy()
+    out[:n_rot, 0] = c * x - s * y
+    out[:n_rot, 1] = s * x + c * y
+    return out
