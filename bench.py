@@ -461,7 +461,7 @@ def iso_leg(name, dev, sync, steps=100, warmup=10):
                       "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
                       "frac_of_8TBs": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       "volume_launch_frac_of_8TBs": nbytes / (vol_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                      "volume_kernel": f"mns::k_jacobian_volume<{real}, {mesh['dim']}, {mesh['degree'] + 1}, true>"}
+                      "volume_kernel": f"mns::k_jacobian_fused<{real}, {mesh['dim']}, {mesh['degree'] + 1}, true>"}
         del y
     out["fp32_speedup_over_fp64"] = out["fp64"]["ms_per_vmult"] / out["fp32"]["ms_per_vmult"]
     # mixed-precision solve on the curved and on the polar mesh

@@ -42,7 +42,8 @@ static void free_all(mns_handle* h) {
                    (void**)&h->d_Em32, (void**)&h->d_diag64, (void**)&h->d_diag32, (void**)&h->d_red, (void**)&h->d_gm,
                    (void**)&h->d_step, (void**)&h->d_state, (void**)&h->d_linc64, (void**)&h->d_linc32,
                    (void**)&h->d_state32, (void**)&h->d_xnode, (void**)&h->d_geo64, (void**)&h->d_geo32,
-                   (void**)&h->d_geox, (void**)&h->d_hiso, (void**)&h->d_iso_flag};
+                   (void**)&h->d_geox, (void**)&h->d_hiso, (void**)&h->d_iso_flag, (void**)&h->d_mgeo64,
+                   (void**)&h->d_mgeo32};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;

@@ -40,6 +40,19 @@ struct IsoLayout {
   static constexpr int SIZE = B + DIM;
 };
 
+// Per mortar point of an iso-parametric interface, stored per face side,
+// segment slot and point at every rotor angle: the inverse Jacobians
+// K[p][m] = d xi_p / d x_m of the own and the other side's interpolated map
+// there, and cos, sin of the point's angle.
+template <int DIM>
+struct IsoMortarLayout {
+  static constexpr int KO = 0;
+  static constexpr int KX = DIM * DIM;
+  static constexpr int C = 2 * DIM * DIM;
+  static constexpr int S = C + 1;
+  static constexpr int SIZE = S + 1;
+};
+
 // 1D tables: Lagrange basis on N Gauss-Lobatto nodes of [0,1] evaluated at the
 // N Gauss points (the volume quadrature of every cell).
 template <typename Real, int N>
@@ -105,11 +118,15 @@ struct MortarTab {
 struct MortarGen {
   double theta_rot;                   // rotor angle
   const double* xnode;                // iso-parametric node positions [node][3] (material frame), or null
+  const void* iso_geo;                // iso-parametric mortar point geometry (IsoMortarLayout, the launch's
+                                      // precision) at the current angle, or null
+  int npiece;                         // segment slots per face side in iso_geo
   double R;                           // interface radius
   double tau_pen[2];                  // penalty of the rotor and stator interface cells (Eq. EqPenalty)
   double inv_dr[2];                   // 1 / dr of the rotor and stator cells
   double inv_dz;                      // 1 / dz (3D), 0 in 2D
   double gll[kMaxN];                  // Gauss-Lobatto nodes on [0, 1]
+  double ginv[kMaxN][kMaxN];          // 1 / (gll[j] - gll[q]) (0 for j = q)
   double FV[2][kMaxN], FD[2][kMaxN];  // L_b, L_b' at the interface (xi_r = 1 rotor, 0 stator)
 };
 
@@ -190,6 +207,9 @@ struct mns_handle {
   double* d_geox = nullptr;     // [cell][point][3] physical positions of the Gauss points
   double* d_hiso = nullptr;     // [cell] element size from the cell volume
   int* d_iso_flag = nullptr;    // set by the metric kernel where det J >= 0
+  double* d_mgeo64 = nullptr;   // [face side][segment slot][mortar point][IsoMortarLayout::SIZE]
+  float* d_mgeo32 = nullptr;
+  int mgeo_pieces = 0;          // segment slots per face side
   long long lin_version = 0;    // incremented by every rotation and linearization
   void* mg = nullptr;           // multigrid hierarchy (mns_solver.hip)
   double* h_red = nullptr;      // pinned host mirror
@@ -314,6 +334,10 @@ int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
 // element sizes and penalty; the per-point tables at the current angle
 int iso_set_nodes(mns_handle* h, const double* xyz, int64_t n_nodes, hipStream_t s);
 int iso_rotate(mns_handle* h, double theta, hipStream_t s);
+// segment slots per face side of the mortar point table, and the table of
+// the current angle (mns_kernels.hip)
+int iso_mortar_pieces(const mns_handle* h);
+int launch_iso_mortar_geo(mns_handle* h, hipStream_t s);
 
 // host setup (mns_setup.cpp)
 void rules_1d(int n, std::vector<double>& gll, std::vector<double>& gx, std::vector<double>& gw);

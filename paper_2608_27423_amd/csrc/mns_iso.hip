@@ -5,9 +5,9 @@
 // (Eq. EqPenalty) from the interpolated cells, and at every rotor angle
 // (Sec. 3.1, x = R(theta) x0) rebuilds per Gauss point the inverse Jacobian,
 // JxW and the mapping term of the Laplacian that the volume kernels read.
-// The mortar integrals stay on the exact interface circle; their kernels
-// evaluate the cells' inverse Jacobians at the mortar points from the same
-// node positions.
+// The mortar integrals stay on the exact interface circle; the inverse
+// Jacobians of both sides' interpolated maps at every mortar point are
+// rebuilt into a table at every angle as well.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -372,6 +372,13 @@ int iso_set_nodes(mns_handle* h, const double* xyz, int64_t n_nodes, hipStream_t
         (e = hipMalloc((void**)&h->d_hiso, (size_t)h->ncells * sizeof(double))) != hipSuccess ||
         (e = hipMalloc((void**)&h->d_iso_flag, sizeof(int))) != hipSuccess)
       return hipfail(h, e, "hipMalloc iso-parametric tables");
+    // mortar point geometry: face sides x segment slots x points
+    h->mgeo_pieces = iso_mortar_pieces(h);
+    const size_t nmg = (size_t)(h->nth[0] + h->nth[1]) * h->nz * h->mgeo_pieces * (d.dim == 3 ? h->n * h->n : h->n) *
+                       (d.dim == 3 ? IsoMortarLayout<3>::SIZE : IsoMortarLayout<2>::SIZE);
+    if ((e = hipMalloc((void**)&h->d_mgeo64, nmg * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&h->d_mgeo32, nmg * sizeof(float))) != hipSuccess)
+      return hipfail(h, e, "hipMalloc iso-parametric mortar tables");
   }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hipfail(h, e, "synchronize");
   const int zero = 0;
@@ -410,7 +417,8 @@ int iso_set_nodes(mns_handle* h, const double* xyz, int64_t n_nodes, hipStream_t
 
 int iso_rotate(mns_handle* h, double theta, hipStream_t s) {
   if (!h->iso) return MNS_OK;
-  return metric(h, theta, true, s);
+  const int rc = metric(h, theta, true, s);
+  return rc ? rc : launch_iso_mortar_geo(h, s);
 }
 
 }  // namespace mns

@@ -12,6 +12,7 @@
 // applies the constraint rows, so the product is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 #include <mutex>
@@ -736,7 +737,7 @@ struct VolumeSmem {
 // ISO: iso-parametric cells (per-point metric G.geo, mixed second
 // derivatives of the increment's velocity in the Laplacian)
 template <typename Real, int DIM, int N, bool ISO = false>
-__device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
+__device__ __attribute__((always_inline)) inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int vblock,
                                     const Real* __restrict__ lin, const Real* __restrict__ src,
                                     Real* __restrict__ E, VolumeSmem<Real, DIM, N, ISO>& sm) {
   using S = Shape<Real, DIM, N>;
@@ -781,6 +782,18 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
 
 #pragma unroll
   for (int q = 0; q < NZ; ++q) {
+    // iso-parametric metric of the lane's point in plane q, requested before
+    // the z and r stages so that its latency overlaps them (3D degree 4:
+    // requested at the theta stage, where the registers allow it)
+    constexpr bool kEarlyGeo = ISO && (DIM == 2 || N <= 4);
+    Real gq[kEarlyGeo ? IsoLayout<DIM>::SIZE : 1];
+    if constexpr (kEarlyGeo) {
+      if (active) {
+        const Real* gp = G.geo + ((size_t)cell * S::NPT + q * PL + me) * IsoLayout<DIM>::SIZE;
+#pragma unroll
+        for (int j = 0; j < IsoLayout<DIM>::SIZE; ++j) gq[j] = gp[j];
+      }
+    }
     // ---- z stage for plane q (registers) -> A
     if (active) {
 #pragma unroll
@@ -919,7 +932,8 @@ __device__ inline void volume_block(const Geom<Real>& G, const Tab1D<Real, N>& T
       Real tc[NC][S::NT];
       if constexpr (ISO) {
         IsoPt<Real, DIM> g;
-        g.load(G.geo + ((size_t)cell * S::NPT + q * PL + me) * IsoLayout<DIM>::SIZE);
+        if constexpr (kEarlyGeo) g.load(gq);
+        else g.load(G.geo + ((size_t)cell * S::NPT + q * PL + me) * IsoLayout<DIM>::SIZE);
         pointwise_jacobian<Real, DIM>(g, rv, rp, lv, nu, ct, tc);
       } else {
         const PtGeom<Real> g = point_geom<Real, DIM, N>(G, sT, C, ta, tb, q);
@@ -2062,11 +2076,14 @@ struct MortarSmem {
   Real coef[MS::FPB][2][MS::NQ][MS::PQ];
 };
 
-template <typename Real, int DIM, int N, int BUDGET = 36000>
+// ISO: iso-parametric cells; phase B takes the inverse Jacobians of both
+// sides at every point from iso_mg (IsoMortarLayout per face side, piece and
+// point at the current angle) instead of the polar formulas
+template <typename Real, int DIM, int N, int BUDGET = 36000, bool ISO = false>
 __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T, int k, int mblock,
                                     const MortarTab<Real, N>* __restrict__ Mp, const Real* __restrict__ mtrig,
                                     const Real* __restrict__ src, Real* __restrict__ Em, int mask,
-                                    MortarSmem<Real, DIM, N, BUDGET>& sm) {
+                                    MortarSmem<Real, DIM, N, BUDGET>& sm, const Real* __restrict__ iso_mg = nullptr) {
   using S = Shape<Real, DIM, N>;
   using MS = MortarShape<Real, DIM, N, BUDGET>;
   constexpr int NC = MS::NC, NZ = MS::NZ, NQ = MS::NQ, NE = MS::NE, FPB = MS::FPB;
@@ -2244,18 +2261,43 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
       Real n[DIM] = {};
       n[0] = side == 0 ? cth : -cth;
       n[1] = side == 0 ? sth : -sth;
+      Real Ko[DIM][DIM], Kx[DIM][DIM];
+      if constexpr (ISO) {
+        using IM = IsoMortarLayout<DIM>;
+        const Real* g = iso_mg + ((size_t)(fs * 2 + pc) * NQ + q) * IM::SIZE;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int d2 = 0; d2 < DIM; ++d2) {
+            Ko[a][d2] = g[IM::KO + a * DIM + d2];
+            Kx[a][d2] = g[IM::KX + a * DIM + d2];
+          }
+      }
       const Real pbar = Real(0.5) * (ev[fl][pc][0][q][DIM * NE] + ev[fl][pc][1][q][DIM * NE]);
       Real jn = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
         const Real* eo = &ev[fl][pc][0][q][m * NE];
         const Real* ex = &ev[fl][pc][1][q][m * NE];
-        const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
-        const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
         Real gavg[DIM];
-        gavg[0] = Real(0.5) * ((cth * dro - sth * dto) + (cth * drx - sth * dtx));
-        gavg[1] = Real(0.5) * ((sth * dro + cth * dto) + (sth * drx + cth * dtx));
-        if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * inv_dz;
+        if constexpr (ISO) {
+#pragma unroll
+          for (int d2 = 0; d2 < DIM; ++d2) {
+            Real go = 0, gx = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              go += Ko[a][d2] * eo[1 + a];
+              gx += Kx[a][d2] * ex[1 + a];
+            }
+            gavg[d2] = Real(0.5) * (go + gx);
+          }
+        } else {
+          const Real dro = eo[2] * idr_o, dto = eo[1] * inv_rdth;
+          const Real drx = ex[2] * idr_x, dtx = ex[1] * inv_rdth;
+          gavg[0] = Real(0.5) * ((cth * dro - sth * dto) + (cth * drx - sth * dtx));
+          gavg[1] = Real(0.5) * ((sth * dro + cth * dto) + (sth * drx + cth * dtx));
+          if constexpr (DIM == 3) gavg[2] = Real(0.5) * (eo[3] + ex[3]) * inv_dz;
+        }
         Real gn = 0;
 #pragma unroll
         for (int d2 = 0; d2 < DIM; ++d2) gn += gavg[d2] * n[d2];
@@ -2267,9 +2309,19 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
         for (int d2 = 0; d2 < DIM; ++d2) Gm[d2] = Real(-0.5) * nu * j * n[d2];
         Real* cf = &coef[fl][pc][q][m * NE];
         cf[0] = jxw * cv;
-        cf[1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
-        cf[2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
-        if constexpr (DIM == 3) cf[3] = jxw * Gm[2] * inv_dz;
+        if constexpr (ISO) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            Real t = 0;
+#pragma unroll
+            for (int d2 = 0; d2 < DIM; ++d2) t += Ko[a][d2] * Gm[d2];
+            cf[1 + a] = jxw * t;
+          }
+        } else {
+          cf[1] = jxw * (-sth * Gm[0] + cth * Gm[1]) * inv_rdth;
+          cf[2] = jxw * (cth * Gm[0] + sth * Gm[1]) * idr_o;
+          if constexpr (DIM == 3) cf[3] = jxw * Gm[2] * inv_dz;
+        }
       }
       Real* cf = &coef[fl][pc][q][DIM * NE];
       cf[0] = jxw * Real(-0.5) * jn;
@@ -2340,33 +2392,35 @@ __device__ inline void mortar_block(const Geom<Real>& G, const Tab1D<Real, N>& T
   }
 }
 
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(64) void k_mortar(Geom<Real> G, Tab1D<Real, N> T, int k,
                                                const MortarTab<Real, N>* __restrict__ Mp,
                                                const Real* __restrict__ mtrig, const Real* __restrict__ src,
-                                               Real* __restrict__ Em, int mask) {
+                                               Real* __restrict__ Em, int mask, const Real* __restrict__ iso_mg) {
   __shared__ MortarSmem<Real, DIM, N> sm;
-  mortar_block<Real, DIM, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, mask, sm);
+  mortar_block<Real, DIM, N, 36000, ISO>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, mask, sm, iso_mg);
 }
 
 // Fused launch: blocks [0, nmb) integrate mortar faces, the rest integrate
 // volume cells; the two block kinds share one LDS allocation.
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 union FusedSmem {
-  VolumeSmem<Real, DIM, N> v;
+  VolumeSmem<Real, DIM, N, ISO> v;
   MortarSmem<Real, DIM, N> m;
 };
 
-template <typename Real, int DIM, int N>
+template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(64) void k_jacobian_fused(Geom<Real> G, Tab1D<Real, N> T, int k, int nmb,
                                                                     const Real* __restrict__ lin,
                                                                     const MortarTab<Real, N>* __restrict__ Mp,
                                                                     const Real* __restrict__ mtrig,
                                                                     const Real* __restrict__ src,
-                                                                    Real* __restrict__ E, Real* __restrict__ Em) {
-  __shared__ FusedSmem<Real, DIM, N> sm;
-  if ((int)blockIdx.x < nmb) mortar_block<Real, DIM, N>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1, sm.m);
-  else volume_block<Real, DIM, N>(G, T, k, blockIdx.x - nmb, lin, src, E, sm.v);
+                                                                    Real* __restrict__ E, Real* __restrict__ Em,
+                                                                    const Real* __restrict__ iso_mg) {
+  __shared__ FusedSmem<Real, DIM, N, ISO> sm;
+  if ((int)blockIdx.x < nmb)
+    mortar_block<Real, DIM, N, 36000, ISO>(G, T, k, blockIdx.x, Mp, mtrig, src, Em, 1, sm.m, iso_mg);
+  else volume_block<Real, DIM, N, ISO>(G, T, k, blockIdx.x - nmb, lin, src, E, sm.v);
 }
 
 // fused launch with the quad volume layout (3D)
@@ -2486,15 +2540,15 @@ __global__ __launch_bounds__(64) void k_mortar_diag(Geom<Real> G, Tab1D<Real, N>
 constexpr int kMaxPieces = 6;  // segments per face: ceil(4) + 2 for ring counts at most 4:1 apart
 
 template <int N>
-__device__ inline void lagrange_gll(const double (&nodes)[kMaxN], double t, double (&L)[N], double (&dL)[N]) {
+__device__ inline void lagrange_gll(const MortarGen& MG, double t, double (&L)[N], double (&dL)[N]) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     double p = 1.0, dp = 0.0;
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       if (q == j) continue;
-      const double inv = 1.0 / (nodes[j] - nodes[q]);
-      const double f = (t - nodes[q]) * inv;
+      const double inv = MG.ginv[j][q];
+      const double f = (t - MG.gll[q]) * inv;
       dp = dp * f + p * inv;
       p = p * f;
     }
@@ -2566,25 +2620,22 @@ __device__ inline void node_position(const double* __restrict__ xnode, long long
 }
 
 // ISO: iso-parametric cells; the gradients at the mortar points go through
-// the inverse Jacobian of each side's interpolated map there (the mortar
-// points, JxW and normals stay those of the exact circle)
+// each side's inverse Jacobian there, read with the points' angles from the
+// table of the current rotor angle (MG.iso_geo; the mortar points, JxW and
+// normals stay those of the exact circle)
 template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real, N> T, int k, MortarGen MG,
                                                        const Real* __restrict__ src, Real* __restrict__ Em,
                                                        int mask) {
   using S = Shape<Real, DIM, N>;
+  using IM = IsoMortarLayout<DIM>;
   constexpr int NC = S::NC, NPT = S::NPT, NZ = S::NZ, NQ = N * NZ, NE = DIM + 1;
   constexpr int NI = (NPT * NC + 63) / 64;
-  constexpr int XI = ISO ? 2 : 1, XN = ISO ? NPT : 1, XQ = ISO ? NQ : 1;
   __shared__ Real U[2][NC][NPT];    // nodal values: own cell (0), other cell (1)
   __shared__ Real ev[2][NQ][NC][NE];// value, d/dxi_theta, d/dxi_r, d/dxi_z at the points
   __shared__ Real cf[NQ][NC][NE];   // own-side test coefficients times JxW
-  __shared__ Real Lo[N][N], dLo[N][N];  // own theta basis at the segment's points [qt][a]
-  __shared__ double X[XI][3][XN];   // iso: node positions of both cells
-  __shared__ double Jq[XI][XQ][DIM][DIM];  // iso: d x_m / d xi_p at the points, both sides
+  __shared__ Real Lt[2][N][N], dLt[2][N][N];  // theta basis of both sides at the segment's points [side][qt][a]
   const int tid = threadIdx.x;
-  double crot = 1.0, srot = 0.0;
-  if constexpr (ISO) sincos(MG.theta_rot, &srot, &crot);
   const int nf0 = G.nth[0] * G.nz;
   const int nsides = nf0 + G.nth[1] * G.nz;
   const int fs = blockIdx.x;
@@ -2604,17 +2655,6 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
       const bool fixed = (mask != 0) & ((m < DIM) ? vel_fixed<Real, DIM>(G, C.dom, ir, iz) : p_fixed(G, C.dom, it, ir, iz));
       U[slot][m][node] = fixed ? Real(0) : src[nd * NC + m];
     }
-    if constexpr (ISO) {
-      for (int node = tid; node < NPT; node += 64) {
-        const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
-        int it, ir, iz;
-        const long long nd = node_of<Real, DIM>(G, k, C, a, b, c, it, ir, iz);
-        double x[3];
-        node_position(MG.xnode, nd, C.dom == 0, crot, srot, x);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) X[slot][m][node] = x[m];
-      }
-    }
   };
   load_cell(own, 0);
   Real acc[NI];
@@ -2629,19 +2669,23 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
     const int fo = F.f0 + p;
     const double a_f = fo * F.dth_o - F.delta;  // other face start, in the own face's local angle
     if (a_f >= F.dth_s - F.tol) break;
+    if (ISO && p >= MG.npiece) break;  // the table's slots bound the segments of a face
     const double lo = fmax(0.0, a_f), hi = fmin(F.dth_s, a_f + F.dth_o);
     if (hi - lo <= F.tol) continue;
     const int ofc = ((fo % F.nto) + F.nto) % F.nto;
     const CellId oth{1 - side, ofc, cr_oth, cz};
-    __syncthreads();  // the previous segment is done with U[1], ev, cf, Lo
+    __syncthreads();  // the previous segment is done with U[1], ev, cf, Lt
     load_cell(oth, 1);
-    for (int qt = tid; qt < N; qt += 64) {
+    // theta basis of both sides at the segment's points
+    for (int i = tid; i < 2 * N; i += 64) {
+      const int sd = i / N, qt = i % N;
+      const double sl = lo + (double)T.x[qt] * (hi - lo);
       double L[N], dL[N];
-      lagrange_gll<N>(MG.gll, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
+      lagrange_gll<N>(MG, sd == 0 ? sl / F.dth_s : (sl - a_f) / F.dth_o, L, dL);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        Lo[qt][a] = (Real)L[a];
-        dLo[qt][a] = (Real)dL[a];
+        Lt[sd][qt][a] = (Real)L[a];
+        dLt[sd][qt][a] = (Real)dL[a];
       }
     }
     __syncthreads();
@@ -2649,9 +2693,6 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
     for (int e = tid; e < 2 * NQ * NC; e += 64) {
       const int sd = e / (NQ * NC), q = (e / NC) % NQ, m = e % NC;
       const int qt = q % N, qz = q / N;
-      const double sl = lo + (double)T.x[qt] * (hi - lo);
-      double L[N], dL[N];
-      lagrange_gll<N>(MG.gll, sd == 0 ? sl / F.dth_s : (sl - a_f) / F.dth_o, L, dL);
       const int cs = sd == 0 ? side : 1 - side;
       Real v = 0, dt = 0, dr = 0, dz = 0;
 #pragma unroll
@@ -2665,8 +2706,8 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
 #pragma unroll
           for (int a = 0; a < N; ++a) {
             const Real u = U[sd][m][(c * N + b) * N + a];
-            s0 += (Real)L[a] * u;
-            s1 += (Real)dL[a] * u;
+            s0 += Lt[sd][qt][a] * u;
+            s1 += dLt[sd][qt][a] * u;
           }
           v += lz * fv * s0;
           dt += lz * fv * s1;
@@ -2680,68 +2721,36 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
       o[2] = dr;
       if constexpr (DIM == 3) o[3] = dz;
     }
-    if constexpr (ISO) {
-      // Jacobian of both sides' maps at the points: the same contraction of
-      // the node positions
-      for (int e = tid; e < 2 * NQ * DIM; e += 64) {
-        const int sd = e / (NQ * DIM), q = (e / DIM) % NQ, m = e % DIM;
-        const int qt = q % N, qz = q / N;
-        const double sl = lo + (double)T.x[qt] * (hi - lo);
-        double L[N], dL[N];
-        lagrange_gll<N>(MG.gll, sd == 0 ? sl / F.dth_s : (sl - a_f) / F.dth_o, L, dL);
-        const int cs = sd == 0 ? side : 1 - side;
-        double dt = 0, dr = 0, dz = 0;
-#pragma unroll
-        for (int c = 0; c < NZ; ++c) {
-          const double lz = (DIM == 3) ? (double)T.V[qz][c] : 1.0;
-          const double dlz = (DIM == 3) ? (double)T.D[qz][c] : 0.0;
-#pragma unroll
-          for (int b = 0; b < N; ++b) {
-            double s0 = 0, s1 = 0;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-              const double x = X[sd][m][(c * N + b) * N + a];
-              s0 += L[a] * x;
-              s1 += dL[a] * x;
-            }
-            dt += lz * MG.FV[cs][b] * s1;
-            dr += lz * MG.FD[cs][b] * s0;
-            dz += dlz * MG.FV[cs][b] * s0;
-          }
-        }
-        Jq[sd][q][m][0] = dt;
-        Jq[sd][q][m][1] = dr;
-        if constexpr (DIM == 3) Jq[sd][q][m][2] = dz;
-      }
-    }
     __syncthreads();
     // the own side's face coefficients at every point
     for (int q = tid; q < NQ; q += 64) {
       const int qt = q % N, qz = q / N;
       const double sl = lo + (double)T.x[qt] * (hi - lo);
-      double sth, cth;
-      sincos(F.start + sl, &sth, &cth);
       double jxw = (double)T.w[qt] * R * (hi - lo);
       if constexpr (DIM == 3) jxw *= (double)T.w[qz] / MG.inv_dz;
-      const Real c = (Real)cth, sn = (Real)sth, J = (Real)jxw;
+      Real c, sn, Ko[DIM][DIM], Kx[DIM][DIM];
+      if constexpr (ISO) {
+        const Real* g = (const Real*)MG.iso_geo + ((size_t)(fs * MG.npiece + p) * NQ + q) * IM::SIZE;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int m = 0; m < DIM; ++m) {
+            Ko[a][m] = g[IM::KO + a * DIM + m];
+            Kx[a][m] = g[IM::KX + a * DIM + m];
+          }
+        c = g[IM::C];
+        sn = g[IM::S];
+      } else {
+        double sth, cth;
+        sincos(F.start + sl, &sth, &cth);
+        c = (Real)cth;
+        sn = (Real)sth;
+      }
+      const Real J = (Real)jxw;
       Real n[DIM] = {};
       n[0] = side == 0 ? c : -c;
       n[1] = side == 0 ? sn : -sn;
       const Real pbar = Real(0.5) * (ev[0][q][DIM][0] + ev[1][q][DIM][0]);
-      Real Ko[DIM][DIM], Kx[DIM][DIM];  // iso: inverse Jacobians of both sides
-      if constexpr (ISO) {
-        double K[DIM][DIM];
-        invert_jacobian<DIM>(Jq[0][q], K);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-          for (int m = 0; m < DIM; ++m) Ko[a][m] = (Real)K[a][m];
-        invert_jacobian<DIM>(Jq[1][q], K);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-          for (int m = 0; m < DIM; ++m) Kx[a][m] = (Real)K[a][m];
-      }
       Real jn = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
@@ -2809,7 +2818,7 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
         const int qt = q % N, qz = q / N;
         const Real lz = (DIM == 3) ? T.V[qz][c] : Real(1);
         const Real dlz = (DIM == 3) ? T.D[qz][c] : Real(0);
-        const Real lt = Lo[qt][a], dlt = dLo[qt][a];
+        const Real lt = Lt[0][qt][a], dlt = dLt[0][qt][a];
         const Real* o = cf[q][m];
         sum += o[0] * lt * fv * lz + o[1] * dlt * fv * lz + o[2] * lt * fd * lz;
         if constexpr (DIM == 3) sum += o[3] * lt * fv * dlz;
@@ -2822,6 +2831,145 @@ __global__ __launch_bounds__(64) void k_mortar_general(Geom<Real> G, Tab1D<Real,
     const int e = tid + 64 * ii;
     const int node = e / NC, m = e % NC;
     if (e < NPT * NC) Em[(size_t)(m * NPT + node) * nsides + fs] = acc[ii];
+  }
+}
+
+// Mortar point geometry of an iso-parametric interface at the current rotor
+// angle (IsoMortarLayout): one block per face side; per segment, point and
+// side the Jacobian of the cell's interpolated map from its node positions
+// (rotor nodes rotated), inverted.  Segment order: with equal ring counts
+// that of mortar_block (two pieces per face, segments of phi = theta mod
+// dtheta, f = phi / dtheta, offset mstep), else that of k_mortar_general.
+template <int DIM, int N>
+__global__ __launch_bounds__(64) void k_iso_mortar_geo(Geom<double> G, Tab1D<double, N> T, int k, MortarGen MG,
+                                                       int polar_order, int mstep, double f_phi,
+                                                       double* __restrict__ g64, float* __restrict__ g32) {
+  using S = Shape<double, DIM, N>;
+  using IM = IsoMortarLayout<DIM>;
+  constexpr int NPT = S::NPT, NZ = S::NZ, NQ = N * NZ;
+  __shared__ double X[2][3][NPT];
+  __shared__ double Lt[2][N][N], dLt[2][N][N];
+  __shared__ double ang[N];
+  const int tid = threadIdx.x;
+  const int nf0 = G.nth[0] * G.nz;
+  const int fs = blockIdx.x;
+  const int side = fs >= nf0;
+  const int f = side ? fs - nf0 : fs;
+  const int nts = pick(side, G.nth);
+  const int ct = f % nts, cz = f / nts;
+  const int cr_own = side == 0 ? G.nr[0] - 1 : 0, cr_oth = side == 0 ? 0 : G.nr[0] - 1;
+  const GenFace F = gen_face(G, MG, side, ct);
+  double crot, srot;
+  sincos(MG.theta_rot, &srot, &crot);
+  auto load_x = [&](const CellId& C, int slot) {
+    for (int node = tid; node < NPT; node += 64) {
+      const int a = node % N, b = (node / N) % N, c = node / S::PLANE;
+      int it, ir, iz;
+      const long long nd = node_of<double, DIM>(G, k, C, a, b, c, it, ir, iz);
+      double x[3];
+      node_position(MG.xnode, nd, C.dom == 0, crot, srot, x);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) X[slot][m][node] = x[m];
+    }
+  };
+  load_x(CellId{side, ct, cr_own, cz}, 0);
+  Piece<double, DIM, N> P[2];
+  if (polar_order) mortar_pieces<double, DIM, N>(G, mstep, side, ct, cz, P);
+  const double dth = F.dth_s;
+  for (int p = 0; p < kMaxPieces && p < MG.npiece; ++p) {
+    CellId oth;
+    double lo = 0, hi = 0, a_f = 0;
+    int seg = 0, jface = 0;
+    if (polar_order) {
+      if (p >= 2) break;
+      seg = P[p].seg;
+      jface = P[p].jface;
+      oth = P[p].other;
+    } else {
+      const int fo = F.f0 + p;
+      a_f = fo * F.dth_o - F.delta;
+      if (a_f >= F.dth_s - F.tol) break;
+      lo = fmax(0.0, a_f);
+      hi = fmin(F.dth_s, a_f + F.dth_o);
+      if (hi - lo <= F.tol) continue;
+      oth = CellId{1 - side, ((fo % F.nto) + F.nto) % F.nto, cr_oth, cz};
+    }
+    __syncthreads();
+    load_x(oth, 1);
+    for (int i = tid; i < 2 * N; i += 64) {
+      const int sd = i / N, qt = i % N;
+      const double t = T.x[qt];
+      double xi;
+      if (polar_order) {
+        // reference coordinate of the stator (s) and rotor (r) cell at the
+        // point, as in the mortar tables of the rotation
+        const double xs = seg == 0 ? t * f_phi : f_phi + t * (1.0 - f_phi);
+        const double xr = seg == 0 ? 1.0 - f_phi + t * f_phi : t * (1.0 - f_phi);
+        const int cs = sd == 0 ? side : 1 - side;
+        xi = cs == 1 ? xs : xr;
+        if (sd == 0) ang[qt] = (jface + xs) * dth;
+      } else {
+        const double sl = lo + t * (hi - lo);
+        xi = sd == 0 ? sl / F.dth_s : (sl - a_f) / F.dth_o;
+        if (sd == 0) ang[qt] = F.start + sl;
+      }
+      double L[N], dL[N];
+      lagrange_gll<N>(MG, xi, L, dL);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        Lt[sd][qt][a] = L[a];
+        dLt[sd][qt][a] = dL[a];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * NQ; e += 64) {
+      const int sd = e / NQ, q = e % NQ;
+      const int qt = q % N, qz = q / N;
+      const int cs = sd == 0 ? side : 1 - side;
+      double J[DIM][DIM];
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+        double dt = 0, dr = 0, dz = 0;
+        for (int c = 0; c < NZ; ++c) {
+          const double lz = (DIM == 3) ? T.V[qz][c] : 1.0;
+          const double dlz = (DIM == 3) ? T.D[qz][c] : 0.0;
+          for (int b = 0; b < N; ++b) {
+            double s0 = 0, s1 = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+              const double x = X[sd][m][(c * N + b) * N + a];
+              s0 += Lt[sd][qt][a] * x;
+              s1 += dLt[sd][qt][a] * x;
+            }
+            dt += lz * MG.FV[cs][b] * s1;
+            dr += lz * MG.FD[cs][b] * s0;
+            dz += dlz * MG.FV[cs][b] * s0;
+          }
+        }
+        J[m][0] = dt;
+        J[m][1] = dr;
+        if constexpr (DIM == 3) J[m][2] = dz;
+      }
+      double K[DIM][DIM];
+      invert_jacobian<DIM>(J, K);
+      const size_t o = ((size_t)(fs * MG.npiece + p) * NQ + q) * IM::SIZE;
+      const int off = sd == 0 ? IM::KO : IM::KX;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+          g64[o + off + a * DIM + m] = K[a][m];
+          g32[o + off + a * DIM + m] = (float)K[a][m];
+        }
+      if (sd == 0) {
+        double sth, cth;
+        sincos(ang[qt], &sth, &cth);
+        g64[o + IM::C] = cth;
+        g64[o + IM::S] = sth;
+        g32[o + IM::C] = (float)cth;
+        g32[o + IM::S] = (float)sth;
+      }
+    }
   }
 }
 
@@ -2855,7 +3003,7 @@ __global__ __launch_bounds__(64) void k_mortar_diag_general(Geom<Real> G, Tab1D<
       for (int qz = 0; qz < NZ; ++qz)
         for (int qt = 0; qt < N; ++qt) {
           double L[N], dL[N];
-          lagrange_gll<N>(MG.gll, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
+          lagrange_gll<N>(MG, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
           const double vz = (DIM == 3) ? (double)T.V[qz][c] : 1.0;
           double jxw = (double)T.w[qt] * MG.R * (hi - lo);
           if (DIM == 3) jxw *= (double)T.w[qz] / MG.inv_dz;
@@ -2918,7 +3066,7 @@ __global__ __launch_bounds__(64) void k_mortar_diag_iso(Geom<Real> G, Tab1D<Real
     for (int q = tid; q < NQ; q += 64) {
       const int qt = q % N, qz = q / N;
       double L[N], dL[N];
-      lagrange_gll<N>(MG.gll, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
+      lagrange_gll<N>(MG, (lo + (double)T.x[qt] * (hi - lo)) / F.dth_s, L, dL);
       double J[DIM][DIM];
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
@@ -3097,6 +3245,9 @@ static MortarGen make_mortar_gen(const mns_handle* h) {
   M.inv_dz = d.dim == 3 ? 1.0 / h->dz : 0.0;
   std::vector<double> L(h->n), dL(h->n), d2L(h->n);
   for (int i = 0; i < h->n; ++i) M.gll[i] = h->gll[i];
+  for (int j = 0; j < h->n; ++j)
+    for (int q = 0; q < h->n; ++q) M.ginv[j][q] = j == q ? 0.0 : 1.0 / (h->gll[j] - h->gll[q]);
+  M.npiece = h->mgeo_pieces;
   for (int side = 0; side < 2; ++side) {
     lagrange_1d(h->gll, side == 0 ? 1.0 : 0.0, L.data(), dL.data(), d2L.data());
     for (int b = 0; b < h->n; ++b) {
@@ -3173,10 +3324,22 @@ template <typename Real, int DIM, int N>
 static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStream_t s) {
   const Geom<Real> G = make_geom<Real>(h);
   const Tab1D<Real, N> T = make_tab<Real, N>(h);
+  if (h->iso && h->equal_rings) {
+    const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
+    const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
+    const Real* img = sizeof(Real) == 8 ? (const Real*)h->d_mgeo64 : (const Real*)h->d_mgeo32;
+    const unsigned blocks = (2u * (unsigned)(G.nth[0] * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
+                           MortarShape<Real, DIM, N>::FPB;
+    launch_k(h, TIMER_MORTAR, k_mortar<Real, DIM, N, true>, dim3(blocks), dim3(64), s, G, T, h->k, M, mtrig, src, Em,
+             mask, img);
+    return hip_check(h, "iso-parametric mortar kernel");
+  }
   if (h->iso) {
     const unsigned nfs = (unsigned)((h->nth[0] + h->nth[1]) * G.nz);
-    launch_k(h, TIMER_MORTAR, k_mortar_general<Real, DIM, N, true>, dim3(nfs), dim3(64), s, G, T, h->k,
-             make_mortar_gen(h), src, Em, mask);
+    MortarGen MG = make_mortar_gen(h);
+    MG.iso_geo = sizeof(Real) == 8 ? (const void*)h->d_mgeo64 : (const void*)h->d_mgeo32;
+    launch_k(h, TIMER_MORTAR, k_mortar_general<Real, DIM, N, true>, dim3(nfs), dim3(64), s, G, T, h->k, MG, src, Em,
+             mask);
     return hip_check(h, "iso-parametric mortar kernel");
   }
   if (!h->equal_rings) {
@@ -3189,7 +3352,8 @@ static int do_mortar(mns_handle* h, const Real* src, Real* Em, int mask, hipStre
   const Real* mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
   const unsigned blocks = (2u * (unsigned)(G.nth[0] * G.nz) + MortarShape<Real, DIM, N>::FPB - 1) /
                          MortarShape<Real, DIM, N>::FPB;
-  launch_k(h, TIMER_MORTAR, k_mortar<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, M, mtrig, src, Em, mask);
+  launch_k(h, TIMER_MORTAR, k_mortar<Real, DIM, N>, dim3(blocks), dim3(64), s, G, T, h->k, M, mtrig, src, Em, mask,
+           (const Real*)nullptr);
   return hip_check(h, "mortar kernel");
 }
 
@@ -3244,10 +3408,11 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
   int rc;
   // launch mode; automatic: one fused launch for small meshes (the mortar
   // work is a latency tail there), the concurrent second stream for large ones
-  int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells ? 2 : 1);
-  // unequal ring counts and iso-parametric cells: the general mortar kernel
-  // runs as its own launch
-  if ((!h->equal_rings || iso) && mode == 1) mode = 0;
+  // (iso-parametric cells: the fused launch at every size, measured faster
+  // than the second stream at 1.1M and 68M DoFs)
+  int mode = h->fused >= 0 ? h->fused : (G.ncells >= kConcurrentCells && !iso ? 2 : 1);
+  // unequal ring counts: the general mortar kernel runs as its own launch
+  if (!h->equal_rings && mode == 1) mode = 0;
   if (mode == 1) {
     // one launch of volume cell blocks and mortar face blocks
     const auto* M = (const MortarTab<Real, N>*)(sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32);
@@ -3277,9 +3442,13 @@ static int do_jacobian(mns_handle* h, const Real* src, Real* dst, hipStream_t s,
         }
       }
     }
-    if (!quad)
+    if (iso)
+      launch_k(h, TIMER_VOLUME, k_jacobian_fused<Real, DIM, N, true>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb,
+               lin, M, mtrig, src, E, Em,
+               sizeof(Real) == 8 ? (const Real*)h->d_mgeo64 : (const Real*)h->d_mgeo32);
+    else if (!quad)
       launch_k(h, TIMER_VOLUME, k_jacobian_fused<Real, DIM, N>, dim3(blocks + nmb), dim3(64), s, G, T, h->k, nmb, lin,
-               M, mtrig, src, E, Em);
+               M, mtrig, src, E, Em, (const Real*)nullptr);
     rc = hip_check(h, "fused volume/mortar kernel");
     if (rc) return rc;
   } else {
@@ -3671,6 +3840,24 @@ int launch_residual(mns_handle* h, const double* state, double* res, hipStream_t
     if (rc) return rc;
   });
   return MNS_OK;
+}
+
+// segment slots per face side: a face meets at most ceil(ratio) + 1 faces of
+// the other ring, ratio the larger of the two cell-angle ratios
+int iso_mortar_pieces(const mns_handle* h) {
+  const int a = std::max(h->nth[0], h->nth[1]), b = std::min(h->nth[0], h->nth[1]);
+  return std::min(kMaxPieces, (a + b - 1) / b + 1);
+}
+
+int launch_iso_mortar_geo(mns_handle* h, hipStream_t s) {
+  if (!h->iso) return MNS_OK;
+  const unsigned nfs = (unsigned)((h->nth[0] + h->nth[1]) * h->nz);
+  MNS_DISPATCH(h->dim, h->k, {
+    hipLaunchKernelGGL((k_iso_mortar_geo<DIM, N>), dim3(nfs), dim3(64), 0, s, make_geom<double>(h),
+                       make_tab<double, N>(h), h->k, make_mortar_gen(h), h->equal_rings ? 1 : 0, h->m,
+                       h->phi / h->dthd[1], h->d_mgeo64, h->d_mgeo32);
+  });
+  return hip_check(h, "iso-parametric mortar geometry kernel");
 }
 
 template <typename Real, int DIM, int N>
