@@ -464,6 +464,15 @@ def iso_leg(name, dev, sync, steps=100, warmup=10):
                       "volume_kernel": f"mns::k_jacobian_fused<{real}, {mesh['dim']}, {mesh['degree'] + 1}, true>"}
         del y
     out["fp32_speedup_over_fp64"] = out["fp64"]["ms_per_vmult"] / out["fp32"]["ms_per_vmult"]
+    # HBM bytes of the FP64 application from the committed counter summary
+    # (profile_vmult.py --iso), when it matches the current kernel source
+    tb, tk = measured_traffic("curved_" + name, out["fp64"]["volume_kernel"])
+    if tb is not None:
+        ms = out["fp64"]["ms_per_vmult"]
+        out["fp64"]["measured_bytes_per_vmult"] = tb
+        out["fp64"]["measured_GBs"] = tb / (ms * 1e-3) / 1e9
+        out["fp64"]["measured_over_algorithmic"] = tb / out["fp64"]["algorithmic_bytes"]
+        out["fp64"]["dominant_launch_measured_bytes"] = tk
     # mixed-precision solve on the curved and on the polar mesh
     sstate = inputs.smooth_field(mesh, inputs.STATE_SEED[name])
     sstate = torch.from_numpy(sstate / np.abs(sstate).max()).to(dev)

@@ -9,6 +9,9 @@ dispatch give the scale from FETCH_SIZE / WRITE_SIZE to bytes.
     rocprofv3 --pmc FETCH_SIZE -f csv -d OUT -o p -- python paper_2608_27423_amd/profile_vmult.py \
         --workload annulus3d_q2_64x8x32
 
+`--iso PERTURB` runs the workload on the curved mesh of
+inputs.iso_node_positions (cells are the Q_k interpolants of their nodes).
+
 `--summarize DIR_FETCH DIR_WRITE` reads the two counter CSV files and prints
 the per-dispatch bytes of every kernel of the run (scaled by the copy); with
 `--traffic-out FILE` it also writes the summary that bench.py reads: the
@@ -46,6 +49,8 @@ def run(args):
     with binding.Operator(mesh) as op:
         op.set_kernel_config(fused_launch=args.fused, volume_layout=args.volume_layout,
                              lin_source_f64=args.lin_source, lin_source_f32=args.lin_source)
+        if args.iso is not None:
+            op.set_node_positions(inputs.iso_node_positions(mesh, args.iso))
         op.rotate_rotor(inputs.rotor_angle(name), mesh["omega"])
         op.set_linearization(state)
         y = torch.empty_like(x)
@@ -100,7 +105,7 @@ def summarize(dfetch, dwrite, traffic_out=None, reps=3, workload=""):
         src = os.path.join(HERE, "csrc", "mns_kernels.hip")
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
         vm = [r for r in rows if r[1] % reps == 0 and r[1] // reps >= 1 and "k_state" not in r[0]
-              and "k_cast" not in r[0] and "k_rotate" not in r[0]]
+              and "k_cast" not in r[0] and "k_rotate" not in r[0] and "k_iso_" not in r[0]]
         with open(traffic_out, "w") as f:
             f.write(f"# HBM bytes of the FP64 vmult kernels, {workload} (read by bench.py); FETCH_SIZE and\n"
                     f"# WRITE_SIZE passes of profile_vmult.py, scaled by the {COPY_BYTES >> 20} MiB copy "
@@ -129,6 +134,8 @@ def main():
     ap.add_argument("--lin-source", type=int, default=0, choices=[0, 1],
                     help="linearization source of the quad volume kernels: 0 = B (full per-point store), "
                          "1 = C (tau and tau R per point, a and grad u from the state)")
+    ap.add_argument("--iso", type=float, default=None, metavar="PERTURB",
+                    help="curved mesh: inputs.iso_node_positions with this interior displacement (in cells)")
     ap.add_argument("--summarize", nargs=2, metavar=("DIR_FETCH", "DIR_WRITE"))
     ap.add_argument("--traffic-out", default=None)
     args = ap.parse_args()
