@@ -20,7 +20,8 @@
  * normal are taken per side (jump = own - other, n = own outward normal, rotor
  * +e_r, stator -e_r); tau_u is frozen in the Jacobian; h = 2 sqrt(A/pi) (2D),
  * (6V/pi)^(1/3) (3D); Gauss-Lobatto nodes with k+1 Gauss points per direction;
- * exact polar geometry; no-slip on every external wall and one pinned pressure
+ * exact polar geometry, or iso-parametric cells from node positions
+ * (mns_set_node_positions); no-slip on every external wall and one pinned pressure
  * DoF (stator node at theta index 0, outermost radius, z index 0).
  *
  * Vector layout (every vector argument): DoF index = node*(d+1) + comp, comps
@@ -117,9 +118,10 @@ int mns_n_dofs(const mns_handle* h, int64_t* n_total, int64_t* n_rotor);
  * u_ALE = omega e_z x x in rotor cells.  Rebuilds the mortar segments of every
  * stator face (one when aligned to 1e-12 of a cell angle, else two), the
  * mapped quadrature tables of Sec. 3.2 and the rotated geometry tables, all in
- * FP64 (cast copies for FP32), with one kernel enqueued on `stream`: work
- * enqueued earlier on `stream` still sees the old tables, later work the new
- * ones.  Allocates nothing and does not synchronize, so it can be captured
+ * FP64 (cast copies for FP32), with one kernel enqueued on `stream` (three
+ * on curved meshes, which also rebuild the per-point metric and the mortar
+ * points' inverse Jacobians): work enqueued earlier on `stream` still sees the
+ * old tables, later work the new ones.  Allocates nothing and does not synchronize, so it can be captured
  * into a graph (the angle is a kernel argument).  Invalidates the
  * linearization (the next apply needs mns_set_linearization).
  * Errors: INVALID_ARG (non-finite theta or omega), HIP. */
@@ -368,20 +370,22 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
                   void* stream);
 
 /* Batched Jacobian application (many rotor/stator instances at once).  A
- * batch holds `count` handles of one dimension and degree (any mesh sizes,
- * angles, viscosities, steady or transient), each rotated and linearized
- * before mns_batch_create.  Vectors of a batch are the instances' vectors
- * concatenated in handle order (mns_batch_n_dofs gives the total length).
- * mns_batch_apply_jacobian computes dst_i = J_i src_i for every instance with
- * one launch for all volume cells and mortar faces (in the block order of the
+ * batch holds `count` handles of any dimensions and degrees (any mesh sizes,
+ * angles, viscosities, steady or transient; polar geometry and equal
+ * interface counts), each rotated and linearized before mns_batch_create.
+ * Vectors of a batch are the instances' vectors concatenated in handle order
+ * (mns_batch_n_dofs gives the total length).  The instances of one dimension
+ * and degree form a launch group: mns_batch_apply_jacobian computes
+ * dst_i = J_i src_i for every instance with, per group, one launch for all
+ * its volume cells and mortar faces (in the block order of the
  * single-instance fused launch, the instance of a block found from block
  * prefix sums) and one gather launch;
  * the arithmetic is that of mns_apply_jacobian, so every slice equals the
  * instance's own product.  Later rotations and linearizations of the handles
  * are seen by later batch calls; a handle must outlive its batches.  The
  * batch allocates its tables at creation and nothing per call.
- * Errors: INVALID_ARG (null, mixed dimension or degree, misaligned vectors),
- * NOT_LINEARIZED, UNSUPPORTED, HIP; creation errors are reported on
+ * Errors: INVALID_ARG (null, misaligned vectors), NOT_LINEARIZED,
+ * UNSUPPORTED (unequal interface counts, curved meshes), HIP; creation errors are reported on
  * handles[0], apply errors by mns_batch_last_error. */
 typedef struct mns_batch mns_batch;
 int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch);

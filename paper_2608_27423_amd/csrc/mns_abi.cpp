@@ -205,16 +205,25 @@ int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch) {
     if (!h) return MNS_ERR_INVALID_ARG;
     if (!h->rotated || !h->linearized)
       return set_error(h, MNS_ERR_NOT_LINEARIZED, "batch: rotate and linearize every handle first");
-    if (h->dim != handles[0]->dim || h->k != handles[0]->k)
-      return set_error(h, MNS_ERR_INVALID_ARG, "batch: all handles need the same dimension and degree");
     if (!h->equal_rings)
       return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need equal interface cell counts");
     if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need the polar geometry");
   }
   auto* b = new mns_batch();
   b->hs.assign(handles, handles + count);
-  b->dim = handles[0]->dim;
-  b->k = handles[0]->k;
+  // one group per (dimension, degree), in the order of first appearance
+  for (int i = 0; i < count; ++i) {
+    mns_batch_group* g = nullptr;
+    for (auto& x : b->groups)
+      if (x.dim == handles[i]->dim && x.k == handles[i]->k) g = &x;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->dim = handles[i]->dim;
+      g->k = handles[i]->k;
+    }
+    g->members.push_back(i);
+  }
   for (int i = 0; i < count; ++i) {
     b->offsets.push_back(b->ndofs);
     b->ndofs += handles[i]->ndofs;
@@ -305,9 +314,11 @@ int mns_batch_solve(mns_batch* b, const double* rhs, double* x, const mns_solve_
 void mns_batch_destroy(mns_batch* b) {
   if (!b) return;
   mns::batch_solver_free(b);
-  if (b->d_items64) (void)hipFree(b->d_items64);
-  if (b->d_items32) (void)hipFree(b->d_items32);
-  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  for (auto& g : b->groups) {
+    if (g.d_items64) (void)hipFree(g.d_items64);
+    if (g.d_items32) (void)hipFree(g.d_items32);
+    if (g.d_prefix) (void)hipFree(g.d_prefix);
+  }
   delete b;
 }
 

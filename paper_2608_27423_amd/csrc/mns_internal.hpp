@@ -252,18 +252,26 @@ struct BatchItem {
 
 }  // namespace mns
 
-// Instances of equal dimension and degree applied together (mns_batch_*).
-struct mns_batch {
-  std::vector<mns_handle*> hs;
+// The instances of one dimension and degree inside a batch: applied by one
+// volume + mortar launch and one gather launch.
+struct mns_batch_group {
   int dim = 0, k = 0;
-  long long ndofs = 0;
-  std::vector<long long> offsets;
+  std::vector<int> members;     // instance indices (handle order)
   // device: items (FP64, FP32), block prefix sums per precision: mortar,
-  // volume (count + 1 each), gather (count + 1, shared)
+  // volume (members + 1 each), gather (members + 1, shared)
   void* d_items64 = nullptr;
   void* d_items32 = nullptr;
   long long* d_prefix = nullptr;
   long long mtot[2] = {0, 0}, vtot[2] = {0, 0}, gtot = 0;
+};
+
+// Instances applied together (mns_batch_*), of any dimensions and degrees:
+// one group per (dimension, degree), in the order of first appearance.
+struct mns_batch {
+  std::vector<mns_handle*> hs;
+  long long ndofs = 0;
+  std::vector<long long> offsets;
+  std::vector<mns_batch_group> groups;
   // batched solver (mns_batch_solve): vector-block segmentation, workspace
   long long* d_seg = nullptr;   // block prefix per instance (count + 1), then dof offsets (count + 1)
   long long nvblk = 0;

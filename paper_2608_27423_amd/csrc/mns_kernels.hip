@@ -3597,14 +3597,14 @@ static void batch_blocks(const mns_handle* h, long long* nmb, long long* nvb, in
 }
 
 template <typename Real, int DIM, int N>
-static void batch_items(mns_batch* b, std::vector<BatchItem<Real>>& items, std::vector<long long>& ms,
-                        std::vector<long long>& vs) {
-  const int count = (int)b->hs.size();
+static void batch_items(const mns_batch* b, const mns_batch_group& g, std::vector<BatchItem<Real>>& items,
+                        std::vector<long long>& ms, std::vector<long long>& vs) {
+  const int count = (int)g.members.size();
   items.resize(count);
   ms.assign(count + 1, 0);
   vs.assign(count + 1, 0);
   for (int i = 0; i < count; ++i) {
-    mns_handle* h = b->hs[i];
+    mns_handle* h = b->hs[g.members[i]];
     BatchItem<Real>& it = items[i];
     it.G = make_geom<Real>(h);
     it.lin = sizeof(Real) == 8 ? (const Real*)h->d_lin64 : (const Real*)h->d_lin32;
@@ -3612,7 +3612,7 @@ static void batch_items(mns_batch* b, std::vector<BatchItem<Real>>& items, std::
     it.Em = sizeof(Real) == 8 ? (Real*)h->d_Em64 : (Real*)h->d_Em32;
     it.mtab = sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32;
     it.mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
-    it.dof_off = b->offsets[i];
+    it.dof_off = b->offsets[g.members[i]];  // offset in the whole batch's vectors
     long long nmb, nvb;
     batch_blocks<Real, DIM, N>(h, &nmb, &nvb, &it.strip);
     ms[i + 1] = ms[i] + nmb;
@@ -3621,29 +3621,29 @@ static void batch_items(mns_batch* b, std::vector<BatchItem<Real>>& items, std::
 }
 
 template <int DIM, int N>
-static int batch_build_t(mns_batch* b) {
+static int batch_build_t(mns_batch* b, mns_batch_group& g) {
   std::vector<BatchItem<double>> i64;
   std::vector<BatchItem<float>> i32;
   std::vector<long long> ms64, vs64, ms32, vs32;
-  batch_items<double, DIM, N>(b, i64, ms64, vs64);
-  batch_items<float, DIM, N>(b, i32, ms32, vs32);
-  const int count = (int)b->hs.size();
+  batch_items<double, DIM, N>(b, g, i64, ms64, vs64);
+  batch_items<float, DIM, N>(b, g, i32, ms32, vs32);
+  const int count = (int)g.members.size();
   std::vector<long long> gs(count + 1, 0);
-  for (int i = 0; i < count; ++i) gs[i + 1] = gs[i] + (b->hs[i]->nnodes + 255) / 256;
-  b->mtot[0] = ms64[count];
-  b->vtot[0] = vs64[count];
-  b->mtot[1] = ms32[count];
-  b->vtot[1] = vs32[count];
-  b->gtot = gs[count];
+  for (int i = 0; i < count; ++i) gs[i + 1] = gs[i] + (b->hs[g.members[i]]->nnodes + 255) / 256;
+  g.mtot[0] = ms64[count];
+  g.vtot[0] = vs64[count];
+  g.mtot[1] = ms32[count];
+  g.vtot[1] = vs32[count];
+  g.gtot = gs[count];
   std::vector<long long> prefix;
   for (const auto* v : {&ms64, &vs64, &ms32, &vs32, &gs}) prefix.insert(prefix.end(), v->begin(), v->end());
   hipError_t e;
-  if ((e = hipMalloc(&b->d_items64, i64.size() * sizeof(i64[0]))) != hipSuccess ||
-      (e = hipMalloc(&b->d_items32, i32.size() * sizeof(i32[0]))) != hipSuccess ||
-      (e = hipMalloc((void**)&b->d_prefix, prefix.size() * sizeof(long long))) != hipSuccess ||
-      (e = hipMemcpy(b->d_items64, i64.data(), i64.size() * sizeof(i64[0]), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(b->d_items32, i32.data(), i32.size() * sizeof(i32[0]), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice)) !=
+  if ((e = hipMalloc(&g.d_items64, i64.size() * sizeof(i64[0]))) != hipSuccess ||
+      (e = hipMalloc(&g.d_items32, i32.size() * sizeof(i32[0]))) != hipSuccess ||
+      (e = hipMalloc((void**)&g.d_prefix, prefix.size() * sizeof(long long))) != hipSuccess ||
+      (e = hipMemcpy(g.d_items64, i64.data(), i64.size() * sizeof(i64[0]), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(g.d_items32, i32.data(), i32.size() * sizeof(i32[0]), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(g.d_prefix, prefix.data(), prefix.size() * sizeof(long long), hipMemcpyHostToDevice)) !=
           hipSuccess) {
     b->err = std::string("batch tables: ") + hipGetErrorString(e);
     return MNS_ERR_HIP;
@@ -3652,39 +3652,46 @@ static int batch_build_t(mns_batch* b) {
 }
 
 int batch_build(mns_batch* b) {
-  switch (b->dim * 10 + b->k) {
-    case 22: return batch_build_t<2, 3>(b);
-    case 23: return batch_build_t<2, 4>(b);
-    case 24: return batch_build_t<2, 5>(b);
-    case 25: return batch_build_t<2, 6>(b);
-    case 32: return batch_build_t<3, 3>(b);
-    case 33: return batch_build_t<3, 4>(b);
-    case 34: return batch_build_t<3, 5>(b);
-    default: b->err = "degree not compiled"; return MNS_ERR_UNSUPPORTED;
+  for (mns_batch_group& g : b->groups) {
+    int rc;
+    switch (g.dim * 10 + g.k) {
+      case 22: rc = batch_build_t<2, 3>(b, g); break;
+      case 23: rc = batch_build_t<2, 4>(b, g); break;
+      case 24: rc = batch_build_t<2, 5>(b, g); break;
+      case 25: rc = batch_build_t<2, 6>(b, g); break;
+      case 32: rc = batch_build_t<3, 3>(b, g); break;
+      case 33: rc = batch_build_t<3, 4>(b, g); break;
+      case 34: rc = batch_build_t<3, 5>(b, g); break;
+      default: b->err = "degree not compiled"; return MNS_ERR_UNSUPPORTED;
+    }
+    if (rc) return rc;
   }
+  return MNS_OK;
 }
 
+// one group: its volume + mortar launch and its gather launch, on the whole
+// batch's vectors (the items hold the instances' offsets)
 template <typename Real, int DIM, int N>
-static int do_batch(mns_batch* b, const Real* src, Real* dst, hipStream_t s) {
-  const int count = (int)b->hs.size();
+static int do_batch(mns_batch* b, const mns_batch_group& g, const Real* src, Real* dst, hipStream_t s) {
+  const int count = (int)g.members.size();
   const int p = sizeof(Real) == 8 ? 0 : 1;
-  const auto* items = (const BatchItem<Real>*)(p == 0 ? b->d_items64 : b->d_items32);
-  const long long* ms = b->d_prefix + (size_t)p * 2 * (count + 1);
+  const auto* items = (const BatchItem<Real>*)(p == 0 ? g.d_items64 : g.d_items32);
+  const long long* ms = g.d_prefix + (size_t)p * 2 * (count + 1);
   const long long* vs = ms + (count + 1);
-  const long long* gs = b->d_prefix + (size_t)4 * (count + 1);
-  const Tab1D<Real, N> T = make_tab<Real, N>(b->hs[0]);
-  const long long blocks = b->mtot[p] + b->vtot[p];
+  const long long* gs = g.d_prefix + (size_t)4 * (count + 1);
+  const Tab1D<Real, N> T = make_tab<Real, N>(b->hs[g.members[0]]);
+  const long long blocks = g.mtot[p] + g.vtot[p];
   constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
   if constexpr (kQuad)
     hipLaunchKernelGGL((k_batch_jacobian_quad<Real, N>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs, count,
-                       T, b->k, src);
+                       T, g.k, src);
   else
     hipLaunchKernelGGL((k_batch_jacobian<Real, DIM, N>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs,
-                       count, T, b->k, src);
+                       count, T, g.k, src);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((k_batch_gather<Real, DIM, N>), dim3((unsigned)b->gtot), dim3(256), 0, s, items, gs, count,
-                       b->k, src, dst);
+    hipLaunchKernelGGL((k_batch_gather<Real, DIM, N>), dim3((unsigned)g.gtot), dim3(256), 0, s, items, gs, count,
+                       g.k, src, dst);
     e = hipGetLastError();
   }
   if (e != hipSuccess) {
@@ -3696,16 +3703,21 @@ static int do_batch(mns_batch* b, const Real* src, Real* dst, hipStream_t s) {
 
 template <typename Real>
 int launch_batch_jacobian(mns_batch* b, const Real* src, Real* dst, hipStream_t s) {
-  switch (b->dim * 10 + b->k) {
-    case 22: return do_batch<Real, 2, 3>(b, src, dst, s);
-    case 23: return do_batch<Real, 2, 4>(b, src, dst, s);
-    case 24: return do_batch<Real, 2, 5>(b, src, dst, s);
-    case 25: return do_batch<Real, 2, 6>(b, src, dst, s);
-    case 32: return do_batch<Real, 3, 3>(b, src, dst, s);
-    case 33: return do_batch<Real, 3, 4>(b, src, dst, s);
-    case 34: return do_batch<Real, 3, 5>(b, src, dst, s);
-    default: b->err = "degree not compiled"; return MNS_ERR_UNSUPPORTED;
+  for (const mns_batch_group& g : b->groups) {
+    int rc;
+    switch (g.dim * 10 + g.k) {
+      case 22: rc = do_batch<Real, 2, 3>(b, g, src, dst, s); break;
+      case 23: rc = do_batch<Real, 2, 4>(b, g, src, dst, s); break;
+      case 24: rc = do_batch<Real, 2, 5>(b, g, src, dst, s); break;
+      case 25: rc = do_batch<Real, 2, 6>(b, g, src, dst, s); break;
+      case 32: rc = do_batch<Real, 3, 3>(b, g, src, dst, s); break;
+      case 33: rc = do_batch<Real, 3, 4>(b, g, src, dst, s); break;
+      case 34: rc = do_batch<Real, 3, 5>(b, g, src, dst, s); break;
+      default: b->err = "degree not compiled"; return MNS_ERR_UNSUPPORTED;
+    }
+    if (rc) return rc;
   }
+  return MNS_OK;
 }
 template int launch_batch_jacobian<double>(mns_batch*, const double*, double*, hipStream_t);
 template int launch_batch_jacobian<float>(mns_batch*, const float*, float*, hipStream_t);

@@ -1,6 +1,7 @@
 """Batched Jacobian application (mns_batch_*): instances of uneven sizes,
-angles, viscosities, steady and transient, in one volume + mortar launch and
-one gather launch.  Every slice must equal the instance's own
+angles, viscosities, steady and transient, of one or several dimensions and
+degrees, in one volume + mortar launch and one gather launch per dimension and
+degree.  Every slice must equal the instance's own
 mns_apply_jacobian product in the same launch form (fused_launch = 1) bit for
 bit (same arithmetic, FP64 and FP32), agree with the default launch to
 rounding, and the FP64 slices match the oracle to the parity bar."""
@@ -84,18 +85,37 @@ def test_batch_equals_single_applications(dim, k):
             op.close()
 
 
-def test_batch_rejects_mixed_degrees():
-    a = binding.Operator(small_mesh(3, 2))
-    c = binding.Operator(small_mesh(3, 3))
+def test_batch_mixed_dimensions_and_degrees():
+    """Instances of 2D degree 2, 3D degree 2, 3D degree 3 and 2D degree 4,
+    interleaved in one batch: one group (volume + mortar launch and gather
+    launch) per dimension and degree, on the whole batch's vectors.  Every
+    slice equals the instance's own product in the batch's launch form bit
+    for bit, FP64 and FP32."""
+    kinds = [(2, 2), (3, 2), (3, 3), (2, 2), (2, 4), (3, 2), (3, 3)]
+    g = np.random.default_rng(77)
+    ops = []
     try:
-        for op in (a, c):
-            op.rotate_rotor(0.1, 1.0)
-            op.set_linearization(torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda"))
-        with pytest.raises(binding.MnsError):
-            binding.Batch([a, c])
+        for j, (dim, k) in enumerate(kinds):
+            mesh = small_mesh(dim, k, n_theta=16 if j % 2 else 7, n_r_rotor=1 + j % 2, n_z=2, nu=0.01 * (1 + j),
+                              steady=j % 2, dt=0.05)
+            op = binding.Operator(mesh)
+            op.rotate_rotor(0.3 + 0.9 * j, 0.7)
+            op.set_linearization(_dev(g.uniform(-1, 1, op.n_dofs)),
+                                 None if mesh["steady"] else _dev(g.uniform(-1, 1, op.n_dofs)))
+            ops.append(op)
+        with binding.Batch(ops) as b:
+            x = g.uniform(-1, 1, b.n_dofs)
+            y64 = b.apply_jacobian(_dev(x)).cpu().numpy()
+            y32 = b.apply_jacobian(_dev(x, torch.float32)).cpu().numpy()
+            for i, op in enumerate(ops):
+                sl = slice(b.offsets[i], b.offsets[i] + op.n_dofs)
+                op.set_kernel_config(fused_launch=1)
+                assert np.array_equal(y64[sl], op.apply_jacobian(_dev(x[sl])).cpu().numpy()), f"instance {i} FP64"
+                assert np.array_equal(y32[sl], op.apply_jacobian(_dev(x[sl], torch.float32)).cpu().numpy()), \
+                    f"instance {i} FP32"
     finally:
-        a.close()
-        c.close()
+        for op in ops:
+            op.close()
 
 
 def _solve_instances(dim):
@@ -151,6 +171,48 @@ def test_batch_solve_matches_direct_solves(dim, precond):
                 assert err < 1e-7
                 assert abs(reps[i]["iterations"] - rep1["iterations"]) <= 2
         assert rc == 0
+    finally:
+        for op in ops:
+            op.close()
+
+
+@pytest.mark.parametrize("precond", ["f32", "f64"])
+def test_batch_solve_mixed_dimensions(precond):
+    """One batched solve over 2D and 3D instances together gives every
+    instance the iterates of the same instances solved in one batch per
+    dimension: the lockstep iteration couples the instances only through the
+    shared column index and restart points."""
+    inst = _solve_instances(2) + _solve_instances(3)
+    order = [0, 3, 1, 4, 2, 5]  # interleaved dimensions
+    ops = []
+    try:
+        g = np.random.default_rng(91)
+        for mesh, theta, omega, state in inst:
+            op = binding.Operator(mesh)
+            op.rotate_rotor(theta, omega)
+            op.set_linearization(_dev(state), _dev(np.zeros(op.n_dofs)))
+            ops.append(op)
+        rhs = [g.uniform(-1, 1, op.n_dofs) for op in ops]
+        opts = dict(rtol=1e-10, restart=30, maxit=1500, precond=precond, cheb_degree=6)
+        per_dim = {}
+        for d, idx in ((2, [0, 1, 2]), (3, [3, 4, 5])):
+            with binding.Batch([ops[i] for i in idx]) as bd:
+                x, rc, reps = bd.solve(_dev(np.concatenate([rhs[i] for i in idx])), check=False, **opts)
+                assert rc == 0
+                xs = x.cpu().numpy()
+                for j, i in enumerate(idx):
+                    per_dim[i] = (xs[bd.offsets[j]:bd.offsets[j] + ops[i].n_dofs], reps[j])
+        with binding.Batch([ops[i] for i in order]) as bm:
+            x, rc, reps = bm.solve(_dev(np.concatenate([rhs[i] for i in order])), check=False, **opts)
+            assert rc == 0
+            xm = x.cpu().numpy()
+            for j, i in enumerate(order):
+                xi = xm[bm.offsets[j]:bm.offsets[j] + ops[i].n_dofs]
+                xd, rd = per_dim[i]
+                print(f"{precond} instance {i}: mixed its {reps[j]['iterations']}, per-dimension {rd['iterations']}, "
+                      f"max diff {np.abs(xi - xd).max():.1e}")
+                assert reps[j]["status"] == 0 and reps[j]["iterations"] == rd["iterations"]
+                assert np.array_equal(xi, xd)
     finally:
         for op in ops:
             op.close()
