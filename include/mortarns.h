@@ -404,7 +404,10 @@ const char* mns_batch_last_error(const mns_batch* batch);
  * once per restart cycle.  Preconditioner:
  * opts->precond -1, MNS_F64 or MNS_F32 (Jacobi-Chebyshev of degree
  * cheb_degree <= 32 on [lambda_i / cheb_range, lambda_i], lambda_i by power
- * iteration per instance); restart <= 31.  An instance that has converged
+ * iteration per instance); restart <= 200 (up to 31 the Gram-Schmidt
+ * kernels hold all coefficients in registers and read each basis vector once
+ * per pass; longer restarts process the columns in chunks of 32).  An
+ * instance that has converged
  * keeps its iterate while the others continue.  reports (count entries, or
  * NULL) receive per-instance iterations, relative residuals and lambda_max
  * (0 without a preconditioner).

@@ -297,10 +297,10 @@ int mns_batch_solve(mns_batch* b, const double* rhs, double* x, const mns_solve_
     b->err = "the batched solver has no multigrid preconditioner";
     return MNS_ERR_UNSUPPORTED;
   }
-  if (!(o.rtol > 0) || o.restart < 1 || o.restart > 31 || o.maxit < 1 || o.cheb_degree < 1 || o.cheb_degree > 32 ||
+  if (!(o.rtol > 0) || o.restart < 1 || o.restart > 200 || o.maxit < 1 || o.cheb_degree < 1 || o.cheb_degree > 32 ||
       !(o.cheb_range > 1) || o.eig_iters < 1 || (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32) ||
       !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0)) {
-    b->err = "invalid batch solve options (restart 1..31, Chebyshev degree 1..32)";
+    b->err = "invalid batch solve options (restart 1..200, Chebyshev degree 1..32)";
     return MNS_ERR_INVALID_ARG;
   }
   try {

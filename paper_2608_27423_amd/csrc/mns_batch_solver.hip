@@ -31,8 +31,12 @@ namespace {
 
 constexpr int kBT = 256;           // threads per block
 constexpr int kBChunk = kBT * 8;   // vector entries per block
-constexpr int kBK = 32;            // register width of the dot kernels (restart <= 31)
-constexpr int kBP = kBK + 1;       // stride of the rows of partial and per-instance sums
+constexpr int kBK = 32;            // register width of one column chunk of the dot kernels
+constexpr int kBMaxRestart = 200;  // columns staged in LDS by the Gram-Schmidt kernels
+
+// stride of the rows of partial and per-instance sums: K + 1 <= restart + 1
+// values (one chunk up to restart 31)
+inline int brow(int m) { return m + 2 > kBK + 1 ? m + 2 : kBK + 1; }
 
 struct BSeg {
   const long long* bstart;  // first block of each instance (count + 1)
@@ -54,8 +58,9 @@ __device__ inline void bseg_range(const BSeg& S, long long b, int& i, long long&
 
 // ---------------------------------------------------------------------------
 // Device state (doubles; count instances, restart m, Chebyshev degree deg):
-// part[nblk][kBP] partial sums, hc[count][kBP] first projection (and w . w
-// before it), h2[count][kBP] second projection (and w . w after the first),
+// part[nblk][P] partial sums, hc[count][P] first projection (and w . w
+// before it), h2[count][P] second projection (and w . w after the first),
+// P = brow(m),
 // n3[count] w . w after the optional third pass, cs/sn[count][m],
 // g[count][m + 1], H[count][m + 1][m], y[count][m], sc[count] scale factors,
 // cheb[deg][count][2], inv_theta[count], inst[count][BI_N], misc[BG_MISC].
@@ -81,12 +86,12 @@ enum {
 
 struct BState {
   double *part, *hc, *h2, *n3, *cs, *sn, *g, *H, *y, *sc, *cheb, *inv_theta, *inst, *misc;
-  int count, m;
+  int count, m, P;
 };
 
 size_t bstate_doubles(long long nblk, int count, int m, int deg) {
-  const size_t c = (size_t)count;
-  return (size_t)nblk * kBP + 2 * c * kBP + c + 2 * c * m + c * (m + 1) + c * (m + 1) * m + c * m + c +
+  const size_t c = (size_t)count, P = (size_t)brow(m);
+  return (size_t)nblk * P + 2 * c * P + c + 2 * c * m + c * (m + 1) + c * (m + 1) * m + c * m + c +
          (size_t)deg * c * 2 + c + c * BI_N + BG_MISC;
 }
 
@@ -94,11 +99,12 @@ BState bstate_view(double* base, long long nblk, int count, int m, int deg) {
   BState G;
   G.count = count;
   G.m = m;
-  const size_t c = (size_t)count;
+  G.P = brow(m);
+  const size_t c = (size_t)count, P = (size_t)G.P;
   G.part = base;
-  G.hc = G.part + (size_t)nblk * kBP;
-  G.h2 = G.hc + c * kBP;
-  G.n3 = G.h2 + c * kBP;
+  G.hc = G.part + (size_t)nblk * P;
+  G.h2 = G.hc + c * P;
+  G.n3 = G.h2 + c * P;
   G.cs = G.n3 + c;
   G.sn = G.cs + c * m;
   G.g = G.sn + c * m;
@@ -116,9 +122,9 @@ __device__ inline double& inst_at(const BState& G, int i, int f) { return G.inst
 __device__ inline bool all_done(const BState& G) { return G.misc[BG_ALLDONE] != 0.0; }
 __device__ inline int col_j(const BState& G) { return (int)G.misc[BG_J]; }
 
-// per-block sums of cnt thread values into part[blockIdx.x * kBP + k]
+// per-block sums of cnt thread values into part[blockIdx.x * P + k0 + k]
 template <int MAXK>
-__device__ inline void bsum_store(double (&v)[MAXK], int cnt, double* part) {
+__device__ inline void bsum_store(double (&v)[MAXK], int cnt, double* part, int P, int k0 = 0) {
   __shared__ double red[kBT / 64][MAXK];
   const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
 #pragma unroll
@@ -133,19 +139,19 @@ __device__ inline void bsum_store(double (&v)[MAXK], int cnt, double* part) {
   if ((int)threadIdx.x < cnt) {
     double t = 0;
     for (int w = 0; w < kBT / 64; ++w) t += red[w][threadIdx.x];
-    part[(long long)blockIdx.x * kBP + threadIdx.x] = t;
+    part[(long long)blockIdx.x * P + k0 + threadIdx.x] = t;
   }
 }
 
 // sums over instance i's blocks of part[.][0 .. cnt) in a fixed order, stored
 // by thread 0 into out[0 .. cnt); ends with a barrier, so that shared-memory
 // results are visible to every thread of the block
-__device__ inline void instance_sums(const BSeg& S, const double* part, int i, int cnt, double* out) {
+__device__ inline void instance_sums(const BSeg& S, const double* part, int P, int i, int cnt, double* out) {
   __shared__ double red[kBT];
   const long long b0 = S.bstart[i], b1 = S.bstart[i + 1];
   for (int k = 0; k < cnt; ++k) {
     double t = 0;
-    for (long long b = b0 + threadIdx.x; b < b1; b += kBT) t += part[b * kBP + k];
+    for (long long b = b0 + threadIdx.x; b < b1; b += kBT) t += part[b * P + k];
     red[threadIdx.x] = t;
     __syncthreads();
     for (int off = kBT / 2; off > 0; off >>= 1) {
@@ -160,13 +166,13 @@ __device__ inline void instance_sums(const BSeg& S, const double* part, int i, i
 // ---- set-up kernels --------------------------------------------------------
 
 // partial sums of w . w
-__global__ __launch_bounds__(kBT) void k_bnorm(BSeg S, const double* __restrict__ w, double* __restrict__ part) {
+__global__ __launch_bounds__(kBT) void k_bnorm(BSeg S, const double* __restrict__ w, double* __restrict__ part, int P) {
   int i;
   long long lo, hi;
   bseg_range(S, blockIdx.x, i, lo, hi);
   double acc[1] = {0};
   for (long long r = lo + threadIdx.x; r < hi; r += kBT) acc[0] += w[r] * w[r];
-  bsum_store<1>(acc, 1, part);
+  bsum_store<1>(acc, 1, part, P);
 }
 
 // ||b_i||, the target rtol ||b_i||, sc = 1 (0 for a zero right-hand side, so
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(kBT) void k_bnorm(BSeg S, const double* __restrict_
 __global__ __launch_bounds__(kBT) void k_bgm_init(BSeg S, BState G, double rtol) {
   const int i = blockIdx.x;
   __shared__ double s[1];
-  instance_sums(S, G.part, i, 1, s);
+  instance_sums(S, G.part, G.P, i, 1, s);
   if (threadIdx.x == 0) {
     const double bn = sqrt(s[0]);
     inst_at(G, i, BI_BN) = bn;
@@ -204,7 +210,7 @@ __global__ void k_bpower_start(BSeg S, BState G) {
 
 // y = D^-1 t (power iteration), partial ||y||^2
 __global__ __launch_bounds__(kBT) void k_bpower(BSeg S, const double* __restrict__ t, const double* __restrict__ diag,
-                                                double* __restrict__ y, double* __restrict__ part) {
+                                                double* __restrict__ y, double* __restrict__ part, int P) {
   int i;
   long long lo, hi;
   bseg_range(S, blockIdx.x, i, lo, hi);
@@ -214,14 +220,14 @@ __global__ __launch_bounds__(kBT) void k_bpower(BSeg S, const double* __restrict
     y[q] = v;
     acc[0] += v * v;
   }
-  bsum_store<1>(acc, 1, part);
+  bsum_store<1>(acc, 1, part, P);
 }
 
 // lambda_i = ||D^-1 J v_i|| and sc = 1 / lambda_i; a breakdown sets BG_BROKEN
 __global__ __launch_bounds__(kBT) void k_bpower_norm(BSeg S, BState G) {
   const int i = blockIdx.x;
   __shared__ double s[1];
-  instance_sums(S, G.part, i, 1, s);
+  instance_sums(S, G.part, G.P, i, 1, s);
   if (threadIdx.x == 0) {
     const double lam = sqrt(s[0]);
     const bool ok = lam > 0 && isfinite(lam);
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(kBT) void k_bcheb_step(BSeg S, Real* __restrict__ r
 
 // r = b - t, partial ||r||^2
 __global__ __launch_bounds__(kBT) void k_bresid(BSeg S, const double* __restrict__ b, const double* __restrict__ t,
-                                                double* __restrict__ r, double* __restrict__ part) {
+                                                double* __restrict__ r, double* __restrict__ part, int P) {
   int i;
   long long lo, hi;
   bseg_range(S, blockIdx.x, i, lo, hi);
@@ -300,14 +306,14 @@ __global__ __launch_bounds__(kBT) void k_bresid(BSeg S, const double* __restrict
     r[q] = v;
     acc[0] += v * v;
   }
-  bsum_store<1>(acc, 1, part);
+  bsum_store<1>(acc, 1, part, P);
 }
 
 // per instance at a cycle start: true residual norm, convergence, g = (||r||, 0, ...)
 __global__ __launch_bounds__(kBT) void k_bgm_cycle(BSeg S, BState G) {
   const int i = blockIdx.x;
   __shared__ double s[1];
-  instance_sums(S, G.part, i, 1, s);
+  instance_sums(S, G.part, G.P, i, 1, s);
   const double rn = sqrt(s[0]);
   const bool done = rn <= inst_at(G, i, BI_TARGET);
   double* gi = G.g + (size_t)i * (G.m + 1);
@@ -392,18 +398,23 @@ __global__ __launch_bounds__(kBT) void k_bgm_dots(BSeg S, BState G, const double
   bseg_range(S, blockIdx.x, i, lo, hi);
   if (inst_at(G, i, BI_DONE) != 0.0) return;
   const int K = col_j(G) + 1;
-  double acc[kBK];
+  // columns in chunks of kBK (one chunk up to restart 31), w . w at index K
+  for (int c0 = 0; c0 <= K; c0 += kBK) {
+    double acc[kBK];
 #pragma unroll
-  for (int k = 0; k < kBK; ++k) acc[k] = 0;
-  for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
-    const double wr = w[r];
+    for (int k = 0; k < kBK; ++k) acc[k] = 0;
+    for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+      const double wr = w[r];
 #pragma unroll
-    for (int k = 0; k < kBK; ++k) {
-      if (k < K) acc[k] += V[(long long)k * N + r] * wr;
-      if (k == K) acc[k] += wr * wr;
+      for (int k = 0; k < kBK; ++k) {
+        const int kk = c0 + k;
+        if (kk < K) acc[k] += V[(long long)kk * N + r] * wr;
+        if (kk == K) acc[k] += wr * wr;
+      }
     }
+    bsum_store<kBK>(acc, K + 1 - c0 < kBK ? K + 1 - c0 : kBK, G.part, G.P, c0);
+    __syncthreads();  // bsum_store's shared rows are reused by the next chunk
   }
-  bsum_store<kBK>(acc, K + 1, G.part);
 }
 
 // w -= sum_k hc[i][k] V_k, then partial dots of the new w with V_k and w . w
@@ -415,7 +426,36 @@ __global__ __launch_bounds__(kBT) void k_bgm_axpy_dots(BSeg S, BState G, const d
   bseg_range(S, blockIdx.x, i, lo, hi);
   if (inst_at(G, i, BI_DONE) != 0.0) return;
   const int K = col_j(G) + 1;
-  const double* hrow = G.hc + (size_t)i * kBP;
+  const double* hrow = G.hc + (size_t)i * G.P;
+  if (K + 1 > kBK) {
+    // long restarts: the update with the coefficients staged in LDS, then the
+    // dots of the new w in chunks (each thread re-reads only its own rows)
+    __shared__ double hs[kBMaxRestart + 1];
+    for (int k = threadIdx.x; k < K; k += kBT) hs[k] = hrow[k];
+    __syncthreads();
+    for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+      double x = w[r];
+      for (int k = 0; k < K; ++k) x -= hs[k] * V[(long long)k * N + r];
+      w[r] = x;
+    }
+    for (int c0 = 0; c0 <= K; c0 += kBK) {
+      double acc[kBK];
+#pragma unroll
+      for (int k = 0; k < kBK; ++k) acc[k] = 0;
+      for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+        const double x = w[r];
+#pragma unroll
+        for (int k = 0; k < kBK; ++k) {
+          const int kk = c0 + k;
+          if (kk < K) acc[k] += V[(long long)kk * N + r] * x;
+          if (kk == K) acc[k] += x * x;
+        }
+      }
+      bsum_store<kBK>(acc, K + 1 - c0 < kBK ? K + 1 - c0 : kBK, G.part, G.P, c0);
+      __syncthreads();
+    }
+    return;
+  }
   double hh[kBK], acc[kBK];
 #pragma unroll
   for (int k = 0; k < kBK; ++k) {
@@ -439,13 +479,13 @@ __global__ __launch_bounds__(kBT) void k_bgm_axpy_dots(BSeg S, BState G, const d
       if (k == K) acc[k] += x * x;
     }
   }
-  bsum_store<kBK>(acc, K + 1, G.part);
+  bsum_store<kBK>(acc, K + 1, G.part, G.P);
 }
 
 // reorthogonalization (DGKS) where the projected norm dropped below 0.7 of the
 // norm before the projection: w -= sum_k h2[i][k] V_k, partial ||w||^2
 __device__ inline bool reorth(const BState& G, int i, int K) {
-  return sqrt(G.h2[(size_t)i * kBP + K]) < 0.7 * sqrt(G.hc[(size_t)i * kBP + K]);
+  return sqrt(G.h2[(size_t)i * G.P + K]) < 0.7 * sqrt(G.hc[(size_t)i * G.P + K]);
 }
 
 __global__ __launch_bounds__(kBT) void k_bgm_reorth(BSeg S, BState G, const double* __restrict__ V, long long N,
@@ -456,14 +496,27 @@ __global__ __launch_bounds__(kBT) void k_bgm_reorth(BSeg S, BState G, const doub
   bseg_range(S, blockIdx.x, i, lo, hi);
   const int K = col_j(G) + 1;
   if (inst_at(G, i, BI_DONE) != 0.0 || !reorth(G, i, K)) return;
-  const double* hrow = G.h2 + (size_t)i * kBP;
+  const double* hrow = G.h2 + (size_t)i * G.P;
+  double acc[1] = {0};
+  if (K > kBK) {
+    __shared__ double hs[kBMaxRestart + 1];
+    for (int k = threadIdx.x; k < K; k += kBT) hs[k] = hrow[k];
+    __syncthreads();
+    for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
+      double x = w[r];
+      for (int k = 0; k < K; ++k) x -= hs[k] * V[(long long)k * N + r];
+      w[r] = x;
+      acc[0] += x * x;
+    }
+    bsum_store<1>(acc, 1, G.part, G.P);
+    return;
+  }
   double hh[kBK];
 #pragma unroll
   for (int k = 0; k < kBK; ++k) {
     hh[k] = 0;
     if (k < K) hh[k] = hrow[k];
   }
-  double acc[1] = {0};
   for (long long r = lo + threadIdx.x; r < hi; r += kBT) {
     double x = w[r];
 #pragma unroll
@@ -472,7 +525,7 @@ __global__ __launch_bounds__(kBT) void k_bgm_reorth(BSeg S, BState G, const doub
     w[r] = x;
     acc[0] += x * x;
   }
-  bsum_store<1>(acc, 1, G.part);
+  bsum_store<1>(acc, 1, G.part, G.P);
 }
 
 // per-instance sums of the partial sums (block i = instance i): which 0:
@@ -483,8 +536,8 @@ __global__ __launch_bounds__(kBT) void k_bgm_reduce(BSeg S, BState G, int which)
   if (inst_at(G, i, BI_DONE) != 0.0) return;
   const int K = col_j(G) + 1;
   if (which == 2 && !reorth(G, i, K)) return;
-  double* out = which == 0 ? G.hc + (size_t)i * kBP : which == 1 ? G.h2 + (size_t)i * kBP : G.n3 + i;
-  instance_sums(S, G.part, i, which == 2 ? 1 : K + 1, out);
+  double* out = which == 0 ? G.hc + (size_t)i * G.P : which == 1 ? G.h2 + (size_t)i * G.P : G.n3 + i;
+  instance_sums(S, G.part, G.P, i, which == 2 ? 1 : K + 1, out);
 }
 
 // Hessenberg column, Givens rotations and residual estimate of column j for
@@ -497,8 +550,8 @@ __global__ __launch_bounds__(kBT) void k_bgm_givens(BState G) {
   int broken = 0;
   for (int i = threadIdx.x; i < G.count; i += kBT) {
     if (inst_at(G, i, BI_DONE) != 0.0) continue;
-    double* hcol = G.hc + (size_t)i * kBP;
-    const double* h2 = G.h2 + (size_t)i * kBP;
+    double* hcol = G.hc + (size_t)i * G.P;
+    const double* h2 = G.h2 + (size_t)i * G.P;
     double wn;
     if (reorth(G, i, K)) {
       wn = sqrt(G.n3[i]);
@@ -597,7 +650,7 @@ __global__ __launch_bounds__(kBT) void k_bgm_update(BSeg S, BState G, const doub
 __global__ __launch_bounds__(kBT) void k_bgm_final(BSeg S, BState G) {
   const int i = blockIdx.x;
   __shared__ double s[1];
-  instance_sums(S, G.part, i, 1, s);
+  instance_sums(S, G.part, G.P, i, 1, s);
   if (threadIdx.x == 0) inst_at(G, i, BI_RES) = sqrt(s[0]);
 }
 
@@ -772,7 +825,7 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   const long long N = B->ndofs;
   const int m = o->restart, deg = o->cheb_degree;
   hipError_t e;
-  if (m < 1 || m > kBK - 1) return MNS_ERR_INVALID_ARG;
+  if (m < 1 || m > kBMaxRestart) return MNS_ERR_INVALID_ARG;
   // segmentation of the concatenated vectors into blocks of one instance
   if (!B->d_seg) {
     std::vector<long long> seg(2 * (size_t)(count + 1), 0);
@@ -852,7 +905,7 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   int rc;
 
   // ||b_i||, targets, x_i = 0 where b_i = 0
-  hipLaunchKernelGGL(k_bnorm, dim3(nb), dim3(kBT), 0, s, S, rhs, G.part);
+  hipLaunchKernelGGL(k_bnorm, dim3(nb), dim3(kBT), 0, s, S, rhs, G.part, G.P);
   hipLaunchKernelGGL(k_bgm_init, dim3(count), dim3(kBT), 0, s, S, G, o->rtol);
   hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)x, (const double*)G.sc, x);
   if ((rc = W.check("batch set-up"))) return rc;
@@ -878,7 +931,7 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
     for (int it = 0; it < o->eig_iters; ++it) {
       if ((rc = W.jac64(W.cb, W.t, s))) return rc;
       hipLaunchKernelGGL(k_bpower, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.t, (const double*)W.diag64, W.cb,
-                         G.part);
+                         G.part, G.P);
       hipLaunchKernelGGL(k_bpower_norm, dim3(count), dim3(kBT), 0, s, S, G);
       hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.cb, (const double*)G.sc, W.cb);
     }
@@ -890,7 +943,7 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   while (total < o->maxit) {
     // true residuals; converged instances stop
     if ((rc = W.jac64(x, W.t, s))) return rc;
-    hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, S, rhs, (const double*)W.t, W.r, G.part);
+    hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, S, rhs, (const double*)W.t, W.r, G.part, G.P);
     hipLaunchKernelGGL(k_bgm_cycle, dim3(count), dim3(kBT), 0, s, S, G);
     hipLaunchKernelGGL(k_bgm_flags, dim3(1), dim3(kBT), 0, s, G, 1);
     hipLaunchKernelGGL(k_bgm_next, dim3(nb), dim3(kBT), 0, s, S, G, W.V, N, (const double*)W.r);
@@ -930,7 +983,7 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   }
   // final true residuals
   if ((rc = W.jac64(x, W.t, s))) return rc;
-  hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, S, rhs, (const double*)W.t, W.r, G.part);
+  hipLaunchKernelGGL(k_bresid, dim3(nb), dim3(kBT), 0, s, S, rhs, (const double*)W.t, W.r, G.part, G.P);
   hipLaunchKernelGGL(k_bgm_final, dim3(count), dim3(kBT), 0, s, S, G);
   if ((rc = W.check("batch residual")) || (rc = W.read_state())) return rc;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

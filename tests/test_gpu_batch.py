@@ -134,8 +134,8 @@ def _solve_instances(dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("precond", ["f32", "f64"])
-def test_batch_solve_matches_direct_solves(dim, precond):
+@pytest.mark.parametrize("precond,restart", [("f32", 30), ("f64", 30), ("f32", 60)])
+def test_batch_solve_matches_direct_solves(dim, precond, restart):
     """mns_batch_solve on uneven instances: every instance reaches the
     requested residual, its solution equals the direct sparse solve of the
     oracle's assembled Jacobian, and its iteration count is that of its own
@@ -156,7 +156,9 @@ def test_batch_solve_matches_direct_solves(dim, precond):
             b = g.uniform(-1, 1, op.n_dofs)
             rhs.append(b)
             direct.append(spla.spsolve(oracle.assemble(oracle_cfg(mesh, theta, omega), state, hist).tocsc(), b))
-        opts = dict(rtol=1e-10, restart=30, maxit=1500, precond=precond, cheb_degree=6)
+        # restart 60: the Gram-Schmidt columns in chunks of 32 (beyond the
+        # kernels' register width)
+        opts = dict(rtol=1e-10, restart=restart, maxit=1500, precond=precond, cheb_degree=6)
         with binding.Batch(ops) as bt:
             x, rc, reps = bt.solve(_dev(np.concatenate(rhs)), check=False, **opts)
             xb = x.cpu().numpy()
@@ -164,7 +166,7 @@ def test_batch_solve_matches_direct_solves(dim, precond):
                 xs, rep1 = op.solve(_dev(rhs[i]), check=False, **opts)
                 sl = slice(bt.offsets[i], bt.offsets[i] + op.n_dofs)
                 err = relmax(xb[sl], direct[i])
-                print(f"dim={dim} {precond} instance {i} ({op.n_dofs} DoFs): batch its {reps[i]['iterations']} "
+                print(f"dim={dim} {precond} restart {restart} instance {i} ({op.n_dofs} DoFs): batch its {reps[i]['iterations']} "
                       f"(single {rep1['iterations']}), rel res {reps[i]['rel_residual']:.1e}, "
                       f"|x - x_direct| / |x| = {err:.1e}")
                 assert reps[i]["status"] == 0 and reps[i]["rel_residual"] <= 1e-10
@@ -240,7 +242,7 @@ def test_batch_solve_edge_cases():
             assert rc == 0
             assert np.all(xb[: ops[0].n_dofs] == 0.0) and reps[0]["iterations"] == 0
             assert reps[1]["status"] == 0 and reps[1]["rel_residual"] <= 1e-10
-            for bad, code in ((dict(restart=32), binding.MNS_ERR_INVALID_ARG),
+            for bad, code in ((dict(restart=201), binding.MNS_ERR_INVALID_ARG),
                               (dict(precond="mg"), binding.MNS_ERR_UNSUPPORTED),
                               (dict(cheb_degree=33), binding.MNS_ERR_INVALID_ARG)):
                 _, rc2, _ = bt.solve(_dev(b), check=False, **dict(opts, **bad))
