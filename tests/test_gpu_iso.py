@@ -8,7 +8,7 @@ FP64 to the parity bar 1e-12 (relative max norm), FP32 to 5e-5.  Cases:
 Jacobian in 2D degrees 2-5 and 3D degrees 2-4, equal and unequal interface
 counts, generic and aligned angles, spinning rotor, steady and BDF2 with
 history and force, Newton and Picard, every launch mode; residual; diagonal;
-dense matrix; allocation-free apply; Jacobi-Chebyshev solve; return to the
+dense matrix; allocation-free apply; Jacobi-Chebyshev solve; BDF2 + Newton step; return to the
 polar geometry; argument errors and the refused combinations."""
 import math
 
@@ -250,3 +250,44 @@ def test_iso_workload_full():
     e64, e32 = relmax(y64, yo), relmax(y32, yo)
     print(f"{name} curved: {x.size} rows (oracle {time.perf_counter() - t0:.1f} s), fp64 {e64:.2e} fp32 {e32:.2e}")
     assert e64 <= TOL64 and e32 <= TOL32
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_iso_bdf2_step_matches_oracle_newton(dim):
+    """One BDF2 + Newton step (mns_bdf2_step: rotation, residual, Jacobian
+    and FGMRES on the curved mesh) reaches the root of the oracle's
+    iso-parametric discrete residual found by its own Newton iteration."""
+    from tests.test_gpu_transient import _oracle_step, _start_fields
+
+    dt = 0.05
+    mesh = small_mesh(dim, 2, n_theta=8 if dim == 2 else 5, steady=0, dt=dt, nu=0.02)
+    un, unm1, f = _start_fields(mesh, 60 + dim)
+    theta, omega = 0.73, 0.6
+    uo, _ = _oracle_step(_cfg(mesh, theta, omega), un, unm1, f, un, dt)
+    with binding.Operator(mesh) as op:
+        op.set_node_positions(inputs.iso_node_positions(mesh, PERT))
+        u = _dev(un).clone()
+        rep = op.bdf2_step(theta, omega, _dev(un), u, u_nm1=_dev(unm1), force=_dev(f), newton_rtol=1e-12,
+                           max_newton=30, linear=dict(rtol=1e-11, restart=200, maxit=4000, precond="f32",
+                                                      cheb_degree=4))
+        ug = u.cpu().numpy()
+    err = relmax(ug, uo)
+    print(f"curved BDF2 dim={dim}: newton {rep['newton_iterations']} linear {rep['linear_iterations']} "
+          f"res {rep['residual0']:.2e} -> {rep['residual']:.2e}; |u_gpu - u_oracle| / |u| = {err:.2e}")
+    assert rep["rc"] == 0 and rep["residual"] <= 1e-12 * rep["residual0"]
+    assert err < 1e-9
+
+
+def test_iso_autotune_keeps_parity():
+    """The launch autotuner on a curved mesh: whatever it chooses (the volume
+    layout and linearization source do not apply there), the product stays
+    the oracle's."""
+    mesh = small_mesh(3, 2, n_theta=16)
+    n, (state, x, _, _) = _inputs(mesh, 13)
+    yo = oracle.apply_jacobian(_cfg(mesh, 1.7, 0.9), state, x)
+    with _operator(mesh, 1.7, 0.9, state) as op:
+        chosen = op.autotune_kernel_config(reps=3)
+        print("autotune on a curved mesh:", chosen)
+        assert chosen == op.get_kernel_config()
+        y = op.apply_jacobian(_dev(x)).cpu().numpy()
+    assert relmax(y, yo) <= TOL64
