@@ -406,19 +406,31 @@ const char* mns_batch_last_error(const mns_batch* batch);
  * cheb_degree <= 32 on [lambda_i / cheb_range, lambda_i], lambda_i by power
  * iteration per instance); restart <= 200 (up to 31 the Gram-Schmidt
  * kernels hold all coefficients in registers and read each basis vector once
- * per pass; longer restarts process the columns in chunks of 32).  An
+ * per pass; longer restarts process the columns in chunks of 32);
+ * MNS_PRECOND_MG or MNS_PRECOND_MG64: the V-cycle of mns_solve on every
+ * instance, with its finest level batched (the pre- and post-smoothing
+ * polynomials of degree mg_smooth_degree <= 32 and the residual run as batch
+ * launches over the instances' level-0 operators, with per-instance
+ * diagonals and lambda_max) and the coarse-grid correction per instance
+ * (restriction, the instance's own cycle from level 1 down to its FP64
+ * coarsest level, prolongation).  Every instance's hierarchy needs two or
+ * more levels (degree 3, or a mesh that can be halved: UNSUPPORTED
+ * otherwise); each handle keeps its hierarchy as after mns_solve.  An
  * instance that has converged
  * keeps its iterate while the others continue.  reports (count entries, or
  * NULL) receive per-instance iterations, relative residuals and lambda_max
- * (0 without a preconditioner).
- * The first call allocates (2 * restart + 10) FP64 and 6 FP32 batch vectors
+ * (0 without a preconditioner; the finest level's with multigrid).
+ * The first call allocates (2 * restart + 12) FP64 and 8 FP32 batch vectors
  * and the solver state (a few KB per instance); a call with a larger restart
  * or degree grows them.  Each instance's diagonal is its handle's, computed
  * (and on the first use allocated) once per linearization and shared with
  * mns_solve, so repeated solves of one linearization give identical iterates.
+ * Multigrid builds or updates each instance's hierarchy as mns_solve does
+ * and, when its finest level is a Picard copy (mg_fine_linearization),
+ * creates a batch over those copies for the call.
  * Synchronizes the stream.
- * Errors: INVALID_ARG, UNSUPPORTED (multigrid), NOT_CONVERGED (some instance
- * reached maxit), HIP. */
+ * Errors: INVALID_ARG, UNSUPPORTED (multigrid on a one-level hierarchy),
+ * NOT_CONVERGED (some instance reached maxit), HIP. */
 int mns_batch_solve(mns_batch* batch, const double* rhs, double* x, const mns_solve_opts* opts,
                     mns_solve_report* reports, void* stream);
 void mns_batch_destroy(mns_batch* batch);

@@ -454,8 +454,12 @@ class Batch:
 
     def _check(self, rc):
         if rc != MNS_OK:
-            raise MnsError(rc, self._L.mns_batch_last_error(self._b).decode())
+            raise MnsError(rc, self.last_error())
         return rc
+
+    def last_error(self):
+        """Message of the batch's last failed call (mns_batch_last_error)."""
+        return self._L.mns_batch_last_error(self._b).decode()
 
     def apply_jacobian(self, src, dst=None):
         import torch

@@ -293,14 +293,17 @@ int mns_batch_solve(mns_batch* b, const double* rhs, double* x, const mns_solve_
   mns_solve_opts o;
   mns_default_solve_opts(&o);
   if (opts) o = *opts;
-  if (o.precond == MNS_PRECOND_MG || o.precond == MNS_PRECOND_MG64) {
-    b->err = "the batched solver has no multigrid preconditioner";
-    return MNS_ERR_UNSUPPORTED;
-  }
   if (!(o.rtol > 0) || o.restart < 1 || o.restart > 200 || o.maxit < 1 || o.cheb_degree < 1 || o.cheb_degree > 32 ||
-      !(o.cheb_range > 1) || o.eig_iters < 1 || (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32) ||
-      !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0)) {
-    b->err = "invalid batch solve options (restart 1..200, Chebyshev degree 1..32)";
+      !(o.cheb_range > 1) || o.eig_iters < 1 ||
+      (o.precond != -1 && o.precond != MNS_F64 && o.precond != MNS_F32 && o.precond != MNS_PRECOND_MG &&
+       o.precond != MNS_PRECOND_MG64) ||
+      !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0) || o.mg_levels < 0 || o.mg_levels > 16 ||
+      o.mg_coarse_degree < 1 || o.mg_coarse_degree > 1000 || o.mg_smooth_degree < 1 || o.mg_smooth_degree > 32 ||
+      !(o.mg_smooth_range > 1) ||
+      (o.mg_coarse_linearization != MNS_LIN_NEWTON && o.mg_coarse_linearization != MNS_LIN_PICARD) ||
+      (o.mg_fine_linearization != MNS_LIN_NEWTON && o.mg_fine_linearization != MNS_LIN_PICARD) ||
+      (o.use_graph != 0 && o.use_graph != 1) || (o.mg_coarse_direct != 0 && o.mg_coarse_direct != 1)) {
+    b->err = "invalid batch solve options (restart 1..200, Chebyshev and smoother degrees 1..32)";
     return MNS_ERR_INVALID_ARG;
   }
   try {

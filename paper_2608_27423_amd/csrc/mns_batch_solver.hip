@@ -292,6 +292,15 @@ __global__ __launch_bounds__(kBT) void k_bcheb_step(BSeg S, Real* __restrict__ r
   }
 }
 
+// out = a + beta c (out may be a)
+template <typename Real>
+__global__ __launch_bounds__(kBT) void k_baxpy(BSeg S, const Real* a, Real beta, const Real* __restrict__ c, Real* out) {
+  int i;
+  long long lo, hi;
+  bseg_range(S, blockIdx.x, i, lo, hi);
+  for (long long q = lo + threadIdx.x; q < hi; q += kBT) out[q] = a[q] + beta * c[q];
+}
+
 // ---- one cycle -------------------------------------------------------------
 
 // r = b - t, partial ||r||^2
@@ -663,8 +672,10 @@ struct BatchSolver {
   BSeg S;
   BState G;
   const mns_solve_opts* o;
-  double *V, *Z, *w, *r, *t, *diag64, *cb, *cr, *cd, *cx, *ct;
-  float *b32, *x32, *r32, *d32, *t32, *diag32;
+  double *V, *Z, *w, *r, *t, *diag64, *cb, *cr, *cd, *cx, *ct, *mr64, *mx64;
+  float *b32, *x32, *r32, *d32, *t32, *diag32, *mr32, *mx32;
+  mns_batch* F = nullptr;  // multigrid: the batch of the level-0 operators
+  int mg_v64 = 0, mg_v32 = 0;
   int vm64 = 0, vm32 = 0;
   int it_vm64 = 0, it_vm32 = 0;  // Jacobian applications of one iteration
   hipGraphExec_t gexec = nullptr;
@@ -685,6 +696,54 @@ struct BatchSolver {
     ++vm32;
     return launch_batch_jacobian<float>(B, src, dst, st);
   }
+  template <typename Real>
+  int jac_fine(const Real* src, Real* dst, hipStream_t st) {
+    ++(sizeof(Real) == 8 ? vm64 : vm32);
+    const int rc = launch_batch_jacobian<Real>(F, src, dst, st);
+    return rc ? fail(rc, F->err) : MNS_OK;
+  }
+
+  // x = Chebyshev polynomial of degree mg_smooth_degree in D0^-1 J0 applied
+  // to b (from zero), J0, D0 the level-0 operators and diagonals
+  template <typename Real>
+  int mg_poly(const Real* b, Real* x, Real* rr, Real* dd, Real* tt, const Real* diag, hipStream_t st) {
+    hipLaunchKernelGGL(k_bcheb_init<Real>, dim3(nb), dim3(kBT), 0, st, S, b, diag, (const double*)G.inv_theta, rr, dd,
+                       x);
+    for (int k = 0; k < o->mg_smooth_degree; ++k) {
+      int rc;
+      if ((rc = jac_fine<Real>(dd, tt, st))) return rc;
+      hipLaunchKernelGGL(k_bcheb_step<Real>, dim3(nb), dim3(kBT), 0, st, S, rr, (const Real*)tt, diag,
+                         (const double*)(G.cheb + (size_t)k * count * 2), dd, x);
+    }
+    return check("batch multigrid smoothing");
+  }
+
+  // one V-cycle (the single-instance cycle's steps): pre-smoothing on the
+  // finest level of every instance, batched; residual; per instance the
+  // coarse-grid correction (restriction, the cycle from level 1 with its
+  // FP64 coarsest level, prolongation); post-smoothing, batched
+  template <typename Real>
+  int mg_vcycle(const Real* b, Real* x, Real* res, Real* xc, Real* rr, Real* dd, Real* tt, const Real* diag,
+                hipStream_t st) {
+    int rc;
+    if ((rc = mg_poly<Real>(b, x, rr, dd, tt, diag, st))) return rc;
+    if ((rc = jac_fine<Real>(x, tt, st))) return rc;
+    hipLaunchKernelGGL(k_baxpy<Real>, dim3(nb), dim3(kBT), 0, st, S, b, Real(-1), (const Real*)tt, res);
+    if ((rc = check("batch multigrid residual"))) return rc;
+    for (int i = 0; i < count; ++i) {
+      const long long off = B->offsets[i];
+      mns_handle* h0 = B->mg_fine_hs[i];
+      if ((rc = launch_constraints<Real>(h0, res + off, res + off, Real(0), 1, st)))
+        return fail(rc, "batch multigrid constraints");
+      if ((rc = mg_instance_correction<Real>(B->hs[i], res + off, x + off, tt + off, o, st)))
+        return fail(rc, "batch multigrid, instance " + std::to_string(i) + ": " + B->hs[i]->err);
+    }
+    if ((rc = jac_fine<Real>(x, tt, st))) return rc;
+    hipLaunchKernelGGL(k_baxpy<Real>, dim3(nb), dim3(kBT), 0, st, S, b, Real(-1), (const Real*)tt, res);
+    if ((rc = mg_poly<Real>(res, xc, rr, dd, tt, diag, st))) return rc;
+    hipLaunchKernelGGL(k_baxpy<Real>, dim3(nb), dim3(kBT), 0, st, S, (const Real*)x, Real(1), (const Real*)xc, x);
+    return check("batch multigrid update");
+  }
   // inst and misc -> host (one synchronization)
   int read_state() {
     const size_t cnt = (size_t)count * BI_N + BG_MISC;
@@ -699,6 +758,14 @@ struct BatchSolver {
   int precondition(hipStream_t st) {
     const int deg = o->cheb_degree;
     int rc;
+    if (o->precond == MNS_PRECOND_MG64) {
+      hipLaunchKernelGGL(k_bgm_in<double>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, cb);
+      return mg_vcycle<double>(cb, cx, mr64, mx64, cr, cd, ct, diag64, st);
+    }
+    if (o->precond == MNS_PRECOND_MG) {
+      hipLaunchKernelGGL(k_bgm_in<float>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, b32);
+      return mg_vcycle<float>(b32, x32, mr32, mx32, r32, d32, t32, diag32, st);
+    }
     if (o->precond == -1) {
       hipLaunchKernelGGL(k_bgm_in<double>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)V, N, cx);
       return check("batch copy");
@@ -728,12 +795,33 @@ struct BatchSolver {
   // One lockstep iteration as a fixed sequence of launches (j is read from
   // the device): preconditioner, FP64 Jacobian, Gram-Schmidt with the
   // optional reorthogonalization, Givens, next basis vector.
+  int mg_counts(int* a64, int* a32) {
+    *a64 = *a32 = 0;
+    for (int i = 0; i < count; ++i) {
+      int c64, c32;
+      mg_instance_counts(B->hs[i], &c64, &c32);
+      *a64 += c64;
+      *a32 += c32;
+    }
+    return MNS_OK;
+  }
+
   int iteration(hipStream_t st) {
     const int v64 = vm64, v32 = vm32;
+    int m64 = 0, m32 = 0;
+    const bool mgp = o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64;
+    if (mgp) mg_counts(&m64, &m32);
     int rc = precondition(st);
     if (rc) return rc;
+    if (mgp) {
+      // Jacobian applications of the instances' own cycles (coarse levels)
+      int a64, a32;
+      mg_counts(&a64, &a32);
+      vm64 += a64 - m64;
+      vm32 += a32 - m32;
+    }
     double* zbuf = r;  // free during a cycle: the residual is read into V_0 at its start
-    if (o->precond == MNS_F32)
+    if (o->precond == MNS_F32 || o->precond == MNS_PRECOND_MG)
       hipLaunchKernelGGL(k_bgm_out<float>, dim3(nb), dim3(kBT), 0, st, S, G, (const float*)x32, N, Z, zbuf);
     else
       hipLaunchKernelGGL(k_bgm_out<double>, dim3(nb), dim3(kBT), 0, st, S, G, (const double*)cx, N, Z, zbuf);
@@ -823,7 +911,8 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   const auto t0 = std::chrono::steady_clock::now();
   const int count = (int)B->hs.size();
   const long long N = B->ndofs;
-  const int m = o->restart, deg = o->cheb_degree;
+  const bool mgp = o->precond == MNS_PRECOND_MG || o->precond == MNS_PRECOND_MG64;
+  const int m = o->restart, deg = std::max(o->cheb_degree, mgp ? o->mg_smooth_degree : 1);
   hipError_t e;
   if (m < 1 || m > kBMaxRestart) return MNS_ERR_INVALID_ARG;
   // segmentation of the concatenated vectors into blocks of one instance
@@ -864,8 +953,8 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
     B->ws = nullptr;
     B->ws32 = nullptr;
     B->ws_m = 0;
-    if ((e = hipMalloc((void**)&B->ws, (size_t)(2 * m + 10) * N * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&B->ws32, 6 * (size_t)N * sizeof(float))) != hipSuccess) {
+    if ((e = hipMalloc((void**)&B->ws, (size_t)(2 * m + 12) * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&B->ws32, 8 * (size_t)N * sizeof(float))) != hipSuccess) {
       B->err = std::string("hipMalloc batch workspace: ") + hipGetErrorString(e);
       return MNS_ERR_HIP;
     }
@@ -893,12 +982,16 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   W.cr = W.cx + N;
   W.cd = W.cr + N;
   W.ct = W.cd + N;
+  W.mr64 = W.ct + N;
+  W.mx64 = W.mr64 + N;
   W.b32 = B->ws32;
   W.x32 = W.b32 + N;
   W.r32 = W.x32 + N;
   W.d32 = W.r32 + N;
   W.t32 = W.d32 + N;
   W.diag32 = W.t32 + N;
+  W.mr32 = W.diag32 + N;
+  W.mx32 = W.mr32 + N;
   const unsigned nb = W.nb;
   const BSeg& S = W.S;
   const BState& G = W.G;
@@ -910,11 +1003,45 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)x, (const double*)G.sc, x);
   if ((rc = W.check("batch set-up"))) return rc;
 
+  // multigrid: every instance's hierarchy set up as mns_solve does; its
+  // level-0 operator (the instance's, or its Picard copy) and that level's
+  // lambda_max; a batch over the level-0 operators for this call when one of
+  // them is a copy
+  struct FineGuard {
+    mns_batch* B;
+    hipStream_t s;
+    ~FineGuard() {
+      if (B->mg_fine) {
+        (void)hipStreamSynchronize(s);  // graph replays may still read its tables
+        mns_batch_destroy(B->mg_fine);
+      }
+      B->mg_fine = nullptr;
+      B->mg_fine_hs.clear();
+    }
+  } fine_guard{B, s};
+  std::vector<double> lam0(count, 0.0);
+  if (mgp) {
+    B->mg_fine_hs.assign(count, nullptr);
+    bool copies = false;
+    for (int i = 0; i < count; ++i) {
+      if ((rc = mg_instance_setup(B->hs[i], o, s, &B->mg_fine_hs[i], &lam0[i])))
+        return W.fail(rc, "batch multigrid, instance " + std::to_string(i) + ": " + B->hs[i]->err);
+      copies = copies || B->mg_fine_hs[i] != B->hs[i];
+    }
+    if (copies) {
+      if ((rc = mns_batch_create(B->mg_fine_hs.data(), count, &B->mg_fine)))
+        return W.fail(rc, "batch of the level-0 operators: " + B->mg_fine_hs[0]->err);
+      W.F = B->mg_fine;
+    } else {
+      W.F = B;
+    }
+  }
   // diagonals of every instance (Alg. Alg-diagonal), FP64 and FP32: each
-  // handle's cached diagonal, computed when its linearization changed
+  // handle's cached diagonal, computed when its linearization changed (with
+  // multigrid: the diagonal of the level-0 operator, set up by its hierarchy)
   for (int i = 0; i < count; ++i) {
-    mns_handle* h = B->hs[i];
-    if ((rc = cached_diagonal(h, s))) return W.fail(rc, "batch diagonal: " + h->err);
+    mns_handle* h = mgp ? B->mg_fine_hs[i] : B->hs[i];
+    if (!mgp && (rc = cached_diagonal(h, s))) return W.fail(rc, "batch diagonal: " + h->err);
     if ((e = hipMemcpyAsync(W.diag64 + B->offsets[i], h->d_diag64, (size_t)h->ndofs * sizeof(double),
                             hipMemcpyDeviceToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(W.diag32 + B->offsets[i], h->d_diag32, (size_t)h->ndofs * sizeof(float),
@@ -922,9 +1049,19 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
       return W.fail(MNS_ERR_HIP, std::string("batch diagonal copy: ") + hipGetErrorString(e));
   }
 
-  // lambda_max of D^-1 J per instance by power iteration from the constant
-  // vector, then the Chebyshev scalars, all on the device
-  if (o->precond != -1) {
+  if (mgp) {
+    // the level-0 lambda_max of every hierarchy, then the smoother's scalars
+    for (int i = 0; i < count; ++i)
+      if ((e = hipMemcpyAsync(G.inst + (size_t)i * BI_N + BI_LAM, &lam0[i], sizeof(double), hipMemcpyHostToDevice,
+                              s)) != hipSuccess)
+        return W.fail(MNS_ERR_HIP, std::string("batch multigrid lambda: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL(k_bcheb_coef, dim3(1), dim3(kBT), 0, s, G, o->mg_smooth_degree, o->cheb_lambda_factor,
+                       o->mg_smooth_range);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+      return W.fail(MNS_ERR_HIP, std::string("batch multigrid set-up: ") + hipGetErrorString(e));
+  } else if (o->precond != -1) {
+    // lambda_max of D^-1 J per instance by power iteration from the constant
+    // vector, then the Chebyshev scalars, all on the device
     if ((rc = launch_fill<double>(W.t, 1.0, N, s))) return W.fail(rc, "fill");
     hipLaunchKernelGGL(k_bpower_start, dim3(1), dim3(kBT), 0, s, S, G);
     hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.t, (const double*)G.sc, W.cb);
@@ -935,7 +1072,8 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
       hipLaunchKernelGGL(k_bpower_norm, dim3(count), dim3(kBT), 0, s, S, G);
       hipLaunchKernelGGL(k_bscale, dim3(nb), dim3(kBT), 0, s, S, (const double*)W.cb, (const double*)G.sc, W.cb);
     }
-    hipLaunchKernelGGL(k_bcheb_coef, dim3(1), dim3(kBT), 0, s, G, deg, o->cheb_lambda_factor, o->cheb_range);
+    hipLaunchKernelGGL(k_bcheb_coef, dim3(1), dim3(kBT), 0, s, G, o->cheb_degree, o->cheb_lambda_factor,
+                       o->cheb_range);
     if ((rc = W.check("batch power iteration"))) return rc;
   }
 

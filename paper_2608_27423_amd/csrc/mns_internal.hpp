@@ -282,6 +282,10 @@ struct mns_batch {
   double* h_small = nullptr;    // pinned mirror of the per-instance flags
   size_t small_doubles = 0;     // capacity of d_small
   hipStream_t cap = nullptr;    // capture stream of the iteration graph
+  // multigrid preconditioner: a batch over the instances' level-0 operators
+  // when one of them is a Picard copy (else the batch itself is used)
+  mns_batch* mg_fine = nullptr;
+  std::vector<mns_handle*> mg_fine_hs;
   std::string err;
 };
 
@@ -336,6 +340,15 @@ int launch_cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t s);
 // h->d_diag64 / d_diag32 hold the diagonal of the current linearization
 // (allocated and computed on first use, reused until it changes)
 int cached_diagonal(mns_handle* h, hipStream_t s);
+// multigrid of one instance of a batched solve: the hierarchy built and set
+// up as mns_solve does (level-0 handle: the instance's or its Picard copy,
+// with its lambda_max); x0 += the V-cycle's coarse-grid correction of the
+// level-0 residual r0 (t0: work vector); Jacobian applications of its cycles
+int mg_instance_setup(mns_handle* h, const mns_solve_opts* o, hipStream_t s, mns_handle** level0, double* lmax0);
+template <typename Real>
+int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, Real* t0, const mns_solve_opts* o,
+                           hipStream_t s);
+void mg_instance_counts(mns_handle* h, int* v64, int* v32);
 int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
 
 // iso-parametric geometry (mns_iso.hip): node positions, fold check,

@@ -1476,6 +1476,64 @@ int mg_vcycle_body(MG* mg, const mns_solve_opts* o, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Multigrid of one instance inside a batched solve (mns_batch_solver.hip):
+// the finest level's smoothing runs batched over the instances; the
+// coarse-grid correction runs per instance through the code above.
+// ---------------------------------------------------------------------------
+namespace mns {
+
+int mg_instance_setup(mns_handle* h, const mns_solve_opts* o, hipStream_t s, mns_handle** level0, double* lmax0) {
+  int rc = ensure_workspace(h, 1);
+  if (rc) return rc;
+  MG* mg = nullptr;
+  if ((rc = mg_build(h, o->mg_levels, &mg))) return rc;
+  // one level would make the cycle a plain polynomial, not smoothing plus
+  // a coarse-grid correction
+  if (mg->L.size() < 2)
+    return set_error(h, MNS_ERR_UNSUPPORTED,
+                     "batched multigrid needs two or more levels (degree 3, or a mesh that can be halved)");
+  if ((rc = mg_setup(h, mg, o, s))) return rc;
+  *level0 = mg->L[0].h;
+  *lmax0 = mg->L[0].lmax;
+  return MNS_OK;
+}
+
+template <typename Real>
+int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, Real* t0, const mns_solve_opts* o,
+                           hipStream_t s) {
+  MG* mg = (MG*)h->mg;
+  if (!mg || mg->L.size() < 2) return set_error(h, MNS_ERR_INVALID_ARG, "multigrid hierarchy missing");
+  MGLevel& L0 = mg->L[0];
+  mns_handle* h0 = L0.h;
+  const unsigned g = grid_for(L0.n);
+  MGLevel& Lc = mg->L[1];
+  Solver Sc = make_solver(Lc.h, s, 1);
+  MGVec<Real> vc = mg_vec<Real>(Lc, Sc);
+  const TxView& X = mg->T[0];
+  int rc;
+  if ((rc = mg_restrict<Real>(X, L0.tr, r0, vc.b, s))) return set_error(h, rc, "multigrid restriction");
+  if ((rc = launch_constraints<Real>(Lc.h, vc.b, vc.b, Real(0), 1, s))) return rc;
+  if ((rc = mg_cycle<Real>(mg, 1, o, s))) return rc;
+  hipLaunchKernelGGL(k_mg_prolong<Real>, dim3((unsigned)((h0->nnodes + 255) / 256)), dim3(256), 0, s, X,
+                     (const Real*)vc.x, t0, (long long)h0->nnodes, 0);
+  if ((rc = launch_constraints<Real>(h0, t0, t0, Real(0), 1, s))) return rc;
+  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)x0, Real(1), (const Real*)t0, x0, L0.n);
+  return hipGetLastError() == hipSuccess ? MNS_OK : set_error(h, MNS_ERR_HIP, "multigrid correction kernels");
+}
+template int mg_instance_correction<float>(mns_handle*, const float*, float*, float*, const mns_solve_opts*,
+                                           hipStream_t);
+template int mg_instance_correction<double>(mns_handle*, const double*, double*, double*, const mns_solve_opts*,
+                                            hipStream_t);
+
+void mg_instance_counts(mns_handle* h, int* v64, int* v32) {
+  MG* mg = (MG*)h->mg;
+  *v64 = *v32 = 0;
+  if (mg) mg_count(mg, v64, v32);
+}
+
+}  // namespace mns
+
 int mns_solve_impl(mns_handle* h, const double* rhs, double* x, const mns_solve_opts* o, mns_solve_report* rep,
                    hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();

@@ -242,6 +242,8 @@ def test_batch_solve_edge_cases():
             assert rc == 0
             assert np.all(xb[: ops[0].n_dofs] == 0.0) and reps[0]["iterations"] == 0
             assert reps[1]["status"] == 0 and reps[1]["rel_residual"] <= 1e-10
+            # multigrid: the second instance (one radial rotor cell) has a
+            # one-level hierarchy, so no coarse-grid correction
             for bad, code in ((dict(restart=201), binding.MNS_ERR_INVALID_ARG),
                               (dict(precond="mg"), binding.MNS_ERR_UNSUPPORTED),
                               (dict(cheb_degree=33), binding.MNS_ERR_INVALID_ARG)):
