@@ -255,10 +255,9 @@ def batch_leg(args, dev, sync):
     t_ssolve = time.perf_counter() - t0
 
     # 10 FGMRES iterations with the multigrid V-cycle (FP32 smoothing, FP64
-    # coarsest level) as preconditioner: batched finest level (smoothing and
-    # residual as batch launches, coarse-grid corrections per instance inside
-    # the iteration graph) against one solve per instance; the hierarchies are
-    # set up by an untimed one-iteration solve first
+    # direct coarsest level) as preconditioner: every level batched over the
+    # instances (inside the iteration graph) against one solve per instance;
+    # the hierarchies are set up by an untimed one-iteration solve first
     mopts = dict(rtol=1e-14, restart=30, maxit=10, precond="mg")
     for b, r in zip(batches, rhs):
         b.solve(r, check=False, **dict(mopts, maxit=1))

@@ -408,14 +408,18 @@ const char* mns_batch_last_error(const mns_batch* batch);
  * kernels hold all coefficients in registers and read each basis vector once
  * per pass; longer restarts process the columns in chunks of 32);
  * MNS_PRECOND_MG or MNS_PRECOND_MG64: the V-cycle of mns_solve on every
- * instance, with its finest level batched (the pre- and post-smoothing
- * polynomials of degree mg_smooth_degree <= 32 and the residual run as batch
- * launches over the instances' level-0 operators, with per-instance
- * diagonals and lambda_max) and the coarse-grid correction per instance
- * (restriction, the instance's own cycle from level 1 down to its FP64
- * coarsest level, prolongation).  Every instance's hierarchy needs two or
- * more levels (degree 3, or a mesh that can be halved: UNSUPPORTED
- * otherwise); each handle keeps its hierarchy as after mns_solve.  An
+ * instance, every level batched: on each level the smoothing polynomials
+ * (degree mg_smooth_degree <= 32, per-instance diagonals and lambda_max) and
+ * the residual run as batch launches over the instances' operators of that
+ * level, the restriction, prolongation and constrained rows as one launch
+ * per step, and the FP64 direct coarsest solves of the instances whose
+ * hierarchy ends there as one launch (hierarchies of different depths mix).
+ * Without a direct coarsest solve on every instance (mg_coarse_direct 0, or
+ * a coarsest level too large for it) the finest level stays batched and each
+ * instance's coarse-grid correction runs through its own cycle.  Every
+ * instance's hierarchy needs two or more levels (degree 3, or a mesh that
+ * can be halved: UNSUPPORTED otherwise); each handle keeps its hierarchy as
+ * after mns_solve.  An
  * instance that has converged
  * keeps its iterate while the others continue.  reports (count entries, or
  * NULL) receive per-instance iterations, relative residuals and lambda_max
@@ -426,8 +430,8 @@ const char* mns_batch_last_error(const mns_batch* batch);
  * (and on the first use allocated) once per linearization and shared with
  * mns_solve, so repeated solves of one linearization give identical iterates.
  * Multigrid builds or updates each instance's hierarchy as mns_solve does
- * and, when its finest level is a Picard copy (mg_fine_linearization),
- * creates a batch over those copies for the call.
+ * and allocates, for the call, the batched levels' vectors and tables (and,
+ * when the finest levels are Picard copies, a batch over those copies).
  * Synchronizes the stream.
  * Errors: INVALID_ARG, UNSUPPORTED (multigrid on a one-level hierarchy),
  * NOT_CONVERGED (some instance reached maxit), HIP. */

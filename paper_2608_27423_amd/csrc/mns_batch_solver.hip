@@ -24,37 +24,18 @@
 #include <string>
 #include <vector>
 
+#include "mns_batch_vec.hpp"
 #include "mns_internal.hpp"
 
 namespace mns {
 namespace {
 
-constexpr int kBT = 256;           // threads per block
-constexpr int kBChunk = kBT * 8;   // vector entries per block
 constexpr int kBK = 32;            // register width of one column chunk of the dot kernels
 constexpr int kBMaxRestart = 200;  // columns staged in LDS by the Gram-Schmidt kernels
 
 // stride of the rows of partial and per-instance sums: K + 1 <= restart + 1
 // values (one chunk up to restart 31)
 inline int brow(int m) { return m + 2 > kBK + 1 ? m + 2 : kBK + 1; }
-
-struct BSeg {
-  const long long* bstart;  // first block of each instance (count + 1)
-  const long long* off;     // first entry of each instance (count + 1)
-  int count;
-};
-
-__device__ inline void bseg_range(const BSeg& S, long long b, int& i, long long& lo, long long& hi) {
-  int a = 0, z = S.count - 1;  // last instance whose first block is at or before b
-  while (a < z) {
-    const int mid = (a + z + 1) >> 1;
-    if (S.bstart[mid] <= b) a = mid;
-    else z = mid - 1;
-  }
-  i = a;
-  lo = S.off[a] + (b - S.bstart[a]) * kBChunk;
-  hi = lo + kBChunk < S.off[a + 1] ? lo + kBChunk : S.off[a + 1];
-}
 
 // ---------------------------------------------------------------------------
 // Device state (doubles; count instances, restart m, Chebyshev degree deg):
@@ -237,68 +218,11 @@ __global__ __launch_bounds__(kBT) void k_bpower_norm(BSeg S, BState G) {
   }
 }
 
-// Chebyshev scalars per instance from lambda_i: start 1/theta, step k (c1, c2)
-// (the recurrence of the single-instance polynomial; not contracted)
+// Chebyshev scalars per instance from lambda_i (BI_LAM)
 __global__ void k_bcheb_coef(BState G, int deg, double lambda_factor, double range) {
-#pragma clang fp contract(off)
   const int count = G.count;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-    const double beta = inst_at(G, i, BI_LAM) * lambda_factor, alpha = beta / range;
-    const double theta = 0.5 * (beta + alpha), delta = 0.5 * (beta - alpha), sigma = theta / delta;
-    G.inv_theta[i] = 1.0 / theta;
-    double rho = 1.0 / sigma;
-    for (int k = 0; k < deg; ++k) {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      G.cheb[((size_t)k * count + i) * 2] = rn * rho;
-      G.cheb[((size_t)k * count + i) * 2 + 1] = 2.0 * rn / delta;
-      rho = rn;
-    }
-  }
-}
-
-// Chebyshev polynomial of D^-1 J with per-instance scalars: start
-// (inv_theta[i]) and step k (c[k][i][0..1])
-template <typename Real>
-__global__ __launch_bounds__(kBT) void k_bcheb_init(BSeg S, const Real* __restrict__ b, const Real* __restrict__ diag,
-                                                    const double* __restrict__ inv_theta, Real* __restrict__ r,
-                                                    Real* __restrict__ d, Real* __restrict__ x) {
-  int i;
-  long long lo, hi;
-  bseg_range(S, blockIdx.x, i, lo, hi);
-  const Real it = (Real)inv_theta[i];
-  for (long long q = lo + threadIdx.x; q < hi; q += kBT) {
-    const Real bi = b[q];
-    const Real di = it * bi / diag[q];
-    r[q] = bi;
-    d[q] = di;
-    x[q] = di;
-  }
-}
-
-template <typename Real>
-__global__ __launch_bounds__(kBT) void k_bcheb_step(BSeg S, Real* __restrict__ r, const Real* __restrict__ Jd,
-                                                    const Real* __restrict__ diag, const double* __restrict__ c,
-                                                    Real* __restrict__ d, Real* __restrict__ x) {
-  int i;
-  long long lo, hi;
-  bseg_range(S, blockIdx.x, i, lo, hi);
-  const Real c1 = (Real)c[2 * i], c2 = (Real)c[2 * i + 1];
-  for (long long q = lo + threadIdx.x; q < hi; q += kBT) {
-    const Real ri = r[q] - Jd[q];
-    const Real di = c1 * d[q] + c2 * ri / diag[q];
-    r[q] = ri;
-    d[q] = di;
-    x[q] += di;
-  }
-}
-
-// out = a + beta c (out may be a)
-template <typename Real>
-__global__ __launch_bounds__(kBT) void k_baxpy(BSeg S, const Real* a, Real beta, const Real* __restrict__ c, Real* out) {
-  int i;
-  long long lo, hi;
-  bseg_range(S, blockIdx.x, i, lo, hi);
-  for (long long q = lo + threadIdx.x; q < hi; q += kBT) out[q] = a[q] + beta * c[q];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    cheb_scalars(inst_at(G, i, BI_LAM), lambda_factor, range, deg, count, i, G.inv_theta, G.cheb);
 }
 
 // ---- one cycle -------------------------------------------------------------
@@ -675,6 +599,7 @@ struct BatchSolver {
   double *V, *Z, *w, *r, *t, *diag64, *cb, *cr, *cd, *cx, *ct, *mr64, *mx64;
   float *b32, *x32, *r32, *d32, *t32, *diag32, *mr32, *mx32;
   mns_batch* F = nullptr;  // multigrid: the batch of the level-0 operators
+  BatchMG* bmg = nullptr;  // multigrid: the batched coarse levels (null: corrections per instance)
   int mg_v64 = 0, mg_v32 = 0;
   int vm64 = 0, vm32 = 0;
   int it_vm64 = 0, it_vm32 = 0;  // Jacobian applications of one iteration
@@ -730,13 +655,17 @@ struct BatchSolver {
     if ((rc = jac_fine<Real>(x, tt, st))) return rc;
     hipLaunchKernelGGL(k_baxpy<Real>, dim3(nb), dim3(kBT), 0, st, S, b, Real(-1), (const Real*)tt, res);
     if ((rc = check("batch multigrid residual"))) return rc;
-    for (int i = 0; i < count; ++i) {
-      const long long off = B->offsets[i];
-      mns_handle* h0 = B->mg_fine_hs[i];
-      if ((rc = launch_constraints<Real>(h0, res + off, res + off, Real(0), 1, st)))
-        return fail(rc, "batch multigrid constraints");
-      if ((rc = mg_instance_correction<Real>(B->hs[i], res + off, x + off, tt + off, o, st)))
-        return fail(rc, "batch multigrid, instance " + std::to_string(i) + ": " + B->hs[i]->err);
+    if (bmg) {
+      if ((rc = bmg_correction<Real>(bmg, res, x, tt, st))) return fail(rc, "batched coarse-grid correction");
+    } else {
+      for (int i = 0; i < count; ++i) {
+        const long long off = B->offsets[i];
+        mns_handle* h0 = B->mg_fine_hs[i];
+        if ((rc = launch_constraints<Real>(h0, res + off, res + off, Real(0), 1, st)))
+          return fail(rc, "batch multigrid constraints");
+        if ((rc = mg_instance_correction<Real>(B->hs[i], res + off, x + off, tt + off, o, st)))
+          return fail(rc, "batch multigrid, instance " + std::to_string(i) + ": " + B->hs[i]->err);
+      }
     }
     if ((rc = jac_fine<Real>(x, tt, st))) return rc;
     hipLaunchKernelGGL(k_baxpy<Real>, dim3(nb), dim3(kBT), 0, st, S, b, Real(-1), (const Real*)tt, res);
@@ -796,7 +725,7 @@ struct BatchSolver {
   // the device): preconditioner, FP64 Jacobian, Gram-Schmidt with the
   // optional reorthogonalization, Givens, next basis vector.
   int mg_counts(int* a64, int* a32) {
-    *a64 = *a32 = 0;
+    bmg_counts(bmg, a64, a32);
     for (int i = 0; i < count; ++i) {
       int c64, c32;
       mg_instance_counts(B->hs[i], &c64, &c32);
@@ -1010,11 +939,11 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
   struct FineGuard {
     mns_batch* B;
     hipStream_t s;
+    BatchMG* bmg = nullptr;
     ~FineGuard() {
-      if (B->mg_fine) {
-        (void)hipStreamSynchronize(s);  // graph replays may still read its tables
-        mns_batch_destroy(B->mg_fine);
-      }
+      if (B->mg_fine || bmg) (void)hipStreamSynchronize(s);  // graph replays may still read their tables
+      bmg_free(bmg);
+      if (B->mg_fine) mns_batch_destroy(B->mg_fine);
       B->mg_fine = nullptr;
       B->mg_fine_hs.clear();
     }
@@ -1035,6 +964,10 @@ int batch_solve_impl(mns_batch* B, const double* rhs, double* x, const mns_solve
     } else {
       W.F = B;
     }
+    // the coarse levels batched when every hierarchy ends in a direct solve
+    rc = bmg_setup(B, B->mg_fine_hs.data(), o, o->precond == MNS_PRECOND_MG, s, &fine_guard.bmg);
+    if (rc && rc != MNS_ERR_UNSUPPORTED) return W.fail(rc, B->err);
+    W.bmg = fine_guard.bmg;
   }
   // diagonals of every instance (Alg. Alg-diagonal), FP64 and FP32: each
   // handle's cached diagonal, computed when its linearization changed (with

@@ -738,4 +738,53 @@ int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s) {
 template int coarse_apply<double>(const void*, const double*, double*, hipStream_t);
 template int coarse_apply<float>(const void*, const float*, float*, hipStream_t);
 
+int coarse_item(const void* state, CoarseItem* it) {
+  const auto* C = (const CoarseDirect*)state;
+  if (!C || !C->Ainv) return MNS_ERR_INVALID_ARG;
+  it->Ainv = C->Ainv;
+  it->lda = C->lda;
+  it->n = C->n;
+  return MNS_OK;
+}
+
+// x = Ainv b for several instances: one row per thread, the columns in
+// chunks of kGemvCols (each chunk's partial sum, then the chunks in order:
+// the summation order of k_gemv_part and k_gemv_sum)
+template <typename Real>
+__global__ __launch_bounds__(kCoarseRows) void k_gemv_batch(const CoarseItem* __restrict__ items, int count,
+                                                            const Real* __restrict__ b, Real* __restrict__ x) {
+  int a = 0, z = count - 1;  // last item whose first block is at or before this block
+  while (a < z) {
+    const int mid = (a + z + 1) >> 1;
+    if (items[mid].blk0 <= (long long)blockIdx.x) a = mid;
+    else z = mid - 1;
+  }
+  const CoarseItem it = items[a];
+  const int i = (int)((long long)blockIdx.x - it.blk0) * kCoarseRows + threadIdx.x;
+  const Real* bi = b + it.off;
+  __shared__ double bs[kGemvCols];
+  double s = 0.0;
+  for (int c0 = 0; c0 < it.n; c0 += kGemvCols) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kGemvCols; e += blockDim.x) bs[e] = c0 + e < it.n ? (double)bi[c0 + e] : 0.0;
+    __syncthreads();
+    if (i < it.n) {
+      double p = 0.0;
+      const int c1 = c0 + kGemvCols < it.n ? c0 + kGemvCols : it.n;
+      for (int c = c0; c < c1; ++c) p += it.Ainv[i + (long long)c * it.lda] * bs[c - c0];
+      s += p;
+    }
+  }
+  if (i < it.n) x[it.off + i] = (Real)s;
+}
+
+template <typename Real>
+int coarse_apply_batch(const CoarseItem* items, int count, long long blocks, const Real* b, Real* x, hipStream_t s) {
+  if (count == 0) return MNS_OK;
+  hipLaunchKernelGGL(k_gemv_batch<Real>, dim3((unsigned)blocks), dim3(kCoarseRows), 0, s, items, count, b, x);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+template int coarse_apply_batch<double>(const CoarseItem*, int, long long, const double*, double*, hipStream_t);
+template int coarse_apply_batch<float>(const CoarseItem*, int, long long, const float*, float*, hipStream_t);
+
 }  // namespace mns

@@ -328,6 +328,21 @@ double coarse_check_error(const void* state);
 int assemble_matrix(mns_handle* h, double* A, long long lda, hipStream_t s);
 template <typename Real>
 int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s);
+// the same solve for several instances in one launch: item j maps the
+// entries [off, off + n) of b to those of x through its inverse; blk0 is its
+// first block (kCoarseRows rows per block, items in block order)
+constexpr int kCoarseRows = 256;
+struct CoarseItem {
+  const double* Ainv;
+  long long lda;
+  int n;
+  long long off;
+  long long blk0;
+};
+// Ainv, lda and n of a coarse solve (INVALID_ARG without one)
+int coarse_item(const void* state, CoarseItem* it);
+template <typename Real>
+int coarse_apply_batch(const CoarseItem* items, int count, long long blocks, const Real* b, Real* x, hipStream_t s);
 
 // vector casts (mns_solver.hip)
 void mg_free(mns_handle* h);
@@ -349,6 +364,21 @@ template <typename Real>
 int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, Real* t0, const mns_solve_opts* o,
                            hipStream_t s);
 void mg_instance_counts(mns_handle* h, int* v64, int* v32);
+// the coarse-grid correction of every instance of a batch at once: each
+// level's smoothing, residual, transfers, constraints and direct coarsest
+// solves as batch launches (mns_solver.hip).  bmg_setup needs the hierarchies
+// set up (mg_instance_setup) and a direct coarsest solve on each
+// (UNSUPPORTED otherwise: the caller corrects per instance); level0[i] is
+// instance i's level-0 handle.  bmg_correction: x0 += the correction of the
+// level-0 residual r0 (its constrained rows zeroed in place), t0 work vector,
+// all in the batch's layout.
+struct BatchMG;
+int bmg_setup(mns_batch* B, mns_handle* const* level0, const mns_solve_opts* o, bool f32, hipStream_t s,
+              BatchMG** out);
+template <typename Real>
+int bmg_correction(BatchMG* M, Real* r0, Real* x0, Real* t0, hipStream_t s);
+void bmg_counts(const BatchMG* M, int* v64, int* v32);
+void bmg_free(BatchMG* M);
 int launch_cast_f32_f64(const float* a, double* b, int64_t n, hipStream_t s);
 
 // iso-parametric geometry (mns_iso.hip): node positions, fold check,

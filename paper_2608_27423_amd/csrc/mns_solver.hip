@@ -8,12 +8,14 @@
 // with a deterministic two-stage reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "mns_batch_vec.hpp"
 #include "mns_internal.hpp"
 
 int mns_build_handle(const mns_mesh_desc* d, hipStream_t stream, mns_handle* h);
@@ -911,11 +913,10 @@ struct TxView {
   long long pt, pr[2], pz, rt, rr[2], rz, et, er[2], ez;  // table offsets (entries)
 };
 
+// fine node g of P x_c (added to the fine value when add)
 template <typename Real>
-__global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __restrict__ fine, long long nnf,
-                             int add) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nnf) return;
+__device__ inline void prolong_node(const TxView& X, const Real* __restrict__ coarse, Real* __restrict__ fine,
+                                    long long g, int add) {
   const int dom = g >= X.off1f;
   const long long l = g - (dom ? X.off1f : 0);
   const int it = (int)(l % X.ntf);
@@ -946,6 +947,13 @@ __global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __
   for (int m = 0; m < X.nc; ++m) fine[g * X.nc + m] = (add ? fine[g * X.nc + m] : Real(0)) + acc[m];
 }
 
+template <typename Real>
+__global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __restrict__ fine, long long nnf,
+                             int add) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < nnf) prolong_node(X, coarse, fine, g, add);
+}
+
 // One direction of the restriction (the transposed 1D prolongation rows):
 // the node grid of `in` has the coarse counts in the directions already
 // restricted and the fine counts in the others; `out` has the coarse count in
@@ -958,11 +966,10 @@ struct RestrictPass {
   long long off1_in, off1_out;  // first stator node of each grid
 };
 
+// output node g of one restriction pass
 template <typename Real>
-__global__ void k_mg_restrict_dir(TxView X, RestrictPass P, const Real* __restrict__ in, Real* __restrict__ out,
-                                  long long nout) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nout) return;
+__device__ inline void restrict_dir_node(const TxView& X, const RestrictPass& P, const Real* __restrict__ in,
+                                         Real* __restrict__ out, long long g) {
   const int dom = g >= P.off1_out;
   const long long l = g - (dom ? P.off1_out : 0);
   const int it = (int)(l % P.nt_out);
@@ -985,6 +992,13 @@ __global__ void k_mg_restrict_dir(TxView X, RestrictPass P, const Real* __restri
   for (int m = 0; m < X.nc; ++m) out[g * X.nc + m] = acc[m];
 }
 
+template <typename Real>
+__global__ void k_mg_restrict_dir(TxView X, RestrictPass P, const Real* __restrict__ in, Real* __restrict__ out,
+                                  long long nout) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < nout) restrict_dir_node(X, P, in, out, g);
+}
+
 
 // coarse nodal values of a fine field: the fine field evaluated at the
 // node counts of the two intermediate grids of the three-pass restriction
@@ -992,20 +1006,31 @@ static long long restrict_tmp_nodes(const TxView& X) {
   return (long long)X.ntc * X.nzf * (X.nrf[0] + X.nrf[1] + X.nrc[0] + X.nrc[1]);
 }
 
+// the three passes of coarse = P^T fine (theta, then r, then z) and their
+// output node counts; tmp holds the two intermediate grids, the second one
+// n[0] * nc entries after the first
+static void restrict_passes(const TxView& X, RestrictPass P[3], long long n[3]) {
+  n[0] = (long long)X.ntc * X.nzf * (X.nrf[0] + X.nrf[1]);
+  n[1] = (long long)X.ntc * X.nzf * (X.nrc[0] + X.nrc[1]);
+  n[2] = (long long)X.ntc * X.nzc * (X.nrc[0] + X.nrc[1]);
+  P[0] = RestrictPass{0, X.ntf, X.nzf, {X.nrf[0], X.nrf[1]}, X.ntc, X.nzf, {X.nrf[0], X.nrf[1]}, X.off1f,
+                      (long long)X.ntc * X.nrf[0] * X.nzf};
+  P[1] = RestrictPass{1, X.ntc, X.nzf, {X.nrf[0], X.nrf[1]}, X.ntc, X.nzf, {X.nrc[0], X.nrc[1]}, P[0].off1_out,
+                      (long long)X.ntc * X.nrc[0] * X.nzf};
+  P[2] = RestrictPass{2, X.ntc, X.nzf, {X.nrc[0], X.nrc[1]}, X.ntc, X.nzc, {X.nrc[0], X.nrc[1]}, P[1].off1_out,
+                      X.off1c};
+}
+
 // coarse = P^T fine: theta, then r, then z (tmp holds the intermediate grids)
 template <typename Real>
 static int mg_restrict(const TxView& X, void* tmp, const Real* fine, Real* coarse, hipStream_t s) {
+  RestrictPass P[3];
+  long long n[3];
+  restrict_passes(X, P, n);
+  const long long n1 = n[0], n2 = n[1], n3 = n[2];
+  const RestrictPass &p1 = P[0], &p2 = P[1], &p3 = P[2];
   Real* t1 = (Real*)tmp;
-  const long long n1 = (long long)X.ntc * X.nzf * (X.nrf[0] + X.nrf[1]);
   Real* t2 = t1 + n1 * X.nc;
-  const long long n2 = (long long)X.ntc * X.nzf * (X.nrc[0] + X.nrc[1]);
-  const long long n3 = (long long)X.ntc * X.nzc * (X.nrc[0] + X.nrc[1]);
-  const RestrictPass p1{0, X.ntf, X.nzf, {X.nrf[0], X.nrf[1]}, X.ntc, X.nzf, {X.nrf[0], X.nrf[1]}, X.off1f,
-                        (long long)X.ntc * X.nrf[0] * X.nzf};
-  const RestrictPass p2{1, X.ntc, X.nzf, {X.nrf[0], X.nrf[1]}, X.ntc, X.nzf, {X.nrc[0], X.nrc[1]}, p1.off1_out,
-                        (long long)X.ntc * X.nrc[0] * X.nzf};
-  const RestrictPass p3{2, X.ntc, X.nzf, {X.nrc[0], X.nrc[1]}, X.ntc, X.nzc, {X.nrc[0], X.nrc[1]}, p2.off1_out,
-                        X.off1c};
   hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, X, p1, fine, t1, n1);
   hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, X, p2,
                      (const Real*)t1, t2, n2);
@@ -1531,6 +1556,397 @@ void mg_instance_counts(mns_handle* h, int* v64, int* v32) {
   *v64 = *v32 = 0;
   if (mg) mg_count(mg, v64, v32);
 }
+
+}  // namespace mns
+
+// ---------------------------------------------------------------------------
+// The coarse-grid correction of every instance of a batch at once.  Level l
+// holds the instances whose hierarchy reaches it, the deepest first, so that
+// those with a coarser level below form a prefix: their smoothing runs as
+// batch launches over their level-l operators (per-instance lambda_max and
+// diagonal), the others take their direct FP64 coarsest solve in one batched
+// launch.  Restriction, prolongation and constraints run as item launches
+// (one item per instance, blocks in item order), with each instance's own
+// transfer tables.  The steps are those of the single-instance cycle.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TxItem {
+  TxView X;
+  RestrictPass P[3];
+  long long n[3];        // output nodes of the restriction passes
+  long long blk[4];      // first block in the launches of passes 0..2 and of the prolongation
+  long long nnf;         // fine nodes (prolongation outputs)
+  void* tmp;             // intermediate grids of the restriction (the instance's own buffer)
+  long long foff, coff;  // the instance's first entry in the fine and in the coarse level vectors
+};
+
+struct ConsItem {
+  const int64_t* cons;  // constrained rows of the instance's level (sorted)
+  long long n;
+  long long off;        // the instance's first entry in the level vector
+  long long blk0;
+};
+
+// last item whose first block of launch `which` is at or before block b
+template <typename Item, typename Get>
+__device__ inline int item_find(const Item* it, int count, long long b, Get first) {
+  int a = 0, z = count - 1;
+  while (a < z) {
+    const int mid = (a + z + 1) >> 1;
+    if (first(it[mid]) <= b) a = mid;
+    else z = mid - 1;
+  }
+  return a;
+}
+
+// restriction pass `pass` of every item: pass 0 reads the fine level vector,
+// pass 2 writes the coarse one
+template <typename Real>
+__global__ __launch_bounds__(256) void k_bmg_restrict(const TxItem* __restrict__ items, int count, int pass,
+                                                      const Real* __restrict__ fine, Real* __restrict__ coarse) {
+  const TxItem& it = items[item_find(items, count, blockIdx.x, [pass](const TxItem& t) { return t.blk[pass]; })];
+  const long long g = ((long long)blockIdx.x - it.blk[pass]) * 256 + threadIdx.x;
+  if (g >= it.n[pass]) return;
+  Real* t1 = (Real*)it.tmp;
+  Real* t2 = t1 + it.n[0] * it.X.nc;
+  const Real* in = pass == 0 ? fine + it.foff : (pass == 1 ? t1 : t2);
+  Real* out = pass == 0 ? t1 : (pass == 1 ? t2 : coarse + it.coff);
+  restrict_dir_node(it.X, it.P[pass], in, out, g);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_bmg_prolong(const TxItem* __restrict__ items, int count,
+                                                     const Real* __restrict__ coarse, Real* __restrict__ fine) {
+  const TxItem& it = items[item_find(items, count, blockIdx.x, [](const TxItem& t) { return t.blk[3]; })];
+  const long long g = ((long long)blockIdx.x - it.blk[3]) * 256 + threadIdx.x;
+  if (g < it.nnf) prolong_node(it.X, coarse + it.coff, fine + it.foff, g, 0);
+}
+
+// constrained rows of every item set to zero
+template <typename Real>
+__global__ __launch_bounds__(256) void k_bmg_constraints(const ConsItem* __restrict__ items, int count,
+                                                         Real* __restrict__ v) {
+  const ConsItem& it = items[item_find(items, count, blockIdx.x, [](const ConsItem& t) { return t.blk0; })];
+  const long long i = ((long long)blockIdx.x - it.blk0) * 256 + threadIdx.x;
+  if (i < it.n) v[it.off + it.cons[i]] = Real(0);
+}
+
+// Chebyshev scalars of count instances from their lambda_max
+__global__ void k_bmg_coef(const double* __restrict__ lam, int count, int deg, double lambda_factor, double range,
+                           double* inv_theta, double* cheb) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    cheb_scalars(lam[i], lambda_factor, range, deg, count, i, inv_theta, cheb);
+}
+
+}  // namespace
+
+namespace mns {
+
+struct BatchMG {
+  struct Level {
+    int count = 0, ncont = 0;        // instances on the level; those with a coarser level (a prefix)
+    long long n = 0, ncn = 0;        // entries of all of them; of the prefix
+    std::vector<long long> off;      // first entry of each (count + 1)
+    mns_batch* bat = nullptr;        // batch over the prefix's level operators (levels >= 1)
+    long long* d_seg = nullptr;      // segments of the prefix: first blocks, first entries (ncont + 1 each)
+    long long nblk = 0;              // vector blocks of the prefix
+    double* d_coef = nullptr;        // inv_theta[ncont], then cheb[deg][ncont][2]
+    void* vec = nullptr;             // b, x, r, rr, dd, tt, cx, diag (levels >= 1, the cycle's precision)
+    TxItem* d_tx = nullptr;          // transfers of the prefix to the next level
+    long long tx_blocks[4] = {0, 0, 0, 0};
+    ConsItem* d_cons = nullptr;      // constrained rows of all instances of the level
+    int ncons = 0;
+    long long cons_blocks = 0;
+    CoarseItem* d_coarse = nullptr;  // direct coarsest solves of the instances after the prefix
+    int ncoarse = 0;
+    long long coarse_blocks = 0;
+  };
+  std::vector<Level> lv;
+  bool f32 = true;
+  int deg = 0;
+  int vm64 = 0, vm32 = 0;
+};
+
+void bmg_free(BatchMG* M) {
+  if (!M) return;
+  for (auto& L : M->lv) {
+    if (L.bat) mns_batch_destroy(L.bat);
+    for (void* p : {(void*)L.d_seg, (void*)L.d_coef, L.vec, (void*)L.d_tx, (void*)L.d_cons, (void*)L.d_coarse})
+      if (p) (void)hipFree(p);
+  }
+  delete M;
+}
+
+void bmg_counts(const BatchMG* M, int* v64, int* v32) {
+  *v64 = M ? M->vm64 : 0;
+  *v32 = M ? M->vm32 : 0;
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
+  if (e == hipSuccess) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+int bmg_setup(mns_batch* B, mns_handle* const* level0, const mns_solve_opts* o, bool f32, hipStream_t s,
+              BatchMG** out) {
+  *out = nullptr;
+  const int count = (int)B->hs.size();
+  std::vector<MG*> mg(count);
+  size_t depth = 0;
+  for (int i = 0; i < count; ++i) {
+    mg[i] = (MG*)B->hs[i]->mg;
+    if (!mg[i] || mg[i]->L.size() < 2 || !mg[i]->coarse_ready || mg[i]->L[0].h != level0[i])
+      return MNS_ERR_UNSUPPORTED;
+    depth = std::max(depth, mg[i]->L.size());
+  }
+  // members of every level: level 0 in the batch's order, the others the
+  // deepest hierarchies first (stable), so that each level's members with a
+  // coarser level are a prefix and are the next level's members, in order
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mg[a]->L.size() > mg[b]->L.size(); });
+  std::vector<std::vector<int>> mem(depth);
+  for (int i = 0; i < count; ++i) mem[0].push_back(i);
+  for (size_t l = 1; l < depth; ++l)
+    for (int i : order)
+      if (mg[i]->L.size() > l) mem[l].push_back(i);
+  std::vector<std::vector<int>> pos(depth, std::vector<int>(count, -1));  // member index of instance i
+  for (size_t l = 0; l < depth; ++l)
+    for (size_t j = 0; j < mem[l].size(); ++j) pos[l][mem[l][j]] = (int)j;
+
+  auto* M = new BatchMG();
+  M->f32 = f32;
+  M->deg = o->mg_smooth_degree;
+  M->lv.resize(depth);
+  const size_t rb = f32 ? sizeof(float) : sizeof(double);
+  hipError_t e = hipSuccess;
+  int rc = MNS_OK;
+  auto fail = [&](const std::string& what) {
+    B->err = "batched multigrid set-up: " + what + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : "");
+    bmg_free(M);
+    return rc ? rc : MNS_ERR_HIP;
+  };
+  for (size_t l = 0; l < depth; ++l) {
+    BatchMG::Level& Lv = M->lv[l];
+    const std::vector<int>& ms = mem[l];
+    Lv.count = (int)ms.size();
+    Lv.off.assign(Lv.count + 1, 0);
+    for (int j = 0; j < Lv.count; ++j) {
+      const int i = ms[j];
+      Lv.off[j + 1] = Lv.off[j] + mg[i]->L[l].n;
+      if (mg[i]->L.size() > l + 1) Lv.ncont = j + 1;
+    }
+    Lv.n = Lv.off[Lv.count];
+    Lv.ncn = Lv.off[Lv.ncont];
+    if (l == 0)
+      for (int j = 0; j < count; ++j)
+        if (Lv.off[j] != B->offsets[j]) return fail("level-0 sizes differ from the batch's");
+    // transfers of the prefix to level l + 1
+    if (Lv.ncont > 0) {
+      std::vector<TxItem> tx(Lv.ncont);
+      long long acc[4] = {0, 0, 0, 0};
+      for (int j = 0; j < Lv.ncont; ++j) {
+        const int i = ms[j];
+        TxItem& t = tx[j];
+        t.X = mg[i]->T[l];
+        restrict_passes(t.X, t.P, t.n);
+        t.nnf = mg[i]->L[l].h->nnodes;
+        t.tmp = mg[i]->L[l].tr;
+        t.foff = Lv.off[j];
+        t.coff = -1;  // set below from the next level's offsets
+        const long long nb[4] = {(t.n[0] + 255) / 256, (t.n[1] + 255) / 256, (t.n[2] + 255) / 256,
+                                 (t.nnf + 255) / 256};
+        for (int p = 0; p < 4; ++p) {
+          t.blk[p] = acc[p];
+          acc[p] += nb[p];
+        }
+      }
+      for (int p = 0; p < 4; ++p) Lv.tx_blocks[p] = acc[p];
+      // the instances' first entries on level l + 1
+      std::vector<long long> off1(mem[l + 1].size() + 1, 0);
+      for (size_t j = 0; j < mem[l + 1].size(); ++j) off1[j + 1] = off1[j] + mg[mem[l + 1][j]]->L[l + 1].n;
+      for (int j = 0; j < Lv.ncont; ++j) {
+        if (pos[l + 1][ms[j]] < 0) return fail("level membership");
+        tx[j].coff = off1[pos[l + 1][ms[j]]];
+      }
+      if ((e = upload(&Lv.d_tx, tx)) != hipSuccess) return fail("transfer items");
+    }
+    // constrained rows of every member
+    {
+      std::vector<ConsItem> ci;
+      long long acc = 0;
+      for (int j = 0; j < Lv.count; ++j) {
+        const mns_handle* hl = mg[ms[j]]->L[l].h;
+        if (hl->n_cons == 0) continue;
+        ci.push_back(ConsItem{hl->d_cons, (long long)hl->n_cons, Lv.off[j], acc});
+        acc += (hl->n_cons + 255) / 256;
+      }
+      Lv.ncons = (int)ci.size();
+      Lv.cons_blocks = acc;
+      if ((e = upload(&Lv.d_cons, ci)) != hipSuccess) return fail("constraint items");
+    }
+    if (l == 0) continue;  // level 0: smoothing and vectors belong to the batched solver
+    // direct coarsest solves of the members after the prefix
+    {
+      std::vector<CoarseItem> co;
+      long long acc = 0;
+      for (int j = Lv.ncont; j < Lv.count; ++j) {
+        CoarseItem it{};
+        if ((rc = coarse_item(mg[ms[j]]->coarse, &it)) || it.n != Lv.off[j + 1] - Lv.off[j])
+          return fail("coarsest-level solve of instance " + std::to_string(ms[j]));
+        it.off = Lv.off[j];
+        it.blk0 = acc;
+        acc += (it.n + kCoarseRows - 1) / kCoarseRows;
+        co.push_back(it);
+      }
+      Lv.ncoarse = (int)co.size();
+      Lv.coarse_blocks = acc;
+      if ((e = upload(&Lv.d_coarse, co)) != hipSuccess) return fail("coarse items");
+    }
+    if ((e = hipMalloc(&Lv.vec, 8 * (size_t)Lv.n * rb)) != hipSuccess) return fail("level vectors");
+    if (Lv.ncont == 0) continue;
+    // the prefix: its batch, segments, diagonals and Chebyshev scalars
+    std::vector<mns_handle*> hs(Lv.ncont);
+    std::vector<long long> seg(2 * (size_t)(Lv.ncont + 1), 0);
+    std::vector<double> lam(Lv.ncont);
+    char* diag = (char*)Lv.vec + 7 * (size_t)Lv.n * rb;
+    for (int j = 0; j < Lv.ncont; ++j) {
+      const MGLevel& ml = mg[ms[j]]->L[l];
+      hs[j] = ml.h;
+      lam[j] = ml.lmax;
+      seg[j + 1] = seg[j] + (ml.n + kBChunk - 1) / kBChunk;
+      seg[Lv.ncont + 1 + j] = Lv.off[j];
+      const void* dsrc = f32 ? (const void*)ml.h->d_diag32 : (const void*)ml.h->d_diag64;
+      if ((e = hipMemcpyAsync(diag + (size_t)Lv.off[j] * rb, dsrc, (size_t)ml.n * rb, hipMemcpyDeviceToDevice, s)) !=
+          hipSuccess)
+        return fail("diagonals");
+    }
+    seg[2 * (size_t)Lv.ncont + 1] = Lv.ncn;
+    Lv.nblk = seg[Lv.ncont];
+    if ((rc = mns_batch_create(hs.data(), Lv.ncont, &Lv.bat))) return fail("level batch: " + hs[0]->err);
+    if ((e = upload(&Lv.d_seg, seg)) != hipSuccess) return fail("segments");
+    double* d_lam = nullptr;
+    if ((e = upload(&d_lam, lam)) != hipSuccess) return fail("spectra");
+    if ((e = hipMalloc((void**)&Lv.d_coef, (size_t)Lv.ncont * (1 + 2 * (size_t)std::max(M->deg, 1)) *
+                                               sizeof(double))) != hipSuccess) {
+      (void)hipFree(d_lam);
+      return fail("Chebyshev scalars");
+    }
+    hipLaunchKernelGGL(k_bmg_coef, dim3(1), dim3(256), 0, s, (const double*)d_lam, Lv.ncont, M->deg,
+                       o->cheb_lambda_factor, o->mg_smooth_range, Lv.d_coef, Lv.d_coef + Lv.ncont);
+    e = hipStreamSynchronize(s);
+    (void)hipFree(d_lam);
+    if (e != hipSuccess) return fail("Chebyshev scalars");
+  }
+  *out = M;
+  return MNS_OK;
+}
+
+template <typename Real>
+static int bmg_jac(BatchMG* M, BatchMG::Level& Lv, const Real* src, Real* dst, hipStream_t s) {
+  ++(sizeof(Real) == 8 ? M->vm64 : M->vm32);
+  return launch_batch_jacobian<Real>(Lv.bat, src, dst, s);
+}
+
+// x = Chebyshev polynomial of degree deg in D^-1 J applied to b (from zero),
+// on the level's prefix
+template <typename Real>
+static int bmg_poly(BatchMG* M, BatchMG::Level& Lv, const Real* b, Real* x, Real* rr, Real* dd, Real* tt,
+                    const Real* diag, hipStream_t s) {
+  const BSeg S{Lv.d_seg, Lv.d_seg + Lv.ncont + 1, Lv.ncont};
+  const unsigned nb = (unsigned)Lv.nblk;
+  hipLaunchKernelGGL(k_bcheb_init<Real>, dim3(nb), dim3(kBT), 0, s, S, b, diag, (const double*)Lv.d_coef, rr, dd, x);
+  for (int k = 0; k < M->deg; ++k) {
+    int rc;
+    if ((rc = bmg_jac<Real>(M, Lv, dd, tt, s))) return rc;
+    hipLaunchKernelGGL(k_bcheb_step<Real>, dim3(nb), dim3(kBT), 0, s, S, rr, (const Real*)tt, diag,
+                       (const double*)(Lv.d_coef + Lv.ncont + (size_t)k * Lv.ncont * 2), dd, x);
+  }
+  return MNS_OK;
+}
+
+template <typename Real>
+static void bmg_constrain(const BatchMG::Level& Lv, Real* v, hipStream_t s) {
+  if (Lv.ncons)
+    hipLaunchKernelGGL(k_bmg_constraints<Real>, dim3((unsigned)Lv.cons_blocks), dim3(256), 0, s,
+                       (const ConsItem*)Lv.d_cons, Lv.ncons, v);
+}
+
+template <typename Real>
+static void bmg_restrict(const BatchMG::Level& Lv, const Real* fine, Real* coarse, hipStream_t s) {
+  for (int p = 0; p < 3; ++p)
+    hipLaunchKernelGGL(k_bmg_restrict<Real>, dim3((unsigned)Lv.tx_blocks[p]), dim3(256), 0, s,
+                       (const TxItem*)Lv.d_tx, Lv.ncont, p, fine, coarse);
+}
+
+template <typename Real>
+static void bmg_prolong(const BatchMG::Level& Lv, const Real* coarse, Real* fine, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmg_prolong<Real>, dim3((unsigned)Lv.tx_blocks[3]), dim3(256), 0, s, (const TxItem*)Lv.d_tx,
+                     Lv.ncont, coarse, fine);
+}
+
+template <typename Real>
+static void bmg_axpy(const Real* a, Real beta, const Real* c, Real* o, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(grid_for(n)), dim3(256), 0, s, a, beta, c, o, n);
+}
+
+// the cycle from level l (>= 1) down: b -> x on every member of the level
+template <typename Real>
+static int bmg_cycle(BatchMG* M, size_t l, hipStream_t s) {
+  BatchMG::Level& Lv = M->lv[l];
+  const long long n = Lv.n;
+  Real* v = (Real*)Lv.vec;
+  Real *b = v, *x = v + n, *r = v + 2 * n, *rr = v + 3 * n, *dd = v + 4 * n, *tt = v + 5 * n, *cx = v + 6 * n;
+  const Real* diag = v + 7 * n;
+  int rc;
+  if (Lv.ncont > 0) {
+    BatchMG::Level& Lc = M->lv[l + 1];
+    Real* vc = (Real*)Lc.vec;
+    if ((rc = bmg_poly<Real>(M, Lv, b, x, rr, dd, tt, diag, s))) return rc;
+    // residual, restricted with constrained rows zero on both levels
+    if ((rc = bmg_jac<Real>(M, Lv, x, tt, s))) return rc;
+    bmg_axpy<Real>(b, Real(-1), tt, r, Lv.ncn, s);
+    bmg_constrain<Real>(Lv, r, s);
+    bmg_restrict<Real>(Lv, r, vc, s);
+    bmg_constrain<Real>(Lc, vc, s);
+    if ((rc = bmg_cycle<Real>(M, l + 1, s))) return rc;
+    // x += P x_c (constrained rows of the correction zero)
+    bmg_prolong<Real>(Lv, vc + Lc.n, r, s);
+    bmg_constrain<Real>(Lv, r, s);
+    bmg_axpy<Real>(x, Real(1), r, x, Lv.ncn, s);
+    // post-smoothing: x += poly(b - J x)
+    if ((rc = bmg_jac<Real>(M, Lv, x, tt, s))) return rc;
+    bmg_axpy<Real>(b, Real(-1), tt, r, Lv.ncn, s);
+    if ((rc = bmg_poly<Real>(M, Lv, r, cx, rr, dd, tt, diag, s))) return rc;
+    bmg_axpy<Real>(x, Real(1), cx, x, Lv.ncn, s);
+  }
+  if (Lv.ncoarse > 0 && (rc = coarse_apply_batch<Real>(Lv.d_coarse, Lv.ncoarse, Lv.coarse_blocks, b, x, s)))
+    return rc;
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+
+template <typename Real>
+int bmg_correction(BatchMG* M, Real* r0, Real* x0, Real* t0, hipStream_t s) {
+  if (!M || M->lv.size() < 2 || (sizeof(Real) == 4) != M->f32) return MNS_ERR_INVALID_ARG;
+  BatchMG::Level &L0 = M->lv[0], &L1 = M->lv[1];
+  Real* v1 = (Real*)L1.vec;
+  bmg_constrain<Real>(L0, r0, s);
+  bmg_restrict<Real>(L0, r0, v1, s);
+  bmg_constrain<Real>(L1, v1, s);
+  int rc = bmg_cycle<Real>(M, 1, s);
+  if (rc) return rc;
+  bmg_prolong<Real>(L0, v1 + L1.n, t0, s);
+  bmg_constrain<Real>(L0, t0, s);
+  bmg_axpy<Real>(x0, Real(1), t0, x0, L0.n, s);
+  return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
+}
+template int bmg_correction<float>(BatchMG*, float*, float*, float*, hipStream_t);
+template int bmg_correction<double>(BatchMG*, double*, double*, double*, hipStream_t);
 
 }  // namespace mns
 

@@ -1,8 +1,10 @@
 """Batched FGMRES with the geometric multigrid V-cycle as preconditioner
-(mns_batch_solve with MNS_PRECOND_MG or MNS_PRECOND_MG64): the finest level's
-Chebyshev smoothing and residual run as batch launches over the instances'
-level-0 operators, the coarse-grid correction (restriction, the instance's own
-cycle from level 1 with its FP64 coarsest level, prolongation) per instance.
+(mns_batch_solve with MNS_PRECOND_MG or MNS_PRECOND_MG64): every level's
+Chebyshev smoothing, residual, transfers and constraints run as batch
+launches over the instances on that level (hierarchies of different depths:
+the shallower ones take their direct FP64 coarsest solve in a batched launch
+while the deeper ones continue), or, without direct coarsest solves, the
+coarse-grid correction runs per instance through its own cycle.
 
 Every instance's solution must equal the direct sparse solve of the oracle's
 assembled Jacobian, its iteration count must be that of its own mns_solve
@@ -89,6 +91,30 @@ def test_batch_multigrid_matches_single_and_direct_solves(dim, precond):
                     assert reps[i]["vmults_f32"] > 0
                 else:
                     assert reps[i]["vmults_f32"] == 0
+    finally:
+        for op in ops:
+            op.close()
+
+
+def test_batch_multigrid_chebyshev_coarsest_level():
+    """mg_coarse_direct = 0: the coarsest level of every hierarchy is an FP64
+    Chebyshev polynomial instead of a direct solve, and the batched solve
+    takes each instance's coarse-grid correction through its own cycle; the
+    iteration counts are still those of the single solves within two."""
+    inst = _mg_instances(2) + _mg_instances(3)[:2]
+    ops = []
+    try:
+        ops, _, rhs = _operators(inst, 131)
+        opts = dict(rtol=1e-10, restart=30, maxit=600, precond="mg", mg_coarse_direct=0)
+        with binding.Batch(ops) as bt:
+            _, rc, reps = bt.solve(_dev(np.concatenate(rhs)), check=False, **opts)
+            assert rc == 0, bt.last_error()
+            for i, op in enumerate(ops):
+                _, rep1 = op.solve(_dev(rhs[i]), check=False, **opts)
+                print(f"Chebyshev coarsest level, instance {i}: batch its {reps[i]['iterations']} "
+                      f"(single {rep1['iterations']})")
+                assert reps[i]["status"] == 0 and rep1["rc"] == 0
+                assert abs(reps[i]["iterations"] - rep1["iterations"]) <= 2
     finally:
         for op in ops:
             op.close()
