@@ -747,44 +747,71 @@ int coarse_item(const void* state, CoarseItem* it) {
   return MNS_OK;
 }
 
-// x = Ainv b for several instances: one row per thread, the columns in
-// chunks of kGemvCols (each chunk's partial sum, then the chunks in order:
-// the summation order of k_gemv_part and k_gemv_sum)
-template <typename Real>
-__global__ __launch_bounds__(kCoarseRows) void k_gemv_batch(const CoarseItem* __restrict__ items, int count,
-                                                            const Real* __restrict__ b, Real* __restrict__ x) {
-  int a = 0, z = count - 1;  // last item whose first block is at or before this block
+// x = Ainv b for several instances, in the two stages of coarse_apply
+// (partial sums over column chunks of kGemvCols, then the chunks summed in
+// order): one launch of (item, row block, chunk) blocks and one of
+// (item, row block) blocks
+int coarse_parts(int n) { return (n + kGemvCols - 1) / kGemvCols; }
+
+void coarse_blocks(int n, long long* part_blocks, long long* sum_blocks) {
+  const long long rows = (n + kGemvRows - 1) / kGemvRows;
+  *part_blocks = rows * coarse_parts(n);
+  *sum_blocks = rows;
+}
+
+__device__ inline int coarse_find(const CoarseItem* items, int count, long long b, bool second) {
+  int a = 0, z = count - 1;  // last item whose first block is at or before b
   while (a < z) {
     const int mid = (a + z + 1) >> 1;
-    if (items[mid].blk0 <= (long long)blockIdx.x) a = mid;
+    if ((second ? items[mid].blk1 : items[mid].blk0) <= b) a = mid;
     else z = mid - 1;
   }
-  const CoarseItem it = items[a];
-  const int i = (int)((long long)blockIdx.x - it.blk0) * kCoarseRows + threadIdx.x;
-  const Real* bi = b + it.off;
-  __shared__ double bs[kGemvCols];
-  double s = 0.0;
-  for (int c0 = 0; c0 < it.n; c0 += kGemvCols) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kGemvCols; e += blockDim.x) bs[e] = c0 + e < it.n ? (double)bi[c0 + e] : 0.0;
-    __syncthreads();
-    if (i < it.n) {
-      double p = 0.0;
-      const int c1 = c0 + kGemvCols < it.n ? c0 + kGemvCols : it.n;
-      for (int c = c0; c < c1; ++c) p += it.Ainv[i + (long long)c * it.lda] * bs[c - c0];
-      s += p;
-    }
-  }
-  if (i < it.n) x[it.off + i] = (Real)s;
+  return a;
 }
 
 template <typename Real>
-int coarse_apply_batch(const CoarseItem* items, int count, long long blocks, const Real* b, Real* x, hipStream_t s) {
+__global__ __launch_bounds__(kGemvRows) void k_gemv_batch_part(const CoarseItem* __restrict__ items, int count,
+                                                               const Real* __restrict__ b) {
+  const CoarseItem& it = items[coarse_find(items, count, blockIdx.x, false)];
+  const long long local = (long long)blockIdx.x - it.blk0;
+  const int rows = (it.n + kGemvRows - 1) / kGemvRows;
+  const int rb = (int)(local % rows), p = (int)(local / rows);
+  const int i = rb * kGemvRows + threadIdx.x;
+  const int c0 = p * kGemvCols;
+  const Real* bi = b + it.off;
+  __shared__ double bs[kGemvCols];
+  for (int e = threadIdx.x; e < kGemvCols; e += blockDim.x) bs[e] = c0 + e < it.n ? (double)bi[c0 + e] : 0.0;
+  __syncthreads();
+  if (i >= it.n) return;
+  double s = 0.0;
+  const int c1 = c0 + kGemvCols < it.n ? c0 + kGemvCols : it.n;
+  for (int c = c0; c < c1; ++c) s += it.Ainv[i + (long long)c * it.lda] * bs[c - c0];
+  it.part[(long long)p * it.n + i] = s;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kGemvRows) void k_gemv_batch_sum(const CoarseItem* __restrict__ items, int count,
+                                                              Real* __restrict__ x) {
+  const CoarseItem& it = items[coarse_find(items, count, blockIdx.x, true)];
+  const int i = (int)((long long)blockIdx.x - it.blk1) * kGemvRows + threadIdx.x;
+  if (i >= it.n) return;
+  const int parts = (it.n + kGemvCols - 1) / kGemvCols;
+  double s = 0.0;
+  for (int p = 0; p < parts; ++p) s += it.part[(long long)p * it.n + i];
+  x[it.off + i] = (Real)s;
+}
+
+template <typename Real>
+int coarse_apply_batch(const CoarseItem* items, int count, long long part_blocks, long long sum_blocks,
+                       const Real* b, Real* x, hipStream_t s) {
   if (count == 0) return MNS_OK;
-  hipLaunchKernelGGL(k_gemv_batch<Real>, dim3((unsigned)blocks), dim3(kCoarseRows), 0, s, items, count, b, x);
+  hipLaunchKernelGGL(k_gemv_batch_part<Real>, dim3((unsigned)part_blocks), dim3(kGemvRows), 0, s, items, count, b);
+  hipLaunchKernelGGL(k_gemv_batch_sum<Real>, dim3((unsigned)sum_blocks), dim3(kGemvRows), 0, s, items, count, x);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
-template int coarse_apply_batch<double>(const CoarseItem*, int, long long, const double*, double*, hipStream_t);
-template int coarse_apply_batch<float>(const CoarseItem*, int, long long, const float*, float*, hipStream_t);
+template int coarse_apply_batch<double>(const CoarseItem*, int, long long, long long, const double*, double*,
+                                        hipStream_t);
+template int coarse_apply_batch<float>(const CoarseItem*, int, long long, long long, const float*, float*,
+                                       hipStream_t);
 
 }  // namespace mns

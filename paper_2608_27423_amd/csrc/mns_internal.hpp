@@ -328,21 +328,26 @@ double coarse_check_error(const void* state);
 int assemble_matrix(mns_handle* h, double* A, long long lda, hipStream_t s);
 template <typename Real>
 int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s);
-// the same solve for several instances in one launch: item j maps the
-// entries [off, off + n) of b to those of x through its inverse; blk0 is its
-// first block (kCoarseRows rows per block, items in block order)
-constexpr int kCoarseRows = 256;
+// the same solve for several instances in two launches: item j maps the
+// entries [off, off + n) of b to those of x through its inverse, with
+// coarse_parts(n) column-chunk partial sums of n values each in part; blk0
+// and blk1 are its first blocks in the partial-sum launch and in the
+// summation launch (items in block order; coarse_blocks gives the counts)
 struct CoarseItem {
   const double* Ainv;
   long long lda;
   int n;
   long long off;
-  long long blk0;
+  double* part;
+  long long blk0, blk1;
 };
+int coarse_parts(int n);
+void coarse_blocks(int n, long long* part_blocks, long long* sum_blocks);
 // Ainv, lda and n of a coarse solve (INVALID_ARG without one)
 int coarse_item(const void* state, CoarseItem* it);
 template <typename Real>
-int coarse_apply_batch(const CoarseItem* items, int count, long long blocks, const Real* b, Real* x, hipStream_t s);
+int coarse_apply_batch(const CoarseItem* items, int count, long long part_blocks, long long sum_blocks,
+                       const Real* b, Real* x, hipStream_t s);
 
 // vector casts (mns_solver.hip)
 void mg_free(mns_handle* h);

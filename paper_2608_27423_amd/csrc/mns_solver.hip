@@ -1659,8 +1659,9 @@ struct BatchMG {
     int ncons = 0;
     long long cons_blocks = 0;
     CoarseItem* d_coarse = nullptr;  // direct coarsest solves of the instances after the prefix
+    double* d_part = nullptr;        // their column-chunk partial sums
     int ncoarse = 0;
-    long long coarse_blocks = 0;
+    long long coarse_blocks[2] = {0, 0};
   };
   std::vector<Level> lv;
   bool f32 = true;
@@ -1672,7 +1673,8 @@ void bmg_free(BatchMG* M) {
   if (!M) return;
   for (auto& L : M->lv) {
     if (L.bat) mns_batch_destroy(L.bat);
-    for (void* p : {(void*)L.d_seg, (void*)L.d_coef, L.vec, (void*)L.d_tx, (void*)L.d_cons, (void*)L.d_coarse})
+    for (void* p : {(void*)L.d_seg, (void*)L.d_coef, L.vec, (void*)L.d_tx, (void*)L.d_cons, (void*)L.d_coarse,
+                    (void*)L.d_part})
       if (p) (void)hipFree(p);
   }
   delete M;
@@ -1794,18 +1796,29 @@ int bmg_setup(mns_batch* B, mns_handle* const* level0, const mns_solve_opts* o, 
     // direct coarsest solves of the members after the prefix
     {
       std::vector<CoarseItem> co;
-      long long acc = 0;
+      std::vector<long long> poff;  // each item's first partial sum
+      long long acc[2] = {0, 0}, nparts = 0;
       for (int j = Lv.ncont; j < Lv.count; ++j) {
         CoarseItem it{};
         if ((rc = coarse_item(mg[ms[j]]->coarse, &it)) || it.n != Lv.off[j + 1] - Lv.off[j])
           return fail("coarsest-level solve of instance " + std::to_string(ms[j]));
         it.off = Lv.off[j];
-        it.blk0 = acc;
-        acc += (it.n + kCoarseRows - 1) / kCoarseRows;
+        poff.push_back(nparts);
+        nparts += (long long)coarse_parts(it.n) * it.n;
+        long long pb, sb;
+        coarse_blocks(it.n, &pb, &sb);
+        it.blk0 = acc[0];
+        it.blk1 = acc[1];
+        acc[0] += pb;
+        acc[1] += sb;
         co.push_back(it);
       }
       Lv.ncoarse = (int)co.size();
-      Lv.coarse_blocks = acc;
+      Lv.coarse_blocks[0] = acc[0];
+      Lv.coarse_blocks[1] = acc[1];
+      if (nparts > 0 && (e = hipMalloc((void**)&Lv.d_part, (size_t)nparts * sizeof(double))) != hipSuccess)
+        return fail("coarse partial sums");
+      for (size_t q = 0; q < co.size(); ++q) co[q].part = Lv.d_part + poff[q];
       if ((e = upload(&Lv.d_coarse, co)) != hipSuccess) return fail("coarse items");
     }
     if ((e = hipMalloc(&Lv.vec, 8 * (size_t)Lv.n * rb)) != hipSuccess) return fail("level vectors");
@@ -1925,7 +1938,8 @@ static int bmg_cycle(BatchMG* M, size_t l, hipStream_t s) {
     if ((rc = bmg_poly<Real>(M, Lv, r, cx, rr, dd, tt, diag, s))) return rc;
     bmg_axpy<Real>(x, Real(1), cx, x, Lv.ncn, s);
   }
-  if (Lv.ncoarse > 0 && (rc = coarse_apply_batch<Real>(Lv.d_coarse, Lv.ncoarse, Lv.coarse_blocks, b, x, s)))
+  if (Lv.ncoarse > 0 && (rc = coarse_apply_batch<Real>(Lv.d_coarse, Lv.ncoarse, Lv.coarse_blocks[0],
+                                                        Lv.coarse_blocks[1], b, x, s)))
     return rc;
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
