@@ -155,18 +155,19 @@ int mns_set_linearization(mns_handle* h, const double* state, const double* u_hi
  * interface cell of each side) follow the interpolated cells.  xyz NULL
  * returns to the exact polar geometry.  The Jacobian, residual, diagonal,
  * matrix reconstruction, allocation-free apply, mns_solve and mns_bdf2_step
- * with the Jacobi-Chebyshev preconditioner support this geometry; it always
+ * (every preconditioner) support this geometry; it always
  * runs the LDS-plane volume layout with the mortar kernel in its own launch
  * (mns_kernel_config's volume layout, fused launch and linearization source
- * do not apply); multigrid and batching need the polar geometry
+ * do not apply); the multigrid V-cycle builds curved coarse levels from
+ * these positions (mns_mg_levels); batching needs the polar geometry
  * (UNSUPPORTED).  Allocates the node and per-point metric tables on first
  * use (13 values per Gauss point in 3D, 7 in 2D, FP64 and FP32) and
  * synchronizes the stream.  Clears the rotation and the linearization (call
- * mns_rotate_rotor and mns_set_linearization again).
+ * mns_rotate_rotor and mns_set_linearization again) and frees a multigrid
+ * hierarchy built for the previous geometry.
  * Errors: INVALID_ARG (n_nodes not the mesh's node count, non-finite values,
  * an interface node off its polar position, a cell whose map folds: det J
- * zero or of the wrong orientation at a Gauss-Lobatto point), UNSUPPORTED (a
- * handle holding a multigrid hierarchy), HIP. */
+ * zero or of the wrong orientation at a Gauss-Lobatto point), HIP. */
 int mns_set_node_positions(mns_handle* h, const double* xyz, int64_t n_nodes, void* stream);
 
 /* Kind of the linearization that the next mns_set_linearization builds.
@@ -284,7 +285,12 @@ void mns_default_solve_opts(mns_solve_opts* opts);
  * space on the same mesh (polynomial level); then degree-2 meshes with
  * n_theta, n_r_rotor, n_r_stator (and n_z in 3D) halved while all stay even
  * (nested polar meshes: every coarse cell is 2 x 2 (x 2) fine cells of the
- * same map).  On every level:
+ * same map).  On a curved mesh (mns_set_node_positions) every coarse level
+ * is curved too: a halved mesh takes every other node position of the level
+ * above, the degree-2 level of a degree-3 mesh the Q3 interpolant of each
+ * cell at its Q2 nodes, and interface nodes stay at their polar positions on
+ * the circle; a coarse cell whose map folds fails the solve with
+ * INVALID_ARG.  On every level:
  * the operator of mns_apply_jacobian with mortar faces at the same rotor
  * angle, linearized at the finest state evaluated at the level's nodes (Newton
  * or, with mg_coarse_linearization = MNS_LIN_PICARD, Picard on the coarse

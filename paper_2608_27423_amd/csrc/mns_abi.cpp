@@ -126,9 +126,10 @@ int mns_rotate_rotor(mns_handle* h, double theta, double omega, void* stream) {
 int mns_set_node_positions(mns_handle* h, const double* xyz, int64_t n_nodes, void* stream) {
   if (!h) return MNS_ERR_INVALID_ARG;
   if (h->ndofs == 0 || !h->d_mtab64) return set_error(h, MNS_ERR_INVALID_ARG, "handle was not set up");
-  if (h->mg) return set_error(h, MNS_ERR_UNSUPPORTED, "the handle holds a multigrid hierarchy");
   int rc;
   try {
+    // a multigrid hierarchy holds coarse levels of the old geometry
+    mns::mg_free(h);
     rc = mns::iso_set_nodes(h, xyz, n_nodes, as_stream(stream));
   } catch (...) {
     rc = set_error(h, MNS_ERR_HIP, "exception in set_node_positions");
@@ -445,8 +446,6 @@ int mns_solve(mns_handle* h, const double* rhs, double* x, const mns_solve_opts*
       (o.use_graph != 0 && o.use_graph != 1) || !(o.cheb_lambda_factor >= 1.0 && o.cheb_lambda_factor <= 4.0) ||
       (o.mg_coarse_direct != 0 && o.mg_coarse_direct != 1))
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid solve options");
-  if (h->iso && (o.precond == MNS_PRECOND_MG || o.precond == MNS_PRECOND_MG64))
-    return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry (coarse levels are polar meshes)");
   mns_solve_report rep{};
   int rc;
   try {
@@ -483,8 +482,6 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
   if (opts) o = *opts;
   if (!(o.newton_rtol >= 0) || !(o.newton_atol >= 0) || o.max_newton < 1 || o.max_newton > 100)
     return set_error(h, MNS_ERR_INVALID_ARG, "invalid step options");
-  if (h->iso && (o.linear.precond == MNS_PRECOND_MG || o.linear.precond == MNS_PRECOND_MG64))
-    return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry (coarse levels are polar meshes)");
   mns_step_report rep{};
   int rc;
   try {
@@ -499,7 +496,6 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
 int mns_mg_levels(mns_handle* h, int* levels) {
   if (!h || !levels) return MNS_ERR_INVALID_ARG;
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
-  if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry");
   try {
     return mns::mg_levels(h, levels, h->stream);
   } catch (...) {
@@ -512,7 +508,6 @@ int mns_mg_prolongate(mns_handle* h, int level, const double* x, double* y, void
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
   if (!aligned(x, 8) || !aligned(y, 8) || x == y)
     return set_error(h, MNS_ERR_INVALID_ARG, "x/y must be distinct 8-byte aligned pointers");
-  if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry");
   try {
     return mns::mg_prolongate64(h, level, x, y, as_stream(stream));
   } catch (...) {
@@ -525,7 +520,6 @@ int mns_mg_restrict(mns_handle* h, int level, const double* x, double* y, void* 
   if (!h->linearized) return set_error(h, MNS_ERR_NOT_LINEARIZED, "call mns_set_linearization first");
   if (!aligned(x, 8) || !aligned(y, 8) || x == y)
     return set_error(h, MNS_ERR_INVALID_ARG, "x/y must be distinct 8-byte aligned pointers");
-  if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "multigrid needs the polar geometry");
   try {
     return mns::mg_restrict64(h, level, x, y, as_stream(stream));
   } catch (...) {

@@ -1222,6 +1222,95 @@ static bool can_halve(const mns_mesh_desc& d) {
   return d.n_theta % 2 == 0 && d.n_theta / 2 >= 4 && d.n_r_rotor % 2 == 0 && d.n_r_stator % 2 == 0 && z;
 }
 
+// Node positions of a coarse level of a curved (iso-parametric) hierarchy
+// from those of the level above (host arrays, n_nodes x 3, the vector
+// layout's node order): a halved degree-2 mesh takes every other node of the
+// finer one (its cells are unions of 2^d finer cells, and the Q2 nodes of the
+// union are finer nodes); the degree-2 level of a degree-3 mesh takes the Q3
+// interpolant of each cell at the Q2 nodes.  Interface nodes are put at their
+// polar positions on the circle, as the mortar requires (the Q3 interpolant
+// of the circle deviates from it between the nodes).
+static int iso_coarse_nodes(const mns_handle* hf, const std::vector<double>& xf, const mns_handle* hc,
+                            std::vector<double>& xc) {
+  const int dim = hc->desc.dim;
+  const bool poly = hf->k == 3 && hc->k == 2;
+  if (!poly && !(hf->k == 2 && hc->k == 2)) return MNS_ERR_UNSUPPORTED;
+  // 1D rule per direction: coarse node index -> (fine indices, weights)
+  double w3[4];  // Q3 Lagrange basis on its Gauss-Lobatto nodes at the cell midpoint
+  {
+    const double x[4] = {0.0, hf->gll[1], hf->gll[2], 1.0};
+    for (int b = 0; b < 4; ++b) {
+      double v = 1.0;
+      for (int c = 0; c < 4; ++c)
+        if (c != b) v *= (0.5 - x[c]) / (x[b] - x[c]);
+      w3[b] = v;
+    }
+  }
+  auto rule = [&](int j, int nfine, bool periodic, int* idx, double* w) {
+    if (!poly) {
+      idx[0] = 2 * j;
+      w[0] = 1.0;
+      return 1;
+    }
+    const int c = j / 2, a = j % 2;
+    if (a == 0) {
+      idx[0] = 3 * c;
+      w[0] = 1.0;
+      return 1;
+    }
+    for (int b = 0; b < 4; ++b) {
+      idx[b] = periodic ? (3 * c + b) % nfine : 3 * c + b;
+      w[b] = w3[b];
+    }
+    return 4;
+  };
+  xc.assign((size_t)hc->nnodes * 3, 0.0);
+  for (int dom = 0; dom < 2; ++dom) {
+    const long long fo = dom ? hf->node_off1 : 0, co = dom ? hc->node_off1 : 0;
+    for (int iz = 0; iz < hc->nzn; ++iz) {
+      int zi[4], ni_z = 1;
+      double zw[4] = {1.0, 0, 0, 0};
+      zi[0] = 0;
+      if (dim == 3) ni_z = rule(iz, hf->nzn, false, zi, zw);
+      for (int ir = 0; ir < hc->nrn[dom]; ++ir) {
+        int ri[4];
+        double rw[4];
+        const int ni_r = rule(ir, hf->nrn[dom], false, ri, rw);
+        for (int it = 0; it < hc->ntd[dom]; ++it) {
+          int ti[4];
+          double tw[4];
+          const int ni_t = rule(it, hf->ntd[dom], true, ti, tw);
+          double p[3] = {0, 0, 0};
+          for (int c = 0; c < ni_z; ++c)
+            for (int b = 0; b < ni_r; ++b)
+              for (int a = 0; a < ni_t; ++a) {
+                const long long nd = fo + ti[a] + (long long)hf->ntd[dom] * (ri[b] + (long long)hf->nrn[dom] * zi[c]);
+                const double ww = zw[c] * rw[b] * tw[a];
+                for (int m = 0; m < 3; ++m) p[m] += ww * xf[(size_t)nd * 3 + m];
+              }
+          const long long cn = co + it + (long long)hc->ntd[dom] * (ir + (long long)hc->nrn[dom] * iz);
+          const bool iface = dom == 0 ? ir == hc->nrn[0] - 1 : ir == 0;
+          if (iface) {
+            const double th = (it / hc->k + hc->gll[it % hc->k]) * hc->dthd[dom];
+            p[0] = hc->desc.r_interface * std::cos(th);
+            p[1] = hc->desc.r_interface * std::sin(th);
+            p[2] = dim == 3 ? (iz / hc->k + hc->gll[iz % hc->k]) * hc->dz : 0.0;
+          }
+          for (int m = 0; m < 3; ++m) xc[(size_t)cn * 3 + m] = p[m];
+        }
+      }
+    }
+  }
+  return MNS_OK;
+}
+
+// the handle's node positions (curved meshes), device -> host
+static int iso_host_nodes(mns_handle* h, std::vector<double>& x) {
+  x.resize((size_t)h->nnodes * 3);
+  const hipError_t e = hipMemcpy(x.data(), h->d_xnode, x.size() * sizeof(double), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? MNS_OK : set_error(h, MNS_ERR_HIP, std::string("node positions: ") + hipGetErrorString(e));
+}
+
 // levels and tables (once per handle)
 static int mg_build(mns_handle* h, int max_levels, MG** out) {
   if (h->mg) {
@@ -1243,6 +1332,12 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
   mg->L.push_back(L0);
   mns_mesh_desc d = h->desc;
   d.n_theta_stator = 0;  // equal ring counts on every level
+  // curved meshes: every coarse level gets node positions from the level above
+  std::vector<double> xprev, xcur;
+  if (h->iso) {
+    int rc = iso_host_nodes(h, xprev);
+    if (rc) return rc;
+  }
   // degree 3: first a degree-2 level on the same mesh, then halved meshes
   bool poly = d.degree == 3;
   while ((poly || can_halve(d)) && (max_levels == 0 || (int)mg->L.size() < max_levels)) {
@@ -1257,6 +1352,11 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
     }
     mns_handle* hc = new mns_handle();
     int rc = mns_build_handle(&d, h->stream, hc);
+    if (!rc && h->iso) {
+      rc = iso_coarse_nodes(mg->L.back().h, xprev, hc, xcur);
+      if (!rc) rc = iso_set_nodes(hc, xcur.data(), hc->nnodes, h->stream);
+      xprev.swap(xcur);
+    }
     if (rc) {
       const std::string msg = hc->err;
       mns_destroy(hc);
@@ -1298,8 +1398,11 @@ static int mg_setup(mns_handle* h, MG* mg, const mns_solve_opts* o, hipStream_t 
   if (o->mg_fine_linearization == MNS_LIN_PICARD) {
     if (!mg->fine) {
       mns_handle* hf = new mns_handle();
-      if ((rc = mns_build_handle(&h->desc, h->stream, hf))) {
-        const std::string msg = hf->err;
+      std::vector<double> xf;
+      if (!(rc = mns_build_handle(&h->desc, h->stream, hf)) && h->iso && !(rc = iso_host_nodes(h, xf)))
+        rc = iso_set_nodes(hf, xf.data(), hf->nnodes, s);
+      if (rc) {
+        const std::string msg = hf->err.empty() ? h->err : hf->err;
         mns_destroy(hf);
         return set_error(h, rc, "multigrid fine copy: " + msg);
       }

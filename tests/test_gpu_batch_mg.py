@@ -57,16 +57,20 @@ def _operators(inst, seed):
     return ops, hist, rhs
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("precond", ["mg", "mg64"])
-def test_batch_multigrid_matches_single_and_direct_solves(dim, precond):
+@pytest.mark.parametrize("dim,precond,extra", [
+    (2, "mg", {}), (3, "mg", {}), (2, "mg64", {}), (3, "mg64", {}),
+    # Gram-Schmidt in column chunks (restart beyond the register width) and
+    # Picard coarse levels with the FP64 cycle
+    (3, "mg", dict(restart=60)), (3, "mg64", dict(mg_coarse_linearization="picard")),
+])
+def test_batch_multigrid_matches_single_and_direct_solves(dim, precond, extra):
     import scipy.sparse.linalg as spla
 
     inst = _mg_instances(dim)
     ops = []
     try:
         ops, hist, rhs = _operators(inst, 80 + dim)
-        opts = dict(rtol=1e-10, restart=30, maxit=600, precond=precond)
+        opts = dict(dict(rtol=1e-10, restart=30, maxit=600, precond=precond), **extra)
         with binding.Batch(ops) as bt:
             x, rc, reps = bt.solve(_dev(np.concatenate(rhs)), check=False, **opts)
             assert rc == 0, bt.last_error()

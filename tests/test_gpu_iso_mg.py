@@ -1,0 +1,117 @@
+"""The multigrid V-cycle on curved (iso-parametric) meshes: every coarse level
+is curved too (a halved degree-2 mesh takes every other node position of the
+level above, the degree-2 level of a degree-3 mesh the Q3 interpolant at its
+Q2 nodes, interface nodes on the circle).  The solves must reach the direct
+solution of the oracle's assembled iso-parametric Jacobian, in about as many
+iterations as on the polar mesh (a coarse geometry that did not follow the
+fine one would show as a slower or failing cycle); a BDF2 + Newton step with
+the V-cycle reaches the oracle's Newton root; new node positions replace a
+hierarchy built for the old ones."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle
+from helpers import oracle_cfg, relmax, small_mesh
+from paper_2608_27423_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+PERT = 0.1
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _mesh(dim, k):
+    if dim == 2:
+        return small_mesh(2, k, n_theta=16, n_r_rotor=4, n_r_stator=4, steady=0, dt=0.02, nu=0.005)
+    if k == 2:
+        return small_mesh(3, 2, n_theta=16, n_r_rotor=2, n_r_stator=2, n_z=2, steady=0, dt=0.02, nu=0.005)
+    return small_mesh(3, 3, n_theta=8, n_r_rotor=1, n_r_stator=1, n_z=1, steady=0, dt=0.02, nu=0.005)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 2), (2, 3), (3, 3)])
+def test_iso_multigrid_solve_matches_direct_solve(dim, k):
+    mesh = _mesh(dim, k)
+    n = inputs.n_dofs(mesh)
+    g = np.random.default_rng(900 + 10 * dim + k)
+    state = inputs.transient_start(mesh, 910 + dim + k)
+    hist = g.uniform(-1, 1, n)
+    b = g.uniform(-1, 1, n)
+    theta, omega = 1.234, 0.7
+    A = oracle.assemble(oracle_cfg(mesh, theta, omega, iso=1, perturb=PERT), state, hist).tocsc()
+    xo = spla.spsolve(A, b)
+    its = {}
+    for geom in ("polar", "curved"):
+        with binding.Operator(mesh) as op:
+            if geom == "curved":
+                op.set_node_positions(inputs.iso_node_positions(mesh, PERT))
+            op.rotate_rotor(theta, omega)
+            op.set_linearization(_dev(state), _dev(hist))
+            levels = op.mg_levels()
+            for precond in ("mg", "mg64"):
+                x, rep = op.solve(_dev(b), rtol=1e-11, restart=100, maxit=2000, precond=precond, check=False)
+                its[geom, precond] = rep["iterations"]
+                assert rep["rc"] == 0, op.last_error()
+                if geom == "curved":
+                    err = relmax(x.cpu().numpy(), xo)
+                    print(f"dim={dim} k={k} curved {precond}: {levels} levels, {rep['iterations']} iterations, "
+                          f"|x - x_direct| / |x| = {err:.2e}")
+                    assert err < 1e-8
+        assert levels >= 2
+    print(f"dim={dim} k={k} iterations: {its}")
+    for p in ("mg", "mg64"):
+        assert its["curved", p] <= 1.5 * its["polar", p] + 5
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_iso_bdf2_step_with_multigrid(dim):
+    """One BDF2 + Newton step on the curved mesh with the FP32 V-cycle as the
+    linear solver's preconditioner reaches the root of the oracle's
+    iso-parametric discrete residual."""
+    from tests.test_gpu_transient import _oracle_step, _start_fields
+
+    dt = 0.05
+    mesh = small_mesh(dim, 2, n_theta=16, n_r_rotor=2, n_r_stator=2, n_z=2, steady=0, dt=dt, nu=0.02)
+    un, unm1, f = _start_fields(mesh, 70 + dim)
+    theta, omega = 0.73, 0.6
+    uo, _ = _oracle_step(oracle_cfg(mesh, theta, omega, iso=1, perturb=PERT), un, unm1, f, un, dt)
+    with binding.Operator(mesh) as op:
+        op.set_node_positions(inputs.iso_node_positions(mesh, PERT))
+        u = _dev(un).clone()
+        rep = op.bdf2_step(theta, omega, _dev(un), u, u_nm1=_dev(unm1), force=_dev(f), newton_rtol=1e-12,
+                           max_newton=30, linear=dict(rtol=1e-11, restart=60, maxit=2000, precond="mg"))
+        ug = u.cpu().numpy()
+    err = relmax(ug, uo)
+    print(f"curved BDF2 + V-cycle dim={dim}: newton {rep['newton_iterations']} linear {rep['linear_iterations']} "
+          f"res {rep['residual0']:.2e} -> {rep['residual']:.2e}; |u_gpu - u_oracle| / |u| = {err:.2e}")
+    assert rep["rc"] == 0 and rep["residual"] <= 1e-12 * rep["residual0"]
+    assert err < 1e-9
+
+
+def test_iso_new_positions_replace_the_hierarchy():
+    """A V-cycle solve on the polar mesh, then node positions: the hierarchy
+    is rebuilt for the curved geometry (the solve reaches the curved
+    operator's direct solution), and back to the polar one."""
+    mesh = _mesh(2, 2)
+    n = inputs.n_dofs(mesh)
+    g = np.random.default_rng(5)
+    state = inputs.transient_start(mesh, 6)
+    b = g.uniform(-1, 1, n)
+    theta, omega = 0.4, 1.0
+    solves = {}
+    for geom, cfg in (("polar", oracle_cfg(mesh, theta, omega)),
+                      ("curved", oracle_cfg(mesh, theta, omega, iso=1, perturb=PERT))):
+        solves[geom] = spla.spsolve(oracle.assemble(cfg, state).tocsc(), b)
+    with binding.Operator(mesh) as op:
+        for geom in ("polar", "curved", "polar"):
+            op.set_node_positions(inputs.iso_node_positions(mesh, PERT) if geom == "curved" else None)
+            op.rotate_rotor(theta, omega)
+            op.set_linearization(_dev(state))
+            x, rep = op.solve(_dev(b), rtol=1e-11, restart=100, maxit=2000, precond="mg")
+            err = relmax(x.cpu().numpy(), solves[geom])
+            print(f"{geom}: {rep['iterations']} iterations, |x - x_direct| / |x| = {err:.2e}")
+            assert err < 1e-8
