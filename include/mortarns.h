@@ -377,11 +377,12 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
 
 /* Batched Jacobian application (many rotor/stator instances at once).  A
  * batch holds `count` handles of any dimensions and degrees (any mesh sizes,
- * angles, viscosities, steady or transient; polar geometry and equal
+ * angles, viscosities, steady or transient, polar or curved geometry; equal
  * interface counts), each rotated and linearized before mns_batch_create.
  * Vectors of a batch are the instances' vectors concatenated in handle order
- * (mns_batch_n_dofs gives the total length).  The instances of one dimension
- * and degree form a launch group: mns_batch_apply_jacobian computes
+ * (mns_batch_n_dofs gives the total length).  The instances of one
+ * dimension, degree and geometry kind (polar, curved) form a launch group:
+ * mns_batch_apply_jacobian computes
  * dst_i = J_i src_i for every instance with, per group, one launch for all
  * its volume cells and mortar faces (in the block order of the
  * single-instance fused launch, the instance of a block found from block
@@ -391,7 +392,7 @@ int mns_bdf2_step(mns_handle* h, double theta_next, double omega, const double* 
  * are seen by later batch calls; a handle must outlive its batches.  The
  * batch allocates its tables at creation and nothing per call.
  * Errors: INVALID_ARG (null, misaligned vectors), NOT_LINEARIZED,
- * UNSUPPORTED (unequal interface counts, curved meshes), HIP; creation errors are reported on
+ * UNSUPPORTED (unequal interface counts), HIP; creation errors are reported on
  * handles[0], apply errors by mns_batch_last_error. */
 typedef struct mns_batch mns_batch;
 int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch);

@@ -208,20 +208,21 @@ int mns_batch_create(mns_handle* const* handles, int count, mns_batch** batch) {
       return set_error(h, MNS_ERR_NOT_LINEARIZED, "batch: rotate and linearize every handle first");
     if (!h->equal_rings)
       return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need equal interface cell counts");
-    if (h->iso) return set_error(h, MNS_ERR_UNSUPPORTED, "batch: instances need the polar geometry");
   }
   auto* b = new mns_batch();
   b->hs.assign(handles, handles + count);
-  // one group per (dimension, degree), in the order of first appearance
+  // one group per (dimension, degree, geometry kind), in the order of first
+  // appearance
   for (int i = 0; i < count; ++i) {
     mns_batch_group* g = nullptr;
     for (auto& x : b->groups)
-      if (x.dim == handles[i]->dim && x.k == handles[i]->k) g = &x;
+      if (x.dim == handles[i]->dim && x.k == handles[i]->k && x.iso == handles[i]->iso) g = &x;
     if (!g) {
       b->groups.emplace_back();
       g = &b->groups.back();
       g->dim = handles[i]->dim;
       g->k = handles[i]->k;
+      g->iso = handles[i]->iso;
     }
     g->members.push_back(i);
   }

@@ -248,14 +248,17 @@ struct BatchItem {
   const Real* mtrig;
   long long dof_off;
   int strip;          // local-result layout of the quad volume kernel
+  const Real* iso_mg; // curved meshes: the mortar point table of the current angle
 };
 
 }  // namespace mns
 
-// The instances of one dimension and degree inside a batch: applied by one
-// volume + mortar launch and one gather launch.
+// The instances of one dimension, degree and geometry kind (polar or
+// curved) inside a batch: applied by one volume + mortar launch and one
+// gather launch.
 struct mns_batch_group {
   int dim = 0, k = 0;
+  bool iso = false;
   std::vector<int> members;     // instance indices (handle order)
   // device: items (FP64, FP32), block prefix sums per precision: mortar,
   // volume (members + 1 each), gather (members + 1, shared)
@@ -265,8 +268,9 @@ struct mns_batch_group {
   long long mtot[2] = {0, 0}, vtot[2] = {0, 0}, gtot = 0;
 };
 
-// Instances applied together (mns_batch_*), of any dimensions and degrees:
-// one group per (dimension, degree), in the order of first appearance.
+// Instances applied together (mns_batch_*), of any dimensions, degrees and
+// geometry kinds: one group per (dimension, degree, kind), in the order of
+// first appearance.
 struct mns_batch {
   std::vector<mns_handle*> hs;
   long long ndofs = 0;

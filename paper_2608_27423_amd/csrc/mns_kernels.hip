@@ -3546,25 +3546,29 @@ __global__ __launch_bounds__(64) void k_batch_jacobian_quad(const BatchItem<Real
   }
 }
 
-template <typename Real, int DIM, int N>
+// LDS-plane volume blocks and mortar blocks (2D, 3D degree 4, and curved
+// cells of every degree: ISO, the blocks of the single-instance curved
+// fused launch)
+template <typename Real, int DIM, int N, bool ISO = false>
 __global__ __launch_bounds__(64) void k_batch_jacobian(const BatchItem<Real>* __restrict__ items,
                                                                     const long long* __restrict__ mstart,
                                                                     const long long* __restrict__ vstart, int count,
                                                                     Tab1D<Real, N> T, int k,
                                                                     const Real* __restrict__ src) {
-  __shared__ FusedSmem<Real, DIM, N> sm;
+  __shared__ FusedSmem<Real, DIM, N, ISO> sm;
   const long long mtot = mstart[count];
   const long long b = blockIdx.x;
   if (b < mtot) {
     const int i = batch_item_of(mstart, count, b);
     const Geom<Real> G = items[i].G;
-    mortar_block<Real, DIM, N>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab,
-                               items[i].mtrig, src + items[i].dof_off, items[i].Em, 1, sm.m);
+    mortar_block<Real, DIM, N, 36000, ISO>(G, T, k, (int)(b - mstart[i]), (const MortarTab<Real, N>*)items[i].mtab,
+                                           items[i].mtrig, src + items[i].dof_off, items[i].Em, 1, sm.m,
+                                           items[i].iso_mg);
   } else {
     const int i = batch_item_of(vstart, count, b - mtot);
     const Geom<Real> G = items[i].G;
-    volume_block<Real, DIM, N>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off,
-                               items[i].E, sm.v);
+    volume_block<Real, DIM, N, ISO>(G, T, k, (int)(b - mtot - vstart[i]), items[i].lin, src + items[i].dof_off,
+                                    items[i].E, sm.v);
   }
 }
 
@@ -3585,15 +3589,16 @@ __global__ __launch_bounds__(256) void k_batch_gather(const BatchItem<Real>* __r
 template <typename Real, int DIM, int N>
 static void batch_blocks(const mns_handle* h, long long* nmb, long long* nvb, int* strip) {
   using S = Shape<Real, DIM, N>;
-  constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
-  const int cpw = kQuad ? QuadShape<Real, N>::CPW : S::CPW;
+  // curved cells: the LDS-plane layout of their fused launch
+  const bool quad = kQuadLayout<Real, DIM, N> && !h->iso;
+  const int cpw = quad ? QuadShape<Real, N>::CPW : S::CPW;
   *nvb = (h->ncells + cpw - 1) / cpw;
   // faces per mortar block: two in the FP64 degree-2 quad launch (its LDS is
   // shared with the LDS-staged volume blocks), the default otherwise
-  constexpr int FPB = (kQuad && sizeof(Real) == 8 && N == 3) ? MortarShape<Real, DIM, N, kLdsQuadBytes>::FPB
-                                                             : MortarShape<Real, DIM, N>::FPB;
+  const int FPB = (quad && sizeof(Real) == 8 && N == 3) ? MortarShape<Real, DIM, N, kLdsQuadBytes>::FPB
+                                                        : MortarShape<Real, DIM, N>::FPB;
   *nmb = (2LL * h->nth[0] * h->nz + FPB - 1) / FPB;  // batches hold equal ring counts only
-  *strip = (kQuad && h->nth[0] % 16 == 0) ? 1 : 0;
+  *strip = (quad && h->nth[0] % 16 == 0) ? 1 : 0;
 }
 
 template <typename Real, int DIM, int N>
@@ -3613,6 +3618,7 @@ static void batch_items(const mns_batch* b, const mns_batch_group& g, std::vecto
     it.mtab = sizeof(Real) == 8 ? h->d_mtab64 : h->d_mtab32;
     it.mtrig = sizeof(Real) == 8 ? (const Real*)h->d_mtrig64 : (const Real*)h->d_mtrig32;
     it.dof_off = b->offsets[g.members[i]];  // offset in the whole batch's vectors
+    it.iso_mg = h->iso ? (sizeof(Real) == 8 ? (const Real*)h->d_mgeo64 : (const Real*)h->d_mgeo32) : nullptr;
     long long nmb, nvb;
     batch_blocks<Real, DIM, N>(h, &nmb, &nvb, &it.strip);
     ms[i + 1] = ms[i] + nmb;
@@ -3682,7 +3688,10 @@ static int do_batch(mns_batch* b, const mns_batch_group& g, const Real* src, Rea
   const Tab1D<Real, N> T = make_tab<Real, N>(b->hs[g.members[0]]);
   const long long blocks = g.mtot[p] + g.vtot[p];
   constexpr bool kQuad = kQuadLayout<Real, DIM, N>;
-  if constexpr (kQuad)
+  if (g.iso)
+    hipLaunchKernelGGL((k_batch_jacobian<Real, DIM, N, true>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs,
+                       count, T, g.k, src);
+  else if constexpr (kQuad)
     hipLaunchKernelGGL((k_batch_jacobian_quad<Real, N>), dim3((unsigned)blocks), dim3(64), 0, s, items, ms, vs, count,
                        T, g.k, src);
   else

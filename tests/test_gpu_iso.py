@@ -9,8 +9,9 @@ Jacobian in 2D degrees 2-5 and 3D degrees 2-4, equal and unequal interface
 counts, generic and aligned angles, spinning rotor, steady and BDF2 with
 history and force, Newton and Picard, every launch mode; residual; diagonal;
 dense matrix; allocation-free apply; Jacobi-Chebyshev solve; BDF2 + Newton step; return to the
-polar geometry; argument errors and the refused combination (batching).
-The multigrid V-cycle on curved meshes: tests/test_gpu_iso_mg.py."""
+polar geometry; argument errors.  The multigrid V-cycle on curved meshes:
+tests/test_gpu_iso_mg.py; batches of curved instances:
+tests/test_gpu_batch_iso.py."""
 import math
 
 import numpy as np
@@ -218,13 +219,12 @@ def test_iso_argument_errors():
         x = inputs.uniform(n, 2)
         assert relmax(op.apply_jacobian(_dev(x)).cpu().numpy(),
                       oracle.apply_jacobian(oracle_cfg(mesh, 0.5, 1.0), state, x)) <= TOL64
-        # batching needs the polar geometry
+        # the curved geometry in place again after the refused sets
         op.set_node_positions(xyz)
         op.rotate_rotor(0.5, 1.0)
         op.set_linearization(_dev(state))
-        with pytest.raises(binding.MnsError) as e:
-            binding.Batch([op])
-        assert e.value.code == binding.MNS_ERR_UNSUPPORTED
+        assert relmax(op.apply_jacobian(_dev(x)).cpu().numpy(),
+                      oracle.apply_jacobian(_cfg(mesh, 0.5, 1.0), state, x)) <= TOL64
 
 
 def test_iso_workload_full():
