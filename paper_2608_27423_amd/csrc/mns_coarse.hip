@@ -35,7 +35,10 @@ namespace mns {
 
 constexpr int kNB = 64;        // panel width of the LU and of the blocked triangular solves
 constexpr int kGemvRows = 256; // rows per workgroup of the matrix-vector product
-constexpr int kGemvCols = 128; // columns per workgroup (partial sums, summed in a second pass)
+// columns per workgroup (partial sums, summed in a second pass): 32 gives a
+// 3456-row inverse 1,512 workgroups of 256 rows, enough loads in flight to
+// read it at 3.7 TB/s (26 us; with 128 columns, 378 workgroups: 59 us)
+constexpr int kGemvCols = 32;
 
 // ---------------------------------------------------------------------------
 // Probing
@@ -335,13 +338,31 @@ __global__ __launch_bounds__(kGemvRows) void k_gemv_part(const double* __restric
   part[(long long)blockIdx.y * n + i] = s;
 }
 
+// y[i] = sum over the parts of part[p][i] for the kSumRows rows of row block
+// rb: the four wavefronts of the block sum a contiguous quarter of the parts
+// each (loads of several parts in flight), then the quarters are added in
+// order
+constexpr int kSumRows = 64;
 template <typename Real>
-__global__ void k_gemv_sum(const double* __restrict__ part, int n, int nparts, Real* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ inline void gemv_sum_rows(const double* __restrict__ part, int n, int nparts, int rb, Real* __restrict__ y) {
+  __shared__ double q[4][kSumRows];
+  const int lane = threadIdx.x % kSumRows, w = threadIdx.x / kSumRows;
+  const int i = rb * kSumRows + lane;
+  const int per = (nparts + 3) / 4, p0 = w * per, p1 = p0 + per < nparts ? p0 + per : nparts;
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[(long long)p * n + i];
-  y[i] = (Real)s;
+  if (i < n) {
+#pragma unroll 8
+    for (int p = p0; p < p1; ++p) s += part[(long long)p * n + i];
+  }
+  q[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < n) y[i] = (Real)(((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane]);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(4 * kSumRows) void k_gemv_sum(const double* __restrict__ part, int n, int nparts,
+                                                           Real* __restrict__ y) {
+  gemv_sum_rows<Real>(part, n, nparts, blockIdx.x, y);
 }
 
 // r = A x - y (check of the reconstruction), partial max |r| and max |y| per block
@@ -732,7 +753,8 @@ int coarse_apply(const void* state, const Real* b, Real* x, hipStream_t s) {
   const int parts = (n + kGemvCols - 1) / kGemvCols;
   hipLaunchKernelGGL(k_gemv_part<Real>, dim3((n + kGemvRows - 1) / kGemvRows, parts), dim3(kGemvRows), 0, s,
                      (const double*)C->Ainv, C->lda, n, b, C->part);
-  hipLaunchKernelGGL(k_gemv_sum<Real>, dim3((n + 255) / 256), dim3(256), 0, s, (const double*)C->part, n, parts, x);
+  hipLaunchKernelGGL(k_gemv_sum<Real>, dim3((n + kSumRows - 1) / kSumRows), dim3(4 * kSumRows), 0, s,
+                     (const double*)C->part, n, parts, x);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 template int coarse_apply<double>(const void*, const double*, double*, hipStream_t);
@@ -756,7 +778,7 @@ int coarse_parts(int n) { return (n + kGemvCols - 1) / kGemvCols; }
 void coarse_blocks(int n, long long* part_blocks, long long* sum_blocks) {
   const long long rows = (n + kGemvRows - 1) / kGemvRows;
   *part_blocks = rows * coarse_parts(n);
-  *sum_blocks = rows;
+  *sum_blocks = (n + kSumRows - 1) / kSumRows;
 }
 
 __device__ inline int coarse_find(const CoarseItem* items, int count, long long b, bool second) {
@@ -790,15 +812,11 @@ __global__ __launch_bounds__(kGemvRows) void k_gemv_batch_part(const CoarseItem*
 }
 
 template <typename Real>
-__global__ __launch_bounds__(kGemvRows) void k_gemv_batch_sum(const CoarseItem* __restrict__ items, int count,
-                                                              Real* __restrict__ x) {
+__global__ __launch_bounds__(4 * kSumRows) void k_gemv_batch_sum(const CoarseItem* __restrict__ items, int count,
+                                                                 Real* __restrict__ x) {
   const CoarseItem& it = items[coarse_find(items, count, blockIdx.x, true)];
-  const int i = (int)((long long)blockIdx.x - it.blk1) * kGemvRows + threadIdx.x;
-  if (i >= it.n) return;
-  const int parts = (it.n + kGemvCols - 1) / kGemvCols;
-  double s = 0.0;
-  for (int p = 0; p < parts; ++p) s += it.part[(long long)p * it.n + i];
-  x[it.off + i] = (Real)s;
+  gemv_sum_rows<Real>(it.part, it.n, (it.n + kGemvCols - 1) / kGemvCols, (int)((long long)blockIdx.x - it.blk1),
+                      x + it.off);
 }
 
 template <typename Real>
@@ -806,7 +824,7 @@ int coarse_apply_batch(const CoarseItem* items, int count, long long part_blocks
                        const Real* b, Real* x, hipStream_t s) {
   if (count == 0) return MNS_OK;
   hipLaunchKernelGGL(k_gemv_batch_part<Real>, dim3((unsigned)part_blocks), dim3(kGemvRows), 0, s, items, count, b);
-  hipLaunchKernelGGL(k_gemv_batch_sum<Real>, dim3((unsigned)sum_blocks), dim3(kGemvRows), 0, s, items, count, x);
+  hipLaunchKernelGGL(k_gemv_batch_sum<Real>, dim3((unsigned)sum_blocks), dim3(4 * kSumRows), 0, s, items, count, x);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 template int coarse_apply_batch<double>(const CoarseItem*, int, long long, long long, const double*, double*,
