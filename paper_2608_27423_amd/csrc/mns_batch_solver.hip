@@ -663,7 +663,7 @@ struct BatchSolver {
         mns_handle* h0 = B->mg_fine_hs[i];
         if ((rc = launch_constraints<Real>(h0, res + off, res + off, Real(0), 1, st)))
           return fail(rc, "batch multigrid constraints");
-        if ((rc = mg_instance_correction<Real>(B->hs[i], res + off, x + off, tt + off, o, st)))
+        if ((rc = mg_instance_correction<Real>(B->hs[i], res + off, x + off, o, st)))
           return fail(rc, "batch multigrid, instance " + std::to_string(i) + ": " + B->hs[i]->err);
       }
     }

@@ -367,11 +367,10 @@ int cached_diagonal(mns_handle* h, hipStream_t s);
 // multigrid of one instance of a batched solve: the hierarchy built and set
 // up as mns_solve does (level-0 handle: the instance's or its Picard copy,
 // with its lambda_max); x0 += the V-cycle's coarse-grid correction of the
-// level-0 residual r0 (t0: work vector); Jacobian applications of its cycles
+// level-0 residual r0; Jacobian applications of its cycles
 int mg_instance_setup(mns_handle* h, const mns_solve_opts* o, hipStream_t s, mns_handle** level0, double* lmax0);
 template <typename Real>
-int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, Real* t0, const mns_solve_opts* o,
-                           hipStream_t s);
+int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, const mns_solve_opts* o, hipStream_t s);
 void mg_instance_counts(mns_handle* h, int* v64, int* v32);
 // the coarse-grid correction of every instance of a batch at once: each
 // level's smoothing, residual, transfers, constraints and direct coarsest

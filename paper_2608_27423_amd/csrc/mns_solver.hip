@@ -913,10 +913,11 @@ struct TxView {
   long long pt, pr[2], pz, rt, rr[2], rz, et, er[2], ez;  // table offsets (entries)
 };
 
-// fine node g of P x_c (added to the fine value when add)
+// fine node g of P x_c (added to the fine value when add); entries flagged
+// in mask (constrained rows, when given) receive a zero correction
 template <typename Real>
 __device__ inline void prolong_node(const TxView& X, const Real* __restrict__ coarse, Real* __restrict__ fine,
-                                    long long g, int add) {
+                                    long long g, int add, const unsigned char* __restrict__ mask = nullptr) {
   const int dom = g >= X.off1f;
   const long long l = g - (dom ? X.off1f : 0);
   const int it = (int)(l % X.ntf);
@@ -944,14 +945,17 @@ __device__ inline void prolong_node(const TxView& X, const Real* __restrict__ co
       }
     }
   }
-  for (int m = 0; m < X.nc; ++m) fine[g * X.nc + m] = (add ? fine[g * X.nc + m] : Real(0)) + acc[m];
+  for (int m = 0; m < X.nc; ++m) {
+    const Real c = (mask && mask[g * X.nc + m]) ? Real(0) : acc[m];
+    fine[g * X.nc + m] = (add ? fine[g * X.nc + m] : Real(0)) + c;
+  }
 }
 
 template <typename Real>
 __global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __restrict__ fine, long long nnf,
-                             int add) {
+                             int add, const unsigned char* __restrict__ mask) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < nnf) prolong_node(X, coarse, fine, g, add);
+  if (g < nnf) prolong_node(X, coarse, fine, g, add, mask);
 }
 
 // One direction of the restriction (the transposed 1D prolongation rows):
@@ -969,7 +973,8 @@ struct RestrictPass {
 // output node g of one restriction pass
 template <typename Real>
 __device__ inline void restrict_dir_node(const TxView& X, const RestrictPass& P, const Real* __restrict__ in,
-                                         Real* __restrict__ out, long long g) {
+                                         Real* __restrict__ out, long long g,
+                                         const unsigned char* __restrict__ mask = nullptr) {
   const int dom = g >= P.off1_out;
   const long long l = g - (dom ? P.off1_out : 0);
   const int it = (int)(l % P.nt_out);
@@ -989,14 +994,15 @@ __device__ inline void restrict_dir_node(const TxView& X, const RestrictPass& P,
     const long long node = base + jt + (long long)P.nt_in * (jr + (long long)nri * jz);
     for (int m = 0; m < X.nc; ++m) acc[m] += (Real)wa * in[node * X.nc + m];
   }
-  for (int m = 0; m < X.nc; ++m) out[g * X.nc + m] = acc[m];
+  for (int m = 0; m < X.nc; ++m) out[g * X.nc + m] = (mask && mask[g * X.nc + m]) ? Real(0) : acc[m];
 }
 
+// mask (last pass only): constrained entries of the coarse level set to zero
 template <typename Real>
 __global__ void k_mg_restrict_dir(TxView X, RestrictPass P, const Real* __restrict__ in, Real* __restrict__ out,
-                                  long long nout) {
+                                  long long nout, const unsigned char* __restrict__ mask) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < nout) restrict_dir_node(X, P, in, out, g);
+  if (g < nout) restrict_dir_node(X, P, in, out, g, mask);
 }
 
 
@@ -1021,9 +1027,11 @@ static void restrict_passes(const TxView& X, RestrictPass P[3], long long n[3]) 
                       X.off1c};
 }
 
-// coarse = P^T fine: theta, then r, then z (tmp holds the intermediate grids)
+// coarse = P^T fine: theta, then r, then z (tmp holds the intermediate grids);
+// cmask: constrained entries of the coarse level written as zero
 template <typename Real>
-static int mg_restrict(const TxView& X, void* tmp, const Real* fine, Real* coarse, hipStream_t s) {
+static int mg_restrict(const TxView& X, void* tmp, const Real* fine, Real* coarse, hipStream_t s,
+                       const unsigned char* cmask = nullptr) {
   RestrictPass P[3];
   long long n[3];
   restrict_passes(X, P, n);
@@ -1031,11 +1039,12 @@ static int mg_restrict(const TxView& X, void* tmp, const Real* fine, Real* coars
   const RestrictPass &p1 = P[0], &p2 = P[1], &p3 = P[2];
   Real* t1 = (Real*)tmp;
   Real* t2 = t1 + n1 * X.nc;
-  hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, X, p1, fine, t1, n1);
+  hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, X, p1, fine, t1, n1,
+                     (const unsigned char*)nullptr);
   hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, X, p2,
-                     (const Real*)t1, t2, n2);
+                     (const Real*)t1, t2, n2, (const unsigned char*)nullptr);
   hipLaunchKernelGGL(k_mg_restrict_dir<Real>, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, X, p3,
-                     (const Real*)t2, coarse, n3);
+                     (const Real*)t2, coarse, n3, cmask);
   return hipGetLastError() == hipSuccess ? MNS_OK : MNS_ERR_HIP;
 }
 
@@ -1073,6 +1082,25 @@ __global__ void k_mg_eval(TxView X, const double* __restrict__ fine, double* __r
   for (int m = 0; m < X.nc; ++m) coarse[g * X.nc + m] = acc[m];
 }
 
+__global__ void k_mask_clear(unsigned char* __restrict__ mask, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    mask[i] = 0;
+}
+
+__global__ void k_mask_set(const int64_t* __restrict__ cons, long long n, unsigned char* __restrict__ mask) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) mask[cons[i]] = 1;
+}
+
+// r = b - t with the constrained entries zero (the residual the cycle
+// restricts; the same arithmetic as k_mg_axpy with beta = -1)
+template <typename Real>
+__global__ void k_mg_resid(const Real* __restrict__ b, const Real* __restrict__ t, Real* __restrict__ r,
+                           const unsigned char* __restrict__ mask, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    r[i] = mask[i] ? Real(0) : b[i] + Real(-1) * t[i];
+}
+
 // out = a + beta * b
 template <typename Real>
 __global__ void k_mg_axpy(const Real* __restrict__ a, Real beta, const Real* __restrict__ b, Real* __restrict__ out,
@@ -1092,6 +1120,7 @@ struct MGLevel {
   void* b = nullptr;        // V-cycle vectors b, x, r (FP32 or FP64, room for FP64)
   double* inj = nullptr;    // injected state, history, force (coarse levels)
   void* tr = nullptr;       // intermediate grids of the three-pass restriction to the next level
+  unsigned char* cmask = nullptr;  // 1 on the level's constrained entries (Dirichlet rows), else 0
   const double* eig_vec = nullptr;  // workspace vector holding the last power-iteration iterate
   const mns_handle* eig_h = nullptr; // handle whose operator it belongs to
   long long eig_gen = -1;           // workspace generation of that handle
@@ -1381,7 +1410,15 @@ static int mg_build(mns_handle* h, int max_levels, MG** out) {
     if (l + 1 < mg->L.size() &&
         (e = hipMalloc(&Lv.tr, (size_t)restrict_tmp_nodes(mg->T[l]) * Lv.h->nc * sizeof(double))) != hipSuccess)
       return mg_err(h, e, "hipMalloc mg");
+    // constrained-entry mask of the level (the constraint list is fixed by
+    // the mesh): the cycle zeroes these entries inside its fused kernels
+    if ((e = hipMalloc((void**)&Lv.cmask, (size_t)Lv.n)) != hipSuccess) return mg_err(h, e, "hipMalloc mg");
+    hipLaunchKernelGGL(k_mask_clear, dim3(grid_for(Lv.n)), dim3(256), 0, h->stream, Lv.cmask, Lv.n);
+    if (Lv.h->n_cons > 0)
+      hipLaunchKernelGGL(k_mask_set, dim3((unsigned)((Lv.h->n_cons + 255) / 256)), dim3(256), 0, h->stream,
+                         (const int64_t*)Lv.h->d_cons, (long long)Lv.h->n_cons, Lv.cmask);
   }
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return mg_err(h, e, "multigrid masks");
   *out = mg;
   return MNS_OK;
 }
@@ -1577,23 +1614,18 @@ static int mg_cycle(MG* mg, size_t l, const mns_solve_opts* o, hipStream_t s) {
   if ((rc = launch_jacobian<Real>(hl, v.x, v.ct, s))) return rc;
   ++(sizeof(Real) == 8 ? mg->vm64 : mg->vm32);
   const unsigned g = grid_for(Lv.n);
-  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.b, Real(-1), (const Real*)v.ct, v.r,
-                     Lv.n);
-  if ((rc = launch_constraints<Real>(hl, v.r, v.r, Real(0), 1, s))) return rc;
+  hipLaunchKernelGGL(k_mg_resid<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.b, (const Real*)v.ct, v.r,
+                     (const unsigned char*)Lv.cmask, Lv.n);
   MGLevel& Lc = mg->L[l + 1];
   Solver Sc = make_solver(Lc.h, s, 1);
   MGVec<Real> vc = mg_vec<Real>(Lc, Sc);
   const TxView& X = mg->T[l];
-  if ((rc = mg_restrict<Real>(X, Lv.tr, (const Real*)v.r, vc.b, s)))
+  if ((rc = mg_restrict<Real>(X, Lv.tr, (const Real*)v.r, vc.b, s, Lc.cmask)))
     return set_error(mg->L[0].h, rc, "multigrid restriction");
-  if ((rc = launch_constraints<Real>(Lc.h, vc.b, vc.b, Real(0), 1, s))) return rc;
   if ((rc = mg_cycle<Real>(mg, l + 1, o, s))) return rc;
   // x += P x_c (constrained rows of the correction zero)
   hipLaunchKernelGGL(k_mg_prolong<Real>, dim3((unsigned)((hl->nnodes + 255) / 256)), dim3(256), 0, s, X,
-                     (const Real*)vc.x, v.r, (long long)hl->nnodes, 0);
-  if ((rc = launch_constraints<Real>(hl, v.r, v.r, Real(0), 1, s))) return rc;
-  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)v.x, Real(1), (const Real*)v.r, v.x,
-                     Lv.n);
+                     (const Real*)vc.x, v.x, (long long)hl->nnodes, 1, (const unsigned char*)Lv.cmask);
   if (hipGetLastError() != hipSuccess) return set_error(mg->L[0].h, MNS_ERR_HIP, "multigrid kernels");
   return mg_smooth<Real>(mg, l, v.b, v.x, false, o->mg_smooth_degree, o->mg_smooth_range, o->cheb_lambda_factor, s);
 }
@@ -1628,31 +1660,24 @@ int mg_instance_setup(mns_handle* h, const mns_solve_opts* o, hipStream_t s, mns
 }
 
 template <typename Real>
-int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, Real* t0, const mns_solve_opts* o,
-                           hipStream_t s) {
+int mg_instance_correction(mns_handle* h, const Real* r0, Real* x0, const mns_solve_opts* o, hipStream_t s) {
   MG* mg = (MG*)h->mg;
   if (!mg || mg->L.size() < 2) return set_error(h, MNS_ERR_INVALID_ARG, "multigrid hierarchy missing");
   MGLevel& L0 = mg->L[0];
   mns_handle* h0 = L0.h;
-  const unsigned g = grid_for(L0.n);
   MGLevel& Lc = mg->L[1];
   Solver Sc = make_solver(Lc.h, s, 1);
   MGVec<Real> vc = mg_vec<Real>(Lc, Sc);
   const TxView& X = mg->T[0];
   int rc;
-  if ((rc = mg_restrict<Real>(X, L0.tr, r0, vc.b, s))) return set_error(h, rc, "multigrid restriction");
-  if ((rc = launch_constraints<Real>(Lc.h, vc.b, vc.b, Real(0), 1, s))) return rc;
+  if ((rc = mg_restrict<Real>(X, L0.tr, r0, vc.b, s, Lc.cmask))) return set_error(h, rc, "multigrid restriction");
   if ((rc = mg_cycle<Real>(mg, 1, o, s))) return rc;
   hipLaunchKernelGGL(k_mg_prolong<Real>, dim3((unsigned)((h0->nnodes + 255) / 256)), dim3(256), 0, s, X,
-                     (const Real*)vc.x, t0, (long long)h0->nnodes, 0);
-  if ((rc = launch_constraints<Real>(h0, t0, t0, Real(0), 1, s))) return rc;
-  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)x0, Real(1), (const Real*)t0, x0, L0.n);
+                     (const Real*)vc.x, x0, (long long)h0->nnodes, 1, (const unsigned char*)L0.cmask);
   return hipGetLastError() == hipSuccess ? MNS_OK : set_error(h, MNS_ERR_HIP, "multigrid correction kernels");
 }
-template int mg_instance_correction<float>(mns_handle*, const float*, float*, float*, const mns_solve_opts*,
-                                           hipStream_t);
-template int mg_instance_correction<double>(mns_handle*, const double*, double*, double*, const mns_solve_opts*,
-                                            hipStream_t);
+template int mg_instance_correction<float>(mns_handle*, const float*, float*, const mns_solve_opts*, hipStream_t);
+template int mg_instance_correction<double>(mns_handle*, const double*, double*, const mns_solve_opts*, hipStream_t);
 
 void mg_instance_counts(mns_handle* h, int* v64, int* v32) {
   MG* mg = (MG*)h->mg;
@@ -2186,6 +2211,7 @@ void mg_free(mns_handle* h) {
     if (Lv.b) (void)hipFree(Lv.b);
     if (Lv.inj) (void)hipFree(Lv.inj);
     if (Lv.tr) (void)hipFree(Lv.tr);
+    if (Lv.cmask) (void)hipFree(Lv.cmask);
     if (l > 0 && Lv.h) mns_destroy(Lv.h);
   }
   if (mg->fine) mns_destroy(mg->fine);
@@ -2221,7 +2247,7 @@ int mg_prolongate64(mns_handle* h, int level, const double* x, double* y, hipStr
   if (level < 0 || level + 1 >= (int)mg->L.size()) return set_error(h, MNS_ERR_INVALID_ARG, "no such multigrid level");
   mns_handle* hf = mg->L[level].h;
   hipLaunchKernelGGL(k_mg_prolong<double>, dim3((unsigned)((hf->nnodes + 255) / 256)), dim3(256), 0, s,
-                     mg->T[level], x, y, (long long)hf->nnodes, 0);
+                     mg->T[level], x, y, (long long)hf->nnodes, 0, (const unsigned char*)nullptr);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? MNS_OK : set_error(h, MNS_ERR_HIP, std::string("prolongation: ") + hipGetErrorString(e));
 }
