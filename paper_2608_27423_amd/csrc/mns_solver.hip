@@ -125,10 +125,12 @@ __global__ void k_update_x(const double* __restrict__ Z, long long n, int K, con
 // Chebyshev start: r = b ; d = D^-1 b / theta ; x = d
 template <typename Real>
 __global__ void k_cheb_init(const Real* __restrict__ b, const Real* __restrict__ diag, Real inv_theta,
-                            Real* __restrict__ r, Real* __restrict__ d, Real* __restrict__ x, long long n) {
+                            Real* __restrict__ r, Real* __restrict__ d, Real* __restrict__ x, long long n,
+                            const Real* __restrict__ sub) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const Real bi = b[i];
+    // sub: the polynomial applied to b - sub (a residual formed on the fly)
+    const Real bi = sub ? b[i] + Real(-1) * sub[i] : b[i];
     const Real di = inv_theta * bi / diag[i];
     r[i] = bi;
     d[i] = di;
@@ -600,13 +602,13 @@ struct Solver {
   // z = Chebyshev(D^-1 J) approximation of J^-1 v, degree `deg`, interval [lmax/range, lmax]
   template <typename Real>
   int chebyshev(const Real* b, Real* x, Real* r, Real* d, Real* t, const Real* diag, int deg, double lmax,
-                double range) {
+                double range, const Real* sub = nullptr) {
     const double beta = lmax, alpha = lmax / range;
     const double theta = 0.5 * (beta + alpha), delta = 0.5 * (beta - alpha);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
     const unsigned g = grid_for(n);
-    hipLaunchKernelGGL(k_cheb_init<Real>, dim3(g), dim3(256), 0, s, b, diag, (Real)(1.0 / theta), r, d, x, n);
+    hipLaunchKernelGGL(k_cheb_init<Real>, dim3(g), dim3(256), 0, s, b, diag, (Real)(1.0 / theta), r, d, x, n, sub);
     for (int k = 0; k < deg; ++k) {
       int rc;
       if constexpr (sizeof(Real) == 8) rc = jac64((const double*)d, (double*)t);
@@ -1560,11 +1562,11 @@ static int mg_smooth(MG* mg, size_t l, const Real* b, Real* x, bool zero, int de
     count += S.vm64 + S.vm32;
     return rc;
   }
-  int rc = launch_jacobian<Real>(hl, x, v.ct, s);
+  // x += poly(b - J x): the residual is formed by the polynomial's first kernel
+  int rc = launch_jacobian<Real>(hl, x, v.r, s);
   if (rc) return rc;
   ++count;
-  hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, b, Real(-1), (const Real*)v.ct, v.r, Lv.n);
-  rc = S.chebyshev<Real>(v.r, v.cx, v.cr, v.cd, v.ct, v.diag, deg, lmax, range);
+  rc = S.chebyshev<Real>(b, v.cx, v.cr, v.cd, v.ct, v.diag, deg, lmax, range, (const Real*)v.r);
   count += S.vm64 + S.vm32;
   if (rc) return rc;
   hipLaunchKernelGGL(k_mg_axpy<Real>, dim3(g), dim3(256), 0, s, (const Real*)x, Real(1), (const Real*)v.cx, x, Lv.n);
