@@ -916,8 +916,11 @@ struct TxView {
 };
 
 // fine node g of P x_c (added to the fine value when add); entries flagged
-// in mask (constrained rows, when given) receive a zero correction
-template <typename Real>
+// in mask (constrained rows, when given) receive a zero correction.  K1T, NCT:
+// the row width and component count when known at compile time (coarse
+// degree 2: 3; 4 components in 3D, 3 in 2D), so that the loops unroll and the
+// components of a coarse node load together; 0: read from X
+template <typename Real, int K1T = 0, int NCT = 0>
 __device__ inline void prolong_node(const TxView& X, const Real* __restrict__ coarse, Real* __restrict__ fine,
                                     long long g, int add, const unsigned char* __restrict__ mask = nullptr) {
   const int dom = g >= X.off1f;
@@ -927,37 +930,53 @@ __device__ inline void prolong_node(const TxView& X, const Real* __restrict__ co
   const int nrf = dom ? X.nrf[1] : X.nrf[0];
   const int nrc = dom ? X.nrc[1] : X.nrc[0];
   const int ir = (int)(l2 % nrf), iz = (int)(l2 / nrf);
-  const int K1 = X.pw;
+  const int K1 = K1T ? K1T : X.pw;
+  const int NC = NCT ? NCT : X.nc;
   const long long ot = X.pt + (long long)it * K1, orr = (dom ? X.pr[1] : X.pr[0]) + (long long)ir * K1,
                   oz = X.pz + (long long)iz * K1;
   const long long cbase = dom ? X.off1c : 0;
   Real acc[4] = {0, 0, 0, 0};
-  for (int a = 0; a < K1; ++a) {
+#pragma unroll
+  for (int a = 0; a < (K1T ? K1T : K1); ++a) {
     const double wt = X.w[ot + a];
     if (wt == 0.0) continue;
-    for (int b = 0; b < K1; ++b) {
+#pragma unroll
+    for (int b = 0; b < (K1T ? K1T : K1); ++b) {
       const double wr = X.w[orr + b];
       if (wr == 0.0) continue;
-      for (int c = 0; c < K1; ++c) {
+#pragma unroll
+      for (int c = 0; c < (K1T ? K1T : K1); ++c) {
         const double wz = X.w[oz + c];
         if (wz == 0.0) continue;
         const long long node = cbase + X.idx[ot + a] + (long long)X.ntc * (X.idx[orr + b] + (long long)nrc * X.idx[oz + c]);
         const Real ww = (Real)(wt * wr * wz);
-        for (int m = 0; m < X.nc; ++m) acc[m] += ww * coarse[node * X.nc + m];
+#pragma unroll
+        for (int m = 0; m < (NCT ? NCT : NC); ++m) acc[m] += ww * coarse[node * NC + m];
       }
     }
   }
-  for (int m = 0; m < X.nc; ++m) {
-    const Real c = (mask && mask[g * X.nc + m]) ? Real(0) : acc[m];
-    fine[g * X.nc + m] = (add ? fine[g * X.nc + m] : Real(0)) + c;
+#pragma unroll
+  for (int m = 0; m < (NCT ? NCT : NC); ++m) {
+    const Real c = (mask && mask[g * NC + m]) ? Real(0) : acc[m];
+    fine[g * NC + m] = (add ? fine[g * NC + m] : Real(0)) + c;
   }
+}
+
+// the compile-time forms for coarse degree 2 (the coarse levels of every
+// hierarchy here), else the general one
+template <typename Real>
+__device__ inline void prolong_node_any(const TxView& X, const Real* __restrict__ coarse, Real* __restrict__ fine,
+                                        long long g, int add, const unsigned char* __restrict__ mask) {
+  if (X.pw == 3 && X.nc == 4) prolong_node<Real, 3, 4>(X, coarse, fine, g, add, mask);
+  else if (X.pw == 3 && X.nc == 3) prolong_node<Real, 3, 3>(X, coarse, fine, g, add, mask);
+  else prolong_node<Real>(X, coarse, fine, g, add, mask);
 }
 
 template <typename Real>
 __global__ void k_mg_prolong(TxView X, const Real* __restrict__ coarse, Real* __restrict__ fine, long long nnf,
                              int add, const unsigned char* __restrict__ mask) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < nnf) prolong_node(X, coarse, fine, g, add, mask);
+  if (g < nnf) prolong_node_any(X, coarse, fine, g, add, mask);
 }
 
 // One direction of the restriction (the transposed 1D prolongation rows):
@@ -1750,7 +1769,7 @@ __global__ __launch_bounds__(256) void k_bmg_prolong(const TxItem* __restrict__ 
                                                      const Real* __restrict__ coarse, Real* __restrict__ fine) {
   const TxItem& it = items[item_find(items, count, blockIdx.x, [](const TxItem& t) { return t.blk[3]; })];
   const long long g = ((long long)blockIdx.x - it.blk[3]) * 256 + threadIdx.x;
-  if (g < it.nnf) prolong_node(it.X, coarse + it.coff, fine + it.foff, g, 0);
+  if (g < it.nnf) prolong_node_any(it.X, coarse + it.coff, fine + it.foff, g, 0, (const unsigned char*)nullptr);
 }
 
 // constrained rows of every item set to zero
