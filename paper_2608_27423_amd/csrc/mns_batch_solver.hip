@@ -600,7 +600,6 @@ struct BatchSolver {
   float *b32, *x32, *r32, *d32, *t32, *diag32, *mr32, *mx32;
   mns_batch* F = nullptr;  // multigrid: the batch of the level-0 operators
   BatchMG* bmg = nullptr;  // multigrid: the batched coarse levels (null: corrections per instance)
-  int mg_v64 = 0, mg_v32 = 0;
   int vm64 = 0, vm32 = 0;
   int it_vm64 = 0, it_vm32 = 0;  // Jacobian applications of one iteration
   hipGraphExec_t gexec = nullptr;
