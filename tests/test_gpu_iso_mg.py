@@ -4,9 +4,11 @@ level above, the degree-2 level of a degree-3 mesh the Q3 interpolant at its
 Q2 nodes, interface nodes on the circle).  The solves must reach the direct
 solution of the oracle's assembled iso-parametric Jacobian, in about as many
 iterations as on the polar mesh (a coarse geometry that did not follow the
-fine one would show as a slower or failing cycle); a BDF2 + Newton step with
-the V-cycle reaches the oracle's Newton root; new node positions replace a
-hierarchy built for the old ones."""
+fine one would show as a slower or failing cycle); Picard coarse levels and a
+Picard copy of the finest level (which takes the mesh's node positions) on a
+steady curved operator; a BDF2 + Newton step with the V-cycle reaches the
+oracle's Newton root; new node positions replace a hierarchy built for the
+old ones."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -114,4 +116,29 @@ def test_iso_new_positions_replace_the_hierarchy():
             x, rep = op.solve(_dev(b), rtol=1e-11, restart=100, maxit=2000, precond="mg")
             err = relmax(x.cpu().numpy(), solves[geom])
             print(f"{geom}: {rep['iterations']} iterations, |x - x_direct| / |x| = {err:.2e}")
+            assert err < 1e-8
+
+
+def test_iso_multigrid_picard_levels_steady():
+    """Steady operator on a curved mesh with Picard coarse levels and a
+    Picard copy of the finest level for smoothing (that copy takes the mesh's
+    node positions): the V-cycle solve reaches the oracle's direct solution of
+    the curved Newton Jacobian."""
+    mesh = small_mesh(3, 2, n_theta=16, n_r_rotor=2, n_r_stator=2, n_z=2, nu=0.02)
+    n = inputs.n_dofs(mesh)
+    sm = inputs.smooth_field(mesh, 12)
+    state = 0.5 * sm / np.abs(sm).max()
+    b = np.random.default_rng(13).uniform(-1, 1, n)
+    theta, omega = 0.9, 0.7
+    xo = spla.spsolve(oracle.assemble(oracle_cfg(mesh, theta, omega, iso=1, perturb=PERT), state).tocsc(), b)
+    with binding.Operator(mesh) as op:
+        op.set_node_positions(inputs.iso_node_positions(mesh, PERT))
+        op.rotate_rotor(theta, omega)
+        op.set_linearization(_dev(state))
+        for kw in (dict(mg_coarse_linearization="picard"),
+                   dict(mg_coarse_linearization="picard", mg_fine_linearization="picard")):
+            x, rep = op.solve(_dev(b), rtol=1e-11, restart=100, maxit=1500, precond="mg", check=False, **kw)
+            err = relmax(x.cpu().numpy(), xo)
+            print(f"curved steady {kw}: {rep['iterations']} iterations, |x - x_direct| / |x| = {err:.2e}")
+            assert rep["rc"] == 0, op.last_error()
             assert err < 1e-8
